@@ -1,0 +1,288 @@
+"""FP64 reference evaluator for stencil pipelines -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may use
+this package.  The product (the HIP library and its Python binding) never
+imports, links or calls it, and it shares no code with the product: it has its
+own expression parser, its own stage loops and its own domain bookkeeping.
+
+What it computes is the plain definition of a pipeline of per-pixel stages
+(the paper, Section 2.2 and Fig. 2: each stage is a function over an integer
+domain whose value at a point is an expression of producer values at constant
+offsets).  Overlapped tiling, fusion and hybrid VGPR/LDS storage change only
+*where* values are kept and how often they are recomputed, never the values
+themselves (Section 2.2, overlapped tiles recompute their halo), so the
+oracle evaluates every stage unfused, over its whole domain, in topological
+order, in float64.
+
+Readings where the paper is silent (it uses interior-only domains):
+  * boundary: every producer read outside the producer's domain takes the
+    value at the nearest point of that domain (clamp to edge, per stage);
+  * down2 keeps even samples, its domain is ceil(W/2) x ceil(H/2);
+  * up2 is the separable 2x expansion with the binomial [1,4,6,4,1]/16
+    (Burt-Adelson EXPAND): even output 2i -> (P(i-1) + 6 P(i) + P(i+1)) / 8,
+    odd output 2i+1 -> (P(i) + P(i+1)) / 2, coarse indices clamped, output
+    domain the size of the finer level;
+  * a pointwise stage reads each source at the same point; a one-channel
+    source is broadcast over channels.
+
+Every function below is pinned by tests under ``tests/`` (brute force on tiny
+images, closed forms on ramps, steps, impulses and corners, and invariants).
+"""
+from __future__ import annotations
+
+import ast
+
+import numpy as np
+
+__all__ = ["evaluate", "evaluate_stage", "parse_expr", "level_size",
+           "stencil", "down2", "up2", "pointwise"]
+
+
+# --------------------------------------------------------------------------
+# Domains
+# --------------------------------------------------------------------------
+
+def level_size(width: int, height: int, level: int):
+    """Domain of a level-``level`` stage of a pipeline whose inputs are W x H:
+    each 2x decimation takes the ceiling of half of each side."""
+    for _ in range(level):
+        width = (width + 1) // 2
+        height = (height + 1) // 2
+    return width, height
+
+
+# --------------------------------------------------------------------------
+# Stage kinds (each takes and returns float64 arrays of shape [C, H, W])
+# --------------------------------------------------------------------------
+
+def stencil(p: np.ndarray, kw: int, kh: int, ax: int, ay: int,
+            weights, scale: float) -> np.ndarray:
+    """S_c(x, y) = scale * sum_{j<kh, i<kw} w[j][i] * P_c(clamp(x+i-ax), clamp(y+j-ay)).
+
+    A constant-offset producer-consumer dependence (Section 2.3's dependence
+    vectors), with the clamp-to-edge boundary reading.
+    """
+    c, h, w = p.shape
+    wts = np.asarray(weights, dtype=np.float64).reshape(kh, kw)
+    xs = np.arange(w)
+    ys = np.arange(h)
+    acc = np.zeros((c, h, w), dtype=np.float64)
+    for j in range(kh):
+        yi = np.clip(ys + j - ay, 0, h - 1)
+        for i in range(kw):
+            if wts[j, i] == 0.0:
+                continue
+            xi = np.clip(xs + i - ax, 0, w - 1)
+            acc += wts[j, i] * p[:, yi][:, :, xi]
+    return float(scale) * acc
+
+
+def down2(p: np.ndarray) -> np.ndarray:
+    """D(x, y) = P(2x, 2y) over ceil(W/2) x ceil(H/2)."""
+    return p[:, 0::2, 0::2].copy()
+
+
+def _expand_axis(p: np.ndarray, axis: int, n_out: int) -> np.ndarray:
+    n_in = p.shape[axis]
+    out_shape = list(p.shape)
+    out_shape[axis] = n_out
+    out = np.empty(out_shape, dtype=np.float64)
+    for x in range(n_out):
+        i = x // 2
+        if x % 2 == 0:
+            a = np.take(p, min(max(i - 1, 0), n_in - 1), axis=axis)
+            b = np.take(p, min(i, n_in - 1), axis=axis)
+            c = np.take(p, min(i + 1, n_in - 1), axis=axis)
+            v = (a + 6.0 * b + c) / 8.0
+        else:
+            a = np.take(p, min(i, n_in - 1), axis=axis)
+            b = np.take(p, min(i + 1, n_in - 1), axis=axis)
+            v = (a + b) / 2.0
+        idx = [slice(None)] * p.ndim
+        idx[axis] = x
+        out[tuple(idx)] = v
+    return out
+
+
+def up2(p: np.ndarray, out_w: int, out_h: int) -> np.ndarray:
+    """Separable 2x binomial expansion, x first then y, to out_w x out_h."""
+    return _expand_axis(_expand_axis(p, 2, out_w), 1, out_h)
+
+
+# --------------------------------------------------------------------------
+# Pointwise expressions: own parser on top of Python's ``ast`` grammar
+# --------------------------------------------------------------------------
+
+_FUNCS = {"abs": 1, "min": 2, "max": 2, "select": 3, "sqrt": 1, "floor": 1}
+_CMP = {ast.Lt: np.less, ast.LtE: np.less_equal, ast.Gt: np.greater,
+        ast.GtE: np.greater_equal}
+
+
+def parse_expr(expr: str) -> ast.AST:
+    """Parses the pointwise expression language and rejects anything outside it.
+
+    Grammar: numbers, ``s<i>`` and ``s<i>[k]`` source references, unary minus,
+    + - * /, one comparison (< <= > >=), and calls abs, min, max, select,
+    sqrt, floor.
+    """
+    tree = ast.parse(expr, mode="eval")
+    for node in ast.walk(tree):
+        ok = isinstance(node, (ast.Expression, ast.BinOp, ast.UnaryOp, ast.Call,
+                               ast.Compare, ast.Name, ast.Constant, ast.Subscript,
+                               ast.Load, ast.Add, ast.Sub, ast.Mult, ast.Div,
+                               ast.USub, ast.UAdd, ast.Lt, ast.LtE, ast.Gt, ast.GtE))
+        if not ok:
+            raise ValueError(f"unsupported syntax {type(node).__name__} in {expr!r}")
+        if isinstance(node, ast.Call):
+            if not isinstance(node.func, ast.Name) or node.func.id not in _FUNCS:
+                raise ValueError(f"unknown function in {expr!r}")
+            if len(node.args) != _FUNCS[node.func.id] or node.keywords:
+                raise ValueError(f"wrong arity for {node.func.id} in {expr!r}")
+        if isinstance(node, ast.Compare) and len(node.ops) != 1:
+            raise ValueError(f"chained comparison in {expr!r}")
+        if isinstance(node, ast.Name) and node.id not in _FUNCS:
+            if not (node.id.startswith("s") and node.id[1:].isdigit()):
+                raise ValueError(f"unknown name {node.id!r} in {expr!r}")
+    return tree
+
+
+def _eval(node, srcs, ch):
+    if isinstance(node, ast.Expression):
+        return _eval(node.body, srcs, ch)
+    if isinstance(node, ast.Constant):
+        return float(node.value)
+    if isinstance(node, ast.Name):
+        s = srcs[int(node.id[1:])]
+        return s[ch] if s.shape[0] > 1 else s[0]
+    if isinstance(node, ast.Subscript):
+        s = srcs[int(node.value.id[1:])]
+        k = node.slice.value if isinstance(node.slice, ast.Constant) else None
+        if not isinstance(k, int) or not 0 <= k < s.shape[0]:
+            raise ValueError("bad channel subscript")
+        return s[k]
+    if isinstance(node, ast.UnaryOp):
+        v = _eval(node.operand, srcs, ch)
+        return -v if isinstance(node.op, ast.USub) else v
+    if isinstance(node, ast.BinOp):
+        a = _eval(node.left, srcs, ch)
+        b = _eval(node.right, srcs, ch)
+        if isinstance(node.op, ast.Add):
+            return a + b
+        if isinstance(node.op, ast.Sub):
+            return a - b
+        if isinstance(node.op, ast.Mult):
+            return a * b
+        return a / b
+    if isinstance(node, ast.Compare):
+        return _CMP[type(node.ops[0])](_eval(node.left, srcs, ch),
+                                       _eval(node.comparators[0], srcs, ch))
+    if isinstance(node, ast.Call):
+        args = [_eval(a, srcs, ch) for a in node.args]
+        f = node.func.id
+        if f == "abs":
+            return np.abs(args[0])
+        if f == "min":
+            return np.minimum(args[0], args[1])
+        if f == "max":
+            return np.maximum(args[0], args[1])
+        if f == "sqrt":
+            return np.sqrt(args[0])
+        if f == "floor":
+            return np.floor(args[0])
+        return np.where(args[0], args[1], args[2])
+    raise ValueError("unsupported node")
+
+
+def pointwise(expr: str, srcs, channels: int) -> np.ndarray:
+    """Evaluates ``expr`` at every point of every output channel in float64."""
+    tree = parse_expr(expr)
+    shape = None
+    for s in srcs:
+        if shape is None:
+            shape = s.shape[1:]
+        elif s.shape[1:] != shape:
+            raise ValueError("pointwise sources must share one domain")
+    out = np.empty((channels,) + tuple(shape), dtype=np.float64)
+    for c in range(channels):
+        out[c] = np.broadcast_to(_eval(tree, srcs, c), shape)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Whole pipelines
+# --------------------------------------------------------------------------
+
+def _levels(spec):
+    lv = {i["name"]: 0 for i in spec["inputs"]}
+    for st in spec["stages"]:
+        k = st["kind"]
+        if k == "stencil":
+            lv[st["name"]] = lv[st["src"]]
+        elif k == "down2":
+            lv[st["name"]] = lv[st["src"]] + 1
+        elif k == "up2":
+            if lv[st["src"]] < 1:
+                raise ValueError("up2 of a level-0 stage")
+            lv[st["name"]] = lv[st["src"]] - 1
+        elif k == "pointwise":
+            ls = {lv[s] for s in st["srcs"]}
+            if len(ls) != 1:
+                raise ValueError("pointwise sources on different levels")
+            lv[st["name"]] = ls.pop()
+        else:
+            raise ValueError(f"unknown stage kind {k!r}")
+    return lv
+
+
+def evaluate_stage(st, vals, lv, width, height):
+    k = st["kind"]
+    if k == "stencil":
+        return stencil(vals[st["src"]], st["kw"], st["kh"], st["ax"], st["ay"],
+                       st["weights"], st["scale"])
+    if k == "down2":
+        return down2(vals[st["src"]])
+    if k == "up2":
+        ow, oh = level_size(width, height, lv[st["name"]])
+        return up2(vals[st["src"]], ow, oh)
+    return pointwise(st["expr"], [vals[s] for s in st["srcs"]], st["channels"])
+
+
+def evaluate(spec: dict, inputs: dict, keep_all: bool = False) -> dict:
+    """Evaluates the pipeline on ``inputs`` (name -> [C, H, W] array).
+
+    Returns the outputs (or every stage when ``keep_all``) as float64 arrays.
+    """
+    lv = _levels(spec)
+    vals = {}
+    shape = None
+    for inp in spec["inputs"]:
+        a = np.asarray(inputs[inp["name"]], dtype=np.float64)
+        if a.ndim == 2:
+            a = a[None]
+        if a.shape[0] != inp["channels"]:
+            raise ValueError(f"input {inp['name']} has {a.shape[0]} channels")
+        if shape is None:
+            shape = a.shape[1:]
+        elif a.shape[1:] != shape:
+            raise ValueError("pipeline inputs must share one size")
+        vals[inp["name"]] = a
+    height, width = shape
+    for st in spec["stages"]:
+        vals[st["name"]] = evaluate_stage(st, vals, lv, width, height)
+    if keep_all:
+        return vals
+    return {name: vals[name] for name in spec["outputs"]}
+
+
+def magnitude(x: np.ndarray) -> float:
+    """max |x| (0 for empty arrays)."""
+    return float(np.max(np.abs(x))) if x.size else 0.0
+
+
+def normwise_error(got: np.ndarray, ref: np.ndarray) -> float:
+    """max_p |got - ref| / max_p |ref| per the whole array (inf-norm relative)."""
+    d = float(np.max(np.abs(got.astype(np.float64) - ref))) if ref.size else 0.0
+    m = magnitude(ref)
+    if m == 0.0:
+        return d
+    return d / m

@@ -1,0 +1,127 @@
+"""Plain-data pipeline descriptions (no arithmetic is performed here).
+
+A pipeline is a dict::
+
+    {"inputs":  [{"name": str, "channels": int}, ...],
+     "stages":  [stage, ...],          # in definition (topological) order
+     "outputs": [name, ...]}
+
+Stage kinds:
+
+* ``stencil``  -- ``src``, ``kw``, ``kh``, anchor ``ax``, ``ay``, row-major
+  ``weights`` (kh*kw numbers) and ``scale``; applied per channel.
+* ``pointwise`` -- ``srcs`` (names), ``expr`` (infix; ``s0``, ``s1``... are the
+  sources at the same channel, ``s0[k]`` is channel k of source 0),
+  ``channels`` (output channel count).
+* ``down2`` / ``up2`` -- ``src``; 2x decimation / 2x expansion.
+
+Every stage's domain is its image size; producer reads outside the domain
+take the value at the nearest edge point (clamp to edge, per stage).
+"""
+from __future__ import annotations
+
+BINOMIAL5 = [1.0, 4.0, 6.0, 4.0, 1.0]
+
+
+def _stencil(name, src, kw, kh, ax, ay, weights, scale):
+    return {"name": name, "kind": "stencil", "src": src, "kw": kw, "kh": kh,
+            "ax": ax, "ay": ay, "weights": list(map(float, weights)),
+            "scale": float(scale)}
+
+
+def _pw(name, srcs, expr, channels):
+    return {"name": name, "kind": "pointwise", "srcs": list(srcs),
+            "expr": expr, "channels": channels}
+
+
+def blur_x(name, src):
+    return _stencil(name, src, 5, 1, 2, 0, BINOMIAL5, 1.0 / 16.0)
+
+
+def blur_y(name, src):
+    return _stencil(name, src, 1, 5, 0, 2, BINOMIAL5, 1.0 / 16.0)
+
+
+def gaussian_blur(channels: int = 1) -> dict:
+    """Two-stage separable 5-tap binomial blur, x then y."""
+    return {"inputs": [{"name": "img", "channels": channels}],
+            "stages": [blur_x("bx", "img"), blur_y("by", "bx")],
+            "outputs": ["by"]}
+
+
+def unsharp_mask(channels: int = 3, weight: float = 1.5,
+                 threshold: float = 0.01) -> dict:
+    """Four-stage unsharp mask: blur x, blur y, sharpen, thresholded select."""
+    return {"inputs": [{"name": "img", "channels": channels}],
+            "stages": [
+                blur_x("bx", "img"),
+                blur_y("by", "bx"),
+                _pw("sharp", ["img", "by"], f"s0 + {weight!r} * (s0 - s1)", channels),
+                _pw("mask", ["img", "by", "sharp"],
+                    f"select(abs(s0 - s1) < {threshold!r}, s0, s2)", channels),
+            ],
+            "outputs": ["mask"]}
+
+
+SOBEL_X = [-1, 0, 1, -2, 0, 2, -1, 0, 1]
+SOBEL_Y = [-1, -2, -1, 0, 0, 0, 1, 2, 1]
+BOX3 = [1] * 9
+
+
+def harris(gray_weights=(0.299, 0.587, 0.114), k: float = 0.04) -> dict:
+    """Harris corner response on an RGB image (ten stages)."""
+    r, g, b = gray_weights
+    return {"inputs": [{"name": "img", "channels": 3}],
+            "stages": [
+                _pw("gray", ["img"], f"{r!r} * s0[0] + {g!r} * s0[1] + {b!r} * s0[2]", 1),
+                _stencil("Ix", "gray", 3, 3, 1, 1, SOBEL_X, 1.0),
+                _stencil("Iy", "gray", 3, 3, 1, 1, SOBEL_Y, 1.0),
+                _pw("Ixx", ["Ix"], "s0 * s0", 1),
+                _pw("Iyy", ["Iy"], "s0 * s0", 1),
+                _pw("Ixy", ["Ix", "Iy"], "s0 * s1", 1),
+                _stencil("Sxx", "Ixx", 3, 3, 1, 1, BOX3, 1.0),
+                _stencil("Syy", "Iyy", 3, 3, 1, 1, BOX3, 1.0),
+                _stencil("Sxy", "Ixy", 3, 3, 1, 1, BOX3, 1.0),
+                _pw("R", ["Sxx", "Syy", "Sxy"],
+                    f"s0 * s1 - s2 * s2 - {k!r} * (s0 + s1) * (s0 + s1)", 1),
+            ],
+            "outputs": ["R"]}
+
+
+def pyramid_blend(levels: int = 4) -> dict:
+    """Laplacian-pyramid blend of A and B under mask M, then collapse.
+
+    Levels 0..levels-1 (levels-1 decimations).  Gaussian levels are
+    G_{l+1} = down2(blur_y(blur_x(G_l))); Laplacian bands L_l = G_l - up2(G_{l+1})
+    with the coarsest band equal to the coarsest Gaussian level; bands are
+    blended as M_l*LA_l + (1-M_l)*LB_l and collapsed by R_l = Lb_l + up2(R_{l+1}).
+    """
+    st = []
+    top = levels - 1
+    for img in ("A", "B", "M"):
+        prev = img
+        for l in range(top):
+            st.append(blur_x(f"{img}bx{l}", prev))
+            st.append(blur_y(f"{img}by{l}", f"{img}bx{l}"))
+            st.append({"name": f"{img}G{l + 1}", "kind": "down2", "src": f"{img}by{l}"})
+            prev = f"{img}G{l + 1}"
+
+    def G(img, l):
+        return img if l == 0 else f"{img}G{l}"
+
+    for img in ("A", "B"):
+        for l in range(top):
+            st.append({"name": f"{img}U{l}", "kind": "up2", "src": G(img, l + 1)})
+            st.append(_pw(f"{img}L{l}", [G(img, l), f"{img}U{l}"], "s0 - s1", 1))
+    for l in range(levels):
+        la = f"AL{l}" if l < top else G("A", top)
+        lb = f"BL{l}" if l < top else G("B", top)
+        st.append(_pw(f"Lb{l}", [G("M", l), la, lb], "s0 * s1 + (1.0 - s0) * s2", 1))
+    prev = f"Lb{top}"
+    for l in range(top - 1, -1, -1):
+        st.append({"name": f"RU{l}", "kind": "up2", "src": prev})
+        st.append(_pw(f"R{l}", [f"Lb{l}", f"RU{l}"], "s0 + s1", 1))
+        prev = f"R{l}"
+    return {"inputs": [{"name": "A", "channels": 1}, {"name": "B", "channels": 1},
+                       {"name": "M", "channels": 1}],
+            "stages": st, "outputs": ["R0"]}
