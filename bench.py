@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the fused wave-tiled unsharp-mask pipeline on one MI355X.
+
+Workload: 4-stage unsharp mask (5-tap binomial blur in x, blur in y,
+sharpen = img + 1.5 (img - blur), select(|img - blur| < 0.01, img, sharpen))
+on a 3x2048x2048 FP32 image, pixels uniform in [0, 1) from a seeded
+splitmix64 stream.  One step = one run of the whole pipeline over the image.
+
+value = output Mpixels/s of the fused path (one kernel per step), with the
+inputs resident in HBM.  Input/output buffer sets rotate over more than the
+256 MB Infinity Cache so each step reads from and writes to HBM.  The unfused
+path (one kernel per stage, intermediates through HBM), the FP16-intermediate
+variant and the FP64 oracle on the host cores are reported beside it.
+
+Roofline: algorithmic bytes = 12 B in + 12 B out per output pixel (3 FP32
+channels), divided by the fused kernel's average duration over the timed
+region (HIP events on the launch stream), against MI355X's 8 TB/s HBM peak.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixels/s per pipeline, fused vs unfused on 1 GPU; % of HBM roofline"
+C, H, W = 3, 2048, 2048
+BYTES_PER_PX = 24  # 3 channels x (4 B in + 4 B out)
+HBM_PEAK_GBS = 8000.0
+DEFAULT_FUSED = "nodes=1,2,3,4 V=4 TX=1 SX=0 TY=16 PF=2"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_sets(torch, img, nsets):
+    dev = torch.device("cuda:0")
+    base = torch.from_numpy(img).to(dev)
+    ins, outs = [], []
+    for i in range(nsets):
+        x = base.clone() if i else base
+        ins.append(x)
+        outs.append(torch.empty_like(x))
+    return ins, outs
+
+
+def calibrate_sleep(torch):
+    """GPU spin cycles per millisecond of torch.cuda._sleep."""
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    torch.cuda._sleep(10_000_000)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = max(e0.elapsed_time(e1), 1e-3)
+    return 10_000_000 / ms
+
+
+def time_plan(torch, plan, ins, outs, steps, warmup, cycles_per_ms):
+    """Average ms per step over `steps` back-to-back runs on the current
+    stream.  The stream is held by a GPU spin while the launches are queued,
+    so host launch overhead does not appear as gaps between kernels."""
+    n = len(ins)
+    t0 = time.perf_counter()
+    for i in range(warmup):
+        plan.run([ins[i % n]], [outs[i % n]])
+    torch.cuda.synchronize()
+    host_ms = (time.perf_counter() - t0) * 1e3 / max(warmup, 1)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    torch.cuda._sleep(int(cycles_per_ms * (host_ms * steps * 1.5 + 5.0)))
+    e0.record(s)
+    for i in range(steps):
+        plan.run([ins[i % n]], [outs[i % n]])
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cpu_baseline(img, seconds=10.0):
+    """The FP64 oracle, as it stands, on a band of rows of the same image."""
+    import numpy as np
+    import oracle
+    from synth import pipelines as P
+    spec = P.unsharp_mask()
+    rows = 128
+    band = np.ascontiguousarray(img[:, :rows, :])
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        oracle.evaluate(spec, {"img": band})
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    per = el / n
+    return {"value": rows * W / per / 1e6, "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
+            "sample": f"rows 0..{rows - 1} of the 3x{H}x{W} input ({n} runs, {el:.1f} s; "
+                      "numpy float64, single-threaded)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--mode", default="fixed", help="schedule mode of the fused path")
+    ap.add_argument("--schedule", default=DEFAULT_FUSED, help="fixed schedule of the fused path")
+    ap.add_argument("--sets", type=int, default=6, help="rotating buffer sets (>256 MB total)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the unfused and FP16 legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(tiles and images are independent; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1909_07190_amd as wt
+    import synth
+    from synth import pipelines as P
+
+    img = synth.uniform_image(2, C, H, W)
+    ins, outs = make_sets(torch, img, args.sets)
+    cyc = calibrate_sleep(torch)
+    spec = P.unsharp_mask()
+    fixed = args.schedule if args.mode == "fixed" else None
+
+    log(f"fused plan ({args.mode}: {fixed})")
+    fused = wt.from_spec(spec).plan(W, H, mode=args.mode, fixed=fixed)
+    ms = time_plan(torch, fused, ins, outs, args.steps, args.warmup, cyc)
+    mpix = H * W / (ms * 1e-3) / 1e6
+    achieved = BYTES_PER_PX * H * W / (ms * 1e-3) / 1e9
+    log(f"fused: {ms * 1e3:.2f} us/step, {mpix:.0f} Mpix/s, {achieved:.0f} GB/s")
+    ref_out = outs[(args.steps - 1) % len(outs)].clone()
+
+    extra = {}
+    if not args.no_extra:
+        unf = wt.from_spec(spec).plan(W, H, mode="unfused")
+        ms_u = time_plan(torch, unf, ins, outs, args.steps, args.warmup, cyc)
+        chk = outs[(args.steps - 1) % len(outs)]
+        diff = float((chk - ref_out).abs().max() / ref_out.abs().max())
+        extra["unfused"] = {"value": H * W / (ms_u * 1e-3) / 1e6, "ms_per_step": ms_u,
+                            "kernels_per_step": unf.num_groups, "fused_speedup": ms_u / ms,
+                            "max_rel_diff_vs_fused": diff}
+        log(f"unfused: {ms_u * 1e3:.2f} us/step ({unf.num_groups} kernels), fused speedup {ms_u / ms:.2f}x")
+        f16 = wt.from_spec(spec).plan(W, H, mode="fixed", fixed=(fixed or DEFAULT_FUSED) + " fp16=1",
+                                      fp16=True)
+        ms_h = time_plan(torch, f16, ins, outs, args.steps, args.warmup, cyc)
+        extra["fp16_intermediates"] = {"value": H * W / (ms_h * 1e-3) / 1e6, "ms_per_step": ms_h}
+        log(f"fp16 intermediates: {ms_h * 1e3:.2f} us/step")
+    cpu = None if args.no_cpu else cpu_baseline(img)
+    if cpu:
+        log(f"oracle: {cpu['value']:.2f} Mpix/s on {cpu['cores']} core(s)")
+
+    out = {
+        "metric": METRIC, "value": mpix, "unit": "Mpixels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "unsharp mask 3x2048x2048 FP32, uniform [0,1) seed 2; "
+                               "blur x, blur y, sharpen, select fused in one wave-tiled kernel",
+                   "schedule": fused.describe().strip(), "buffer_sets": args.sets},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

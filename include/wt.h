@@ -1,0 +1,162 @@
+/*
+ * wavetile -- fused wave-tiled stencil pipelines for MI355X (gfx950).
+ *
+ * C ABI of the library.  No C++ types cross this boundary; every call returns
+ * a wt_status and, on failure, leaves a message retrievable with
+ * wt_last_error() (thread-local, valid until the next failing call on the
+ * same thread).  No call throws.
+ *
+ * The operation (the paper, Sections 2.2-2.3 and Fig. 2): an image-processing
+ * pipeline is a DAG of stages; each stage is a function over an integer
+ * domain whose value at a point is an expression of producer values at
+ * constant offsets (dependence vectors).  The library evaluates the pipeline
+ * by fusing stages into groups executed as overlapped tiles, one tile per
+ * 64-lane wavefront (Section 4), storing each tile partly in VGPRs and partly
+ * in LDS (hybrid tiling, Section 5 and Algorithm 1), with fusion and tile
+ * sizes chosen by a cost model (Section 6 and Algorithm 2).
+ *
+ * Boundary reading used throughout (the paper uses interior-only domains):
+ * every stage's domain is its full image size, and a producer read outside
+ * the producer's domain takes the value at the nearest domain point (clamp
+ * to edge, applied per stage).
+ *
+ * Images are planar (channel-major), row-major, with strides in ELEMENTS.
+ * Pixel buffers are device memory owned by the caller; the library never
+ * frees or retains them beyond a call.
+ */
+#ifndef WAVETILE_WT_H
+#define WAVETILE_WT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WT_OK = 0,
+    WT_E_INVALID = -1,     /* bad argument or malformed pipeline             */
+    WT_E_UNSUPPORTED = -2, /* valid request the library does not handle      */
+    WT_E_SHAPE = -3,       /* image size / channels / alignment mismatch     */
+    WT_E_NOMEM = -4,       /* device or host allocation failed               */
+    WT_E_COMPILE = -5,     /* run-time compilation of a kernel failed        */
+    WT_E_HIP = -6,         /* a HIP runtime call failed (incl. async faults) */
+    WT_E_INTERNAL = -7
+} wt_status;
+
+typedef enum { WT_F32 = 0, WT_F16 = 1 } wt_dtype;
+
+typedef enum { WT_DOWN2 = 0, WT_UP2 = 1 } wt_resample_kind;
+
+typedef struct {
+    void* data;          /* device pointer to channel 0, row 0, column 0        */
+    int32_t width;
+    int32_t height;
+    int32_t channels;
+    int32_t dtype;       /* wt_dtype                                            */
+    int64_t row_stride;  /* elements between rows; 0 means width                */
+    int64_t chan_stride; /* elements between channel planes; 0 = height*row_stride */
+} wt_image;
+
+typedef struct wt_pipeline wt_pipeline; /* opaque */
+typedef struct wt_plan wt_plan;         /* opaque */
+
+/* ---------------------------------------------------------------------- */
+/* Pipeline construction.  Node ids are dense, in creation order; inputs and  */
+/* stages share one id space.  A pipeline is immutable once a plan uses it.   */
+/* ---------------------------------------------------------------------- */
+
+wt_status wt_pipeline_create(wt_pipeline** out);
+void wt_pipeline_destroy(wt_pipeline* p);
+
+/* An input image with `channels` planes. */
+wt_status wt_input(wt_pipeline* p, int channels, int* id);
+
+/* Stencil stage, per channel (the paper's Stencil / Correlate stages, Fig. 2):
+ *   S_c(x,y) = scale * sum_{j<kh, i<kw} weights[j*kw+i] * P_c(x+i-ax, y+j-ay)
+ * with clamp-to-edge producer reads.  `weights` (kh*kw values, row-major) is
+ * copied.  Kernel sides 1..15. */
+wt_status wt_stencil(wt_pipeline* p, int src, int kw, int kh, int ax, int ay,
+                     const double* weights, double scale, int* id);
+
+/* Pointwise stage (the paper's Function with a Case expression, Fig. 2).
+ * `expr` is infix over s0..s{nsrc-1} (source i at the same channel; a
+ * one-channel source broadcasts) and s<i>[k] (channel k of source i), with
+ * numbers, unary -, + - * /, one comparison (< <= > >=) inside
+ * select(cond, a, b), and abs, min, max, sqrt, floor.  All sources must lie
+ * on the same pyramid level.  Output has `out_channels` planes. */
+wt_status wt_pointwise(wt_pipeline* p, const int* srcs, int nsrc,
+                       const char* expr, int out_channels, int* id);
+
+/* 2x resampling (scaled dependences, Section 5's alignment and scaling):
+ *   WT_DOWN2: D(x,y) = P(2x,2y), domain ceil(W/2) x ceil(H/2);
+ *   WT_UP2:   separable binomial expansion, even 2i -> (P(i-1)+6P(i)+P(i+1))/8,
+ *             odd 2i+1 -> (P(i)+P(i+1))/2, to the next finer level's domain. */
+wt_status wt_resample(wt_pipeline* p, int src, int kind, int* id);
+
+/* Marks a node as a pipeline output (outputs are numbered in call order). */
+wt_status wt_output(wt_pipeline* p, int id);
+
+/* ---------------------------------------------------------------------- */
+/* Planning                                                                  */
+/* ---------------------------------------------------------------------- */
+
+typedef enum {
+    WT_SCHED_UNFUSED = 0,  /* one kernel per stage, intermediates in HBM      */
+    WT_SCHED_ANALYTIC = 1, /* DP fusion with the analytical cost (Alg. 2)      */
+    WT_SCHED_MLP = 2,      /* DP fusion ranked by the learned cost model       */
+    WT_SCHED_AUTOTUNE = 3, /* analytic top-k candidates, measured on device    */
+    WT_SCHED_FIXED = 4     /* schedule text in `fixed_schedule`                */
+} wt_sched_mode;
+
+enum {
+    WT_PLAN_NO_DEVICE = 1 /* generate and compile code only; run() refused   */
+};
+
+typedef struct {
+    int32_t mode;               /* wt_sched_mode                               */
+    int32_t fp16_intermediates; /* store fused/materialised intermediates FP16 */
+    int32_t flags;              /* WT_PLAN_* bits                              */
+    int32_t autotune_topk;      /* candidates measured in WT_SCHED_AUTOTUNE    */
+    const char* fixed_schedule; /* WT_SCHED_FIXED (see wt_plan_describe)       */
+    const char* model_path;     /* WT_SCHED_MLP weights file                   */
+    const char* cache_dir;      /* code-object cache; NULL = $WT_CACHE_DIR or none */
+} wt_sched_opts;
+
+/* Plans `p` for width x height inputs: fusion, tile sizes, code generation and
+ * compilation.  `opts` may be NULL (analytic mode, FP32).  Allocates device
+ * buffers for intermediates materialised between groups. */
+wt_status wt_plan_create(const wt_pipeline* p, const wt_sched_opts* opts,
+                         int width, int height, wt_plan** out);
+
+/* Runs the plan asynchronously on `hip_stream` (a hipStream_t; NULL = the
+ * default stream).  in[i] is input i (creation order), out[i] output i; sizes
+ * must equal the planned ones.  Inputs and outputs must not alias. */
+wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
+                      const wt_image* out, int nout, void* hip_stream);
+
+/* Schedule as text: one line per group,
+ *   "g<i> nodes=<id,id,...> V=<v> TX=<t> SX=<s> TY=<rows> WPB=<w> fp16=<0|1>"
+ * The same text (lines or ';'-separated) is accepted by WT_SCHED_FIXED.
+ * Writes at most `len` bytes including the terminator; *needed gets the full
+ * size. */
+wt_status wt_plan_describe(const wt_plan* plan, char* buf, size_t len, size_t* needed);
+
+/* HIP source generated for group `group`. */
+wt_status wt_plan_source(const wt_plan* plan, int group, char* buf, size_t len,
+                         size_t* needed);
+
+/* Number of kernel launches per run. */
+int wt_plan_num_groups(const wt_plan* plan);
+
+/* Destroys the plan; its stream must have drained. */
+void wt_plan_destroy(wt_plan* plan);
+
+const char* wt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVETILE_WT_H */

@@ -1,0 +1,215 @@
+"""wavetile: fused wave-tiled stencil pipelines on MI355X (gfx950).
+
+Thin ctypes binding over the C ABI in ``include/wt.h``: argument marshalling
+only.  Every step of a pipeline runs in the library's generated HIP kernels;
+there is no Python or CPU fallback, and importing this package fails loudly
+when ``libwavetile.so`` has not been built.  PyTorch supplies device memory
+and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["Pipeline", "Plan", "WtError", "lib", "SCHED", "from_spec", "LIB_PATH"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwavetile.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1909_07190_amd.build` "
+                      "(or __graft_entry__.build()) first")
+lib = ctypes.CDLL(LIB_PATH)
+
+SCHED = {"unfused": 0, "analytic": 1, "mlp": 2, "autotune": 3, "fixed": 4}
+DOWN2, UP2 = 0, 1
+F32, F16 = 0, 1
+PLAN_NO_DEVICE = 1
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+
+
+class WtImage(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("row_stride", ctypes.c_int64), ("chan_stride", ctypes.c_int64)]
+
+
+class WtSchedOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("fp16_intermediates", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("autotune_topk", ctypes.c_int32),
+                ("fixed_schedule", ctypes.c_char_p), ("model_path", ctypes.c_char_p),
+                ("cache_dir", ctypes.c_char_p)]
+
+
+def _sig(name, restype, *args):
+    f = getattr(lib, name)
+    f.restype = restype
+    f.argtypes = list(args)
+    return f
+
+
+_sig("wt_last_error", ctypes.c_char_p)
+_sig("wt_pipeline_create", ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
+_sig("wt_pipeline_destroy", None, ctypes.c_void_p)
+_sig("wt_input", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, _c_int_p)
+_sig("wt_stencil", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double, _c_int_p)
+_sig("wt_pointwise", ctypes.c_int, ctypes.c_void_p, _c_int_p, ctypes.c_int, ctypes.c_char_p,
+     ctypes.c_int, _c_int_p)
+_sig("wt_resample", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p)
+_sig("wt_output", ctypes.c_int, ctypes.c_void_p, ctypes.c_int)
+_sig("wt_plan_create", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtSchedOpts), ctypes.c_int,
+     ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
+_sig("wt_plan_run", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtImage), ctypes.c_int,
+     ctypes.POINTER(WtImage), ctypes.c_int, ctypes.c_void_p)
+_sig("wt_plan_describe", ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t,
+     ctypes.POINTER(ctypes.c_size_t))
+_sig("wt_plan_source", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t,
+     ctypes.POINTER(ctypes.c_size_t))
+_sig("wt_plan_num_groups", ctypes.c_int, ctypes.c_void_p)
+_sig("wt_plan_destroy", None, ctypes.c_void_p)
+
+
+class WtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"wavetile error {status}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st != 0:
+        raise WtError(st, lib.wt_last_error().decode(errors="replace"))
+
+
+class Pipeline:
+    """Builder for a pipeline DAG; node ids are returned by each call."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib.wt_pipeline_create(ctypes.byref(h)))
+        self._h = h
+        self.names: dict[str, int] = {}
+        self.channels: dict[int, int] = {}
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib.wt_pipeline_destroy(self._h)
+            self._h = None
+
+    def input(self, channels: int) -> int:
+        i = ctypes.c_int()
+        _check(lib.wt_input(self._h, channels, ctypes.byref(i)))
+        self.channels[i.value] = channels
+        return i.value
+
+    def stencil(self, src, kw, kh, ax, ay, weights, scale=1.0) -> int:
+        w = (ctypes.c_double * (kw * kh))(*[float(v) for v in weights])
+        i = ctypes.c_int()
+        _check(lib.wt_stencil(self._h, src, kw, kh, ax, ay, w, float(scale), ctypes.byref(i)))
+        self.channels[i.value] = self.channels[src]
+        return i.value
+
+    def pointwise(self, srcs, expr: str, channels: int) -> int:
+        arr = (ctypes.c_int * len(srcs))(*srcs)
+        i = ctypes.c_int()
+        _check(lib.wt_pointwise(self._h, arr, len(srcs), expr.encode(), channels, ctypes.byref(i)))
+        self.channels[i.value] = channels
+        return i.value
+
+    def resample(self, src, kind) -> int:
+        i = ctypes.c_int()
+        _check(lib.wt_resample(self._h, src, kind, ctypes.byref(i)))
+        self.channels[i.value] = self.channels[src]
+        return i.value
+
+    def output(self, node: int):
+        _check(lib.wt_output(self._h, node))
+
+    def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
+             no_device=False, model_path=None, cache_dir=None, autotune_topk=0) -> "Plan":
+        return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
+                    autotune_topk)
+
+
+def from_spec(spec: dict) -> Pipeline:
+    """Builds a Pipeline from a plain-data description (see synth.pipelines)."""
+    p = Pipeline()
+    for inp in spec["inputs"]:
+        p.names[inp["name"]] = p.input(inp["channels"])
+    for st in spec["stages"]:
+        k = st["kind"]
+        if k == "stencil":
+            i = p.stencil(p.names[st["src"]], st["kw"], st["kh"], st["ax"], st["ay"],
+                          st["weights"], st["scale"])
+        elif k == "pointwise":
+            i = p.pointwise([p.names[s] for s in st["srcs"]], st["expr"], st["channels"])
+        elif k in ("down2", "up2"):
+            i = p.resample(p.names[st["src"]], DOWN2 if k == "down2" else UP2)
+        else:
+            raise ValueError(f"unknown stage kind {k!r}")
+        p.names[st["name"]] = i
+    for o in spec["outputs"]:
+        p.output(p.names[o])
+    return p
+
+
+def _image(t) -> WtImage:
+    import torch
+    if not t.is_cuda:
+        raise ValueError("images must be device tensors")
+    if t.dtype != torch.float32:
+        raise ValueError("images must be float32")
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.stride(2) != 1:
+        raise ValueError("images must be [C, H, W] with unit column stride")
+    c, h, w = t.shape
+    return WtImage(t.data_ptr(), w, h, c, F32, t.stride(1), t.stride(0))
+
+
+class Plan:
+    """A compiled schedule for one image size."""
+
+    def __init__(self, pipe: Pipeline, width, height, mode, fp16, fixed, no_device,
+                 model_path, cache_dir, autotune_topk):
+        self.pipe = pipe  # keeps the pipeline alive
+        opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), PLAN_NO_DEVICE if no_device else 0,
+                           autotune_topk, fixed.encode() if fixed else None,
+                           model_path.encode() if model_path else None,
+                           cache_dir.encode() if cache_dir else None)
+        h = ctypes.c_void_p()
+        _check(lib.wt_plan_create(pipe._h, ctypes.byref(opts), width, height, ctypes.byref(h)))
+        self._h = h
+        self.width, self.height = width, height
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib.wt_plan_destroy(self._h)
+            self._h = None
+
+    def run(self, inputs, outputs, stream=None):
+        """Launches the plan on `stream` (default: torch's current stream)."""
+        import torch
+        ins = (WtImage * max(1, len(inputs)))(*[_image(t) for t in inputs])
+        outs = (WtImage * max(1, len(outputs)))(*[_image(t) for t in outputs])
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(lib.wt_plan_run(self._h, ins, len(inputs), outs, len(outputs), ctypes.c_void_p(s)))
+
+    def describe(self) -> str:
+        n = ctypes.c_size_t()
+        _check(lib.wt_plan_describe(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib.wt_plan_describe(self._h, buf, n.value, None))
+        return buf.value.decode()
+
+    def source(self, group: int) -> str:
+        n = ctypes.c_size_t()
+        _check(lib.wt_plan_source(self._h, group, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib.wt_plan_source(self._h, group, buf, n.value, None))
+        return buf.value.decode()
+
+    @property
+    def num_groups(self) -> int:
+        return lib.wt_plan_num_groups(self._h)

@@ -1,0 +1,221 @@
+// The C ABI (include/wt.h): argument checking, error translation and the
+// pipeline builder.  No exception crosses this boundary.
+#include <cmath>
+#include <functional>
+#include <cstring>
+#include <string>
+
+#include "wt_internal.h"
+#include "wt_runtime.h"
+
+struct wt_pipeline {
+    wt::Pipeline p;
+};
+struct wt_plan {
+    std::unique_ptr<wt::Plan> impl;
+};
+
+namespace {
+thread_local std::string g_err;
+
+template <class F>
+wt_status guard(F&& f) {
+    try {
+        f();
+        return WT_OK;
+    } catch (const wt::Error& e) {
+        g_err = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_err = "out of host memory";
+        return WT_E_NOMEM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return WT_E_INTERNAL;
+    }
+}
+
+wt::Node& new_node(wt_pipeline* p, wt::Kind k) {
+    p->p.nodes.emplace_back();
+    wt::Node& n = p->p.nodes.back();
+    n.kind = k;
+    n.id = (int)p->p.nodes.size() - 1;
+    return n;
+}
+
+void check_src(const wt_pipeline* p, int src) {
+    if (src < 0 || src >= (int)p->p.nodes.size()) wt::fail(WT_E_INVALID, "unknown source node " + std::to_string(src));
+}
+}  // namespace
+
+extern "C" {
+
+const char* wt_last_error(void) { return g_err.c_str(); }
+
+wt_status wt_pipeline_create(wt_pipeline** out) {
+    return guard([&] {
+        if (!out) wt::fail(WT_E_INVALID, "null output pointer");
+        *out = new wt_pipeline();
+    });
+}
+
+void wt_pipeline_destroy(wt_pipeline* p) { delete p; }
+
+wt_status wt_input(wt_pipeline* p, int channels, int* id) {
+    return guard([&] {
+        if (!p || !id) wt::fail(WT_E_INVALID, "null argument");
+        if (channels < 1 || channels > 16) wt::fail(WT_E_INVALID, "channels must be in 1..16");
+        wt::Node& n = new_node(p, wt::Kind::Input);
+        n.channels = channels;
+        n.bound = 1.0;
+        p->p.inputs.push_back(n.id);
+        *id = n.id;
+    });
+}
+
+wt_status wt_stencil(wt_pipeline* p, int src, int kw, int kh, int ax, int ay, const double* weights,
+                     double scale, int* id) {
+    return guard([&] {
+        if (!p || !id || !weights) wt::fail(WT_E_INVALID, "null argument");
+        check_src(p, src);
+        if (kw < 1 || kw > 15 || kh < 1 || kh > 15) wt::fail(WT_E_INVALID, "stencil sides must be in 1..15");
+        if (ax < 0 || ax >= kw || ay < 0 || ay >= kh) wt::fail(WT_E_INVALID, "stencil anchor outside the kernel");
+        if (!std::isfinite(scale)) wt::fail(WT_E_INVALID, "non-finite scale");
+        double absum = 0.0;
+        for (int i = 0; i < kw * kh; ++i) {
+            if (!std::isfinite(weights[i])) wt::fail(WT_E_INVALID, "non-finite weight");
+            absum += std::fabs(weights[i]);
+        }
+        const wt::Node s = p->p.nodes[src];
+        wt::Node& n = new_node(p, wt::Kind::Stencil);
+        n.srcs = {src};
+        n.channels = s.channels;
+        n.level = s.level;
+        n.kw = kw;
+        n.kh = kh;
+        n.ax = ax;
+        n.ay = ay;
+        n.weights.assign(weights, weights + kw * kh);
+        n.scale = scale;
+        n.bound = absum * std::fabs(scale) * s.bound;
+        *id = n.id;
+    });
+}
+
+wt_status wt_pointwise(wt_pipeline* p, const int* srcs, int nsrc, const char* expr, int out_channels, int* id) {
+    return guard([&] {
+        if (!p || !id || !srcs || !expr) wt::fail(WT_E_INVALID, "null argument");
+        if (nsrc < 1 || nsrc > 8) wt::fail(WT_E_INVALID, "pointwise stages take 1..8 sources");
+        if (out_channels < 1 || out_channels > 16) wt::fail(WT_E_INVALID, "channels must be in 1..16");
+        std::vector<double> bounds;
+        int level = -1;
+        for (int i = 0; i < nsrc; ++i) {
+            check_src(p, srcs[i]);
+            const wt::Node& s = p->p.nodes[srcs[i]];
+            if (level >= 0 && s.level != level) wt::fail(WT_E_INVALID, "pointwise sources on different levels");
+            level = s.level;
+            bounds.push_back(s.bound);
+        }
+        wt::Expr e = wt::parse_expr(expr, nsrc);
+        for (int i = 0; i < nsrc; ++i) {
+            const wt::Node& s = p->p.nodes[srcs[i]];
+            if (wt::expr_max_channel(e, i) >= s.channels)
+                wt::fail(WT_E_INVALID, "channel subscript beyond source " + std::to_string(i) + "'s channels");
+        }
+        // implicit (same-channel) references need 1 or out_channels channels
+        std::function<void(const wt::Expr&)> chk = [&](const wt::Expr& x) {
+            if (x.op == wt::Expr::Src && x.chan < 0) {
+                int c = p->p.nodes[srcs[x.src]].channels;
+                if (c != 1 && c != out_channels)
+                    wt::fail(WT_E_INVALID, "source s" + std::to_string(x.src) + " has " + std::to_string(c) +
+                                               " channels; use s" + std::to_string(x.src) + "[k]");
+            }
+            for (const auto& k : x.kids) chk(k);
+        };
+        chk(e);
+        wt::Node& n = new_node(p, wt::Kind::Pointwise);
+        n.srcs.assign(srcs, srcs + nsrc);
+        n.channels = out_channels;
+        n.level = level;
+        n.expr_text = expr;
+        n.expr = std::move(e);
+        n.bound = wt::expr_bound(n.expr, bounds);
+        *id = n.id;
+    });
+}
+
+wt_status wt_resample(wt_pipeline* p, int src, int kind, int* id) {
+    return guard([&] {
+        if (!p || !id) wt::fail(WT_E_INVALID, "null argument");
+        check_src(p, src);
+        if (kind != WT_DOWN2 && kind != WT_UP2) wt::fail(WT_E_INVALID, "unknown resample kind");
+        const wt::Node s = p->p.nodes[src];
+        if (kind == WT_UP2 && s.level < 1) wt::fail(WT_E_INVALID, "up2 of a full-resolution node");
+        if (kind == WT_DOWN2 && s.level >= 24) wt::fail(WT_E_INVALID, "too many decimations");
+        wt::Node& n = new_node(p, kind == WT_DOWN2 ? wt::Kind::Down2 : wt::Kind::Up2);
+        n.srcs = {src};
+        n.channels = s.channels;
+        n.level = s.level + (kind == WT_DOWN2 ? 1 : -1);
+        n.bound = s.bound;
+        *id = n.id;
+    });
+}
+
+wt_status wt_output(wt_pipeline* p, int id) {
+    return guard([&] {
+        if (!p) wt::fail(WT_E_INVALID, "null pipeline");
+        check_src(p, id);
+        if (p->p.nodes[id].kind == wt::Kind::Input) wt::fail(WT_E_INVALID, "an input cannot be an output");
+        if (p->p.is_output(id)) wt::fail(WT_E_INVALID, "node already marked as output");
+        p->p.outputs.push_back(id);
+    });
+}
+
+wt_status wt_plan_create(const wt_pipeline* p, const wt_sched_opts* opts, int width, int height, wt_plan** out) {
+    return guard([&] {
+        if (!p || !out) wt::fail(WT_E_INVALID, "null argument");
+        *out = nullptr;
+        auto impl = wt::create_plan(p->p, opts, width, height);
+        *out = new wt_plan{std::move(impl)};
+    });
+}
+
+wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin, const wt_image* out, int nout, void* stream) {
+    return guard([&] {
+        if (!plan) wt::fail(WT_E_INVALID, "null plan");
+        wt::run_plan(*plan->impl, in, nin, out, nout, stream);
+    });
+}
+
+static wt_status copy_out(const std::string& s, char* buf, size_t len, size_t* needed) {
+    if (needed) *needed = s.size() + 1;
+    if (buf && len) {
+        size_t n = std::min(len - 1, s.size());
+        std::memcpy(buf, s.data(), n);
+        buf[n] = '\0';
+    }
+    return WT_OK;
+}
+
+wt_status wt_plan_describe(const wt_plan* plan, char* buf, size_t len, size_t* needed) {
+    wt_status st = guard([&] {
+        if (!plan) wt::fail(WT_E_INVALID, "null plan");
+    });
+    if (st != WT_OK) return st;
+    return copy_out(wt::describe_plan(*plan->impl), buf, len, needed);
+}
+
+wt_status wt_plan_source(const wt_plan* plan, int group, char* buf, size_t len, size_t* needed) {
+    wt_status st = guard([&] {
+        if (!plan) wt::fail(WT_E_INVALID, "null plan");
+        if (group < 0 || group >= (int)plan->impl->groups.size()) wt::fail(WT_E_INVALID, "group out of range");
+    });
+    if (st != WT_OK) return st;
+    return copy_out(plan->impl->groups[group].src, buf, len, needed);
+}
+
+int wt_plan_num_groups(const wt_plan* plan) { return plan ? (int)plan->impl->groups.size() : 0; }
+
+void wt_plan_destroy(wt_plan* plan) { delete plan; }
+
+}  // extern "C"

@@ -1,0 +1,577 @@
+// HIP code generation for fused wave-tile groups.
+//
+// One generated kernel per group.  Each wavefront computes one overlapped
+// tile (OTPW, the paper's Section 4) and synchronises its stages at wave
+// level only.  Every producer load inside the group is classified at
+// generation time into the four load types of hybrid tiling (Section 5,
+// Fig. 4; Algorithm 1 and its generalisation in Appendix A) and emitted as:
+//   (1) a VGPR of the same lane       -> a named register
+//   (2) a value in the LDS sub-tiles  -> ds_read
+//   (3) a VGPR of another lane of the same register sub-tile and
+//   (4) a VGPR of another lane of the previous register sub-tile
+//                                      -> DPP wavefront shift (one-lane
+//                                         distance) or ds_bpermute.
+// Register tiles are fully unrolled into compile-time-indexed arrays (the
+// paper's explicit register naming), and the y direction is streamed with a
+// per-stage ring of rows whose slots are fixed per unrolled step.
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <set>
+#include <sstream>
+
+#include "wt_internal.h"
+#include "wt_device_src.inc"  // kWtDeviceSrc: device/wt_device.h as a string
+
+namespace wt {
+
+std::string device_prelude() { return kWtDeviceSrc; }
+
+namespace {
+
+std::string flit(double v) {
+    char b[64];
+    std::snprintf(b, sizeof b, "%.9e", (double)(float)v);
+    return std::string("(") + b + "f)";
+}
+
+int pmod(int a, int m) { return ((a % m) + m) % m; }
+
+struct Gen {
+    const Pipeline& P;
+    const GroupSched& g;
+    const GroupGeom& geo;
+    std::ostringstream o;
+    int V, SX, RX, N, SUB;
+    std::map<std::string, std::string> memo;  // per unrolled step
+    int tmp = 0;
+    std::string ind = "    ";
+
+    Gen(const Pipeline& p, const GroupSched& gs, const GroupGeom& ge)
+        : P(p), g(gs), geo(ge), V(gs.V), SX(gs.SX), RX(gs.TX - gs.SX), N(ge.N), SUB(64 * gs.V) {}
+
+    const NodeGeom& G(int id) const { return geo.nodes.at(geo.index.at(id)); }
+    std::string I(int v) { return std::to_string(v); }
+    void line(const std::string& s) { o << ind << s << "\n"; }
+
+    bool has_regs(const NodeGeom& n) const { return RX > 0 && (n.consumed || !n.member); }
+    bool has_lds(const NodeGeom& n) const { return SX > 0 && (n.consumed || !n.member); }
+    std::string reg(int id, int slot, int ch, int kr, int e) {
+        return "w" + I(id) + "[" + I(slot) + "][" + I(ch) + "][" + I(kr) + "][" + I(e) + "]";
+    }
+    // LDS element index of (slot, ch, j) of node id
+    std::string lidx(int id, int slot, int ch, const std::string& j) {
+        const NodeGeom& n = G(id);
+        return "L" + I(id) + "[" + I((slot * n.nch + ch) * SX * SUB) + " + (" + j + ")]";
+    }
+    std::string lread(int id, int slot, int ch, const std::string& j) {
+        return "(float)" + lidx(id, slot, ch, j);
+    }
+    std::string fresh(const std::string& pfx) { return pfx + I(tmp++); }
+    std::string memoize(const std::string& expr) {
+        auto it = memo.find(expr);
+        if (it != memo.end()) return it->second;
+        std::string n = fresh("t");
+        line("const float " + n + " = " + expr + ";");
+        memo[expr] = n;
+        return n;
+    }
+
+    // Producer value for consumer c (channel slot of the producer chp) at
+    // sub-tile k, element e, through dependence (dx, dy), at unrolled step ph.
+    // Slot offset delta = dx - (a_p - a_c); q = e + delta locates the source
+    // element relative to this lane's first element.
+    std::string read(int c, int p, int chp, int k, int e, int dx, int dy, int ph) {
+        const NodeGeom& cg = G(c);
+        const NodeGeom& pg = G(p);
+        int drow = pg.lead - cg.lead - dy;
+        if (drow < 0 || drow >= pg.win) fail(WT_E_INTERNAL, "ring window too small");
+        int slot = pmod(ph - drow, pg.win);
+        int delta = dx - (pg.skew - cg.skew);
+        if (g.align == 1 && delta > 0) fail(WT_E_INTERNAL, "skew invariant violated");
+        int q = e + delta;
+        std::string own = I(k * SUB) + " + lane * " + I(V);
+        if (q >= 0 && q < V) {
+            if (k >= SX) return reg(p, slot, chp, k - SX, q);                 // type 1
+            return memoize(lread(p, slot, chp, own + " + " + I(q)));            // type 2
+        }
+        if (q < 0) {
+            int d = (-q + V - 1) / V;
+            int ep = q + d * V;
+            if (d > 63) fail(WT_E_UNSUPPORTED, "dependence distance exceeds one wavefront; raise V");
+            if (k < SX)  // whole read inside the LDS sub-tiles: type 2 for every lane
+                return memoize(lread(p, slot, chp, "max(" + own + " + " + I(q) + ", 0)"));
+            std::string cur = reg(p, slot, chp, k - SX, ep);
+            if (d == 1) {
+                if (k - 1 >= SX)  // types 3 (lanes 1..63) + 4 (lane 0)
+                    return memoize("wt_shift1(" + cur + ", " + reg(p, slot, chp, k - 1 - SX, ep) + ")");
+                if (k - 1 >= 0) {  // types 3 + 2: lane 0 reads the last LDS sub-tile
+                    std::string b = memoize(lread(p, slot, chp, I((k - 1) * SUB + 63 * V + ep)));
+                    return memoize("wt_shr1(" + cur + ", " + b + ")");
+                }
+                // lane 0 belongs to the overlap: any value
+                return memoize("wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(" + cur + "), WT_DPP_WAVE_SHR1, 0xF, 0xF, true))");
+            }
+            if (k - 1 >= SX)
+                return memoize("wt_shiftd(" + cur + ", " + reg(p, slot, chp, k - 1 - SX, ep) + ", " +
+                               I(d) + ", lane)");
+            if (k - 1 >= 0) {
+                std::string pv = memoize(lread(p, slot, chp, I((k - 1) * SUB) + " + ((lane - " + I(d) +
+                                                               ") & 63) * " + I(V) + " + " + I(ep)));
+                return memoize("wt_shiftd_l(" + cur + ", " + pv + ", " + I(d) + ", lane)");
+            }
+            return memoize("wt_shiftd(" + cur + ", " + cur + ", " + I(d) + ", lane)");
+        }
+        // q >= V: source to the right (lane t + d, or the next sub-tile)
+        int d = q / V;
+        int ep = q - d * V;
+        if (d > 63) fail(WT_E_UNSUPPORTED, "dependence distance exceeds one wavefront; raise V");
+        if (k < SX) {
+            std::string lv = memoize(lread(p, slot, chp, "min(" + own + " + " + I(q) + ", " + I(SX * SUB - 1) + ")"));
+            if (k + 1 < SX || SX == g.TX) return lv;  // type 2 (or overlap past the strip)
+            // last LDS sub-tile: lanes t >= 64-d read the first register sub-tile
+            std::string nx = reg(p, slot, chp, 0, ep);
+            std::string rot = d == 1 ? "wt_rol1(" + nx + ")"
+                                     : "wt_as_f(__builtin_amdgcn_ds_bpermute(((lane + " + I(d) +
+                                           ") & 63) << 2, wt_as_i(" + nx + ")))";
+            std::string rv = memoize(rot);
+            return memoize("(lane >= " + I(64 - d) + " ? " + rv + " : " + lv + ")");
+        }
+        std::string cur = reg(p, slot, chp, k - SX, ep);
+        if (k + 1 >= g.TX) {  // lanes past the strip belong to the overlap: any value
+            if (d == 1) return memoize("wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(" + cur + "), WT_DPP_WAVE_SHL1, 0xF, 0xF, true))");
+            return memoize("wt_shiftdn(" + cur + ", " + cur + ", " + I(d) + ", lane)");
+        }
+        std::string next = reg(p, slot, chp, k + 1 - SX, ep);
+        if (d == 1) return memoize("wt_shift1n(" + cur + ", " + next + ")");
+        return memoize("wt_shiftdn(" + cur + ", " + next + ", " + I(d) + ", lane)");
+    }
+
+    int src_chan(const NodeGeom& p, int ch_c, int explicit_ch) {
+        if (explicit_ch >= 0) return explicit_ch;
+        return p.nch == 1 ? 0 : ch_c;
+    }
+
+    std::string expr(const Expr& e, int c, int ch, int k, int el, int ph) {
+        const Node& n = P.nodes[c];
+        auto K = [&](int i) { return expr(e.kids[i], c, ch, k, el, ph); };
+        switch (e.op) {
+            case Expr::Const: return flit(e.value);
+            case Expr::Src: {
+                int p = n.srcs[e.src];
+                return read(c, p, src_chan(G(p), ch, e.chan), k, el, 0, 0, ph);
+            }
+            case Expr::Neg: return "(-" + K(0) + ")";
+            case Expr::Add: return "(" + K(0) + " + " + K(1) + ")";
+            case Expr::Sub: return "(" + K(0) + " - " + K(1) + ")";
+            case Expr::Mul: return "(" + K(0) + " * " + K(1) + ")";
+            case Expr::Div: return "(" + K(0) + " / " + K(1) + ")";
+            case Expr::Lt: return "(" + K(0) + " < " + K(1) + ")";
+            case Expr::Le: return "(" + K(0) + " <= " + K(1) + ")";
+            case Expr::Gt: return "(" + K(0) + " > " + K(1) + ")";
+            case Expr::Ge: return "(" + K(0) + " >= " + K(1) + ")";
+            case Expr::Abs: return "fabsf(" + K(0) + ")";
+            case Expr::Min: return "fminf(" + K(0) + ", " + K(1) + ")";
+            case Expr::Max: return "fmaxf(" + K(0) + ", " + K(1) + ")";
+            case Expr::Sqrt: return "sqrtf(" + K(0) + ")";
+            case Expr::Floor: return "floorf(" + K(0) + ")";
+            case Expr::Select: return "(" + K(0) + " ? " + K(1) + " : " + K(2) + ")";
+        }
+        fail(WT_E_INTERNAL, "bad expression node");
+    }
+
+    std::string value(int c, int ch, int k, int e, int ph) {
+        const Node& n = P.nodes[c];
+        if (n.kind == Kind::Pointwise) return expr(n.expr, c, ch, k, e, ph);
+        int p = n.srcs[0];
+        int chp = src_chan(G(p), ch, -1);
+        std::string acc;
+        for (const Tap& t : P.taps(c, p)) {
+            std::string r = read(c, p, chp, k, e, t.dx, t.dy, ph);
+            if (acc.empty()) acc = flit(t.w) + " * " + r;
+            else acc = "fmaf(" + flit(t.w) + ", " + r + ", " + acc + ")";
+        }
+        return acc;
+    }
+
+    std::string chan_off(int id, bool dst, int slot_idx, int ch) {
+        const NodeGeom& n = G(id);
+        std::string cs = std::string(dst ? "A.dst_cs[" : "A.src_cs[") + I(slot_idx) + "]";
+        if (geo.chan_parallel) return P.nodes[id].channels == 1 ? "0" : "(long long)cp * " + cs;
+        (void)n;
+        return "(long long)" + I(ch) + " * " + cs;
+    }
+
+    // ------------------------------------------------------------ loads --
+    void emit_load(int li, const NodeGeom& n, int ph) {
+        std::string ty = n.mem_half ? "_Float16" : "float";
+        int slot = pmod(ph, n.win);
+        for (int ch = 0; ch < n.nch; ++ch) {
+            line("{  // load node " + I(n.id) + " channel slot " + I(ch) + ", row kk + " + I(n.lead));
+            ind += "    ";
+            line("const int yr = wt_clampi(kk + " + I(n.lead) + ", 0, H - 1);");
+            line("const " + ty + "* rp = (const " + ty + "*)A.src[" + I(li) + "] + " +
+                 chan_off(n.id, false, li, ch) + " + (long long)yr * A.src_rs[" + I(li) + "];");
+            for (int k = 0; k < g.TX; ++k) {
+                // VGPR sub-tiles load straight into their ring registers (no
+                // copy, so the wait for the load falls at its first use);
+                // LDS sub-tiles go through a temporary.
+                std::vector<std::string> dst;
+                std::string v;
+                if (k >= SX) {
+                    for (int e = 0; e < V; ++e) dst.push_back(reg(n.id, slot, ch, k - SX, e));
+                } else {
+                    v = fresh("ld");
+                    line("float " + v + "[" + I(V) + "];");
+                    for (int e = 0; e < V; ++e) dst.push_back(v + "[" + I(e) + "]");
+                }
+                std::string xb = "x0 - " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V);
+                line("{ const int xb = " + xb + ";");
+                if (!border) {
+                    if (V == 1) line("  " + dst[0] + " = (float)rp[xb];");
+                    else {
+                        std::string vt = n.mem_half ? (V == 4 ? "wt_h4" : "wt_h2") : (V == 4 ? "wt_f4" : "wt_f2");
+                        line("  const " + vt + " q = *(const " + vt + "*)(rp + xb);");
+                        for (int e = 0; e < V; ++e) line("  " + dst[e] + " = (float)q[" + I(e) + "];");
+                    }
+                } else {
+                    for (int e = 0; e < V; ++e)
+                        line("  " + dst[e] + " = (float)rp[wt_clampi(xb + " + I(e) + ", 0, W - 1)];");
+                }
+                line("}");
+                if (k < SX) emit_lds_store(n, slot, ch, k, v);
+            }
+            ind.resize(ind.size() - 4);
+            line("}");
+        }
+        if (SX > 0) line("wt_wave_sync();");
+    }
+
+    void emit_lds_store(const NodeGeom& n, int slot, int ch, int k, const std::string& arr) {
+        std::string j = I(k * SUB) + " + lane * " + I(V);
+        std::string base = "&" + lidx(n.id, slot, ch, j);
+        if (n.half) {
+            if (V == 1) line(base.substr(1) + " = (_Float16)" + arr + "[0];");
+            else {
+                std::string vt = V == 4 ? "wt_h4" : "wt_h2";
+                std::string init;
+                for (int e = 0; e < V; ++e) init += (e ? ", " : "") + std::string("(_Float16)") + arr + "[" + I(e) + "]";
+                line("*(" + vt + "*)(" + base + ") = " + vt + "{" + init + "};");
+            }
+        } else {
+            if (V == 1) line(base.substr(1) + " = " + arr + "[0];");
+            else {
+                std::string vt = V == 4 ? "wt_f4" : "wt_f2";
+                std::string init;
+                for (int e = 0; e < V; ++e) init += (e ? ", " : "") + arr + "[" + I(e) + "]";
+                line("*(" + vt + "*)(" + base + ") = " + vt + "{" + init + "};");
+            }
+        }
+    }
+
+    // ----------------------------------------------------------- stores --
+    // Live-out row stored with buffer stores: rows and columns outside the
+    // tile's output range get an offset past the buffer's end, which the
+    // hardware discards, so no branch (and no conservative s_waitcnt at a
+    // control-flow merge) surrounds the store.
+    void emit_store(int oi, const NodeGeom& n, int ch, int k, const std::string& arr, const std::string& R) {
+        std::string rsrc = "S" + I(oi) + "_" + I(ch);
+        int esz = n.mem_half ? 2 : 4;
+        line("{ const int jb = " + I(k * SUB) + " + lane * " + I(V) + ";");
+        line("  const int xp = x0 - " + I(n.skew) + " + jb;");
+        line("  const bool ok = " + R + " >= y0 && " + R + " < kend && " + R + " < H && jb >= " + I(geo.S0) +
+             " && jb < " + I(geo.S0 + geo.X) + ";");
+        line("  const int ob = (int)(((long long)" + R + " * A.dst_rs[" + I(oi) + "] + xp) * " + I(esz) + ");");
+        if (!border) {
+            line("  const int off = ok ? ob : WT_OOB;");
+            if (n.mem_half) {
+                std::string vals;
+                for (int e = 0; e < V; ++e) vals += (e ? ", " : "") + std::string("(_Float16)") + arr + "[" + I(e) + "]";
+                if (V == 1) line("  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)" + arr + "[0]), " + rsrc + ", off, 0, 0);");
+                else if (V == 2) line("  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, wt_h2{" + vals + "}), " + rsrc + ", off, 0, 0);");
+                else line("  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(wt_u2, wt_h4{" + vals + "}), " + rsrc + ", off, 0, 0);");
+            } else {
+                std::string vals;
+                for (int e = 0; e < V; ++e) vals += (e ? ", " : "") + arr + "[" + I(e) + "]";
+                if (V == 1) line("  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, " + arr + "[0]), " + rsrc + ", off, 0, 0);");
+                else if (V == 2) line("  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(wt_u2, wt_f2{" + vals + "}), " + rsrc + ", off, 0, 0);");
+                else line("  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(wt_u4, wt_f4{" + vals + "}), " + rsrc + ", off, 0, 0);");
+            }
+        } else {
+            for (int e = 0; e < V; ++e) {
+                line("  { const int off = (ok && xp + " + I(e) + " >= 0 && xp + " + I(e) + " < W) ? ob + " + I(e * esz) +
+                     " : WT_OOB;");
+                if (n.mem_half)
+                    line("    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)" + arr + "[" +
+                         I(e) + "]), " + rsrc + ", off, 0, 0); }");
+                else
+                    line("    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, " + arr + "[" + I(e) +
+                         "]), " + rsrc + ", off, 0, 0); }");
+            }
+        }
+        line("}");
+    }
+
+    // ----------------------------------------------------- clamp fix-ups --
+    // Positions of a stage row outside [0, W) take the value at x = 0 / W-1
+    // (per-stage clamp to edge); only border waves execute this.
+    void emit_fix_x(const NodeGeom& n, int slot) {
+        line("{  // clamp node " + I(n.id) + " at the image's left/right edge");
+        ind += "    ";
+        line("const int j0 = " + I(n.skew) + " - x0;");
+        line("const int jw = W - 1 - x0 + " + I(n.skew) + ";");
+        for (int ch = 0; ch < n.nch; ++ch) {
+            std::string e0 = fresh("edge"), ew = fresh("edge");
+            line("float " + e0 + " = 0.f, " + ew + " = 0.f;");
+            for (int pass = 0; pass < 2; ++pass) {
+                std::string j = pass ? "jw" : "j0", dst = pass ? ew : e0;
+                line("if (" + j + " >= 0 && " + j + " < " + I(N) + ") {");
+                line("  const int fk = " + j + " / " + I(SUB) + ", ft = (" + j + " % " + I(SUB) + ") / " + I(V) +
+                     ", fe = " + j + " % " + I(V) + ";");
+                if (SX > 0) line("  if (fk < " + I(SX) + ") " + dst + " = " + lread(n.id, slot, ch, j) + ";");
+                for (int k = SX; k < g.TX; ++k)
+                    for (int e = 0; e < V; ++e)
+                        line("  if (fk == " + I(k) + " && fe == " + I(e) + ") " + dst + " = wt_readlane(" +
+                             reg(n.id, slot, ch, k - SX, e) + ", ft);");
+                line("}");
+            }
+            for (int k = 0; k < g.TX; ++k)
+                for (int e = 0; e < V; ++e) {
+                    std::string pos = "(x0 - " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) + " + " + I(e) + ")";
+                    if (k >= SX) {
+                        std::string r = reg(n.id, slot, ch, k - SX, e);
+                        line(r + " = " + pos + " < 0 ? " + e0 + " : (" + pos + " >= W ? " + ew + " : " + r + ");");
+                    } else {
+                        std::string l = lidx(n.id, slot, ch, I(k * SUB) + " + lane * " + I(V) + " + " + I(e));
+                        line("if (" + pos + " < 0) " + l + " = " + e0 + "; else if (" + pos + " >= W) " + l +
+                             " = " + ew + ";");
+                    }
+                }
+        }
+        if (SX > 0) line("wt_wave_sync();");
+        ind.resize(ind.size() - 4);
+        line("}");
+    }
+
+    void copy_row(const NodeGeom& n, int from, int to) {
+        for (int ch = 0; ch < n.nch; ++ch) {
+            for (int kr = 0; kr < RX; ++kr)
+                for (int e = 0; e < V; ++e) line(reg(n.id, to, ch, kr, e) + " = " + reg(n.id, from, ch, kr, e) + ";");
+            for (int k = 0; k < SX; ++k)
+                for (int e = 0; e < V; ++e) {
+                    std::string j = I(k * SUB) + " + lane * " + I(V) + " + " + I(e);
+                    line(lidx(n.id, to, ch, j) + " = " + lidx(n.id, from, ch, j) + ";");
+                }
+        }
+    }
+
+    // ----------------------------------------------------------- member --
+    void emit_member(const NodeGeom& n, int ph, bool stores) {
+        int slot = pmod(ph, n.win);
+        line("// stage " + I(n.id) + ": row r = kk + " + I(n.lead));
+        std::string R = "r" + I(n.id);
+        line("const int " + R + " = kk + " + I(n.lead) + ";");
+        int oi = -1;
+        for (size_t i = 0; i < geo.liveouts.size(); ++i)
+            if (geo.liveouts[i] == n.id) oi = (int)i;
+        for (int ch = 0; ch < n.nch; ++ch) {
+            for (int k = 0; k < g.TX; ++k) {
+                std::string arr = fresh("v");
+                line("float " + arr + "[" + I(V) + "];");
+                for (int e = 0; e < V; ++e) line(arr + "[" + I(e) + "] = " + value(n.id, ch, k, e, ph) + ";");
+                if (n.consumed) {
+                    if (k >= SX) {
+                        for (int e = 0; e < V; ++e)
+                            line(reg(n.id, slot, ch, k - SX, e) + " = " + (n.half ? "wt_h(" + arr + "[" + I(e) + "])"
+                                                                                  : arr + "[" + I(e) + "]") + ";");
+                    } else {
+                        emit_lds_store(n, slot, ch, k, arr);
+                    }
+                }
+                if (oi >= 0 && stores) emit_store(oi, n, ch, k, arr, R);
+            }
+        }
+        if (n.consumed && SX > 0) line("wt_wave_sync();");
+        if (border && n.consumed && n.fix_x) emit_fix_x(n, slot);
+        if (n.consumed && n.fix_top && n.win > 1) {
+            line("if (" + R + " == 0) {  // rows above the image repeat row 0");
+            ind += "    ";
+            for (int s = 1; s < n.win; ++s) copy_row(n, slot, pmod(slot - s, n.win));
+            if (SX > 0) line("wt_wave_sync();");
+            ind.resize(ind.size() - 4);
+            line("}");
+        }
+        if (n.consumed && n.fix_bot) {
+            line("if (" + R + " >= H) {  // rows below the image repeat row H-1");
+            ind += "    ";
+            copy_row(n, pmod(slot - 1, n.win), slot);
+            if (SX > 0) line("wt_wave_sync();");
+            ind.resize(ind.size() - 4);
+            line("}");
+        }
+    }
+
+    bool border = false;
+
+    // The whole streamed loop, for interior waves (vector loads and stores,
+    // no clamping) or for border waves (clamped loads, masked stores, x
+    // fix-ups).  Every path through one body issues the same memory
+    // instructions, so the compiler's wait counts stay exact.
+    // One streamed step: loads, then every member in topological order.
+    // `pro` >= 0 marks prologue step `pro` (only nodes whose rows are already
+    // needed are computed; no stores); `q` >= 0 is the output-row index of an
+    // epilogue step (loads past the tile's last needed row are skipped).
+    void emit_step(int ph, const std::string& kk, int pro, int q) {
+        memo.clear();
+        line("{ const int kk = " + kk + ";");
+        ind += "    ";
+        int li = 0;
+        for (auto& n : geo.nodes) {
+            if (n.member) continue;
+            bool on = (pro < 0 || n.first_step <= pro) && (q < 0 || q <= g.TY - 1 - g.PF);
+            if (on) emit_load(li, n, ph);
+            ++li;
+        }
+        for (auto& n : geo.nodes)
+            if (n.member && (pro < 0 || n.first_step <= pro)) emit_member(n, ph, pro < 0);
+        ind.resize(ind.size() - 4);
+        line("}");
+    }
+
+    // The whole streamed tile, for interior waves (vector loads and stores,
+    // no clamping) or for border waves (clamped loads, masked stores, x
+    // fix-ups).  Every path through one body issues the same memory
+    // instructions, so the compiler's wait counts stay exact.
+    void body(bool b) {
+        border = b;
+        ind += "    ";
+        for (auto& n : geo.nodes)
+            if (has_regs(n))
+                line("float w" + I(n.id) + "[" + I(n.win) + "][" + I(n.nch) + "][" + I(RX) + "][" + I(V) + "] = {};");
+        for (int s = 0; s < geo.D; ++s) emit_step(s % geo.U, "y0 - " + I(geo.D - s), s, -1);
+        if (geo.NMAIN > 0) {
+            line("for (int it = 0; it < " + I(geo.NMAIN) + "; ++it) {");
+            ind += "    ";
+            line("const int kb = y0 + it * " + I(geo.U) + ";");
+            for (int j = 0; j < geo.U; ++j) emit_step((geo.D + j) % geo.U, "kb + " + I(j), -1, -1);
+            ind.resize(ind.size() - 4);
+            line("}");
+        }
+        for (int j = 0; j < geo.E; ++j) {
+            int qrow = geo.NMAIN * geo.U + j;
+            emit_step((geo.D + j) % geo.U, "y0 + " + I(qrow), -1, qrow);
+        }
+        ind.resize(ind.size() - 4);
+    }
+
+    std::string kernel(const std::string& kname) {
+        int amax = 0, amin = 1 << 30;
+        for (auto& n : geo.nodes) {
+            amax = std::max(amax, n.skew);
+            amin = std::min(amin, n.skew);
+        }
+        o << "// group: " << describe_group(g) << "\n";
+        o << "// N=" << N << " X=" << geo.X << " S0=" << geo.S0 << " base=" << geo.base << " D=" << geo.D << " U=" << geo.U
+          << " NMAIN=" << geo.NMAIN << " E=" << geo.E
+          << " lds/wave=" << geo.lds_bytes << " chan_parallel=" << geo.chan_parallel << "\n";
+        for (auto& n : geo.nodes)
+            o << "//   node " << n.id << (n.member ? " member" : " loaded") << (n.liveout ? " liveout" : "")
+              << " skew=" << n.skew << " lead=" << n.lead << " win=" << n.win << " nch=" << n.nch
+              << " first=" << n.first_step << " vlo=" << n.vlo << " vhi=" << n.vhi << (n.half ? " fp16" : "") << (n.mem_half ? " mem-fp16" : "") << "\n";
+        o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * g.WPB << ") " << kname
+          << "(const WtArgs A) {\n";
+        line("const int lane = threadIdx.x & 63;");
+        // wave-uniform tile coordinates live in SGPRs (scalar branches)
+        line("const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * " + I(g.WPB) + " + (threadIdx.x >> 6));");
+        line("if (wid >= A.nwaves) return;");
+        line("const int ty = wid % A.tiles_y;");
+        line("const int rr = wid / A.tiles_y;");
+        line("const int tx = rr % A.tiles_x;");
+        line("const int cp = rr / A.tiles_x;");
+        line("(void)cp;");
+        line("const int W = A.W, H = A.H;");
+        line("const int x0 = tx * " + I(geo.X) + " + (" + I(geo.base) + ");");
+        line("const int y0 = ty * " + I(g.TY) + ";");
+        line("const int kend = y0 + " + I(g.TY) + ";");
+        line("const bool bx = (x0 - " + I(amax) + " < 0) || (x0 - " + I(amin) + " + " + I(N) + " > W);");
+        if (geo.lds_bytes > 0) {
+            line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
+            line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
+            for (auto& n : geo.nodes)
+                if (has_lds(n))
+                    line(std::string(n.half ? "_Float16" : "float") + "* L" + I(n.id) + " = (" +
+                         (n.half ? "_Float16" : "float") + "*)(lds + " + I(n.lds_off) + ");");
+        }
+        // buffer resources for the live-outs, one per channel plane
+        for (size_t oi = 0; oi < geo.liveouts.size(); ++oi) {
+            const NodeGeom& n = G(geo.liveouts[oi]);
+            std::string ty = n.mem_half ? "_Float16" : "float";
+            for (int ch = 0; ch < n.nch; ++ch)
+                line("const __amdgpu_buffer_rsrc_t S" + I((int)oi) + "_" + I(ch) +
+                     " = __builtin_amdgcn_make_buffer_rsrc((" + ty + "*)A.dst[" + I((int)oi) + "] + " +
+                     chan_off(n.id, true, (int)oi, ch) + ", 0, (int)((long long)H * A.dst_rs[" + I((int)oi) +
+                     "] * " + I(n.mem_half ? 2 : 4) + "), WT_RSRC_W3);");
+        }
+        line("if (!bx) {");
+        body(false);
+        line("} else {");
+        body(true);
+        line("}");
+        o << "}\n";
+        return o.str();
+    }
+};
+
+}  // namespace
+
+std::string generate_group_source(const Pipeline& p, const GroupSched& g, const GroupGeom& geo,
+                                  const std::string& kname) {
+    if ((int)geo.loaded.size() > 16 || (int)geo.liveouts.size() > 16)
+        fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
+    Gen gen(p, g, geo);
+    return device_prelude() + "\n" + gen.kernel(kname);
+}
+
+// 2x resampling kernels: one thread per output pixel, clamped reads.  Not
+// fused (a scaled dependence ends a group in this implementation).
+std::string generate_resample_source(const Pipeline& p, const GroupSched& g, const std::string& kname,
+                                     bool src_half, bool dst_half) {
+    const std::string st = src_half ? "_Float16" : "float", dt = dst_half ? "_Float16" : "float";
+    const Node& n = p.nodes[g.nodes[0]];
+    std::ostringstream o;
+    o << device_prelude() << "\n";
+    o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname << "(const WtArgs A) {\n";
+    o << "    const int x = blockIdx.x * 64 + (threadIdx.x & 63);\n";
+    o << "    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);\n";
+    o << "    const int c = blockIdx.z;\n";
+    o << "    if (x >= A.W || y >= A.H) return;\n";
+    o << "    const " << st << "* s = (const " << st << "*)A.src[0] + (long long)c * A.src_cs[0];\n";
+    o << "    " << dt << "* d = (" << dt << "*)A.dst[0] + (long long)c * A.dst_cs[0];\n";
+    o << "    const long long rs = A.src_rs[0];\n";
+    if (n.kind == Kind::Down2) {
+        o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")(float)s[(long long)(2 * y) * rs + 2 * x];\n";
+    } else {
+        o << "    const int Ws = A.Ws, Hs = A.Hs;\n";
+        o << "    const int i = x >> 1, jr = y >> 1;\n";
+        o << "    int xs[3]; float wx[3]; int nx;\n";
+        o << "    if (x & 1) { xs[0] = min(i, Ws - 1); xs[1] = min(i + 1, Ws - 1); wx[0] = 0.5f; wx[1] = 0.5f; nx = 2; }\n";
+        o << "    else { xs[0] = wt_clampi(i - 1, 0, Ws - 1); xs[1] = min(i, Ws - 1); xs[2] = min(i + 1, Ws - 1);\n";
+        o << "           wx[0] = 0.125f; wx[1] = 0.75f; wx[2] = 0.125f; nx = 3; }\n";
+        o << "    int ys[3]; float wy[3]; int ny;\n";
+        o << "    if (y & 1) { ys[0] = min(jr, Hs - 1); ys[1] = min(jr + 1, Hs - 1); wy[0] = 0.5f; wy[1] = 0.5f; ny = 2; }\n";
+        o << "    else { ys[0] = wt_clampi(jr - 1, 0, Hs - 1); ys[1] = min(jr, Hs - 1); ys[2] = min(jr + 1, Hs - 1);\n";
+        o << "           wy[0] = 0.125f; wy[1] = 0.75f; wy[2] = 0.125f; ny = 3; }\n";
+        o << "    float acc = 0.f;\n";
+        o << "    for (int b = 0; b < ny; ++b) {\n";
+        o << "        const " << st << "* row = s + (long long)ys[b] * rs;\n";
+        o << "        float h = 0.f;\n";
+        o << "        for (int a = 0; a < nx; ++a) h = fmaf(wx[a], (float)row[xs[a]], h);\n";
+        o << "        acc = fmaf(wy[b], h, acc);\n";
+        o << "    }\n";
+        o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")acc;\n";
+    }
+    o << "}\n";
+    return o.str();
+}
+
+}  // namespace wt

@@ -1,0 +1,319 @@
+// Plans and their execution: schedule -> generated kernels -> launches.
+// The host side of the paper's compilation pipeline (Fig. 6: fusion, OTPW,
+// hybrid tiling, code generation) plus the run-time launch of one kernel per
+// fused group in topological order (Section 7's execution protocol).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdlib>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+#include <thread>
+
+#include "wt_internal.h"
+#include "wt_runtime.h"
+
+namespace wt {
+
+namespace {
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(WT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int64_t round_up64(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+std::pair<int, int> level_dims(int W, int H, int level) {
+    for (int i = 0; i < level; ++i) {
+        W = (W + 1) / 2;
+        H = (H + 1) / 2;
+    }
+    return {W, H};
+}
+
+// Deterministic, content-derived kernel name: distinct across plans in one
+// process (profiles stay readable) and stable across runs (the code cache
+// keys on the source, which contains the name).
+std::string kernel_name(const Pipeline& p, const GroupSched& g, int gi) {
+    std::ostringstream os;
+    os << describe_group(g) << "|";
+    for (int id : g.nodes) {
+        const Node& n = p.nodes[id];
+        os << (int)n.kind << ":" << n.channels << ":" << n.level << ":" << n.kw << "x" << n.kh << ":"
+           << n.ax << "," << n.ay << ":" << n.scale << ":" << n.expr_text << ":";
+        for (double w : n.weights) os << w << ",";
+        for (int s : n.srcs) os << "s" << s;
+        os << ";";
+    }
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : os.str()) h = (h ^ c) * 1099511628211ull;
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "wt_g%d_%s_%012llx", gi, g.nodes.size() > 1 ? "fused" : "stage",
+                  (unsigned long long)(h & 0xffffffffffffull));
+    return buf;
+}
+
+}  // namespace
+
+Plan::~Plan() {
+    for (auto& g : groups)
+        if (g.mod) hipModuleUnload(g.mod);
+    for (auto& b : bufs)
+        if (b.second.ptr) hipFree(b.second.ptr);
+}
+
+std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H) {
+    if (W <= 0 || H <= 0) fail(WT_E_SHAPE, "plan size must be positive");
+    if (W > (1 << 24) || H > (1 << 24)) fail(WT_E_SHAPE, "plan size too large");
+    if (p.outputs.empty()) fail(WT_E_INVALID, "pipeline has no outputs");
+    auto plan = std::make_unique<Plan>();
+    plan->p = p;
+    plan->W = W;
+    plan->H = H;
+    wt_sched_opts def{};
+    def.mode = WT_SCHED_ANALYTIC;
+    const wt_sched_opts& opts = o ? *o : def;
+    plan->no_device = (opts.flags & WT_PLAN_NO_DEVICE) != 0;
+    plan->fp16 = opts.fp16_intermediates != 0;
+    const char* env_cache = std::getenv("WT_CACHE_DIR");
+    plan->cache_dir = opts.cache_dir ? opts.cache_dir : (env_cache ? env_cache : "");
+    if (!plan->no_device) hip_check(hipGetDevice(&plan->device), "hipGetDevice");
+    plan->machine = plan->no_device ? Machine{} : machine_from_device(plan->device);
+
+    SchedRequest req;
+    req.mode = opts.mode;
+    req.fp16 = plan->fp16;
+    req.W = W;
+    req.H = H;
+    if (opts.fixed_schedule) req.fixed = opts.fixed_schedule;
+    if (opts.model_path) req.model_path = opts.model_path;
+    plan->sched = make_schedule(p, plan->machine, req);
+    build_groups(*plan);
+    return plan;
+}
+
+// Geometry, memory dtypes, code generation, compilation and module loading
+// for every group of plan.sched.
+void build_groups(Plan& plan) {
+    const Pipeline& p = plan.p;
+    plan.groups.clear();
+    std::vector<bool> in_memory(p.nodes.size(), false);
+    for (int i : p.inputs) in_memory[i] = true;
+    for (size_t gi = 0; gi < plan.sched.groups.size(); ++gi) {
+        GroupRt gr;
+        gr.g = plan.sched.groups[gi];
+        gr.resample = is_resample_group(p, gr.g);
+        int lvl = p.nodes[gr.g.nodes[0]].level;
+        auto d = level_dims(plan.W, plan.H, lvl);
+        gr.W = d.first;
+        gr.H = d.second;
+        gr.kname = kernel_name(p, gr.g, (int)gi);
+        auto half_mem = [&](int id) { return plan.fp16 && p.nodes[id].kind != Kind::Input && !p.is_output(id); };
+        if (gr.resample) {
+            const Node& n = p.nodes[gr.g.nodes[0]];
+            if (!in_memory[n.srcs[0]]) fail(WT_E_INVALID, "schedule order: resample source not yet produced");
+            auto sd = level_dims(plan.W, plan.H, p.nodes[n.srcs[0]].level);
+            gr.Ws = sd.first;
+            gr.Hs = sd.second;
+            gr.loaded = {n.srcs[0]};
+            gr.liveouts = {n.id};
+            gr.src = generate_resample_source(p, gr.g, gr.kname, half_mem(n.srcs[0]), half_mem(n.id));
+            gr.mem_half_in = {half_mem(n.srcs[0])};
+            gr.mem_half_out = {half_mem(n.id)};
+            gr.tiles_x = (gr.W + 63) / 64;
+            gr.tiles_y = (gr.H + 3) / 4;
+            gr.nwaves = gr.tiles_x * gr.tiles_y * n.channels;
+        } else {
+            gr.geo = group_geometry(p, gr.g);
+            for (auto& ng : gr.geo.nodes) ng.mem_half = (!ng.member || ng.liveout) && half_mem(ng.id);
+            for (int l : gr.geo.loaded) {
+                if (!in_memory[l]) fail(WT_E_INVALID, "schedule order: node " + std::to_string(l) + " used before produced");
+                gr.mem_half_in.push_back(half_mem(l));
+            }
+            for (int l : gr.geo.liveouts) gr.mem_half_out.push_back(half_mem(l));
+            gr.loaded = gr.geo.loaded;
+            gr.liveouts = gr.geo.liveouts;
+            gr.src = generate_group_source(p, gr.g, gr.geo, gr.kname);
+            int amin = 1 << 30, amax = 0;
+            for (int lo : gr.geo.liveouts) {
+                const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(lo)];
+                amin = std::min(amin, ng.skew);
+                amax = std::max(amax, ng.skew);
+            }
+            int start_min = amin - amax;
+            gr.tiles_x = (gr.W - start_min + gr.geo.X - 1) / gr.geo.X;
+            gr.tiles_y = (gr.H + gr.g.TY - 1) / gr.g.TY;
+            int ch = gr.geo.chan_parallel ? gr.geo.C : 1;
+            gr.nwaves = gr.tiles_x * gr.tiles_y * ch;
+            if (gr.geo.lds_bytes_per_wg > plan.machine.max_lds_per_wg)
+                fail(WT_E_UNSUPPORTED, "group needs " + std::to_string(gr.geo.lds_bytes_per_wg) +
+                                           " bytes of LDS per workgroup");
+        }
+        for (int l : gr.liveouts) in_memory[l] = true;
+        plan.groups.push_back(std::move(gr));
+    }
+    for (int o : p.outputs)
+        if (!in_memory[o]) fail(WT_E_INVALID, "schedule does not produce output node " + std::to_string(o));
+
+    // compile in parallel on host cores
+    std::vector<std::vector<char>> code(plan.groups.size());
+    std::vector<std::string> errs(plan.groups.size());
+    std::atomic<size_t> next{0};
+    int nthr = std::max(1, std::min<int>((int)plan.groups.size(), (int)std::thread::hardware_concurrency()));
+    nthr = std::min(nthr, 16);
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nthr; ++t)
+        pool.emplace_back([&] {
+            for (size_t i; (i = next++) < plan.groups.size();) {
+                try {
+                    code[i] = compile_hip(plan.groups[i].src, plan.groups[i].kname, plan.cache_dir);
+                } catch (const std::exception& e) {
+                    errs[i] = e.what();
+                }
+            }
+        });
+    for (auto& t : pool) t.join();
+    for (size_t i = 0; i < errs.size(); ++i)
+        if (!errs[i].empty()) fail(WT_E_COMPILE, errs[i]);
+    if (plan.no_device) return;
+
+    for (size_t i = 0; i < plan.groups.size(); ++i) {
+        GroupRt& gr = plan.groups[i];
+        hip_check(hipModuleLoadData(&gr.mod, code[i].data()), "hipModuleLoadData");
+        hip_check(hipModuleGetFunction(&gr.fn, gr.mod, gr.kname.c_str()), "hipModuleGetFunction");
+    }
+    // device buffers for intermediates materialised between groups
+    for (auto& gr : plan.groups) {
+        for (size_t i = 0; i < gr.liveouts.size(); ++i) {
+            int id = gr.liveouts[i];
+            if (p.is_output(id) || plan.bufs.count(id)) continue;
+            auto d = level_dims(plan.W, plan.H, p.nodes[id].level);
+            Buf b;
+            b.half = gr.mem_half_out[i];
+            b.rs = round_up64(d.first, 64);
+            b.cs = b.rs * d.second;
+            size_t bytes = (size_t)b.cs * p.nodes[id].channels * (b.half ? 2 : 4);
+            hipError_t e = hipMalloc(&b.ptr, std::max<size_t>(bytes, 256));
+            if (e != hipSuccess) fail(WT_E_NOMEM, "hipMalloc of an intermediate buffer failed");
+            plan.bufs[id] = b;
+        }
+    }
+}
+
+namespace {
+struct ImgRef {
+    const void* ptr;
+    int64_t rs, cs;
+};
+
+ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const char* what, int idx) {
+    std::string tag = std::string(what) + " " + std::to_string(idx);
+    if (!im.data) fail(WT_E_INVALID, tag + ": null data");
+    if (im.width != W || im.height != H)
+        fail(WT_E_SHAPE, tag + ": size " + std::to_string(im.width) + "x" + std::to_string(im.height) +
+                             " differs from the planned " + std::to_string(W) + "x" + std::to_string(H));
+    if (im.channels != n.channels)
+        fail(WT_E_SHAPE, tag + ": " + std::to_string(im.channels) + " channels, expected " +
+                             std::to_string(n.channels));
+    if (im.dtype != WT_F32) fail(WT_E_UNSUPPORTED, tag + ": only WT_F32 images are supported");
+    ImgRef r;
+    r.ptr = im.data;
+    r.rs = im.row_stride ? im.row_stride : im.width;
+    r.cs = im.chan_stride ? im.chan_stride : r.rs * im.height;
+    if (r.rs < im.width) fail(WT_E_SHAPE, tag + ": row stride smaller than the width");
+    if (im.channels > 1 && r.cs < r.rs * im.height)
+        fail(WT_E_SHAPE, tag + ": channel stride smaller than a plane");
+    return r;
+}
+
+void check_align(const ImgRef& r, int V, const std::string& tag) {
+    if (V == 1) return;
+    if ((reinterpret_cast<uintptr_t>(r.ptr) % (4 * V)) || (r.rs % V) || (r.cs % V))
+        fail(WT_E_SHAPE, tag + ": buffer or strides not aligned to " + std::to_string(V) +
+                             " elements as the plan's vector width requires");
+}
+}  // namespace
+
+void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int nout, void* stream) {
+    if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
+    const Pipeline& p = plan.p;
+    if (nin != (int)p.inputs.size()) fail(WT_E_INVALID, "expected " + std::to_string(p.inputs.size()) + " inputs");
+    if (nout != (int)p.outputs.size())
+        fail(WT_E_INVALID, "expected " + std::to_string(p.outputs.size()) + " outputs");
+    if ((!in && nin) || (!out && nout)) fail(WT_E_INVALID, "null image array");
+    std::map<int, ImgRef> mem;
+    for (int i = 0; i < nin; ++i) mem[p.inputs[i]] = check_image(in[i], p.nodes[p.inputs[i]], plan.W, plan.H, "input", i);
+    for (int i = 0; i < nout; ++i) {
+        int id = p.outputs[i];
+        auto d = level_dims(plan.W, plan.H, p.nodes[id].level);
+        ImgRef r = check_image(out[i], p.nodes[id], d.first, d.second, "output", i);
+        for (auto& kv : mem)
+            if (kv.second.ptr == r.ptr) fail(WT_E_INVALID, "output " + std::to_string(i) + " aliases another image");
+        mem[id] = r;
+    }
+    for (auto& kv : plan.bufs) mem[kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
+
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (auto& gr : plan.groups) {
+        WtArgsHost a;
+        std::memset(&a, 0, sizeof a);
+        for (size_t i = 0; i < gr.loaded.size(); ++i) {
+            const ImgRef& r = mem.at(gr.loaded[i]);
+            if (!gr.resample && p.nodes[gr.loaded[i]].kind == Kind::Input)
+                check_align(r, gr.g.V, "input node " + std::to_string(gr.loaded[i]));
+            a.src[i] = r.ptr;
+            a.src_rs[i] = r.rs;
+            a.src_cs[i] = r.cs;
+        }
+        for (size_t i = 0; i < gr.liveouts.size(); ++i) {
+            const ImgRef& r = mem.at(gr.liveouts[i]);
+            if (!gr.resample && p.is_output(gr.liveouts[i]))
+                check_align(r, gr.g.V, "output node " + std::to_string(gr.liveouts[i]));
+            a.dst[i] = const_cast<void*>(r.ptr);
+            a.dst_rs[i] = r.rs;
+            a.dst_cs[i] = r.cs;
+        }
+        a.W = gr.W;
+        a.H = gr.H;
+        a.Ws = gr.Ws;
+        a.Hs = gr.Hs;
+        a.tiles_x = gr.tiles_x;
+        a.tiles_y = gr.tiles_y;
+        a.nwaves = gr.nwaves;
+        void* params[] = {&a};
+        hipError_t e;
+        if (gr.resample) {
+            int C = p.nodes[gr.g.nodes[0]].channels;
+            e = hipModuleLaunchKernel(gr.fn, gr.tiles_x, gr.tiles_y, C, 256, 1, 1, 0, st, params, nullptr);
+        } else {
+            int grid = (gr.nwaves + gr.g.WPB - 1) / gr.g.WPB;
+            e = hipModuleLaunchKernel(gr.fn, grid, 1, 1, 64 * gr.g.WPB, 1, 1, 0, st, params, nullptr);
+        }
+        hip_check(e, "hipModuleLaunchKernel");
+    }
+}
+
+std::string describe_plan(const Plan& plan) {
+    std::ostringstream os;
+    for (size_t i = 0; i < plan.sched.groups.size(); ++i)
+        os << "g" << i << " " << describe_group(plan.sched.groups[i]) << "\n";
+    return os.str();
+}
+
+Machine machine_from_device(int device) {
+    Machine m;
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, device) != hipSuccess) return m;
+    if (pr.multiProcessorCount > 0) m.ncu = pr.multiProcessorCount;
+    if (pr.warpSize > 0) m.wave = pr.warpSize;
+    if (pr.maxSharedMemoryPerMultiProcessor > 0) m.lds_per_cu = (int)pr.maxSharedMemoryPerMultiProcessor;
+    if (pr.sharedMemPerBlock > 0) m.max_lds_per_wg = (int)pr.sharedMemPerBlock;
+    if (pr.clockRate > 0) m.clock_hz = pr.clockRate * 1e3;
+    m.name = pr.gcnArchName;
+    return m;
+}
+
+}  // namespace wt

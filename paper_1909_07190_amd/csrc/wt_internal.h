@@ -1,0 +1,174 @@
+// Internal types of the wavetile library (host side).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/wt.h"
+
+namespace wt {
+
+// Error carried across internal layers; converted to wt_status at the C ABI.
+struct Error : std::runtime_error {
+    wt_status status;
+    Error(wt_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+[[noreturn]] void fail(wt_status s, const std::string& msg);
+
+// ---------------------------------------------------------------- IR -----
+
+// Pointwise expression tree.
+struct Expr {
+    enum Op { Const, Src, Neg, Add, Sub, Mul, Div, Lt, Le, Gt, Ge,
+              Abs, Min, Max, Select, Sqrt, Floor };
+    Op op = Const;
+    double value = 0.0;  // Const
+    int src = -1;        // Src: index into the stage's source list
+    int chan = -1;       // Src: explicit channel, or -1 for "same channel"
+    std::vector<Expr> kids;
+};
+Expr parse_expr(const std::string& text, int nsrc);
+// max |value| over all points, given bounds on each source's magnitude.
+double expr_bound(const Expr& e, const std::vector<double>& src_bounds);
+bool expr_has_explicit_channel(const Expr& e);
+int expr_max_channel(const Expr& e, int src);
+
+enum class Kind { Input, Stencil, Pointwise, Down2, Up2 };
+
+struct Tap { int dx, dy; double w; };
+
+struct Node {
+    Kind kind = Kind::Input;
+    int id = -1;
+    int channels = 1;
+    int level = 0;               // pyramid level (0 = input resolution)
+    std::vector<int> srcs;
+    // stencil
+    int kw = 1, kh = 1, ax = 0, ay = 0;
+    std::vector<double> weights;
+    double scale = 1.0;
+    // pointwise
+    std::string expr_text;
+    Expr expr;
+    double bound = 1.0;          // magnitude bound (inputs assumed in [-1, 1])
+};
+
+struct Pipeline {
+    std::vector<Node> nodes;
+    std::vector<int> inputs;     // node ids of inputs, creation order
+    std::vector<int> outputs;    // node ids of outputs, wt_output order
+    // consumers[n] = node ids reading n
+    std::vector<std::vector<int>> consumers() const;
+    // Constant-offset taps of consumer c on producer p (empty if c does not
+    // read p, or reads it through a resampling dependence).
+    std::vector<Tap> taps(int c, int p) const;
+    bool is_output(int n) const;
+};
+
+// ---------------------------------------------------------- schedule -----
+
+// One fused group and its tile configuration (the paper's tile sizes, thread
+// block size and register fraction, Algorithm 2's arguments).
+struct GroupSched {
+    std::vector<int> nodes;  // member stage ids, topological order
+    int V = 4;               // contiguous elements per lane along x
+    int TX = 1;              // sub-tiles along x, each 64*V columns
+    int SX = 0;              // leading sub-tiles kept in LDS (TX-SX in VGPRs)
+    int TY = 16;             // output rows per wave tile
+    int WPB = 1;             // waves per workgroup
+    bool fp16 = false;       // intermediates stored as FP16
+    int PF = 1;              // rows of input loaded ahead of their first use
+    int align = 0;           // 0: centred (reads from both neighbours);
+                             // 1: the paper's right-hyperplane skew (reads from the left only)
+};
+bool is_resample_group(const Pipeline& p, const GroupSched& g);
+
+struct Schedule { std::vector<GroupSched> groups; };
+
+std::string describe_group(const GroupSched& g);
+Schedule parse_schedule(const std::string& text, const Pipeline& p);
+
+// Geometry of a stencil/pointwise group (Section 4's warp-overlapped tile with
+// Section 5's skewed sub-tiles); see geometry.cpp.
+struct NodeGeom {
+    int id;
+    bool member;        // computed in the group (else loaded from memory)
+    bool liveout;       // stored to memory
+    int skew;           // x alignment a_n: slot j <-> x = x0 - skew + j
+    int lead;           // at step k the node holds row k + lead
+    int win;            // rows kept (ring size)
+    int nch;            // storage channels held by one wave
+    bool fix_top, fix_bot, fix_x;  // clamp fix-ups needed (see codegen)
+    int vlo;            // first valid slot
+    int vhi;            // invalid slots at the right end of a row
+    int first_step;     // first step (0 = tile start) at which its row is needed
+    bool consumed;      // read by another member of the group
+    int lds_off;        // byte offset of its LDS ring within the wave's LDS
+    bool half;          // in-group storage is FP16
+    bool mem_half;      // its memory buffer holds FP16 (set by the runtime)
+};
+struct GroupGeom {
+    std::vector<NodeGeom> nodes;    // loaded nodes first, then members (topo)
+    std::map<int, int> index;       // node id -> position in `nodes`
+    bool chan_parallel = true;      // one channel per wave
+    int C = 1;                      // channel count when chan_parallel
+    int N = 0;                      // slots per row = TX*64*V
+    int X = 0;                      // output columns per tile
+    int S0 = 0;                     // first stored slot
+    int base = 0;                   // x0 of tile 0
+    int D = 0;                      // warm-up steps before the first output row
+    int U = 1;                      // steps per unrolled loop body
+    int NMAIN = 0;                  // full U-step periods of the main loop
+    int E = 0;                      // epilogue steps (TY = NMAIN*U + E)
+    int lds_bytes = 0;              // LDS bytes per wave
+    int lds_bytes_per_wg = 0;
+    std::vector<int> loaded, liveouts;
+};
+GroupGeom group_geometry(const Pipeline& p, const GroupSched& g);
+
+// ---------------------------------------------------------- machine ------
+struct Machine {
+    std::string name = "gfx950";
+    int ncu = 256;               // compute units
+    int simd_per_cu = 4;
+    int wave = 64;
+    int vgpr_per_simd_lane = 512;  // VGPR file per lane per SIMD
+    int vgpr_granule = 8;
+    int max_vgpr_per_wave = 256;  // architectural VGPRs addressable by a wave
+    int max_waves_per_simd = 8;
+    int max_wg_per_cu = 32;
+    int lds_per_cu = 160 * 1024;
+    int max_lds_per_wg = 160 * 1024;
+    double hbm_bw = 8.0e12;      // bytes / s
+    double clock_hz = 2.4e9;
+    int tx_sizes[2] = {64, 128}; // candidate transaction sizes, bytes
+};
+Machine machine_from_device(int device);  // falls back to the constant table
+
+// ------------------------------------------------------------- codegen ---
+std::string generate_group_source(const Pipeline& p, const GroupSched& g,
+                                  const GroupGeom& geo, const std::string& kname);
+std::string generate_resample_source(const Pipeline& p, const GroupSched& g,
+                                     const std::string& kname, bool src_half, bool dst_half);
+std::string device_prelude();
+
+// ----------------------------------------------------------- scheduler ---
+struct SchedRequest {
+    int mode = WT_SCHED_ANALYTIC;
+    bool fp16 = false;
+    int W = 0, H = 0;
+    std::string fixed;
+    std::string model_path;
+};
+Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r);
+Schedule schedule_unfused(const Pipeline& p, bool fp16);
+
+// ----------------------------------------------------------------- jit ---
+std::vector<char> compile_hip(const std::string& src, const std::string& name,
+                              const std::string& cache_dir);
+
+}  // namespace wt

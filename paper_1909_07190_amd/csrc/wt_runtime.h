@@ -1,0 +1,70 @@
+// Plan objects shared by the runtime and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "wt_internal.h"
+
+namespace wt {
+
+// Host mirror of the device-side WtArgs (device/wt_device.h); field order and
+// sizes must match.
+struct WtArgsHost {
+    const void* src[16];
+    void* dst[16];
+    long long src_rs[16];
+    long long src_cs[16];
+    long long dst_rs[16];
+    long long dst_cs[16];
+    int W, H;
+    int Ws, Hs;
+    int tiles_x, tiles_y;
+    int nwaves;
+    int pad;
+};
+static_assert(sizeof(WtArgsHost) == 16 * 8 * 6 + 8 * 4, "WtArgs layout");
+
+struct Buf {
+    void* ptr = nullptr;
+    int64_t rs = 0, cs = 0;
+    bool half = false;
+};
+
+struct GroupRt {
+    GroupSched g;
+    GroupGeom geo;
+    bool resample = false;
+    std::string src, kname;
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    int W = 0, H = 0, Ws = 0, Hs = 0;
+    int tiles_x = 0, tiles_y = 0, nwaves = 0;
+    std::vector<int> loaded, liveouts;
+    std::vector<bool> mem_half_in, mem_half_out;
+};
+
+struct Plan {
+    Pipeline p;
+    Schedule sched;
+    std::vector<GroupRt> groups;
+    std::map<int, Buf> bufs;  // intermediates materialised between groups
+    Machine machine;
+    int W = 0, H = 0;
+    int device = 0;
+    bool no_device = false;
+    bool fp16 = false;
+    std::string cache_dir;
+    ~Plan();
+};
+
+std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H);
+void build_groups(Plan& plan);
+void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int nout, void* stream);
+std::string describe_plan(const Plan& plan);
+
+}  // namespace wt

@@ -1,0 +1,104 @@
+"""CPU tests of the C ABI: exported symbols, argument checking, schedule
+text, and that generated kernels compile for gfx950 (no GPU needed: plans
+made with WT_PLAN_NO_DEVICE generate and compile code but run nothing)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1909_07190_amd as wt
+from synth import pipelines as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "wt.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wt_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = header_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(wt.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_builder_rejects_bad_arguments():
+    p = wt.Pipeline()
+    img = p.input(3)
+    with pytest.raises(wt.WtError):
+        p.stencil(img, 0, 3, 0, 0, [])
+    with pytest.raises(wt.WtError):
+        p.stencil(img, 3, 1, 3, 0, [1, 1, 1])          # anchor outside kernel
+    with pytest.raises(wt.WtError):
+        p.stencil(99, 3, 1, 1, 0, [1, 1, 1])           # unknown source
+    with pytest.raises(wt.WtError):
+        p.pointwise([img], "s0 +", 3)                   # syntax
+    with pytest.raises(wt.WtError):
+        p.pointwise([img], "s1", 3)                     # source index
+    with pytest.raises(wt.WtError):
+        p.pointwise([img], "s0[3]", 1)                  # channel subscript
+    with pytest.raises(wt.WtError):
+        p.pointwise([img], "s0 < 1", 3)                 # bare comparison
+    with pytest.raises(wt.WtError):
+        p.pointwise([img], "s0", 2)                     # 3 channels into 2
+    with pytest.raises(wt.WtError):
+        p.resample(img, wt.UP2)                         # up2 at level 0
+    with pytest.raises(wt.WtError):
+        p.output(img)                                   # inputs are not outputs
+    ok = p.pointwise([img], "select(abs(s0[0] - 0.5) <= 0.25, -s0[1], min(s0[2], 2) / 4)", 1)
+    p.output(ok)
+    with pytest.raises(wt.WtError):
+        p.output(ok)
+
+
+def test_plan_errors():
+    pipe = wt.from_spec(P.gaussian_blur())
+    with pytest.raises(wt.WtError):
+        pipe.plan(0, 10, no_device=True)
+    with pytest.raises(wt.WtError):
+        pipe.plan(64, 64, mode="fixed", fixed="nodes=1 V=4", no_device=True)       # misses node 2
+    with pytest.raises(wt.WtError):
+        pipe.plan(64, 64, mode="fixed", fixed="nodes=2;nodes=1", no_device=True)   # order
+    with pytest.raises(wt.WtError):
+        pipe.plan(64, 64, mode="fixed", fixed="nodes=1,2 V=3", no_device=True)     # bad V
+    with pytest.raises(wt.WtError):
+        pipe.plan(64, 64, mode="fixed", fixed="nodes=1,2 bogus=1", no_device=True)
+    plan = pipe.plan(64, 64, mode="fixed", fixed="g0 nodes=1,2 V=2 TX=3 SX=1 TY=9 PF=1",
+                     no_device=True)
+    text = plan.describe()
+    assert "V=2 TX=3 SX=1 TY=9" in text
+    with pytest.raises(wt.WtError):
+        plan.run([], [], stream=0)                      # no-device plans never run
+
+
+def _compile(spec, fixed, fp16=False, w=512, h=256):
+    plan = wt.from_spec(spec).plan(w, h, mode="fixed", fixed=fixed, fp16=fp16, no_device=True)
+    src = plan.source(0)
+    assert "wt_g0" in src
+    return plan
+
+
+def test_generated_kernels_compile_for_gfx950():
+    from test_gpu_parity import BLUR_CASES, UM_CASES
+    for fixed, w, h in BLUR_CASES:
+        _compile(P.gaussian_blur(), fixed, w=w, h=h)
+    for fixed, fp16 in UM_CASES:
+        _compile(P.unsharp_mask(), fixed, fp16=fp16)
+
+
+def test_load_types_in_generated_source():
+    """The four producer-load types appear as the expected primitives: own
+    registers, LDS reads from the LDS sub-tiles, DPP shifts inside a register
+    sub-tile, and DPP shift-with-fill from the neighbouring sub-tile."""
+    plan = _compile(P.gaussian_blur(), "nodes=1,2 V=1 TX=3 SX=1 TY=4 PF=0 align=1")
+    src = plan.source(0)
+    body = src[src.index("extern \"C\""):]
+    assert "wt_shift1(" in body            # types 3 + 4 (register sub-tiles)
+    assert "wt_shr1(" in body              # type 3 + 2 (lane 0 from LDS)
+    assert "(float)L0[" in body            # type 2
+    assert "ds_bpermute" not in body or "wt_shiftd" in body
