@@ -81,6 +81,26 @@ def time_plan(torch, plan, ins, outs, steps, warmup, cycles_per_ms):
     return e0.elapsed_time(e1) / steps
 
 
+def copy_reference(torch, ins, outs, steps, cycles_per_ms):
+    """HBM bandwidth of a plain device copy of the same buffers (read + write
+    of one 3x2048x2048 FP32 image per step), timed like the pipeline."""
+    n = len(ins)
+    for i in range(5):
+        outs[i % n].copy_(ins[i % n])
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(int(cycles_per_ms * 5.0))
+    e0.record(s)
+    for i in range(steps):
+        outs[i % n].copy_(ins[i % n])
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nbytes = 2 * ins[0].numel() * ins[0].element_size()
+    return {"GB/s": nbytes / (ms * 1e-3) / 1e9, "us_per_copy": ms * 1e3, "bytes": nbytes}
+
+
 def cpu_baseline(img, seconds=10.0):
     """The FP64 oracle, as it stands, on a band of rows of the same image."""
     import numpy as np
@@ -154,6 +174,8 @@ def main():
         ms_h = time_plan(torch, f16, ins, outs, args.steps, args.warmup, cyc)
         extra["fp16_intermediates"] = {"value": H * W / (ms_h * 1e-3) / 1e6, "ms_per_step": ms_h}
         log(f"fp16 intermediates: {ms_h * 1e3:.2f} us/step")
+    copy = copy_reference(torch, ins, outs, args.steps, cyc)
+    log(f"device copy reference: {copy['GB/s']:.0f} GB/s")
     cpu = None if args.no_cpu else cpu_baseline(img)
     if cpu:
         log(f"oracle: {cpu['value']:.2f} Mpix/s on {cpu['cores']} core(s)")
@@ -170,6 +192,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
     }
+    out["copy_reference"] = copy
     out.update(extra)
     print(json.dumps(out), flush=True)
 

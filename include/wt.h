@@ -150,6 +150,23 @@ wt_status wt_plan_source(const wt_plan* plan, int group, char* buf, size_t len,
 /* Number of kernel launches per run. */
 int wt_plan_num_groups(const wt_plan* plan);
 
+/* Launch description of group `group`, for tools and tests that execute
+ * the generated source themselves (e.g. a host emulator).  Buffers follow
+ * the group's loaded/live-out order; *_half flags mark FP16 buffers. */
+typedef struct {
+    int32_t resample;         /* 1: 2x resampling kernel (grid tiles_x x tiles_y x channels, 256 threads) */
+    int32_t waves_per_group;  /* fused kernels: waves per workgroup                                  */
+    int32_t nwaves;           /* fused kernels: wave tiles in the launch                             */
+    int32_t tiles_x, tiles_y;
+    int32_t width, height;    /* domain of the group's stages                                        */
+    int32_t src_width, src_height; /* resampling: source domain                                      */
+    int32_t channels;         /* resampling: channel planes                                          */
+    int32_t nloaded, nliveouts;
+    int32_t loaded[16], liveouts[16];
+    int32_t loaded_half[16], liveout_half[16];
+} wt_group_info;
+wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out);
+
 /* Destroys the plan; its stream must have drained. */
 void wt_plan_destroy(wt_plan* plan);
 

@@ -214,6 +214,35 @@ wt_status wt_plan_source(const wt_plan* plan, int group, char* buf, size_t len, 
     return copy_out(plan->impl->groups[group].src, buf, len, needed);
 }
 
+wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out) {
+    return guard([&] {
+        if (!plan || !out) wt::fail(WT_E_INVALID, "null argument");
+        if (group < 0 || group >= (int)plan->impl->groups.size()) wt::fail(WT_E_INVALID, "group out of range");
+        const wt::GroupRt& g = plan->impl->groups[group];
+        std::memset(out, 0, sizeof *out);
+        out->resample = g.resample;
+        out->waves_per_group = g.g.WPB;
+        out->nwaves = g.nwaves;
+        out->tiles_x = g.tiles_x;
+        out->tiles_y = g.tiles_y;
+        out->width = g.W;
+        out->height = g.H;
+        out->src_width = g.Ws;
+        out->src_height = g.Hs;
+        out->channels = plan->impl->p.nodes[g.g.nodes[0]].channels;
+        out->nloaded = (int)g.loaded.size();
+        out->nliveouts = (int)g.liveouts.size();
+        for (size_t i = 0; i < g.loaded.size(); ++i) {
+            out->loaded[i] = g.loaded[i];
+            out->loaded_half[i] = g.mem_half_in[i];
+        }
+        for (size_t i = 0; i < g.liveouts.size(); ++i) {
+            out->liveouts[i] = g.liveouts[i];
+            out->liveout_half[i] = g.mem_half_out[i];
+        }
+    });
+}
+
 int wt_plan_num_groups(const wt_plan* plan) { return plan ? (int)plan->impl->groups.size() : 0; }
 
 void wt_plan_destroy(wt_plan* plan) { delete plan; }

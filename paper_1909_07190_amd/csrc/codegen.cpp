@@ -225,7 +225,7 @@ struct Gen {
                     line("float " + v + "[" + I(V) + "];");
                     for (int e = 0; e < V; ++e) dst.push_back(v + "[" + I(e) + "]");
                 }
-                std::string xb = "x0 - " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V);
+                std::string xb = "x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V);
                 line("{ const int xb = " + xb + ";");
                 if (!border) {
                     if (V == 1) line("  " + dst[0] + " = (float)rp[xb];");
@@ -278,7 +278,7 @@ struct Gen {
         std::string rsrc = "S" + I(oi) + "_" + I(ch);
         int esz = n.mem_half ? 2 : 4;
         line("{ const int jb = " + I(k * SUB) + " + lane * " + I(V) + ";");
-        line("  const int xp = x0 - " + I(n.skew) + " + jb;");
+        line("  const int xp = x0 + " + I(n.skew) + " + jb;");
         line("  const bool ok = " + R + " >= y0 && " + R + " < kend && " + R + " < H && jb >= " + I(geo.S0) +
              " && jb < " + I(geo.S0 + geo.X) + ";");
         line("  const int ob = (int)(((long long)" + R + " * A.dst_rs[" + I(oi) + "] + xp) * " + I(esz) + ");");
@@ -318,8 +318,8 @@ struct Gen {
     void emit_fix_x(const NodeGeom& n, int slot) {
         line("{  // clamp node " + I(n.id) + " at the image's left/right edge");
         ind += "    ";
-        line("const int j0 = " + I(n.skew) + " - x0;");
-        line("const int jw = W - 1 - x0 + " + I(n.skew) + ";");
+        line("const int j0 = -x0 - " + I(n.skew) + ";");
+        line("const int jw = W - 1 - x0 - " + I(n.skew) + ";");
         for (int ch = 0; ch < n.nch; ++ch) {
             std::string e0 = fresh("edge"), ew = fresh("edge");
             line("float " + e0 + " = 0.f, " + ew + " = 0.f;");
@@ -337,7 +337,7 @@ struct Gen {
             }
             for (int k = 0; k < g.TX; ++k)
                 for (int e = 0; e < V; ++e) {
-                    std::string pos = "(x0 - " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) + " + " + I(e) + ")";
+                    std::string pos = "(x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) + " + " + I(e) + ")";
                     if (k >= SX) {
                         std::string r = reg(n.id, slot, ch, k - SX, e);
                         line(r + " = " + pos + " < 0 ? " + e0 + " : (" + pos + " >= W ? " + ew + " : " + r + ");");
@@ -493,7 +493,7 @@ struct Gen {
         line("const int x0 = tx * " + I(geo.X) + " + (" + I(geo.base) + ");");
         line("const int y0 = ty * " + I(g.TY) + ";");
         line("const int kend = y0 + " + I(g.TY) + ";");
-        line("const bool bx = (x0 - " + I(amax) + " < 0) || (x0 - " + I(amin) + " + " + I(N) + " > W);");
+        line("const bool bx = (x0 + " + I(amin) + " < 0) || (x0 + " + I(amax) + " + " + I(N) + " > W);");
         if (geo.lds_bytes > 0) {
             line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
             line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");

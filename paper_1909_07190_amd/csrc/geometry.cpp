@@ -10,12 +10,17 @@
 // its row k + lead, so consecutive rows are the skewed parallelogram sub-tiles
 // of the split dimension and only a window of `win` rows is kept per stage.
 //
-// Alignment (Section 5, "alignment and scaling"): each node n gets an x skew
-// a_n with a_p >= a_c + dx for every dependence (dx, dy) of consumer c on p,
-// so that in slot space every producer read is at offset dx - (a_p - a_c) <= 0:
+// Alignment (Section 5, "alignment and scaling"): slot j of node n holds
+// x = x0 + a_n + j.  With align=1 each node n gets an x skew a_n with
+// a_p >= a_c + dx for every dependence (dx, dy) of consumer c on p (producers
+// shifted right, parallel to the right hyperplane), so that in slot space
+// every producer read is at offset dx - (a_p - a_c) <= 0:
 // a read comes from the same slot or from the left, which gives exactly the
 // four load types (own register / LDS / other lane of the same sub-tile /
 // other lane of the previous sub-tile).  The same rule on y gives the leads.
+// With align=0 (the default) all skews are 0 and reads may also come from
+// the right: because a whole stage row is resident before its consumers run,
+// the next sub-tile plays the role of the previous one for those reads.
 #include <algorithm>
 #include <numeric>
 #include <set>
@@ -162,19 +167,21 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
     }
 
     geo.N = g.TX * 64 * g.V;
-    int vlo = 0, vhi = 0, amin = 1 << 30;
+    int vlo = 0, vhi = 0, amax = 0;
     for (int lo : geo.liveouts) {
         const NodeGeom& ng = geo.nodes[geo.index[lo]];
         vlo = std::max(vlo, ng.vlo);
         vhi = std::max(vhi, ng.vhi);
-        amin = std::min(amin, ng.skew);
+        amax = std::max(amax, ng.skew);
     }
     geo.S0 = round_up(vlo, g.V);
     geo.X = (geo.N - vhi - geo.S0) / g.V * g.V;
     if (geo.X <= 0)
         fail(WT_E_UNSUPPORTED, "tile too narrow for the group's halo (" + std::to_string(vlo + vhi) +
                                    " columns); raise TX or V");
-    geo.base = amin - geo.S0;
+    // slot j of node n holds x = x0 + a_n + j; tile 0 starts the live-out
+    // with the largest skew at x = 0 (the others start left of it)
+    geo.base = -amax - geo.S0;
 
     // warm-up: the earliest step at which some node must hold a valid row
     std::map<int, int> first;  // first needed row relative to y0

@@ -143,7 +143,7 @@ void build_groups(Plan& plan) {
                 amin = std::min(amin, ng.skew);
                 amax = std::max(amax, ng.skew);
             }
-            int start_min = amin - amax;
+            int start_min = amin - amax;  // leftmost stored x of tile 0
             gr.tiles_x = (gr.W - start_min + gr.geo.X - 1) / gr.geo.X;
             gr.tiles_y = (gr.H + gr.g.TY - 1) / gr.g.TY;
             int ch = gr.geo.chan_parallel ? gr.geo.C : 1;

@@ -1,0 +1,143 @@
+"""Runs a plan's generated kernels on the CPU with the lane emulator
+(tests/emu/wt_emu.h): the exact HIP source the library compiles for gfx950,
+built for the host with clang, one wavefront at a time as 64 threads."""
+import ctypes
+import hashlib
+import os
+import subprocess
+
+import numpy as np
+
+import oracle
+import paper_1909_07190_amd as wt
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(os.path.dirname(HERE), "_build", "emu")
+CLANG = "/opt/rocm/llvm/bin/clang++"
+
+
+class GroupInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("resample", "waves_per_group", "nwaves", "tiles_x", "tiles_y", "width", "height",
+                 "src_width", "src_height", "channels", "nloaded", "nliveouts")] + \
+               [("loaded", ctypes.c_int32 * 16), ("liveouts", ctypes.c_int32 * 16),
+                ("loaded_half", ctypes.c_int32 * 16), ("liveout_half", ctypes.c_int32 * 16)]
+
+
+class Args(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p * 16), ("dst", ctypes.c_void_p * 16),
+                ("src_rs", ctypes.c_int64 * 16), ("src_cs", ctypes.c_int64 * 16),
+                ("dst_rs", ctypes.c_int64 * 16), ("dst_cs", ctypes.c_int64 * 16)] + \
+               [(n, ctypes.c_int32) for n in ("W", "H", "Ws", "Hs", "tiles_x", "tiles_y", "nwaves", "pad")]
+
+
+wt.lib.wt_plan_group_info.restype = ctypes.c_int
+wt.lib.wt_plan_group_info.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(GroupInfo)]
+
+RUNNER = r"""
+extern "C" int wt_emu_run(const WtArgs* a, int nwaves, int wpb) {
+    std::barrier<> bar(64);
+    wt_emu_bar = &bar;
+    std::vector<std::thread> th;
+    int nblocks = (nwaves + wpb - 1) / wpb;
+    for (int l = 0; l < 64; ++l)
+        th.emplace_back([&, l] {
+            wt_emu_lane = l;
+            for (int b = 0; b < nblocks; ++b)
+                for (int w = 0; w < wpb; ++w) {
+                    blockIdx.x = b; threadIdx.x = w * 64 + l;
+                    bar.arrive_and_wait();
+                    WT_EMU_KERNEL(*a);
+                    bar.arrive_and_wait();
+                }
+        });
+    for (auto& t : th) t.join();
+    return 0;
+}
+extern "C" int wt_emu_run_grid(const WtArgs* a, int gx, int gy, int gz, int nthr) {
+    for (int z = 0; z < gz; ++z) for (int y = 0; y < gy; ++y) for (int x = 0; x < gx; ++x)
+        for (int t = 0; t < nthr; ++t) {
+            blockIdx.x = x; blockIdx.y = y; blockIdx.z = z; threadIdx.x = t;
+            WT_EMU_KERNEL(*a);
+        }
+    return 0;
+}
+"""
+
+
+def _compile(src, kname):
+    os.makedirs(CACHE, exist_ok=True)
+    text = '#include "wt_emu.h"\n' + src + f"\n#define WT_EMU_KERNEL {kname}\n" + RUNNER
+    h = hashlib.sha1(text.encode()).hexdigest()[:16]
+    so = os.path.join(CACHE, f"{kname}_{h}.so")
+    if not os.path.exists(so):
+        cpp = so[:-3] + ".cpp"
+        open(cpp, "w").write(text)
+        subprocess.run([CLANG, "-std=c++20", "-O1", "-shared", "-fPIC", "-pthread", "-w",
+                        f"-I{os.path.join(HERE, 'emu')}", cpp, "-o", so + ".tmp"], check=True)
+        os.replace(so + ".tmp", so)
+    lib = ctypes.CDLL(so)
+    lib.wt_emu_run.argtypes = [ctypes.POINTER(Args), ctypes.c_int, ctypes.c_int]
+    lib.wt_emu_run_grid.argtypes = [ctypes.POINTER(Args)] + [ctypes.c_int] * 4
+    return lib
+
+
+def _meta(spec):
+    lv, ch = {}, {}
+    names = []
+    for i in spec["inputs"]:
+        lv[i["name"]], ch[i["name"]] = 0, i["channels"]
+        names.append(i["name"])
+    for st in spec["stages"]:
+        n = st["name"]
+        names.append(n)
+        if st["kind"] == "pointwise":
+            lv[n], ch[n] = lv[st["srcs"][0]], st["channels"]
+        else:
+            d = {"down2": 1, "up2": -1}.get(st["kind"], 0)
+            lv[n], ch[n] = lv[st["src"]] + d, ch[st["src"]]
+    return names, lv, ch
+
+
+def emulate(spec, inputs, **plan_kw):
+    """Runs `spec` through the generated kernels on the CPU; returns the outputs."""
+    names, lv, ch = _meta(spec)
+    first = inputs[spec["inputs"][0]["name"]]
+    h, w = first.shape[-2:]
+    plan = wt.from_spec(spec).plan(w, h, no_device=True, **plan_kw)
+    bufs = {}  # node id -> array
+
+    def buf(node_id, half):
+        if node_id not in bufs:
+            nm = names[node_id]
+            bw, bh = oracle.level_size(w, h, lv[nm])
+            bufs[node_id] = np.full((ch[nm], bh, bw), np.nan, dtype=np.float16 if half else np.float32)
+        return bufs[node_id]
+
+    import concurrent.futures as cf
+    srcs = [plan.source(g) for g in range(plan.num_groups)]
+    knames = [s[s.index("void __launch_bounds__"):].split("(")[1].split(")")[1].strip() for s in srcs]
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
+        libs = list(ex.map(lambda a: _compile(*a), zip(srcs, knames)))
+    for i, inp in enumerate(spec["inputs"]):
+        bufs[i] = np.ascontiguousarray(inputs[inp["name"]], dtype=np.float32).reshape(ch[inp["name"]], h, w)
+    for g in range(plan.num_groups):
+        gi = GroupInfo()
+        wt._check(wt.lib.wt_plan_group_info(plan._h, g, ctypes.byref(gi)))
+        lib = libs[g]
+        a = Args()
+        for i in range(gi.nloaded):
+            b = buf(gi.loaded[i], bool(gi.loaded_half[i]))
+            a.src[i] = b.ctypes.data
+            a.src_rs[i], a.src_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
+        for i in range(gi.nliveouts):
+            b = buf(gi.liveouts[i], bool(gi.liveout_half[i]))
+            a.dst[i] = b.ctypes.data
+            a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
+        a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
+        a.tiles_x, a.tiles_y, a.nwaves = gi.tiles_x, gi.tiles_y, gi.nwaves
+        if gi.resample:
+            lib.wt_emu_run_grid(ctypes.byref(a), gi.tiles_x, gi.tiles_y, gi.channels, 256)
+        else:
+            lib.wt_emu_run(ctypes.byref(a), gi.nwaves, gi.waves_per_group)
+    return {o: bufs[names.index(o)].astype(np.float32) for o in spec["outputs"]}, plan

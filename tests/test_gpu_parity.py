@@ -102,3 +102,57 @@ def test_unsharp_full_size():
     check_unsharp(got["mask"], img, 1e-5, UM)
     got, _ = run_gpu(UM, {"img": img}, mode="fixed", fixed=fixed + " fp16=1", fp16=True)
     check_unsharp(got["mask"], img, 2e-3, UM)
+
+
+HARRIS = P.harris()
+HARRIS_EXACT = P.harris(gray_weights=(1.0, 0.0, 0.0), k=1.0 / 32)
+HARRIS_FUSED = "nodes=1,2,3,4,5,6,7,8,9,10 V=4 TX=1 SX=0 TY=16 PF=1"
+HARRIS_CASES = [
+    HARRIS_FUSED,
+    "nodes=1,2,3,4,5,6,7,8,9,10 V=2 TX=2 SX=1 TY=8 PF=1 align=1",
+    "nodes=1,2,3 V=4 TX=1 SX=0 TY=16;nodes=4,5,6,7,8,9,10 V=4 TX=1 SX=0 TY=16 PF=2",
+]
+
+
+@pytest.mark.parametrize("fixed", HARRIS_CASES)
+def test_harris_schedules(fixed):
+    h, w = 67, 520
+    _say(f"harris {w}x{h} [{fixed}]")
+    sq = synth.white_squares(np.zeros((3, h, w), np.float32), 5, count=20, side_lo=3, side_hi=30)
+    got, _ = run_gpu(HARRIS_EXACT, {"img": sq}, mode="fixed", fixed=fixed)
+    assert_exact(got["R"], oracle.evaluate(HARRIS_EXACT, {"img": sq})["R"], fixed)
+    got, _ = run_gpu(HARRIS_EXACT, {"img": sq}, mode="fixed", fixed=fixed + " fp16=1", fp16=True)
+    assert_exact(got["R"], oracle.evaluate(HARRIS_EXACT, {"img": sq})["R"], fixed + " fp16")
+    img = synth.uniform_image(3, 3, h, w)
+    got, _ = run_gpu(HARRIS, {"img": img}, mode="fixed", fixed=fixed)
+    assert_normwise(got["R"], oracle.evaluate(HARRIS, {"img": img})["R"], 1e-5, fixed)
+
+
+def test_harris_full_size_fp16():
+    _say("harris 3x4096x4096 + 200 squares, FP16 intermediates")
+    img = synth.white_squares(synth.uniform_image(3, 3, 4096, 4096), 3, count=200)
+    got, _ = run_gpu(HARRIS, {"img": img}, mode="fixed", fixed=HARRIS_FUSED + " fp16=1", fp16=True)
+    ref = oracle.evaluate(HARRIS, {"img": img})["R"]
+    assert_normwise(got["R"], ref, 2e-3, "harris fp16")
+    got, _ = run_gpu(HARRIS, {"img": img}, mode="fixed", fixed=HARRIS_FUSED)
+    assert_normwise(got["R"], ref, 1e-5, "harris fp32")
+
+
+@pytest.mark.parametrize("mode", ["unfused", "analytic"])
+def test_pyramid_blend(mode):
+    spec = P.pyramid_blend(4)
+    for (w, h) in [(45, 37), (700, 513)]:
+        _say(f"pyramid {w}x{h} {mode}")
+        ins = {"A": synth.uniform_image(21, 1, h, w), "B": synth.uniform_image(22, 1, h, w),
+               "M": synth.ramp_mask(h, w)}
+        got, _ = run_gpu(spec, ins, mode=mode)
+        assert_normwise(got["R0"], oracle.evaluate(spec, ins)["R0"], 1e-5, mode)
+
+
+def test_pyramid_two_level_exact():
+    _say("pyramid 2-level exact")
+    spec = P.pyramid_blend(2)
+    a, b = synth.dyadic_image(31, 1, 130, 260), synth.dyadic_image(32, 1, 130, 260)
+    for m in (np.ones((1, 130, 260), np.float32), np.zeros((1, 130, 260), np.float32)):
+        got, _ = run_gpu(spec, {"A": a, "B": b, "M": m}, mode="analytic")
+        assert_exact(got["R0"], oracle.evaluate(spec, {"A": a, "B": b, "M": m})["R0"], "pyramid")
