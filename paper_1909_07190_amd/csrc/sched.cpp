@@ -1,4 +1,5 @@
 // Schedules: which stages are fused and with which tile configuration.
+#include <algorithm>
 #include <set>
 
 #include "wt_internal.h"
@@ -25,9 +26,30 @@ Schedule schedule_unfused(const Pipeline& p, bool fp16) {
 
 Schedule schedule_analytic(const Pipeline& p, const Machine& m, const SchedRequest& r);
 
+// Largest vector width a group may use: groups that read pipeline inputs or
+// write pipeline outputs address the caller's dense rows, so V must divide
+// that level's width (intermediate buffers are padded by the library).
+int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H) {
+    bool user = false;
+    for (int n : g.nodes) {
+        if (p.is_output(n)) user = true;
+        for (int s : p.nodes[n].srcs)
+            if (p.nodes[s].kind == Kind::Input) user = true;
+    }
+    if (!user) return 4;
+    int lw = W;
+    for (int i = 0; i < p.nodes[g.nodes[0]].level; ++i) lw = (lw + 1) / 2;
+    (void)H;
+    return lw % 4 == 0 ? 4 : (lw % 2 == 0 ? 2 : 1);
+}
+
 Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r) {
     switch (r.mode) {
-        case WT_SCHED_UNFUSED: return schedule_unfused(p, r.fp16);
+        case WT_SCHED_UNFUSED: {
+            Schedule s = schedule_unfused(p, r.fp16);
+            for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H));
+            return s;
+        }
         case WT_SCHED_FIXED: {
             if (r.fixed.empty()) fail(WT_E_INVALID, "WT_SCHED_FIXED needs fixed_schedule");
             Schedule s = parse_schedule(r.fixed, p);
@@ -35,7 +57,11 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
         }
         case WT_SCHED_ANALYTIC:
         case WT_SCHED_MLP:
-        case WT_SCHED_AUTOTUNE: return schedule_analytic(p, m, r);
+        case WT_SCHED_AUTOTUNE: {
+            Schedule s = schedule_analytic(p, m, r);
+            for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H));
+            return s;
+        }
         default: fail(WT_E_INVALID, "unknown schedule mode");
     }
 }

@@ -166,6 +166,7 @@ struct SchedRequest {
 };
 Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r);
 Schedule schedule_unfused(const Pipeline& p, bool fp16);
+int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H);
 
 // ----------------------------------------------------------------- jit ---
 std::vector<char> compile_hip(const std::string& src, const std::string& name,
