@@ -167,6 +167,14 @@ typedef struct {
 } wt_group_info;
 wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out);
 
+/* Test hook for the fusion search (Section 6, DP-Fusion with Algorithm 2):
+ * minimum total predicted time (microseconds, gfx950 machine model) found by
+ * the dynamic program, and by exhaustive enumeration of every partition into
+ * ready, connected, single-level groups of at most `max_group` stages under
+ * the same group costs (+inf when the pipeline has more than 10 stages). */
+wt_status wt_fusion_costs(const wt_pipeline* p, int width, int height, int fp16, int max_group,
+                          double* dp_us, double* exhaustive_us);
+
 /* Destroys the plan; its stream must have drained. */
 void wt_plan_destroy(wt_plan* plan);
 

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["ir.cpp", "geometry.cpp", "codegen.cpp", "sched.cpp", "fusion.cpp",
-                "cost.cpp", "jit.cpp", "runtime.cpp", "capi.cpp"]
+                "cost.cpp", "autotune.cpp", "jit.cpp", "runtime.cpp", "capi.cpp"]
 DEVICE_SOURCES: list[str] = []
 # Packed-FP32 VALU forms are disabled in every HIP compilation.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -243,6 +243,19 @@ wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out)
     });
 }
 
+wt_status wt_fusion_costs(const wt_pipeline* p, int width, int height, int fp16, int max_group, double* dp_us,
+                          double* exhaustive_us) {
+    return guard([&] {
+        if (!p || !dp_us || !exhaustive_us) wt::fail(WT_E_INVALID, "null argument");
+        wt::SchedRequest r;
+        r.W = width;
+        r.H = height;
+        r.fp16 = fp16 != 0;
+        r.max_group = max_group;
+        wt::fusion_costs(p->p, wt::Machine{}, r, dp_us, exhaustive_us);
+    });
+}
+
 int wt_plan_num_groups(const wt_plan* plan) { return plan ? (int)plan->impl->groups.size() : 0; }
 
 void wt_plan_destroy(wt_plan* plan) { delete plan; }

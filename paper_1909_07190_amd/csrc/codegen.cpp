@@ -228,10 +228,14 @@ struct Gen {
                 std::string xb = "x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V);
                 line("{ const int xb = " + xb + ";");
                 if (!border) {
-                    if (V == 1) line("  " + dst[0] + " = (float)rp[xb];");
+                    std::string ld0 = g.NT ? "__builtin_nontemporal_load(rp + xb)" : "rp[xb]";
+                    if (V == 1) line("  " + dst[0] + " = (float)" + ld0 + ";");
                     else {
                         std::string vt = n.mem_half ? (V == 4 ? "wt_h4" : "wt_h2") : (V == 4 ? "wt_f4" : "wt_f2");
-                        line("  const " + vt + " q = *(const " + vt + "*)(rp + xb);");
+                        if (g.NT)
+                            line("  const " + vt + " q = __builtin_nontemporal_load((const " + vt + "*)(rp + xb));");
+                        else
+                            line("  const " + vt + " q = *(const " + vt + "*)(rp + xb);");
                         for (int e = 0; e < V; ++e) line("  " + dst[e] + " = (float)q[" + I(e) + "];");
                     }
                 } else {
@@ -276,6 +280,7 @@ struct Gen {
     // control-flow merge) surrounds the store.
     void emit_store(int oi, const NodeGeom& n, int ch, int k, const std::string& arr, const std::string& R) {
         std::string rsrc = "S" + I(oi) + "_" + I(ch);
+        const std::string aux = g.NT ? "WT_CPOL_NT" : "0";
         int esz = n.mem_half ? 2 : 4;
         line("{ const int jb = " + I(k * SUB) + " + lane * " + I(V) + ";");
         line("  const int xp = x0 + " + I(n.skew) + " + jb;");
@@ -287,15 +292,15 @@ struct Gen {
             if (n.mem_half) {
                 std::string vals;
                 for (int e = 0; e < V; ++e) vals += (e ? ", " : "") + std::string("(_Float16)") + arr + "[" + I(e) + "]";
-                if (V == 1) line("  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)" + arr + "[0]), " + rsrc + ", off, 0, 0);");
-                else if (V == 2) line("  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, wt_h2{" + vals + "}), " + rsrc + ", off, 0, 0);");
-                else line("  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(wt_u2, wt_h4{" + vals + "}), " + rsrc + ", off, 0, 0);");
+                if (V == 1) line("  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)" + arr + "[0]), " + rsrc + ", off, 0, " + aux + ");");
+                else if (V == 2) line("  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, wt_h2{" + vals + "}), " + rsrc + ", off, 0, " + aux + ");");
+                else line("  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(wt_u2, wt_h4{" + vals + "}), " + rsrc + ", off, 0, " + aux + ");");
             } else {
                 std::string vals;
                 for (int e = 0; e < V; ++e) vals += (e ? ", " : "") + arr + "[" + I(e) + "]";
-                if (V == 1) line("  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, " + arr + "[0]), " + rsrc + ", off, 0, 0);");
-                else if (V == 2) line("  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(wt_u2, wt_f2{" + vals + "}), " + rsrc + ", off, 0, 0);");
-                else line("  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(wt_u4, wt_f4{" + vals + "}), " + rsrc + ", off, 0, 0);");
+                if (V == 1) line("  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, " + arr + "[0]), " + rsrc + ", off, 0, " + aux + ");");
+                else if (V == 2) line("  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(wt_u2, wt_f2{" + vals + "}), " + rsrc + ", off, 0, " + aux + ");");
+                else line("  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(wt_u4, wt_f4{" + vals + "}), " + rsrc + ", off, 0, " + aux + ");");
             }
         } else {
             for (int e = 0; e < V; ++e) {
@@ -303,10 +308,10 @@ struct Gen {
                      " : WT_OOB;");
                 if (n.mem_half)
                     line("    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)" + arr + "[" +
-                         I(e) + "]), " + rsrc + ", off, 0, 0); }");
+                         I(e) + "]), " + rsrc + ", off, 0, " + aux + "); }");
                 else
                     line("    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, " + arr + "[" + I(e) +
-                         "]), " + rsrc + ", off, 0, 0); }");
+                         "]), " + rsrc + ", off, 0, " + aux + "); }");
             }
         }
         line("}");
@@ -482,7 +487,17 @@ struct Gen {
           << "(const WtArgs A) {\n";
         line("const int lane = threadIdx.x & 63;");
         // wave-uniform tile coordinates live in SGPRs (scalar branches)
-        line("const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * " + I(g.WPB) + " + (threadIdx.x >> 6));");
+        if (g.XCD) {
+            // Workgroups are dispatched round-robin over the 8 XCDs; give each
+            // XCD a contiguous range of tiles so vertically adjacent tiles
+            // (which share halo rows) run on one XCD and meet in its L2.
+            line("const int nb = gridDim.x, b = blockIdx.x;");
+            line("const int xq = nb / WT_NXCD, xr = nb % WT_NXCD, xi = b % WT_NXCD;");
+            line("const int lb = xi * xq + min(xi, xr) + b / WT_NXCD;");
+            line("const int wid = __builtin_amdgcn_readfirstlane(lb * " + I(g.WPB) + " + (threadIdx.x >> 6));");
+        } else {
+            line("const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * " + I(g.WPB) + " + (threadIdx.x >> 6));");
+        }
         line("if (wid >= A.nwaves) return;");
         line("const int ty = wid % A.tiles_y;");
         line("const int rr = wid / A.tiles_y;");

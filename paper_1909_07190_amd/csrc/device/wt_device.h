@@ -20,6 +20,10 @@ typedef unsigned int wt_u4 __attribute__((ext_vector_type(4)));
 // at WT_OOB are discarded by the hardware range check.
 #define WT_RSRC_W3 0x00020000
 #define WT_OOB 0x7FFFFFFF
+// Cache-policy operand of buffer stores: the non-temporal (streaming) bit.
+#define WT_CPOL_NT 2
+// Accelerator complex dies; workgroups are dispatched to them round-robin.
+#define WT_NXCD 8
 
 #define WT_DEV static __device__ __forceinline__
 

@@ -1,39 +1,300 @@
-// Fusion search (placeholder: maximal same-level fusion; replaced by the
-// bounded DP over convex groups with the analytical cost).
+// Fusion search: which stages run fused in one kernel and with which tile
+// configuration (the paper, Section 6: DP-Fusion driven by the GPU cost
+// function, and the argmin over tile sizes, block sizes, register fraction
+// and transaction size).
+//
+// The paper uses PolyMage's Bounded DP-Fusion without specifying it.  This
+// search is a dynamic program over down-closed sets S of already scheduled
+// stages (memoised on a bitmask): from S it may schedule any group G of
+// unscheduled stages that is ready (every producer of a member is in S or G,
+// which also makes G convex), connected, on one pyramid level, and of at most
+// K stages; resampling stages form groups of their own.  The cost of a group
+// is the predicted time of its best configuration, where "best" is the
+// argmin of Algorithm 2's score over the configuration grid; the DP minimises
+// the sum over groups.
+#include <algorithm>
+#include <cmath>
+#include <functional>
+#include <map>
 #include <set>
+#include <unordered_map>
 
-#include "wt_internal.h"
+#include "wt_cost.h"
 
 namespace wt {
 
-Schedule schedule_analytic(const Pipeline& p, const Machine& m, const SchedRequest& r) {
-    (void)m;
-    Schedule s;
-    GroupSched cur;
-    int level = -1;
-    auto flush = [&] {
-        if (!cur.nodes.empty()) s.groups.push_back(cur);
-        cur = GroupSched{};
-        cur.fp16 = r.fp16;
-    };
-    cur.fp16 = r.fp16;
-    for (const Node& n : p.nodes) {
-        if (n.kind == Kind::Input) continue;
-        bool fusable = n.kind == Kind::Stencil || n.kind == Kind::Pointwise;
-        if (!fusable) {
-            flush();
-            GroupSched g;
-            g.nodes = {n.id};
-            s.groups.push_back(g);
-            level = -1;
-            continue;
+namespace {
+
+
+struct Search {
+    const Pipeline& p;
+    const Machine& m;
+    const SchedRequest& r;
+    std::vector<int> stages;           // stage node ids (non-inputs), ascending
+    std::map<int, int> pos;            // node id -> bit
+    std::vector<uint64_t> prod, adj;   // per bit: producer bits / undirected neighbours
+    std::vector<bool> fusable;
+    std::map<int, StageProfile> prof;
+    std::unordered_map<uint64_t, std::pair<double, GroupSched>> gcache;
+    std::unordered_map<uint64_t, std::pair<double, uint64_t>> memo;
+    int K;
+    long long groups_costed = 0;
+
+    Search(const Pipeline& pp, const Machine& mm, const SchedRequest& rr) : p(pp), m(mm), r(rr) {
+        for (const Node& n : p.nodes)
+            if (n.kind != Kind::Input) {
+                pos[n.id] = (int)stages.size();
+                stages.push_back(n.id);
+            }
+        if (stages.size() > 64) fail(WT_E_UNSUPPORTED, "fusion search handles at most 64 stages");
+        prod.assign(stages.size(), 0);
+        adj.assign(stages.size(), 0);
+        fusable.assign(stages.size(), false);
+        for (size_t i = 0; i < stages.size(); ++i) {
+            const Node& n = p.nodes[stages[i]];
+            fusable[i] = n.kind == Kind::Stencil || n.kind == Kind::Pointwise;
+            for (int s : n.srcs)
+                if (pos.count(s)) {
+                    prod[i] |= 1ull << pos[s];
+                    adj[i] |= 1ull << pos[s];
+                    adj[pos[s]] |= 1ull << i;
+                }
+            prof[stages[i]] = estimate_stage(p, stages[i], m);
         }
-        if (n.level != level) flush();
-        level = n.level;
-        cur.nodes.push_back(n.id);
+        K = r.max_group > 0 ? r.max_group : 12;
     }
-    flush();
-    return s;
+
+    // Best configuration of one group: argmin of Algorithm 2's score.
+    std::pair<double, GroupSched> cost_of(uint64_t g) {
+        auto it = gcache.find(g);
+        if (it != gcache.end()) return it->second;
+        ++groups_costed;
+        std::vector<int> nodes;
+        for (size_t i = 0; i < stages.size(); ++i)
+            if (g >> i & 1) nodes.push_back(stages[i]);
+        GroupSched base;
+        base.nodes = nodes;
+        base.fp16 = r.fp16;
+        if (nodes.size() == 1 && !fusable[pos[nodes[0]]]) {
+            double t = resample_pred_us(p, nodes[0], m, r.W, r.H, r.fp16, r.fp16 && !p.is_output(nodes[0]));
+            auto res = std::make_pair(t, base);
+            gcache[g] = res;
+            return res;
+        }
+        double best_score = INFINITY, best_pred = INFINITY;
+        GroupSched best = base;
+        for (const ScoredConfig& sc : score_configs(p, m, r, nodes))
+            if (sc.cost.alg2.score < best_score) {
+                best_score = sc.cost.alg2.score;
+                best_pred = sc.cost.pred_us;
+                best = sc.g;
+            }
+        auto res = std::make_pair(best_pred, best);
+        gcache[g] = res;
+        return res;
+    }
+
+    // Ready, connected groups of at most K stages whose lowest stage is `seed`.
+    void enumerate(uint64_t S, int seed, std::vector<uint64_t>& out) {
+        uint64_t all = stages.size() == 64 ? ~0ull : ((1ull << stages.size()) - 1);
+        uint64_t avail = all & ~S;
+        int lvl = p.nodes[stages[seed]].level;
+        std::function<void(uint64_t, uint64_t)> grow = [&](uint64_t G, uint64_t ext) {
+            // G is connected; record it if ready
+            bool ready = true;
+            for (size_t i = 0; i < stages.size() && ready; ++i)
+                if ((G >> i & 1) && (prod[i] & ~(S | G))) ready = false;
+            if (ready) out.push_back(G);
+            if (__builtin_popcountll(G) >= K) return;
+            while (ext) {
+                int v = __builtin_ctzll(ext);
+                ext &= ext - 1;
+                uint64_t ng = G | (1ull << v);
+                uint64_t next = ext;
+                uint64_t nb = adj[v] & avail & ~ng & ~((1ull << seed) - 1) & ~(1ull << seed);
+                for (size_t i = 0; i < stages.size(); ++i)
+                    if ((nb >> i & 1) && (!fusable[i] || p.nodes[stages[i]].level != lvl)) nb &= ~(1ull << i);
+                // neighbours of v not adjacent to G before (ESU extension)
+                uint64_t gadj = 0;
+                for (size_t i = 0; i < stages.size(); ++i)
+                    if (G >> i & 1) gadj |= adj[i];
+                next |= nb & ~gadj & ~G;
+                grow(ng, next);
+            }
+        };
+        if (!fusable[seed]) {
+            if (!(prod[seed] & ~S)) out.push_back(1ull << seed);
+            return;
+        }
+        uint64_t ext = adj[seed] & avail & ~((1ull << seed) - 1) & ~(1ull << seed);
+        for (size_t i = 0; i < stages.size(); ++i)
+            if ((ext >> i & 1) && (!fusable[i] || p.nodes[stages[i]].level != lvl)) ext &= ~(1ull << i);
+        grow(1ull << seed, ext);
+    }
+
+    double solve(uint64_t S) {
+        uint64_t all = stages.size() == 64 ? ~0ull : ((1ull << stages.size()) - 1);
+        if (S == all) return 0.0;
+        auto it = memo.find(S);
+        if (it != memo.end()) return it->second.first;
+        double best = INFINITY;
+        uint64_t best_g = 0;
+        std::vector<uint64_t> cands;
+        for (size_t v = 0; v < stages.size(); ++v)
+            if (!(S >> v & 1) && !(prod[v] & ~S)) enumerate(S, (int)v, cands);
+        for (uint64_t G : cands) {
+            double c = cost_of(G).first;
+            if (!std::isfinite(c)) continue;
+            double t = c + solve(S | G);
+            if (t < best) {
+                best = t;
+                best_g = G;
+            }
+        }
+        memo[S] = {best, best_g};
+        return best;
+    }
+
+    Schedule extract() {
+        Schedule s;
+        uint64_t S = 0;
+        uint64_t all = stages.size() == 64 ? ~0ull : ((1ull << stages.size()) - 1);
+        while (S != all) {
+            uint64_t G = memo.at(S).second;
+            if (!G) fail(WT_E_INTERNAL, "fusion search found no feasible schedule");
+            s.groups.push_back(cost_of(G).second);
+            S |= G;
+        }
+        return s;
+    }
+};
+
+}  // namespace
+
+// Table 3's V100 weights, the starting point on gfx950 until refitted from
+// the autotuner's measurements.
+const double kGfx950Weights[7] = {50, 0.5, 60, 10, 2, 100, 1};
+
+std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,
+                                        const std::vector<int>& nodes) {
+    std::vector<ScoredConfig> out;
+    std::map<int, StageProfile> prof;
+    for (int n : nodes) prof[n] = estimate_stage(p, n, m);
+    GroupSched base;
+    base.nodes = nodes;
+    base.fp16 = r.fp16;
+    int vmax = max_vector_width(p, base, r.W, r.H);
+    const double* w = r.weights ? r.weights : kGfx950Weights;
+    for (int V : {4, 2, 1}) {
+        if (V > vmax) continue;
+        for (int TX : {1, 2, 4})
+            for (int SX = 0; SX <= TX; ++SX)
+                for (int PF : {1, 2}) {
+                    GroupSched s = base;
+                    s.V = V;
+                    s.TX = TX;
+                    s.SX = SX;
+                    s.PF = PF;
+                    GroupGeom geo;
+                    try {
+                        geo = group_geometry(p, s);
+                    } catch (const Error&) {
+                        continue;
+                    }
+                    for (auto& ng : geo.nodes)
+                        ng.mem_half = r.fp16 && p.nodes[ng.id].kind != Kind::Input && !p.is_output(ng.id) &&
+                                      (!ng.member || ng.liveout);
+                    for (int TY : {8, 16, 32, 64})
+                        for (int WPB : {1, 2, 4}) {
+                            s.TY = TY;
+                            s.WPB = WPB;
+                            GroupGeom gg = geo;
+                            gg.lds_bytes_per_wg = geo.lds_bytes * WPB;
+                            for (int tx : {m.tx_sizes[0], m.tx_sizes[1]}) {
+                                GroupCost c = group_cost(p, s, gg, m, r.W, r.H, prof, tx, w);
+                                if (!c.alg2.feasible || c.nwaves <= 0) continue;
+                                out.push_back({s, c, tx});
+                            }
+                        }
+                }
+    }
+    return out;
+}
+
+Schedule schedule_analytic(const Pipeline& p, const Machine& m, const SchedRequest& r) {
+    Search srch(p, m, r);
+    double t = srch.solve(0);
+    if (!std::isfinite(t)) fail(WT_E_UNSUPPORTED, "no feasible schedule for this pipeline");
+    return srch.extract();
+}
+
+// Minimum total predicted time by the DP and by exhaustive enumeration of all
+// partitions into ready groups under the same group costs (test hook; the
+// exhaustive search is exponential and refuses more than 10 stages).
+void fusion_costs(const Pipeline& p, const Machine& m, const SchedRequest& r, double* dp, double* brute) {
+    Search srch(p, m, r);
+    *dp = srch.solve(0);
+    *brute = INFINITY;
+    size_t n = srch.stages.size();
+    if (n > 10) return;
+    // assign each stage a group label (restricted growth strings), then test
+    // that the group graph is acyclic and every group is fusable/connected
+    std::vector<int> lab(n, 0);
+    std::function<void(size_t, int)> rec = [&](size_t i, int k) {
+        if (i == n) {
+            std::vector<uint64_t> gs(k, 0);
+            for (size_t j = 0; j < n; ++j) gs[lab[j]] |= 1ull << j;
+            double tot = 0;
+            // order groups: repeatedly pick a ready group
+            uint64_t S = 0;
+            std::vector<bool> used(k, false);
+            for (int step = 0; step < k; ++step) {
+                int pick = -1;
+                for (int g = 0; g < k && pick < 0; ++g) {
+                    if (used[g]) continue;
+                    bool ready = true;
+                    for (size_t j = 0; j < n; ++j)
+                        if ((gs[g] >> j & 1) && (srch.prod[j] & ~(S | gs[g]))) ready = false;
+                    if (ready) pick = g;
+                }
+                if (pick < 0) return;  // cyclic group graph
+                used[pick] = true;
+                S |= gs[pick];
+                // group admissibility as in the DP
+                uint64_t G = gs[pick];
+                int cnt = __builtin_popcountll(G);
+                if (cnt > srch.K) return;
+                int lvl = -1;
+                for (size_t j = 0; j < n; ++j)
+                    if (G >> j & 1) {
+                        if (cnt > 1 && !srch.fusable[j]) return;
+                        int l = p.nodes[srch.stages[j]].level;
+                        if (lvl >= 0 && l != lvl) return;
+                        lvl = l;
+                    }
+                // connected
+                uint64_t seen = G & (~G + 1), frontier = seen;
+                while (frontier) {
+                    uint64_t nf = 0;
+                    for (size_t j = 0; j < n; ++j)
+                        if (frontier >> j & 1) nf |= srch.adj[j] & G & ~seen;
+                    seen |= nf;
+                    frontier = nf;
+                }
+                if (seen != G) return;
+                double c = srch.cost_of(G).first;
+                if (!std::isfinite(c)) return;
+                tot += c;
+            }
+            *brute = std::min(*brute, tot);
+            return;
+        }
+        for (int l = 0; l <= k; ++l) {
+            lab[i] = l;
+            rec(i + 1, std::max(k, l + 1));
+        }
+    };
+    rec(0, 0);
 }
 
 }  // namespace wt

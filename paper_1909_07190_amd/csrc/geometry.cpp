@@ -238,7 +238,8 @@ std::string describe_group(const GroupSched& g) {
     os << "nodes=";
     for (size_t i = 0; i < g.nodes.size(); ++i) os << (i ? "," : "") << g.nodes[i];
     os << " V=" << g.V << " TX=" << g.TX << " SX=" << g.SX << " TY=" << g.TY
-       << " WPB=" << g.WPB << " PF=" << g.PF << " fp16=" << (g.fp16 ? 1 : 0) << " align=" << g.align;
+       << " WPB=" << g.WPB << " PF=" << g.PF << " fp16=" << (g.fp16 ? 1 : 0) << " align=" << g.align
+       << " XCD=" << g.XCD << " NT=" << g.NT;
     return os.str();
 }
 
@@ -271,6 +272,8 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p) {
                 else if (k == "fp16") g.fp16 = std::stoi(v) != 0;
                 else if (k == "align") g.align = std::stoi(v);
                 else if (k == "PF") g.PF = std::stoi(v);
+                else if (k == "XCD") g.XCD = std::stoi(v);
+                else if (k == "NT") g.NT = std::stoi(v);
                 else fail(WT_E_INVALID, "unknown schedule key '" + k + "'");
             } catch (const std::logic_error&) {
                 fail(WT_E_INVALID, "bad schedule value '" + tok + "'");

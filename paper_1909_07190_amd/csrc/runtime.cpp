@@ -18,13 +18,9 @@
 
 namespace wt {
 
-namespace {
-
 void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) fail(WT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-int64_t round_up64(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 std::pair<int, int> level_dims(int W, int H, int level) {
     for (int i = 0; i < level; ++i) {
@@ -33,6 +29,10 @@ std::pair<int, int> level_dims(int W, int H, int level) {
     }
     return {W, H};
 }
+
+namespace {
+
+int64_t round_up64(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Deterministic, content-derived kernel name: distinct across plans in one
 // process (profiles stay readable) and stable across runs (the code cache
@@ -92,84 +92,74 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     if (opts.model_path) req.model_path = opts.model_path;
     plan->sched = make_schedule(p, plan->machine, req);
     build_groups(*plan);
+    if (opts.mode == WT_SCHED_AUTOTUNE && !plan->no_device)
+        autotune_plan(*plan, opts.autotune_topk > 0 ? opts.autotune_topk : 6);
     return plan;
 }
 
-// Geometry, memory dtypes, code generation, compilation and module loading
-// for every group of plan.sched.
-void build_groups(Plan& plan) {
+// Geometry, memory dtypes and generated source of group `gi` of a plan.
+void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     const Pipeline& p = plan.p;
-    plan.groups.clear();
-    std::vector<bool> in_memory(p.nodes.size(), false);
-    for (int i : p.inputs) in_memory[i] = true;
-    for (size_t gi = 0; gi < plan.sched.groups.size(); ++gi) {
-        GroupRt gr;
-        gr.g = plan.sched.groups[gi];
-        gr.resample = is_resample_group(p, gr.g);
-        int lvl = p.nodes[gr.g.nodes[0]].level;
-        auto d = level_dims(plan.W, plan.H, lvl);
-        gr.W = d.first;
-        gr.H = d.second;
-        gr.kname = kernel_name(p, gr.g, (int)gi);
-        auto half_mem = [&](int id) { return plan.fp16 && p.nodes[id].kind != Kind::Input && !p.is_output(id); };
-        if (gr.resample) {
-            const Node& n = p.nodes[gr.g.nodes[0]];
-            if (!in_memory[n.srcs[0]]) fail(WT_E_INVALID, "schedule order: resample source not yet produced");
-            auto sd = level_dims(plan.W, plan.H, p.nodes[n.srcs[0]].level);
-            gr.Ws = sd.first;
-            gr.Hs = sd.second;
-            gr.loaded = {n.srcs[0]};
-            gr.liveouts = {n.id};
-            gr.src = generate_resample_source(p, gr.g, gr.kname, half_mem(n.srcs[0]), half_mem(n.id));
-            gr.mem_half_in = {half_mem(n.srcs[0])};
-            gr.mem_half_out = {half_mem(n.id)};
-            gr.tiles_x = (gr.W + 63) / 64;
-            gr.tiles_y = (gr.H + 3) / 4;
-            gr.nwaves = gr.tiles_x * gr.tiles_y * n.channels;
-        } else {
-            gr.geo = group_geometry(p, gr.g);
-            for (auto& ng : gr.geo.nodes) ng.mem_half = (!ng.member || ng.liveout) && half_mem(ng.id);
-            for (int l : gr.geo.loaded) {
-                if (!in_memory[l]) fail(WT_E_INVALID, "schedule order: node " + std::to_string(l) + " used before produced");
-                gr.mem_half_in.push_back(half_mem(l));
-            }
-            for (int l : gr.geo.liveouts) gr.mem_half_out.push_back(half_mem(l));
-            gr.loaded = gr.geo.loaded;
-            gr.liveouts = gr.geo.liveouts;
-            gr.src = generate_group_source(p, gr.g, gr.geo, gr.kname);
-            int amin = 1 << 30, amax = 0;
-            for (int lo : gr.geo.liveouts) {
-                const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(lo)];
-                amin = std::min(amin, ng.skew);
-                amax = std::max(amax, ng.skew);
-            }
-            int start_min = amin - amax;  // leftmost stored x of tile 0
-            gr.tiles_x = (gr.W - start_min + gr.geo.X - 1) / gr.geo.X;
-            gr.tiles_y = (gr.H + gr.g.TY - 1) / gr.g.TY;
-            int ch = gr.geo.chan_parallel ? gr.geo.C : 1;
-            gr.nwaves = gr.tiles_x * gr.tiles_y * ch;
-            if (gr.geo.lds_bytes_per_wg > plan.machine.max_lds_per_wg)
-                fail(WT_E_UNSUPPORTED, "group needs " + std::to_string(gr.geo.lds_bytes_per_wg) +
-                                           " bytes of LDS per workgroup");
-        }
-        for (int l : gr.liveouts) in_memory[l] = true;
-        plan.groups.push_back(std::move(gr));
+    gr.resample = is_resample_group(p, gr.g);
+    int lvl = p.nodes[gr.g.nodes[0]].level;
+    auto d = level_dims(plan.W, plan.H, lvl);
+    gr.W = d.first;
+    gr.H = d.second;
+    gr.kname = kernel_name(p, gr.g, gi);
+    auto half_mem = [&](int id) { return plan.fp16 && p.nodes[id].kind != Kind::Input && !p.is_output(id); };
+    gr.mem_half_in.clear();
+    gr.mem_half_out.clear();
+    if (gr.resample) {
+        const Node& n = p.nodes[gr.g.nodes[0]];
+        auto sd = level_dims(plan.W, plan.H, p.nodes[n.srcs[0]].level);
+        gr.Ws = sd.first;
+        gr.Hs = sd.second;
+        gr.loaded = {n.srcs[0]};
+        gr.liveouts = {n.id};
+        gr.src = generate_resample_source(p, gr.g, gr.kname, half_mem(n.srcs[0]), half_mem(n.id));
+        gr.mem_half_in = {half_mem(n.srcs[0])};
+        gr.mem_half_out = {half_mem(n.id)};
+        gr.tiles_x = (gr.W + 63) / 64;
+        gr.tiles_y = (gr.H + 3) / 4;
+        gr.nwaves = gr.tiles_x * gr.tiles_y * n.channels;
+        return;
     }
-    for (int o : p.outputs)
-        if (!in_memory[o]) fail(WT_E_INVALID, "schedule does not produce output node " + std::to_string(o));
+    gr.geo = group_geometry(p, gr.g);
+    for (auto& ng : gr.geo.nodes) ng.mem_half = (!ng.member || ng.liveout) && half_mem(ng.id);
+    for (int l : gr.geo.loaded) gr.mem_half_in.push_back(half_mem(l));
+    for (int l : gr.geo.liveouts) gr.mem_half_out.push_back(half_mem(l));
+    gr.loaded = gr.geo.loaded;
+    gr.liveouts = gr.geo.liveouts;
+    gr.src = generate_group_source(p, gr.g, gr.geo, gr.kname);
+    int amin = 1 << 30, amax = 0;
+    for (int lo : gr.geo.liveouts) {
+        const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(lo)];
+        amin = std::min(amin, ng.skew);
+        amax = std::max(amax, ng.skew);
+    }
+    int start_min = amin - amax;  // leftmost stored x of tile 0
+    gr.tiles_x = (gr.W - start_min + gr.geo.X - 1) / gr.geo.X;
+    gr.tiles_y = (gr.H + gr.g.TY - 1) / gr.g.TY;
+    int ch = gr.geo.chan_parallel ? gr.geo.C : 1;
+    gr.nwaves = gr.tiles_x * gr.tiles_y * ch;
+    if (gr.geo.lds_bytes_per_wg > plan.machine.max_lds_per_wg)
+        fail(WT_E_UNSUPPORTED, "group needs " + std::to_string(gr.geo.lds_bytes_per_wg) + " bytes of LDS per workgroup");
+}
 
-    // compile in parallel on host cores
-    std::vector<std::vector<char>> code(plan.groups.size());
-    std::vector<std::string> errs(plan.groups.size());
+// Compiles the groups' sources in parallel on host cores (hipRTC), then
+// loads the code objects unless the plan has no device.
+void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs) {
+    std::vector<std::vector<char>> code(grs.size());
+    std::vector<std::string> errs(grs.size());
     std::atomic<size_t> next{0};
-    int nthr = std::max(1, std::min<int>((int)plan.groups.size(), (int)std::thread::hardware_concurrency()));
+    int nthr = std::max(1, std::min<int>((int)grs.size(), (int)std::thread::hardware_concurrency()));
     nthr = std::min(nthr, 16);
     std::vector<std::thread> pool;
     for (int t = 0; t < nthr; ++t)
         pool.emplace_back([&] {
-            for (size_t i; (i = next++) < plan.groups.size();) {
+            for (size_t i; (i = next++) < grs.size();) {
                 try {
-                    code[i] = compile_hip(plan.groups[i].src, plan.groups[i].kname, plan.cache_dir);
+                    code[i] = compile_hip(grs[i]->src, grs[i]->kname, plan.cache_dir);
                 } catch (const std::exception& e) {
                     errs[i] = e.what();
                 }
@@ -179,12 +169,37 @@ void build_groups(Plan& plan) {
     for (size_t i = 0; i < errs.size(); ++i)
         if (!errs[i].empty()) fail(WT_E_COMPILE, errs[i]);
     if (plan.no_device) return;
-
-    for (size_t i = 0; i < plan.groups.size(); ++i) {
-        GroupRt& gr = plan.groups[i];
-        hip_check(hipModuleLoadData(&gr.mod, code[i].data()), "hipModuleLoadData");
-        hip_check(hipModuleGetFunction(&gr.fn, gr.mod, gr.kname.c_str()), "hipModuleGetFunction");
+    for (size_t i = 0; i < grs.size(); ++i) {
+        if (grs[i]->mod) continue;
+        hip_check(hipModuleLoadData(&grs[i]->mod, code[i].data()), "hipModuleLoadData");
+        hip_check(hipModuleGetFunction(&grs[i]->fn, grs[i]->mod, grs[i]->kname.c_str()), "hipModuleGetFunction");
     }
+}
+
+// Geometry, code generation, compilation and module loading for every group
+// of plan.sched, then device buffers for the intermediates.
+void build_groups(Plan& plan) {
+    const Pipeline& p = plan.p;
+    for (auto& g : plan.groups)
+        if (g.mod) hipModuleUnload(g.mod);
+    plan.groups.clear();
+    std::vector<bool> in_memory(p.nodes.size(), false);
+    for (int i : p.inputs) in_memory[i] = true;
+    for (size_t gi = 0; gi < plan.sched.groups.size(); ++gi) {
+        GroupRt gr;
+        gr.g = plan.sched.groups[gi];
+        prepare_group(plan, gr, (int)gi);
+        for (int l : gr.loaded)
+            if (!in_memory[l]) fail(WT_E_INVALID, "schedule order: node " + std::to_string(l) + " used before produced");
+        for (int l : gr.liveouts) in_memory[l] = true;
+        plan.groups.push_back(std::move(gr));
+    }
+    for (int o : p.outputs)
+        if (!in_memory[o]) fail(WT_E_INVALID, "schedule does not produce output node " + std::to_string(o));
+    std::vector<GroupRt*> grs;
+    for (auto& g : plan.groups) grs.push_back(&g);
+    compile_groups(plan, grs);
+    if (plan.no_device) return;
     // device buffers for intermediates materialised between groups
     for (auto& gr : plan.groups) {
         for (size_t i = 0; i < gr.liveouts.size(); ++i) {
@@ -204,10 +219,6 @@ void build_groups(Plan& plan) {
 }
 
 namespace {
-struct ImgRef {
-    const void* ptr;
-    int64_t rs, cs;
-};
 
 ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const char* what, int idx) {
     std::string tag = std::string(what) + " " + std::to_string(idx);
@@ -257,43 +268,48 @@ void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int 
     for (auto& kv : plan.bufs) mem[kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
 
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    for (auto& gr : plan.groups) {
-        WtArgsHost a;
-        std::memset(&a, 0, sizeof a);
-        for (size_t i = 0; i < gr.loaded.size(); ++i) {
-            const ImgRef& r = mem.at(gr.loaded[i]);
-            if (!gr.resample && p.nodes[gr.loaded[i]].kind == Kind::Input)
-                check_align(r, gr.g.V, "input node " + std::to_string(gr.loaded[i]));
-            a.src[i] = r.ptr;
-            a.src_rs[i] = r.rs;
-            a.src_cs[i] = r.cs;
-        }
-        for (size_t i = 0; i < gr.liveouts.size(); ++i) {
-            const ImgRef& r = mem.at(gr.liveouts[i]);
-            if (!gr.resample && p.is_output(gr.liveouts[i]))
-                check_align(r, gr.g.V, "output node " + std::to_string(gr.liveouts[i]));
-            a.dst[i] = const_cast<void*>(r.ptr);
-            a.dst_rs[i] = r.rs;
-            a.dst_cs[i] = r.cs;
-        }
-        a.W = gr.W;
-        a.H = gr.H;
-        a.Ws = gr.Ws;
-        a.Hs = gr.Hs;
-        a.tiles_x = gr.tiles_x;
-        a.tiles_y = gr.tiles_y;
-        a.nwaves = gr.nwaves;
-        void* params[] = {&a};
-        hipError_t e;
-        if (gr.resample) {
-            int C = p.nodes[gr.g.nodes[0]].channels;
-            e = hipModuleLaunchKernel(gr.fn, gr.tiles_x, gr.tiles_y, C, 256, 1, 1, 0, st, params, nullptr);
-        } else {
-            int grid = (gr.nwaves + gr.g.WPB - 1) / gr.g.WPB;
-            e = hipModuleLaunchKernel(gr.fn, grid, 1, 1, 64 * gr.g.WPB, 1, 1, 0, st, params, nullptr);
-        }
-        hip_check(e, "hipModuleLaunchKernel");
+    for (auto& gr : plan.groups) launch_group(plan, gr, mem, st);
+}
+
+void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st) {
+    const Pipeline& p = plan.p;
+    WtArgsHost a;
+    std::memset(&a, 0, sizeof a);
+    for (size_t i = 0; i < gr.loaded.size(); ++i) {
+        const ImgRef& r = mem.at(gr.loaded[i]);
+        if (!gr.resample && p.nodes[gr.loaded[i]].kind == Kind::Input)
+            check_align(r, gr.g.V, "input node " + std::to_string(gr.loaded[i]));
+        a.src[i] = r.ptr;
+        a.src_rs[i] = r.rs;
+        a.src_cs[i] = r.cs;
     }
+    for (size_t i = 0; i < gr.liveouts.size(); ++i) {
+        const ImgRef& r = mem.at(gr.liveouts[i]);
+        if (!gr.resample && p.is_output(gr.liveouts[i]))
+            check_align(r, gr.g.V, "output node " + std::to_string(gr.liveouts[i]));
+        if ((double)r.rs * gr.H * (gr.mem_half_out[i] ? 2 : 4) >= 2147483647.0)
+            fail(WT_E_UNSUPPORTED, "an output plane of 2 GiB or more");
+        a.dst[i] = const_cast<void*>(r.ptr);
+        a.dst_rs[i] = r.rs;
+        a.dst_cs[i] = r.cs;
+    }
+    a.W = gr.W;
+    a.H = gr.H;
+    a.Ws = gr.Ws;
+    a.Hs = gr.Hs;
+    a.tiles_x = gr.tiles_x;
+    a.tiles_y = gr.tiles_y;
+    a.nwaves = gr.nwaves;
+    void* params[] = {&a};
+    hipError_t e;
+    if (gr.resample) {
+        int C = p.nodes[gr.g.nodes[0]].channels;
+        e = hipModuleLaunchKernel(gr.fn, gr.tiles_x, gr.tiles_y, C, 256, 1, 1, 0, st, params, nullptr);
+    } else {
+        int grid = (gr.nwaves + gr.g.WPB - 1) / gr.g.WPB;
+        e = hipModuleLaunchKernel(gr.fn, grid, 1, 1, 64 * gr.g.WPB, 1, 1, 0, st, params, nullptr);
+    }
+    hip_check(e, "hipModuleLaunchKernel");
 }
 
 std::string describe_plan(const Plan& plan) {

@@ -82,6 +82,8 @@ struct GroupSched {
     int WPB = 1;             // waves per workgroup
     bool fp16 = false;       // intermediates stored as FP16
     int PF = 1;              // rows of input loaded ahead of their first use
+    int XCD = 1;             // 1: remap workgroups so each XCD gets adjacent tiles
+    int NT = 0;              // 1: non-temporal loads and stores
     int align = 0;           // 0: centred (reads from both neighbours);
                              // 1: the paper's right-hyperplane skew (reads from the left only)
 };
@@ -131,21 +133,30 @@ struct GroupGeom {
 GroupGeom group_geometry(const Pipeline& p, const GroupSched& g);
 
 // ---------------------------------------------------------- machine ------
+// The paper's Table 1 parameters, for gfx950 (MI355X) by default.
 struct Machine {
     std::string name = "gfx950";
-    int ncu = 256;               // compute units
+    int ncu = 256;                 // compute units (NSMs)
     int simd_per_cu = 4;
-    int wave = 64;
+    int wave = 64;                 // WarpSize
     int vgpr_per_simd_lane = 512;  // VGPR file per lane per SIMD
-    int vgpr_granule = 8;
-    int max_vgpr_per_wave = 256;  // architectural VGPRs addressable by a wave
+    int vgpr_granule = 8;          // allocation granule
     int max_waves_per_simd = 8;
-    int max_wg_per_cu = 32;
-    int lds_per_cu = 160 * 1024;
-    int max_lds_per_wg = 160 * 1024;
-    double hbm_bw = 8.0e12;      // bytes / s
+    int max_waves_per_cu = 32;     // MaxWarpPerSM
+    int max_wg_per_cu = 32;        // MaxTbPerSM
+    int lds_per_cu = 160 * 1024;   // ShMemPerSM
+    int max_lds_per_wg = 160 * 1024;  // MaxShMemPerTb
+    int regs_per_cu = 131072;      // RegPerSM (4 SIMDs x 512 VGPRs x 64 lanes)
+    int max_regs_per_lane = 256;   // MaxRegPerThread (architectural VGPRs)
+    bool amd_vgpr_alloc = true;    // occupancy from per-SIMD VGPR allocation
+    int cores_per_cu = 64;         // 4 SIMDs x 16 lanes
+    double hbm_bw = 8.0e12;        // GlMemBW, bytes / s
     double clock_hz = 2.4e9;
-    int tx_sizes[2] = {64, 128}; // candidate transaction sizes, bytes
+    int tx_sizes[2] = {64, 128};   // GlMemTxSize candidates, bytes
+    double mem_latency_s = 2.0e-6; // loaded HBM latency (bytes in flight needed)
+    double hbm_efficiency = 0.75;  // achievable fraction of peak for streaming
+    double launch_us = 2.0;        // per-kernel launch and drain
+    int max_vgpr_per_wave = 256;   // architectural VGPRs addressable by a wave
 };
 Machine machine_from_device(int device);  // falls back to the constant table
 
@@ -163,10 +174,13 @@ struct SchedRequest {
     int W = 0, H = 0;
     std::string fixed;
     std::string model_path;
+    int max_group = 12;               // bound on stages per fused group
+    const double* weights = nullptr;  // Algorithm 2 weights (default: refitted table)
 };
 Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r);
 Schedule schedule_unfused(const Pipeline& p, bool fp16);
 int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H);
+void fusion_costs(const Pipeline& p, const Machine& m, const SchedRequest& r, double* dp, double* brute);
 
 // ----------------------------------------------------------------- jit ---
 std::vector<char> compile_hip(const std::string& src, const std::string& name,

@@ -62,6 +62,17 @@ struct Plan {
     ~Plan();
 };
 
+struct ImgRef {
+    const void* ptr;
+    int64_t rs, cs;
+};
+
+void hip_check(hipError_t e, const char* what);
+std::pair<int, int> level_dims(int W, int H, int level);
+void prepare_group(const Plan& plan, GroupRt& gr, int gi);
+void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs);
+void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st);
+void autotune_plan(Plan& plan, int topk);
 std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H);
 void build_groups(Plan& plan);
 void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int nout, void* stream);

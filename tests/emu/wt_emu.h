@@ -21,7 +21,7 @@
 #include <vector>
 
 struct wt_emu_dim3 { unsigned x = 0, y = 0, z = 0; };
-static thread_local wt_emu_dim3 threadIdx, blockIdx;
+static thread_local wt_emu_dim3 threadIdx, blockIdx, gridDim;
 static thread_local int wt_emu_lane = 0;
 static std::barrier<>* wt_emu_bar = nullptr;
 static uint32_t wt_emu_x[64];

@@ -45,7 +45,7 @@ extern "C" int wt_emu_run(const WtArgs* a, int nwaves, int wpb) {
             wt_emu_lane = l;
             for (int b = 0; b < nblocks; ++b)
                 for (int w = 0; w < wpb; ++w) {
-                    blockIdx.x = b; threadIdx.x = w * 64 + l;
+                    blockIdx.x = b; threadIdx.x = w * 64 + l; gridDim.x = nblocks;
                     bar.arrive_and_wait();
                     WT_EMU_KERNEL(*a);
                     bar.arrive_and_wait();
@@ -58,6 +58,7 @@ extern "C" int wt_emu_run_grid(const WtArgs* a, int gx, int gy, int gz, int nthr
     for (int z = 0; z < gz; ++z) for (int y = 0; y < gy; ++y) for (int x = 0; x < gx; ++x)
         for (int t = 0; t < nthr; ++t) {
             blockIdx.x = x; blockIdx.y = y; blockIdx.z = z; threadIdx.x = t;
+            gridDim.x = gx; gridDim.y = gy; gridDim.z = gz;
             WT_EMU_KERNEL(*a);
         }
     return 0;
