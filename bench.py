@@ -29,7 +29,7 @@ METRIC = "Mpixels/s per pipeline, fused vs unfused on 1 GPU; % of HBM roofline"
 C, H, W = 3, 2048, 2048
 BYTES_PER_PX = 24  # 3 channels x (4 B in + 4 B out)
 HBM_PEAK_GBS = 8000.0
-DEFAULT_FUSED = "nodes=1,2,3,4 V=4 TX=1 SX=0 TY=16 PF=2"
+DEFAULT_FUSED = "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1"
 
 
 def log(msg):
@@ -123,6 +123,65 @@ def cpu_baseline(img, seconds=10.0):
                       "numpy float64, single-threaded)"}
 
 
+def bench_other(args, torch, wt, synth, P):
+    """Secondary workloads (same timing method), one JSON line each."""
+    import numpy as np
+    cyc = calibrate_sleep(torch)
+    dev = torch.device("cuda:0")
+    res = {"workload": args.workload}
+    if args.workload in ("harris", "blur"):
+        if args.workload == "harris":
+            C_, H_, W_, spec, seed = 3, 4096, 4096, P.harris(), 3
+            img = synth.white_squares(synth.uniform_image(seed, C_, H_, W_), seed, count=200)
+            bpp = 16  # 12 B RGB in + 4 B out
+        else:
+            C_, H_, W_, spec, seed = 1, 256, 256, P.gaussian_blur(), 1
+            img = synth.uniform_image(seed, C_, H_, W_)
+            bpp = 8
+        base = torch.from_numpy(img).to(dev)
+        nsets = max(2, min(8, int(1.2e9 // (base.numel() * 4 * 1.33)) or 2))
+        ins = [base.clone() for _ in range(nsets)]
+        outs = [torch.empty((1, H_, W_), device=dev) for _ in range(nsets)]
+        for mode, fp16 in (("autotune", True), ("autotune", False), ("unfused", False)):
+            plan = wt.from_spec(spec).plan(W_, H_, mode=mode, fp16=fp16)
+            ms = time_plan(torch, plan, ins, outs, args.steps, args.warmup, cyc)
+            key = f"{mode}{'_fp16' if fp16 else ''}"
+            res[key] = {"Mpix/s": H_ * W_ / (ms * 1e-3) / 1e6, "us": ms * 1e3,
+                        "GB/s_algorithmic": bpp * H_ * W_ / (ms * 1e-3) / 1e9,
+                        "kernels": plan.num_groups, "schedule": plan.describe().strip()}
+            log(f"{args.workload} {key}: {ms * 1e3:.1f} us, {res[key]['GB/s_algorithmic']:.0f} GB/s")
+    elif args.workload == "pyramid":
+        spec = P.pyramid_blend(4)
+        sizes = synth.batch_sizes(4, 64)
+        ins, outs, px = [], [], 0
+        for i, (w, h) in enumerate(sizes):
+            a = torch.from_numpy(synth.uniform_image(4000 + 2 * i, 1, h, w)).to(dev)
+            b = torch.from_numpy(synth.uniform_image(4001 + 2 * i, 1, h, w)).to(dev)
+            m = torch.from_numpy(synth.ramp_mask(h, w)).to(dev)
+            ins.append([a, b, m])
+            outs.append([torch.empty((1, h, w), device=dev)])
+            px += w * h
+        for mode in ("analytic", "unfused"):
+            plan = wt.from_spec(spec).plan(sizes[0][0], sizes[0][1], mode=mode, any_width=True)
+            for _ in range(2):
+                plan.run_batch(ins, outs)
+            torch.cuda.synchronize()
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record(s)
+            for _ in range(reps):
+                plan.run_batch(ins, outs)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            res[mode] = {"Mpix/s": px / (ms * 1e-3) / 1e6, "ms": ms, "groups": plan.num_groups,
+                         "GB/s_algorithmic": 16 * px / (ms * 1e-3) / 1e9}
+            log(f"pyramid batch {mode}: {ms:.2f} ms, {res[mode]['Mpix/s']:.0f} Mpix/s, {plan.num_groups} launches")
+        res["pixels"] = px
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +192,8 @@ def main():
     ap.add_argument("--sets", type=int, default=6, help="rotating buffer sets (>256 MB total)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the unfused and FP16 legs")
+    ap.add_argument("--workload", default="unsharp", choices=["unsharp", "harris", "blur", "pyramid"],
+                    help="unsharp (default, the reported metric) or a secondary workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -145,6 +206,8 @@ def main():
     import synth
     from synth import pipelines as P
 
+    if args.workload != "unsharp":
+        return bench_other(args, torch, wt, synth, P)
     img = synth.uniform_image(2, C, H, W)
     ins, outs = make_sets(torch, img, args.sets)
     cyc = calibrate_sleep(torch)

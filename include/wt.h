@@ -111,7 +111,9 @@ typedef enum {
 } wt_sched_mode;
 
 enum {
-    WT_PLAN_NO_DEVICE = 1 /* generate and compile code only; run() refused   */
+    WT_PLAN_NO_DEVICE = 1, /* generate and compile code only; run() refused   */
+    WT_PLAN_ANY_WIDTH = 2  /* caller images may have any width and stride:
+                              groups touching them use one element per lane */
 };
 
 typedef struct {
@@ -135,6 +137,18 @@ wt_status wt_plan_create(const wt_pipeline* p, const wt_sched_opts* opts,
  * must equal the planned ones.  Inputs and outputs must not alias. */
 wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
                       const wt_image* out, int nout, void* hip_stream);
+
+/* Runs the plan over a batch of `nimg` image sets of possibly different
+ * sizes: in[i*nin + k] is input k of image i, out[i*nout + k] output k.
+ * Every group runs as one persistent launch over the tiles of all images
+ * (the project's batched launch); the group sequence is captured in a
+ * hipGraph on the first run of a batch shape (the list of sizes) and
+ * replayed while the shape is unchanged (only image pointers may change).
+ * Intermediates live in a plan-owned arena sized for the shape.  Each
+ * image must satisfy the plan's vector-width alignment (plan with
+ * WT_PLAN_ANY_WIDTH for arbitrary widths).  Asynchronous on `hip_stream`. */
+wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in,
+                            const wt_image* out, void* hip_stream);
 
 /* Schedule as text: one line per group,
  *   "g<i> nodes=<id,id,...> V=<v> TX=<t> SX=<s> TY=<rows> WPB=<w> fp16=<0|1>"

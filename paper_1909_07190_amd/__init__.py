@@ -23,6 +23,7 @@ SCHED = {"unfused": 0, "analytic": 1, "mlp": 2, "autotune": 3, "fixed": 4}
 DOWN2, UP2 = 0, 1
 F32, F16 = 0, 1
 PLAN_NO_DEVICE = 1
+PLAN_ANY_WIDTH = 2
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 
@@ -61,6 +62,8 @@ _sig("wt_plan_create", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtSchedOpts
      ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
 _sig("wt_plan_run", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtImage), ctypes.c_int,
      ctypes.POINTER(WtImage), ctypes.c_int, ctypes.c_void_p)
+_sig("wt_plan_run_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
+     ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_describe", ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t,
      ctypes.POINTER(ctypes.c_size_t))
 _sig("wt_plan_source", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t,
@@ -125,9 +128,10 @@ class Pipeline:
         _check(lib.wt_output(self._h, node))
 
     def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
-             no_device=False, model_path=None, cache_dir=None, autotune_topk=0) -> "Plan":
+             no_device=False, model_path=None, cache_dir=None, autotune_topk=0,
+             any_width=False) -> "Plan":
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
-                    autotune_topk)
+                    autotune_topk, any_width)
 
 
 def from_spec(spec: dict) -> Pipeline:
@@ -170,9 +174,10 @@ class Plan:
     """A compiled schedule for one image size."""
 
     def __init__(self, pipe: Pipeline, width, height, mode, fp16, fixed, no_device,
-                 model_path, cache_dir, autotune_topk):
+                 model_path, cache_dir, autotune_topk, any_width=False):
         self.pipe = pipe  # keeps the pipeline alive
-        opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), PLAN_NO_DEVICE if no_device else 0,
+        flags = (PLAN_NO_DEVICE if no_device else 0) | (PLAN_ANY_WIDTH if any_width else 0)
+        opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), flags,
                            autotune_topk, fixed.encode() if fixed else None,
                            model_path.encode() if model_path else None,
                            cache_dir.encode() if cache_dir else None)
@@ -195,6 +200,18 @@ class Plan:
             stream = torch.cuda.current_stream()
         s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         _check(lib.wt_plan_run(self._h, ins, len(inputs), outs, len(outputs), ctypes.c_void_p(s)))
+
+    def run_batch(self, inputs, outputs, stream=None):
+        """Runs a batch: inputs[i] / outputs[i] are the tensors of image i."""
+        import torch
+        ins = [_image(t) for img in inputs for t in img]
+        outs = [_image(t) for img in outputs for t in img]
+        a_in = (WtImage * len(ins))(*ins)
+        a_out = (WtImage * len(outs))(*outs)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(lib.wt_plan_run_batch(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
 
     def describe(self) -> str:
         n = ctypes.c_size_t()

@@ -1,7 +1,7 @@
 """Builds libwavetile.so in-tree (host C++ with g++, device code with hipcc
 for gfx950), then links it against the HIP runtime and hipRTC.
 
-Usage: python -m paper_1909_07190_amd.build   (or build() from Python)
+Usage: python paper_1909_07190_amd/build.py   (or __graft_entry__.build())
 """
 from __future__ import annotations
 
@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["ir.cpp", "geometry.cpp", "codegen.cpp", "sched.cpp", "fusion.cpp",
-                "cost.cpp", "autotune.cpp", "jit.cpp", "runtime.cpp", "capi.cpp"]
+                "cost.cpp", "autotune.cpp", "batch.cpp", "jit.cpp", "runtime.cpp", "capi.cpp"]
 DEVICE_SOURCES: list[str] = []
 # Packed-FP32 VALU forms are disabled in every HIP compilation.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -104,6 +104,7 @@ void autotune_plan(Plan& plan, int topk) {
     req.W = plan.W;
     req.H = plan.H;
     req.fp16 = plan.fp16;
+    req.any_width = plan.any_width;
     uint64_t phash = 1469598103934665603ull;
     for (auto& g : plan.groups)
         for (unsigned char c : g.kname) phash = (phash ^ c) * 1099511628211ull;
@@ -128,7 +129,7 @@ void autotune_plan(Plan& plan, int topk) {
         add(cur);
         for (int i = 0; i < topk && i < (int)by_pred.size(); ++i) add(by_pred[i]->g);
         for (int i = 0; i < topk && i < (int)by_score.size(); ++i) add(by_score[i]->g);
-        int vmax = max_vector_width(p, cur, plan.W, plan.H);
+        int vmax = max_vector_width(p, cur, plan.W, plan.H, plan.any_width);
         for (int V : {4, 2})
             for (int TX : {1, 2})
                 for (int TY : {16, 32}) {

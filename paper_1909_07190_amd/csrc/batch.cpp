@@ -1,0 +1,206 @@
+// Batched execution: many images of different sizes through one plan, one
+// persistent launch per group covering the tiles of every image, the whole
+// group sequence captured once per batch shape in a hipGraph and replayed.
+//
+// Per batch shape (the list of image sizes) the plan keeps: an arena with
+// every image's intermediates, a device table of per-image kernel arguments
+// for every group (rewritten before each run, so only the pointers of the
+// caller's images may change between runs), the per-group work prefix sums
+// and the instantiated graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "wt_runtime.h"
+
+namespace wt {
+
+BatchState::~BatchState() {
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    if (arena) hipFree(arena);
+    if (dargs) hipFree(dargs);
+}
+
+namespace {
+
+void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, int& ty, int& work) {
+    const Pipeline& p = plan.p;
+    if (gr.resample) {
+        tx = (lw + 63) / 64;
+        ty = (lh + 3) / 4;
+        work = tx * ty * p.nodes[gr.g.nodes[0]].channels;
+        return;
+    }
+    int amin = 1 << 30, amax = 0;
+    for (int lo : gr.geo.liveouts) {
+        const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(lo)];
+        amin = std::min(amin, ng.skew);
+        amax = std::max(amax, ng.skew);
+    }
+    tx = (lw - (amin - amax) + gr.geo.X - 1) / gr.geo.X;
+    ty = (lh + gr.g.TY - 1) / gr.g.TY;
+    work = tx * ty * (gr.geo.chan_parallel ? gr.geo.C : 1);
+}
+
+void check_batch_image(const wt_image& im, const Node& n, int W, int H, const std::string& tag) {
+    if (!im.data) fail(WT_E_INVALID, tag + ": null data");
+    if (im.width != W || im.height != H) fail(WT_E_SHAPE, tag + ": size mismatch within the image's set");
+    if (im.channels != n.channels) fail(WT_E_SHAPE, tag + ": wrong channel count");
+    if (im.dtype != WT_F32) fail(WT_E_UNSUPPORTED, tag + ": only WT_F32 images are supported");
+}
+
+}  // namespace
+
+void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
+    if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
+    const Pipeline& p = plan.p;
+    const int nin = (int)p.inputs.size(), nout = (int)p.outputs.size();
+    if (nimg < 1) fail(WT_E_INVALID, "batch needs at least one image");
+    if (!in || !out) fail(WT_E_INVALID, "null image array");
+    const int G = (int)plan.groups.size();
+
+    // sizes and per-image memory of the caller's images
+    std::vector<std::pair<int, int>> sizes(nimg);
+    std::vector<std::map<int, ImgRef>> mem(nimg);
+    for (int i = 0; i < nimg; ++i) {
+        const wt_image& first = in[(size_t)i * nin];
+        int W = first.width, H = first.height;
+        if (W <= 0 || H <= 0 || W > (1 << 24) || H > (1 << 24)) fail(WT_E_SHAPE, "bad image size in batch");
+        sizes[i] = {W, H};
+        for (int k = 0; k < nin; ++k) {
+            const wt_image& im = in[(size_t)i * nin + k];
+            int id = p.inputs[k];
+            check_batch_image(im, p.nodes[id], W, H, "batch image " + std::to_string(i) + " input " + std::to_string(k));
+            int64_t rs = im.row_stride ? im.row_stride : im.width;
+            mem[i][id] = {im.data, rs, im.chan_stride ? im.chan_stride : rs * im.height};
+        }
+        for (int k = 0; k < nout; ++k) {
+            const wt_image& im = out[(size_t)i * nout + k];
+            int id = p.outputs[k];
+            auto d = level_dims(W, H, p.nodes[id].level);
+            check_batch_image(im, p.nodes[id], d.first, d.second,
+                              "batch image " + std::to_string(i) + " output " + std::to_string(k));
+            int64_t rs = im.row_stride ? im.row_stride : im.width;
+            mem[i][id] = {im.data, rs, im.chan_stride ? im.chan_stride : rs * im.height};
+        }
+    }
+
+    if (!plan.batch || plan.batch->sizes != sizes) {
+        plan.batch.reset();
+        auto st = std::make_unique<BatchState>();
+        st->sizes = sizes;
+        // arena for every image's intermediates
+        std::vector<std::map<int, Buf>> bufs(nimg);
+        size_t off = 0;
+        for (int i = 0; i < nimg; ++i)
+            for (auto& gr : plan.groups)
+                for (size_t k = 0; k < gr.liveouts.size(); ++k) {
+                    int id = gr.liveouts[k];
+                    if (p.is_output(id) || bufs[i].count(id)) continue;
+                    auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[id].level);
+                    Buf b;
+                    b.half = gr.mem_half_out[k];
+                    b.rs = (d.first + 63) / 64 * 64;
+                    b.cs = b.rs * d.second;
+                    b.ptr = reinterpret_cast<void*>(off);  // offset until the arena exists
+                    off += ((size_t)b.cs * p.nodes[id].channels * (b.half ? 2 : 4) + 255) / 256 * 256;
+                    bufs[i][id] = b;
+                }
+        if (off) {
+            if (hipMalloc(&st->arena, off) != hipSuccess) fail(WT_E_NOMEM, "batch intermediates");
+            st->arena_bytes = off;
+        }
+        st->bufs = bufs;
+        for (auto& m : st->bufs)
+            for (auto& kv : m) kv.second.ptr = static_cast<char*>(st->arena) + reinterpret_cast<size_t>(kv.second.ptr);
+        // per-group work and launch grids
+        st->total.resize(G);
+        st->grid.resize(G);
+        st->tiles.assign((size_t)G * nimg, {0, 0, 0});
+        for (int g = 0; g < G; ++g) {
+            int tot = 0;
+            for (int i = 0; i < nimg; ++i) {
+                auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[plan.groups[g].g.nodes[0]].level);
+                int tx, ty, w;
+                tile_counts(plan, plan.groups[g], d.first, d.second, tx, ty, w);
+                st->tiles[(size_t)g * nimg + i] = {tx, ty, w};
+                tot += w;
+            }
+            st->total[g] = tot;
+            const GroupRt& gr = plan.groups[g];
+            int per_cu = 1;
+            int threads = gr.resample ? 256 : 64 * gr.g.WPB;
+            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gr.fn_batch, threads, 0) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            int units = gr.resample ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
+            st->grid[g] = std::max(1, std::min(units, per_cu * plan.machine.ncu));
+        }
+        // device argument table: [g][img] WtArgs, then [g][nimg + 1] starts
+        st->args_bytes = (size_t)G * nimg * sizeof(WtArgsHost);
+        st->dargs_bytes = st->args_bytes + (size_t)G * (nimg + 1) * sizeof(int);
+        if (hipMalloc(&st->dargs, st->dargs_bytes) != hipSuccess) fail(WT_E_NOMEM, "batch argument table");
+        st->host.resize(st->dargs_bytes);
+        // capture the launch sequence once for this shape
+        hipStream_t cs;
+        hip_check(hipStreamCreate(&cs), "hipStreamCreate");
+        hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        for (int g = 0; g < G; ++g) {
+            const GroupRt& gr = plan.groups[g];
+            const void* a = static_cast<char*>(st->dargs) + (size_t)g * nimg * sizeof(WtArgsHost);
+            const void* s = static_cast<char*>(st->dargs) + st->args_bytes + (size_t)g * (nimg + 1) * sizeof(int);
+            int ni = nimg, tot = st->total[g];
+            void* params[] = {&a, &s, &ni, &tot};
+            int threads = gr.resample ? 256 : 64 * gr.g.WPB;
+            hipError_t e = hipModuleLaunchKernel(gr.fn_batch, st->grid[g], 1, 1, threads, 1, 1, 0, cs, params, nullptr);
+            if (e != hipSuccess) {
+                hipGraph_t tmp;
+                hipStreamEndCapture(cs, &tmp);
+                if (tmp) hipGraphDestroy(tmp);
+                hipStreamDestroy(cs);
+                hip_check(e, "hipModuleLaunchKernel (capture)");
+            }
+        }
+        hip_check(hipStreamEndCapture(cs, &st->graph), "hipStreamEndCapture");
+        hipStreamDestroy(cs);
+        hip_check(hipGraphInstantiate(&st->exec, st->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+        plan.batch = std::move(st);
+    }
+
+    BatchState& st = *plan.batch;
+    for (int i = 0; i < nimg; ++i)
+        for (auto& kv : st.bufs[i]) mem[i][kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
+    // fill the argument table
+    std::memset(st.host.data(), 0, st.host.size());
+    for (int g = 0; g < G; ++g) {
+        const GroupRt& gr = plan.groups[g];
+        int* starts = reinterpret_cast<int*>(st.host.data() + st.args_bytes) + (size_t)g * (nimg + 1);
+        int acc = 0;
+        for (int i = 0; i < nimg; ++i) {
+            WtArgsHost& a = reinterpret_cast<WtArgsHost*>(st.host.data())[(size_t)g * nimg + i];
+            auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[gr.g.nodes[0]].level);
+            fill_args(plan, gr, mem[i], a, "batch image " + std::to_string(i));
+            a.W = d.first;
+            a.H = d.second;
+            if (gr.resample) {
+                auto sd = level_dims(sizes[i].first, sizes[i].second, p.nodes[p.nodes[gr.g.nodes[0]].srcs[0]].level);
+                a.Ws = sd.first;
+                a.Hs = sd.second;
+            }
+            const auto& t = st.tiles[(size_t)g * nimg + i];
+            a.tiles_x = t[0];
+            a.tiles_y = t[1];
+            a.nwaves = t[2];
+            starts[i] = acc;
+            acc += t[2];
+        }
+        starts[nimg] = acc;
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hip_check(hipMemcpyAsync(st.dargs, st.host.data(), st.host.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    hip_check(hipGraphLaunch(st.exec, s), "hipGraphLaunch");
+}
+
+}  // namespace wt

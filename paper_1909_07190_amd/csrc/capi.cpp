@@ -187,6 +187,13 @@ wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin, const wt_image
     });
 }
 
+wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
+    return guard([&] {
+        if (!plan) wt::fail(WT_E_INVALID, "null plan");
+        wt::run_plan_batch(*plan->impl, nimg, in, out, stream);
+    });
+}
+
 static wt_status copy_out(const std::string& s, char* buf, size_t len, size_t* needed) {
     if (needed) *needed = s.size() + 1;
     if (buf && len) {

@@ -112,14 +112,17 @@ struct Gen {
                 // lane 0 belongs to the overlap: any value
                 return memoize("wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(" + cur + "), WT_DPP_WAVE_SHR1, 0xF, 0xF, true))");
             }
-            if (k - 1 >= SX)
-                return memoize("wt_shiftd(" + cur + ", " + reg(p, slot, chp, k - 1 - SX, ep) + ", " +
-                               I(d) + ", lane)");
+            if (k - 1 >= SX) {
+                std::string prv = reg(p, slot, chp, k - 1 - SX, ep);
+                if (d == 2) return memoize("wt_shift2(" + cur + ", " + prv + ")");
+                return memoize("wt_shiftd(" + cur + ", " + prv + ", " + I(d) + ", lane)");
+            }
             if (k - 1 >= 0) {
                 std::string pv = memoize(lread(p, slot, chp, I((k - 1) * SUB) + " + ((lane - " + I(d) +
                                                                ") & 63) * " + I(V) + " + " + I(ep)));
                 return memoize("wt_shiftd_l(" + cur + ", " + pv + ", " + I(d) + ", lane)");
             }
+            if (d == 2) return memoize("wt_shift2(" + cur + ", " + cur + ")");
             return memoize("wt_shiftd(" + cur + ", " + cur + ", " + I(d) + ", lane)");
         }
         // q >= V: source to the right (lane t + d, or the next sub-tile)
@@ -140,10 +143,12 @@ struct Gen {
         std::string cur = reg(p, slot, chp, k - SX, ep);
         if (k + 1 >= g.TX) {  // lanes past the strip belong to the overlap: any value
             if (d == 1) return memoize("wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(" + cur + "), WT_DPP_WAVE_SHL1, 0xF, 0xF, true))");
+            if (d == 2) return memoize("wt_shift2n(" + cur + ", " + cur + ")");
             return memoize("wt_shiftdn(" + cur + ", " + cur + ", " + I(d) + ", lane)");
         }
         std::string next = reg(p, slot, chp, k + 1 - SX, ep);
         if (d == 1) return memoize("wt_shift1n(" + cur + ", " + next + ")");
+        if (d == 2) return memoize("wt_shift2n(" + cur + ", " + next + ")");
         return memoize("wt_shiftdn(" + cur + ", " + next + ", " + I(d) + ", lane)");
     }
 
@@ -469,11 +474,14 @@ struct Gen {
         ind.resize(ind.size() - 4);
     }
 
-    std::string kernel(const std::string& kname) {
-        int amax = 0, amin = 1 << 30;
+    int amax_ = 0, amin_ = 0;
+
+    void header() {
+        amax_ = 0;
+        amin_ = 1 << 30;
         for (auto& n : geo.nodes) {
-            amax = std::max(amax, n.skew);
-            amin = std::min(amin, n.skew);
+            amax_ = std::max(amax_, n.skew);
+            amin_ = std::min(amin_, n.skew);
         }
         o << "// group: " << describe_group(g) << "\n";
         o << "// N=" << N << " X=" << geo.X << " S0=" << geo.S0 << " base=" << geo.base << " D=" << geo.D << " U=" << geo.U
@@ -482,23 +490,38 @@ struct Gen {
         for (auto& n : geo.nodes)
             o << "//   node " << n.id << (n.member ? " member" : " loaded") << (n.liveout ? " liveout" : "")
               << " skew=" << n.skew << " lead=" << n.lead << " win=" << n.win << " nch=" << n.nch
-              << " first=" << n.first_step << " vlo=" << n.vlo << " vhi=" << n.vhi << (n.half ? " fp16" : "") << (n.mem_half ? " mem-fp16" : "") << "\n";
-        o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * g.WPB << ") " << kname
-          << "(const WtArgs A) {\n";
-        line("const int lane = threadIdx.x & 63;");
-        // wave-uniform tile coordinates live in SGPRs (scalar branches)
+              << " first=" << n.first_step << " vlo=" << n.vlo << " vhi=" << n.vhi << (n.half ? " fp16" : "")
+              << (n.mem_half ? " mem-fp16" : "") << "\n";
+    }
+
+    // Index of this wave among all waves of the launch (wave-uniform, in an
+    // SGPR).  Workgroups are dispatched round-robin over the 8 XCDs; with
+    // XCD=1 each XCD gets a contiguous range of tiles so vertically adjacent
+    // tiles (which share halo rows) run on one XCD and meet in its L2.
+    void wave_index(const std::string& var) {
         if (g.XCD) {
-            // Workgroups are dispatched round-robin over the 8 XCDs; give each
-            // XCD a contiguous range of tiles so vertically adjacent tiles
-            // (which share halo rows) run on one XCD and meet in its L2.
             line("const int nb = gridDim.x, b = blockIdx.x;");
             line("const int xq = nb / WT_NXCD, xr = nb % WT_NXCD, xi = b % WT_NXCD;");
             line("const int lb = xi * xq + min(xi, xr) + b / WT_NXCD;");
-            line("const int wid = __builtin_amdgcn_readfirstlane(lb * " + I(g.WPB) + " + (threadIdx.x >> 6));");
+            line("const int " + var + " = __builtin_amdgcn_readfirstlane(lb * " + I(g.WPB) + " + (threadIdx.x >> 6));");
         } else {
-            line("const int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * " + I(g.WPB) + " + (threadIdx.x >> 6));");
+            line("const int " + var + " = __builtin_amdgcn_readfirstlane(blockIdx.x * " + I(g.WPB) +
+                 " + (threadIdx.x >> 6));");
         }
-        line("if (wid >= A.nwaves) return;");
+    }
+
+    void lds_decl() {
+        if (geo.lds_bytes <= 0) return;
+        line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
+        line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
+        for (auto& n : geo.nodes)
+            if (has_lds(n))
+                line(std::string(n.half ? "_Float16" : "float") + "* L" + I(n.id) + " = (" +
+                     (n.half ? "_Float16" : "float") + "*)(lds + " + I(n.lds_off) + ");");
+    }
+
+    // One wave tile `wid` of the image described by `A`.
+    void tile() {
         line("const int ty = wid % A.tiles_y;");
         line("const int rr = wid / A.tiles_y;");
         line("const int tx = rr % A.tiles_x;");
@@ -508,15 +531,7 @@ struct Gen {
         line("const int x0 = tx * " + I(geo.X) + " + (" + I(geo.base) + ");");
         line("const int y0 = ty * " + I(g.TY) + ";");
         line("const int kend = y0 + " + I(g.TY) + ";");
-        line("const bool bx = (x0 + " + I(amin) + " < 0) || (x0 + " + I(amax) + " + " + I(N) + " > W);");
-        if (geo.lds_bytes > 0) {
-            line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
-            line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
-            for (auto& n : geo.nodes)
-                if (has_lds(n))
-                    line(std::string(n.half ? "_Float16" : "float") + "* L" + I(n.id) + " = (" +
-                         (n.half ? "_Float16" : "float") + "*)(lds + " + I(n.lds_off) + ");");
-        }
+        line("const bool bx = (x0 + " + I(amin_) + " < 0) || (x0 + " + I(amax_) + " + " + I(N) + " > W);");
         // buffer resources for the live-outs, one per channel plane
         for (size_t oi = 0; oi < geo.liveouts.size(); ++oi) {
             const NodeGeom& n = G(geo.liveouts[oi]);
@@ -532,6 +547,44 @@ struct Gen {
         line("} else {");
         body(true);
         line("}");
+    }
+
+    // Single-image kernel: one wave per tile.
+    std::string kernel(const std::string& kname) {
+        header();
+        o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * g.WPB << ") " << kname
+          << "(const WtArgs A) {\n";
+        line("const int lane = threadIdx.x & 63;");
+        wave_index("wid");
+        line("if (wid >= A.nwaves) return;");
+        lds_decl();
+        tile();
+        o << "}\n";
+        return o.str();
+    }
+
+    // Batched persistent kernel: the launch's waves loop over the tiles of
+    // all images; image i owns tiles start[i] .. start[i+1]-1 and its
+    // arguments are AB[i].
+    std::string batch_kernel(const std::string& kname) {
+        o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * g.WPB << ") " << kname
+          << "_batch(const WtArgs* __restrict__ AB, const int* __restrict__ start, const int nimg, const int total) {\n";
+        line("const int lane = threadIdx.x & 63;");
+        wave_index("w0");
+        line("const int wstride = gridDim.x * " + I(g.WPB) + ";");
+        lds_decl();
+        line("for (int t = w0; t < total; t += wstride) {");
+        ind += "    ";
+        line("int lo = 0, hi = nimg;");
+        line("while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (start[mid] <= t) lo = mid; else hi = mid; }");
+        line("const int img = __builtin_amdgcn_readfirstlane(lo);");
+        line("const WtArgs& A = AB[img];");
+        line("const int wid = t - start[img];");
+        line("{");
+        tile();
+        line("}");
+        ind.resize(ind.size() - 4);
+        line("}");
         o << "}\n";
         return o.str();
     }
@@ -544,21 +597,28 @@ std::string generate_group_source(const Pipeline& p, const GroupSched& g, const 
     if ((int)geo.loaded.size() > 16 || (int)geo.liveouts.size() > 16)
         fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
     Gen gen(p, g, geo);
-    return device_prelude() + "\n" + gen.kernel(kname);
+    std::string single = gen.kernel(kname);
+    Gen gb(p, g, geo);
+    gb.header();
+    gb.o.str("");
+    std::string batch = gb.batch_kernel(kname);
+    return device_prelude() + "\n" + single + "\n" + batch;
 }
 
 // 2x resampling kernels: one thread per output pixel, clamped reads.  Not
-// fused (a scaled dependence ends a group in this implementation).
+// fused (a scaled dependence ends a group in this implementation).  The
+// single-image kernel runs a (tiles_x, tiles_y, channels) grid of 256-thread
+// blocks (64 x 4 pixels); the batched kernel loops its blocks over the
+// blocks of all images.
 std::string generate_resample_source(const Pipeline& p, const GroupSched& g, const std::string& kname,
                                      bool src_half, bool dst_half) {
     const std::string st = src_half ? "_Float16" : "float", dt = dst_half ? "_Float16" : "float";
     const Node& n = p.nodes[g.nodes[0]];
     std::ostringstream o;
     o << device_prelude() << "\n";
-    o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname << "(const WtArgs A) {\n";
-    o << "    const int x = blockIdx.x * 64 + (threadIdx.x & 63);\n";
-    o << "    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);\n";
-    o << "    const int c = blockIdx.z;\n";
+    o << "static __device__ __forceinline__ void " << kname << "_body(const WtArgs& A, int bxi, int byi, int c) {\n";
+    o << "    const int x = bxi * 64 + (threadIdx.x & 63);\n";
+    o << "    const int y = byi * 4 + (threadIdx.x >> 6);\n";
     o << "    if (x >= A.W || y >= A.H) return;\n";
     o << "    const " << st << "* s = (const " << st << "*)A.src[0] + (long long)c * A.src_cs[0];\n";
     o << "    " << dt << "* d = (" << dt << "*)A.dst[0] + (long long)c * A.dst_cs[0];\n";
@@ -585,6 +645,20 @@ std::string generate_resample_source(const Pipeline& p, const GroupSched& g, con
         o << "    }\n";
         o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")acc;\n";
     }
+    o << "}\n";
+    o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname << "(const WtArgs A) {\n";
+    o << "    " << kname << "_body(A, blockIdx.x, blockIdx.y, blockIdx.z);\n";
+    o << "}\n";
+    o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname
+      << "_batch(const WtArgs* __restrict__ AB, const int* __restrict__ start, const int nimg, const int total) {\n";
+    o << "    for (int t = blockIdx.x; t < total; t += gridDim.x) {\n";
+    o << "        int lo = 0, hi = nimg;\n";
+    o << "        while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (start[mid] <= t) lo = mid; else hi = mid; }\n";
+    o << "        const WtArgs& A = AB[lo];\n";
+    o << "        const int l = t - start[lo];\n";
+    o << "        const int r = l / A.tiles_x;\n";
+    o << "        " << kname << "_body(A, l % A.tiles_x, r % A.tiles_y, r / A.tiles_y);\n";
+    o << "    }\n";
     o << "}\n";
     return o.str();
 }

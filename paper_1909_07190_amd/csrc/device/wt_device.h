@@ -88,6 +88,16 @@ WT_DEV float wt_shiftdn(float cur, float next, int d, int lane) {
     return lane < 64 - d ? c : n;
 }
 
+// Two-lane shifts composed from one-lane DPP shifts (no LDS crossbar):
+// lanes 2..63 read cur of lane t-2, lanes 0..1 read prev of lanes 62..63.
+WT_DEV float wt_shift2(float cur, float prev) {
+    return wt_shift1(wt_shift1(cur, prev), wt_shift1(prev, prev));
+}
+// Mirror image: lanes 0..61 read cur of lane t+2, lanes 62..63 next of lanes 0..1.
+WT_DEV float wt_shift2n(float cur, float next) {
+    return wt_shift1n(wt_shift1n(cur, next), wt_shift1n(next, next));
+}
+
 // Types 3 + 4 for a d-lane shift, 1 <= d <= 63: lanes t >= d read cur of lane
 // t-d, lanes t < d read prev of lane 64+t-d.
 WT_DEV float wt_shiftd(float cur, float prev, int d, int lane) {

@@ -183,7 +183,7 @@ std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, con
     GroupSched base;
     base.nodes = nodes;
     base.fp16 = r.fp16;
-    int vmax = max_vector_width(p, base, r.W, r.H);
+    int vmax = max_vector_width(p, base, r.W, r.H, r.any_width);
     const double* w = r.weights ? r.weights : kGfx950Weights;
     for (int V : {4, 2, 1}) {
         if (V > vmax) continue;

@@ -59,6 +59,7 @@ std::string kernel_name(const Pipeline& p, const GroupSched& g, int gi) {
 }  // namespace
 
 Plan::~Plan() {
+    batch.reset();
     for (auto& g : groups)
         if (g.mod) hipModuleUnload(g.mod);
     for (auto& b : bufs)
@@ -78,6 +79,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     const wt_sched_opts& opts = o ? *o : def;
     plan->no_device = (opts.flags & WT_PLAN_NO_DEVICE) != 0;
     plan->fp16 = opts.fp16_intermediates != 0;
+    plan->any_width = (opts.flags & WT_PLAN_ANY_WIDTH) != 0;
     const char* env_cache = std::getenv("WT_CACHE_DIR");
     plan->cache_dir = opts.cache_dir ? opts.cache_dir : (env_cache ? env_cache : "");
     if (!plan->no_device) hip_check(hipGetDevice(&plan->device), "hipGetDevice");
@@ -88,6 +90,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     req.fp16 = plan->fp16;
     req.W = W;
     req.H = H;
+    req.any_width = plan->any_width;
     if (opts.fixed_schedule) req.fixed = opts.fixed_schedule;
     if (opts.model_path) req.model_path = opts.model_path;
     plan->sched = make_schedule(p, plan->machine, req);
@@ -173,6 +176,8 @@ void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs) {
         if (grs[i]->mod) continue;
         hip_check(hipModuleLoadData(&grs[i]->mod, code[i].data()), "hipModuleLoadData");
         hip_check(hipModuleGetFunction(&grs[i]->fn, grs[i]->mod, grs[i]->kname.c_str()), "hipModuleGetFunction");
+        hip_check(hipModuleGetFunction(&grs[i]->fn_batch, grs[i]->mod, (grs[i]->kname + "_batch").c_str()),
+                  "hipModuleGetFunction");
     }
 }
 
@@ -180,6 +185,7 @@ void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs) {
 // of plan.sched, then device buffers for the intermediates.
 void build_groups(Plan& plan) {
     const Pipeline& p = plan.p;
+    plan.batch.reset();
     for (auto& g : plan.groups)
         if (g.mod) hipModuleUnload(g.mod);
     plan.groups.clear();
@@ -271,14 +277,14 @@ void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int 
     for (auto& gr : plan.groups) launch_group(plan, gr, mem, st);
 }
 
-void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st) {
+void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, WtArgsHost& a,
+               const std::string& tag) {
     const Pipeline& p = plan.p;
-    WtArgsHost a;
     std::memset(&a, 0, sizeof a);
     for (size_t i = 0; i < gr.loaded.size(); ++i) {
         const ImgRef& r = mem.at(gr.loaded[i]);
         if (!gr.resample && p.nodes[gr.loaded[i]].kind == Kind::Input)
-            check_align(r, gr.g.V, "input node " + std::to_string(gr.loaded[i]));
+            check_align(r, gr.g.V, tag + " input node " + std::to_string(gr.loaded[i]));
         a.src[i] = r.ptr;
         a.src_rs[i] = r.rs;
         a.src_cs[i] = r.cs;
@@ -286,13 +292,20 @@ void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRe
     for (size_t i = 0; i < gr.liveouts.size(); ++i) {
         const ImgRef& r = mem.at(gr.liveouts[i]);
         if (!gr.resample && p.is_output(gr.liveouts[i]))
-            check_align(r, gr.g.V, "output node " + std::to_string(gr.liveouts[i]));
-        if ((double)r.rs * gr.H * (gr.mem_half_out[i] ? 2 : 4) >= 2147483647.0)
-            fail(WT_E_UNSUPPORTED, "an output plane of 2 GiB or more");
+            check_align(r, gr.g.V, tag + " output node " + std::to_string(gr.liveouts[i]));
         a.dst[i] = const_cast<void*>(r.ptr);
         a.dst_rs[i] = r.rs;
         a.dst_cs[i] = r.cs;
     }
+}
+
+void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st) {
+    const Pipeline& p = plan.p;
+    WtArgsHost a;
+    fill_args(plan, gr, mem, a, "");
+    for (size_t i = 0; i < gr.liveouts.size(); ++i)
+        if ((double)a.dst_rs[i] * gr.H * (gr.mem_half_out[i] ? 2 : 4) >= 2147483647.0)
+            fail(WT_E_UNSUPPORTED, "an output plane of 2 GiB or more");
     a.W = gr.W;
     a.H = gr.H;
     a.Ws = gr.Ws;

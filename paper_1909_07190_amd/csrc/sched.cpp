@@ -29,7 +29,7 @@ Schedule schedule_analytic(const Pipeline& p, const Machine& m, const SchedReque
 // Largest vector width a group may use: groups that read pipeline inputs or
 // write pipeline outputs address the caller's dense rows, so V must divide
 // that level's width (intermediate buffers are padded by the library).
-int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H) {
+int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H, bool any_width) {
     bool user = false;
     for (int n : g.nodes) {
         if (p.is_output(n)) user = true;
@@ -37,6 +37,7 @@ int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H) {
             if (p.nodes[s].kind == Kind::Input) user = true;
     }
     if (!user) return 4;
+    if (any_width) return 1;
     int lw = W;
     for (int i = 0; i < p.nodes[g.nodes[0]].level; ++i) lw = (lw + 1) / 2;
     (void)H;
@@ -47,7 +48,7 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
     switch (r.mode) {
         case WT_SCHED_UNFUSED: {
             Schedule s = schedule_unfused(p, r.fp16);
-            for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H));
+            for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
             return s;
         }
         case WT_SCHED_FIXED: {
@@ -59,7 +60,7 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
         case WT_SCHED_MLP:
         case WT_SCHED_AUTOTUNE: {
             Schedule s = schedule_analytic(p, m, r);
-            for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H));
+            for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
             return s;
         }
         default: fail(WT_E_INVALID, "unknown schedule mode");

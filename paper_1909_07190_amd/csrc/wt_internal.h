@@ -82,7 +82,7 @@ struct GroupSched {
     int WPB = 1;             // waves per workgroup
     bool fp16 = false;       // intermediates stored as FP16
     int PF = 1;              // rows of input loaded ahead of their first use
-    int XCD = 1;             // 1: remap workgroups so each XCD gets adjacent tiles
+    int XCD = 0;             // 1: remap workgroups so each XCD gets adjacent tiles
     int NT = 0;              // 1: non-temporal loads and stores
     int align = 0;           // 0: centred (reads from both neighbours);
                              // 1: the paper's right-hyperplane skew (reads from the left only)
@@ -175,11 +175,12 @@ struct SchedRequest {
     std::string fixed;
     std::string model_path;
     int max_group = 12;               // bound on stages per fused group
+    bool any_width = false;           // caller images of any width / stride
     const double* weights = nullptr;  // Algorithm 2 weights (default: refitted table)
 };
 Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r);
 Schedule schedule_unfused(const Pipeline& p, bool fp16);
-int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H);
+int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H, bool any_width = false);
 void fusion_costs(const Pipeline& p, const Machine& m, const SchedRequest& r, double* dp, double* brute);
 
 // ----------------------------------------------------------------- jit ---

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <map>
 #include <memory>
 #include <string>
@@ -41,11 +42,28 @@ struct GroupRt {
     bool resample = false;
     std::string src, kname;
     hipModule_t mod = nullptr;
-    hipFunction_t fn = nullptr;
+    hipFunction_t fn = nullptr;        // single image, one wave (or block) per tile
+    hipFunction_t fn_batch = nullptr;  // persistent, all images of a batch
     int W = 0, H = 0, Ws = 0, Hs = 0;
     int tiles_x = 0, tiles_y = 0, nwaves = 0;
     std::vector<int> loaded, liveouts;
     std::vector<bool> mem_half_in, mem_half_out;
+};
+
+// State of the last batch shape run through a plan (see batch.cpp).
+struct BatchState {
+    std::vector<std::pair<int, int>> sizes;
+    void* arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<std::map<int, Buf>> bufs;  // per image: intermediates in the arena
+    std::vector<std::array<int, 3>> tiles; // [group][img]: tiles_x, tiles_y, work items
+    std::vector<int> total, grid;          // per group
+    void* dargs = nullptr;                 // device argument table
+    size_t args_bytes = 0, dargs_bytes = 0;
+    std::vector<char> host;                // host copy of the table
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~BatchState();
 };
 
 struct Plan {
@@ -58,7 +76,9 @@ struct Plan {
     int device = 0;
     bool no_device = false;
     bool fp16 = false;
+    bool any_width = false;
     std::string cache_dir;
+    std::unique_ptr<BatchState> batch;
     ~Plan();
 };
 
@@ -72,6 +92,9 @@ std::pair<int, int> level_dims(int W, int H, int level);
 void prepare_group(const Plan& plan, GroupRt& gr, int gi);
 void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs);
 void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st);
+void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, WtArgsHost& a,
+               const std::string& tag);
+void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
 void autotune_plan(Plan& plan, int topk);
 std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H);
 void build_groups(Plan& plan);

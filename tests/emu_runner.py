@@ -54,6 +54,32 @@ extern "C" int wt_emu_run(const WtArgs* a, int nwaves, int wpb) {
     for (auto& t : th) t.join();
     return 0;
 }
+extern "C" int wt_emu_run_batch(const WtArgs* ab, const int* start, int nimg, int total, int nblocks, int wpb) {
+    std::barrier<> bar(64);
+    wt_emu_bar = &bar;
+    std::vector<std::thread> th;
+    for (int l = 0; l < 64; ++l)
+        th.emplace_back([&, l] {
+            wt_emu_lane = l;
+            for (int b = 0; b < nblocks; ++b)
+                for (int w = 0; w < wpb; ++w) {
+                    blockIdx.x = b; threadIdx.x = w * 64 + l; gridDim.x = nblocks;
+                    bar.arrive_and_wait();
+                    WT_EMU_KERNEL_BATCH(ab, start, nimg, total);
+                    bar.arrive_and_wait();
+                }
+        });
+    for (auto& t : th) t.join();
+    return 0;
+}
+extern "C" int wt_emu_run_grid_batch(const WtArgs* ab, const int* start, int nimg, int total, int nblocks) {
+    for (int b = 0; b < nblocks; ++b)
+        for (int t = 0; t < 256; ++t) {
+            blockIdx.x = b; threadIdx.x = t; gridDim.x = nblocks;
+            WT_EMU_KERNEL_BATCH(ab, start, nimg, total);
+        }
+    return 0;
+}
 extern "C" int wt_emu_run_grid(const WtArgs* a, int gx, int gy, int gz, int nthr) {
     for (int z = 0; z < gz; ++z) for (int y = 0; y < gy; ++y) for (int x = 0; x < gx; ++x)
         for (int t = 0; t < nthr; ++t) {
@@ -68,7 +94,7 @@ extern "C" int wt_emu_run_grid(const WtArgs* a, int gx, int gy, int gz, int nthr
 
 def _compile(src, kname):
     os.makedirs(CACHE, exist_ok=True)
-    text = '#include "wt_emu.h"\n' + src + f"\n#define WT_EMU_KERNEL {kname}\n" + RUNNER
+    text = '#include "wt_emu.h"\n' + src + f"\n#define WT_EMU_KERNEL {kname}\n#define WT_EMU_KERNEL_BATCH {kname}_batch\n" + RUNNER
     h = hashlib.sha1(text.encode()).hexdigest()[:16]
     so = os.path.join(CACHE, f"{kname}_{h}.so")
     if not os.path.exists(so):
@@ -80,6 +106,8 @@ def _compile(src, kname):
     lib = ctypes.CDLL(so)
     lib.wt_emu_run.argtypes = [ctypes.POINTER(Args), ctypes.c_int, ctypes.c_int]
     lib.wt_emu_run_grid.argtypes = [ctypes.POINTER(Args)] + [ctypes.c_int] * 4
+    lib.wt_emu_run_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 4
+    lib.wt_emu_run_grid_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 3
     return lib
 
 
@@ -142,3 +170,69 @@ def emulate(spec, inputs, **plan_kw):
         else:
             lib.wt_emu_run(ctypes.byref(a), gi.nwaves, gi.waves_per_group)
     return {o: bufs[names.index(o)].astype(np.float32) for o in spec["outputs"]}, plan
+
+
+def emulate_batch(spec, images, nblocks=3, **plan_kw):
+    """Runs a batch of images (list of input dicts, sizes may differ) through
+    the persistent batch kernels on the CPU, `nblocks` workgroups per launch
+    so the grid-stride loop runs; per-image arguments come from one plan per
+    image size (no device).  Returns one output dict per image."""
+    names, lv, ch = _meta(spec)
+    plans, bufs_all = [], []
+    for inputs in images:
+        first = inputs[spec["inputs"][0]["name"]]
+        h, w = first.shape[-2:]
+        if not plans:
+            plans.append(wt.from_spec(spec).plan(w, h, no_device=True, **plan_kw))
+        else:  # a batch shares one schedule: replay the first plan's
+            kw = dict(plan_kw, mode="fixed", fixed=plans[0].describe())
+            plans.append(wt.from_spec(spec).plan(w, h, no_device=True, **kw))
+        bufs = {}
+        for i, inp in enumerate(spec["inputs"]):
+            bufs[i] = np.ascontiguousarray(inputs[inp["name"]], dtype=np.float32).reshape(ch[inp["name"]], h, w)
+        bufs_all.append((w, h, bufs))
+    ngroups = plans[0].num_groups
+    for g in range(ngroups):
+        src = plans[0].source(g)
+        kname = src[src.index("void __launch_bounds__"):].split("(")[1].split(")")[1].strip()
+        lib = _compile(src, kname)
+        arr = (Args * len(images))()
+        start = (ctypes.c_int * (len(images) + 1))()
+        total = 0
+        resample = False
+        wpb = 1
+        for k, plan in enumerate(plans):
+            gi = GroupInfo()
+            wt._check(wt.lib.wt_plan_group_info(plan._h, g, ctypes.byref(gi)))
+            resample = bool(gi.resample)
+            wpb = gi.waves_per_group
+            w, h, bufs = bufs_all[k]
+
+            def buf(node_id, half):
+                if node_id not in bufs:
+                    nm = names[node_id]
+                    bw, bh = oracle.level_size(w, h, lv[nm])
+                    bufs[node_id] = np.full((ch[nm], bh, bw), np.nan, dtype=np.float16 if half else np.float32)
+                return bufs[node_id]
+
+            a = arr[k]
+            for i in range(gi.nloaded):
+                b = buf(gi.loaded[i], bool(gi.loaded_half[i]))
+                a.src[i] = b.ctypes.data
+                a.src_rs[i], a.src_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
+            for i in range(gi.nliveouts):
+                b = buf(gi.liveouts[i], bool(gi.liveout_half[i]))
+                a.dst[i] = b.ctypes.data
+                a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
+            a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
+            a.tiles_x, a.tiles_y = gi.tiles_x, gi.tiles_y
+            work = gi.tiles_x * gi.tiles_y * gi.channels if gi.resample else gi.nwaves
+            a.nwaves = gi.nwaves
+            start[k] = total
+            total += work
+        start[len(images)] = total
+        if resample:
+            lib.wt_emu_run_grid_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks)
+        else:
+            lib.wt_emu_run_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
+    return [{o: b[names.index(o)].astype(np.float32) for o in spec["outputs"]} for (_, _, b) in bufs_all]

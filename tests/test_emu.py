@@ -86,3 +86,23 @@ def test_pyramid_two_level_exact():
     for m in (np.ones((1, 21, 33), np.float32), np.zeros((1, 21, 33), np.float32)):
         got, _ = emulate(spec, {"A": a, "B": b, "M": m}, mode="analytic")
         assert_exact(got["R0"], oracle.evaluate(spec, {"A": a, "B": b, "M": m})["R0"], "pyramid")
+
+
+def test_batched_persistent_kernels_emulated():
+    """Persistent batch kernels over images of different sizes (grid-stride
+    loop with a deliberately small grid) equal the oracle per image."""
+    from emu_runner import emulate_batch
+    spec = P.unsharp_mask(channels=1)
+    sizes = [(60, 17), (131, 40), (97, 9)]
+    images = [{"img": synth.uniform_image(40 + i, 1, h, w)} for i, (w, h) in enumerate(sizes)]
+    outs = emulate_batch(spec, images, nblocks=3, mode="fixed",
+                         fixed="nodes=1,2,3,4 V=1 TX=2 SX=0 TY=8 PF=1")
+    for inp, got in zip(images, outs):
+        check_unsharp(got["mask"], inp["img"], 1e-5, spec)
+    spec = P.pyramid_blend(3)
+    sizes = [(45, 37), (30, 21)]
+    images = [{"A": synth.uniform_image(50 + i, 1, h, w), "B": synth.uniform_image(60 + i, 1, h, w),
+               "M": synth.ramp_mask(h, w)} for i, (w, h) in enumerate(sizes)]
+    outs = emulate_batch(spec, images, nblocks=2, mode="analytic", any_width=True)
+    for inp, got in zip(images, outs):
+        assert_normwise(got["R0"], oracle.evaluate(spec, inp)["R0"], 1e-5, "batched pyramid")
