@@ -189,6 +189,42 @@ wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out)
 wt_status wt_fusion_costs(const wt_pipeline* p, int width, int height, int fp16, int max_group,
                           double* dp_us, double* exhaustive_us);
 
+/* ---------------------------------------------------------------------- */
+/* Learned cost model: a fully connected ReLU network over the 40 model      */
+/* features of a (group, configuration), predicting log kernel time; trained */
+/* on the device (forward, backward, MSE and Adam kernels).  Host pointers;  */
+/* the library copies to and from the device.  Parameters are laid out layer */
+/* by layer: W_l (dims[l] x dims[l+1], row-major) then b_l.                  */
+/* ---------------------------------------------------------------------- */
+typedef struct wt_mlp wt_mlp;
+wt_status wt_mlp_create(const int* dims, int nlayers, uint64_t seed, wt_mlp** out);
+void wt_mlp_destroy(wt_mlp* m);
+size_t wt_mlp_num_params(const wt_mlp* m);
+wt_status wt_mlp_get_params(const wt_mlp* m, float* params, size_t n);
+wt_status wt_mlp_set_params(wt_mlp* m, const float* params, size_t n);
+/* Raw network output for `batch` rows of x (no normalisation). */
+wt_status wt_mlp_forward(wt_mlp* m, const float* x, int batch, float* y);
+/* MSE of the raw output against t and its gradient w.r.t. every parameter. */
+wt_status wt_mlp_forward_backward(wt_mlp* m, const float* x, const float* t, int batch,
+                                  float* loss, float* grads);
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) with given gradients. */
+wt_status wt_mlp_adam_step(wt_mlp* m, const float* grads, float lr);
+/* Trains on n samples (features z-scored and target standardised on this
+ * set, stored in the model); returns the last epoch's mean loss. */
+wt_status wt_mlp_train(wt_mlp* m, const float* x, const float* t, int n, int epochs, int batch,
+                       float lr, uint64_t seed, float* final_loss);
+/* Prediction in target units for n feature rows (stored normalisation). */
+wt_status wt_mlp_predict(wt_mlp* m, const float* x, int n, float* y);
+wt_status wt_mlp_save(const wt_mlp* m, const char* path);
+wt_status wt_mlp_load(const char* path, wt_mlp** out);
+/* Features of every configuration the search grid holds for `nodes` of a
+ * pipeline planned at width x height (row-major, 40 per configuration), with
+ * each configuration's schedule text (';'-separated) -- the learned model's
+ * inputs as the scheduler sees them. */
+wt_status wt_group_features(const wt_pipeline* p, const int* nodes, int nnodes, int width, int height,
+                            int fp16, float* features, int max_rows, int* rows, char* text,
+                            size_t text_len);
+
 /* Destroys the plan; its stream must have drained. */
 void wt_plan_destroy(wt_plan* plan);
 

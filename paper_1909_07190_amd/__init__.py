@@ -230,3 +230,122 @@ class Plan:
     @property
     def num_groups(self) -> int:
         return lib.wt_plan_num_groups(self._h)
+
+
+# ---------------------------------------------------------------------------
+# Learned cost model
+# ---------------------------------------------------------------------------
+_f_p = ctypes.POINTER(ctypes.c_float)
+_sig("wt_mlp_create", ctypes.c_int, _c_int_p, ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p))
+_sig("wt_mlp_destroy", None, ctypes.c_void_p)
+_sig("wt_mlp_num_params", ctypes.c_size_t, ctypes.c_void_p)
+_sig("wt_mlp_get_params", ctypes.c_int, ctypes.c_void_p, _f_p, ctypes.c_size_t)
+_sig("wt_mlp_set_params", ctypes.c_int, ctypes.c_void_p, _f_p, ctypes.c_size_t)
+_sig("wt_mlp_forward", ctypes.c_int, ctypes.c_void_p, _f_p, ctypes.c_int, _f_p)
+_sig("wt_mlp_forward_backward", ctypes.c_int, ctypes.c_void_p, _f_p, _f_p, ctypes.c_int, _f_p, _f_p)
+_sig("wt_mlp_adam_step", ctypes.c_int, ctypes.c_void_p, _f_p, ctypes.c_float)
+_sig("wt_mlp_train", ctypes.c_int, ctypes.c_void_p, _f_p, _f_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.c_float, ctypes.c_uint64, _f_p)
+_sig("wt_mlp_predict", ctypes.c_int, ctypes.c_void_p, _f_p, ctypes.c_int, _f_p)
+_sig("wt_mlp_save", ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p)
+_sig("wt_mlp_load", ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p))
+_sig("wt_group_features", ctypes.c_int, ctypes.c_void_p, _c_int_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.c_int, _f_p, ctypes.c_int, _c_int_p, ctypes.c_char_p, ctypes.c_size_t)
+
+NUM_FEATURES = 40
+
+
+def _fbuf(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(_f_p)
+
+
+class Mlp:
+    """The learned cost model (device training through the C ABI)."""
+
+    def __init__(self, dims=(NUM_FEATURES, 128, 128, 128, 1), seed=1, _handle=None):
+        if _handle is not None:
+            self._h = _handle
+        else:
+            d = (ctypes.c_int * len(dims))(*dims)
+            h = ctypes.c_void_p()
+            _check(lib.wt_mlp_create(d, len(dims), seed, ctypes.byref(h)))
+            self._h = h
+        self.dims = tuple(dims)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib.wt_mlp_destroy(self._h)
+            self._h = None
+
+    @property
+    def num_params(self):
+        return lib.wt_mlp_num_params(self._h)
+
+    def params(self):
+        import numpy as np
+        out = np.empty(self.num_params, np.float32)
+        _check(lib.wt_mlp_get_params(self._h, out.ctypes.data_as(_f_p), out.size))
+        return out
+
+    def set_params(self, p):
+        a, ptr = _fbuf(p)
+        _check(lib.wt_mlp_set_params(self._h, ptr, a.size))
+
+    def forward(self, x):
+        import numpy as np
+        a, ptr = _fbuf(x)
+        y = np.empty((a.shape[0], self.dims[-1]), np.float32)
+        _check(lib.wt_mlp_forward(self._h, ptr, a.shape[0], y.ctypes.data_as(_f_p)))
+        return y
+
+    def forward_backward(self, x, t):
+        import numpy as np
+        a, px = _fbuf(x)
+        b, pt = _fbuf(t)
+        g = np.empty(self.num_params, np.float32)
+        loss = ctypes.c_float()
+        _check(lib.wt_mlp_forward_backward(self._h, px, pt, a.shape[0], ctypes.byref(loss),
+                                           g.ctypes.data_as(_f_p)))
+        return loss.value, g
+
+    def adam_step(self, grads, lr):
+        a, p = _fbuf(grads)
+        _check(lib.wt_mlp_adam_step(self._h, p, lr))
+
+    def train(self, x, t, epochs=200, batch=256, lr=1e-3, seed=1):
+        a, px = _fbuf(x)
+        b, pt = _fbuf(t)
+        loss = ctypes.c_float()
+        _check(lib.wt_mlp_train(self._h, px, pt, a.shape[0], epochs, batch, lr, seed, ctypes.byref(loss)))
+        return loss.value
+
+    def predict(self, x):
+        import numpy as np
+        a, px = _fbuf(x)
+        y = np.empty(a.shape[0], np.float32)
+        _check(lib.wt_mlp_predict(self._h, px, a.shape[0], y.ctypes.data_as(_f_p)))
+        return y
+
+    def save(self, path):
+        _check(lib.wt_mlp_save(self._h, path.encode()))
+
+    @classmethod
+    def load(cls, path):
+        h = ctypes.c_void_p()
+        _check(lib.wt_mlp_load(path.encode(), ctypes.byref(h)))
+        m = cls(_handle=h)
+        return m
+
+
+def group_features(pipe, nodes, width, height, fp16=False, max_rows=4096):
+    """(features [rows x 40], schedule texts) of every configuration of a group."""
+    import numpy as np
+    feats = np.zeros((max_rows, NUM_FEATURES), np.float32)
+    n = ctypes.c_int()
+    buf = ctypes.create_string_buffer(max_rows * 128)
+    arr = (ctypes.c_int * len(nodes))(*nodes)
+    _check(lib.wt_group_features(pipe._h, arr, len(nodes), width, height, int(fp16),
+                                 feats.ctypes.data_as(_f_p), max_rows, ctypes.byref(n), buf, len(buf)))
+    return feats[:n.value], buf.value.decode().split(";") if n.value else []

@@ -5,7 +5,9 @@
 #include <cstring>
 #include <string>
 
+#include "wt_cost.h"
 #include "wt_internal.h"
+#include "wt_mlp.h"
 #include "wt_runtime.h"
 
 struct wt_pipeline {
@@ -13,6 +15,9 @@ struct wt_pipeline {
 };
 struct wt_plan {
     std::unique_ptr<wt::Plan> impl;
+};
+struct wt_mlp {
+    std::unique_ptr<wt::Mlp> impl;
 };
 
 namespace {
@@ -260,6 +265,103 @@ wt_status wt_fusion_costs(const wt_pipeline* p, int width, int height, int fp16,
         r.fp16 = fp16 != 0;
         r.max_group = max_group;
         wt::fusion_costs(p->p, wt::Machine{}, r, dp_us, exhaustive_us);
+    });
+}
+
+wt_status wt_mlp_create(const int* dims, int nlayers, uint64_t seed, wt_mlp** out) {
+    return guard([&] {
+        if (!dims || !out || nlayers < 2 || nlayers > 16) wt::fail(WT_E_INVALID, "bad mlp arguments");
+        *out = new wt_mlp{std::make_unique<wt::Mlp>(std::vector<int>(dims, dims + nlayers), seed)};
+    });
+}
+void wt_mlp_destroy(wt_mlp* m) { delete m; }
+size_t wt_mlp_num_params(const wt_mlp* m) { return m ? m->impl->nparams : 0; }
+wt_status wt_mlp_get_params(const wt_mlp* m, float* params, size_t n) {
+    return guard([&] {
+        if (!m || !params || n != m->impl->nparams) wt::fail(WT_E_INVALID, "bad parameter buffer");
+        std::memcpy(params, m->impl->host.data(), n * sizeof(float));
+    });
+}
+wt_status wt_mlp_set_params(wt_mlp* m, const float* params, size_t n) {
+    return guard([&] {
+        if (!m || !params || n != m->impl->nparams) wt::fail(WT_E_INVALID, "bad parameter buffer");
+        std::memcpy(m->impl->host.data(), params, n * sizeof(float));
+        m->impl->upload_params();
+    });
+}
+wt_status wt_mlp_forward(wt_mlp* m, const float* x, int batch, float* y) {
+    return guard([&] {
+        if (!m || !x || !y || batch < 1) wt::fail(WT_E_INVALID, "bad forward arguments");
+        m->impl->forward(x, batch, y);
+    });
+}
+wt_status wt_mlp_forward_backward(wt_mlp* m, const float* x, const float* t, int batch, float* loss, float* grads) {
+    return guard([&] {
+        if (!m || !x || !t || !loss || batch < 1) wt::fail(WT_E_INVALID, "bad backward arguments");
+        *loss = m->impl->forward_backward(x, t, batch, grads);
+    });
+}
+wt_status wt_mlp_adam_step(wt_mlp* m, const float* grads, float lr) {
+    return guard([&] {
+        if (!m || !grads) wt::fail(WT_E_INVALID, "bad adam arguments");
+        m->impl->adam_from_host(grads, lr);
+    });
+}
+wt_status wt_mlp_train(wt_mlp* m, const float* x, const float* t, int n, int epochs, int batch, float lr,
+                       uint64_t seed, float* final_loss) {
+    return guard([&] {
+        if (!m || !x || !t || n < 2 || epochs < 1 || batch < 1) wt::fail(WT_E_INVALID, "bad training arguments");
+        float l = m->impl->train(x, t, n, epochs, batch, lr, seed);
+        if (final_loss) *final_loss = l;
+    });
+}
+wt_status wt_mlp_predict(wt_mlp* m, const float* x, int n, float* y) {
+    return guard([&] {
+        if (!m || !x || !y || n < 1) wt::fail(WT_E_INVALID, "bad predict arguments");
+        m->impl->predict(x, n, y);
+    });
+}
+wt_status wt_mlp_save(const wt_mlp* m, const char* path) {
+    return guard([&] {
+        if (!m || !path) wt::fail(WT_E_INVALID, "null argument");
+        m->impl->save(path);
+    });
+}
+wt_status wt_mlp_load(const char* path, wt_mlp** out) {
+    return guard([&] {
+        if (!path || !out) wt::fail(WT_E_INVALID, "null argument");
+        *out = new wt_mlp{wt::Mlp::load(path)};
+    });
+}
+
+wt_status wt_group_features(const wt_pipeline* p, const int* nodes, int nnodes, int width, int height, int fp16,
+                            float* features, int max_rows, int* rows, char* text, size_t text_len) {
+    return guard([&] {
+        if (!p || !nodes || nnodes < 1 || !rows) wt::fail(WT_E_INVALID, "null argument");
+        wt::SchedRequest r;
+        r.W = width;
+        r.H = height;
+        r.fp16 = fp16 != 0;
+        std::vector<int> ns(nodes, nodes + nnodes);
+        std::sort(ns.begin(), ns.end());
+        auto cfgs = wt::score_configs(p->p, wt::Machine{}, r, ns);
+        std::string all;
+        int n = 0;
+        for (const auto& c : cfgs) {
+            if (n >= max_rows) break;
+            wt::GroupGeom geo = wt::group_geometry(p->p, c.g);
+            std::vector<double> f = wt::group_features(p->p, c.g, geo, c.cost, width, height, c.tx_size);
+            if (features)
+                for (int k = 0; k < wt::kNumFeatures; ++k) features[(size_t)n * wt::kNumFeatures + k] = (float)f[k];
+            all += (n ? ";" : "") + wt::describe_group(c.g);
+            ++n;
+        }
+        *rows = n;
+        if (text && text_len) {
+            size_t k = std::min(text_len - 1, all.size());
+            std::memcpy(text, all.data(), k);
+            text[k] = '\0';
+        }
     });
 }
 

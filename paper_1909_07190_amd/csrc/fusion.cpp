@@ -20,6 +20,7 @@
 #include <unordered_map>
 
 #include "wt_cost.h"
+#include "wt_mlp.h"
 
 namespace wt {
 
@@ -83,12 +84,34 @@ struct Search {
         }
         double best_score = INFINITY, best_pred = INFINITY;
         GroupSched best = base;
-        for (const ScoredConfig& sc : score_configs(p, m, r, nodes))
-            if (sc.cost.alg2.score < best_score) {
-                best_score = sc.cost.alg2.score;
-                best_pred = sc.cost.pred_us;
-                best = sc.g;
+        std::vector<ScoredConfig> cfgs = score_configs(p, m, r, nodes);
+        if (r.model && !cfgs.empty()) {
+            // learned model: predicted time of every configuration; the
+            // analytical prediction stands in outside the training range
+            std::vector<float> feats;
+            feats.reserve(cfgs.size() * kNumFeatures);
+            for (const auto& sc : cfgs) {
+                std::vector<double> f = group_features(p, sc.g, *sc.geo, sc.cost, r.W, r.H, sc.tx_size);
+                for (double v : f) feats.push_back((float)v);
             }
+            std::vector<float> pred(cfgs.size());
+            r.model->predict(feats.data(), (int)cfgs.size(), pred.data());
+            for (size_t i = 0; i < cfgs.size(); ++i) {
+                bool inside = r.model->max_abs_z(&feats[i * kNumFeatures]) <= 4.0;
+                double t = inside ? std::exp((double)pred[i]) : cfgs[i].cost.pred_us;
+                if (t < best_pred) {
+                    best_pred = t;
+                    best = cfgs[i].g;
+                }
+            }
+        } else {
+            for (const ScoredConfig& sc : cfgs)
+                if (sc.cost.alg2.score < best_score) {
+                    best_score = sc.cost.alg2.score;
+                    best_pred = sc.cost.pred_us;
+                    best = sc.g;
+                }
+        }
         auto res = std::make_pair(best_pred, best);
         gcache[g] = res;
         return res;
@@ -204,6 +227,7 @@ std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, con
                     for (auto& ng : geo.nodes)
                         ng.mem_half = r.fp16 && p.nodes[ng.id].kind != Kind::Input && !p.is_output(ng.id) &&
                                       (!ng.member || ng.liveout);
+                    auto shared = std::make_shared<const GroupGeom>(geo);
                     for (int TY : {8, 16, 32, 64})
                         for (int WPB : {1, 2, 4}) {
                             s.TY = TY;
@@ -213,7 +237,7 @@ std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, con
                             for (int tx : {m.tx_sizes[0], m.tx_sizes[1]}) {
                                 GroupCost c = group_cost(p, s, gg, m, r.W, r.H, prof, tx, w);
                                 if (!c.alg2.feasible || c.nwaves <= 0) continue;
-                                out.push_back({s, c, tx});
+                                out.push_back({s, c, tx, shared});
                             }
                         }
                 }

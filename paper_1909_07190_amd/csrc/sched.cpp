@@ -3,6 +3,7 @@
 #include <set>
 
 #include "wt_internal.h"
+#include "wt_mlp.h"
 
 namespace wt {
 
@@ -56,8 +57,16 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
             Schedule s = parse_schedule(r.fixed, p);
             return s;
         }
+        case WT_SCHED_MLP: {
+            if (r.model_path.empty()) fail(WT_E_INVALID, "WT_SCHED_MLP needs model_path");
+            std::unique_ptr<Mlp> model = Mlp::load(r.model_path);
+            SchedRequest rr = r;
+            rr.model = model.get();
+            Schedule s = schedule_analytic(p, m, rr);
+            for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
+            return s;
+        }
         case WT_SCHED_ANALYTIC:
-        case WT_SCHED_MLP:
         case WT_SCHED_AUTOTUNE: {
             Schedule s = schedule_analytic(p, m, r);
             for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));

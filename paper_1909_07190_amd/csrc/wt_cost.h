@@ -1,6 +1,7 @@
 // Analytical cost model (Algorithm 2) and the gfx950 schedule adapter.
 #pragma once
 #include <map>
+#include <memory>
 
 #include "wt_internal.h"
 
@@ -59,6 +60,7 @@ struct ScoredConfig {
     GroupSched g;
     GroupCost cost;
     int tx_size = 128;
+    std::shared_ptr<const GroupGeom> geo;  // geometry of (V, TX, SX, PF)
 };
 // Every feasible configuration of the group `nodes` over the search grid.
 std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,

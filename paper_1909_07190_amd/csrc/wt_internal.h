@@ -12,6 +12,8 @@
 
 namespace wt {
 
+struct Mlp;
+
 // Error carried across internal layers; converted to wt_status at the C ABI.
 struct Error : std::runtime_error {
     wt_status status;
@@ -177,6 +179,7 @@ struct SchedRequest {
     int max_group = 12;               // bound on stages per fused group
     bool any_width = false;           // caller images of any width / stride
     const double* weights = nullptr;  // Algorithm 2 weights (default: refitted table)
+    Mlp* model = nullptr;             // learned cost model (WT_SCHED_MLP)
 };
 Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r);
 Schedule schedule_unfused(const Pipeline& p, bool fp16);
