@@ -176,10 +176,46 @@ def bench_other(args, torch, wt, synth, P):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
             res[mode] = {"Mpix/s": px / (ms * 1e-3) / 1e6, "ms": ms, "groups": plan.num_groups,
-                         "GB/s_algorithmic": 16 * px / (ms * 1e-3) / 1e9}
+                         "GB/s_algorithmic": 16 * px / (ms * 1e-3) / 1e9,
+                         "schedule": plan.describe().strip()}
             log(f"pyramid batch {mode}: {ms:.2f} ms, {res[mode]['Mpix/s']:.0f} Mpix/s, {plan.num_groups} launches")
+            # the same schedule, one plan per image size, images run one by one
+            fixed = plan.describe()
+            plans = [wt.from_spec(spec).plan(w, h, mode="fixed", fixed=fixed, any_width=True) for (w, h) in sizes]
+            for pl, i, o in zip(plans, ins, outs):
+                pl.run(i, o)
+            torch.cuda.synchronize()
+            e0.record(s)
+            for _ in range(reps):
+                for pl, i, o in zip(plans, ins, outs):
+                    pl.run(i, o)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms1 = e0.elapsed_time(e1) / reps
+            res[mode]["per_image_ms"] = ms1
+            log(f"pyramid per-image {mode}: {ms1:.2f} ms, {px / (ms1 * 1e-3) / 1e6:.0f} Mpix/s")
+            del plans
         res["pixels"] = px
     print(json.dumps(res), flush=True)
+
+
+def profile_traffic(kname):
+    """HBM bytes per launch of kernel `kname` from the committed rocprofv3
+    counter summaries (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each
+    scaled by what the counter reads for a copy kernel of known size), or
+    None when no summary covers this exact kernel (its name carries a hash of
+    its source, so a changed kernel has no figure until it is profiled)."""
+    import glob
+    import re
+    pat = re.compile(r"^traffic (\S+) fetch_kib=([\d.]+) write_kib=([\d.]+) "
+                     r"fetch_scale=([\d.]+) write_scale=([\d.]+)\s*$")
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            m = pat.match(line.strip())
+            if m and m.group(1) == kname:
+                f, w, fs, ws = (float(m.group(i)) for i in range(2, 6))
+                return (f * fs + w * ws) * 1024.0
+    return None
 
 
 def main():
@@ -243,6 +279,9 @@ def main():
     if cpu:
         log(f"oracle: {cpu['value']:.2f} Mpix/s on {cpu['cores']} core(s)")
 
+    import re
+    kname = re.search(r"wt_g0_fused_[0-9a-f]+", fused.source(0)).group(0)
+    traffic = profile_traffic(kname)
     out = {
         "metric": METRIC, "value": mpix, "unit": "Mpixels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -250,9 +289,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "unsharp mask 3x2048x2048 FP32, uniform [0,1) seed 2; "
                                "blur x, blur y, sharpen, select fused in one wave-tiled kernel",
-                   "schedule": fused.describe().strip(), "buffer_sets": args.sets},
+                   "schedule": fused.describe().strip(), "kernel": kname, "buffer_sets": args.sets},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
     }
     out["copy_reference"] = copy

@@ -112,8 +112,10 @@ typedef enum {
 
 enum {
     WT_PLAN_NO_DEVICE = 1, /* generate and compile code only; run() refused   */
-    WT_PLAN_ANY_WIDTH = 2  /* caller images may have any width and stride:
+    WT_PLAN_ANY_WIDTH = 2, /* caller images may have any width and stride:
                               groups touching them use one element per lane */
+    WT_PLAN_NO_COMPILE = 4 /* schedule and generate code only (implies
+                              WT_PLAN_NO_DEVICE); wt_plan_source still works */
 };
 
 typedef struct {
@@ -224,6 +226,20 @@ wt_status wt_mlp_load(const char* path, wt_mlp** out);
 wt_status wt_group_features(const wt_pipeline* p, const int* nodes, int nnodes, int width, int height,
                             int fp16, float* features, int max_rows, int* rows, char* text,
                             size_t text_len);
+
+/* Measures candidate groups of a pipeline on the current device, for the
+ * learned model's training data (the paper times whole schedules; this times
+ * single groups).  groups[i] is one group's schedule text ("nodes=... V=...
+ * TX=... SX=... TY=... WPB=... PF=...", as in wt_plan_describe), timed on
+ * zero-filled scratch images of every node at width x height: 3 samples of
+ * `reps` back-to-back launches, minimum of the sample means, in
+ * microseconds, into times_us[i] (host array of n doubles; +inf when the
+ * group cannot be built for this pipeline).  When $WT_MEASURE_DB names a
+ * file, one JSON line per fused group is appended (tagged `tag`) with its
+ * 40 model features.  Synchronous; allocates and frees its scratch. */
+wt_status wt_measure_groups(const wt_pipeline* p, int width, int height, int fp16, int n,
+                            const char* const* groups, int reps, const char* tag,
+                            double* times_us);
 
 /* Destroys the plan; its stream must have drained. */
 void wt_plan_destroy(wt_plan* plan);

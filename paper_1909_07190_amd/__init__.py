@@ -9,14 +9,22 @@ and streams.
 from __future__ import annotations
 
 import ctypes
+import sys
 import os
 
 __all__ = ["Pipeline", "Plan", "WtError", "lib", "SCHED", "from_spec", "LIB_PATH"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwavetile.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1909_07190_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: run `python paper_1909_07190_amd/build.py` "
                       "(or __graft_entry__.build()) first")
+# One HIP runtime per process: torch ships its own libamdhip64 / libhiprtc
+# under the same sonames as the system ROCm's.  Loading torch first makes the
+# library bind to those, so its kernels, modules and streams live in the same
+# runtime as the tensors it is handed (loaded the other way round, torch would
+# then find no device).
+import torch  # noqa: E402,F401
+
 lib = ctypes.CDLL(LIB_PATH)
 
 SCHED = {"unfused": 0, "analytic": 1, "mlp": 2, "autotune": 3, "fixed": 4}
@@ -24,6 +32,7 @@ DOWN2, UP2 = 0, 1
 F32, F16 = 0, 1
 PLAN_NO_DEVICE = 1
 PLAN_ANY_WIDTH = 2
+PLAN_NO_COMPILE = 4
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 
@@ -93,9 +102,11 @@ class Pipeline:
         self.names: dict[str, int] = {}
         self.channels: dict[int, int] = {}
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            lib.wt_pipeline_destroy(self._h)
+    def __del__(self, _finalizing=sys.is_finalizing, _destroy=lib.wt_pipeline_destroy):
+        # at interpreter exit the module's globals may already be gone and
+        # the process is about to release everything anyway
+        if getattr(self, "_h", None) and not _finalizing():
+            _destroy(self._h)
             self._h = None
 
     def input(self, channels: int) -> int:
@@ -129,9 +140,9 @@ class Pipeline:
 
     def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
              no_device=False, model_path=None, cache_dir=None, autotune_topk=0,
-             any_width=False) -> "Plan":
+             any_width=False, no_compile=False) -> "Plan":
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
-                    autotune_topk, any_width)
+                    autotune_topk, any_width, no_compile)
 
 
 def from_spec(spec: dict) -> Pipeline:
@@ -174,9 +185,10 @@ class Plan:
     """A compiled schedule for one image size."""
 
     def __init__(self, pipe: Pipeline, width, height, mode, fp16, fixed, no_device,
-                 model_path, cache_dir, autotune_topk, any_width=False):
+                 model_path, cache_dir, autotune_topk, any_width=False, no_compile=False):
         self.pipe = pipe  # keeps the pipeline alive
-        flags = (PLAN_NO_DEVICE if no_device else 0) | (PLAN_ANY_WIDTH if any_width else 0)
+        flags = ((PLAN_NO_DEVICE if no_device else 0) | (PLAN_ANY_WIDTH if any_width else 0)
+                 | (PLAN_NO_COMPILE if no_compile else 0))
         opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), flags,
                            autotune_topk, fixed.encode() if fixed else None,
                            model_path.encode() if model_path else None,
@@ -186,9 +198,11 @@ class Plan:
         self._h = h
         self.width, self.height = width, height
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            lib.wt_plan_destroy(self._h)
+    def __del__(self, _finalizing=sys.is_finalizing, _destroy=lib.wt_plan_destroy):
+        # at interpreter exit the module's globals may already be gone and
+        # the process is about to release everything anyway
+        if getattr(self, "_h", None) and not _finalizing():
+            _destroy(self._h)
             self._h = None
 
     def run(self, inputs, outputs, stream=None):
@@ -274,9 +288,11 @@ class Mlp:
             self._h = h
         self.dims = tuple(dims)
 
-    def __del__(self):
-        if getattr(self, "_h", None):
-            lib.wt_mlp_destroy(self._h)
+    def __del__(self, _finalizing=sys.is_finalizing, _destroy=lib.wt_mlp_destroy):
+        # at interpreter exit the module's globals may already be gone and
+        # the process is about to release everything anyway
+        if getattr(self, "_h", None) and not _finalizing():
+            _destroy(self._h)
             self._h = None
 
     @property
@@ -349,3 +365,18 @@ def group_features(pipe, nodes, width, height, fp16=False, max_rows=4096):
     _check(lib.wt_group_features(pipe._h, arr, len(nodes), width, height, int(fp16),
                                  feats.ctypes.data_as(_f_p), max_rows, ctypes.byref(n), buf, len(buf)))
     return feats[:n.value], buf.value.decode().split(";") if n.value else []
+
+
+_sig("wt_measure_groups", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.c_int, ctypes.c_char_p,
+     ctypes.POINTER(ctypes.c_double))
+
+
+def measure_groups(pipe, groups, width, height, fp16=False, reps=20, tag=""):
+    """Device time in microseconds of each candidate group (schedule text per
+    group), on scratch images; appends to $WT_MEASURE_DB when set."""
+    n = len(groups)
+    arr = (ctypes.c_char_p * max(n, 1))(*[g.encode() for g in groups])
+    out = (ctypes.c_double * max(n, 1))()
+    _check(lib.wt_measure_groups(pipe._h, width, height, int(fp16), n, arr, reps, tag.encode(), out))
+    return [out[i] for i in range(n)]

@@ -50,6 +50,44 @@ std::string json_escape(const std::string& s) {
     return o;
 }
 
+// Analytical quantities of one configuration as the scheduler sees them
+// (the transaction size with the better Algorithm 2 score).
+ScoredConfig score_one(const Pipeline& p, const Machine& m, const GroupSched& g, const GroupGeom& geo, int W,
+                       int H) {
+    std::map<int, StageProfile> prof;
+    for (int n : g.nodes) prof[n] = estimate_stage(p, n, m);
+    ScoredConfig best;
+    best.g = g;
+    bool have = false;
+    for (int tx : {m.tx_sizes[0], m.tx_sizes[1]}) {
+        GroupCost c = group_cost(p, g, geo, m, W, H, prof, tx, kGfx950Weights);
+        if (!have || c.alg2.score < best.cost.alg2.score) {
+            best.cost = c;
+            best.tx_size = tx;
+            have = true;
+        }
+    }
+    return best;
+}
+
+// One measurement database line: the configuration, its measured and
+// predicted time, Algorithm 2's terms and the 40 model features.
+void write_db_line(std::ofstream& db, const std::string& tag, const Plan& plan, const GroupRt& gr, double us) {
+    ScoredConfig sc = score_one(plan.p, plan.machine, gr.g, gr.geo, plan.W, plan.H);
+    std::vector<double> f = group_features(plan.p, gr.g, gr.geo, sc.cost, plan.W, plan.H, sc.tx_size);
+    std::ostringstream os;
+    os.precision(9);
+    os << "{\"pipeline\": \"" << json_escape(tag) << "\", \"W\": " << plan.W << ", \"H\": " << plan.H
+       << ", \"group\": \"" << json_escape(describe_group(gr.g)) << "\", \"measured_us\": " << us
+       << ", \"pred_us\": " << sc.cost.pred_us << ", \"score\": " << sc.cost.alg2.score << ", \"terms\": [";
+    for (int i = 0; i < 7; ++i) os << (i ? ", " : "") << sc.cost.alg2.terms[i];
+    os << "], \"features\": [";
+    for (size_t i = 0; i < f.size(); ++i) os << (i ? ", " : "") << f[i];
+    os << "]}\n";
+    db << os.str();
+    db.flush();
+}
+
 }  // namespace
 
 // Measured time (microseconds) of one launch of `gr`: 3 samples of `reps`
@@ -108,6 +146,9 @@ void autotune_plan(Plan& plan, int topk) {
     uint64_t phash = 1469598103934665603ull;
     for (auto& g : plan.groups)
         for (unsigned char c : g.kname) phash = (phash ^ c) * 1099511628211ull;
+    char hbuf[32];
+    std::snprintf(hbuf, sizeof hbuf, "%016llx", (unsigned long long)phash);
+    const std::string tag = hbuf;
 
     for (size_t gi = 0; gi < plan.sched.groups.size(); ++gi) {
         if (plan.groups[gi].resample) continue;
@@ -165,40 +206,72 @@ void autotune_plan(Plan& plan, int topk) {
                 best_t = us;
                 best = t.g;
             }
-            if (db.is_open()) {
-                // model quantities of the measured configuration
-                GroupCost c;
-                int txs = 128;
-                for (const auto& s : all)
-                    if (describe_group(s.g) == describe_group(t.g)) {
-                        c = s.cost;
-                        txs = s.tx_size;
-                        break;
-                    }
-                std::vector<double> f = group_features(p, t.g, t.geo, c, plan.W, plan.H, txs);
-                std::ostringstream os;
-                os.precision(9);
-                char h[32];
-                std::snprintf(h, sizeof h, "%016llx", (unsigned long long)phash);
-                os << "{\"pipeline\": \"" << h << "\", \"W\": " << plan.W << ", \"H\": " << plan.H
-                   << ", \"group\": \"" << json_escape(describe_group(t.g)) << "\", \"measured_us\": " << us
-                   << ", \"pred_us\": " << c.pred_us << ", \"score\": " << c.alg2.score << ", \"terms\": [";
-                for (int i = 0; i < 7; ++i) os << (i ? ", " : "") << c.alg2.terms[i];
-                os << "], \"features\": [";
-                for (size_t i = 0; i < f.size(); ++i) os << (i ? ", " : "") << f[i];
-                os << "]}\n";
-                db << os.str();
-            }
+            if (db.is_open()) write_db_line(db, tag, plan, t, us);
         }
-        for (auto& t : trials)
-            if (t.mod) {
-                hipModuleUnload(t.mod);
-                t.mod = nullptr;
-            }
+        for (auto& t : trials) unload_group(t);
         plan.sched.groups[gi] = best;
     }
     hipStreamDestroy(st);
     build_groups(plan);
+}
+
+// Times arbitrary candidate groups of a pipeline on scratch images (every
+// node's image allocated at its level's size, zero-filled), for building the
+// measurement database.  Groups that cannot be built get +inf.
+void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vector<std::string>& descs, int reps,
+                    const std::string& tag, double* out_us) {
+    Plan plan;
+    plan.p = p;
+    plan.W = W;
+    plan.H = H;
+    plan.fp16 = fp16;
+    const char* env_cache = std::getenv("WT_CACHE_DIR");
+    plan.cache_dir = env_cache ? env_cache : "";
+    hip_check(hipGetDevice(&plan.device), "hipGetDevice");
+    plan.machine = machine_from_device(plan.device);
+    std::vector<GroupRt> trials(descs.size());
+    std::vector<GroupRt*> ok;
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < descs.size(); ++i) {
+        out_us[i] = INFINITY;
+        try {
+            Schedule sc = parse_schedule(descs[i], p, true);
+            if (sc.groups.size() != 1) fail(WT_E_INVALID, "one group per entry");
+            trials[i].g = sc.groups[0];
+            trials[i].g.fp16 = fp16;
+            prepare_group(plan, trials[i], 0);
+        } catch (const Error&) {
+            continue;
+        }
+        ok.push_back(&trials[i]);
+        idx.push_back(i);
+    }
+    compile_groups(plan, ok);
+    DeviceScratch scr;
+    std::map<int, ImgRef> mem;
+    for (const Node& n : p.nodes) {
+        auto d = level_dims(W, H, n.level);
+        int64_t rs = (d.first + 63) / 64 * 64;
+        mem[n.id] = {scr.alloc((size_t)rs * d.second * n.channels * 4), rs, rs * d.second};
+    }
+    hipStream_t st;
+    hip_check(hipStreamCreate(&st), "hipStreamCreate");
+    const char* dbp = std::getenv("WT_MEASURE_DB");
+    std::ofstream db;
+    if (dbp && *dbp) db.open(dbp, std::ios::app);
+    try {
+        for (size_t k = 0; k < ok.size(); ++k) {
+            double us = time_group_us(plan, *ok[k], mem, st, reps);
+            out_us[idx[k]] = us;
+            if (db.is_open() && !ok[k]->resample) write_db_line(db, tag, plan, *ok[k], us);
+        }
+    } catch (...) {
+        hipStreamDestroy(st);
+        for (auto* t : ok) unload_group(*t);
+        throw;
+    }
+    hipStreamDestroy(st);
+    for (auto* t : ok) unload_group(*t);
 }
 
 }  // namespace wt

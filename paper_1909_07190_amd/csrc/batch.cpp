@@ -23,6 +23,24 @@ BatchState::~BatchState() {
     if (dargs) hipFree(dargs);
 }
 
+// Workgroups of `fn` resident on one CU: the runtime's occupancy answer, or
+// the count from the kernel's VGPR and LDS use (waves per SIMD =
+// min(8, 512 / VGPRs rounded up to the allocation granule of 8), 4 SIMDs per
+// CU), whichever is larger.  Launching more than fit only queues workgroups.
+int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads) {
+    int api = 0;
+    if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&api, fn, threads, 0) != hipSuccess) api = 0;
+    int regs = 0, lds = 0;
+    if (hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, fn) != hipSuccess) regs = 0;
+    if (hipFuncGetAttribute(&lds, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, fn) != hipSuccess) lds = 0;
+    int alloc = std::max(8, (regs + 7) / 8 * 8);
+    int waves_simd = std::min(8, 512 / alloc);
+    int waves_wg = (threads + 63) / 64;
+    int own = std::max(1, 4 * waves_simd / waves_wg);
+    if (lds > 0) own = std::max(1, std::min(own, plan.machine.lds_per_cu / lds));
+    return std::max(api, own);
+}
+
 namespace {
 
 void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, int& ty, int& work) {
@@ -89,6 +107,12 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
 
     if (!plan.batch || plan.batch->sizes != sizes) {
         plan.batch.reset();
+        {  // the batched kernels, compiled on first use
+            std::vector<GroupRt*> need;
+            for (auto& gr : plan.groups)
+                if (!gr.fn_batch) need.push_back(&gr);
+            if (!need.empty()) compile_groups(plan, need, true);
+        }
         auto st = std::make_unique<BatchState>();
         st->sizes = sizes;
         // arena for every image's intermediates
@@ -118,6 +142,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
         // per-group work and launch grids
         st->total.resize(G);
         st->grid.resize(G);
+        st->per_cu.resize(G);
         st->tiles.assign((size_t)G * nimg, {0, 0, 0});
         for (int g = 0; g < G; ++g) {
             int tot = 0;
@@ -130,11 +155,9 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
             }
             st->total[g] = tot;
             const GroupRt& gr = plan.groups[g];
-            int per_cu = 1;
             int threads = gr.resample ? 256 : 64 * gr.g.WPB;
-            if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gr.fn_batch, threads, 0) != hipSuccess ||
-                per_cu < 1)
-                per_cu = 1;
+            int per_cu = resident_blocks_per_cu(plan, gr.fn_batch, threads);
+            st->per_cu[g] = per_cu;
             int units = gr.resample ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
             st->grid[g] = std::max(1, std::min(units, per_cu * plan.machine.ncu));
         }

@@ -268,6 +268,22 @@ wt_status wt_fusion_costs(const wt_pipeline* p, int width, int height, int fp16,
     });
 }
 
+wt_status wt_measure_groups(const wt_pipeline* p, int width, int height, int fp16, int n,
+                            const char* const* groups, int reps, const char* tag, double* times_us) {
+    return guard([&] {
+        if (!p || (n > 0 && (!groups || !times_us))) wt::fail(WT_E_INVALID, "null argument");
+        if (n < 0 || reps < 1 || reps > 100000) wt::fail(WT_E_INVALID, "bad count");
+        if (width <= 0 || height <= 0 || width > (1 << 16) || height > (1 << 16))
+            wt::fail(WT_E_SHAPE, "bad measurement size");
+        std::vector<std::string> d;
+        for (int i = 0; i < n; ++i) {
+            if (!groups[i]) wt::fail(WT_E_INVALID, "null group text");
+            d.emplace_back(groups[i]);
+        }
+        wt::measure_groups(p->p, width, height, fp16 != 0, d, reps, tag ? tag : "", times_us);
+    });
+}
+
 wt_status wt_mlp_create(const int* dims, int nlayers, uint64_t seed, wt_mlp** out) {
     return guard([&] {
         if (!dims || !out || nlayers < 2 || nlayers > 16) wt::fail(WT_E_INVALID, "bad mlp arguments");

@@ -578,7 +578,9 @@ struct Gen {
         line("int lo = 0, hi = nimg;");
         line("while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (start[mid] <= t) lo = mid; else hi = mid; }");
         line("const int img = __builtin_amdgcn_readfirstlane(lo);");
-        line("const WtArgs& A = AB[img];");
+        // a private copy: the compiler keeps the fields it uses in registers
+        // instead of reloading them after every store
+        line("const WtArgs A = AB[img];");
         line("const int wid = t - start[img];");
         line("{");
         tile();
@@ -592,8 +594,8 @@ struct Gen {
 
 }  // namespace
 
-std::string generate_group_source(const Pipeline& p, const GroupSched& g, const GroupGeom& geo,
-                                  const std::string& kname) {
+GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const GroupGeom& geo,
+                                   const std::string& kname) {
     if ((int)geo.loaded.size() > 16 || (int)geo.liveouts.size() > 16)
         fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
     Gen gen(p, g, geo);
@@ -602,7 +604,7 @@ std::string generate_group_source(const Pipeline& p, const GroupSched& g, const 
     gb.header();
     gb.o.str("");
     std::string batch = gb.batch_kernel(kname);
-    return device_prelude() + "\n" + single + "\n" + batch;
+    return GroupSources{device_prelude(), "", single, batch};
 }
 
 // 2x resampling kernels: one thread per output pixel, clamped reads.  Not
@@ -610,12 +612,11 @@ std::string generate_group_source(const Pipeline& p, const GroupSched& g, const 
 // single-image kernel runs a (tiles_x, tiles_y, channels) grid of 256-thread
 // blocks (64 x 4 pixels); the batched kernel loops its blocks over the
 // blocks of all images.
-std::string generate_resample_source(const Pipeline& p, const GroupSched& g, const std::string& kname,
-                                     bool src_half, bool dst_half) {
+GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g, const std::string& kname,
+                                      bool src_half, bool dst_half) {
     const std::string st = src_half ? "_Float16" : "float", dt = dst_half ? "_Float16" : "float";
     const Node& n = p.nodes[g.nodes[0]];
     std::ostringstream o;
-    o << device_prelude() << "\n";
     o << "static __device__ __forceinline__ void " << kname << "_body(const WtArgs& A, int bxi, int byi, int c) {\n";
     o << "    const int x = bxi * 64 + (threadIdx.x & 63);\n";
     o << "    const int y = byi * 4 + (threadIdx.x >> 6);\n";
@@ -646,21 +647,25 @@ std::string generate_resample_source(const Pipeline& p, const GroupSched& g, con
         o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")acc;\n";
     }
     o << "}\n";
+    const std::string body = o.str();
+    o.str("");
     o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname << "(const WtArgs A) {\n";
     o << "    " << kname << "_body(A, blockIdx.x, blockIdx.y, blockIdx.z);\n";
     o << "}\n";
+    const std::string single = o.str();
+    o.str("");
     o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname
       << "_batch(const WtArgs* __restrict__ AB, const int* __restrict__ start, const int nimg, const int total) {\n";
     o << "    for (int t = blockIdx.x; t < total; t += gridDim.x) {\n";
     o << "        int lo = 0, hi = nimg;\n";
     o << "        while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (start[mid] <= t) lo = mid; else hi = mid; }\n";
-    o << "        const WtArgs& A = AB[lo];\n";
+    o << "        const WtArgs A = AB[lo];\n";
     o << "        const int l = t - start[lo];\n";
     o << "        const int r = l / A.tiles_x;\n";
     o << "        " << kname << "_body(A, l % A.tiles_x, r % A.tiles_y, r / A.tiles_y);\n";
     o << "    }\n";
     o << "}\n";
-    return o.str();
+    return GroupSources{device_prelude(), body, single, o.str()};
 }
 
 }  // namespace wt

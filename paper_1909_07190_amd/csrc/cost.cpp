@@ -20,6 +20,8 @@
 //    times 4 SIMDs, instead of registers-per-SM / registers-per-thread.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <set>
 
 #include "wt_cost.h"
@@ -209,6 +211,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
         compute_ns += sp.ns_per_point * pts;
         valu_ops += sp.valu_ops * pts;
         computed += (double)active * geo.N * n.nch;
+        c.code_ops += (double)sp.valu_ops * n.nch * g.TX * g.V;
         useful += (double)g.TY * geo.X * n.nch;
         if (n.liveout) {
             int esz = n.mem_half ? 2 : 4;
@@ -235,6 +238,8 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     in.compute_time_per_wave = compute_ns * 1e-9;
     in.frac_overlap = useful > 0 ? computed / useful - 1.0 : 0.0;
     c.alg2 = alg2(in, m, w);
+    c.code_ops *= geo.D + geo.U + geo.E;
+    if (c.code_ops > m.max_code_ops) c.alg2.feasible = false;
     c.regs_est = regs;
     c.lds_per_wg = lds;
     c.requested_bytes = (load_bytes + store_bytes) * nwaves;

@@ -13,6 +13,9 @@
 // argmin of Algorithm 2's score over the configuration grid; the DP minimises
 // the sum over groups.
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <functional>
 #include <map>
@@ -247,7 +250,12 @@ std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, con
 
 Schedule schedule_analytic(const Pipeline& p, const Machine& m, const SchedRequest& r) {
     Search srch(p, m, r);
+    auto t0 = std::chrono::steady_clock::now();
     double t = srch.solve(0);
+    if (std::getenv("WT_DEBUG_SEARCH"))
+        fprintf(stderr, "search: %zu stages, %lld groups costed, %zu states, %.3f s\n", srch.stages.size(),
+                srch.groups_costed, srch.memo.size(),
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     if (!std::isfinite(t)) fail(WT_E_UNSUPPORTED, "no feasible schedule for this pipeline");
     return srch.extract();
 }

@@ -243,7 +243,7 @@ std::string describe_group(const GroupSched& g) {
     return os.str();
 }
 
-Schedule parse_schedule(const std::string& text, const Pipeline& p) {
+Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial) {
     Schedule s;
     std::string t = text;
     std::replace(t.begin(), t.end(), ';', '\n');
@@ -259,6 +259,7 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p) {
             auto eq = tok.find('=');
             if (eq == std::string::npos) continue;  // e.g. a "g0" label
             std::string k = tok.substr(0, eq), v = tok.substr(eq + 1);
+            if (k.rfind("batch_", 0) == 0) continue;  // launch facts in a plan description
             try {
                 if (k == "nodes") {
                     std::istringstream vs(v);
@@ -290,9 +291,10 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p) {
         }
         s.groups.push_back(g);
     }
-    for (const Node& n : p.nodes)
-        if (n.kind != Kind::Input && !seen.count(n.id))
-            fail(WT_E_INVALID, "schedule misses node " + std::to_string(n.id));
+    if (!partial)
+        for (const Node& n : p.nodes)
+            if (n.kind != Kind::Input && !seen.count(n.id))
+                fail(WT_E_INVALID, "schedule misses node " + std::to_string(n.id));
     return s;
 }
 

@@ -34,34 +34,40 @@ namespace {
 
 int64_t round_up64(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Deterministic, content-derived kernel name: distinct across plans in one
-// process (profiles stay readable) and stable across runs (the code cache
-// keys on the source, which contains the name).
-std::string kernel_name(const Pipeline& p, const GroupSched& g, int gi) {
-    std::ostringstream os;
-    os << describe_group(g) << "|";
-    for (int id : g.nodes) {
-        const Node& n = p.nodes[id];
-        os << (int)n.kind << ":" << n.channels << ":" << n.level << ":" << n.kw << "x" << n.kh << ":"
-           << n.ax << "," << n.ay << ":" << n.scale << ":" << n.expr_text << ":";
-        for (double w : n.weights) os << w << ",";
-        for (int s : n.srcs) os << "s" << s;
-        os << ";";
-    }
+// Content-addressed kernel names: the hash of the generated text (written
+// with a placeholder name), so two kernels share a name only if their code
+// is identical, and any change to the generator renames the kernel (profile
+// figures keyed by name then no longer apply to it).
+const char* const kNamePlaceholder = "wt_kernel_name_placeholder";
+
+std::string kernel_name(const GroupSources& gs, const GroupSched& g, int gi) {
     uint64_t h = 1469598103934665603ull;
-    for (unsigned char c : os.str()) h = (h ^ c) * 1099511628211ull;
+    for (const std::string* part : {&gs.prelude, &gs.common, &gs.single, &gs.batch})
+        for (unsigned char c : *part) h = (h ^ c) * 1099511628211ull;
     char buf[64];
     std::snprintf(buf, sizeof buf, "wt_g%d_%s_%012llx", gi, g.nodes.size() > 1 ? "fused" : "stage",
                   (unsigned long long)(h & 0xffffffffffffull));
     return buf;
 }
 
+void name_sources(GroupRt& gr, GroupSources gs, int gi) {
+    gr.kname = kernel_name(gs, gr.g, gi);
+    for (std::string* part : {&gs.common, &gs.single, &gs.batch}) {
+        std::string& t = *part;
+        const std::string ph = kNamePlaceholder;
+        for (size_t pos = 0; (pos = t.find(ph, pos)) != std::string::npos; pos += gr.kname.size())
+            t.replace(pos, ph.size(), gr.kname);
+    }
+    gr.src = gs.full();
+    gr.src_single = gs.single_module();
+    gr.src_batch = gs.batch_module();
+}
+
 }  // namespace
 
 Plan::~Plan() {
     batch.reset();
-    for (auto& g : groups)
-        if (g.mod) hipModuleUnload(g.mod);
+    for (auto& g : groups) unload_group(g);
     for (auto& b : bufs)
         if (b.second.ptr) hipFree(b.second.ptr);
 }
@@ -77,7 +83,8 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     wt_sched_opts def{};
     def.mode = WT_SCHED_ANALYTIC;
     const wt_sched_opts& opts = o ? *o : def;
-    plan->no_device = (opts.flags & WT_PLAN_NO_DEVICE) != 0;
+    plan->no_device = (opts.flags & (WT_PLAN_NO_DEVICE | WT_PLAN_NO_COMPILE)) != 0;
+    plan->no_compile = (opts.flags & WT_PLAN_NO_COMPILE) != 0;
     plan->fp16 = opts.fp16_intermediates != 0;
     plan->any_width = (opts.flags & WT_PLAN_ANY_WIDTH) != 0;
     const char* env_cache = std::getenv("WT_CACHE_DIR");
@@ -108,7 +115,6 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     auto d = level_dims(plan.W, plan.H, lvl);
     gr.W = d.first;
     gr.H = d.second;
-    gr.kname = kernel_name(p, gr.g, gi);
     auto half_mem = [&](int id) { return plan.fp16 && p.nodes[id].kind != Kind::Input && !p.is_output(id); };
     gr.mem_half_in.clear();
     gr.mem_half_out.clear();
@@ -119,7 +125,8 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
         gr.Hs = sd.second;
         gr.loaded = {n.srcs[0]};
         gr.liveouts = {n.id};
-        gr.src = generate_resample_source(p, gr.g, gr.kname, half_mem(n.srcs[0]), half_mem(n.id));
+        name_sources(gr, generate_resample_source(p, gr.g, kNamePlaceholder, half_mem(n.srcs[0]), half_mem(n.id)),
+                     gi);
         gr.mem_half_in = {half_mem(n.srcs[0])};
         gr.mem_half_out = {half_mem(n.id)};
         gr.tiles_x = (gr.W + 63) / 64;
@@ -133,7 +140,7 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     for (int l : gr.geo.liveouts) gr.mem_half_out.push_back(half_mem(l));
     gr.loaded = gr.geo.loaded;
     gr.liveouts = gr.geo.liveouts;
-    gr.src = generate_group_source(p, gr.g, gr.geo, gr.kname);
+    name_sources(gr, generate_group_source(p, gr.g, gr.geo, kNamePlaceholder), gi);
     int amin = 1 << 30, amax = 0;
     for (int lo : gr.geo.liveouts) {
         const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(lo)];
@@ -149,9 +156,17 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
         fail(WT_E_UNSUPPORTED, "group needs " + std::to_string(gr.geo.lds_bytes_per_wg) + " bytes of LDS per workgroup");
 }
 
-// Compiles the groups' sources in parallel on host cores (hipRTC), then
-// loads the code objects unless the plan has no device.
-void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs) {
+void unload_group(GroupRt& gr) {
+    if (gr.mod) hipModuleUnload(gr.mod);
+    if (gr.mod_batch) hipModuleUnload(gr.mod_batch);
+    gr.mod = gr.mod_batch = nullptr;
+    gr.fn = gr.fn_batch = nullptr;
+}
+
+// Compiles the groups' single-image modules (or, with `batch`, their batched
+// modules) in parallel on host cores (hipRTC), then loads the code objects
+// unless the plan has no device.
+void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch) {
     std::vector<std::vector<char>> code(grs.size());
     std::vector<std::string> errs(grs.size());
     std::atomic<size_t> next{0};
@@ -162,7 +177,8 @@ void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs) {
         pool.emplace_back([&] {
             for (size_t i; (i = next++) < grs.size();) {
                 try {
-                    code[i] = compile_hip(grs[i]->src, grs[i]->kname, plan.cache_dir);
+                    code[i] = compile_hip(batch ? grs[i]->src_batch : grs[i]->src_single,
+                                          grs[i]->kname + (batch ? "_batch" : ""), plan.cache_dir);
                 } catch (const std::exception& e) {
                     errs[i] = e.what();
                 }
@@ -173,11 +189,17 @@ void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs) {
         if (!errs[i].empty()) fail(WT_E_COMPILE, errs[i]);
     if (plan.no_device) return;
     for (size_t i = 0; i < grs.size(); ++i) {
-        if (grs[i]->mod) continue;
-        hip_check(hipModuleLoadData(&grs[i]->mod, code[i].data()), "hipModuleLoadData");
-        hip_check(hipModuleGetFunction(&grs[i]->fn, grs[i]->mod, grs[i]->kname.c_str()), "hipModuleGetFunction");
-        hip_check(hipModuleGetFunction(&grs[i]->fn_batch, grs[i]->mod, (grs[i]->kname + "_batch").c_str()),
-                  "hipModuleGetFunction");
+        GroupRt& g = *grs[i];
+        if (batch) {
+            if (g.mod_batch) continue;
+            hip_check(hipModuleLoadData(&g.mod_batch, code[i].data()), "hipModuleLoadData");
+            hip_check(hipModuleGetFunction(&g.fn_batch, g.mod_batch, (g.kname + "_batch").c_str()),
+                      "hipModuleGetFunction");
+        } else {
+            if (g.mod) continue;
+            hip_check(hipModuleLoadData(&g.mod, code[i].data()), "hipModuleLoadData");
+            hip_check(hipModuleGetFunction(&g.fn, g.mod, g.kname.c_str()), "hipModuleGetFunction");
+        }
     }
 }
 
@@ -186,8 +208,7 @@ void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs) {
 void build_groups(Plan& plan) {
     const Pipeline& p = plan.p;
     plan.batch.reset();
-    for (auto& g : plan.groups)
-        if (g.mod) hipModuleUnload(g.mod);
+    for (auto& g : plan.groups) unload_group(g);
     plan.groups.clear();
     std::vector<bool> in_memory(p.nodes.size(), false);
     for (int i : p.inputs) in_memory[i] = true;
@@ -204,7 +225,7 @@ void build_groups(Plan& plan) {
         if (!in_memory[o]) fail(WT_E_INVALID, "schedule does not produce output node " + std::to_string(o));
     std::vector<GroupRt*> grs;
     for (auto& g : plan.groups) grs.push_back(&g);
-    compile_groups(plan, grs);
+    if (!plan.no_compile) compile_groups(plan, grs);
     if (plan.no_device) return;
     // device buffers for intermediates materialised between groups
     for (auto& gr : plan.groups) {
@@ -327,8 +348,13 @@ void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRe
 
 std::string describe_plan(const Plan& plan) {
     std::ostringstream os;
-    for (size_t i = 0; i < plan.sched.groups.size(); ++i)
-        os << "g" << i << " " << describe_group(plan.sched.groups[i]) << "\n";
+    for (size_t i = 0; i < plan.sched.groups.size(); ++i) {
+        os << "g" << i << " " << describe_group(plan.sched.groups[i]);
+        if (plan.batch && i < plan.batch->grid.size())
+            os << " batch_grid=" << plan.batch->grid[i] << " batch_wg_per_cu=" << plan.batch->per_cu[i]
+               << " batch_work=" << plan.batch->total[i];
+        os << "\n";
+    }
     return os.str();
 }
 

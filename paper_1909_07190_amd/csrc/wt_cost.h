@@ -52,6 +52,7 @@ struct GroupCost {
     double regs_est = 0, lds_per_wg = 0;
     double requested_bytes = 0, compulsory_bytes = 0, valu_ops = 0;
     long long nwaves = 0;
+    double code_ops = 0;         // straight-line VALU operations per kernel body
 };
 GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& geo, const Machine& m, int W,
                      int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7]);

@@ -94,7 +94,8 @@ bool is_resample_group(const Pipeline& p, const GroupSched& g);
 struct Schedule { std::vector<GroupSched> groups; };
 
 std::string describe_group(const GroupSched& g);
-Schedule parse_schedule(const std::string& text, const Pipeline& p);
+// `partial`: the text may name a subset of the stages (measurement).
+Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial = false);
 
 // Geometry of a stencil/pointwise group (Section 4's warp-overlapped tile with
 // Section 5's skewed sub-tiles); see geometry.cpp.
@@ -159,14 +160,28 @@ struct Machine {
     double hbm_efficiency = 0.75;  // achievable fraction of peak for streaming
     double launch_us = 2.0;        // per-kernel launch and drain
     int max_vgpr_per_wave = 256;   // architectural VGPRs addressable by a wave
+    // Straight-line code bound: estimated VALU operations emitted per kernel
+    // body (prologue + unrolled main loop + epilogue, every member, every
+    // element a lane owns).  Beyond it the kernel no longer fits the
+    // instruction cache and takes tens of seconds to compile.
+    double max_code_ops = 12000;
 };
 Machine machine_from_device(int device);  // falls back to the constant table
 
 // ------------------------------------------------------------- codegen ---
-std::string generate_group_source(const Pipeline& p, const GroupSched& g,
-                                  const GroupGeom& geo, const std::string& kname);
-std::string generate_resample_source(const Pipeline& p, const GroupSched& g,
-                                     const std::string& kname, bool src_half, bool dst_half);
+// A group's kernels: the single-image kernel `kname` and the batched
+// persistent kernel `kname_batch`, each after the shared device prelude.
+// They are compiled as separate modules (the batched one on first use).
+struct GroupSources {
+    std::string prelude, common, single, batch;  // common: helpers both kernels call
+    std::string full() const { return prelude + "\n" + common + single + "\n" + batch; }
+    std::string single_module() const { return prelude + "\n" + common + single; }
+    std::string batch_module() const { return prelude + "\n" + common + batch; }
+};
+GroupSources generate_group_source(const Pipeline& p, const GroupSched& g,
+                                   const GroupGeom& geo, const std::string& kname);
+GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g,
+                                      const std::string& kname, bool src_half, bool dst_half);
 std::string device_prelude();
 
 // ----------------------------------------------------------- scheduler ---

@@ -40,8 +40,9 @@ struct GroupRt {
     GroupSched g;
     GroupGeom geo;
     bool resample = false;
-    std::string src, kname;
-    hipModule_t mod = nullptr;
+    std::string src, kname;            // src: both kernels (for inspection)
+    std::string src_single, src_batch; // the two compiled modules
+    hipModule_t mod = nullptr, mod_batch = nullptr;
     hipFunction_t fn = nullptr;        // single image, one wave (or block) per tile
     hipFunction_t fn_batch = nullptr;  // persistent, all images of a batch
     int W = 0, H = 0, Ws = 0, Hs = 0;
@@ -57,7 +58,7 @@ struct BatchState {
     size_t arena_bytes = 0;
     std::vector<std::map<int, Buf>> bufs;  // per image: intermediates in the arena
     std::vector<std::array<int, 3>> tiles; // [group][img]: tiles_x, tiles_y, work items
-    std::vector<int> total, grid;          // per group
+    std::vector<int> total, grid, per_cu;  // per group
     void* dargs = nullptr;                 // device argument table
     size_t args_bytes = 0, dargs_bytes = 0;
     std::vector<char> host;                // host copy of the table
@@ -75,6 +76,7 @@ struct Plan {
     int W = 0, H = 0;
     int device = 0;
     bool no_device = false;
+    bool no_compile = false;
     bool fp16 = false;
     bool any_width = false;
     std::string cache_dir;
@@ -90,12 +92,16 @@ struct ImgRef {
 void hip_check(hipError_t e, const char* what);
 std::pair<int, int> level_dims(int W, int H, int level);
 void prepare_group(const Plan& plan, GroupRt& gr, int gi);
-void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs);
+void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch = false);
+void unload_group(GroupRt& gr);
 void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st);
 void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, WtArgsHost& a,
                const std::string& tag);
+int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads);
 void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
 void autotune_plan(Plan& plan, int topk);
+void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vector<std::string>& descs, int reps,
+                    const std::string& tag, double* out_us);
 std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H);
 void build_groups(Plan& plan);
 void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int nout, void* stream);
