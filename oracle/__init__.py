@@ -23,7 +23,16 @@ Readings where the paper is silent (it uses interior-only domains):
     odd output 2i+1 -> (P(i) + P(i+1)) / 2, coarse indices clamped, output
     domain the size of the finer level;
   * a pointwise stage reads each source at the same point; a one-channel
-    source is broadcast over channels.
+    source is broadcast over channels;
+  * integer stages (types u8, u16, i16, i32): values are int64 in the oracle.
+    An integer stencil takes the exact sum of integer weights times producer
+    values, divides by its positive integer divisor d rounding halves up,
+    floor((sum + floor(d/2)) / d), and saturates to its type's range; an
+    integer pointwise expression (integer constants, no division) is
+    evaluated exactly and saturated.  A float stage reading an integer stage
+    sees its value converted exactly.  Integer stages do not take up2
+    (a rounding rule for the expansion is not defined) and never read float
+    stages.
 
 Every function below is pinned by tests under ``tests/`` (brute force on tiny
 images, closed forms on ramps, steps, impulses and corners, and invariants).
@@ -35,7 +44,11 @@ import ast
 import numpy as np
 
 __all__ = ["evaluate", "evaluate_stage", "parse_expr", "level_size",
-           "stencil", "down2", "up2", "pointwise"]
+           "stencil", "stencil_int", "down2", "up2", "pointwise", "INT_TYPES"]
+
+# Value range of each integer type.
+INT_TYPES = {"u8": (0, 255), "u16": (0, 65535), "i16": (-32768, 32767),
+             "i32": (-(2 ** 31), 2 ** 31 - 1)}
 
 
 # --------------------------------------------------------------------------
@@ -75,6 +88,36 @@ def stencil(p: np.ndarray, kw: int, kh: int, ax: int, ay: int,
             xi = np.clip(xs + i - ax, 0, w - 1)
             acc += wts[j, i] * p[:, yi][:, :, xi]
     return float(scale) * acc
+
+
+def stencil_int(p: np.ndarray, kw: int, kh: int, ax: int, ay: int,
+                weights, divisor: int, dtype: str) -> np.ndarray:
+    """Integer stencil on an int64 producer: the exact sum
+    acc = sum_{j,i} w[j][i] * P_c(clamp(x+i-ax), clamp(y+j-ay)), then
+    floor((acc + floor(d/2)) / d) (ties round up) saturated to ``dtype``."""
+    if p.dtype != np.int64:
+        raise ValueError("integer stencils read integer stages")
+    if int(divisor) < 1:
+        raise ValueError("divisor must be a positive integer")
+    wl = [int(v) for v in weights]
+    if any(float(v) != float(int(v)) for v in weights):
+        raise ValueError("integer stencil weights must be integers")
+    c, h, w = p.shape
+    wts = np.asarray(wl, dtype=np.int64).reshape(kh, kw)
+    xs = np.arange(w)
+    ys = np.arange(h)
+    acc = np.zeros((c, h, w), dtype=np.int64)
+    for j in range(kh):
+        yi = np.clip(ys + j - ay, 0, h - 1)
+        for i in range(kw):
+            if wts[j, i] == 0:
+                continue
+            xi = np.clip(xs + i - ax, 0, w - 1)
+            acc += wts[j, i] * p[:, yi][:, :, xi]
+    d = int(divisor)
+    q = (acc + d // 2) // d  # numpy's // on integers floors
+    lo, hi = INT_TYPES[dtype]
+    return np.clip(q, lo, hi)
 
 
 def down2(p: np.ndarray) -> np.ndarray:
@@ -146,10 +189,14 @@ def parse_expr(expr: str) -> ast.AST:
     return tree
 
 
-def _eval(node, srcs, ch):
+def _eval(node, srcs, ch, integer=False):
     if isinstance(node, ast.Expression):
-        return _eval(node.body, srcs, ch)
+        return _eval(node.body, srcs, ch, integer)
     if isinstance(node, ast.Constant):
+        if integer:
+            if float(node.value) != int(node.value):
+                raise ValueError("integer expressions take integer constants")
+            return np.int64(int(node.value))
         return float(node.value)
     if isinstance(node, ast.Name):
         s = srcs[int(node.id[1:])]
@@ -161,24 +208,28 @@ def _eval(node, srcs, ch):
             raise ValueError("bad channel subscript")
         return s[k]
     if isinstance(node, ast.UnaryOp):
-        v = _eval(node.operand, srcs, ch)
+        v = _eval(node.operand, srcs, ch, integer)
         return -v if isinstance(node.op, ast.USub) else v
     if isinstance(node, ast.BinOp):
-        a = _eval(node.left, srcs, ch)
-        b = _eval(node.right, srcs, ch)
+        a = _eval(node.left, srcs, ch, integer)
+        b = _eval(node.right, srcs, ch, integer)
         if isinstance(node.op, ast.Add):
             return a + b
         if isinstance(node.op, ast.Sub):
             return a - b
         if isinstance(node.op, ast.Mult):
             return a * b
+        if integer:
+            raise ValueError("integer expressions have no division")
         return a / b
     if isinstance(node, ast.Compare):
-        return _CMP[type(node.ops[0])](_eval(node.left, srcs, ch),
-                                       _eval(node.comparators[0], srcs, ch))
+        return _CMP[type(node.ops[0])](_eval(node.left, srcs, ch, integer),
+                                       _eval(node.comparators[0], srcs, ch, integer))
     if isinstance(node, ast.Call):
-        args = [_eval(a, srcs, ch) for a in node.args]
+        args = [_eval(a, srcs, ch, integer) for a in node.args]
         f = node.func.id
+        if integer and f in ("sqrt", "floor"):
+            raise ValueError(f"{f} is not an integer operation")
         if f == "abs":
             return np.abs(args[0])
         if f == "min":
@@ -193,18 +244,26 @@ def _eval(node, srcs, ch):
     raise ValueError("unsupported node")
 
 
-def pointwise(expr: str, srcs, channels: int) -> np.ndarray:
-    """Evaluates ``expr`` at every point of every output channel in float64."""
+def pointwise(expr: str, srcs, channels: int, dtype: str = "f32") -> np.ndarray:
+    """Evaluates ``expr`` at every point of every output channel, in float64,
+    or for an integer ``dtype`` exactly in int64 and saturated to its range."""
     tree = parse_expr(expr)
+    integer = dtype in INT_TYPES
+    if integer and any(s.dtype != np.int64 for s in srcs):
+        raise ValueError("integer pointwise stages read integer stages only")
     shape = None
     for s in srcs:
         if shape is None:
             shape = s.shape[1:]
         elif s.shape[1:] != shape:
             raise ValueError("pointwise sources must share one domain")
-    out = np.empty((channels,) + tuple(shape), dtype=np.float64)
+    out = np.empty((channels,) + tuple(shape), dtype=np.int64 if integer else np.float64)
     for c in range(channels):
-        out[c] = np.broadcast_to(_eval(tree, srcs, c), shape)
+        v = _eval(tree, srcs, c, integer)
+        if integer:
+            lo, hi = INT_TYPES[dtype]
+            v = np.clip(v, lo, hi)
+        out[c] = np.broadcast_to(v, shape)
     return out
 
 
@@ -236,27 +295,42 @@ def _levels(spec):
 
 def evaluate_stage(st, vals, lv, width, height):
     k = st["kind"]
+    dtype = st.get("dtype", "f32")
     if k == "stencil":
+        if dtype in INT_TYPES:
+            return stencil_int(vals[st["src"]], st["kw"], st["kh"], st["ax"], st["ay"],
+                               st["weights"], st.get("divisor", 1), dtype)
         return stencil(vals[st["src"]], st["kw"], st["kh"], st["ax"], st["ay"],
                        st["weights"], st["scale"])
     if k == "down2":
         return down2(vals[st["src"]])
     if k == "up2":
+        if vals[st["src"]].dtype == np.int64:
+            raise ValueError("up2 of an integer stage")
         ow, oh = level_size(width, height, lv[st["name"]])
         return up2(vals[st["src"]], ow, oh)
-    return pointwise(st["expr"], [vals[s] for s in st["srcs"]], st["channels"])
+    return pointwise(st["expr"], [vals[s] for s in st["srcs"]], st["channels"], dtype)
 
 
 def evaluate(spec: dict, inputs: dict, keep_all: bool = False) -> dict:
     """Evaluates the pipeline on ``inputs`` (name -> [C, H, W] array).
 
-    Returns the outputs (or every stage when ``keep_all``) as float64 arrays.
+    Returns the outputs (or every stage when ``keep_all``) as float64 arrays,
+    int64 for integer stages.
     """
     lv = _levels(spec)
     vals = {}
     shape = None
     for inp in spec["inputs"]:
-        a = np.asarray(inputs[inp["name"]], dtype=np.float64)
+        dtype = inp.get("dtype", "f32")
+        if dtype in INT_TYPES:
+            a = np.asarray(inputs[inp["name"]])
+            lo, hi = INT_TYPES[dtype]
+            if a.size and (a.min() < lo or a.max() > hi or np.any(a != np.floor(a))):
+                raise ValueError(f"input {inp['name']} holds values outside {dtype}")
+            a = a.astype(np.int64)
+        else:
+            a = np.asarray(inputs[inp["name"]], dtype=np.float64)
         if a.ndim == 2:
             a = a[None]
         if a.shape[0] != inp["channels"]:

@@ -1,0 +1,436 @@
+"""Training data, training and evaluation of the learned cost model.
+
+The learned model (a 40-128-128-128-1 ReLU network over the features the
+scheduler computes for a (fusion group, configuration) pair) predicts the log
+of the group's kernel time.  Its data are timings the library itself takes on
+the device:
+
+* ``collect``: for each pipeline, candidate groups (the analytical
+  schedule's groups, every stage alone, and random connected convex groups of
+  2..12 stages) are timed under several configurations each (the analytical
+  model's pick and random draws from the search grid) through
+  ``measure_groups``; every timing is appended to a JSON-lines database.
+* ``train``: the network is trained on the device (the library's forward,
+  backward and Adam kernels) on a split of the database by pipeline.
+* ``evaluate``: for held-out pipelines, whole plans scheduled by the
+  analytical model, by the learned model and by the autotuner are timed next
+  to the unfused plan and to the best schedule assembled from the measured
+  candidates (a dynamic program over measured group times), and both models'
+  rankings are compared to the measurements (Kendall tau).
+
+Command line: ``python -m paper_1909_07190_amd.learn collect|train|evaluate``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import random
+import sys
+import time
+
+import numpy as np
+
+from . import NUM_FEATURES, Mlp, from_spec, group_features, measure_groups
+
+FUSABLE = ("stencil", "pointwise")
+
+
+# ---------------------------------------------------------------- structure --
+
+class Dag:
+    """Stage structure of a plain-data pipeline spec, by library node id."""
+
+    def __init__(self, spec, pipe):
+        self.spec = spec
+        self.pipe = pipe
+        self.kind, self.level, self.prod = {}, {}, {}
+        for inp in spec["inputs"]:
+            i = pipe.names[inp["name"]]
+            self.kind[i], self.level[i], self.prod[i] = "input", 0, []
+        for st in spec["stages"]:
+            i = pipe.names[st["name"]]
+            srcs = [pipe.names[s] for s in st.get("srcs", [st.get("src")])]
+            self.kind[i] = st["kind"]
+            self.prod[i] = srcs
+            lv = self.level[srcs[0]]
+            self.level[i] = lv + 1 if st["kind"] == "down2" else lv - 1 if st["kind"] == "up2" else lv
+        self.stages = sorted(i for i, k in self.kind.items() if k != "input")
+        self.cons = {i: [] for i in self.kind}
+        for i, ps in self.prod.items():
+            for s in ps:
+                self.cons[s].append(i)
+
+    def fusable(self, i):
+        return self.kind[i] in FUSABLE
+
+    def _closure(self, start, nxt):
+        seen, stack = set(), list(start)
+        while stack:
+            v = stack.pop()
+            for u in nxt[v]:
+                if u not in seen:
+                    seen.add(u)
+                    stack.append(u)
+        return seen
+
+    def convex(self, group):
+        g = set(group)
+        down = self._closure(g, self.cons) - g
+        up = self._closure(g, self.prod) - g
+        return not (down & up)
+
+    def random_group(self, rng, size):
+        seeds = [i for i in self.stages if self.fusable(i)]
+        if not seeds:
+            return None
+        g = [rng.choice(seeds)]
+        lvl = self.level[g[0]]
+        for _ in range(4 * size):
+            if len(g) >= size:
+                break
+            nb = sorted({u for v in g for u in self.prod[v] + self.cons[v]
+                         if u not in g and self.kind[u] in FUSABLE and self.level[u] == lvl})
+            if not nb:
+                break
+            u = rng.choice(nb)
+            if self.convex(g + [u]):
+                g.append(u)
+        return sorted(g) if len(g) >= 2 else None
+
+
+def _group_text(nodes, cfg=""):
+    return "nodes=" + ",".join(str(n) for n in nodes) + (" " + cfg if cfg else "")
+
+
+def _parse_groups(describe_text):
+    out = []
+    for line in describe_text.strip().splitlines():
+        toks = [t for t in line.split() if "=" in t and not t.startswith("batch_")]
+        nodes = [int(x) for x in toks[0].split("=")[1].split(",")]
+        out.append((nodes, " ".join(toks)))
+    return out
+
+
+# ------------------------------------------------------------------ collect --
+
+def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_groups=6,
+            reps=20, seed=0, log=print):
+    """Times candidate groups of every pipeline in `specs` (dict tag -> spec);
+    appends to the database `db` (JSON lines)."""
+    os.environ["WT_MEASURE_DB"] = db
+    rng = random.Random(seed)
+    n_total = 0
+    for tag, spec in specs.items():
+        t0 = time.time()
+        pipe = from_spec(spec)
+        dag = Dag(spec, pipe)
+        plan = pipe.plan(width, height, mode="analytic", no_compile=True)
+        texts = []
+        groups = []
+        for nodes, text in _parse_groups(plan.describe()):
+            groups.append((nodes, configs_per_group))
+            texts.append(text)  # the analytical pick itself
+        for i in dag.stages:
+            groups.append(([i], 1 if dag.fusable(i) else 0))
+            if not dag.fusable(i):
+                texts.append(_group_text([i]))
+        for _ in range(random_groups):
+            g = dag.random_group(rng, rng.randint(2, 12))
+            if g:
+                groups.append((g, configs_per_group))
+        seen = set(texts)
+        for nodes, k in groups:
+            if k == 0:
+                continue
+            _, cfgs = group_features(pipe, nodes, width, height)
+            cfgs = [c for c in cfgs if c]
+            for c in rng.sample(cfgs, min(k, len(cfgs))):
+                if c not in seen:
+                    seen.add(c)
+                    texts.append(c)
+        times = measure_groups(pipe, texts, width, height, reps=reps, tag=tag)
+        n_total += len(texts)
+        ok = sum(1 for t in times if math.isfinite(t))
+        log(f"collect {tag}: {len(spec['stages'])} stages, {len(texts)} candidates ({ok} timed), "
+            f"{time.time() - t0:.1f} s, {n_total} so far")
+    return n_total
+
+
+# -------------------------------------------------------------------- train --
+
+def load_db(paths):
+    rows = []
+    for p in paths:
+        with open(p) as f:
+            for line in f:
+                line = line.strip()
+                if line:
+                    r = json.loads(line)
+                    if math.isfinite(r["measured_us"]) and r["measured_us"] > 0:
+                        rows.append(r)
+    return rows
+
+
+def split_tags(rows, test_fraction=0.2, seed=0):
+    tags = sorted({r["pipeline"] for r in rows})
+    rng = random.Random(seed)
+    rng.shuffle(tags)
+    ntest = max(1, int(round(len(tags) * test_fraction))) if len(tags) > 1 else 0
+    return set(tags[ntest:]), set(tags[:ntest])
+
+
+def train(rows, model_path, epochs=200, batch=256, lr=1e-3, seed=1, log=print):
+    x = np.array([r["features"] for r in rows], np.float32)
+    y = np.log(np.array([r["measured_us"] for r in rows], np.float64)).astype(np.float32)
+    assert x.shape[1] == NUM_FEATURES
+    net = Mlp(seed=seed)
+    t0 = time.time()
+    loss = net.train(x, y, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    log(f"train: {len(rows)} rows, {epochs} epochs, {time.time() - t0:.1f} s, final loss {loss}")
+    net.save(model_path)
+    return net
+
+
+def kendall_tau(a, b):
+    n, s = len(a), 0
+    cnt = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            d = (a[i] - a[j]) * (b[i] - b[j])
+            if d > 0:
+                s += 1
+            elif d < 0:
+                s -= 1
+            cnt += 1
+    return s / cnt if cnt else float("nan")
+
+
+def ranking_report(rows, net):
+    """Per group (same pipeline and node set, two or more configurations):
+    Kendall tau of the analytical predicted time, Algorithm 2's score and the
+    network's prediction against the measurements, and the regret of each
+    model's top pick (its measured time over the best measured)."""
+    by = {}
+    for r in rows:
+        key = (r["pipeline"], r["group"].split()[0])
+        by.setdefault(key, []).append(r)
+    taus = {"analytic_pred": [], "alg2_score": [], "mlp": []}
+    regret = {"analytic_pred": [], "alg2_score": [], "mlp": []}
+    for rs in by.values():
+        if len(rs) < 2:
+            continue
+        meas = [r["measured_us"] for r in rs]
+        pred_mlp = list(np.exp(net.predict(np.array([r["features"] for r in rs], np.float32))))
+        for name, pred in (("analytic_pred", [r["pred_us"] for r in rs]),
+                           ("alg2_score", [r["score"] for r in rs]), ("mlp", pred_mlp)):
+            taus[name].append(kendall_tau(pred, meas))
+            regret[name].append(meas[int(np.argmin(pred))] / min(meas))
+    out = {}
+    for name in taus:
+        t = [v for v in taus[name] if math.isfinite(v)]
+        out[name] = {"groups": len(t), "kendall_tau_mean": float(np.mean(t)) if t else None,
+                     "top1_regret_geomean": float(np.exp(np.mean(np.log(regret[name])))) if regret[name] else None}
+    return out
+
+
+# ----------------------------------------------------------------- evaluate --
+
+def _time_plan(torch, plan, ins, outs, reps=20):
+    for _ in range(3):
+        plan.run(ins, outs)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            plan.run(ins, outs)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e3 / reps)
+    return best
+
+
+def best_measured_schedule(dag, rows, resample_us):
+    """Minimum-total-time partition of the stages into measured candidate
+    groups (each at its best measured configuration), by a dynamic program over
+    down-closed stage sets; returns (total microseconds, schedule text)."""
+    best = {}
+    for r in rows:
+        nodes = tuple(int(x) for x in r["group"].split()[0].split("=")[1].split(","))
+        if nodes not in best or r["measured_us"] < best[nodes][0]:
+            best[nodes] = (r["measured_us"], r["group"])
+    for i, (us, text) in resample_us.items():
+        best[(i,)] = (us, text)
+    stages = dag.stages
+    bit = {s: 1 << k for k, s in enumerate(stages)}
+    full = (1 << len(stages)) - 1
+    cand = []
+    for nodes, (us, text) in best.items():
+        m = 0
+        for n in nodes:
+            m |= bit[n]
+        need = 0
+        for n in nodes:
+            for p in dag.prod[n]:
+                if p in bit and not (m & bit[p]):
+                    need |= bit[p]
+        cand.append((m, need, us, text))
+    memo = {}
+
+    def solve(S):
+        if S == full:
+            return 0.0, []
+        if S in memo:
+            return memo[S]
+        res = (float("inf"), [])
+        for m, need, us, text in cand:
+            if m & S or (need & ~S):
+                continue
+            t, rest = solve(S | m)
+            if us + t < res[0]:
+                res = (us + t, [text] + rest)
+        memo[S] = res
+        return res
+
+    sys.setrecursionlimit(10000)
+    t, texts = solve(0)
+    return t, ";".join(texts)
+
+
+def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, log=print):
+    import torch
+
+    dev = torch.device("cuda:0")
+    results = []
+    for tag, spec in specs.items():
+        pipe = from_spec(spec)
+        dag = Dag(spec, pipe)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(len(results) + 1)
+        ins = [torch.rand((1, height, width), device=dev, generator=gen) for _ in spec["inputs"]]
+        outs = []
+        for o in spec["outputs"]:
+            lv = dag.level[pipe.names[o]]
+            w, h = width, height
+            for _ in range(lv):
+                w, h = (w + 1) // 2, (h + 1) // 2
+            outs.append(torch.empty((1, h, w), device=dev))
+        res = {"pipeline": tag, "stages": len(spec["stages"])}
+        plans = {
+            "unfused": pipe.plan(width, height, mode="unfused"),
+            "analytic": pipe.plan(width, height, mode="analytic"),
+            "mlp": pipe.plan(width, height, mode="mlp", model_path=model_path),
+            "autotune": pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk),
+        }
+        drows = [r for r in rows if r["pipeline"] == tag]
+        if drows:
+            res_us = {}
+            for i in dag.stages:
+                if not dag.fusable(i):
+                    t = measure_groups(pipe, [_group_text([i])], width, height)[0]
+                    res_us[i] = (t, _group_text([i]))
+            t_sum, text = best_measured_schedule(dag, drows, res_us)
+            if math.isfinite(t_sum):
+                plans["best_measured"] = pipe.plan(width, height, mode="fixed", fixed=text)
+                res["best_measured_sum_us"] = t_sum
+        for name, plan in plans.items():
+            res[name + "_us"] = _time_plan(torch, plan, ins, outs)
+            res[name + "_groups"] = plan.num_groups
+        best = min(v for k, v in res.items() if k.endswith("_us") and not k.endswith("sum_us"))
+        res["best_us"] = best
+        results.append(res)
+        log(json.dumps(res))
+    return results
+
+
+def summarize(results):
+    def gm(xs):
+        xs = [x for x in xs if x > 0 and math.isfinite(x)]
+        return float(np.exp(np.mean(np.log(xs)))) if xs else None
+
+    out = {"pipelines": len(results)}
+    for m in ("analytic", "mlp", "autotune", "unfused"):
+        r = [x[m + "_us"] / x["best_us"] for x in results]
+        out[m] = {"geomean_over_best": gm(r), "within_10pct": float(np.mean([v <= 1.10 for v in r]))}
+    out["mlp_gain_over_analytic"] = gm([x["analytic_us"] / x["mlp_us"] for x in results])
+    out["mlp_speedup_over_unfused"] = gm([x["unfused_us"] / x["mlp_us"] for x in results])
+    return out
+
+
+# ---------------------------------------------------------------------- cli --
+
+def _seeds(text):
+    out = []
+    for part in text.split(","):
+        if "-" in part:
+            a, b = part.split("-")
+            out.extend(range(int(a), int(b) + 1))
+        else:
+            out.append(int(part))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_1909_07190_amd.learn")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect", help="time candidate groups of random pipelines")
+    c.add_argument("--seeds", required=True, help="random pipeline seeds, e.g. 0-99")
+    c.add_argument("--db", required=True)
+    c.add_argument("--configs", type=int, default=4)
+    c.add_argument("--random-groups", type=int, default=6)
+    c.add_argument("--size", type=int, default=2048)
+    t = sub.add_parser("train", help="train the network on the device")
+    t.add_argument("--db", required=True, nargs="+")
+    t.add_argument("--model", required=True)
+    t.add_argument("--epochs", type=int, default=200)
+    t.add_argument("--report", help="write the ranking report (JSON) here")
+    e = sub.add_parser("evaluate", help="compare whole-plan schedules on held-out pipelines")
+    e.add_argument("--db", required=True, nargs="+")
+    e.add_argument("--model", required=True)
+    e.add_argument("--max-pipelines", type=int, default=0)
+    e.add_argument("--size", type=int, default=2048)
+    e.add_argument("--out", help="append per-pipeline JSON lines here")
+    a = ap.parse_args(argv)
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from synth import dags
+
+    def log(m):
+        print(m, flush=True)
+
+    if a.cmd == "collect":
+        specs = {f"dag{s}": dags.random_dag(s) for s in _seeds(a.seeds)}
+        collect(specs, a.db, a.size, a.size, a.configs, a.random_groups, log=log)
+    elif a.cmd == "train":
+        rows = load_db(a.db)
+        tr, te = split_tags(rows)
+        train_rows = [r for r in rows if r["pipeline"] in tr]
+        net = train(train_rows, a.model, epochs=a.epochs, log=log)
+        rep = {"train_pipelines": len(tr), "test_pipelines": len(te), "train_rows": len(train_rows),
+               "test_rows": len(rows) - len(train_rows),
+               "train": ranking_report(train_rows, net),
+               "test": ranking_report([r for r in rows if r["pipeline"] in te], net)}
+        log(json.dumps(rep))
+        if a.report:
+            with open(a.report, "w") as f:
+                json.dump(rep, f, indent=1)
+    elif a.cmd == "evaluate":
+        rows = load_db(a.db)
+        _, te = split_tags(rows)
+        tags = sorted(te, key=lambda s: int(s[3:]) if s[3:].isdigit() else s)
+        if a.max_pipelines:
+            tags = tags[:a.max_pipelines]
+        specs = {tg: dags.random_dag(int(tg[3:])) for tg in tags}
+        res = evaluate(specs, rows, a.model, a.size, a.size, log=log)
+        if a.out:
+            with open(a.out, "a") as f:
+                for r in res:
+                    f.write(json.dumps(r) + "\n")
+        log(json.dumps(summarize(res)))
+
+
+if __name__ == "__main__":
+    main()

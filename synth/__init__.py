@@ -80,6 +80,16 @@ def dyadic_image(seed: int, channels: int, height: int, width: int,
         channels, height, width)
 
 
+def integer_image(seed: int, channels: int, height: int, width: int,
+                  lo: int, hi: int) -> np.ndarray:
+    """Planar CHW int64 image with values in [lo, hi] (the top 32 bits of
+    each draw reduced modulo hi - lo + 1; the caller casts to the storage
+    type)."""
+    u = splitmix64_block(seed, 0, channels * height * width)
+    k = (u >> np.uint64(32)) % np.uint64(hi - lo + 1)
+    return (k.astype(np.int64) + lo).reshape(channels, height, width)
+
+
 def white_squares(img: np.ndarray, seed: int, count: int = 200,
                   side_lo: int = 8, side_hi: int = 128) -> np.ndarray:
     """Paints ``count`` axis-aligned squares of value 1.0 into every channel.

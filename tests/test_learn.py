@@ -1,0 +1,119 @@
+"""Host logic of the learned-model campaign: candidate groups, the schedule
+assembled from measured groups, and the ranking statistics."""
+import itertools
+import random
+
+import pytest
+
+import paper_1909_07190_amd as wt
+from paper_1909_07190_amd import learn
+from synth import dags
+
+
+def _paths(dag, a, b):
+    """True if there is a path a -> b (a != b)."""
+    return b in dag._closure({a}, dag.cons)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_random_groups_are_convex_connected_single_level(seed):
+    spec = dags.random_dag(seed)
+    pipe = wt.from_spec(spec)
+    dag = learn.Dag(spec, pipe)
+    rng = random.Random(seed)
+    for _ in range(20):
+        g = dag.random_group(rng, rng.randint(2, 12))
+        if g is None:
+            continue
+        assert 2 <= len(g) <= 12
+        assert all(dag.fusable(i) for i in g)
+        assert len({dag.level[i] for i in g}) == 1
+        # convex by brute force: no outside node on a path between two members
+        for v in dag.stages:
+            if v in g:
+                continue
+            assert not (any(_paths(dag, a, v) for a in g) and any(_paths(dag, v, b) for b in g))
+        # connected (undirected)
+        seen, stack = {g[0]}, [g[0]]
+        while stack:
+            v = stack.pop()
+            for u in dag.prod[v] + dag.cons[v]:
+                if u in g and u not in seen:
+                    seen.add(u)
+                    stack.append(u)
+        assert seen == set(g)
+
+
+def test_best_measured_schedule_is_exhaustive_minimum():
+    spec = dags.random_dag(7, lo=6, hi=7)
+    pipe = wt.from_spec(spec)
+    dag = learn.Dag(spec, pipe)
+    rng = random.Random(3)
+    rows, groups = [], set()
+    for i in dag.stages:
+        groups.add((i,))
+    for _ in range(30):
+        g = dag.random_group(rng, rng.randint(2, 4))
+        if g:
+            groups.add(tuple(g))
+    res = {}
+    for g in groups:
+        if len(g) == 1 and not dag.fusable(g[0]):
+            res[g[0]] = (rng.uniform(5, 20), learn._group_text(list(g)))
+            continue
+        for k in range(2):
+            rows.append({"pipeline": "t", "group": learn._group_text(list(g), f"V={2 ** k}"),
+                         "measured_us": rng.uniform(5, 50)})
+    t, text = learn.best_measured_schedule(dag, rows, res)
+    # exhaustive: every set of candidate groups that partitions the stages
+    # and can be ordered (each group's producers come earlier)
+    best = {}
+    for r in rows:
+        g = tuple(int(x) for x in r["group"].split()[0].split("=")[1].split(","))
+        best[g] = min(best.get(g, float("inf")), r["measured_us"])
+    for i, (us, _) in res.items():
+        best[(i,)] = us
+    cands = list(best)
+    stages = set(dag.stages)
+    ref = float("inf")
+
+    def orderable(parts):
+        done, left = set(), list(parts)
+        while left:
+            for p in left:
+                if all(q in done or q in p or dag.kind[q] == "input" for n in p for q in dag.prod[n]):
+                    done |= set(p)
+                    left.remove(p)
+                    break
+            else:
+                return False
+        return True
+
+    def rec(covered, parts, cost):
+        nonlocal ref
+        if cost >= ref:
+            return
+        if covered == stages:
+            if orderable(parts):
+                ref = cost
+            return
+        first = min(stages - covered)
+        for c in cands:
+            if first in c and not (set(c) & covered):
+                rec(covered | set(c), parts + [c], cost + best[c])
+
+    rec(set(), [], 0.0)
+    assert t == pytest.approx(ref)
+    assert sorted(int(n) for part in text.split(";") for n in part.split()[0][6:].split(",")) == sorted(stages)
+
+
+def test_kendall_tau():
+    assert learn.kendall_tau([1, 2, 3], [10, 20, 30]) == 1.0
+    assert learn.kendall_tau([1, 2, 3], [30, 20, 10]) == -1.0
+    assert learn.kendall_tau([1, 2, 3, 4], [1, 3, 2, 4]) == pytest.approx(4 / 6)
+
+
+def test_split_by_pipeline_is_disjoint():
+    rows = [{"pipeline": f"dag{i % 10}"} for i in range(100)]
+    tr, te = learn.split_tags(rows, 0.2, seed=1)
+    assert not (tr & te) and len(te) == 2 and len(tr) == 8
