@@ -45,7 +45,10 @@ typedef enum {
     WT_E_INTERNAL = -7
 } wt_status;
 
-typedef enum { WT_F32 = 0, WT_F16 = 1 } wt_dtype;
+/* Element types.  WT_F32 images feed float stages; the integer types carry
+ * integer stages (exact integer arithmetic, saturated to the type's range).
+ * WT_F16 describes FP16 intermediates only (never a caller image). */
+typedef enum { WT_F32 = 0, WT_F16 = 1, WT_U8 = 2, WT_U16 = 3, WT_I16 = 4, WT_I32 = 5 } wt_dtype;
 
 typedef enum { WT_DOWN2 = 0, WT_UP2 = 1 } wt_resample_kind;
 
@@ -70,8 +73,13 @@ typedef struct wt_plan wt_plan;         /* opaque */
 wt_status wt_pipeline_create(wt_pipeline** out);
 void wt_pipeline_destroy(wt_pipeline* p);
 
-/* An input image with `channels` planes. */
+/* An input image with `channels` planes (WT_F32 elements). */
 wt_status wt_input(wt_pipeline* p, int channels, int* id);
+
+/* An input image of element type `dtype` (WT_F32, WT_U8, WT_U16, WT_I16 or
+ * WT_I32).  Integer inputs make integer stages possible downstream; float
+ * stages reading them see the values converted to FP32. */
+wt_status wt_input_typed(wt_pipeline* p, int channels, int dtype, int* id);
 
 /* Stencil stage, per channel (the paper's Stencil / Correlate stages, Fig. 2):
  *   S_c(x,y) = scale * sum_{j<kh, i<kw} weights[j*kw+i] * P_c(x+i-ax, y+j-ay)
@@ -79,6 +87,17 @@ wt_status wt_input(wt_pipeline* p, int channels, int* id);
  * copied.  Kernel sides 1..15. */
 wt_status wt_stencil(wt_pipeline* p, int src, int kw, int kh, int ax, int ay,
                      const double* weights, double scale, int* id);
+
+/* Integer stencil stage of type `out` (WT_U8, WT_U16, WT_I16, WT_I32) on an
+ * integer source, per channel:
+ *   acc = sum_{j<kh, i<kw} weights[j*kw+i] * P_c(x+i-ax, y+j-ay)   (exact)
+ *   S_c(x,y) = saturate_out(floor((acc + floor(divisor/2)) / divisor))
+ * i.e. division rounding halves up (for divisor 2^s: (acc + 2^(s-1)) >> s).
+ * Clamp-to-edge reads as for wt_stencil.  |weights| <= 32767,
+ * 1 <= divisor <= 2^24; a pipeline whose sums could leave the 32-bit range
+ * is refused with WT_E_UNSUPPORTED (GPU arithmetic is 32-bit and exact). */
+wt_status wt_stencil_int(wt_pipeline* p, int src, int kw, int kh, int ax, int ay,
+                         const int32_t* weights, int32_t divisor, int out, int* id);
 
 /* Pointwise stage (the paper's Function with a Case expression, Fig. 2).
  * `expr` is infix over s0..s{nsrc-1} (source i at the same channel; a
@@ -89,7 +108,17 @@ wt_status wt_stencil(wt_pipeline* p, int src, int kw, int kh, int ax, int ay,
 wt_status wt_pointwise(wt_pipeline* p, const int* srcs, int nsrc,
                        const char* expr, int out_channels, int* id);
 
-/* 2x resampling (scaled dependences, Section 5's alignment and scaling):
+/* Pointwise stage of element type `out`.  WT_F32 is wt_pointwise.  An
+ * integer `out` needs integer sources and an integer expression (integer
+ * constants; no /, sqrt or floor), evaluated exactly and saturated to the
+ * type's range; expressions whose intermediate values could leave the
+ * 32-bit range are refused with WT_E_UNSUPPORTED. */
+wt_status wt_pointwise_typed(wt_pipeline* p, const int* srcs, int nsrc, const char* expr,
+                             int out_channels, int out, int* id);
+
+/* 2x resampling (scaled dependences, Section 5's alignment and scaling);
+ * the result has the source's element type (WT_UP2 of an integer stage is
+ * refused: the expansion would need a rounding rule):
  *   WT_DOWN2: D(x,y) = P(2x,2y), domain ceil(W/2) x ceil(H/2);
  *   WT_UP2:   separable binomial expansion, even 2i -> (P(i-1)+6P(i)+P(i+1))/8,
  *             odd 2i+1 -> (P(i)+P(i+1))/2, to the next finer level's domain. */
@@ -168,7 +197,8 @@ int wt_plan_num_groups(const wt_plan* plan);
 
 /* Launch description of group `group`, for tools and tests that execute
  * the generated source themselves (e.g. a host emulator).  Buffers follow
- * the group's loaded/live-out order; *_half flags mark FP16 buffers. */
+ * the group's loaded/live-out order; *_half flags mark FP16 buffers and
+ * *_dtype give every buffer's element type. */
 typedef struct {
     int32_t resample;         /* 1: 2x resampling kernel (grid tiles_x x tiles_y x channels, 256 threads) */
     int32_t waves_per_group;  /* fused kernels: waves per workgroup                                  */
@@ -180,6 +210,7 @@ typedef struct {
     int32_t nloaded, nliveouts;
     int32_t loaded[16], liveouts[16];
     int32_t loaded_half[16], liveout_half[16];
+    int32_t loaded_dtype[16], liveout_dtype[16]; /* wt_dtype of each buffer  */
 } wt_group_info;
 wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out);
 
@@ -236,7 +267,9 @@ wt_status wt_group_features(const wt_pipeline* p, const int* nodes, int nnodes, 
  * microseconds, into times_us[i] (host array of n doubles; +inf when the
  * group cannot be built for this pipeline).  When $WT_MEASURE_DB names a
  * file, one JSON line per fused group is appended (tagged `tag`) with its
- * 40 model features.  Synchronous; allocates and frees its scratch. */
+ * 40 model features.  Synchronous; allocates and frees its scratch.
+ * reps == 0 compiles the groups into the code cache only (no device is
+ * touched; times_us[i] = 0 for buildable groups). */
 wt_status wt_measure_groups(const wt_pipeline* p, int width, int height, int fp16, int n,
                             const char* const* groups, int reps, const char* tag,
                             double* times_us);

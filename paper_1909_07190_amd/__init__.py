@@ -29,7 +29,9 @@ lib = ctypes.CDLL(LIB_PATH)
 
 SCHED = {"unfused": 0, "analytic": 1, "mlp": 2, "autotune": 3, "fixed": 4}
 DOWN2, UP2 = 0, 1
-F32, F16 = 0, 1
+F32, F16, U8, U16, I16, I32 = 0, 1, 2, 3, 4, 5
+# plain-data names of the element types
+DTYPES = {"f32": F32, "u8": U8, "u16": U16, "i16": I16, "i32": I32}
 PLAN_NO_DEVICE = 1
 PLAN_ANY_WIDTH = 2
 PLAN_NO_COMPILE = 4
@@ -61,6 +63,11 @@ _sig("wt_last_error", ctypes.c_char_p)
 _sig("wt_pipeline_create", ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
 _sig("wt_pipeline_destroy", None, ctypes.c_void_p)
 _sig("wt_input", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, _c_int_p)
+_sig("wt_input_typed", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p)
+_sig("wt_stencil_int", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int, _c_int_p)
+_sig("wt_pointwise_typed", ctypes.c_int, ctypes.c_void_p, _c_int_p, ctypes.c_int, ctypes.c_char_p,
+     ctypes.c_int, ctypes.c_int, _c_int_p)
 _sig("wt_stencil", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
      ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double, _c_int_p)
 _sig("wt_pointwise", ctypes.c_int, ctypes.c_void_p, _c_int_p, ctypes.c_int, ctypes.c_char_p,
@@ -109,10 +116,18 @@ class Pipeline:
             _destroy(self._h)
             self._h = None
 
-    def input(self, channels: int) -> int:
+    def input(self, channels: int, dtype: str = "f32") -> int:
         i = ctypes.c_int()
-        _check(lib.wt_input(self._h, channels, ctypes.byref(i)))
+        _check(lib.wt_input_typed(self._h, channels, DTYPES[dtype], ctypes.byref(i)))
         self.channels[i.value] = channels
+        return i.value
+
+    def stencil_int(self, src, kw, kh, ax, ay, weights, divisor, dtype) -> int:
+        w = (ctypes.c_int32 * (kw * kh))(*[int(v) for v in weights])
+        i = ctypes.c_int()
+        _check(lib.wt_stencil_int(self._h, src, kw, kh, ax, ay, w, int(divisor), DTYPES[dtype],
+                                  ctypes.byref(i)))
+        self.channels[i.value] = self.channels[src]
         return i.value
 
     def stencil(self, src, kw, kh, ax, ay, weights, scale=1.0) -> int:
@@ -122,10 +137,11 @@ class Pipeline:
         self.channels[i.value] = self.channels[src]
         return i.value
 
-    def pointwise(self, srcs, expr: str, channels: int) -> int:
+    def pointwise(self, srcs, expr: str, channels: int, dtype: str = "f32") -> int:
         arr = (ctypes.c_int * len(srcs))(*srcs)
         i = ctypes.c_int()
-        _check(lib.wt_pointwise(self._h, arr, len(srcs), expr.encode(), channels, ctypes.byref(i)))
+        _check(lib.wt_pointwise_typed(self._h, arr, len(srcs), expr.encode(), channels, DTYPES[dtype],
+                                      ctypes.byref(i)))
         self.channels[i.value] = channels
         return i.value
 
@@ -149,14 +165,18 @@ def from_spec(spec: dict) -> Pipeline:
     """Builds a Pipeline from a plain-data description (see synth.pipelines)."""
     p = Pipeline()
     for inp in spec["inputs"]:
-        p.names[inp["name"]] = p.input(inp["channels"])
+        p.names[inp["name"]] = p.input(inp["channels"], inp.get("dtype", "f32"))
     for st in spec["stages"]:
         k = st["kind"]
-        if k == "stencil":
+        dt = st.get("dtype", "f32")
+        if k == "stencil" and dt != "f32":
+            i = p.stencil_int(p.names[st["src"]], st["kw"], st["kh"], st["ax"], st["ay"],
+                              st["weights"], st.get("divisor", 1), dt)
+        elif k == "stencil":
             i = p.stencil(p.names[st["src"]], st["kw"], st["kh"], st["ax"], st["ay"],
                           st["weights"], st["scale"])
         elif k == "pointwise":
-            i = p.pointwise([p.names[s] for s in st["srcs"]], st["expr"], st["channels"])
+            i = p.pointwise([p.names[s] for s in st["srcs"]], st["expr"], st["channels"], dt)
         elif k in ("down2", "up2"):
             i = p.resample(p.names[st["src"]], DOWN2 if k == "down2" else UP2)
         else:
@@ -171,14 +191,15 @@ def _image(t) -> WtImage:
     import torch
     if not t.is_cuda:
         raise ValueError("images must be device tensors")
-    if t.dtype != torch.float32:
-        raise ValueError("images must be float32")
+    tmap = {torch.float32: F32, torch.uint8: U8, torch.uint16: U16, torch.int16: I16, torch.int32: I32}
+    if t.dtype not in tmap:
+        raise ValueError(f"unsupported image dtype {t.dtype}")
     if t.dim() == 2:
         t = t.unsqueeze(0)
     if t.dim() != 3 or t.stride(2) != 1:
         raise ValueError("images must be [C, H, W] with unit column stride")
     c, h, w = t.shape
-    return WtImage(t.data_ptr(), w, h, c, F32, t.stride(1), t.stride(0))
+    return WtImage(t.data_ptr(), w, h, c, tmap[t.dtype], t.stride(1), t.stride(0))
 
 
 class Plan:

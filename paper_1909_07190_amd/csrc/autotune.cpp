@@ -227,8 +227,11 @@ void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vecto
     plan.fp16 = fp16;
     const char* env_cache = std::getenv("WT_CACHE_DIR");
     plan.cache_dir = env_cache ? env_cache : "";
-    hip_check(hipGetDevice(&plan.device), "hipGetDevice");
-    plan.machine = machine_from_device(plan.device);
+    plan.no_device = reps == 0;  // compile only (fills the code cache)
+    if (!plan.no_device) {
+        hip_check(hipGetDevice(&plan.device), "hipGetDevice");
+        plan.machine = machine_from_device(plan.device);
+    }
     std::vector<GroupRt> trials(descs.size());
     std::vector<GroupRt*> ok;
     std::vector<size_t> idx;
@@ -247,6 +250,10 @@ void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vecto
         idx.push_back(i);
     }
     compile_groups(plan, ok);
+    if (plan.no_device) {
+        for (size_t i : idx) out_us[i] = 0.0;
+        return;
+    }
     DeviceScratch scr;
     std::map<int, ImgRef> mem;
     for (const Node& n : p.nodes) {

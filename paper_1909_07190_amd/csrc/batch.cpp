@@ -66,7 +66,7 @@ void check_batch_image(const wt_image& im, const Node& n, int W, int H, const st
     if (!im.data) fail(WT_E_INVALID, tag + ": null data");
     if (im.width != W || im.height != H) fail(WT_E_SHAPE, tag + ": size mismatch within the image's set");
     if (im.channels != n.channels) fail(WT_E_SHAPE, tag + ": wrong channel count");
-    if (im.dtype != WT_F32) fail(WT_E_UNSUPPORTED, tag + ": only WT_F32 images are supported");
+    if (im.dtype != n.dtype) fail(WT_E_SHAPE, tag + ": element type differs from the node's");
 }
 
 }  // namespace
@@ -129,7 +129,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
                     b.rs = (d.first + 63) / 64 * 64;
                     b.cs = b.rs * d.second;
                     b.ptr = reinterpret_cast<void*>(off);  // offset until the arena exists
-                    off += ((size_t)b.cs * p.nodes[id].channels * (b.half ? 2 : 4) + 255) / 256 * 256;
+                    off += ((size_t)b.cs * p.nodes[id].channels * node_esize(p, id, b.half) + 255) / 256 * 256;
                     bufs[i][id] = b;
                 }
         if (off) {

@@ -66,14 +66,87 @@ wt_status wt_pipeline_create(wt_pipeline** out) {
 
 void wt_pipeline_destroy(wt_pipeline* p) { delete p; }
 
-wt_status wt_input(wt_pipeline* p, int channels, int* id) {
+wt_status wt_input_typed(wt_pipeline* p, int channels, int dtype, int* id) {
     return guard([&] {
         if (!p || !id) wt::fail(WT_E_INVALID, "null argument");
         if (channels < 1 || channels > 16) wt::fail(WT_E_INVALID, "channels must be in 1..16");
+        if (dtype != WT_F32 && !wt::is_int_dtype(dtype)) wt::fail(WT_E_UNSUPPORTED, "input element type");
         wt::Node& n = new_node(p, wt::Kind::Input);
         n.channels = channels;
+        n.dtype = dtype;
         n.bound = 1.0;
+        if (n.is_int()) {
+            auto r = wt::dtype_range(dtype);
+            n.rlo = (double)r.first;
+            n.rhi = (double)r.second;
+            n.bound = std::max(std::fabs(n.rlo), std::fabs(n.rhi));
+        }
         p->p.inputs.push_back(n.id);
+        *id = n.id;
+    });
+}
+
+wt_status wt_input(wt_pipeline* p, int channels, int* id) { return wt_input_typed(p, channels, WT_F32, id); }
+
+namespace {
+// Integer values are exact in 32-bit registers below this magnitude.
+constexpr double kInt32Max = 2147483647.0;
+
+bool expr_is_integer(const wt::Expr& e) {
+    switch (e.op) {
+        case wt::Expr::Div: case wt::Expr::Sqrt: case wt::Expr::Floor: return false;
+        case wt::Expr::Const:
+            if (e.value != std::floor(e.value) || std::fabs(e.value) > 16777216.0) return false;
+            break;
+        default: break;
+    }
+    for (const auto& k : e.kids)
+        if (!expr_is_integer(k)) return false;
+    return true;
+}
+}  // namespace
+
+wt_status wt_stencil_int(wt_pipeline* p, int src, int kw, int kh, int ax, int ay, const int32_t* weights,
+                         int32_t divisor, int out, int* id) {
+    return guard([&] {
+        if (!p || !id || !weights) wt::fail(WT_E_INVALID, "null argument");
+        check_src(p, src);
+        if (kw < 1 || kw > 15 || kh < 1 || kh > 15) wt::fail(WT_E_INVALID, "stencil sides must be in 1..15");
+        if (ax < 0 || ax >= kw || ay < 0 || ay >= kh) wt::fail(WT_E_INVALID, "stencil anchor outside the kernel");
+        if (!wt::is_int_dtype(out)) wt::fail(WT_E_INVALID, "integer stencils produce an integer type");
+        if (divisor < 1 || divisor > (1 << 24)) wt::fail(WT_E_INVALID, "divisor must be in 1..2^24");
+        const wt::Node s = p->p.nodes[src];
+        if (!s.is_int()) wt::fail(WT_E_UNSUPPORTED, "integer stencils read integer stages");
+        double lo = 0, hi = 0, wsum = 0;
+        for (int i = 0; i < kw * kh; ++i) {
+            if (weights[i] < -32767 || weights[i] > 32767) wt::fail(WT_E_INVALID, "|weight| must be <= 32767");
+            double w = weights[i];
+            lo += std::min(w * s.rlo, w * s.rhi);
+            hi += std::max(w * s.rlo, w * s.rhi);
+            wsum += std::fabs(w);
+        }
+        (void)wsum;
+        double half = (double)(divisor / 2);
+        if (std::max(std::fabs(lo), std::fabs(hi)) + half > kInt32Max)
+            wt::fail(WT_E_UNSUPPORTED, "integer stencil sums may leave the 32-bit range");
+        wt::Node& n = new_node(p, wt::Kind::Stencil);
+        n.srcs = {src};
+        n.channels = s.channels;
+        n.level = s.level;
+        n.kw = kw;
+        n.kh = kh;
+        n.ax = ax;
+        n.ay = ay;
+        n.dtype = out;
+        n.iweights.assign(weights, weights + kw * kh);
+        n.weights.assign(weights, weights + kw * kh);
+        n.divisor = divisor;
+        n.scale = 1.0 / divisor;
+        auto r = wt::dtype_range(out);
+        n.rlo = std::max((double)r.first, std::floor((lo + half) / divisor));
+        n.rhi = std::min((double)r.second, std::floor((hi + half) / divisor));
+        if (n.rlo > n.rhi) n.rlo = n.rhi = std::min(std::max(0.0, (double)r.first), (double)r.second);
+        n.bound = std::max(std::fabs(n.rlo), std::fabs(n.rhi));
         *id = n.id;
     });
 }
@@ -108,7 +181,13 @@ wt_status wt_stencil(wt_pipeline* p, int src, int kw, int kh, int ax, int ay, co
 }
 
 wt_status wt_pointwise(wt_pipeline* p, const int* srcs, int nsrc, const char* expr, int out_channels, int* id) {
+    return wt_pointwise_typed(p, srcs, nsrc, expr, out_channels, WT_F32, id);
+}
+
+wt_status wt_pointwise_typed(wt_pipeline* p, const int* srcs, int nsrc, const char* expr, int out_channels, int out,
+                             int* id) {
     return guard([&] {
+        if (out != WT_F32 && !wt::is_int_dtype(out)) wt::fail(WT_E_UNSUPPORTED, "pointwise element type");
         if (!p || !id || !srcs || !expr) wt::fail(WT_E_INVALID, "null argument");
         if (nsrc < 1 || nsrc > 8) wt::fail(WT_E_INVALID, "pointwise stages take 1..8 sources");
         if (out_channels < 1 || out_channels > 16) wt::fail(WT_E_INVALID, "channels must be in 1..16");
@@ -138,13 +217,37 @@ wt_status wt_pointwise(wt_pipeline* p, const int* srcs, int nsrc, const char* ex
             for (const auto& k : x.kids) chk(k);
         };
         chk(e);
+        double rlo = 0, rhi = 0;
+        if (wt::is_int_dtype(out)) {
+            std::vector<wt::Interval> iv;
+            for (int i = 0; i < nsrc; ++i) {
+                const wt::Node& s = p->p.nodes[srcs[i]];
+                if (!s.is_int()) wt::fail(WT_E_UNSUPPORTED, "integer pointwise stages read integer stages only");
+                iv.push_back({s.rlo, s.rhi});
+            }
+            if (!expr_is_integer(e))
+                wt::fail(WT_E_UNSUPPORTED, "integer expressions take integer constants and no /, sqrt or floor");
+            double mx = 0;
+            wt::Interval r = wt::expr_range(e, iv, &mx);
+            if (!(mx <= kInt32Max)) wt::fail(WT_E_UNSUPPORTED, "integer expression may leave the 32-bit range");
+            auto tr = wt::dtype_range(out);
+            rlo = std::max((double)tr.first, r.lo);
+            rhi = std::min((double)tr.second, r.hi);
+            if (rlo > rhi) rlo = rhi = std::min(std::max(r.lo, (double)tr.first), (double)tr.second);
+        }
         wt::Node& n = new_node(p, wt::Kind::Pointwise);
         n.srcs.assign(srcs, srcs + nsrc);
         n.channels = out_channels;
         n.level = level;
         n.expr_text = expr;
         n.expr = std::move(e);
+        n.dtype = out;
         n.bound = wt::expr_bound(n.expr, bounds);
+        if (n.is_int()) {
+            n.rlo = rlo;
+            n.rhi = rhi;
+            n.bound = std::max(std::fabs(rlo), std::fabs(rhi));
+        }
         *id = n.id;
     });
 }
@@ -157,11 +260,15 @@ wt_status wt_resample(wt_pipeline* p, int src, int kind, int* id) {
         const wt::Node s = p->p.nodes[src];
         if (kind == WT_UP2 && s.level < 1) wt::fail(WT_E_INVALID, "up2 of a full-resolution node");
         if (kind == WT_DOWN2 && s.level >= 24) wt::fail(WT_E_INVALID, "too many decimations");
+        if (kind == WT_UP2 && s.is_int()) wt::fail(WT_E_UNSUPPORTED, "up2 of an integer stage");
         wt::Node& n = new_node(p, kind == WT_DOWN2 ? wt::Kind::Down2 : wt::Kind::Up2);
         n.srcs = {src};
         n.channels = s.channels;
         n.level = s.level + (kind == WT_DOWN2 ? 1 : -1);
         n.bound = s.bound;
+        n.dtype = s.dtype;
+        n.rlo = s.rlo;
+        n.rhi = s.rhi;
         *id = n.id;
     });
 }
@@ -247,10 +354,12 @@ wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out)
         for (size_t i = 0; i < g.loaded.size(); ++i) {
             out->loaded[i] = g.loaded[i];
             out->loaded_half[i] = g.mem_half_in[i];
+            out->loaded_dtype[i] = g.mem_half_in[i] ? WT_F16 : plan->impl->p.nodes[g.loaded[i]].dtype;
         }
         for (size_t i = 0; i < g.liveouts.size(); ++i) {
             out->liveouts[i] = g.liveouts[i];
             out->liveout_half[i] = g.mem_half_out[i];
+            out->liveout_dtype[i] = g.mem_half_out[i] ? WT_F16 : plan->impl->p.nodes[g.liveouts[i]].dtype;
         }
     });
 }
@@ -272,7 +381,7 @@ wt_status wt_measure_groups(const wt_pipeline* p, int width, int height, int fp1
                             const char* const* groups, int reps, const char* tag, double* times_us) {
     return guard([&] {
         if (!p || (n > 0 && (!groups || !times_us))) wt::fail(WT_E_INVALID, "null argument");
-        if (n < 0 || reps < 1 || reps > 100000) wt::fail(WT_E_INVALID, "bad count");
+        if (n < 0 || reps < 0 || reps > 100000) wt::fail(WT_E_INVALID, "bad count");
         if (width <= 0 || height <= 0 || width > (1 << 16) || height > (1 << 16))
             wt::fail(WT_E_SHAPE, "bad measurement size");
         std::vector<std::string> d;

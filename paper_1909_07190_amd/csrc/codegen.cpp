@@ -54,6 +54,33 @@ struct Gen {
     std::string I(int v) { return std::to_string(v); }
     void line(const std::string& s) { o << ind << s << "\n"; }
 
+    bool isint(int id) const { return P.nodes[id].is_int(); }
+    // register / LDS type of a node's values, and its element type in memory
+    std::string ctype(int id) const { return isint(id) ? "int" : "float"; }
+    std::string mtype(const NodeGeom& n) const {
+        return isint(n.id) ? dtype_ctype(P.nodes[n.id].dtype) : (n.mem_half ? "_Float16" : "float");
+    }
+    int msize(const NodeGeom& n) const { return isint(n.id) ? dtype_size(P.nodes[n.id].dtype) : (n.mem_half ? 2 : 4); }
+    // ext_vector type of V elements of C type `t`
+    static std::string vec(const std::string& t, int V) {
+        std::string b = t == "float" ? "wt_f" : t == "_Float16" ? "wt_h" : t == "int" ? "wt_i" :
+                        t == "unsigned char" ? "wt_b" : t == "unsigned short" ? "wt_us" : "wt_s";
+        return b + std::to_string(V);
+    }
+    // unsigned type of `bytes` bytes and the buffer store of that width
+    static std::string store_ty(int bytes) {
+        switch (bytes) {
+            case 1: return "unsigned char";
+            case 2: return "unsigned short";
+            case 4: return "unsigned int";
+            case 8: return "wt_u2";
+            default: return "wt_u4";
+        }
+    }
+    static std::string store_fn(int bytes) {
+        return "__builtin_amdgcn_raw_buffer_store_b" + std::to_string(bytes * 8);
+    }
+
     bool has_regs(const NodeGeom& n) const { return RX > 0 && (n.consumed || !n.member); }
     bool has_lds(const NodeGeom& n) const { return SX > 0 && (n.consumed || !n.member); }
     std::string reg(int id, int slot, int ch, int kr, int e) {
@@ -65,14 +92,14 @@ struct Gen {
         return "L" + I(id) + "[" + I((slot * n.nch + ch) * SX * SUB) + " + (" + j + ")]";
     }
     std::string lread(int id, int slot, int ch, const std::string& j) {
-        return "(float)" + lidx(id, slot, ch, j);
+        return "(" + ctype(id) + ")" + lidx(id, slot, ch, j);
     }
     std::string fresh(const std::string& pfx) { return pfx + I(tmp++); }
     std::string memoize(const std::string& expr) {
         auto it = memo.find(expr);
         if (it != memo.end()) return it->second;
         std::string n = fresh("t");
-        line("const float " + n + " = " + expr + ";");
+        line("const auto " + n + " = " + expr + ";");
         memo[expr] = n;
         return n;
     }
@@ -110,7 +137,7 @@ struct Gen {
                     return memoize("wt_shr1(" + cur + ", " + b + ")");
                 }
                 // lane 0 belongs to the overlap: any value
-                return memoize("wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(" + cur + "), WT_DPP_WAVE_SHR1, 0xF, 0xF, true))");
+                return memoize("wt_mov_shr1(" + cur + ")");
             }
             if (k - 1 >= SX) {
                 std::string prv = reg(p, slot, chp, k - 1 - SX, ep);
@@ -135,14 +162,13 @@ struct Gen {
             // last LDS sub-tile: lanes t >= 64-d read the first register sub-tile
             std::string nx = reg(p, slot, chp, 0, ep);
             std::string rot = d == 1 ? "wt_rol1(" + nx + ")"
-                                     : "wt_as_f(__builtin_amdgcn_ds_bpermute(((lane + " + I(d) +
-                                           ") & 63) << 2, wt_as_i(" + nx + ")))";
+                                     : "wt_bperm(((lane + " + I(d) + ") & 63) << 2, " + nx + ")";
             std::string rv = memoize(rot);
             return memoize("(lane >= " + I(64 - d) + " ? " + rv + " : " + lv + ")");
         }
         std::string cur = reg(p, slot, chp, k - SX, ep);
         if (k + 1 >= g.TX) {  // lanes past the strip belong to the overlap: any value
-            if (d == 1) return memoize("wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(" + cur + "), WT_DPP_WAVE_SHL1, 0xF, 0xF, true))");
+            if (d == 1) return memoize("wt_mov_shl1(" + cur + ")");
             if (d == 2) return memoize("wt_shift2n(" + cur + ", " + cur + ")");
             return memoize("wt_shiftdn(" + cur + ", " + cur + ", " + I(d) + ", lane)");
         }
@@ -159,12 +185,15 @@ struct Gen {
 
     std::string expr(const Expr& e, int c, int ch, int k, int el, int ph) {
         const Node& n = P.nodes[c];
+        const bool in = n.is_int();
         auto K = [&](int i) { return expr(e.kids[i], c, ch, k, el, ph); };
         switch (e.op) {
-            case Expr::Const: return flit(e.value);
+            case Expr::Const: return in ? "(" + std::to_string((long long)e.value) + ")" : flit(e.value);
             case Expr::Src: {
                 int p = n.srcs[e.src];
-                return read(c, p, src_chan(G(p), ch, e.chan), k, el, 0, 0, ph);
+                std::string r = read(c, p, src_chan(G(p), ch, e.chan), k, el, 0, 0, ph);
+                // a float stage sees integer values converted (exactly, in range)
+                return (!in && isint(p)) ? "(float)" + r : r;
             }
             case Expr::Neg: return "(-" + K(0) + ")";
             case Expr::Add: return "(" + K(0) + " + " + K(1) + ")";
@@ -175,9 +204,9 @@ struct Gen {
             case Expr::Le: return "(" + K(0) + " <= " + K(1) + ")";
             case Expr::Gt: return "(" + K(0) + " > " + K(1) + ")";
             case Expr::Ge: return "(" + K(0) + " >= " + K(1) + ")";
-            case Expr::Abs: return "fabsf(" + K(0) + ")";
-            case Expr::Min: return "fminf(" + K(0) + ", " + K(1) + ")";
-            case Expr::Max: return "fmaxf(" + K(0) + ", " + K(1) + ")";
+            case Expr::Abs: return (in ? "wt_abs(" : "fabsf(") + K(0) + ")";
+            case Expr::Min: return (in ? "wt_min(" : "fminf(") + K(0) + ", " + K(1) + ")";
+            case Expr::Max: return (in ? "wt_max(" : "fmaxf(") + K(0) + ", " + K(1) + ")";
             case Expr::Sqrt: return "sqrtf(" + K(0) + ")";
             case Expr::Floor: return "floorf(" + K(0) + ")";
             case Expr::Select: return "(" + K(0) + " ? " + K(1) + " : " + K(2) + ")";
@@ -187,9 +216,39 @@ struct Gen {
 
     std::string value(int c, int ch, int k, int e, int ph) {
         const Node& n = P.nodes[c];
-        if (n.kind == Kind::Pointwise) return expr(n.expr, c, ch, k, e, ph);
+        std::string sat;
+        if (n.is_int()) {
+            auto r = dtype_range(n.dtype);
+            sat = ", " + std::to_string(r.first) + ", " + std::to_string(r.second) + ")";
+            if (n.dtype == WT_I32) sat.clear();  // 32-bit values never leave the type
+        }
+        if (n.kind == Kind::Pointwise) {
+            std::string v = expr(n.expr, c, ch, k, e, ph);
+            return sat.empty() ? v : "wt_sat(" + v + sat;
+        }
         int p = n.srcs[0];
         int chp = src_chan(G(p), ch, -1);
+        if (n.is_int()) {
+            // exact integer sum, quotient rounded half up, saturation
+            std::string acc;
+            for (int j = 0; j < n.kh; ++j)
+                for (int i = 0; i < n.kw; ++i) {
+                    long long w = n.iweights[(size_t)j * n.kw + i];
+                    if (!w) continue;
+                    std::string r = read(c, p, chp, k, e, i - n.ax, j - n.ay, ph);
+                    std::string term = w == 1 ? r : "(" + std::to_string(w) + ") * " + r;
+                    acc = acc.empty() ? term : acc + " + " + term;
+                }
+            if (acc.empty()) acc = "0";
+            long long d = n.divisor;
+            std::string q = "(" + acc + ")";
+            if (d > 1) {
+                int sh = 0;
+                while ((1LL << sh) < d) ++sh;
+                q = (1LL << sh) == d ? "wt_rshift(" + q + ", " + I(sh) + ")" : "wt_rdiv(" + q + ", " + std::to_string(d) + ")";
+            }
+            return sat.empty() ? q : "wt_sat(" + q + sat;
+        }
         std::string acc;
         for (const Tap& t : P.taps(c, p)) {
             std::string r = read(c, p, chp, k, e, t.dx, t.dy, ph);
@@ -209,7 +268,7 @@ struct Gen {
 
     // ------------------------------------------------------------ loads --
     void emit_load(int li, const NodeGeom& n, int ph) {
-        std::string ty = n.mem_half ? "_Float16" : "float";
+        const std::string ty = mtype(n), ct = ctype(n.id);
         int slot = pmod(ph, n.win);
         for (int ch = 0; ch < n.nch; ++ch) {
             line("{  // load node " + I(n.id) + " channel slot " + I(ch) + ", row kk + " + I(n.lead));
@@ -227,25 +286,25 @@ struct Gen {
                     for (int e = 0; e < V; ++e) dst.push_back(reg(n.id, slot, ch, k - SX, e));
                 } else {
                     v = fresh("ld");
-                    line("float " + v + "[" + I(V) + "];");
+                    line(ct + " " + v + "[" + I(V) + "];");
                     for (int e = 0; e < V; ++e) dst.push_back(v + "[" + I(e) + "]");
                 }
                 std::string xb = "x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V);
                 line("{ const int xb = " + xb + ";");
                 if (!border) {
                     std::string ld0 = g.NT ? "__builtin_nontemporal_load(rp + xb)" : "rp[xb]";
-                    if (V == 1) line("  " + dst[0] + " = (float)" + ld0 + ";");
+                    if (V == 1) line("  " + dst[0] + " = (" + ct + ")" + ld0 + ";");
                     else {
-                        std::string vt = n.mem_half ? (V == 4 ? "wt_h4" : "wt_h2") : (V == 4 ? "wt_f4" : "wt_f2");
+                        std::string vt = vec(ty, V);
                         if (g.NT)
                             line("  const " + vt + " q = __builtin_nontemporal_load((const " + vt + "*)(rp + xb));");
                         else
                             line("  const " + vt + " q = *(const " + vt + "*)(rp + xb);");
-                        for (int e = 0; e < V; ++e) line("  " + dst[e] + " = (float)q[" + I(e) + "];");
+                        for (int e = 0; e < V; ++e) line("  " + dst[e] + " = (" + ct + ")q[" + I(e) + "];");
                     }
                 } else {
                     for (int e = 0; e < V; ++e)
-                        line("  " + dst[e] + " = (float)rp[wt_clampi(xb + " + I(e) + ", 0, W - 1)];");
+                        line("  " + dst[e] + " = (" + ct + ")rp[wt_clampi(xb + " + I(e) + ", 0, W - 1)];");
                 }
                 line("}");
                 if (k < SX) emit_lds_store(n, slot, ch, k, v);
@@ -270,7 +329,7 @@ struct Gen {
         } else {
             if (V == 1) line(base.substr(1) + " = " + arr + "[0];");
             else {
-                std::string vt = V == 4 ? "wt_f4" : "wt_f2";
+                std::string vt = vec(ctype(n.id), V);
                 std::string init;
                 for (int e = 0; e < V; ++e) init += (e ? ", " : "") + arr + "[" + I(e) + "]";
                 line("*(" + vt + "*)(" + base + ") = " + vt + "{" + init + "};");
@@ -286,13 +345,35 @@ struct Gen {
     void emit_store(int oi, const NodeGeom& n, int ch, int k, const std::string& arr, const std::string& R) {
         std::string rsrc = "S" + I(oi) + "_" + I(ch);
         const std::string aux = g.NT ? "WT_CPOL_NT" : "0";
-        int esz = n.mem_half ? 2 : 4;
+        int esz = msize(n);
         line("{ const int jb = " + I(k * SUB) + " + lane * " + I(V) + ";");
         line("  const int xp = x0 + " + I(n.skew) + " + jb;");
         line("  const bool ok = " + R + " >= y0 && " + R + " < kend && " + R + " < H && jb >= " + I(geo.S0) +
              " && jb < " + I(geo.S0 + geo.X) + ";");
         line("  const int ob = (int)(((long long)" + R + " * A.dst_rs[" + I(oi) + "] + xp) * " + I(esz) + ");");
-        if (!border) {
+        if (isint(n.id)) {
+            // integer live-out: values are already saturated to the type
+            const std::string mt = mtype(n);
+            if (!border) {
+                line("  const int off = ok ? ob : WT_OOB;");
+                std::string v;
+                if (V == 1) v = "(" + mt + ")" + arr + "[0]";
+                else {
+                    std::string vals;
+                    for (int e = 0; e < V; ++e) vals += (e ? ", " : "") + std::string("(") + mt + ")" + arr + "[" + I(e) + "]";
+                    v = vec(mt, V) + "{" + vals + "}";
+                }
+                line("  " + store_fn(V * esz) + "(__builtin_bit_cast(" + store_ty(V * esz) + ", " + v + "), " + rsrc +
+                     ", off, 0, " + aux + ");");
+            } else {
+                for (int e = 0; e < V; ++e) {
+                    line("  { const int off = (ok && xp + " + I(e) + " >= 0 && xp + " + I(e) + " < W) ? ob + " +
+                         I(e * esz) + " : WT_OOB;");
+                    line("    " + store_fn(esz) + "(__builtin_bit_cast(" + store_ty(esz) + ", (" + mt + ")" + arr + "[" +
+                         I(e) + "]), " + rsrc + ", off, 0, " + aux + "); }");
+                }
+            }
+        } else if (!border) {
             line("  const int off = ok ? ob : WT_OOB;");
             if (n.mem_half) {
                 std::string vals;
@@ -332,7 +413,7 @@ struct Gen {
         line("const int jw = W - 1 - x0 - " + I(n.skew) + ";");
         for (int ch = 0; ch < n.nch; ++ch) {
             std::string e0 = fresh("edge"), ew = fresh("edge");
-            line("float " + e0 + " = 0.f, " + ew + " = 0.f;");
+            line(ctype(n.id) + " " + e0 + " = 0, " + ew + " = 0;");
             for (int pass = 0; pass < 2; ++pass) {
                 std::string j = pass ? "jw" : "j0", dst = pass ? ew : e0;
                 line("if (" + j + " >= 0 && " + j + " < " + I(N) + ") {");
@@ -387,7 +468,7 @@ struct Gen {
         for (int ch = 0; ch < n.nch; ++ch) {
             for (int k = 0; k < g.TX; ++k) {
                 std::string arr = fresh("v");
-                line("float " + arr + "[" + I(V) + "];");
+                line(ctype(n.id) + " " + arr + "[" + I(V) + "];");
                 for (int e = 0; e < V; ++e) line(arr + "[" + I(e) + "] = " + value(n.id, ch, k, e, ph) + ";");
                 if (n.consumed) {
                     if (k >= SX) {
@@ -457,7 +538,7 @@ struct Gen {
         ind += "    ";
         for (auto& n : geo.nodes)
             if (has_regs(n))
-                line("float w" + I(n.id) + "[" + I(n.win) + "][" + I(n.nch) + "][" + I(RX) + "][" + I(V) + "] = {};");
+                line(ctype(n.id) + " w" + I(n.id) + "[" + I(n.win) + "][" + I(n.nch) + "][" + I(RX) + "][" + I(V) + "] = {};");
         for (int s = 0; s < geo.D; ++s) emit_step(s % geo.U, "y0 - " + I(geo.D - s), s, -1);
         if (geo.NMAIN > 0) {
             line("for (int it = 0; it < " + I(geo.NMAIN) + "; ++it) {");
@@ -516,8 +597,8 @@ struct Gen {
         line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
         for (auto& n : geo.nodes)
             if (has_lds(n))
-                line(std::string(n.half ? "_Float16" : "float") + "* L" + I(n.id) + " = (" +
-                     (n.half ? "_Float16" : "float") + "*)(lds + " + I(n.lds_off) + ");");
+                line(std::string(n.half ? "_Float16" : ctype(n.id)) + "* L" + I(n.id) + " = (" +
+                     (n.half ? "_Float16" : ctype(n.id)) + "*)(lds + " + I(n.lds_off) + ");");
     }
 
     // One wave tile `wid` of the image described by `A`.
@@ -535,12 +616,12 @@ struct Gen {
         // buffer resources for the live-outs, one per channel plane
         for (size_t oi = 0; oi < geo.liveouts.size(); ++oi) {
             const NodeGeom& n = G(geo.liveouts[oi]);
-            std::string ty = n.mem_half ? "_Float16" : "float";
+            std::string ty = mtype(n);
             for (int ch = 0; ch < n.nch; ++ch)
                 line("const __amdgpu_buffer_rsrc_t S" + I((int)oi) + "_" + I(ch) +
                      " = __builtin_amdgcn_make_buffer_rsrc((" + ty + "*)A.dst[" + I((int)oi) + "] + " +
                      chan_off(n.id, true, (int)oi, ch) + ", 0, (int)((long long)H * A.dst_rs[" + I((int)oi) +
-                     "] * " + I(n.mem_half ? 2 : 4) + "), WT_RSRC_W3);");
+                     "] * " + I(msize(n)) + "), WT_RSRC_W3);");
         }
         line("if (!bx) {");
         body(false);
@@ -614,8 +695,10 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const
 // blocks of all images.
 GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g, const std::string& kname,
                                       bool src_half, bool dst_half) {
-    const std::string st = src_half ? "_Float16" : "float", dt = dst_half ? "_Float16" : "float";
     const Node& n = p.nodes[g.nodes[0]];
+    const Node& sn = p.nodes[n.srcs[0]];
+    const std::string st = sn.is_int() ? dtype_ctype(sn.dtype) : src_half ? "_Float16" : "float";
+    const std::string dt = n.is_int() ? dtype_ctype(n.dtype) : dst_half ? "_Float16" : "float";
     std::ostringstream o;
     o << "static __device__ __forceinline__ void " << kname << "_body(const WtArgs& A, int bxi, int byi, int c) {\n";
     o << "    const int x = bxi * 64 + (threadIdx.x & 63);\n";
@@ -625,7 +708,8 @@ GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g, co
     o << "    " << dt << "* d = (" << dt << "*)A.dst[0] + (long long)c * A.dst_cs[0];\n";
     o << "    const long long rs = A.src_rs[0];\n";
     if (n.kind == Kind::Down2) {
-        o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")(float)s[(long long)(2 * y) * rs + 2 * x];\n";
+        o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")(" << (n.is_int() ? "int" : "float")
+          << ")s[(long long)(2 * y) * rs + 2 * x];\n";
     } else {
         o << "    const int Ws = A.Ws, Hs = A.Hs;\n";
         o << "    const int i = x >> 1, jr = y >> 1;\n";

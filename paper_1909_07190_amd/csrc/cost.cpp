@@ -193,7 +193,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
         if (stored) regs += (double)n.win * n.nch * RX * g.V;
         if (!n.member) {
             const Node& nd = p.nodes[n.id];
-            int esz = n.mem_half ? 2 : 4;
+            int esz = p.nodes[n.id].is_int() ? dtype_size(p.nodes[n.id].dtype) : (n.mem_half ? 2 : 4);
             int rows = std::max(0, steps - g.PF - n.first_step);
             double row_bytes = (double)geo.N * esz;
             load_bytes += rows * row_bytes * n.nch;
@@ -214,7 +214,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
         c.code_ops += (double)sp.valu_ops * n.nch * g.TX * g.V;
         useful += (double)g.TY * geo.X * n.nch;
         if (n.liveout) {
-            int esz = n.mem_half ? 2 : 4;
+            int esz = p.nodes[n.id].is_int() ? dtype_size(p.nodes[n.id].dtype) : (n.mem_half ? 2 : 4);
             store_bytes += (double)g.TY * geo.X * esz * n.nch;
             int ch = geo.chan_parallel ? 1 : p.nodes[n.id].channels;
             comp_bytes += (double)lw * lh * esz * (geo.chan_parallel ? p.nodes[n.id].channels : ch);
@@ -224,7 +224,8 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     tx_comp = 0;
     for (int l : geo.loaded) {
         const NodeGeom& n = geo.nodes[geo.index.at(l)];
-        tx_comp += std::ceil((double)lw * lh * (n.mem_half ? 2 : 4) * p.nodes[l].channels / tx_size);
+        int esz = p.nodes[l].is_int() ? dtype_size(p.nodes[l].dtype) : (n.mem_half ? 2 : 4);
+        tx_comp += std::ceil((double)lw * lh * esz * p.nodes[l].channels / tx_size);
     }
 
     Alg2In in;
@@ -259,7 +260,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     double row_in_flight = 0;
     for (int l : geo.loaded) {
         const NodeGeom& n = geo.nodes[geo.index.at(l)];
-        row_in_flight += (double)geo.N * (n.mem_half ? 2 : 4) * n.nch;
+        row_in_flight += (double)geo.N * (p.nodes[l].is_int() ? dtype_size(p.nodes[l].dtype) : (n.mem_half ? 2 : 4)) * n.nch;
     }
     double inflight = resident_waves * row_in_flight * (g.PF + 1);
     double need = m.hbm_bw * m.mem_latency_s;

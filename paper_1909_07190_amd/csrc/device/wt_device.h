@@ -14,6 +14,14 @@ typedef _Float16 wt_h2 __attribute__((ext_vector_type(2)));
 typedef _Float16 wt_h4 __attribute__((ext_vector_type(4)));
 typedef unsigned int wt_u2 __attribute__((ext_vector_type(2)));
 typedef unsigned int wt_u4 __attribute__((ext_vector_type(4)));
+typedef int wt_i2 __attribute__((ext_vector_type(2)));
+typedef int wt_i4 __attribute__((ext_vector_type(4)));
+typedef unsigned char wt_b2 __attribute__((ext_vector_type(2)));
+typedef unsigned char wt_b4 __attribute__((ext_vector_type(4)));
+typedef unsigned short wt_us2 __attribute__((ext_vector_type(2)));
+typedef unsigned short wt_us4 __attribute__((ext_vector_type(4)));
+typedef short wt_s2 __attribute__((ext_vector_type(2)));
+typedef short wt_s4 __attribute__((ext_vector_type(4)));
 
 // Buffer resource word 3 for raw (untyped, stride 0) buffers on GFX9/CDNA,
 // and an offset past any buffer this library describes (<= 2 GiB): stores
@@ -53,70 +61,87 @@ struct WtArgs {
 WT_DEV float wt_as_f(int v) { return __builtin_bit_cast(float, v); }
 WT_DEV int wt_as_i(float v) { return __builtin_bit_cast(int, v); }
 
+// Lane exchanges move 32-bit values: FP32 stage values or the exact 32-bit
+// integers of integer stages (T = float or int).
+template <typename T> WT_DEV int wt_bits(T v) { return __builtin_bit_cast(int, v); }
+template <typename T> WT_DEV T wt_unbits(int v) { return __builtin_bit_cast(T, v); }
+
 // Lane t receives cur from lane t-1; lane 0 keeps `old0` (its own value of
 // the second operand).  bound_ctrl off: the invalid source lane keeps old.
-WT_DEV float wt_shr1(float cur, float old0) {
-    return wt_as_f(__builtin_amdgcn_update_dpp(wt_as_i(old0), wt_as_i(cur),
-                                               WT_DPP_WAVE_SHR1, 0xF, 0xF, false));
+template <typename T> WT_DEV T wt_shr1(T cur, T old0) {
+    return wt_unbits<T>(__builtin_amdgcn_update_dpp(wt_bits(old0), wt_bits(cur),
+                                                     WT_DPP_WAVE_SHR1, 0xF, 0xF, false));
 }
 
 // Lane t receives v from lane (t-1) mod 64.
-WT_DEV float wt_ror1(float v) {
-    return wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(v), WT_DPP_WAVE_ROR1, 0xF, 0xF, false));
+template <typename T> WT_DEV T wt_ror1(T v) {
+    return wt_unbits<T>(__builtin_amdgcn_mov_dpp(wt_bits(v), WT_DPP_WAVE_ROR1, 0xF, 0xF, false));
 }
 
 // Types 3 + 4 for a one-lane shift: lanes 1..63 read `cur` of lane t-1 (same
 // sub-tile); lane 0 reads `prev` of lane 63 (previous sub-tile).
-WT_DEV float wt_shift1(float cur, float prev) { return wt_shr1(cur, wt_ror1(prev)); }
+template <typename T> WT_DEV T wt_shift1(T cur, T prev) { return wt_shr1(cur, wt_ror1(prev)); }
 
 // Mirror images for reads to the right: lane t receives cur from lane t+1;
 // lane 63 keeps `old63`.
-WT_DEV float wt_shl1(float cur, float old63) {
-    return wt_as_f(__builtin_amdgcn_update_dpp(wt_as_i(old63), wt_as_i(cur),
-                                               WT_DPP_WAVE_SHL1, 0xF, 0xF, false));
+template <typename T> WT_DEV T wt_shl1(T cur, T old63) {
+    return wt_unbits<T>(__builtin_amdgcn_update_dpp(wt_bits(old63), wt_bits(cur),
+                                                     WT_DPP_WAVE_SHL1, 0xF, 0xF, false));
 }
-WT_DEV float wt_rol1(float v) {
-    return wt_as_f(__builtin_amdgcn_mov_dpp(wt_as_i(v), WT_DPP_WAVE_ROL1, 0xF, 0xF, false));
+template <typename T> WT_DEV T wt_rol1(T v) {
+    return wt_unbits<T>(__builtin_amdgcn_mov_dpp(wt_bits(v), WT_DPP_WAVE_ROL1, 0xF, 0xF, false));
+}
+// One-lane shifts where the lane past the end may take any value (it lies in
+// the tile's overlap): bound_ctrl on, a single DPP move.
+template <typename T> WT_DEV T wt_mov_shr1(T v) {
+    return wt_unbits<T>(__builtin_amdgcn_mov_dpp(wt_bits(v), WT_DPP_WAVE_SHR1, 0xF, 0xF, true));
+}
+template <typename T> WT_DEV T wt_mov_shl1(T v) {
+    return wt_unbits<T>(__builtin_amdgcn_mov_dpp(wt_bits(v), WT_DPP_WAVE_SHL1, 0xF, 0xF, true));
+}
+// Value of v in lane (byte address addr) / 4, through the LDS crossbar.
+template <typename T> WT_DEV T wt_bperm(int addr, T v) {
+    return wt_unbits<T>(__builtin_amdgcn_ds_bpermute(addr, wt_bits(v)));
 }
 // Lanes 0..62 read cur of lane t+1; lane 63 reads `next` of lane 0 (next sub-tile).
-WT_DEV float wt_shift1n(float cur, float next) { return wt_shl1(cur, wt_rol1(next)); }
+template <typename T> WT_DEV T wt_shift1n(T cur, T next) { return wt_shl1(cur, wt_rol1(next)); }
 // Lanes t < 64-d read cur of lane t+d; lanes t >= 64-d read next of lane t+d-64.
-WT_DEV float wt_shiftdn(float cur, float next, int d, int lane) {
+template <typename T> WT_DEV T wt_shiftdn(T cur, T next, int d, int lane) {
     int a = ((lane + d) & 63) << 2;
-    float c = wt_as_f(__builtin_amdgcn_ds_bpermute(a, wt_as_i(cur)));
-    float n = wt_as_f(__builtin_amdgcn_ds_bpermute(a, wt_as_i(next)));
+    T c = wt_bperm(a, cur);
+    T n = wt_bperm(a, next);
     return lane < 64 - d ? c : n;
 }
 
 // Two-lane shifts composed from one-lane DPP shifts (no LDS crossbar):
 // lanes 2..63 read cur of lane t-2, lanes 0..1 read prev of lanes 62..63.
-WT_DEV float wt_shift2(float cur, float prev) {
+template <typename T> WT_DEV T wt_shift2(T cur, T prev) {
     return wt_shift1(wt_shift1(cur, prev), wt_shift1(prev, prev));
 }
 // Mirror image: lanes 0..61 read cur of lane t+2, lanes 62..63 next of lanes 0..1.
-WT_DEV float wt_shift2n(float cur, float next) {
+template <typename T> WT_DEV T wt_shift2n(T cur, T next) {
     return wt_shift1n(wt_shift1n(cur, next), wt_shift1n(next, next));
 }
 
 // Types 3 + 4 for a d-lane shift, 1 <= d <= 63: lanes t >= d read cur of lane
 // t-d, lanes t < d read prev of lane 64+t-d.
-WT_DEV float wt_shiftd(float cur, float prev, int d, int lane) {
+template <typename T> WT_DEV T wt_shiftd(T cur, T prev, int d, int lane) {
     int a = ((lane - d) & 63) << 2;
-    float c = wt_as_f(__builtin_amdgcn_ds_bpermute(a, wt_as_i(cur)));
-    float p = wt_as_f(__builtin_amdgcn_ds_bpermute(a, wt_as_i(prev)));
+    T c = wt_bperm(a, cur);
+    T p = wt_bperm(a, prev);
     return lane >= d ? c : p;
 }
 
 // As wt_shiftd, with lanes t < d taking `prev_here`, a value each such lane
 // already holds (read from the LDS sub-tile: load type 2).
-WT_DEV float wt_shiftd_l(float cur, float prev_here, int d, int lane) {
-    float c = wt_as_f(__builtin_amdgcn_ds_bpermute(((lane - d) & 63) << 2, wt_as_i(cur)));
+template <typename T> WT_DEV T wt_shiftd_l(T cur, T prev_here, int d, int lane) {
+    T c = wt_bperm(((lane - d) & 63) << 2, cur);
     return lane >= d ? c : prev_here;
 }
 
 // Value of v in lane `src` (wave-uniform), broadcast.
-WT_DEV float wt_readlane(float v, int src) {
-    return wt_as_f(__builtin_amdgcn_readlane(wt_as_i(v), src));
+template <typename T> WT_DEV T wt_readlane(T v, int src) {
+    return wt_unbits<T>(__builtin_amdgcn_readlane(wt_bits(v), src));
 }
 
 // Orders this wave's LDS accesses across lanes: the hardware executes one
@@ -132,3 +157,20 @@ WT_DEV void wt_wave_sync() {
 WT_DEV float wt_h(float v) { return (float)(_Float16)v; }
 
 WT_DEV int wt_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Integer stage arithmetic (exact in 32 bits: the library bounds every sum).
+// Quotient rounded half up: floor((a + d/2) / d) for d >= 1.
+WT_DEV int wt_rdiv(int a, int d) {
+    int n = a + (d >> 1);
+    int q = n / d;
+    return (n % d != 0 && n < 0) ? q - 1 : q;
+}
+// Same for d = 2^s, s >= 1: arithmetic shift floors.
+WT_DEV int wt_rshift(int a, int s) { return (a + (1 << (s - 1))) >> s; }
+WT_DEV int wt_sat(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+WT_DEV int wt_abs(int v) { return v < 0 ? -v : v; }
+WT_DEV float wt_abs(float v) { return fabsf(v); }
+WT_DEV int wt_min(int a, int b) { return a < b ? a : b; }
+WT_DEV float wt_min(float a, float b) { return fminf(a, b); }
+WT_DEV int wt_max(int a, int b) { return a > b ? a : b; }
+WT_DEV float wt_max(float a, float b) { return fmaxf(a, b); }

@@ -1,6 +1,7 @@
 // Pipeline IR: stage DAG, dependence offsets and the pointwise expression
 // language (the paper, Section 2.2 "PolyMage DSL" and Section 2.3
 // "Dependence Vectors").
+#include <algorithm>
 #include <cctype>
 #include <cmath>
 #include <sstream>
@@ -191,6 +192,69 @@ double expr_bound(const Expr& e, const std::vector<double>& sb) {
         case Expr::Sqrt: return std::sqrt(k(0));
         default: return 1.0;  // comparisons
     }
+}
+
+bool is_int_dtype(int dt) { return dt == WT_U8 || dt == WT_U16 || dt == WT_I16 || dt == WT_I32; }
+
+int dtype_size(int dt) {
+    switch (dt) {
+        case WT_U8: return 1;
+        case WT_U16: case WT_I16: case WT_F16: return 2;
+        default: return 4;
+    }
+}
+
+std::pair<long long, long long> dtype_range(int dt) {
+    switch (dt) {
+        case WT_U8: return {0, 255};
+        case WT_U16: return {0, 65535};
+        case WT_I16: return {-32768, 32767};
+        case WT_I32: return {-2147483648LL, 2147483647LL};
+        default: fail(WT_E_INTERNAL, "dtype_range of a float type");
+    }
+}
+
+const char* dtype_ctype(int dt) {
+    switch (dt) {
+        case WT_U8: return "unsigned char";
+        case WT_U16: return "unsigned short";
+        case WT_I16: return "short";
+        case WT_I32: return "int";
+        case WT_F16: return "_Float16";
+        default: return "float";
+    }
+}
+
+// Interval arithmetic over the expression tree; comparisons yield [0, 1].
+Interval expr_range(const Expr& e, const std::vector<Interval>& sr, double* max_abs) {
+    auto k = [&](int i) { return expr_range(e.kids[i], sr, max_abs); };
+    Interval r{0, 0};
+    switch (e.op) {
+        case Expr::Const: r = {e.value, e.value}; break;
+        case Expr::Src: r = sr[e.src]; break;
+        case Expr::Neg: { Interval a = k(0); r = {-a.hi, -a.lo}; break; }
+        case Expr::Abs: {
+            Interval a = k(0);
+            double m = std::max(std::fabs(a.lo), std::fabs(a.hi));
+            r = {(a.lo <= 0 && a.hi >= 0) ? 0.0 : std::min(std::fabs(a.lo), std::fabs(a.hi)), m};
+            break;
+        }
+        case Expr::Add: { Interval a = k(0), b = k(1); r = {a.lo + b.lo, a.hi + b.hi}; break; }
+        case Expr::Sub: { Interval a = k(0), b = k(1); r = {a.lo - b.hi, a.hi - b.lo}; break; }
+        case Expr::Mul: {
+            Interval a = k(0), b = k(1);
+            double c[4] = {a.lo * b.lo, a.lo * b.hi, a.hi * b.lo, a.hi * b.hi};
+            r = {*std::min_element(c, c + 4), *std::max_element(c, c + 4)};
+            break;
+        }
+        case Expr::Min: { Interval a = k(0), b = k(1); r = {std::min(a.lo, b.lo), std::min(a.hi, b.hi)}; break; }
+        case Expr::Max: { Interval a = k(0), b = k(1); r = {std::max(a.lo, b.lo), std::max(a.hi, b.hi)}; break; }
+        case Expr::Select: { k(0); Interval a = k(1), b = k(2); r = {std::min(a.lo, b.lo), std::max(a.hi, b.hi)}; break; }
+        case Expr::Lt: case Expr::Le: case Expr::Gt: case Expr::Ge: k(0); k(1); r = {0, 1}; break;
+        default: r = {-INFINITY, INFINITY}; break;  // division, sqrt, floor: not integer operations
+    }
+    if (max_abs) *max_abs = std::max(*max_abs, std::max(std::fabs(r.lo), std::fabs(r.hi)));
+    return r;
 }
 
 bool expr_has_explicit_channel(const Expr& e) {

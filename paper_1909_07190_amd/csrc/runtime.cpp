@@ -115,7 +115,9 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     auto d = level_dims(plan.W, plan.H, lvl);
     gr.W = d.first;
     gr.H = d.second;
-    auto half_mem = [&](int id) { return plan.fp16 && p.nodes[id].kind != Kind::Input && !p.is_output(id); };
+    auto half_mem = [&](int id) {
+        return plan.fp16 && p.nodes[id].kind != Kind::Input && !p.is_output(id) && !p.nodes[id].is_int();
+    };
     gr.mem_half_in.clear();
     gr.mem_half_out.clear();
     if (gr.resample) {
@@ -237,7 +239,7 @@ void build_groups(Plan& plan) {
             b.half = gr.mem_half_out[i];
             b.rs = round_up64(d.first, 64);
             b.cs = b.rs * d.second;
-            size_t bytes = (size_t)b.cs * p.nodes[id].channels * (b.half ? 2 : 4);
+            size_t bytes = (size_t)b.cs * p.nodes[id].channels * node_esize(p, id, b.half);
             hipError_t e = hipMalloc(&b.ptr, std::max<size_t>(bytes, 256));
             if (e != hipSuccess) fail(WT_E_NOMEM, "hipMalloc of an intermediate buffer failed");
             plan.bufs[id] = b;
@@ -256,7 +258,9 @@ ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const char* 
     if (im.channels != n.channels)
         fail(WT_E_SHAPE, tag + ": " + std::to_string(im.channels) + " channels, expected " +
                              std::to_string(n.channels));
-    if (im.dtype != WT_F32) fail(WT_E_UNSUPPORTED, tag + ": only WT_F32 images are supported");
+    if (im.dtype != n.dtype)
+        fail(WT_E_SHAPE, tag + ": element type " + std::to_string(im.dtype) + ", the node's is " +
+                             std::to_string(n.dtype));
     ImgRef r;
     r.ptr = im.data;
     r.rs = im.row_stride ? im.row_stride : im.width;
@@ -267,9 +271,9 @@ ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const char* 
     return r;
 }
 
-void check_align(const ImgRef& r, int V, const std::string& tag) {
+void check_align(const ImgRef& r, int V, int esize, const std::string& tag) {
     if (V == 1) return;
-    if ((reinterpret_cast<uintptr_t>(r.ptr) % (4 * V)) || (r.rs % V) || (r.cs % V))
+    if ((reinterpret_cast<uintptr_t>(r.ptr) % (esize * V)) || (r.rs % V) || (r.cs % V))
         fail(WT_E_SHAPE, tag + ": buffer or strides not aligned to " + std::to_string(V) +
                              " elements as the plan's vector width requires");
 }
@@ -305,7 +309,7 @@ void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>&
     for (size_t i = 0; i < gr.loaded.size(); ++i) {
         const ImgRef& r = mem.at(gr.loaded[i]);
         if (!gr.resample && p.nodes[gr.loaded[i]].kind == Kind::Input)
-            check_align(r, gr.g.V, tag + " input node " + std::to_string(gr.loaded[i]));
+            check_align(r, gr.g.V, node_esize(p, gr.loaded[i], false), tag + " input node " + std::to_string(gr.loaded[i]));
         a.src[i] = r.ptr;
         a.src_rs[i] = r.rs;
         a.src_cs[i] = r.cs;
@@ -313,7 +317,7 @@ void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>&
     for (size_t i = 0; i < gr.liveouts.size(); ++i) {
         const ImgRef& r = mem.at(gr.liveouts[i]);
         if (!gr.resample && p.is_output(gr.liveouts[i]))
-            check_align(r, gr.g.V, tag + " output node " + std::to_string(gr.liveouts[i]));
+            check_align(r, gr.g.V, node_esize(p, gr.liveouts[i], false), tag + " output node " + std::to_string(gr.liveouts[i]));
         a.dst[i] = const_cast<void*>(r.ptr);
         a.dst_rs[i] = r.rs;
         a.dst_cs[i] = r.cs;
@@ -325,7 +329,7 @@ void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRe
     WtArgsHost a;
     fill_args(plan, gr, mem, a, "");
     for (size_t i = 0; i < gr.liveouts.size(); ++i)
-        if ((double)a.dst_rs[i] * gr.H * (gr.mem_half_out[i] ? 2 : 4) >= 2147483647.0)
+        if ((double)a.dst_rs[i] * gr.H * node_esize(plan.p, gr.liveouts[i], gr.mem_half_out[i]) >= 2147483647.0)
             fail(WT_E_UNSUPPORTED, "an output plane of 2 GiB or more");
     a.W = gr.W;
     a.H = gr.H;

@@ -41,6 +41,17 @@ int expr_max_channel(const Expr& e, int src);
 
 enum class Kind { Input, Stencil, Pointwise, Down2, Up2 };
 
+// Element types (wt_dtype): integer stages compute exactly in 32-bit
+// integers and saturate to their type's range.
+bool is_int_dtype(int dt);
+int dtype_size(int dt);                        // bytes per element in memory
+std::pair<long long, long long> dtype_range(int dt);
+const char* dtype_ctype(int dt);               // C type of one element
+// Interval [lo, hi] of an expression over sources in the given intervals,
+// and the largest magnitude any subexpression can take.
+struct Interval { double lo, hi; };
+Interval expr_range(const Expr& e, const std::vector<Interval>& srcs, double* max_abs);
+
 struct Tap { int dx, dy; double w; };
 
 struct Node {
@@ -57,6 +68,12 @@ struct Node {
     std::string expr_text;
     Expr expr;
     double bound = 1.0;          // magnitude bound (inputs assumed in [-1, 1])
+    // element type; integer stencils use integer weights and a divisor
+    int dtype = WT_F32;
+    std::vector<long long> iweights;
+    long long divisor = 1;
+    double rlo = 0, rhi = 0;     // integer stages: value interval (after saturation)
+    bool is_int() const { return is_int_dtype(dtype); }
 };
 
 struct Pipeline {

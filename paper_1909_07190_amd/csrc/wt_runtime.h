@@ -90,6 +90,11 @@ struct ImgRef {
 };
 
 void hip_check(hipError_t e, const char* what);
+// Bytes per element of node `id`'s images in memory (`half`: FP16 storage of
+// a float intermediate).
+inline int node_esize(const Pipeline& p, int id, bool half) {
+    return p.nodes[id].is_int() ? dtype_size(p.nodes[id].dtype) : (half ? 2 : 4);
+}
 std::pair<int, int> level_dims(int W, int H, int level);
 void prepare_group(const Plan& plan, GroupRt& gr, int gi);
 void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch = false);

@@ -116,13 +116,16 @@ def _parse_groups(describe_text):
 # ------------------------------------------------------------------ collect --
 
 def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_groups=6,
-            reps=20, seed=0, log=print):
+            reps=20, seed=0, log=print, compile_only=False):
     """Times candidate groups of every pipeline in `specs` (dict tag -> spec);
-    appends to the database `db` (JSON lines)."""
-    os.environ["WT_MEASURE_DB"] = db
-    rng = random.Random(seed)
+    appends to the database `db` (JSON lines).  The candidates of a pipeline
+    depend only on (seed, tag), so `compile_only` can fill the code cache on a
+    machine without a device ahead of the timing run."""
+    if not compile_only:
+        os.environ["WT_MEASURE_DB"] = db
     n_total = 0
     for tag, spec in specs.items():
+        rng = random.Random(f"{seed}:{tag}")
         t0 = time.time()
         pipe = from_spec(spec)
         dag = Dag(spec, pipe)
@@ -150,11 +153,11 @@ def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_grou
                 if c not in seen:
                     seen.add(c)
                     texts.append(c)
-        times = measure_groups(pipe, texts, width, height, reps=reps, tag=tag)
+        times = measure_groups(pipe, texts, width, height, reps=0 if compile_only else reps, tag=tag)
         n_total += len(texts)
         ok = sum(1 for t in times if math.isfinite(t))
-        log(f"collect {tag}: {len(spec['stages'])} stages, {len(texts)} candidates ({ok} timed), "
-            f"{time.time() - t0:.1f} s, {n_total} so far")
+        log(f"{'compile' if compile_only else 'collect'} {tag}: {len(spec['stages'])} stages, "
+            f"{len(texts)} candidates ({ok} built), {time.time() - t0:.1f} s, {n_total} so far")
     return n_total
 
 
@@ -382,6 +385,8 @@ def main(argv=None):
     c.add_argument("--configs", type=int, default=4)
     c.add_argument("--random-groups", type=int, default=6)
     c.add_argument("--size", type=int, default=2048)
+    c.add_argument("--compile-only", action="store_true",
+                   help="only compile the candidates into $WT_CACHE_DIR (no device needed)")
     t = sub.add_parser("train", help="train the network on the device")
     t.add_argument("--db", required=True, nargs="+")
     t.add_argument("--model", required=True)
@@ -403,7 +408,8 @@ def main(argv=None):
 
     if a.cmd == "collect":
         specs = {f"dag{s}": dags.random_dag(s) for s in _seeds(a.seeds)}
-        collect(specs, a.db, a.size, a.size, a.configs, a.random_groups, log=log)
+        collect(specs, a.db, a.size, a.size, a.configs, a.random_groups, log=log,
+                compile_only=a.compile_only)
     elif a.cmd == "train":
         rows = load_db(a.db)
         tr, te = split_tags(rows)

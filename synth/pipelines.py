@@ -15,6 +15,12 @@ Stage kinds:
   ``channels`` (output channel count).
 * ``down2`` / ``up2`` -- ``src``; 2x decimation / 2x expansion.
 
+Element types: an input or a stencil / pointwise stage may carry ``dtype``
+(``"f32"`` by default, or ``"u8"``, ``"u16"``, ``"i16"``, ``"i32"``); an
+integer stencil has integer ``weights`` and a positive integer ``divisor``
+(its result is the sum divided by ``divisor``, halves rounded up, saturated
+to the type).
+
 Every stage's domain is its image size; producer reads outside the domain
 take the value at the nearest edge point (clamp to edge, per stage).
 """
@@ -125,3 +131,48 @@ def pyramid_blend(levels: int = 4) -> dict:
     return {"inputs": [{"name": "A", "channels": 1}, {"name": "B", "channels": 1},
                        {"name": "M", "channels": 1}],
             "stages": st, "outputs": ["R0"]}
+
+
+def _istencil(name, src, kw, kh, ax, ay, weights, divisor, dtype):
+    return {"name": name, "kind": "stencil", "src": src, "kw": kw, "kh": kh,
+            "ax": ax, "ay": ay, "weights": [int(w) for w in weights],
+            "divisor": int(divisor), "dtype": dtype, "scale": 1.0 / divisor}
+
+
+def binomial_u8(channels: int = 1) -> dict:
+    """Separable 5-tap binomial blur on 8-bit images: (sum [1,4,6,4,1] x + 8) >> 4
+    per pass, the integer counterpart of the Gaussian blur."""
+    return {"inputs": [{"name": "img", "channels": channels, "dtype": "u8"}],
+            "stages": [_istencil("bx", "img", 5, 1, 2, 0, [1, 4, 6, 4, 1], 16, "u8"),
+                       _istencil("by", "bx", 1, 5, 0, 2, [1, 4, 6, 4, 1], 16, "u8")],
+            "outputs": ["by"]}
+
+
+def integer_unsharp(channels: int = 1) -> dict:
+    """8-bit unsharp mask: binomial blur, signed 16-bit detail, sharpened
+    result saturated back to 8 bits; the detail is an output too."""
+    return {"inputs": [{"name": "img", "channels": channels, "dtype": "u8"}],
+            "stages": [_istencil("bx", "img", 5, 1, 2, 0, [1, 4, 6, 4, 1], 16, "u8"),
+                       _istencil("by", "bx", 1, 5, 0, 2, [1, 4, 6, 4, 1], 16, "u8"),
+                       {"name": "detail", "kind": "pointwise", "srcs": ["img", "by"],
+                        "expr": "s0 - s1", "channels": channels, "dtype": "i16"},
+                       {"name": "sharp", "kind": "pointwise", "srcs": ["img", "detail"],
+                        "expr": "s0 + 2 * s1", "channels": channels, "dtype": "u8"}],
+            "outputs": ["sharp", "detail"]}
+
+
+def integer_gradient() -> dict:
+    """16-bit image: Sobel gradients in i32, L1 magnitude saturated to u16, a
+    box-filtered i16 response with a non-power-of-two divisor, a decimated
+    copy, and a float stage reading integers."""
+    return {"inputs": [{"name": "img", "channels": 1, "dtype": "u16"}],
+            "stages": [_istencil("gx", "img", 3, 3, 1, 1, [-1, 0, 1, -2, 0, 2, -1, 0, 1], 1, "i32"),
+                       _istencil("gy", "img", 3, 3, 1, 1, [-1, -2, -1, 0, 0, 0, 1, 2, 1], 1, "i32"),
+                       {"name": "mag", "kind": "pointwise", "srcs": ["gx", "gy"],
+                        "expr": "abs(s0) + abs(s1)", "channels": 1, "dtype": "u16"},
+                       _istencil("box", "gx", 3, 3, 1, 1, [1] * 9, 9, "i16"),
+                       {"name": "small", "kind": "down2", "src": "mag"},
+                       {"name": "f", "kind": "stencil", "src": "small", "kw": 3, "kh": 1, "ax": 1, "ay": 0,
+                        "weights": [1.0, 2.0, 1.0], "scale": 0.25}],
+            "outputs": ["mag", "box", "f"]}
+

@@ -66,6 +66,7 @@ template <class T>
 static inline void wt_emu_bstore(T v, wt_emu_rsrc r, int off) {
     if ((uint64_t)(uint32_t)off + sizeof(T) <= r.num) std::memcpy(r.base + (uint32_t)off, &v, sizeof(T));
 }
+#define __builtin_amdgcn_raw_buffer_store_b8(v, r, o, so, aux) wt_emu_bstore((v), (r), (o))
 #define __builtin_amdgcn_raw_buffer_store_b16(v, r, o, so, aux) wt_emu_bstore((v), (r), (o))
 #define __builtin_amdgcn_raw_buffer_store_b32(v, r, o, so, aux) wt_emu_bstore((v), (r), (o))
 #define __builtin_amdgcn_raw_buffer_store_b64(v, r, o, so, aux) wt_emu_bstore((v), (r), (o))

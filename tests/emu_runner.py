@@ -21,7 +21,8 @@ class GroupInfo(ctypes.Structure):
                 ("resample", "waves_per_group", "nwaves", "tiles_x", "tiles_y", "width", "height",
                  "src_width", "src_height", "channels", "nloaded", "nliveouts")] + \
                [("loaded", ctypes.c_int32 * 16), ("liveouts", ctypes.c_int32 * 16),
-                ("loaded_half", ctypes.c_int32 * 16), ("liveout_half", ctypes.c_int32 * 16)]
+                ("loaded_half", ctypes.c_int32 * 16), ("liveout_half", ctypes.c_int32 * 16),
+                ("loaded_dtype", ctypes.c_int32 * 16), ("liveout_dtype", ctypes.c_int32 * 16)]
 
 
 class Args(ctypes.Structure):
@@ -128,6 +129,21 @@ def _meta(spec):
     return names, lv, ch
 
 
+NP_DTYPE = {0: np.float32, 1: np.float16, 2: np.uint8, 3: np.uint16, 4: np.int16, 5: np.int32}
+SPEC_NP = {"f32": np.float32, "u8": np.uint8, "u16": np.uint16, "i16": np.int16, "i32": np.int32}
+
+
+def _blank(shape, code):
+    t = NP_DTYPE[code]
+    if np.issubdtype(t, np.floating):
+        return np.full(shape, np.nan, dtype=t)
+    return np.full(shape, 0x5A, dtype=t)  # a value kernels must overwrite
+
+
+def _result(b):
+    return b.astype(np.int64) if np.issubdtype(b.dtype, np.integer) else b.astype(np.float32)
+
+
 def emulate(spec, inputs, **plan_kw):
     """Runs `spec` through the generated kernels on the CPU; returns the outputs."""
     names, lv, ch = _meta(spec)
@@ -136,11 +152,11 @@ def emulate(spec, inputs, **plan_kw):
     plan = wt.from_spec(spec).plan(w, h, no_device=True, **plan_kw)
     bufs = {}  # node id -> array
 
-    def buf(node_id, half):
+    def buf(node_id, code):
         if node_id not in bufs:
             nm = names[node_id]
             bw, bh = oracle.level_size(w, h, lv[nm])
-            bufs[node_id] = np.full((ch[nm], bh, bw), np.nan, dtype=np.float16 if half else np.float32)
+            bufs[node_id] = _blank((ch[nm], bh, bw), code)
         return bufs[node_id]
 
     import concurrent.futures as cf
@@ -149,18 +165,19 @@ def emulate(spec, inputs, **plan_kw):
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         libs = list(ex.map(lambda a: _compile(*a), zip(srcs, knames)))
     for i, inp in enumerate(spec["inputs"]):
-        bufs[i] = np.ascontiguousarray(inputs[inp["name"]], dtype=np.float32).reshape(ch[inp["name"]], h, w)
+        t = SPEC_NP[inp.get("dtype", "f32")]
+        bufs[i] = np.ascontiguousarray(inputs[inp["name"]]).astype(t).reshape(ch[inp["name"]], h, w)
     for g in range(plan.num_groups):
         gi = GroupInfo()
         wt._check(wt.lib.wt_plan_group_info(plan._h, g, ctypes.byref(gi)))
         lib = libs[g]
         a = Args()
         for i in range(gi.nloaded):
-            b = buf(gi.loaded[i], bool(gi.loaded_half[i]))
+            b = buf(gi.loaded[i], gi.loaded_dtype[i])
             a.src[i] = b.ctypes.data
             a.src_rs[i], a.src_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
         for i in range(gi.nliveouts):
-            b = buf(gi.liveouts[i], bool(gi.liveout_half[i]))
+            b = buf(gi.liveouts[i], gi.liveout_dtype[i])
             a.dst[i] = b.ctypes.data
             a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
         a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
@@ -169,7 +186,7 @@ def emulate(spec, inputs, **plan_kw):
             lib.wt_emu_run_grid(ctypes.byref(a), gi.tiles_x, gi.tiles_y, gi.channels, 256)
         else:
             lib.wt_emu_run(ctypes.byref(a), gi.nwaves, gi.waves_per_group)
-    return {o: bufs[names.index(o)].astype(np.float32) for o in spec["outputs"]}, plan
+    return {o: _result(bufs[names.index(o)]) for o in spec["outputs"]}, plan
 
 
 def emulate_batch(spec, images, nblocks=3, **plan_kw):
@@ -189,7 +206,8 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
             plans.append(wt.from_spec(spec).plan(w, h, no_device=True, **kw))
         bufs = {}
         for i, inp in enumerate(spec["inputs"]):
-            bufs[i] = np.ascontiguousarray(inputs[inp["name"]], dtype=np.float32).reshape(ch[inp["name"]], h, w)
+            t = SPEC_NP[inp.get("dtype", "f32")]
+            bufs[i] = np.ascontiguousarray(inputs[inp["name"]]).astype(t).reshape(ch[inp["name"]], h, w)
         bufs_all.append((w, h, bufs))
     ngroups = plans[0].num_groups
     for g in range(ngroups):
@@ -208,20 +226,20 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
             wpb = gi.waves_per_group
             w, h, bufs = bufs_all[k]
 
-            def buf(node_id, half):
+            def buf(node_id, code):
                 if node_id not in bufs:
                     nm = names[node_id]
                     bw, bh = oracle.level_size(w, h, lv[nm])
-                    bufs[node_id] = np.full((ch[nm], bh, bw), np.nan, dtype=np.float16 if half else np.float32)
+                    bufs[node_id] = _blank((ch[nm], bh, bw), code)
                 return bufs[node_id]
 
             a = arr[k]
             for i in range(gi.nloaded):
-                b = buf(gi.loaded[i], bool(gi.loaded_half[i]))
+                b = buf(gi.loaded[i], gi.loaded_dtype[i])
                 a.src[i] = b.ctypes.data
                 a.src_rs[i], a.src_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
             for i in range(gi.nliveouts):
-                b = buf(gi.liveouts[i], bool(gi.liveout_half[i]))
+                b = buf(gi.liveouts[i], gi.liveout_dtype[i])
                 a.dst[i] = b.ctypes.data
                 a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
             a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
@@ -235,4 +253,4 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
             lib.wt_emu_run_grid_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks)
         else:
             lib.wt_emu_run_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
-    return [{o: b[names.index(o)].astype(np.float32) for o in spec["outputs"]} for (_, _, b) in bufs_all]
+    return [{o: _result(b[names.index(o)]) for o in spec["outputs"]} for (_, _, b) in bufs_all]

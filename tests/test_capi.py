@@ -56,6 +56,42 @@ def test_builder_rejects_bad_arguments():
         p.output(ok)
 
 
+def _status(fn, *a):
+    try:
+        fn(*a)
+    except wt.WtError as e:
+        return e.status
+    return 0
+
+
+def test_integer_builder_rules():
+    p = wt.Pipeline()
+    f = p.input(1)
+    u8 = p.input(1, "u8")
+    i32 = p.input(1, "i32")
+    UNSUP = -2
+    # integer stencils read integer stages only
+    assert _status(p.stencil_int, f, 3, 1, 1, 0, [1, 2, 1], 4, "u8") == UNSUP
+    # sums that may leave 32 bits are refused
+    assert _status(p.stencil_int, i32, 3, 1, 1, 0, [1, 2, 1], 4, "i32") == UNSUP
+    assert _status(p.stencil_int, u8, 3, 1, 1, 0, [1, 2, 1], 0, "u8") == -1      # divisor
+    assert _status(p.stencil_int, u8, 3, 1, 1, 0, [1, 40000, 1], 1, "u8") == -1  # weight range
+    assert _status(p.stencil_int, u8, 3, 1, 1, 0, [1, 2, 1], 4, "f32") == -1     # output type
+    # integer expressions: integer constants, no division
+    assert _status(p.pointwise, [u8], "s0 / 2", 1, "i16") == UNSUP
+    assert _status(p.pointwise, [u8], "s0 + 0.5", 1, "i16") == UNSUP
+    assert _status(p.pointwise, [u8, f], "s0 + s1", 1, "i16") == UNSUP
+    assert _status(p.pointwise, [i32, i32], "s0 * s1", 1, "i32") == UNSUP       # 32-bit bound
+    b = p.stencil_int(u8, 5, 1, 2, 0, [1, 4, 6, 4, 1], 16, "u8")
+    d = p.resample(b, wt.DOWN2)
+    assert _status(p.resample, d, wt.UP2) == UNSUP                              # no integer up2
+    # float stages may read integer stages
+    p.stencil(b, 3, 1, 1, 0, [1, 2, 1], 0.25)
+    p.pointwise([u8, f], "s0 * s1 + 0.5", 1)
+    ok = p.pointwise([u8, b], "max(s0 - 2 * s1, -7)", 1, "i16")
+    p.output(ok)
+
+
 def test_plan_errors():
     pipe = wt.from_spec(P.gaussian_blur())
     with pytest.raises(wt.WtError):

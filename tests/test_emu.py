@@ -106,3 +106,40 @@ def test_batched_persistent_kernels_emulated():
     outs = emulate_batch(spec, images, nblocks=2, mode="analytic", any_width=True)
     for inp, got in zip(images, outs):
         assert_normwise(got["R0"], oracle.evaluate(spec, inp)["R0"], 1e-5, "batched pyramid")
+
+
+# ------------------------------------------------------------ integer stages
+INT_CASES = [
+    (P.binomial_u8(), "nodes=1,2 V=4 TX=1 SX=0 TY=8 PF=2", 260, 29, 0, 255),
+    (P.binomial_u8(), "nodes=1,2 V=1 TX=2 SX=1 TY=5 PF=1 align=1", 131, 19, 0, 255),
+    (P.integer_unsharp(), "nodes=1,2,3,4 V=2 TX=2 SX=0 TY=6 PF=1", 150, 37, 0, 255),
+    (P.integer_unsharp(), "nodes=1,2,3,4 V=4 TX=2 SX=1 TY=4 PF=2 align=1", 300, 13, 0, 255),
+    (P.integer_unsharp(), "nodes=1 V=2 TY=4;nodes=2 V=1 TY=8;nodes=3,4 V=4 TY=16", 77, 21, 0, 255),
+    (P.integer_gradient(), "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=8;nodes=5;nodes=6 V=1", 90, 33, 0, 65535),
+    (P.integer_gradient(), "nodes=1 V=4;nodes=2 V=1 TY=3;nodes=3 V=2;nodes=4 V=4 TX=2 SX=1;nodes=5;nodes=6 V=2",
+     130, 17, 0, 65535),
+]
+
+
+@pytest.mark.parametrize("spec,fixed,w,h,lo,hi", INT_CASES)
+def test_integer_pipelines_emulated_bit_exact(spec, fixed, w, h, lo, hi):
+    img = synth.integer_image(w * h, 1, h, w, lo, hi)
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fixed=fixed)
+    ref = oracle.evaluate(spec, {"img": img})
+    for k, r in ref.items():
+        if r.dtype == np.int64:
+            assert got[k].dtype == np.int64 and np.array_equal(got[k], r), f"{k}: {fixed}"
+        else:
+            assert_normwise(got[k], r, 1e-5, f"{k}: {fixed}")
+
+
+def test_integer_saturation_emulated():
+    """All-255 input: the 8-bit sharpen saturates; a zero region clips at 0."""
+    spec = P.integer_unsharp()
+    img = np.full((1, 20, 70), 255, dtype=np.int64)
+    img[:, :, 30:] = 0
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fixed="nodes=1,2,3,4 V=2 TX=1 SX=0 TY=8")
+    ref = oracle.evaluate(spec, {"img": img})
+    assert ref["sharp"].max() == 255 and ref["sharp"].min() == 0
+    for k in ref:
+        assert np.array_equal(got[k], ref[k])

@@ -221,3 +221,52 @@ def test_batched_persistent_graph(spec_name):
     for k in range(len(sizes)):
         for a, b in zip(tout[k], tout2[k]):
             assert torch.equal(a, b), f"replay differs for image {k}"
+
+
+# ------------------------------------------------------------ integer stages
+# Bit-exact against the oracle's int64 arithmetic (sums, rounded divisions and
+# saturation), through fused, split and unfused schedules, LDS sub-tiles,
+# both alignments, ragged sizes and every integer type.
+INT_CASES = [
+    ("binomial_u8", "nodes=1,2 V=4 TX=1 SX=0 TY=16 PF=2", 256, 256, 0, 255),
+    ("binomial_u8", "nodes=1,2 V=1 TX=2 SX=1 TY=5 PF=1 align=1", 131, 19, 0, 255),
+    ("integer_unsharp", "nodes=1,2,3,4 V=2 TX=2 SX=0 TY=6 PF=1", 150, 37, 0, 255),
+    ("integer_unsharp", "nodes=1,2,3,4 V=4 TX=2 SX=1 TY=4 PF=2 align=1", 300, 13, 0, 255),
+    ("integer_unsharp", "nodes=1 V=2 TY=4;nodes=2 V=1 TY=8;nodes=3,4 V=4 TY=16", 77, 21, 0, 255),
+    ("integer_gradient", "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=8;nodes=5;nodes=6 V=1", 90, 33, 0, 65535),
+    ("integer_gradient", "nodes=1 V=4;nodes=2 V=1 TY=3;nodes=3 V=2;nodes=4 V=4 TX=2 SX=1;nodes=5;nodes=6 V=2",
+     130, 17, 0, 65535),
+    ("integer_unsharp", None, 2048, 2048, 0, 255),
+]
+
+
+@pytest.mark.parametrize("name,fixed,w,h,lo,hi", INT_CASES)
+def test_integer_pipelines_bit_exact(name, fixed, w, h, lo, hi):
+    _say(f"integer {name} {fixed} {w}x{h}")
+    spec = getattr(P, name)()
+    img = synth.integer_image(w + h, 1, h, w, lo, hi)
+    kw = {"mode": "fixed", "fixed": fixed} if fixed else {"mode": "unfused"}
+    got, _ = run_gpu(spec, {"img": img}, **kw)
+    if fixed is None:
+        fused, _ = run_gpu(spec, {"img": img}, mode="fixed", fixed="nodes=1,2,3,4 V=4 TX=1 SX=0 TY=32 PF=2")
+        for k in got:
+            assert np.array_equal(got[k], fused[k])
+    ref = oracle.evaluate(spec, {"img": img})
+    for k, r in ref.items():
+        if r.dtype == np.int64:
+            assert np.array_equal(got[k], r), f"{k}: max diff {np.abs(got[k] - r).max()}"
+        else:
+            assert_normwise(got[k], r, 1e-5, k)
+
+
+def test_integer_saturation_corners():
+    _say("integer saturation")
+    spec = P.integer_unsharp()
+    img = np.full((1, 40, 300), 255, dtype=np.int64)
+    img[:, :, 150:] = 0
+    img[:, 20:, 100:200] = 128
+    got, _ = run_gpu(spec, {"img": img}, mode="fixed", fixed="nodes=1,2,3,4 V=4 TX=1 SX=0 TY=8")
+    ref = oracle.evaluate(spec, {"img": img})
+    assert ref["sharp"].max() == 255 and ref["sharp"].min() == 0 and ref["detail"].min() < 0
+    for k in ref:
+        assert np.array_equal(got[k], ref[k])

@@ -5,8 +5,22 @@ import numpy as np
 import oracle
 
 
+# numpy storage type of each element type, and the same-size type torch
+# moves it as (torch has few uint16 operations: those buffers travel as int16)
+_NP = {"f32": np.float32, "u8": np.uint8, "u16": np.uint16, "i16": np.int16, "i32": np.int32}
+_MOVE = {"f32": np.float32, "u8": np.uint8, "u16": np.int16, "i16": np.int16, "i32": np.int32}
+
+
+def _dtypes(spec):
+    dt = {i["name"]: i.get("dtype", "f32") for i in spec["inputs"]}
+    for st in spec["stages"]:
+        dt[st["name"]] = dt[st["src"]] if st["kind"] in ("down2", "up2") else st.get("dtype", "f32")
+    return dt
+
+
 def run_gpu(spec, inputs, width=None, height=None, **plan_kw):
-    """Runs `spec` on the GPU through the C ABI; returns {output name: float32 array}."""
+    """Runs `spec` on the GPU through the C ABI; returns {output name: array}
+    (float32 for float outputs, int64 for integer outputs)."""
     import torch
     import paper_1909_07190_amd as wt
     pipe = wt.from_spec(spec)
@@ -14,17 +28,33 @@ def run_gpu(spec, inputs, width=None, height=None, **plan_kw):
     h, w = first.shape[-2:]
     plan = pipe.plan(width or w, height or h, **plan_kw)
     dev = torch.device("cuda:0")
-    ins = [torch.from_numpy(np.ascontiguousarray(inputs[i["name"]], dtype=np.float32)).to(dev)
-           for i in spec["inputs"]]
+    dts = _dtypes(spec)
+
+    def to_dev(a, dt):
+        t = torch.from_numpy(np.ascontiguousarray(a).astype(_NP[dt]).view(_MOVE[dt])).to(dev)
+        return t.view(torch.uint16) if dt == "u16" else t
+
+    ins = [to_dev(inputs[i["name"]], dts[i["name"]]) for i in spec["inputs"]]
     lv = _levels(spec)
     outs = []
     for o in spec["outputs"]:
         ow, oh = oracle.level_size(w, h, lv[o])
         ch = _channels(spec)[o]
-        outs.append(torch.full((ch, oh, ow), float("nan"), device=dev, dtype=torch.float32))
+        if dts[o] == "f32":
+            outs.append(torch.full((ch, oh, ow), float("nan"), device=dev, dtype=torch.float32))
+        else:  # a value the kernel must overwrite
+            outs.append(to_dev(np.full((ch, oh, ow), 0x5A), dts[o]))
     plan.run(ins, outs)
     torch.cuda.synchronize()
-    return {o: t.cpu().numpy() for o, t in zip(spec["outputs"], outs)}, plan
+    res = {}
+    for o, t in zip(spec["outputs"], outs):
+        if dts[o] == "f32":
+            res[o] = t.cpu().numpy()
+        else:
+            if dts[o] == "u16":
+                t = t.view(torch.int16)
+            res[o] = t.cpu().numpy().view(_NP[dts[o]]).astype(np.int64)
+    return res, plan
 
 
 def _levels(spec):
