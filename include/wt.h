@@ -274,6 +274,17 @@ wt_status wt_measure_groups(const wt_pipeline* p, int width, int height, int fp1
                             const char* const* groups, int reps, const char* tag,
                             double* times_us);
 
+/* Pre-profiling of stage `node` (the paper, Section 6): the time of one
+ * evaluation of its body by a single lane with operands in LDS (microbench-
+ * mark over many iterations, less the bare loop), and the VGPRs of its body
+ * (its unfused kernel's allocation less input rings and addressing), as the
+ * analytical model uses them.  measure = 1 times it on the current device
+ * (results are cached per stage signature for the process); measure = 0 only
+ * compiles the microbenchmarks and returns the static estimate.  *measured
+ * tells which. */
+wt_status wt_stage_profile(const wt_pipeline* p, int node, int width, int height, int measure,
+                           double* ns_per_point, int* vgprs, int* measured);
+
 /* Destroys the plan; its stream must have drained. */
 void wt_plan_destroy(wt_plan* plan);
 

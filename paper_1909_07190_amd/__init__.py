@@ -401,3 +401,15 @@ def measure_groups(pipe, groups, width, height, fp16=False, reps=20, tag=""):
     out = (ctypes.c_double * max(n, 1))()
     _check(lib.wt_measure_groups(pipe._h, width, height, int(fp16), n, arr, reps, tag.encode(), out))
     return [out[i] for i in range(n)]
+
+
+_sig("wt_stage_profile", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.POINTER(ctypes.c_double), _c_int_p, _c_int_p)
+
+
+def stage_profile(pipe, node, width, height, measure=True):
+    """(ns per evaluation, VGPRs, measured?) of a stage as the cost model sees it."""
+    ns, vg, me = ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+    _check(lib.wt_stage_profile(pipe._h, node, width, height, int(measure), ctypes.byref(ns),
+                                ctypes.byref(vg), ctypes.byref(me)))
+    return ns.value, vg.value, bool(me.value)

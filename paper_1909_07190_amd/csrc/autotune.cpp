@@ -159,7 +159,7 @@ void autotune_plan(Plan& plan, int topk) {
             by_pred.push_back(&c);
             by_score.push_back(&c);
         }
-        std::sort(by_pred.begin(), by_pred.end(), [](auto a, auto b) { return a->cost.pred_us < b->cost.pred_us; });
+        std::sort(by_pred.begin(), by_pred.end(), [](auto a, auto b) { return a->cost.cal_us < b->cost.cal_us; });
         std::sort(by_score.begin(), by_score.end(),
                   [](auto a, auto b) { return a->cost.alg2.score < b->cost.alg2.score; });
         std::vector<GroupSched> cands;
@@ -250,6 +250,7 @@ void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vecto
         idx.push_back(i);
     }
     compile_groups(plan, ok);
+    if (!plan.no_device && preprofile_enabled()) preprofile(plan);
     if (plan.no_device) {
         for (size_t i : idx) out_us[i] = 0.0;
         return;

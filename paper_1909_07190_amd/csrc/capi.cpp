@@ -393,6 +393,22 @@ wt_status wt_measure_groups(const wt_pipeline* p, int width, int height, int fp1
     });
 }
 
+wt_status wt_stage_profile(const wt_pipeline* p, int node, int width, int height, int measure,
+                           double* ns_per_point, int* vgprs, int* measured) {
+    return guard([&] {
+        if (!p || !ns_per_point || !vgprs || !measured) wt::fail(WT_E_INVALID, "null argument");
+        check_src(p, node);
+        const wt::Node& n = p->p.nodes[node];
+        if (n.kind != wt::Kind::Stencil && n.kind != wt::Kind::Pointwise)
+            wt::fail(WT_E_INVALID, "only stencil and pointwise stages are profiled");
+        if (width <= 0 || height <= 0) wt::fail(WT_E_SHAPE, "bad size");
+        wt::StageProfile sp = wt::stage_profile(p->p, node, width, height, measure != 0);
+        *ns_per_point = sp.ns_per_point;
+        *vgprs = sp.vgprs;
+        *measured = sp.measured ? 1 : 0;
+    });
+}
+
 wt_status wt_mlp_create(const int* dims, int nlayers, uint64_t seed, wt_mlp** out) {
     return guard([&] {
         if (!dims || !out || nlayers < 2 || nlayers > 16) wt::fail(WT_E_INVALID, "bad mlp arguments");

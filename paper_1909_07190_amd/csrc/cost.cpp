@@ -142,6 +142,7 @@ static int expr_ops(const Expr& e) {
 StageProfile estimate_stage(const Pipeline& p, int id, const Machine& m) {
     const Node& n = p.nodes[id];
     StageProfile s;
+    if (lookup_profile(p, id, s)) return s;  // measured by pre-profiling
     int ops = 1;
     if (n.kind == Kind::Stencil) {
         int taps = 0, dx = 0;
@@ -248,6 +249,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     c.valu_ops = valu_ops * nwaves;
     if (!c.alg2.feasible) {
         c.pred_us = INFINITY;
+        c.cal_us = INFINITY;
         return c;
     }
     // Predicted time (the additive quantity the fusion search sums): HBM
@@ -268,7 +270,15 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     double t_mem = hbm_bytes / (m.hbm_bw * std::max(eff, 0.02));
     double t_alu = c.valu_ops * 64 / (m.ncu * m.simd_per_cu * 16.0 * m.clock_hz);
     c.pred_us = std::max(t_mem, t_alu) * 1e6 + m.launch_us;
+    c.cal_us = calibrated_us(c.pred_us, c.alg2.terms, kGfx950Fit);
     return c;
+}
+
+double calibrated_us(double pred_us, const double terms[7], const AnalyticFit& f) {
+    if (!(pred_us > 0) || !std::isfinite(pred_us)) return INFINITY;
+    double z = f.c0 + f.c1 * std::log(pred_us);
+    for (int k = 0; k < 7; ++k) z += f.w[k] * terms[k];
+    return std::exp(z);
 }
 
 double resample_pred_us(const Pipeline& p, int id, const Machine& m, int W, int H, bool half_in, bool half_out) {

@@ -9,9 +9,12 @@
 // unscheduled stages that is ready (every producer of a member is in S or G,
 // which also makes G convex), connected, on one pyramid level, and of at most
 // K stages; resampling stages form groups of their own.  The cost of a group
-// is the predicted time of its best configuration, where "best" is the
-// argmin of Algorithm 2's score over the configuration grid; the DP minimises
-// the sum over groups.
+// is the time of its best configuration over the configuration grid, and the
+// DP minimises the sum over groups.  With the analytical model both the
+// argmin and the sum use the calibrated time: Algorithm 2's terms and the
+// roofline-style predicted time, combined with coefficients refitted on
+// gfx950 measurements (the paper's score alone ranks configurations but has
+// no unit to sum); with the learned model, its predicted time.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -68,7 +71,7 @@ struct Search {
         K = r.max_group > 0 ? r.max_group : 12;
     }
 
-    // Best configuration of one group: argmin of Algorithm 2's score.
+    // Best configuration of one group and its time.
     std::pair<double, GroupSched> cost_of(uint64_t g) {
         auto it = gcache.find(g);
         if (it != gcache.end()) return it->second;
@@ -101,17 +104,18 @@ struct Search {
             r.model->predict(feats.data(), (int)cfgs.size(), pred.data());
             for (size_t i = 0; i < cfgs.size(); ++i) {
                 bool inside = r.model->max_abs_z(&feats[i * kNumFeatures]) <= 4.0;
-                double t = inside ? std::exp((double)pred[i]) : cfgs[i].cost.pred_us;
+                double t = inside ? std::exp((double)pred[i]) : cfgs[i].cost.cal_us;
                 if (t < best_pred) {
                     best_pred = t;
                     best = cfgs[i].g;
                 }
             }
         } else {
+            // the refitted analytical model: argmin of the calibrated time
             for (const ScoredConfig& sc : cfgs)
-                if (sc.cost.alg2.score < best_score) {
-                    best_score = sc.cost.alg2.score;
-                    best_pred = sc.cost.pred_us;
+                if (sc.cost.cal_us < best_score) {
+                    best_score = sc.cost.cal_us;
+                    best_pred = sc.cost.cal_us;
                     best = sc.g;
                 }
         }
@@ -197,9 +201,12 @@ struct Search {
 
 }  // namespace
 
-// Table 3's V100 weights, the starting point on gfx950 until refitted from
-// the autotuner's measurements.
+// Table 3's V100 weights (Algorithm 2's score in the paper's form).
 const double kGfx950Weights[7] = {50, 0.5, 60, 10, 2, 100, 1};
+
+// Refit on gfx950 (learn.py fit-analytic: bounded least squares of log
+// measured time over the measurement database's training pipelines).
+const AnalyticFit kGfx950Fit = {-0.98293, 0.72811, {0.18254, 1.98017, 0.0, 0.0, 0.23228, 0.0, 0.05261}};
 
 std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,
                                         const std::vector<int>& nodes) {

@@ -100,6 +100,9 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     req.any_width = plan->any_width;
     if (opts.fixed_schedule) req.fixed = opts.fixed_schedule;
     if (opts.model_path) req.model_path = opts.model_path;
+    if (!plan->no_device && preprofile_enabled() &&
+        (opts.mode == WT_SCHED_ANALYTIC || opts.mode == WT_SCHED_MLP || opts.mode == WT_SCHED_AUTOTUNE))
+        preprofile(*plan);
     plan->sched = make_schedule(p, plan->machine, req);
     build_groups(*plan);
     if (opts.mode == WT_SCHED_AUTOTUNE && !plan->no_device)

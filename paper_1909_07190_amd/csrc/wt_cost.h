@@ -45,6 +45,8 @@ struct StageProfile {
     bool measured = false;
 };
 StageProfile estimate_stage(const Pipeline& p, int id, const Machine& m);
+// The measured profile of a stage, if pre-profiling has timed its signature.
+bool lookup_profile(const Pipeline& p, int id, StageProfile& out);
 
 struct GroupCost {
     Alg2Out alg2;
@@ -53,6 +55,7 @@ struct GroupCost {
     double requested_bytes = 0, compulsory_bytes = 0, valu_ops = 0;
     long long nwaves = 0;
     double code_ops = 0;         // straight-line VALU operations per kernel body
+    double cal_us = 0;           // calibrated time (kGfx950Fit)
 };
 GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& geo, const Machine& m, int W,
                      int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7]);
@@ -66,7 +69,18 @@ struct ScoredConfig {
 // Every feasible configuration of the group `nodes` over the search grid.
 std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,
                                         const std::vector<int>& nodes);
+// Algorithm 2's weights as the paper's Table 3 gives them for the V100 (the
+// score keeps the paper's form; it is also one of the learned model's
+// features).
 extern const double kGfx950Weights[7];
+// The analytical model refitted on gfx950 measurements: calibrated time
+// exp(c0 + c1 log(pred_us) + sum_k w_k term_k), the quantity the analytical
+// scheduler minimises within a group and sums across groups.
+struct AnalyticFit {
+    double c0, c1, w[7];
+};
+extern const AnalyticFit kGfx950Fit;
+double calibrated_us(double pred_us, const double terms[7], const AnalyticFit& f);
 
 // 40 features of a (group, configuration) for the learned cost model:
 // 12 structural, 10 schedule, 12 analytical-model terms, 6 workload.

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "wt_internal.h"
+#include "wt_cost.h"
 
 namespace wt {
 
@@ -105,6 +106,12 @@ void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>&
 int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads);
 void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
 void autotune_plan(Plan& plan, int topk);
+// Times every stage body of plan.p not yet profiled (needs a device).
+void preprofile(const Plan& plan);
+bool preprofile_enabled();
+// Profile of stage `id` as the cost model sees it; `measure` runs the
+// pre-profiling on the device first, otherwise only compiles its kernels.
+StageProfile stage_profile(const Pipeline& p, int id, int W, int H, bool measure);
 void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vector<std::string>& descs, int reps,
                     const std::string& tag, double* out_us);
 std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H);

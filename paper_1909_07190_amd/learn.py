@@ -238,6 +238,53 @@ def ranking_report(rows, net):
     return out
 
 
+# ------------------------------------------------------- analytical refit --
+
+def fit_analytic(rows):
+    """Refits the analytical model on gfx950 measurements: least squares of
+    log(measured time) on an intercept, log(the roofline-style predicted
+    time) and Algorithm 2's seven terms, with non-negative coefficients on
+    the terms (they are penalties) and on log(predicted time).  Returns
+    {"c0", "c1", "w": [7]}; the model's calibrated time is
+    exp(c0 + c1 log(pred_us) + sum_k w_k term_k)."""
+    from scipy.optimize import lsq_linear
+
+    rows = [r for r in rows if math.isfinite(r.get("pred_us", float("inf"))) and r["pred_us"] > 0]
+    a = np.array([[1.0, math.log(r["pred_us"])] + list(r["terms"]) for r in rows])
+    b = np.log(np.array([r["measured_us"] for r in rows]))
+    lo = [-np.inf] + [0.0] * 8
+    res = lsq_linear(a, b, bounds=(lo, [np.inf] * 9))
+    x = res.x
+    return {"c0": float(x[0]), "c1": float(x[1]), "w": [float(v) for v in x[2:]], "rows": len(rows)}
+
+
+def calibrated(fit, r):
+    return math.exp(fit["c0"] + fit["c1"] * math.log(r["pred_us"]) +
+                    sum(w * t for w, t in zip(fit["w"], r["terms"])))
+
+
+def analytic_report(rows, fit):
+    """Top-1 regret (geomean over groups) and Kendall tau of the calibrated
+    time, and the log-space correlation with the measurements."""
+    by = {}
+    for r in rows:
+        by.setdefault((r["pipeline"], r["group"].split()[0]), []).append(r)
+    taus, reg = [], []
+    for rs in by.values():
+        if len(rs) < 2:
+            continue
+        meas = [r["measured_us"] for r in rs]
+        pred = [calibrated(fit, r) for r in rs]
+        taus.append(kendall_tau(pred, meas))
+        reg.append(meas[int(np.argmin(pred))] / min(meas))
+    lm = np.log([r["measured_us"] for r in rows])
+    lp = np.log([calibrated(fit, r) for r in rows])
+    return {"groups": len(reg), "kendall_tau_mean": float(np.nanmean(taus)) if taus else None,
+            "top1_regret_geomean": float(np.exp(np.mean(np.log(reg)))) if reg else None,
+            "log_corr": float(np.corrcoef(lm, lp)[0, 1]) if len(rows) > 2 else None,
+            "median_abs_log_err": float(np.median(np.abs(lm - lp)))}
+
+
 # ----------------------------------------------------------------- evaluate --
 
 def _time_plan(torch, plan, ins, outs, reps=20):
@@ -392,6 +439,9 @@ def main(argv=None):
     t.add_argument("--model", required=True)
     t.add_argument("--epochs", type=int, default=200)
     t.add_argument("--report", help="write the ranking report (JSON) here")
+    f = sub.add_parser("fit-analytic", help="refit the analytical model's coefficients")
+    f.add_argument("--db", required=True, nargs="+")
+    f.add_argument("--out", help="write the fit and its report (JSON) here")
     e = sub.add_parser("evaluate", help="compare whole-plan schedules on held-out pipelines")
     e.add_argument("--db", required=True, nargs="+")
     e.add_argument("--model", required=True)
@@ -423,6 +473,17 @@ def main(argv=None):
         if a.report:
             with open(a.report, "w") as f:
                 json.dump(rep, f, indent=1)
+    elif a.cmd == "fit-analytic":
+        rows = load_db(a.db)
+        tr, te = split_tags(rows)
+        train_rows = [r for r in rows if r["pipeline"] in tr]
+        test_rows = [r for r in rows if r["pipeline"] in te]
+        fit = fit_analytic(train_rows)
+        rep = {"fit": fit, "train": analytic_report(train_rows, fit), "test": analytic_report(test_rows, fit)}
+        log(json.dumps(rep))
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(rep, fh, indent=1)
     elif a.cmd == "evaluate":
         rows = load_db(a.db)
         _, te = split_tags(rows)

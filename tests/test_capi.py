@@ -138,3 +138,15 @@ def test_load_types_in_generated_source():
     assert "wt_shr1(" in body              # type 3 + 2 (lane 0 from LDS)
     assert "(float)L0[" in body            # type 2
     assert "ds_bpermute" not in body or "wt_shiftd" in body
+
+
+def test_preprofiling_microbenchmarks_compile_for_gfx950():
+    """Without a device, pre-profiling compiles every stage's microbenchmark
+    and unfused kernel and the cost model keeps its static estimate."""
+    for spec in (P.unsharp_mask(), P.integer_gradient()):
+        pipe = wt.from_spec(spec)
+        nin = len(spec["inputs"])
+        for k, st in enumerate(spec["stages"]):
+            if st["kind"] in ("stencil", "pointwise"):
+                ns, vg, measured = wt.stage_profile(pipe, nin + k, 128, 64, measure=False)
+                assert ns > 0 and vg >= 2 and not measured
