@@ -222,6 +222,22 @@ wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out)
 wt_status wt_fusion_costs(const wt_pipeline* p, int width, int height, int fp16, int max_group,
                           double* dp_us, double* exhaustive_us);
 
+/* Test hooks for the model's formulas (Section 4, Algorithm 2, Table 1).
+ * wt_alg2_eval evaluates Algorithm 2 for one configuration given the
+ * quantities it reads, on machine table `machine` (0: gfx950, 1: GTX 1080Ti),
+ * with weights w[7] (NULL: Table 3's V100 row).
+ *   in[9]  = {scratchpad bytes per block, registers per thread, warps per
+ *             block, blocks, transactions, compulsory transactions, bytes per
+ *             warp, compute seconds per warp, redundant / useful points}
+ *   out[12] = {feasible, score, occupancy, scratchpad-limited warps per SM,
+ *              register-limited warps per SM, terms[0..6]}
+ * wt_otpw_geometry gives Section 4's warp sizes for block[3] and warp size
+ * `ws`, and the scratchpad elements of one block for tile[3] and overlap[3]:
+ * prod_i ceil(block_i / warp_i) * (tile_i * warp_i + overlap_i). */
+wt_status wt_alg2_eval(int machine, const double* in, const double* w, double* out);
+wt_status wt_otpw_geometry(const int* block, int ws, const int* tile, const int* overlap, int* warp,
+                           int64_t* scratch_elems);
+
 /* ---------------------------------------------------------------------- */
 /* Learned cost model: a fully connected ReLU network over the 40 model      */
 /* features of a (group, configuration), predicting log kernel time; trained */

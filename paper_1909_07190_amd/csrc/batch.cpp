@@ -46,8 +46,10 @@ namespace {
 void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, int& ty, int& work) {
     const Pipeline& p = plan.p;
     if (gr.resample) {
-        tx = (lw + 63) / 64;
-        ty = (lh + 3) / 4;
+        int bw, bh;
+        resample_block(p, gr.g, bw, bh);
+        tx = (lw + bw - 1) / bw;
+        ty = (lh + bh - 1) / bh;
         work = tx * ty * p.nodes[gr.g.nodes[0]].channels;
         return;
     }

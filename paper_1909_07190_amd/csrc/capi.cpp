@@ -409,6 +409,44 @@ wt_status wt_stage_profile(const wt_pipeline* p, int node, int width, int height
     });
 }
 
+wt_status wt_alg2_eval(int machine, const double* in, const double* w, double* out) {
+    return guard([&] {
+        if (!in || !out) wt::fail(WT_E_INVALID, "null argument");
+        if (machine != 0 && machine != 1) wt::fail(WT_E_INVALID, "machine must be 0 or 1");
+        wt::Machine m = machine ? wt::machine_gtx1080ti() : wt::machine_gfx950();
+        wt::Alg2In a;
+        a.smem_per_wg = in[0];
+        a.regs_per_lane = in[1];
+        a.waves_per_wg = (int)in[2];
+        a.total_wg = (long long)in[3];
+        a.total_tx = in[4];
+        a.compulsory_tx = in[5];
+        a.mem_bytes_per_wave = in[6];
+        a.compute_time_per_wave = in[7];
+        a.frac_overlap = in[8];
+        if (a.waves_per_wg < 1 || a.total_wg < 1) wt::fail(WT_E_INVALID, "bad block counts");
+        wt::Alg2Out o = wt::alg2(a, m, w ? w : wt::kGfx950Weights);
+        out[0] = o.feasible ? 1 : 0;
+        out[1] = o.score;
+        out[2] = o.occupancy;
+        out[3] = o.shmem_occ;
+        out[4] = o.reg_occ;
+        for (int k = 0; k < 7; ++k) out[5 + k] = o.terms[k];
+    });
+}
+
+wt_status wt_otpw_geometry(const int* block, int ws, const int* tile, const int* overlap, int* warp,
+                           int64_t* scratch_elems) {
+    return guard([&] {
+        if (!block || !tile || !overlap || !warp || !scratch_elems) wt::fail(WT_E_INVALID, "null argument");
+        if (ws < 1) wt::fail(WT_E_INVALID, "bad warp size");
+        for (int i = 0; i < 3; ++i)
+            if (block[i] < 1 || tile[i] < 1 || overlap[i] < 0) wt::fail(WT_E_INVALID, "bad sizes");
+        wt::warp_sizes(block, ws, warp);
+        *scratch_elems = wt::scratchpad_elems(tile, block, warp, overlap);
+    });
+}
+
 wt_status wt_mlp_create(const int* dims, int nlayers, uint64_t seed, wt_mlp** out) {
     return guard([&] {
         if (!dims || !out || nlayers < 2 || nlayers > 16) wt::fail(WT_E_INVALID, "bad mlp arguments");

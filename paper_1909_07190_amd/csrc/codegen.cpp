@@ -688,11 +688,21 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const
     return GroupSources{device_prelude(), "", single, batch};
 }
 
-// 2x resampling kernels: one thread per output pixel, clamped reads.  Not
-// fused (a scaled dependence ends a group in this implementation).  The
-// single-image kernel runs a (tiles_x, tiles_y, channels) grid of 256-thread
-// blocks (64 x 4 pixels); the batched kernel loops its blocks over the
-// blocks of all images.
+// 2x resampling kernels (not fused: a scaled dependence ends a group in this
+// implementation).  down2: a thread per output pixel, 64 x 4 per 256-thread
+// workgroup.  up2: a thread per coarse pixel (i, j) producing the output quad
+// (2i..2i+1, 2j..2j+1) from the clamped 3 x 3 coarse neighbourhood -- the
+// separable expansion in x (even (P(i-1) + 6 P(i) + P(i+1)) / 8, odd
+// (P(i) + P(i+1)) / 2) on three coarse rows, then the same in y -- 128 x 8
+// outputs per workgroup.  The single-image kernel runs a
+// (tiles_x, tiles_y, channels) grid; the batched kernel loops its workgroups
+// over the blocks of all images.
+void resample_block(const Pipeline& p, const GroupSched& g, int& bw, int& bh) {
+    bool up = p.nodes[g.nodes[0]].kind == Kind::Up2;
+    bw = up ? 128 : 64;
+    bh = up ? 8 : 4;
+}
+
 GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g, const std::string& kname,
                                       bool src_half, bool dst_half) {
     const Node& n = p.nodes[g.nodes[0]];
@@ -701,34 +711,37 @@ GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g, co
     const std::string dt = n.is_int() ? dtype_ctype(n.dtype) : dst_half ? "_Float16" : "float";
     std::ostringstream o;
     o << "static __device__ __forceinline__ void " << kname << "_body(const WtArgs& A, int bxi, int byi, int c) {\n";
-    o << "    const int x = bxi * 64 + (threadIdx.x & 63);\n";
-    o << "    const int y = byi * 4 + (threadIdx.x >> 6);\n";
-    o << "    if (x >= A.W || y >= A.H) return;\n";
     o << "    const " << st << "* s = (const " << st << "*)A.src[0] + (long long)c * A.src_cs[0];\n";
     o << "    " << dt << "* d = (" << dt << "*)A.dst[0] + (long long)c * A.dst_cs[0];\n";
-    o << "    const long long rs = A.src_rs[0];\n";
+    o << "    const long long rs = A.src_rs[0], ds = A.dst_rs[0];\n";
     if (n.kind == Kind::Down2) {
-        o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")(" << (n.is_int() ? "int" : "float")
+        o << "    const int x = bxi * 64 + (threadIdx.x & 63);\n";
+        o << "    const int y = byi * 4 + (threadIdx.x >> 6);\n";
+        o << "    if (x >= A.W || y >= A.H) return;\n";
+        o << "    d[(long long)y * ds + x] = (" << dt << ")(" << (n.is_int() ? "int" : "float")
           << ")s[(long long)(2 * y) * rs + 2 * x];\n";
     } else {
+        o << "    const int i = bxi * 64 + (threadIdx.x & 63);\n";
+        o << "    const int j = byi * 4 + (threadIdx.x >> 6);\n";
+        o << "    const int x = 2 * i, y = 2 * j;\n";
+        o << "    if (x >= A.W || y >= A.H) return;\n";
         o << "    const int Ws = A.Ws, Hs = A.Hs;\n";
-        o << "    const int i = x >> 1, jr = y >> 1;\n";
-        o << "    int xs[3]; float wx[3]; int nx;\n";
-        o << "    if (x & 1) { xs[0] = min(i, Ws - 1); xs[1] = min(i + 1, Ws - 1); wx[0] = 0.5f; wx[1] = 0.5f; nx = 2; }\n";
-        o << "    else { xs[0] = wt_clampi(i - 1, 0, Ws - 1); xs[1] = min(i, Ws - 1); xs[2] = min(i + 1, Ws - 1);\n";
-        o << "           wx[0] = 0.125f; wx[1] = 0.75f; wx[2] = 0.125f; nx = 3; }\n";
-        o << "    int ys[3]; float wy[3]; int ny;\n";
-        o << "    if (y & 1) { ys[0] = min(jr, Hs - 1); ys[1] = min(jr + 1, Hs - 1); wy[0] = 0.5f; wy[1] = 0.5f; ny = 2; }\n";
-        o << "    else { ys[0] = wt_clampi(jr - 1, 0, Hs - 1); ys[1] = min(jr, Hs - 1); ys[2] = min(jr + 1, Hs - 1);\n";
-        o << "           wy[0] = 0.125f; wy[1] = 0.75f; wy[2] = 0.125f; ny = 3; }\n";
-        o << "    float acc = 0.f;\n";
-        o << "    for (int b = 0; b < ny; ++b) {\n";
-        o << "        const " << st << "* row = s + (long long)ys[b] * rs;\n";
-        o << "        float h = 0.f;\n";
-        o << "        for (int a = 0; a < nx; ++a) h = fmaf(wx[a], (float)row[xs[a]], h);\n";
-        o << "        acc = fmaf(wy[b], h, acc);\n";
+        o << "    const int xm = wt_clampi(i - 1, 0, Ws - 1), x0 = min(i, Ws - 1), xp = min(i + 1, Ws - 1);\n";
+        o << "    float he[3], ho[3];\n";
+        o << "    for (int b = 0; b < 3; ++b) {\n";
+        o << "        const " << st << "* row = s + (long long)wt_clampi(j - 1 + b, 0, Hs - 1) * rs;\n";
+        o << "        const float pm = (float)row[xm], p0 = (float)row[x0], pp = (float)row[xp];\n";
+        o << "        he[b] = fmaf(0.125f, pp, fmaf(0.75f, p0, 0.125f * pm));\n";
+        o << "        ho[b] = fmaf(0.5f, pp, 0.5f * p0);\n";
         o << "    }\n";
-        o << "    d[(long long)y * A.dst_rs[0] + x] = (" << dt << ")acc;\n";
+        o << "    " << dt << "* r0 = d + (long long)y * ds;\n";
+        o << "    r0[x] = (" << dt << ")fmaf(0.125f, he[2], fmaf(0.75f, he[1], 0.125f * he[0]));\n";
+        o << "    if (x + 1 < A.W) r0[x + 1] = (" << dt << ")fmaf(0.125f, ho[2], fmaf(0.75f, ho[1], 0.125f * ho[0]));\n";
+        o << "    if (y + 1 < A.H) {\n";
+        o << "        " << dt << "* r1 = r0 + ds;\n";
+        o << "        r1[x] = (" << dt << ")fmaf(0.5f, he[2], 0.5f * he[1]);\n";
+        o << "        if (x + 1 < A.W) r1[x + 1] = (" << dt << ")fmaf(0.5f, ho[2], 0.5f * ho[1]);\n";
+        o << "    }\n";
     }
     o << "}\n";
     const std::string body = o.str();

@@ -134,8 +134,10 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
                      gi);
         gr.mem_half_in = {half_mem(n.srcs[0])};
         gr.mem_half_out = {half_mem(n.id)};
-        gr.tiles_x = (gr.W + 63) / 64;
-        gr.tiles_y = (gr.H + 3) / 4;
+        int bw, bh;
+        resample_block(p, gr.g, bw, bh);
+        gr.tiles_x = (gr.W + bw - 1) / bw;
+        gr.tiles_y = (gr.H + bh - 1) / bh;
         gr.nwaves = gr.tiles_x * gr.tiles_y * n.channels;
         return;
     }

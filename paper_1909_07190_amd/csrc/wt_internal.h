@@ -199,6 +199,9 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g,
                                    const GroupGeom& geo, const std::string& kname);
 GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g,
                                       const std::string& kname, bool src_half, bool dst_half);
+// Output pixels one 256-thread workgroup of a resampling kernel covers:
+// down2 64 x 4 (a pixel per thread), up2 128 x 8 (a 2x2 quad per thread).
+void resample_block(const Pipeline& p, const GroupSched& g, int& bw, int& bh);
 std::string device_prelude();
 
 // ----------------------------------------------------------- scheduler ---
