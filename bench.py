@@ -161,8 +161,10 @@ def bench_other(args, torch, wt, synth, P):
             ins.append([a, b, m])
             outs.append([torch.empty((1, h, w), device=dev)])
             px += w * h
-        for mode in ("analytic", "unfused"):
-            plan = wt.from_spec(spec).plan(sizes[0][0], sizes[0][1], mode=mode, any_width=True)
+        # plans are scheduled (and autotuned) at the median image size
+        mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
+        for mode in ("autotune", "analytic", "unfused"):
+            plan = wt.from_spec(spec).plan(mw, mh, mode=mode, any_width=True)
             for _ in range(2):
                 plan.run_batch(ins, outs)
             torch.cuda.synchronize()

@@ -603,10 +603,17 @@ struct Gen {
 
     // One wave tile `wid` of the image described by `A`.
     void tile() {
-        line("const int ty = wid % A.tiles_y;");
-        line("const int rr = wid / A.tiles_y;");
-        line("const int tx = rr % A.tiles_x;");
-        line("const int cp = rr / A.tiles_x;");
+        if (g.ORD == 1) {  // horizontally adjacent tiles on consecutive waves
+            line("const int tx = wid % A.tiles_x;");
+            line("const int rr = wid / A.tiles_x;");
+            line("const int ty = rr % A.tiles_y;");
+            line("const int cp = rr / A.tiles_y;");
+        } else {
+            line("const int ty = wid % A.tiles_y;");
+            line("const int rr = wid / A.tiles_y;");
+            line("const int tx = rr % A.tiles_x;");
+            line("const int cp = rr / A.tiles_x;");
+        }
         line("(void)cp;");
         line("const int W = A.W, H = A.H;");
         line("const int x0 = tx * " + I(geo.X) + " + (" + I(geo.base) + ");");

@@ -240,6 +240,7 @@ std::string describe_group(const GroupSched& g) {
     os << " V=" << g.V << " TX=" << g.TX << " SX=" << g.SX << " TY=" << g.TY
        << " WPB=" << g.WPB << " PF=" << g.PF << " fp16=" << (g.fp16 ? 1 : 0) << " align=" << g.align
        << " XCD=" << g.XCD << " NT=" << g.NT;
+    if (g.ORD) os << " ORD=" << g.ORD;
     return os.str();
 }
 
@@ -274,6 +275,7 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
                 else if (k == "align") g.align = std::stoi(v);
                 else if (k == "PF") g.PF = std::stoi(v);
                 else if (k == "XCD") g.XCD = std::stoi(v);
+                else if (k == "ORD") g.ORD = std::stoi(v);
                 else if (k == "NT") g.NT = std::stoi(v);
                 else fail(WT_E_INVALID, "unknown schedule key '" + k + "'");
             } catch (const std::logic_error&) {

@@ -102,6 +102,8 @@ struct GroupSched {
     bool fp16 = false;       // intermediates stored as FP16
     int PF = 1;              // rows of input loaded ahead of their first use
     int XCD = 0;             // 1: remap workgroups so each XCD gets adjacent tiles
+    int ORD = 0;             // tile order of the wave index: 0 rows of tiles fastest
+                             // (vertical neighbours adjacent), 1 columns fastest
     int NT = 0;              // 1: non-temporal loads and stores
     int align = 0;           // 0: centred (reads from both neighbours);
                              // 1: the paper's right-hyperplane skew (reads from the left only)

@@ -125,16 +125,15 @@ def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_grou
         os.environ["WT_MEASURE_DB"] = db
     n_total = 0
     for tag, spec in specs.items():
-        rng = random.Random(f"{seed}:{tag}")
+        # separate seeded streams: the random groups, and each group's
+        # configurations, do not depend on the analytical schedule (so code
+        # compiled ahead stays valid when the model changes)
+        rng = random.Random(f"{seed}:{tag}:groups")
         t0 = time.time()
         pipe = from_spec(spec)
         dag = Dag(spec, pipe)
-        plan = pipe.plan(width, height, mode="analytic", no_compile=True)
         texts = []
         groups = []
-        for nodes, text in _parse_groups(plan.describe()):
-            groups.append((nodes, configs_per_group))
-            texts.append(text)  # the analytical pick itself
         for i in dag.stages:
             groups.append(([i], 1 if dag.fusable(i) else 0))
             if not dag.fusable(i):
@@ -143,13 +142,18 @@ def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_grou
             g = dag.random_group(rng, rng.randint(2, 12))
             if g:
                 groups.append((g, configs_per_group))
+        plan = pipe.plan(width, height, mode="analytic", no_compile=True)
+        for nodes, text in _parse_groups(plan.describe()):
+            groups.append((nodes, configs_per_group))
+            texts.append(text)  # the analytical pick itself
         seen = set(texts)
         for nodes, k in groups:
             if k == 0:
                 continue
             _, cfgs = group_features(pipe, nodes, width, height)
             cfgs = [c for c in cfgs if c]
-            for c in rng.sample(cfgs, min(k, len(cfgs))):
+            crng = random.Random(f"{seed}:{tag}:{','.join(map(str, nodes))}")
+            for c in crng.sample(cfgs, min(k, len(cfgs))):
                 if c not in seen:
                     seen.add(c)
                     texts.append(c)
