@@ -135,7 +135,7 @@ typedef enum {
     WT_SCHED_UNFUSED = 0,  /* one kernel per stage, intermediates in HBM      */
     WT_SCHED_ANALYTIC = 1, /* DP fusion with the analytical cost (Alg. 2)      */
     WT_SCHED_MLP = 2,      /* DP fusion ranked by the learned cost model       */
-    WT_SCHED_AUTOTUNE = 3, /* analytic top-k candidates, measured on device    */
+    WT_SCHED_AUTOTUNE = 3, /* top-k candidates (analytic or learned), measured */
     WT_SCHED_FIXED = 4     /* schedule text in `fixed_schedule`                */
 } wt_sched_mode;
 
@@ -153,7 +153,8 @@ typedef struct {
     int32_t flags;              /* WT_PLAN_* bits                              */
     int32_t autotune_topk;      /* candidates measured in WT_SCHED_AUTOTUNE    */
     const char* fixed_schedule; /* WT_SCHED_FIXED (see wt_plan_describe)       */
-    const char* model_path;     /* WT_SCHED_MLP weights file                   */
+    const char* model_path;     /* WT_SCHED_MLP weights file; with WT_SCHED_
+                                   AUTOTUNE, the learned model ranks candidates */
     const char* cache_dir;      /* code-object cache; NULL = $WT_CACHE_DIR or none */
 } wt_sched_opts;
 

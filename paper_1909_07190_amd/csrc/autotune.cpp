@@ -21,6 +21,7 @@
 #include <sstream>
 
 #include "wt_cost.h"
+#include "wt_mlp.h"
 #include "wt_runtime.h"
 
 namespace wt {
@@ -129,7 +130,7 @@ std::map<int, ImgRef> scratch_memory(const Plan& plan, DeviceScratch& sc) {
     return mem;
 }
 
-void autotune_plan(Plan& plan, int topk) {
+void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
     const Pipeline& p = plan.p;
     DeviceScratch sc;
     std::map<int, ImgRef> mem = scratch_memory(plan, sc);
@@ -138,6 +139,8 @@ void autotune_plan(Plan& plan, int topk) {
     const char* dbp = std::getenv("WT_MEASURE_DB");
     std::ofstream db;
     if (dbp && *dbp) db.open(dbp, std::ios::app);
+    std::unique_ptr<Mlp> model;
+    if (!model_path.empty()) model = Mlp::load(model_path);
     SchedRequest req;
     req.W = plan.W;
     req.H = plan.H;
@@ -159,7 +162,27 @@ void autotune_plan(Plan& plan, int topk) {
             by_pred.push_back(&c);
             by_score.push_back(&c);
         }
-        std::sort(by_pred.begin(), by_pred.end(), [](auto a, auto b) { return a->cost.cal_us < b->cost.cal_us; });
+        if (model) {
+            // rank by the learned model (analytical time outside its range)
+            std::vector<float> feats;
+            for (auto& c : all) {
+                std::vector<double> f = group_features(p, c.g, *c.geo, c.cost, plan.W, plan.H, c.tx_size);
+                for (double v : f) feats.push_back((float)v);
+            }
+            std::vector<float> pred(all.size());
+            if (!all.empty()) model->predict(feats.data(), (int)all.size(), pred.data());
+            std::vector<double> t(all.size());
+            for (size_t i = 0; i < all.size(); ++i)
+                t[i] = model->max_abs_z(&feats[i * kNumFeatures]) <= 4.0 ? std::exp((double)pred[i]) : all[i].cost.cal_us;
+            std::vector<size_t> idx(all.size());
+            for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+            std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return t[a] < t[b]; });
+            by_pred.clear();
+            for (size_t i : idx) by_pred.push_back(&all[i]);
+        } else {
+            std::sort(by_pred.begin(), by_pred.end(),
+                      [](auto a, auto b) { return a->cost.cal_us < b->cost.cal_us; });
+        }
         std::sort(by_score.begin(), by_score.end(),
                   [](auto a, auto b) { return a->cost.alg2.score < b->cost.alg2.score; });
         std::vector<GroupSched> cands;

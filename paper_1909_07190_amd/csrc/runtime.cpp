@@ -106,7 +106,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     plan->sched = make_schedule(p, plan->machine, req);
     build_groups(*plan);
     if (opts.mode == WT_SCHED_AUTOTUNE && !plan->no_device)
-        autotune_plan(*plan, opts.autotune_topk > 0 ? opts.autotune_topk : 6);
+        autotune_plan(*plan, opts.autotune_topk > 0 ? opts.autotune_topk : 6, opts.model_path ? opts.model_path : "");
     return plan;
 }
 

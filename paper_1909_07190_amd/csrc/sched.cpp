@@ -68,7 +68,15 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
         }
         case WT_SCHED_ANALYTIC:
         case WT_SCHED_AUTOTUNE: {
-            Schedule s = schedule_analytic(p, m, r);
+            // the autotuner starts from the learned model's schedule when
+            // given one, else from the analytical model's
+            std::unique_ptr<Mlp> model;
+            SchedRequest rr = r;
+            if (r.mode == WT_SCHED_AUTOTUNE && !r.model_path.empty()) {
+                model = Mlp::load(r.model_path);
+                rr.model = model.get();
+            }
+            Schedule s = schedule_analytic(p, m, rr);
             for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
             return s;
         }

@@ -105,7 +105,9 @@ void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>&
                const std::string& tag);
 int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads);
 void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
-void autotune_plan(Plan& plan, int topk);
+// Measures candidate configurations of every fused group and keeps the
+// fastest; candidates ranked by the learned model when `model_path` is set.
+void autotune_plan(Plan& plan, int topk, const std::string& model_path = "");
 // Times every stage body of plan.p not yet profiled (needs a device).
 void preprofile(const Plan& plan);
 bool preprofile_enabled();

@@ -378,6 +378,8 @@ def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, 
             "analytic": pipe.plan(width, height, mode="analytic"),
             "mlp": pipe.plan(width, height, mode="mlp", model_path=model_path),
             "autotune": pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk),
+            "mlp_autotune": pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk,
+                                      model_path=model_path),
         }
         drows = [r for r in rows if r["pipeline"] == tag]
         if drows:
@@ -406,7 +408,7 @@ def summarize(results):
         return float(np.exp(np.mean(np.log(xs)))) if xs else None
 
     out = {"pipelines": len(results)}
-    for m in ("analytic", "mlp", "autotune", "unfused"):
+    for m in ("analytic", "mlp", "autotune", "mlp_autotune", "unfused"):
         r = [x[m + "_us"] / x["best_us"] for x in results]
         out[m] = {"geomean_over_best": gm(r), "within_10pct": float(np.mean([v <= 1.10 for v in r]))}
     out["mlp_gain_over_analytic"] = gm([x["analytic_us"] / x["mlp_us"] for x in results])
