@@ -95,14 +95,27 @@ struct Gen {
         return "(" + ctype(id) + ")" + lidx(id, slot, ch, j);
     }
     std::string fresh(const std::string& pfx) { return pfx + I(tmp++); }
-    std::string memoize(const std::string& expr) {
+    std::string memoize(const std::string& expr, bool opaque = false) {
         auto it = memo.find(expr);
         if (it != memo.end()) return it->second;
         std::string n = fresh("t");
-        line("const auto " + n + " = " + expr + ";");
+        if (opaque) {
+            // An integer lane exchange, kept opaque to the compiler: without
+            // this the backend folds the DPP move into the following integer
+            // add / subtract (v_add_u32_dpp, v_subrev_u32_dpp), and those
+            // folded forms gave wrong values on gfx950, while the separate
+            // move is exact.  (Float arithmetic here is never folded: its
+            // operands are literal constants.)
+            line("auto " + n + " = " + expr + ";");
+            line("asm volatile(\"\" : \"+v\"(" + n + "));");
+        } else {
+            line("const auto " + n + " = " + expr + ";");
+        }
         memo[expr] = n;
         return n;
     }
+    // memoize for a lane exchange of node p's values
+    std::string xchg(int p, const std::string& expr) { return memoize(expr, isint(p)); }
 
     // Producer value for consumer c (channel slot of the producer chp) at
     // sub-tile k, element e, through dependence (dx, dy), at unrolled step ph.
@@ -131,26 +144,26 @@ struct Gen {
             std::string cur = reg(p, slot, chp, k - SX, ep);
             if (d == 1) {
                 if (k - 1 >= SX)  // types 3 (lanes 1..63) + 4 (lane 0)
-                    return memoize("wt_shift1(" + cur + ", " + reg(p, slot, chp, k - 1 - SX, ep) + ")");
+                    return xchg(p, "wt_shift1(" + cur + ", " + reg(p, slot, chp, k - 1 - SX, ep) + ")");
                 if (k - 1 >= 0) {  // types 3 + 2: lane 0 reads the last LDS sub-tile
                     std::string b = memoize(lread(p, slot, chp, I((k - 1) * SUB + 63 * V + ep)));
-                    return memoize("wt_shr1(" + cur + ", " + b + ")");
+                    return xchg(p, "wt_shr1(" + cur + ", " + b + ")");
                 }
                 // lane 0 belongs to the overlap: any value
-                return memoize("wt_mov_shr1(" + cur + ")");
+                return xchg(p, "wt_mov_shr1(" + cur + ")");
             }
             if (k - 1 >= SX) {
                 std::string prv = reg(p, slot, chp, k - 1 - SX, ep);
-                if (d == 2) return memoize("wt_shift2(" + cur + ", " + prv + ")");
-                return memoize("wt_shiftd(" + cur + ", " + prv + ", " + I(d) + ", lane)");
+                if (d == 2) return xchg(p, "wt_shift2(" + cur + ", " + prv + ")");
+                return xchg(p, "wt_shiftd(" + cur + ", " + prv + ", " + I(d) + ", lane)");
             }
             if (k - 1 >= 0) {
                 std::string pv = memoize(lread(p, slot, chp, I((k - 1) * SUB) + " + ((lane - " + I(d) +
                                                                ") & 63) * " + I(V) + " + " + I(ep)));
-                return memoize("wt_shiftd_l(" + cur + ", " + pv + ", " + I(d) + ", lane)");
+                return xchg(p, "wt_shiftd_l(" + cur + ", " + pv + ", " + I(d) + ", lane)");
             }
-            if (d == 2) return memoize("wt_shift2(" + cur + ", " + cur + ")");
-            return memoize("wt_shiftd(" + cur + ", " + cur + ", " + I(d) + ", lane)");
+            if (d == 2) return xchg(p, "wt_shift2(" + cur + ", " + cur + ")");
+            return xchg(p, "wt_shiftd(" + cur + ", " + cur + ", " + I(d) + ", lane)");
         }
         // q >= V: source to the right (lane t + d, or the next sub-tile)
         int d = q / V;
@@ -163,19 +176,19 @@ struct Gen {
             std::string nx = reg(p, slot, chp, 0, ep);
             std::string rot = d == 1 ? "wt_rol1(" + nx + ")"
                                      : "wt_bperm(((lane + " + I(d) + ") & 63) << 2, " + nx + ")";
-            std::string rv = memoize(rot);
+            std::string rv = xchg(p, rot);
             return memoize("(lane >= " + I(64 - d) + " ? " + rv + " : " + lv + ")");
         }
         std::string cur = reg(p, slot, chp, k - SX, ep);
         if (k + 1 >= g.TX) {  // lanes past the strip belong to the overlap: any value
-            if (d == 1) return memoize("wt_mov_shl1(" + cur + ")");
-            if (d == 2) return memoize("wt_shift2n(" + cur + ", " + cur + ")");
-            return memoize("wt_shiftdn(" + cur + ", " + cur + ", " + I(d) + ", lane)");
+            if (d == 1) return xchg(p, "wt_mov_shl1(" + cur + ")");
+            if (d == 2) return xchg(p, "wt_shift2n(" + cur + ", " + cur + ")");
+            return xchg(p, "wt_shiftdn(" + cur + ", " + cur + ", " + I(d) + ", lane)");
         }
         std::string next = reg(p, slot, chp, k + 1 - SX, ep);
-        if (d == 1) return memoize("wt_shift1n(" + cur + ", " + next + ")");
-        if (d == 2) return memoize("wt_shift2n(" + cur + ", " + next + ")");
-        return memoize("wt_shiftdn(" + cur + ", " + next + ", " + I(d) + ", lane)");
+        if (d == 1) return xchg(p, "wt_shift1n(" + cur + ", " + next + ")");
+        if (d == 2) return xchg(p, "wt_shift2n(" + cur + ", " + next + ")");
+        return xchg(p, "wt_shiftdn(" + cur + ", " + next + ", " + I(d) + ", lane)");
     }
 
     int src_chan(const NodeGeom& p, int ch_c, int explicit_ch) {
