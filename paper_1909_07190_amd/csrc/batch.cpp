@@ -54,7 +54,7 @@ void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, i
         return;
     }
     int amin = 1 << 30, amax = 0;
-    for (int lo : gr.geo.liveouts) {
+    for (int lo : gr.geo.outs) {
         const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(lo)];
         amin = std::min(amin, ng.skew);
         amax = std::max(amax, ng.skew);

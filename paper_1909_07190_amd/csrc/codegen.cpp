@@ -416,6 +416,41 @@ struct Gen {
         line("}");
     }
 
+    // Element size in memory of decimated output k (a down2 of a member).
+    int dec_size(size_t k) const {
+        int d = geo.dec[k].first;
+        return P.nodes[d].is_int() ? dtype_size(P.nodes[d].dtype) : (dec_half(k) ? 2 : 4);
+    }
+    bool dec_half(size_t k) const {
+        int d = geo.dec[k].first;
+        return g.fp16 && !P.nodes[d].is_int() && !P.is_output(d);
+    }
+    // Decimated store of a member row (down2 fused into its producer): on
+    // even rows, the elements at even x go to (x/2, r/2) of the down2 node;
+    // every other element's offset is past the buffer, so the hardware drops
+    // it (no branch).
+    void emit_dec_store(size_t k, const NodeGeom& n, int ch, int kk, const std::string& arr, const std::string& R) {
+        int oi = (int)(geo.liveouts.size() + k);
+        std::string rsrc = "S" + I(oi) + "_" + I(ch);
+        const std::string aux = g.NT ? "WT_CPOL_NT" : "0";
+        int esz = dec_size(k);
+        int d = geo.dec[k].first;
+        std::string mt = P.nodes[d].is_int() ? dtype_ctype(P.nodes[d].dtype) : (dec_half(k) ? "_Float16" : "float");
+        line("{ const int jb = " + I(kk * SUB) + " + lane * " + I(V) + ";");
+        line("  const int xp = x0 + " + I(n.skew) + " + jb;");
+        line("  const bool okd = (" + R + " & 1) == 0 && " + R + " >= y0 && " + R + " < kend && " + R +
+             " < H && jb >= " + I(geo.S0) + " && jb < " + I(geo.S0 + geo.X) + ";");
+        line("  const long long rb = (long long)(" + R + " >> 1) * A.dst_rs[" + I(oi) + "];");
+        for (int e = 0; e < V; ++e) {
+            std::string x = "(xp + " + I(e) + ")";
+            line("  { const int off = (okd && (" + x + " & 1) == 0 && " + x + " >= 0 && " + x + " < W) ? (int)((rb + (" + x +
+                 " >> 1)) * " + I(esz) + ") : WT_OOB;");
+            line("    " + store_fn(esz) + "(__builtin_bit_cast(" + store_ty(esz) + ", (" + mt + ")" + arr + "[" + I(e) +
+                 "]), " + rsrc + ", off, 0, " + aux + "); }");
+        }
+        line("}");
+    }
+
     // ----------------------------------------------------- clamp fix-ups --
     // Positions of a stage row outside [0, W) take the value at x = 0 / W-1
     // (per-stage clamp to edge); only border waves execute this.
@@ -493,6 +528,8 @@ struct Gen {
                     }
                 }
                 if (oi >= 0 && stores) emit_store(oi, n, ch, k, arr, R);
+                for (size_t d = 0; d < geo.dec.size(); ++d)
+                    if (stores && geo.dec[d].second == n.id) emit_dec_store(d, n, ch, k, arr, R);
             }
         }
         if (n.consumed && SX > 0) line("wt_wave_sync();");
@@ -643,6 +680,15 @@ struct Gen {
                      chan_off(n.id, true, (int)oi, ch) + ", 0, (int)((long long)H * A.dst_rs[" + I((int)oi) +
                      "] * " + I(msize(n)) + "), WT_RSRC_W3);");
         }
+        for (size_t k = 0; k < geo.dec.size(); ++k) {
+            int oi = (int)(geo.liveouts.size() + k);
+            const NodeGeom& src = G(geo.dec[k].second);
+            for (int ch = 0; ch < src.nch; ++ch)
+                line("const __amdgpu_buffer_rsrc_t S" + I(oi) + "_" + I(ch) +
+                     " = __builtin_amdgcn_make_buffer_rsrc((char*)A.dst[" + I(oi) + "] + " +
+                     I(dec_size(k)) + " * (" + chan_off(src.id, true, oi, ch) + "), 0, (int)((long long)((H + 1) >> 1) * A.dst_rs[" +
+                     I(oi) + "] * " + I(dec_size(k)) + "), WT_RSRC_W3);");
+        }
         line("if (!bx) {");
         body(false);
         line("} else {");
@@ -697,7 +743,7 @@ struct Gen {
 
 GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const GroupGeom& geo,
                                    const std::string& kname) {
-    if ((int)geo.loaded.size() > 16 || (int)geo.liveouts.size() > 16)
+    if ((int)geo.loaded.size() > 16 || (int)(geo.liveouts.size() + geo.dec.size()) > 16)
         fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
     Gen gen(p, g, geo);
     std::string single = gen.kernel(kname);

@@ -171,7 +171,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
         lh = (lh + 1) / 2;
     }
     int amin = 1 << 30, amax = 0;
-    for (int lo : geo.liveouts) {
+    for (int lo : geo.outs) {
         amin = std::min(amin, geo.nodes[geo.index.at(lo)].skew);
         amax = std::max(amax, geo.nodes[geo.index.at(lo)].skew);
     }
@@ -220,6 +220,12 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
             int ch = geo.chan_parallel ? 1 : p.nodes[n.id].channels;
             comp_bytes += (double)lw * lh * esz * (geo.chan_parallel ? p.nodes[n.id].channels : ch);
         }
+    }
+    for (auto& ds : geo.dec) {  // decimated outputs: a quarter of the member's points
+        const NodeGeom& n = geo.nodes[geo.index.at(ds.second)];
+        int esz = p.nodes[ds.first].is_int() ? dtype_size(p.nodes[ds.first].dtype) : (n.mem_half ? 2 : 4);
+        store_bytes += (double)g.TY * geo.X * esz * n.nch / 4.0;
+        comp_bytes += (double)lw * lh * esz * p.nodes[ds.first].channels / 4.0;
     }
     lds = geo.lds_bytes_per_wg;
     tx_comp = 0;

@@ -65,13 +65,25 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         for (int s : p.nodes[m].srcs)
             if (!mem.count(s)) loaded.insert(s);
     geo.loaded.assign(loaded.begin(), loaded.end());
+    std::set<int> dec(g.dec.begin(), g.dec.end());
+    for (int d : g.dec) {
+        if (d < 0 || d >= (int)p.nodes.size() || p.nodes[d].kind != Kind::Down2)
+            fail(WT_E_INVALID, "dec names a node that is not a down2 stage");
+        int s = p.nodes[d].srcs[0];
+        if (!mem.count(s)) fail(WT_E_INVALID, "dec node " + std::to_string(d) + " decimates a non-member");
+        geo.dec.push_back({d, s});
+    }
     for (int m : g.nodes) {
         bool lo = p.is_output(m);
         for (int c : cons[m])
-            if (!mem.count(c)) lo = true;
+            if (!mem.count(c) && !dec.count(c)) lo = true;
         if (lo) geo.liveouts.push_back(m);
     }
-    if (geo.liveouts.empty()) fail(WT_E_INVALID, "group has no live-out");
+    geo.outs = geo.liveouts;
+    for (auto& ds : geo.dec)
+        if (std::find(geo.outs.begin(), geo.outs.end(), ds.second) == geo.outs.end()) geo.outs.push_back(ds.second);
+    std::sort(geo.outs.begin(), geo.outs.end());
+    if (geo.outs.empty()) fail(WT_E_INVALID, "group has no live-out");
 
     // channel mode
     int C = p.nodes[g.nodes[0]].channels;
@@ -93,6 +105,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         NodeGeom& ng = geo.nodes[i];
         geo.index[ng.id] = (int)i;
         ng.liveout = std::find(geo.liveouts.begin(), geo.liveouts.end(), ng.id) != geo.liveouts.end();
+        ng.out = std::find(geo.outs.begin(), geo.outs.end(), ng.id) != geo.outs.end();
         ng.skew = ng.lead = 0;
         ng.win = 1;
         ng.nch = par ? 1 : p.nodes[ng.id].channels;
@@ -125,7 +138,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
             }
         }
         if (g.align == 0) a = 0;
-        if ((ng.liveout || !ng.member) && a % g.V) a = round_up(a, g.V);
+        if ((ng.out || !ng.member) && a % g.V) a = round_up(a, g.V);
         ng.skew = a;
         ng.lead = L;
         ng.consumed = any;
@@ -168,7 +181,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
 
     geo.N = g.TX * 64 * g.V;
     int vlo = 0, vhi = 0, amax = 0;
-    for (int lo : geo.liveouts) {
+    for (int lo : geo.outs) {
         const NodeGeom& ng = geo.nodes[geo.index[lo]];
         vlo = std::max(vlo, ng.vlo);
         vhi = std::max(vhi, ng.vhi);
@@ -185,7 +198,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
 
     // warm-up: the earliest step at which some node must hold a valid row
     std::map<int, int> first;  // first needed row relative to y0
-    for (int lo : geo.liveouts) first[lo] = 0;
+    for (int lo : geo.outs) first[lo] = 0;
     for (int id : order) {
         if (!first.count(id)) first[id] = 0;
         for (int c : cons[id]) {
@@ -241,6 +254,10 @@ std::string describe_group(const GroupSched& g) {
        << " WPB=" << g.WPB << " PF=" << g.PF << " fp16=" << (g.fp16 ? 1 : 0) << " align=" << g.align
        << " XCD=" << g.XCD << " NT=" << g.NT;
     if (g.ORD) os << " ORD=" << g.ORD;
+    if (!g.dec.empty()) {
+        os << " dec=";
+        for (size_t i = 0; i < g.dec.size(); ++i) os << (i ? "," : "") << g.dec[i];
+    }
     return os.str();
 }
 
@@ -276,6 +293,11 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
                 else if (k == "PF") g.PF = std::stoi(v);
                 else if (k == "XCD") g.XCD = std::stoi(v);
                 else if (k == "ORD") g.ORD = std::stoi(v);
+                else if (k == "dec") {
+                    std::istringstream vs(v);
+                    std::string n;
+                    while (std::getline(vs, n, ',')) g.dec.push_back(std::stoi(n));
+                }
                 else if (k == "NT") g.NT = std::stoi(v);
                 else fail(WT_E_INVALID, "unknown schedule key '" + k + "'");
             } catch (const std::logic_error&) {
@@ -290,6 +312,10 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
                 fail(WT_E_INVALID, "schedule names a non-stage node " + std::to_string(n));
             if (!seen.insert(n).second)
                 fail(WT_E_INVALID, "node " + std::to_string(n) + " in two groups");
+        }
+        for (int d : g.dec) {  // a decimated down2 is produced by this group
+            if (d < 0 || d >= (int)p.nodes.size()) fail(WT_E_INVALID, "dec names an unknown node");
+            if (!seen.insert(d).second) fail(WT_E_INVALID, "node " + std::to_string(d) + " in two groups");
         }
         s.groups.push_back(g);
     }

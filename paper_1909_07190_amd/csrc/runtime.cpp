@@ -147,9 +147,13 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     for (int l : gr.geo.liveouts) gr.mem_half_out.push_back(half_mem(l));
     gr.loaded = gr.geo.loaded;
     gr.liveouts = gr.geo.liveouts;
+    for (auto& ds : gr.geo.dec) {  // decimated outputs follow the live-outs
+        gr.liveouts.push_back(ds.first);
+        gr.mem_half_out.push_back(half_mem(ds.first));
+    }
     name_sources(gr, generate_group_source(p, gr.g, gr.geo, kNamePlaceholder), gi);
     int amin = 1 << 30, amax = 0;
-    for (int lo : gr.geo.liveouts) {
+    for (int lo : gr.geo.outs) {
         const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(lo)];
         amin = std::min(amin, ng.skew);
         amax = std::max(amax, ng.skew);
@@ -321,7 +325,8 @@ void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>&
     }
     for (size_t i = 0; i < gr.liveouts.size(); ++i) {
         const ImgRef& r = mem.at(gr.liveouts[i]);
-        if (!gr.resample && p.is_output(gr.liveouts[i]))
+        bool decimated = std::find(gr.g.dec.begin(), gr.g.dec.end(), gr.liveouts[i]) != gr.g.dec.end();
+        if (!gr.resample && !decimated && p.is_output(gr.liveouts[i]))
             check_align(r, gr.g.V, node_esize(p, gr.liveouts[i], false), tag + " output node " + std::to_string(gr.liveouts[i]));
         a.dst[i] = const_cast<void*>(r.ptr);
         a.dst_rs[i] = r.rs;

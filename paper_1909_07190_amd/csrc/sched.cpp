@@ -45,6 +45,28 @@ int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H, bool 
     return lw % 4 == 0 ? 4 : (lw % 2 == 0 ? 2 : 1);
 }
 
+// A down2 whose source is computed in a fused (non-resampling) group is
+// written by that group directly, decimated: its own launch and the
+// full-resolution read of its source disappear.  Its consumers still come
+// after the producing group, so the order stays valid.
+void absorb_downsamples(const Pipeline& p, Schedule& s) {
+    std::vector<GroupSched> out;
+    for (const GroupSched& g : s.groups) {
+        bool absorbed = false;
+        if (g.nodes.size() == 1 && p.nodes[g.nodes[0]].kind == Kind::Down2) {
+            int src = p.nodes[g.nodes[0]].srcs[0];
+            for (GroupSched& h : out)
+                if (!is_resample_group(p, h) && std::binary_search(h.nodes.begin(), h.nodes.end(), src)) {
+                    h.dec.push_back(g.nodes[0]);
+                    absorbed = true;
+                    break;
+                }
+        }
+        if (!absorbed) out.push_back(g);
+    }
+    s.groups = out;
+}
+
 Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r) {
     switch (r.mode) {
         case WT_SCHED_UNFUSED: {
@@ -64,6 +86,7 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
             rr.model = model.get();
             Schedule s = schedule_analytic(p, m, rr);
             for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
+            absorb_downsamples(p, s);
             return s;
         }
         case WT_SCHED_ANALYTIC:
@@ -78,6 +101,7 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
             }
             Schedule s = schedule_analytic(p, m, rr);
             for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
+            absorb_downsamples(p, s);
             return s;
         }
         default: fail(WT_E_INVALID, "unknown schedule mode");

@@ -107,6 +107,8 @@ struct GroupSched {
     int NT = 0;              // 1: non-temporal loads and stores
     int align = 0;           // 0: centred (reads from both neighbours);
                              // 1: the paper's right-hyperplane skew (reads from the left only)
+    std::vector<int> dec;    // down2 stages this group writes directly: the even
+                             // rows and columns of a member, stored decimated
 };
 bool is_resample_group(const Pipeline& p, const GroupSched& g);
 
@@ -122,6 +124,7 @@ struct NodeGeom {
     int id;
     bool member;        // computed in the group (else loaded from memory)
     bool liveout;       // stored to memory
+    bool out = false;   // needed over the tile's output range (live-out or decimated)
     int skew;           // x alignment a_n: slot j <-> x = x0 - skew + j
     int lead;           // at step k the node holds row k + lead
     int win;            // rows kept (ring size)
@@ -151,6 +154,9 @@ struct GroupGeom {
     int lds_bytes = 0;              // LDS bytes per wave
     int lds_bytes_per_wg = 0;
     std::vector<int> loaded, liveouts;
+    std::vector<std::pair<int, int>> dec;  // (down2 node, member it decimates)
+    std::vector<int> outs;          // nodes needed over the tile's output range:
+                                    // live-outs and decimated members
 };
 GroupGeom group_geometry(const Pipeline& p, const GroupSched& g);
 

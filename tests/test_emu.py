@@ -143,3 +143,35 @@ def test_integer_saturation_emulated():
     assert ref["sharp"].max() == 255 and ref["sharp"].min() == 0
     for k in ref:
         assert np.array_equal(got[k], ref[k])
+
+
+# ------------------------------------------------- down2 fused into producer
+DEC_SPEC = {"inputs": [{"name": "img", "channels": 2}],
+            "stages": [P.blur_x("bx", "img"), P.blur_y("by", "bx"),
+                       {"name": "d", "kind": "down2", "src": "by"},
+                       {"name": "e", "kind": "pointwise", "srcs": ["d"], "expr": "s0 * 2", "channels": 2}],
+            "outputs": ["e", "by"]}
+
+
+@pytest.mark.parametrize("fixed,w,h", [
+    ("nodes=1,2 V=4 TX=1 SX=0 TY=8 dec=3;nodes=4 V=1", 132, 21),
+    ("nodes=1,2 V=2 TX=2 SX=1 TY=5 PF=1 dec=3;nodes=4 V=2", 130, 17),
+    ("nodes=1,2 V=1 TX=1 SX=0 TY=6 align=1 dec=3;nodes=4 V=1", 67, 13),
+])
+def test_decimated_store_emulated(fixed, w, h):
+    img = synth.dyadic_image(7, 2, h, w)
+    got, _ = emulate(DEC_SPEC, {"img": img}, mode="fixed", fixed=fixed)
+    ref = oracle.evaluate(DEC_SPEC, {"img": img})
+    for k in ref:
+        assert_exact(got[k], ref[k], f"{k}: {fixed}")
+
+
+def test_decimated_only_output_emulated():
+    """A member whose only consumer is the down2 is never stored itself."""
+    spec = {"inputs": [{"name": "img", "channels": 1}],
+            "stages": [P.blur_x("bx", "img"), P.blur_y("by", "bx"), {"name": "d", "kind": "down2", "src": "by"}],
+            "outputs": ["d"]}
+    img = synth.dyadic_image(8, 1, 29, 97)
+    got, plan = emulate(spec, {"img": img}, mode="analytic", any_width=True)
+    assert "dec=3" in plan.describe() and plan.num_groups == 1
+    assert_exact(got["d"], oracle.evaluate(spec, {"img": img})["d"], plan.describe())
