@@ -211,7 +211,8 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
         for (auto& g : cands) {
             GroupRt gr;
             gr.g = g;
-            gr.g.dec = cur.dec;  // decimated outputs stay with the group
+            gr.g.dec = cur.dec;  // decimated outputs and expanded inputs stay with the group
+            gr.g.exp = cur.exp;
             try {
                 prepare_group(plan, gr, (int)gi);
             } catch (const Error&) {

@@ -280,7 +280,59 @@ struct Gen {
     }
 
     // ------------------------------------------------------------ loads --
+    // Row kk + lead of an up2 node read by expansion: every element is the
+    // separable 2x expansion of the coarse source at the clamped fine point
+    // (x first, then y: even index 2i -> (P(i-1) + 6 P(i) + P(i+1)) / 8, odd
+    // 2i+1 -> (P(i) + P(i+1)) / 2, coarse indices clamped), gathered from the
+    // coarse image (a quarter of the fine one, mostly served by the caches).
+    void emit_expand_load(int li, const NodeGeom& n, int ph) {
+        const std::string ty = n.mem_half ? "_Float16" : "float";
+        int slot = pmod(ph, n.win);
+        for (int ch = 0; ch < n.nch; ++ch) {
+            line("{  // expand node " + I(n.expand_src) + " into node " + I(n.id) + " channel slot " + I(ch) +
+                 ", row kk + " + I(n.lead));
+            ind += "    ";
+            line("const int Wc = (W + 1) >> 1, Hc = (H + 1) >> 1;");
+            line("const int yr = wt_clampi(kk + " + I(n.lead) + ", 0, H - 1);");
+            line("const int jr = yr >> 1;");
+            line("const float wy0 = (yr & 1) ? 0.0f : 0.125f, wy1 = (yr & 1) ? 0.5f : 0.75f, wy2 = (yr & 1) ? 0.5f : 0.125f;");
+            line("const " + ty + "* cb = (const " + ty + "*)A.src[" + I(li) + "] + " + chan_off(n.id, false, li, ch) + ";");
+            line("const " + ty + "* r0 = cb + (long long)wt_clampi(jr - 1, 0, Hc - 1) * A.src_rs[" + I(li) + "];");
+            line("const " + ty + "* r1 = cb + (long long)min(jr, Hc - 1) * A.src_rs[" + I(li) + "];");
+            line("const " + ty + "* r2 = cb + (long long)min(jr + 1, Hc - 1) * A.src_rs[" + I(li) + "];");
+            for (int k = 0; k < g.TX; ++k) {
+                std::vector<std::string> dst;
+                std::string v;
+                if (k >= SX) {
+                    for (int e = 0; e < V; ++e) dst.push_back(reg(n.id, slot, ch, k - SX, e));
+                } else {
+                    v = fresh("ld");
+                    line("float " + v + "[" + I(V) + "];");
+                    for (int e = 0; e < V; ++e) dst.push_back(v + "[" + I(e) + "]");
+                }
+                for (int e = 0; e < V; ++e) {
+                    line("{ const int xf = wt_clampi(x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) +
+                         " + " + I(e) + ", 0, W - 1);");
+                    line("  const int i = xf >> 1;");
+                    line("  const int xa = wt_clampi(i - 1, 0, Wc - 1), xb = min(i, Wc - 1), xc = min(i + 1, Wc - 1);");
+                    line("  const float wx0 = (xf & 1) ? 0.0f : 0.125f, wx1 = (xf & 1) ? 0.5f : 0.75f, "
+                         "wx2 = (xf & 1) ? 0.5f : 0.125f;");
+                    line("  const float h0 = fmaf(wx2, (float)r0[xc], fmaf(wx1, (float)r0[xb], wx0 * (float)r0[xa]));");
+                    line("  const float h1 = fmaf(wx2, (float)r1[xc], fmaf(wx1, (float)r1[xb], wx0 * (float)r1[xa]));");
+                    line("  const float h2 = fmaf(wx2, (float)r2[xc], fmaf(wx1, (float)r2[xb], wx0 * (float)r2[xa]));");
+                    line("  " + dst[e] + " = fmaf(wy2, h2, fmaf(wy1, h1, wy0 * h0));");
+                    line("}");
+                }
+                if (k < SX) emit_lds_store(n, slot, ch, k, v);
+            }
+            ind.resize(ind.size() - 4);
+            line("}");
+        }
+        if (SX > 0) line("wt_wave_sync();");
+    }
+
     void emit_load(int li, const NodeGeom& n, int ph) {
+        if (n.expand_src >= 0) return emit_expand_load(li, n, ph);
         const std::string ty = mtype(n), ct = ctype(n.id);
         int slot = pmod(ph, n.win);
         for (int ch = 0; ch < n.nch; ++ch) {

@@ -196,12 +196,15 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
             const Node& nd = p.nodes[n.id];
             int esz = p.nodes[n.id].is_int() ? dtype_size(p.nodes[n.id].dtype) : (n.mem_half ? 2 : 4);
             int rows = std::max(0, steps - g.PF - n.first_step);
-            double row_bytes = (double)geo.N * esz;
+            // an expanded up2 reads its coarse source: half the columns, and
+            // each coarse row serves two fine rows
+            double row_bytes = (double)geo.N * esz * (n.expand_src >= 0 ? 0.25 : 1.0);
             load_bytes += rows * row_bytes * n.nch;
             int segs = (int)std::ceil(row_bytes / tx_size) + 1;
             tx += (double)rows * segs * n.nch;
             int ch = geo.chan_parallel ? 1 : nd.channels;
-            comp_bytes += (double)lw * lh * esz * (geo.chan_parallel ? nd.channels : ch);
+            comp_bytes += (double)lw * lh * esz * (geo.chan_parallel ? nd.channels : ch) *
+                          (n.expand_src >= 0 ? 0.25 : 1.0);
             continue;
         }
         auto it = prof.find(n.id);

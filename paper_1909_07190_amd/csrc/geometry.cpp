@@ -101,8 +101,15 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
     // nodes: loaded first, then members in topological order
     for (int l : geo.loaded) geo.nodes.push_back({l, false, false});
     for (int m : g.nodes) geo.nodes.push_back({m, true, false});
+    for (int u : g.exp) {
+        if (u < 0 || u >= (int)p.nodes.size() || p.nodes[u].kind != Kind::Up2)
+            fail(WT_E_INVALID, "exp names a node that is not an up2 stage");
+        if (!loaded.count(u)) fail(WT_E_INVALID, "exp node " + std::to_string(u) + " is not read by the group");
+    }
     for (size_t i = 0; i < geo.nodes.size(); ++i) {
         NodeGeom& ng = geo.nodes[i];
+        if (!ng.member && std::find(g.exp.begin(), g.exp.end(), ng.id) != g.exp.end())
+            ng.expand_src = p.nodes[ng.id].srcs[0];
         geo.index[ng.id] = (int)i;
         ng.liveout = std::find(geo.liveouts.begin(), geo.liveouts.end(), ng.id) != geo.liveouts.end();
         ng.out = std::find(geo.outs.begin(), geo.outs.end(), ng.id) != geo.outs.end();
@@ -258,6 +265,10 @@ std::string describe_group(const GroupSched& g) {
         os << " dec=";
         for (size_t i = 0; i < g.dec.size(); ++i) os << (i ? "," : "") << g.dec[i];
     }
+    if (!g.exp.empty()) {
+        os << " exp=";
+        for (size_t i = 0; i < g.exp.size(); ++i) os << (i ? "," : "") << g.exp[i];
+    }
     return os.str();
 }
 
@@ -267,7 +278,7 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
     std::replace(t.begin(), t.end(), ';', '\n');
     std::istringstream lines(t);
     std::string line;
-    std::set<int> seen;
+    std::set<int> seen, expanded;
     while (std::getline(lines, line)) {
         std::istringstream ws(line);
         std::string tok;
@@ -293,10 +304,10 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
                 else if (k == "PF") g.PF = std::stoi(v);
                 else if (k == "XCD") g.XCD = std::stoi(v);
                 else if (k == "ORD") g.ORD = std::stoi(v);
-                else if (k == "dec") {
+                else if (k == "dec" || k == "exp") {
                     std::istringstream vs(v);
                     std::string n;
-                    while (std::getline(vs, n, ',')) g.dec.push_back(std::stoi(n));
+                    while (std::getline(vs, n, ',')) (k == "dec" ? g.dec : g.exp).push_back(std::stoi(n));
                 }
                 else if (k == "NT") g.NT = std::stoi(v);
                 else fail(WT_E_INVALID, "unknown schedule key '" + k + "'");
@@ -317,11 +328,12 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
             if (d < 0 || d >= (int)p.nodes.size()) fail(WT_E_INVALID, "dec names an unknown node");
             if (!seen.insert(d).second) fail(WT_E_INVALID, "node " + std::to_string(d) + " in two groups");
         }
+        for (int u : g.exp) expanded.insert(u);  // may be expanded by several groups
         s.groups.push_back(g);
     }
     if (!partial)
         for (const Node& n : p.nodes)
-            if (n.kind != Kind::Input && !seen.count(n.id))
+            if (n.kind != Kind::Input && !seen.count(n.id) && !expanded.count(n.id))
                 fail(WT_E_INVALID, "schedule misses node " + std::to_string(n.id));
     return s;
 }

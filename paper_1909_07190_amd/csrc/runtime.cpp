@@ -142,10 +142,17 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
         return;
     }
     gr.geo = group_geometry(p, gr.g);
-    for (auto& ng : gr.geo.nodes) ng.mem_half = (!ng.member || ng.liveout) && half_mem(ng.id);
-    for (int l : gr.geo.loaded) gr.mem_half_in.push_back(half_mem(l));
+    // an expanded up2 is read from its coarse source's buffer
+    auto buffer_of = [&](int id) {
+        const NodeGeom& ng = gr.geo.nodes[gr.geo.index.at(id)];
+        return ng.expand_src >= 0 ? ng.expand_src : id;
+    };
+    for (auto& ng : gr.geo.nodes)
+        ng.mem_half = (!ng.member || ng.liveout) && half_mem(ng.member ? ng.id : buffer_of(ng.id));
+    for (int l : gr.geo.loaded) gr.mem_half_in.push_back(half_mem(buffer_of(l)));
     for (int l : gr.geo.liveouts) gr.mem_half_out.push_back(half_mem(l));
-    gr.loaded = gr.geo.loaded;
+    gr.loaded.clear();
+    for (int l : gr.geo.loaded) gr.loaded.push_back(buffer_of(l));
     gr.liveouts = gr.geo.liveouts;
     for (auto& ds : gr.geo.dec) {  // decimated outputs follow the live-outs
         gr.liveouts.push_back(ds.first);

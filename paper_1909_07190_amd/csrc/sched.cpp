@@ -67,6 +67,38 @@ void absorb_downsamples(const Pipeline& p, Schedule& s) {
     s.groups = out;
 }
 
+// An up2 that is not a pipeline output and whose every consumer is fused
+// in a (non-resampling) group is read by expansion inside those groups: its
+// launch and its full-resolution image disappear.
+void absorb_upsamples(const Pipeline& p, Schedule& s) {
+    auto cons = p.consumers();
+    std::vector<GroupSched> out;
+    std::vector<int> drop;
+    for (const GroupSched& g : s.groups) {
+        if (g.nodes.size() != 1 || p.nodes[g.nodes[0]].kind != Kind::Up2 || p.is_output(g.nodes[0])) continue;
+        int u = g.nodes[0];
+        bool ok = !cons[u].empty();
+        for (int c : cons[u]) {
+            bool found = false;
+            for (const GroupSched& h : s.groups)
+                if (!is_resample_group(p, h) && std::binary_search(h.nodes.begin(), h.nodes.end(), c)) found = true;
+            ok = ok && found;
+        }
+        if (ok) drop.push_back(u);
+    }
+    for (GroupSched g : s.groups) {
+        if (g.nodes.size() == 1 && std::count(drop.begin(), drop.end(), g.nodes[0])) continue;
+        if (!is_resample_group(p, g))
+            for (int u : drop)
+                for (int c : cons[u])
+                    if (std::binary_search(g.nodes.begin(), g.nodes.end(), c) &&
+                        !std::count(g.exp.begin(), g.exp.end(), u))
+                        g.exp.push_back(u);
+        out.push_back(g);
+    }
+    s.groups = out;
+}
+
 Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& r) {
     switch (r.mode) {
         case WT_SCHED_UNFUSED: {
@@ -87,6 +119,7 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
             Schedule s = schedule_analytic(p, m, rr);
             for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
             absorb_downsamples(p, s);
+            absorb_upsamples(p, s);
             return s;
         }
         case WT_SCHED_ANALYTIC:
@@ -102,6 +135,7 @@ Schedule make_schedule(const Pipeline& p, const Machine& m, const SchedRequest& 
             Schedule s = schedule_analytic(p, m, rr);
             for (auto& g : s.groups) g.V = std::min(g.V, max_vector_width(p, g, r.W, r.H, r.any_width));
             absorb_downsamples(p, s);
+            absorb_upsamples(p, s);
             return s;
         }
         default: fail(WT_E_INVALID, "unknown schedule mode");

@@ -109,6 +109,8 @@ struct GroupSched {
                              // 1: the paper's right-hyperplane skew (reads from the left only)
     std::vector<int> dec;    // down2 stages this group writes directly: the even
                              // rows and columns of a member, stored decimated
+    std::vector<int> exp;    // up2 stages this group reads by expanding their
+                             // coarse source on the fly (never materialised)
 };
 bool is_resample_group(const Pipeline& p, const GroupSched& g);
 
@@ -125,6 +127,7 @@ struct NodeGeom {
     bool member;        // computed in the group (else loaded from memory)
     bool liveout;       // stored to memory
     bool out = false;   // needed over the tile's output range (live-out or decimated)
+    int expand_src = -1; // loaded up2 node computed from this coarse node on the fly
     int skew;           // x alignment a_n: slot j <-> x = x0 - skew + j
     int lead;           // at step k the node holds row k + lead
     int win;            // rows kept (ring size)

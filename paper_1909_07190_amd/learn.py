@@ -107,7 +107,7 @@ def _group_text(nodes, cfg=""):
 def _parse_groups(describe_text):
     out = []
     for line in describe_text.strip().splitlines():
-        toks = [t for t in line.split() if "=" in t and not t.startswith(("batch_", "dec="))]
+        toks = [t for t in line.split() if "=" in t and not t.startswith(("batch_", "dec=", "exp="))]
         nodes = [int(x) for x in toks[0].split("=")[1].split(",")]
         out.append((nodes, " ".join(toks)))
     return out

@@ -175,3 +175,42 @@ def test_decimated_only_output_emulated():
     got, plan = emulate(spec, {"img": img}, mode="analytic", any_width=True)
     assert "dec=3" in plan.describe() and plan.num_groups == 1
     assert_exact(got["d"], oracle.evaluate(spec, {"img": img})["d"], plan.describe())
+
+
+# ----------------------------------------- up2 read by expansion in a group
+# node 1 = down2(img) (materialised), node 2 = up2(node 1) read by expansion,
+# node 3 = 3x3 stencil of it, node 4 = pointwise of img, node 3 and node 2
+EXP_SPEC = {"inputs": [{"name": "img", "channels": 1}],
+            "stages": [{"name": "small", "kind": "down2", "src": "img"},
+                       {"name": "u", "kind": "up2", "src": "small"},
+                       {"name": "s", "kind": "stencil", "src": "u", "kw": 3, "kh": 3, "ax": 1, "ay": 1,
+                        "weights": [1, 2, 1, 2, 4, 2, 1, 2, 1], "scale": 1.0 / 16},
+                       {"name": "o", "kind": "pointwise", "srcs": ["img", "s", "u"], "expr": "s0 - s1 + 0.5 * s2",
+                        "channels": 1}],
+            "outputs": ["o"]}
+
+
+@pytest.mark.parametrize("fixed,w,h,fp16", [
+    ("nodes=1;nodes=3,4 V=4 TX=1 SX=0 TY=8 exp=2", 132, 21, False),
+    ("nodes=1;nodes=3,4 V=2 TX=2 SX=1 TY=5 PF=1 exp=2", 130, 17, False),
+    ("nodes=1;nodes=3,4 V=1 TX=1 SX=0 TY=6 align=1 exp=2", 67, 13, False),
+    ("nodes=1;nodes=3 V=1 TY=4 exp=2;nodes=4 V=1 exp=2", 67, 13, False),
+    ("nodes=1;nodes=3,4 V=1 TX=2 SX=0 TY=7 exp=2 fp16=1", 65, 15, True),
+])
+def test_expanded_up2_emulated(fixed, w, h, fp16):
+    img = synth.uniform_image(3, 1, h, w)
+    got, _ = emulate(EXP_SPEC, {"img": img}, mode="fixed", fixed=fixed, fp16=fp16)
+    ref = oracle.evaluate(EXP_SPEC, {"img": img})
+    assert_normwise(got["o"], ref["o"], 2e-3 if fp16 else 1e-5, fixed)
+
+
+def test_pyramid_schedule_expands_and_decimates():
+    spec = P.pyramid_blend(3)
+    img = {"A": synth.uniform_image(1, 1, 37, 70), "B": synth.uniform_image(2, 1, 37, 70),
+           "M": synth.ramp_mask(37, 70)}
+    got, plan = emulate(spec, img, mode="analytic", any_width=True)
+    d = plan.describe()
+    assert "exp=" in d and "dec=" in d
+    ref = oracle.evaluate(spec, img)
+    for k in ref:
+        assert_normwise(got[k], ref[k], 1e-5, d)
