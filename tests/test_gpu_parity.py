@@ -270,3 +270,33 @@ def test_integer_saturation_corners():
     assert ref["sharp"].max() == 255 and ref["sharp"].min() == 0 and ref["detail"].min() < 0
     for k in ref:
         assert np.array_equal(got[k], ref[k])
+
+
+# ------------------------------- fused resampling: decimated stores, expansion
+RESAMPLE_SPEC = {"inputs": [{"name": "img", "channels": 2}],
+                 "stages": [P.blur_x("bx", "img"), P.blur_y("by", "bx"),
+                            {"name": "d", "kind": "down2", "src": "by"},
+                            {"name": "u", "kind": "up2", "src": "d"},
+                            {"name": "s", "kind": "stencil", "src": "u", "kw": 3, "kh": 3, "ax": 1, "ay": 1,
+                             "weights": [1, 2, 1, 2, 4, 2, 1, 2, 1], "scale": 1.0 / 16},
+                            {"name": "o", "kind": "pointwise", "srcs": ["img", "s", "u"],
+                             "expr": "s0 - s1 + 0.5 * s2", "channels": 2}],
+                 "outputs": ["o", "d"]}
+
+
+@pytest.mark.parametrize("fixed,w,h", [
+    ("nodes=1,2 V=4 TX=1 SX=0 TY=8 dec=3;nodes=5,6 V=4 TX=1 SX=0 TY=16 exp=4", 132, 37),
+    ("nodes=1,2 V=2 TX=2 SX=1 TY=5 PF=1 dec=3;nodes=5,6 V=2 TX=2 SX=1 TY=7 exp=4", 130, 17),
+    ("nodes=1,2 V=1 TX=1 SX=0 TY=6 align=1 dec=3;nodes=5 V=1 exp=4;nodes=6 V=1 exp=4", 67, 13),
+    (None, 2048, 1024),
+])
+def test_fused_resampling(fixed, w, h):
+    _say(f"fused resampling {fixed} {w}x{h}")
+    img = synth.uniform_image(9, 2, h, w)
+    kw = {"mode": "fixed", "fixed": fixed} if fixed else {"mode": "analytic"}
+    got, plan = run_gpu(RESAMPLE_SPEC, {"img": img}, **kw)
+    if fixed is None:
+        assert "dec=3" in plan.describe() and "exp=4" in plan.describe()
+    ref = oracle.evaluate(RESAMPLE_SPEC, {"img": img})
+    for k in ref:
+        assert_normwise(got[k], ref[k], 1e-5, f"{k}: {plan.describe()}")
