@@ -29,6 +29,7 @@ METRIC = "Mpixels/s per pipeline, fused vs unfused on 1 GPU; % of HBM roofline"
 C, H, W = 3, 2048, 2048
 BYTES_PER_PX = 24  # 3 channels x (4 B in + 4 B out)
 HBM_PEAK_GBS = 8000.0
+OTPTB_FUSED = "nodes=1,2,3,4 V=2 TX=1 TY=16 WPB=4 BLK=1"
 DEFAULT_FUSED = "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1"
 
 
@@ -275,6 +276,13 @@ def main():
         ms_h = time_plan(torch, f16, ins, outs, args.steps, args.warmup, cyc)
         extra["fp16_intermediates"] = {"value": H * W / (ms_h * 1e-3) / 1e6, "ms_per_step": ms_h}
         log(f"fp16 intermediates: {ms_h * 1e3:.2f} us/step")
+        # the paper's baseline execution model: one overlapped tile per
+        # workgroup, stages in LDS with workgroup barriers (same fusion)
+        blk = wt.from_spec(spec).plan(W, H, mode="fixed", fixed=OTPTB_FUSED)
+        ms_b = time_plan(torch, blk, ins, outs, args.steps, args.warmup, cyc)
+        extra["one_tile_per_workgroup"] = {"value": H * W / (ms_b * 1e-3) / 1e6, "ms_per_step": ms_b,
+                                           "schedule": OTPTB_FUSED, "wave_tile_speedup": ms_b / ms}
+        log(f"one tile per workgroup: {ms_b * 1e3:.2f} us/step, wave tiles {ms_b / ms:.2f}x faster")
     copy = copy_reference(torch, ins, outs, args.steps, cyc)
     log(f"device copy reference: {copy['GB/s']:.0f} GB/s")
     cpu = None if args.no_cpu else cpu_baseline(img)

@@ -59,6 +59,13 @@ void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, i
         amin = std::min(amin, ng.skew);
         amax = std::max(amax, ng.skew);
     }
+    if (gr.g.BLK) {  // work items are tiles (one workgroup each)
+        int bw = block_tile_w(gr.g);
+        tx = (lw + bw - 1) / bw;
+        ty = (lh + gr.g.TY - 1) / gr.g.TY;
+        work = tx * ty * (gr.geo.chan_parallel ? gr.geo.C : 1);
+        return;
+    }
     tx = (lw - (amin - amax) + gr.geo.X - 1) / gr.geo.X;
     ty = (lh + gr.g.TY - 1) / gr.g.TY;
     work = tx * ty * (gr.geo.chan_parallel ? gr.geo.C : 1);
@@ -160,7 +167,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
             int threads = gr.resample ? 256 : 64 * gr.g.WPB;
             int per_cu = resident_blocks_per_cu(plan, gr.fn_batch, threads);
             st->per_cu[g] = per_cu;
-            int units = gr.resample ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
+            int units = (gr.resample || gr.g.BLK) ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
             st->grid[g] = std::max(1, std::min(units, per_cu * plan.machine.ncu));
         }
         // device argument table: [g][img] WtArgs, then [g][nimg + 1] starts

@@ -793,10 +793,250 @@ struct Gen {
 
 }  // namespace
 
+namespace {
+
+// The paper's one-overlapped-tile-per-thread-block execution (Section 3,
+// Fig. 3), kept as the ablation baseline of OTPW: a workgroup computes one
+// BX x BY output tile; every stage is evaluated over its whole (halo-grown)
+// region into LDS by all threads, with a workgroup barrier between stages;
+// loaded nodes are staged into LDS first; live-outs are written at the end.
+struct BlockGen {
+    const Pipeline& P;
+    const GroupSched& g;
+    const GroupGeom& geo;
+    std::ostringstream o;
+    int BX, BY, T;
+    struct Region { int x0 = 0, x1 = 0, y0 = 0, y1 = 0, off = 0; };
+    std::map<int, Region> reg;  // node id -> region relative to the tile origin
+    int lds_elems = 0;
+
+    BlockGen(const Pipeline& p, const GroupSched& gs, const GroupGeom& ge)
+        : P(p), g(gs), geo(ge), BX(block_tile_w(gs)), BY(gs.TY), T(64 * gs.WPB) {
+        std::set<int> mem(g.nodes.begin(), g.nodes.end());
+        auto cons = P.consumers();
+        for (int lo : geo.outs) reg[lo] = {0, BX, 0, BY, 0};
+        std::vector<int> order;
+        for (auto& ng : geo.nodes) order.push_back(ng.id);
+        std::sort(order.rbegin(), order.rend());
+        for (int id : order) {
+            Region r;
+            bool any = reg.count(id) > 0;
+            if (any) r = reg[id];
+            for (int c : cons[id]) {
+                if (!mem.count(c)) continue;
+                const Region& rc = reg.at(c);
+                for (const Tap& t : P.taps(c, id)) {
+                    Region q{rc.x0 + t.dx, rc.x1 + t.dx, rc.y0 + t.dy, rc.y1 + t.dy, 0};
+                    if (!any) r = q;
+                    r.x0 = std::min(r.x0, q.x0);
+                    r.x1 = std::max(r.x1, q.x1);
+                    r.y0 = std::min(r.y0, q.y0);
+                    r.y1 = std::max(r.y1, q.y1);
+                    any = true;
+                }
+            }
+            reg[id] = r;
+        }
+        for (auto& ng : geo.nodes) {
+            Region& r = reg[ng.id];
+            r.off = lds_elems;
+            lds_elems += (r.x1 - r.x0) * (r.y1 - r.y0) * ng.nch;
+        }
+        if ((long long)lds_elems * 4 > 64 * 1024)
+            fail(WT_E_UNSUPPORTED, "one-tile-per-workgroup group needs more than 64 KiB of LDS");
+    }
+    const NodeGeom& G(int id) const { return geo.nodes.at(geo.index.at(id)); }
+    static std::string I(long long v) { return std::to_string(v); }
+    std::string ct(int id) const { return P.nodes[id].is_int() ? "int" : "float"; }
+    std::string arr(int id) const { return "L" + I(id); }
+    int RW(int id) const { return reg.at(id).x1 - reg.at(id).x0; }
+    int RH(int id) const { return reg.at(id).y1 - reg.at(id).y0; }
+    int chan(int p, int ch_c, int explicit_ch) const {
+        if (explicit_ch >= 0) return explicit_ch;
+        return G(p).nch == 1 ? 0 : ch_c;
+    }
+    // value of producer p (channel slot chp) at global (gx + dx, gy + dy),
+    // clamped to the image (per-stage clamp to edge)
+    std::string rd(int c, int p, int chp, int dx, int dy) {
+        const Region& r = reg.at(p);
+        std::string x = "(wt_clampi(gx + (" + I(dx) + "), 0, W - 1) - ox - (" + I(r.x0) + "))";
+        std::string y = "(wt_clampi(gy + (" + I(dy) + "), 0, H - 1) - oy - (" + I(r.y0) + "))";
+        std::string v = arr(p) + "[" + I((long long)chp * RW(p) * RH(p)) + " + wt_clampi(" + y + ", 0, " + I(RH(p) - 1) +
+                        ") * " + I(RW(p)) + " + wt_clampi(" + x + ", 0, " + I(RW(p) - 1) + ")]";
+        return (!P.nodes[c].is_int() && P.nodes[p].is_int()) ? "(float)" + v : v;
+    }
+    std::string expr(const Expr& e, int c, int ch) {
+        const bool in = P.nodes[c].is_int();
+        auto K = [&](int i) { return expr(e.kids[i], c, ch); };
+        char b[64];
+        switch (e.op) {
+            case Expr::Const:
+                if (in) return "(" + I((long long)e.value) + ")";
+                std::snprintf(b, sizeof b, "(%.9ef)", (double)(float)e.value);
+                return b;
+            case Expr::Src: {
+                int p = P.nodes[c].srcs[e.src];
+                return rd(c, p, chan(p, ch, e.chan), 0, 0);
+            }
+            case Expr::Neg: return "(-" + K(0) + ")";
+            case Expr::Add: return "(" + K(0) + " + " + K(1) + ")";
+            case Expr::Sub: return "(" + K(0) + " - " + K(1) + ")";
+            case Expr::Mul: return "(" + K(0) + " * " + K(1) + ")";
+            case Expr::Div: return "(" + K(0) + " / " + K(1) + ")";
+            case Expr::Lt: return "(" + K(0) + " < " + K(1) + ")";
+            case Expr::Le: return "(" + K(0) + " <= " + K(1) + ")";
+            case Expr::Gt: return "(" + K(0) + " > " + K(1) + ")";
+            case Expr::Ge: return "(" + K(0) + " >= " + K(1) + ")";
+            case Expr::Abs: return (in ? "wt_abs(" : "fabsf(") + K(0) + ")";
+            case Expr::Min: return (in ? "wt_min(" : "fminf(") + K(0) + ", " + K(1) + ")";
+            case Expr::Max: return (in ? "wt_max(" : "fmaxf(") + K(0) + ", " + K(1) + ")";
+            case Expr::Sqrt: return "sqrtf(" + K(0) + ")";
+            case Expr::Floor: return "floorf(" + K(0) + ")";
+            case Expr::Select: return "(" + K(0) + " ? " + K(1) + " : " + K(2) + ")";
+        }
+        fail(WT_E_INTERNAL, "bad expression node");
+    }
+    std::string value(int c, int ch) {
+        const Node& n = P.nodes[c];
+        std::string sat;
+        if (n.is_int() && n.dtype != WT_I32) {
+            auto r = dtype_range(n.dtype);
+            sat = ", " + I(r.first) + ", " + I(r.second) + ")";
+        }
+        if (n.kind == Kind::Pointwise) {
+            std::string v = expr(n.expr, c, ch);
+            return sat.empty() ? v : "wt_sat(" + v + sat;
+        }
+        int p = n.srcs[0];
+        int chp = chan(p, ch, -1);
+        std::string acc;
+        if (n.is_int()) {
+            for (int j = 0; j < n.kh; ++j)
+                for (int i = 0; i < n.kw; ++i) {
+                    long long w = n.iweights[(size_t)j * n.kw + i];
+                    if (!w) continue;
+                    std::string t = "(" + I(w) + ") * " + rd(c, p, chp, i - n.ax, j - n.ay);
+                    acc = acc.empty() ? t : acc + " + " + t;
+                }
+            if (acc.empty()) acc = "0";
+            std::string q = n.divisor > 1 ? "wt_rdiv(" + acc + ", " + I(n.divisor) + ")" : "(" + acc + ")";
+            return sat.empty() ? q : "wt_sat(" + q + sat;
+        }
+        for (const Tap& t : P.taps(c, p)) {
+            char w[64];
+            std::snprintf(w, sizeof w, "(%.9ef)", (double)(float)t.w);
+            std::string r = rd(c, p, chp, t.dx, t.dy);
+            acc = acc.empty() ? std::string(w) + " * " + r : "fmaf(" + std::string(w) + ", " + r + ", " + acc + ")";
+        }
+        return acc.empty() ? "0.0f" : acc;
+    }
+    std::string chan_off(int id, bool dst, int slot, int ch) {
+        std::string cs = std::string(dst ? "A.dst_cs[" : "A.src_cs[") + I(slot) + "]";
+        if (geo.chan_parallel) return P.nodes[id].channels == 1 ? "0" : "(long long)cp * " + cs;
+        return "(long long)" + I(ch) + " * " + cs;
+    }
+    std::string mtype(int id, bool half) const {
+        return P.nodes[id].is_int() ? dtype_ctype(P.nodes[id].dtype) : (half ? "_Float16" : "float");
+    }
+    // body for tile index t of the image described by A
+    void tile_body() {
+        o << "    const int ty = t % A.tiles_y, rr = t / A.tiles_y, tx = rr % A.tiles_x, cp = rr / A.tiles_x;\n";
+        o << "    (void)cp;\n";
+        o << "    const int W = A.W, H = A.H;\n";
+        o << "    const int ox = tx * " << BX << ", oy = ty * " << BY << ";\n";
+        // stage the loaded nodes
+        for (size_t li = 0; li < geo.loaded.size(); ++li) {
+            const NodeGeom& n = G(geo.loaded[li]);
+            const Region& r = reg.at(n.id);
+            std::string ty = mtype(n.id, n.mem_half);
+            for (int ch = 0; ch < n.nch; ++ch) {
+                o << "    { const " << ty << "* s = (const " << ty << "*)A.src[" << li << "] + " << chan_off(n.id, false, (int)li, ch)
+                  << ";\n";
+                o << "      for (int i = threadIdx.x; i < " << RW(n.id) * RH(n.id) << "; i += " << T << ") {\n";
+                o << "        const int gx = wt_clampi(ox + (" << r.x0 << ") + i % " << RW(n.id) << ", 0, W - 1);\n";
+                o << "        const int gy = wt_clampi(oy + (" << r.y0 << ") + i / " << RW(n.id) << ", 0, H - 1);\n";
+                o << "        " << arr(n.id) << "[" << (long long)ch * RW(n.id) * RH(n.id) << " + i] = (" << ct(n.id)
+                  << ")s[(long long)gy * A.src_rs[" << li << "] + gx];\n";
+                o << "      } }\n";
+            }
+        }
+        o << "    __syncthreads();\n";
+        for (int m : g.nodes) {
+            const NodeGeom& n = G(m);
+            const Region& r = reg.at(m);
+            for (int ch = 0; ch < n.nch; ++ch) {
+                o << "    for (int i = threadIdx.x; i < " << RW(m) * RH(m) << "; i += " << T << ") {  // stage " << m << "\n";
+                o << "      const int gx = ox + (" << r.x0 << ") + i % " << RW(m) << ", gy = oy + (" << r.y0 << ") + i / "
+                  << RW(m) << ";\n";
+                o << "      " << arr(m) << "[" << (long long)ch * RW(m) * RH(m) << " + i] = " << value(m, ch) << ";\n";
+                o << "    }\n";
+            }
+            o << "    __syncthreads();\n";
+        }
+        for (size_t oi = 0; oi < geo.liveouts.size(); ++oi) {
+            int id = geo.liveouts[oi];
+            const NodeGeom& n = G(id);
+            const Region& r = reg.at(id);
+            std::string ty = mtype(id, n.mem_half);
+            for (int ch = 0; ch < n.nch; ++ch) {
+                o << "    { " << ty << "* d = (" << ty << "*)A.dst[" << oi << "] + " << chan_off(id, true, (int)oi, ch) << ";\n";
+                o << "      for (int i = threadIdx.x; i < " << BX * BY << "; i += " << T << ") {\n";
+                o << "        const int gx = ox + i % " << BX << ", gy = oy + i / " << BX << ";\n";
+                o << "        if (gx < W && gy < H) d[(long long)gy * A.dst_rs[" << oi << "] + gx] = (" << ty << ")"
+                  << arr(id) << "[" << (long long)ch * RW(id) * RH(id) << " + (i / " << BX << " - (" << r.y0 << ")) * "
+                  << RW(id) << " + i % " << BX << " - (" << r.x0 << ")];\n";
+                o << "      } }\n";
+            }
+        }
+    }
+    void lds_decl() {
+        o << "    __shared__ float wt_lds[" << std::max(1, lds_elems) << "];\n";
+        for (auto& ng : geo.nodes)
+            o << "    " << ct(ng.id) << "* " << arr(ng.id) << " = (" << ct(ng.id) << "*)(wt_lds + " << reg.at(ng.id).off
+              << ");\n";
+    }
+    std::string single(const std::string& kname) {
+        o.str("");
+        o << "extern \"C\" __global__ void __launch_bounds__(" << T << ") " << kname << "(const WtArgs A) {\n";
+        lds_decl();
+        o << "    const int t = blockIdx.x;\n";
+        tile_body();
+        o << "}\n";
+        return o.str();
+    }
+    std::string batch(const std::string& kname) {
+        o.str("");
+        o << "extern \"C\" __global__ void __launch_bounds__(" << T << ") " << kname
+          << "_batch(const WtArgs* __restrict__ AB, const int* __restrict__ start, const int nimg, const int total) {\n";
+        lds_decl();
+        o << "  for (int tt = blockIdx.x; tt < total; tt += gridDim.x) {\n";
+        o << "    int lo = 0, hi = nimg;\n";
+        o << "    while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (start[mid] <= tt) lo = mid; else hi = mid; }\n";
+        o << "    const WtArgs A = AB[lo];\n";
+        o << "    const int t = tt - start[lo];\n";
+        o << "    __syncthreads();\n";
+        tile_body();
+        o << "  }\n";
+        o << "}\n";
+        return o.str();
+    }
+};
+
+}  // namespace
+
+int block_tile_w(const GroupSched& g) { return 64 * g.V * g.TX; }
+
 GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const GroupGeom& geo,
                                    const std::string& kname) {
     if ((int)geo.loaded.size() > 16 || (int)(geo.liveouts.size() + geo.dec.size()) > 16)
         fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
+    if (g.BLK) {
+        if (!geo.dec.empty() || !g.exp.empty()) fail(WT_E_UNSUPPORTED, "fused resampling in a one-tile-per-workgroup group");
+        BlockGen b(p, g, geo);
+        std::string single = b.single(kname);
+        std::string batch = b.batch(kname);
+        return GroupSources{device_prelude(), "", single, batch};
+    }
     Gen gen(p, g, geo);
     std::string single = gen.kernel(kname);
     Gen gb(p, g, geo);

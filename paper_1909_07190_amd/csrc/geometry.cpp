@@ -261,6 +261,7 @@ std::string describe_group(const GroupSched& g) {
        << " WPB=" << g.WPB << " PF=" << g.PF << " fp16=" << (g.fp16 ? 1 : 0) << " align=" << g.align
        << " XCD=" << g.XCD << " NT=" << g.NT;
     if (g.ORD) os << " ORD=" << g.ORD;
+    if (g.BLK) os << " BLK=" << g.BLK;
     if (!g.dec.empty()) {
         os << " dec=";
         for (size_t i = 0; i < g.dec.size(); ++i) os << (i ? "," : "") << g.dec[i];
@@ -304,6 +305,7 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
                 else if (k == "PF") g.PF = std::stoi(v);
                 else if (k == "XCD") g.XCD = std::stoi(v);
                 else if (k == "ORD") g.ORD = std::stoi(v);
+                else if (k == "BLK") g.BLK = std::stoi(v);
                 else if (k == "dec" || k == "exp") {
                     std::istringstream vs(v);
                     std::string n;

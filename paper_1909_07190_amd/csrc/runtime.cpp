@@ -166,9 +166,16 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
         amax = std::max(amax, ng.skew);
     }
     int start_min = amin - amax;  // leftmost stored x of tile 0
+    int ch = gr.geo.chan_parallel ? gr.geo.C : 1;
+    if (gr.g.BLK) {  // one tile per workgroup: nwaves counts every wave of every tile
+        int bw = block_tile_w(gr.g);
+        gr.tiles_x = (gr.W + bw - 1) / bw;
+        gr.tiles_y = (gr.H + gr.g.TY - 1) / gr.g.TY;
+        gr.nwaves = gr.tiles_x * gr.tiles_y * ch * gr.g.WPB;
+        return;
+    }
     gr.tiles_x = (gr.W - start_min + gr.geo.X - 1) / gr.geo.X;
     gr.tiles_y = (gr.H + gr.g.TY - 1) / gr.g.TY;
-    int ch = gr.geo.chan_parallel ? gr.geo.C : 1;
     gr.nwaves = gr.tiles_x * gr.tiles_y * ch;
     if (gr.geo.lds_bytes_per_wg > plan.machine.max_lds_per_wg)
         fail(WT_E_UNSUPPORTED, "group needs " + std::to_string(gr.geo.lds_bytes_per_wg) + " bytes of LDS per workgroup");

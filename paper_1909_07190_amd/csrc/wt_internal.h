@@ -111,7 +111,11 @@ struct GroupSched {
                              // rows and columns of a member, stored decimated
     std::vector<int> exp;    // up2 stages this group reads by expanding their
                              // coarse source on the fly (never materialised)
+    int BLK = 0;             // 1: one tile per workgroup, stages in LDS with
+                             // workgroup barriers between them (the paper's
+                             // OTPTB baseline); tile (64*V*TX) x TY
 };
+int block_tile_w(const GroupSched& g);  // output columns of a BLK tile
 bool is_resample_group(const Pipeline& p, const GroupSched& g);
 
 struct Schedule { std::vector<GroupSched> groups; };

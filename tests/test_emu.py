@@ -214,3 +214,26 @@ def test_pyramid_schedule_expands_and_decimates():
     ref = oracle.evaluate(spec, img)
     for k in ref:
         assert_normwise(got[k], ref[k], 1e-5, d)
+
+
+# ---------------------------------- one tile per workgroup (OTPTB ablation)
+@pytest.mark.parametrize("spec,fixed,w,h", [
+    (BLUR, "nodes=1,2 V=1 TX=1 TY=8 BLK=1", 130, 21),
+    (UM, "nodes=1,2,3,4 V=2 TX=1 TY=5 BLK=1", 200, 13),
+    (HARRIS_EXACT, "nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=1 TY=8 BLK=1", 70, 19),
+    (P.integer_unsharp(), "nodes=1,2,3,4 V=1 TX=2 TY=6 BLK=1", 150, 11),
+])
+def test_one_tile_per_workgroup_emulated(spec, fixed, w, h):
+    if spec["inputs"][0].get("dtype") == "u8":
+        img = synth.integer_image(5, 1, h, w, 0, 255)
+    elif spec is HARRIS_EXACT:
+        img = synth.white_squares(np.zeros((3, h, w), np.float32), 3, count=6, side_lo=3, side_hi=9)
+    else:
+        img = synth.dyadic_image(5, spec["inputs"][0]["channels"], h, w)
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fixed=fixed)
+    ref = oracle.evaluate(spec, {"img": img})
+    for k in ref:
+        if ref[k].dtype == np.int64:
+            assert np.array_equal(got[k], ref[k]), fixed
+        else:
+            assert_exact(got[k], ref[k], fixed)

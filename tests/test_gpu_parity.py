@@ -300,3 +300,22 @@ def test_fused_resampling(fixed, w, h):
     ref = oracle.evaluate(RESAMPLE_SPEC, {"img": img})
     for k in ref:
         assert_normwise(got[k], ref[k], 1e-5, f"{k}: {plan.describe()}")
+
+
+# ---------------------------------- one tile per workgroup (OTPTB ablation)
+@pytest.mark.parametrize("name,fixed,w,h", [
+    ("blur", "nodes=1,2 V=2 TX=1 TY=16 WPB=4 BLK=1", 300, 77),
+    ("unsharp", "nodes=1,2,3,4 V=2 TX=1 TY=8 WPB=4 BLK=1", 260, 96),
+    ("harris", "nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=2 TY=8 WPB=4 BLK=1", 200, 50),
+])
+def test_one_tile_per_workgroup(name, fixed, w, h):
+    _say(f"otptb {name} {fixed} {w}x{h}")
+    spec = {"blur": BLUR, "unsharp": UM, "harris": P.harris()}[name]
+    img = synth.uniform_image(11, spec["inputs"][0]["channels"], h, w)
+    got, _ = run_gpu(spec, {"img": img}, mode="fixed", fixed=fixed)
+    ref = oracle.evaluate(spec, {"img": img}, keep_all=(name == "unsharp"))
+    if name == "unsharp":
+        check_unsharp(got["mask"], img, 1e-5, UM)
+    else:
+        for k in spec["outputs"]:
+            assert_normwise(got[k], ref[k], 1e-5, fixed)
