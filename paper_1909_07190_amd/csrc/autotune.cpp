@@ -78,12 +78,21 @@ void write_db_line(std::ofstream& db, const std::string& tag, const Plan& plan, 
     std::vector<double> f = group_features(plan.p, gr.g, gr.geo, sc.cost, plan.W, plan.H, sc.tx_size);
     std::ostringstream os;
     os.precision(9);
+    // JSON has no infinity: non-finite model quantities are written as null
+    auto num = [](double v) {
+        std::ostringstream t;
+        t.precision(9);
+        if (std::isfinite(v)) t << v;
+        else t << "null";
+        return t.str();
+    };
     os << "{\"pipeline\": \"" << json_escape(tag) << "\", \"W\": " << plan.W << ", \"H\": " << plan.H
-       << ", \"group\": \"" << json_escape(describe_group(gr.g)) << "\", \"measured_us\": " << us
-       << ", \"pred_us\": " << sc.cost.pred_us << ", \"score\": " << sc.cost.alg2.score << ", \"terms\": [";
-    for (int i = 0; i < 7; ++i) os << (i ? ", " : "") << sc.cost.alg2.terms[i];
+       << ", \"group\": \"" << json_escape(describe_group(gr.g)) << "\", \"measured_us\": " << num(us)
+       << ", \"pred_us\": " << num(sc.cost.pred_us) << ", \"score\": " << num(sc.cost.alg2.score)
+       << ", \"terms\": [";
+    for (int i = 0; i < 7; ++i) os << (i ? ", " : "") << num(sc.cost.alg2.terms[i]);
     os << "], \"features\": [";
-    for (size_t i = 0; i < f.size(); ++i) os << (i ? ", " : "") << f[i];
+    for (size_t i = 0; i < f.size(); ++i) os << (i ? ", " : "") << num(f[i]);
     os << "]}\n";
     db << os.str();
     db.flush();

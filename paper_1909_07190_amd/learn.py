@@ -27,6 +27,7 @@ import json
 import math
 import os
 import random
+import re
 import sys
 import time
 
@@ -173,10 +174,18 @@ def load_db(paths):
         with open(p) as f:
             for line in f:
                 line = line.strip()
-                if line:
-                    r = json.loads(line)
-                    if math.isfinite(r["measured_us"]) and r["measured_us"] > 0:
-                        rows.append(r)
+                if not line:
+                    continue
+                # non-finite model quantities (a configuration the model
+                # deems infeasible) are written as null; older lines as inf
+                line = re.sub(r"(?<=[\[ ,:])-?inf(?=[\],}])", "null", line)
+                r = json.loads(line)
+                feats = r.get("features") or []
+                ok = (r["measured_us"] is not None and math.isfinite(r["measured_us"]) and r["measured_us"] > 0
+                      and len(feats) == NUM_FEATURES and all(v is not None and math.isfinite(v) for v in feats)
+                      and r.get("pred_us") is not None and all(t is not None for t in r.get("terms", [])))
+                if ok:
+                    rows.append(r)
     return rows
 
 
