@@ -363,7 +363,7 @@ def best_measured_schedule(dag, rows, resample_us):
     return t, ";".join(texts)
 
 
-def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, log=print):
+def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, log=print, out_path=None):
     import torch
 
     dev = torch.device("cuda:0")
@@ -408,6 +408,9 @@ def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, 
         res["best_us"] = best
         results.append(res)
         log(json.dumps(res))
+        if out_path:  # one line per pipeline as it completes
+            with open(out_path, "a") as f:
+                f.write(json.dumps(res) + "\n")
     return results
 
 
@@ -417,9 +420,11 @@ def summarize(results):
         return float(np.exp(np.mean(np.log(xs)))) if xs else None
 
     out = {"pipelines": len(results)}
-    for m in ("analytic", "mlp", "autotune", "mlp_autotune", "unfused"):
-        r = [x[m + "_us"] / x["best_us"] for x in results]
-        out[m] = {"geomean_over_best": gm(r), "within_10pct": float(np.mean([v <= 1.10 for v in r]))}
+    for m in ("analytic", "mlp", "autotune", "mlp_autotune", "best_measured", "unfused"):
+        r = [x[m + "_us"] / x["best_us"] for x in results if m + "_us" in x]
+        if r:
+            out[m] = {"geomean_over_best": gm(r), "within_10pct": float(np.mean([v <= 1.10 for v in r])),
+                      "pipelines": len(r)}
     out["mlp_gain_over_analytic"] = gm([x["analytic_us"] / x["mlp_us"] for x in results])
     out["mlp_speedup_over_unfused"] = gm([x["unfused_us"] / x["mlp_us"] for x in results])
     return out
@@ -461,8 +466,11 @@ def main(argv=None):
     e.add_argument("--db", required=True, nargs="+")
     e.add_argument("--model", required=True)
     e.add_argument("--max-pipelines", type=int, default=0)
+    e.add_argument("--skip", type=int, default=0, help="skip the first held-out pipelines")
     e.add_argument("--size", type=int, default=2048)
     e.add_argument("--out", help="append per-pipeline JSON lines here")
+    sm = sub.add_parser("summarize", help="summarise per-pipeline evaluation lines")
+    sm.add_argument("--results", required=True, nargs="+")
     a = ap.parse_args(argv)
 
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -499,18 +507,21 @@ def main(argv=None):
         if a.out:
             with open(a.out, "w") as fh:
                 json.dump(rep, fh, indent=1)
+    elif a.cmd == "summarize":
+        res = []
+        for path in a.results:
+            with open(path) as f:
+                res.extend(json.loads(line) for line in f if line.strip())
+        log(json.dumps(summarize(res)))
     elif a.cmd == "evaluate":
         rows = load_db(a.db)
         _, te = split_tags(rows)
         tags = sorted(te, key=lambda s: int(s[3:]) if s[3:].isdigit() else s)
+        tags = tags[a.skip:]
         if a.max_pipelines:
             tags = tags[:a.max_pipelines]
         specs = {tg: dags.random_dag(int(tg[3:])) for tg in tags}
-        res = evaluate(specs, rows, a.model, a.size, a.size, log=log)
-        if a.out:
-            with open(a.out, "a") as f:
-                for r in res:
-                    f.write(json.dumps(r) + "\n")
+        res = evaluate(specs, rows, a.model, a.size, a.size, log=log, out_path=a.out)
         log(json.dumps(summarize(res)))
 
 
