@@ -612,7 +612,7 @@ struct Gen {
     // instructions, so the compiler's wait counts stay exact.
     // One streamed step: loads, then every member in topological order.
     // `pro` >= 0 marks prologue step `pro` (only nodes whose rows are already
-    // needed are computed; no stores); `q` >= 0 is the output-row index of an
+    // needed are computed; stores only of rows inside the tile); `q` >= 0 is the output-row index of an
     // epilogue step (loads past the tile's last needed row are skipped).
     void emit_step(int ph, const std::string& kk, int pro, int q) {
         memo.clear();
@@ -625,8 +625,11 @@ struct Gen {
             if (on) emit_load(li, n, ph);
             ++li;
         }
+        // a consumed live-out leads the group's last stage, so its first
+        // rows of the tile (row offset pro - D + lead >= 0) come out of the
+        // warm-up steps and are stored there
         for (auto& n : geo.nodes)
-            if (n.member && (pro < 0 || n.first_step <= pro)) emit_member(n, ph, pro < 0);
+            if (n.member && (pro < 0 || n.first_step <= pro)) emit_member(n, ph, pro < 0 || pro - geo.D + n.lead >= 0);
         ind.resize(ind.size() - 4);
         line("}");
     }

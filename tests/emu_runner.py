@@ -186,6 +186,7 @@ def emulate(spec, inputs, **plan_kw):
             lib.wt_emu_run_grid(ctypes.byref(a), gi.tiles_x, gi.tiles_y, gi.channels, 256)
         else:
             lib.wt_emu_run(ctypes.byref(a), gi.nwaves, gi.waves_per_group)
+    plan.emu_buffers = bufs  # node id -> array, for diagnosis
     return {o: _result(bufs[names.index(o)]) for o in spec["outputs"]}, plan
 
 

@@ -237,3 +237,41 @@ def test_one_tile_per_workgroup_emulated(spec, fixed, w, h):
             assert np.array_equal(got[k], ref[k]), fixed
         else:
             assert_exact(got[k], ref[k], fixed)
+
+
+# ------------------------------------------- consumed live-outs in a group
+# An output that later stages of its own group read with vertical taps is
+# computed ahead of the group's last stage: its first rows of each tile come
+# out of the warm-up steps and must be stored from there.  Blur with both
+# passes as outputs, and a 3-stage chain whose middle stage is an output.
+BLUR_BOTH = dict(BLUR, outputs=["bx", "by"])
+CHAIN3 = {
+    "inputs": [{"name": "img", "channels": 1}],
+    "stages": [
+        {"name": "a", "kind": "stencil", "src": "img", "kw": 3, "kh": 3, "ax": 1, "ay": 1,
+         "weights": [1.0, 2.0, 1.0, 2.0, 4.0, 2.0, 1.0, 2.0, 1.0], "scale": 0.0625},
+        {"name": "b", "kind": "pointwise", "srcs": ["a"], "expr": "0.5 * s0 + 0.25", "channels": 1},
+        {"name": "c", "kind": "stencil", "src": "b", "kw": 1, "kh": 5, "ax": 0, "ay": 2,
+         "weights": [1.0, 4.0, 6.0, 4.0, 1.0], "scale": 0.0625},
+        {"name": "d", "kind": "stencil", "src": "c", "kw": 3, "kh": 3, "ax": 1, "ay": 1,
+         "weights": [1.0, 1.0, 1.0, 1.0, 0.0, 1.0, 1.0, 1.0, 1.0], "scale": 0.125},
+    ],
+    "outputs": ["a", "c", "d"],
+}
+
+
+@pytest.mark.parametrize("spec,fixed,w,h", [
+    (BLUR_BOTH, "nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=2", 140, 37),
+    (BLUR_BOTH, "nodes=1,2 V=4 TX=2 SX=1 TY=5 PF=1 align=1", 260, 23),
+    (BLUR_BOTH, "nodes=1,2 V=1 TX=1 TY=6 BLK=1", 70, 19),
+    (CHAIN3, "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=8 PF=1", 132, 35),
+    (CHAIN3, "nodes=1,2,3,4 V=1 TX=2 SX=1 TY=3 PF=0 align=1", 131, 17),
+    (CHAIN3, "nodes=1,2;nodes=3,4 V=4 TX=1 SX=0 TY=16 PF=2", 264, 41),
+    (CHAIN3, "nodes=1,2,3,4 V=1 TX=1 TY=8 BLK=1", 70, 21),
+])
+def test_consumed_liveout_rows_stored(spec, fixed, w, h):
+    img = synth.dyadic_image(9, 1, h, w)
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fixed=fixed)
+    ref = oracle.evaluate(spec, {"img": img})
+    for k in spec["outputs"]:
+        assert_exact(got[k], ref[k], f"{fixed}: {k}")

@@ -319,3 +319,71 @@ def test_one_tile_per_workgroup(name, fixed, w, h):
     else:
         for k in spec["outputs"]:
             assert_normwise(got[k], ref[k], 1e-5, fixed)
+
+
+# ------------------------------------------------ full-size configured workloads
+def test_pyramid_batch_full_workload():
+    """The configured batch (64 pairs, sides uniform in 512..4096) through the
+    analytical schedule in one persistent launch per group; the three
+    smallest images are checked entirely against the oracle, every image for
+    finiteness."""
+    import torch
+    import paper_1909_07190_amd as wt
+    spec = P.pyramid_blend(4)
+    sizes = synth.batch_sizes(4, 64)
+    _say(f"pyramid full batch {len(sizes)} pairs")
+    dev = torch.device("cuda:0")
+    tin, tout = [], []
+    for i, (w, h) in enumerate(sizes):
+        a = torch.from_numpy(synth.uniform_image(4000 + 2 * i, 1, h, w)).to(dev)
+        b = torch.from_numpy(synth.uniform_image(4001 + 2 * i, 1, h, w)).to(dev)
+        m = torch.from_numpy(synth.ramp_mask(h, w)).to(dev)
+        tin.append([a, b, m])
+        tout.append([torch.full((1, h, w), float("nan"), device=dev)])
+    mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
+    plan = wt.from_spec(spec).plan(mw, mh, mode="analytic", any_width=True)
+    plan.run_batch(tin, tout)
+    torch.cuda.synchronize()
+    for i in range(len(sizes)):
+        assert torch.isfinite(tout[i][0]).all(), f"image {i}"
+    for i in sorted(range(len(sizes)), key=lambda k: sizes[k][0] * sizes[k][1])[:3]:
+        w, h = sizes[i]
+        ref = oracle.evaluate(spec, {"A": tin[i][0].cpu().numpy(), "B": tin[i][1].cpu().numpy(),
+                                     "M": tin[i][2].cpu().numpy()})
+        assert_normwise(tout[i][0].cpu().numpy(), ref[spec["outputs"][0]], 1e-5, f"image {i} {w}x{h}")
+
+
+@pytest.mark.parametrize("seed", [200, 201, 202])
+def test_random_dag_full_size(seed):
+    """Random pipelines of the learned-scheduler workload at 2048 x 2048
+    under the analytical schedule (fused groups, decimated stores, expanded
+    up-sampling) against the oracle."""
+    from synth import dags
+    spec = dags.random_dag(seed)
+    _say(f"random dag {seed}: {len(spec['stages'])} stages")
+    imgs = {inp["name"]: synth.uniform_image(seed * 7 + k, 1, 2048, 2048) for k, inp in enumerate(spec["inputs"])}
+    got, plan = run_gpu(spec, imgs, mode="analytic")
+    ref = oracle.evaluate(spec, imgs)
+    for k in spec["outputs"]:
+        assert_normwise(got[k], ref[k], 1e-5, f"{k}: {plan.describe()}")
+
+
+# ------------------------------------------- consumed live-outs in a group
+BLUR_BOTH = dict(BLUR, outputs=["bx", "by"])
+
+
+@pytest.mark.parametrize("fixed,w,h", [
+    ("nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=2", 300, 77),
+    ("nodes=1,2 V=4 TX=2 SX=1 TY=5 PF=1 align=1", 516, 45),
+    ("nodes=1,2 V=1 TX=1 TY=8 WPB=4 BLK=1", 200, 41),
+])
+def test_consumed_liveout_rows_stored(fixed, w, h):
+    """Both blur passes are outputs: the horizontal pass is read by the
+    vertical one inside the group, so its first rows of every tile come out
+    of the warm-up steps and are stored there."""
+    _say(f"consumed live-out {fixed} {w}x{h}")
+    img = synth.dyadic_image(9, 1, h, w)
+    got, _ = run_gpu(BLUR_BOTH, {"img": img}, mode="fixed", fixed=fixed)
+    ref = oracle.evaluate(BLUR_BOTH, {"img": img})
+    for k in BLUR_BOTH["outputs"]:
+        assert_exact(got[k], ref[k], f"{fixed}: {k}")
