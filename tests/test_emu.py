@@ -275,3 +275,17 @@ def test_consumed_liveout_rows_stored(spec, fixed, w, h):
     ref = oracle.evaluate(spec, {"img": img})
     for k in spec["outputs"]:
         assert_exact(got[k], ref[k], f"{fixed}: {k}")
+
+
+@pytest.mark.parametrize("seed", [200, 201])
+def test_random_pipeline_analytic_emulated(seed):
+    """Random pipelines of the learned-scheduler workload under the
+    analytical schedule (fused groups with consumed live-outs, decimated
+    stores, expanded up-sampling) against the oracle."""
+    from synth import dags
+    spec = dags.random_dag(seed)
+    imgs = {inp["name"]: synth.uniform_image(seed * 7 + k, 1, 38, 132) for k, inp in enumerate(spec["inputs"])}
+    got, plan = emulate(spec, imgs, mode="analytic")
+    ref = oracle.evaluate(spec, imgs)
+    for k in spec["outputs"]:
+        assert_normwise(got[k], ref[k], 1e-5, f"{k}: {plan.describe()}")
