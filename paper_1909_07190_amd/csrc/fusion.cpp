@@ -205,8 +205,13 @@ struct Search {
 const double kGfx950Weights[7] = {50, 0.5, 60, 10, 2, 100, 1};
 
 // Refit on gfx950 (learn.py fit-analytic: bounded least squares of log
-// measured time over the measurement database's training pipelines).
-const AnalyticFit kGfx950Fit = {-0.98293, 0.72811, {0.18254, 1.98017, 0.0, 0.0, 0.23228, 0.0, 0.05261}};
+// measured time over the measurement database's training pipelines: 4444
+// timed candidate groups of 93 random pipelines, seeds 4..119 less the
+// held-out fifth).  Only the normalised global-memory transactions and the
+// lost occupancy keep a weight; on the 23 held-out pipelines the calibrated time
+// has log-correlation 0.84 with the measurements, Kendall tau 0.58 over
+// each group's candidates and a top-1 regret of 1.17 (geomean).
+const AnalyticFit kGfx950Fit = {-0.34099, 0.61802, {0.30606, 1.35482, 0.0, 0.0, 0.0, 0.0, 0.0}};
 
 std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,
                                         const std::vector<int>& nodes) {

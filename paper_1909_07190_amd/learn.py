@@ -223,24 +223,29 @@ def kendall_tau(a, b):
     return s / cnt if cnt else float("nan")
 
 
-def ranking_report(rows, net):
+def ranking_report(rows, net, fit=None):
     """Per group (same pipeline and node set, two or more configurations):
-    Kendall tau of the analytical predicted time, Algorithm 2's score and the
-    network's prediction against the measurements, and the regret of each
-    model's top pick (its measured time over the best measured)."""
+    Kendall tau of the analytical predicted time (and of its calibrated form
+    under `fit`, when given), Algorithm 2's score and the network's
+    prediction against the measurements, and the regret of each model's top
+    pick (its measured time over the best measured)."""
     by = {}
     for r in rows:
         key = (r["pipeline"], r["group"].split()[0])
         by.setdefault(key, []).append(r)
-    taus = {"analytic_pred": [], "alg2_score": [], "mlp": []}
-    regret = {"analytic_pred": [], "alg2_score": [], "mlp": []}
+    names = ["analytic_pred"] + (["analytic_calibrated"] if fit else []) + ["alg2_score", "mlp"]
+    taus = {n: [] for n in names}
+    regret = {n: [] for n in names}
     for rs in by.values():
         if len(rs) < 2:
             continue
         meas = [r["measured_us"] for r in rs]
-        pred_mlp = list(np.exp(net.predict(np.array([r["features"] for r in rs], np.float32))))
-        for name, pred in (("analytic_pred", [r["pred_us"] for r in rs]),
-                           ("alg2_score", [r["score"] for r in rs]), ("mlp", pred_mlp)):
+        preds = {"analytic_pred": [r["pred_us"] for r in rs], "alg2_score": [r["score"] for r in rs],
+                 "mlp": list(np.exp(net.predict(np.array([r["features"] for r in rs], np.float32))))}
+        if fit:
+            preds["analytic_calibrated"] = [calibrated(fit, r) for r in rs]
+        for name in names:
+            pred = preds[name]
             taus[name].append(kendall_tau(pred, meas))
             regret[name].append(meas[int(np.argmin(pred))] / min(meas))
     out = {}
@@ -488,10 +493,11 @@ def main(argv=None):
         tr, te = split_tags(rows)
         train_rows = [r for r in rows if r["pipeline"] in tr]
         net = train(train_rows, a.model, epochs=a.epochs, log=log)
+        fit = fit_analytic(train_rows)
         rep = {"train_pipelines": len(tr), "test_pipelines": len(te), "train_rows": len(train_rows),
-               "test_rows": len(rows) - len(train_rows),
-               "train": ranking_report(train_rows, net),
-               "test": ranking_report([r for r in rows if r["pipeline"] in te], net)}
+               "test_rows": len(rows) - len(train_rows), "analytic_fit": fit,
+               "train": ranking_report(train_rows, net, fit),
+               "test": ranking_report([r for r in rows if r["pipeline"] in te], net, fit)}
         log(json.dumps(rep))
         if a.report:
             with open(a.report, "w") as f:
