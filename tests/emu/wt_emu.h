@@ -54,7 +54,8 @@ static inline int wt_emu_dpp(int old, int src, int ctrl, bool bound_ctrl) {
 #define __builtin_amdgcn_readlane(v, l) ((int)wt_emu_xchg((uint32_t)(v), (l)))
 #define __builtin_amdgcn_readfirstlane(v) ((int)wt_emu_xchg((uint32_t)(v), 0))
 #define __builtin_amdgcn_wave_barrier() wt_emu_bar->arrive_and_wait()
-// one-wave workgroups only (the emulator runs a workgroup's waves one after another)
+// a barrier over the threads the runner started together: one wave, or a
+// whole workgroup for one-tile-per-workgroup kernels
 #define __syncthreads() wt_emu_bar->arrive_and_wait()
 #define __builtin_amdgcn_fence(a, b) ((void)0)
 

@@ -55,6 +55,43 @@ extern "C" int wt_emu_run(const WtArgs* a, int nwaves, int wpb) {
     for (auto& t : th) t.join();
     return 0;
 }
+// one-tile-per-workgroup kernels: all waves of a workgroup run together
+// (their __syncthreads is a barrier over 64 * wpb threads; they use no lane
+// exchanges)
+extern "C" int wt_emu_run_wg(const WtArgs* a, int nblocks, int wpb) {
+    std::barrier<> bar(64 * wpb);
+    wt_emu_bar = &bar;
+    std::vector<std::thread> th;
+    for (int t = 0; t < 64 * wpb; ++t)
+        th.emplace_back([&, t] {
+            wt_emu_lane = t & 63;
+            for (int b = 0; b < nblocks; ++b) {
+                blockIdx.x = b; threadIdx.x = t; gridDim.x = nblocks;
+                bar.arrive_and_wait();
+                WT_EMU_KERNEL(*a);
+                bar.arrive_and_wait();
+            }
+        });
+    for (auto& t : th) t.join();
+    return 0;
+}
+extern "C" int wt_emu_run_wg_batch(const WtArgs* ab, const int* start, int nimg, int total, int nblocks, int wpb) {
+    std::barrier<> bar(64 * wpb);
+    wt_emu_bar = &bar;
+    std::vector<std::thread> th;
+    for (int t = 0; t < 64 * wpb; ++t)
+        th.emplace_back([&, t] {
+            wt_emu_lane = t & 63;
+            for (int b = 0; b < nblocks; ++b) {
+                blockIdx.x = b; threadIdx.x = t; gridDim.x = nblocks;
+                bar.arrive_and_wait();
+                WT_EMU_KERNEL_BATCH(ab, start, nimg, total);
+                bar.arrive_and_wait();
+            }
+        });
+    for (auto& t : th) t.join();
+    return 0;
+}
 extern "C" int wt_emu_run_batch(const WtArgs* ab, const int* start, int nimg, int total, int nblocks, int wpb) {
     std::barrier<> bar(64);
     wt_emu_bar = &bar;
@@ -109,7 +146,14 @@ def _compile(src, kname):
     lib.wt_emu_run_grid.argtypes = [ctypes.POINTER(Args)] + [ctypes.c_int] * 4
     lib.wt_emu_run_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 4
     lib.wt_emu_run_grid_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 3
+    lib.wt_emu_run_wg.argtypes = [ctypes.POINTER(Args), ctypes.c_int, ctypes.c_int]
+    lib.wt_emu_run_wg_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 4
     return lib
+
+
+def _is_blk(plan, g):
+    """Whether group g runs one tile per workgroup (BLK=1 in its schedule)."""
+    return "BLK=1" in plan.describe().splitlines()[g].split()
 
 
 def _meta(spec):
@@ -184,6 +228,8 @@ def emulate(spec, inputs, **plan_kw):
         a.tiles_x, a.tiles_y, a.nwaves = gi.tiles_x, gi.tiles_y, gi.nwaves
         if gi.resample:
             lib.wt_emu_run_grid(ctypes.byref(a), gi.tiles_x, gi.tiles_y, gi.channels, 256)
+        elif _is_blk(plan, g):
+            lib.wt_emu_run_wg(ctypes.byref(a), gi.nwaves // gi.waves_per_group, gi.waves_per_group)
         else:
             lib.wt_emu_run(ctypes.byref(a), gi.nwaves, gi.waves_per_group)
     plan.emu_buffers = bufs  # node id -> array, for diagnosis
@@ -245,13 +291,20 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
                 a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
             a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
             a.tiles_x, a.tiles_y = gi.tiles_x, gi.tiles_y
-            work = gi.tiles_x * gi.tiles_y * gi.channels if gi.resample else gi.nwaves
+            if gi.resample:
+                work = gi.tiles_x * gi.tiles_y * gi.channels
+            elif _is_blk(plan, g):
+                work = gi.nwaves // gi.waves_per_group  # one workgroup per tile
+            else:
+                work = gi.nwaves
             a.nwaves = gi.nwaves
             start[k] = total
             total += work
         start[len(images)] = total
         if resample:
             lib.wt_emu_run_grid_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks)
+        elif _is_blk(plans[0], g):
+            lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
         else:
             lib.wt_emu_run_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
     return [{o: _result(b[names.index(o)]) for o in spec["outputs"]} for (_, _, b) in bufs_all]

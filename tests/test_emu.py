@@ -99,6 +99,10 @@ def test_batched_persistent_kernels_emulated():
                          fixed="nodes=1,2,3,4 V=1 TX=2 SX=0 TY=8 PF=1")
     for inp, got in zip(images, outs):
         check_unsharp(got["mask"], inp["img"], 1e-5, spec)
+    # one tile per workgroup, four waves sharing each tile
+    outs = emulate_batch(spec, images, nblocks=2, mode="fixed", fixed="nodes=1,2,3,4 V=1 TX=1 TY=8 WPB=4 BLK=1")
+    for inp, got in zip(images, outs):
+        check_unsharp(got["mask"], inp["img"], 1e-5, spec)
     spec = P.pyramid_blend(3)
     sizes = [(45, 37), (30, 21)]
     images = [{"A": synth.uniform_image(50 + i, 1, h, w), "B": synth.uniform_image(60 + i, 1, h, w),
@@ -222,6 +226,9 @@ def test_pyramid_schedule_expands_and_decimates():
     (UM, "nodes=1,2,3,4 V=2 TX=1 TY=5 BLK=1", 200, 13),
     (HARRIS_EXACT, "nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=1 TY=8 BLK=1", 70, 19),
     (P.integer_unsharp(), "nodes=1,2,3,4 V=1 TX=2 TY=6 BLK=1", 150, 11),
+    (UM, "nodes=1,2,3,4 V=1 TX=1 TY=16 WPB=4 BLK=1", 140, 37),
+    (HARRIS_EXACT, "nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=1 TY=8 WPB=8 BLK=1", 90, 21),
+    (BLUR, "nodes=1,2 V=2 TX=1 TY=8 WPB=16 BLK=1", 260, 20),
 ])
 def test_one_tile_per_workgroup_emulated(spec, fixed, w, h):
     if spec["inputs"][0].get("dtype") == "u8":
