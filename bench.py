@@ -29,7 +29,7 @@ METRIC = "Mpixels/s per pipeline, fused vs unfused on 1 GPU; % of HBM roofline"
 C, H, W = 3, 2048, 2048
 BYTES_PER_PX = 24  # 3 channels x (4 B in + 4 B out)
 HBM_PEAK_GBS = 8000.0
-OTPTB_FUSED = "nodes=1,2,3,4 V=2 TX=1 TY=16 WPB=4 BLK=1"
+OTPTB_FUSED = "nodes=1,2,3,4 V=1 TX=1 TY=16 WPB=4 BLK=1"
 DEFAULT_FUSED = "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1"
 
 

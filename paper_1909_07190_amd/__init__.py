@@ -157,8 +157,19 @@ class Pipeline:
     def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
              no_device=False, model_path=None, cache_dir=None, autotune_topk=0,
              any_width=False, no_compile=False) -> "Plan":
+        """Schedules and compiles the pipeline for width x height.  mode
+        "mlp" without a model_path uses the network trained on gfx950
+        measurements that ships with the package (GFX950_COST_MODEL)."""
+        if mode == "mlp" and model_path is None:
+            model_path = GFX950_COST_MODEL
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
                     autotune_topk, any_width, no_compile)
+
+
+# The cost network trained on gfx950: 4444 timed candidate groups of 93
+# random pipelines (learn.py train); its ranking report on the held-out
+# pipelines is gfx950_cost_mlp_report.json beside it.
+GFX950_COST_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gfx950_cost_mlp.txt")
 
 
 def from_spec(spec: dict) -> Pipeline:
