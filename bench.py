@@ -143,10 +143,12 @@ def bench_other(args, torch, wt, synth, P):
         nsets = max(2, min(8, int(1.2e9 // (base.numel() * 4 * 1.33)) or 2))
         ins = [base.clone() for _ in range(nsets)]
         outs = [torch.empty((1, H_, W_), device=dev) for _ in range(nsets)]
-        for mode, fp16 in (("autotune", True), ("autotune", False), ("unfused", False)):
-            plan = wt.from_spec(spec).plan(W_, H_, mode=mode, fp16=fp16)
+        legs = (("autotune", True, None), ("autotune", False, None), ("mlp", False, None),
+                ("autotune", False, wt.GFX950_COST_MODEL), ("unfused", False, None))
+        for mode, fp16, model in legs:
+            plan = wt.from_spec(spec).plan(W_, H_, mode=mode, fp16=fp16, model_path=model)
             ms = time_plan(torch, plan, ins, outs, args.steps, args.warmup, cyc)
-            key = f"{mode}{'_fp16' if fp16 else ''}"
+            key = f"{'mlp_' if model else ''}{mode}{'_fp16' if fp16 else ''}"
             res[key] = {"Mpix/s": H_ * W_ / (ms * 1e-3) / 1e6, "us": ms * 1e3,
                         "GB/s_algorithmic": bpp * H_ * W_ / (ms * 1e-3) / 1e9,
                         "kernels": plan.num_groups, "schedule": plan.describe().strip()}
@@ -164,7 +166,7 @@ def bench_other(args, torch, wt, synth, P):
             px += w * h
         # plans are scheduled (and autotuned) at the median image size
         mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
-        for mode in ("autotune", "analytic", "unfused"):
+        for mode in ("autotune", "mlp", "analytic", "unfused"):
             plan = wt.from_spec(spec).plan(mw, mh, mode=mode, any_width=True)
             for _ in range(2):
                 plan.run_batch(ins, outs)
@@ -283,6 +285,15 @@ def main():
         extra["one_tile_per_workgroup"] = {"value": H * W / (ms_b * 1e-3) / 1e6, "ms_per_step": ms_b,
                                            "schedule": OTPTB_FUSED, "wave_tile_speedup": ms_b / ms}
         log(f"one tile per workgroup: {ms_b * 1e3:.2f} us/step, wave tiles {ms_b / ms:.2f}x faster")
+        # what the schedulers choose for this pipeline on their own
+        sched = {}
+        for mode in ("mlp", "analytic"):
+            pl = wt.from_spec(spec).plan(W, H, mode=mode)
+            ms_s = time_plan(torch, pl, ins, outs, args.steps, args.warmup, cyc)
+            sched[mode] = {"value": H * W / (ms_s * 1e-3) / 1e6, "ms_per_step": ms_s,
+                           "schedule": pl.describe().strip()}
+            log(f"{mode} schedule: {ms_s * 1e3:.2f} us/step ({pl.describe().strip()})")
+        extra["schedulers"] = sched
     copy = copy_reference(torch, ins, outs, args.steps, cyc)
     log(f"device copy reference: {copy['GB/s']:.0f} GB/s")
     cpu = None if args.no_cpu else cpu_baseline(img)

@@ -279,7 +279,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     double t_mem = hbm_bytes / (m.hbm_bw * std::max(eff, 0.02));
     double t_alu = c.valu_ops * 64 / (m.ncu * m.simd_per_cu * 16.0 * m.clock_hz);
     c.pred_us = std::max(t_mem, t_alu) * 1e6 + m.launch_us;
-    c.cal_us = calibrated_us(c.pred_us, c.alg2.terms, kGfx950Fit);
+    c.cal_us = calibrated_us(c.pred_us, c.alg2.terms, active_fit());
     return c;
 }
 

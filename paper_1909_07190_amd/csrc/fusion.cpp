@@ -15,6 +15,7 @@
 // roofline-style predicted time, combined with coefficients refitted on
 // gfx950 measurements (the paper's score alone ranks configurations but has
 // no unit to sum); with the learned model, its predicted time.
+#include <string>
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -212,6 +213,37 @@ const double kGfx950Weights[7] = {50, 0.5, 60, 10, 2, 100, 1};
 // has log-correlation 0.84 with the measurements, Kendall tau 0.58 over
 // each group's candidates and a top-1 regret of 1.17 (geomean).
 const AnalyticFit kGfx950Fit = {-0.34099, 0.61802, {0.30606, 1.35482, 0.0, 0.0, 0.0, 0.0, 0.0}};
+
+const AnalyticFit& active_fit() {
+    static const AnalyticFit fit = [] {
+        AnalyticFit f = kGfx950Fit;
+        const char* e = std::getenv("WT_ANALYTIC_FIT");
+        if (!e || !*e) return f;
+        double v[9];
+        int n = 0;
+        std::string text(e);
+        size_t pos = 0;
+        while (n < 9 && pos <= text.size()) {
+            size_t q = text.find(',', pos);
+            std::string tok = text.substr(pos, q == std::string::npos ? std::string::npos : q - pos);
+            char* end = nullptr;
+            v[n] = std::strtod(tok.c_str(), &end);
+            if (tok.empty() || end != tok.c_str() + tok.size() || !std::isfinite(v[n])) break;
+            ++n;
+            if (q == std::string::npos) break;
+            pos = q + 1;
+        }
+        if (n != 9) {
+            std::fprintf(stderr, "wavetile: WT_ANALYTIC_FIT needs 9 comma-separated numbers; using the built-in fit\n");
+            return f;
+        }
+        f.c0 = v[0];
+        f.c1 = v[1];
+        for (int k = 0; k < 7; ++k) f.w[k] = v[2 + k];
+        return f;
+    }();
+    return fit;
+}
 
 std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,
                                         const std::vector<int>& nodes) {

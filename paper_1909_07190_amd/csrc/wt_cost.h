@@ -55,7 +55,7 @@ struct GroupCost {
     double requested_bytes = 0, compulsory_bytes = 0, valu_ops = 0;
     long long nwaves = 0;
     double code_ops = 0;         // straight-line VALU operations per kernel body
-    double cal_us = 0;           // calibrated time (kGfx950Fit)
+    double cal_us = 0;           // calibrated time (active_fit())
 };
 GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& geo, const Machine& m, int W,
                      int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7]);
@@ -80,6 +80,9 @@ struct AnalyticFit {
     double c0, c1, w[7];
 };
 extern const AnalyticFit kGfx950Fit;
+// The fit in use: kGfx950Fit, or nine numbers "c0,c1,w0,...,w6" from
+// $WT_ANALYTIC_FIT (read once; for evaluating refits without a rebuild).
+const AnalyticFit& active_fit();
 double calibrated_us(double pred_us, const double terms[7], const AnalyticFit& f);
 
 // 40 features of a (group, configuration) for the learned cost model:

@@ -117,11 +117,15 @@ def _parse_groups(describe_text):
 # ------------------------------------------------------------------ collect --
 
 def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_groups=6,
-            reps=20, seed=0, log=print, compile_only=False):
+            reps=20, seed=0, log=print, compile_only=False, picks_only=False):
     """Times candidate groups of every pipeline in `specs` (dict tag -> spec);
     appends to the database `db` (JSON lines).  The candidates of a pipeline
     depend only on (seed, tag), so `compile_only` can fill the code cache on a
-    machine without a device ahead of the timing run."""
+    machine without a device ahead of the timing run.  With `picks_only`, only
+    the groups of the analytical model's current plan, at its chosen
+    configurations, are timed: the rows that correct the model where its own
+    choices lead it (a refit on them is one round of learning from the
+    model's mistakes)."""
     if not compile_only:
         os.environ["WT_MEASURE_DB"] = db
     n_total = 0
@@ -136,16 +140,20 @@ def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_grou
         texts = []
         groups = []
         for i in dag.stages:
+            if picks_only:
+                break
             groups.append(([i], 1 if dag.fusable(i) else 0))
             if not dag.fusable(i):
                 texts.append(_group_text([i]))
-        for _ in range(random_groups):
+        for _ in range(0 if picks_only else random_groups):
             g = dag.random_group(rng, rng.randint(2, 12))
             if g:
                 groups.append((g, configs_per_group))
         plan = pipe.plan(width, height, mode="analytic", no_compile=True)
         for nodes, text in _parse_groups(plan.describe()):
-            groups.append((nodes, configs_per_group))
+            if len(nodes) == 1 and not dag.fusable(nodes[0]):
+                continue  # resampling kernels have no model features
+            groups.append((nodes, 0 if picks_only else configs_per_group))
             texts.append(text)  # the analytical pick itself
         seen = set(texts)
         for nodes, k in groups:
@@ -258,18 +266,23 @@ def ranking_report(rows, net, fit=None):
 
 # ------------------------------------------------------- analytical refit --
 
-def fit_analytic(rows):
+def fit_analytic(rows, weights=None):
     """Refits the analytical model on gfx950 measurements: least squares of
     log(measured time) on an intercept, log(the roofline-style predicted
     time) and Algorithm 2's seven terms, with non-negative coefficients on
     the terms (they are penalties) and on log(predicted time).  Returns
     {"c0", "c1", "w": [7]}; the model's calibrated time is
-    exp(c0 + c1 log(pred_us) + sum_k w_k term_k)."""
+    exp(c0 + c1 log(pred_us) + sum_k w_k term_k).  `weights` (one per row)
+    weight the squared residuals."""
     from scipy.optimize import lsq_linear
 
-    rows = [r for r in rows if math.isfinite(r.get("pred_us", float("inf"))) and r["pred_us"] > 0]
-    a = np.array([[1.0, math.log(r["pred_us"])] + list(r["terms"]) for r in rows])
-    b = np.log(np.array([r["measured_us"] for r in rows]))
+    if weights is None:
+        weights = [1.0] * len(rows)
+    keep = [i for i, r in enumerate(rows) if math.isfinite(r.get("pred_us", float("inf"))) and r["pred_us"] > 0]
+    rows = [rows[i] for i in keep]
+    sw = np.sqrt(np.array([weights[i] for i in keep], np.float64))
+    a = np.array([[1.0, math.log(r["pred_us"])] + list(r["terms"]) for r in rows]) * sw[:, None]
+    b = np.log(np.array([r["measured_us"] for r in rows])) * sw
     lo = [-np.inf] + [0.0] * 8
     res = lsq_linear(a, b, bounds=(lo, [np.inf] * 9))
     x = res.x
@@ -368,7 +381,11 @@ def best_measured_schedule(dag, rows, resample_us):
     return t, ";".join(texts)
 
 
-def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, log=print, out_path=None):
+ALL_MODES = ("unfused", "analytic", "mlp", "autotune", "mlp_autotune", "best_measured")
+
+
+def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, log=print, out_path=None,
+             modes=ALL_MODES):
     import torch
 
     dev = torch.device("cuda:0")
@@ -387,16 +404,17 @@ def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, 
                 w, h = (w + 1) // 2, (h + 1) // 2
             outs.append(torch.empty((1, h, w), device=dev))
         res = {"pipeline": tag, "stages": len(spec["stages"])}
-        plans = {
-            "unfused": pipe.plan(width, height, mode="unfused"),
-            "analytic": pipe.plan(width, height, mode="analytic"),
-            "mlp": pipe.plan(width, height, mode="mlp", model_path=model_path),
-            "autotune": pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk),
-            "mlp_autotune": pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk,
-                                      model_path=model_path),
+        make = {
+            "unfused": lambda: pipe.plan(width, height, mode="unfused"),
+            "analytic": lambda: pipe.plan(width, height, mode="analytic"),
+            "mlp": lambda: pipe.plan(width, height, mode="mlp", model_path=model_path),
+            "autotune": lambda: pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk),
+            "mlp_autotune": lambda: pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk,
+                                              model_path=model_path),
         }
+        plans = {m: make[m]() for m in modes if m in make}
         drows = [r for r in rows if r["pipeline"] == tag]
-        if drows:
+        if drows and "best_measured" in modes:
             res_us = {}
             for i in dag.stages:
                 if not dag.fusable(i):
@@ -409,8 +427,7 @@ def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, 
         for name, plan in plans.items():
             res[name + "_us"] = _time_plan(torch, plan, ins, outs)
             res[name + "_groups"] = plan.num_groups
-        best = min(v for k, v in res.items() if k.endswith("_us") and not k.endswith("sum_us"))
-        res["best_us"] = best
+        res["best_us"] = min(v for k, v in res.items() if k.endswith("_us") and not k.endswith("sum_us"))
         results.append(res)
         log(json.dumps(res))
         if out_path:  # one line per pipeline as it completes
@@ -459,6 +476,8 @@ def main(argv=None):
     c.add_argument("--size", type=int, default=2048)
     c.add_argument("--compile-only", action="store_true",
                    help="only compile the candidates into $WT_CACHE_DIR (no device needed)")
+    c.add_argument("--picks-only", action="store_true",
+                   help="time only the analytical model's current picks")
     t = sub.add_parser("train", help="train the network on the device")
     t.add_argument("--db", required=True, nargs="+")
     t.add_argument("--model", required=True)
@@ -467,6 +486,8 @@ def main(argv=None):
     f = sub.add_parser("fit-analytic", help="refit the analytical model's coefficients")
     f.add_argument("--db", required=True, nargs="+")
     f.add_argument("--out", help="write the fit and its report (JSON) here")
+    f.add_argument("--picks-db", nargs="+", help="rows of the model's own picks, from collect --picks-only")
+    f.add_argument("--picks-weight", type=float, default=5.0, help="weight of each picks row in the fit")
     e = sub.add_parser("evaluate", help="compare whole-plan schedules on held-out pipelines")
     e.add_argument("--db", required=True, nargs="+")
     e.add_argument("--model", required=True)
@@ -474,6 +495,7 @@ def main(argv=None):
     e.add_argument("--skip", type=int, default=0, help="skip the first held-out pipelines")
     e.add_argument("--size", type=int, default=2048)
     e.add_argument("--out", help="append per-pipeline JSON lines here")
+    e.add_argument("--modes", help="comma-separated subset of " + ",".join(ALL_MODES))
     sm = sub.add_parser("summarize", help="summarise per-pipeline evaluation lines")
     sm.add_argument("--results", required=True, nargs="+")
     a = ap.parse_args(argv)
@@ -487,7 +509,7 @@ def main(argv=None):
     if a.cmd == "collect":
         specs = {f"dag{s}": dags.random_dag(s) for s in _seeds(a.seeds)}
         collect(specs, a.db, a.size, a.size, a.configs, a.random_groups, log=log,
-                compile_only=a.compile_only)
+                compile_only=a.compile_only, picks_only=a.picks_only)
     elif a.cmd == "train":
         rows = load_db(a.db)
         tr, te = split_tags(rows)
@@ -507,7 +529,10 @@ def main(argv=None):
         tr, te = split_tags(rows)
         train_rows = [r for r in rows if r["pipeline"] in tr]
         test_rows = [r for r in rows if r["pipeline"] in te]
-        fit = fit_analytic(train_rows)
+        # the model's own picks (collect --picks-only) on training pipelines
+        picks = [r for r in load_db(a.picks_db) if r["pipeline"] in tr] if a.picks_db else []
+        fit = fit_analytic(train_rows + picks, [1.0] * len(train_rows) + [a.picks_weight] * len(picks))
+        fit["picks_rows"] = len(picks)
         rep = {"fit": fit, "train": analytic_report(train_rows, fit), "test": analytic_report(test_rows, fit)}
         log(json.dumps(rep))
         if a.out:
@@ -527,7 +552,8 @@ def main(argv=None):
         if a.max_pipelines:
             tags = tags[:a.max_pipelines]
         specs = {tg: dags.random_dag(int(tg[3:])) for tg in tags}
-        res = evaluate(specs, rows, a.model, a.size, a.size, log=log, out_path=a.out)
+        modes = tuple(a.modes.split(",")) if a.modes else ALL_MODES
+        res = evaluate(specs, rows, a.model, a.size, a.size, log=log, out_path=a.out, modes=modes)
         log(json.dumps(summarize(res)))
 
 

@@ -102,3 +102,35 @@ def test_fusion_dp_equals_exhaustive(name):
     assert dp == pytest.approx(ex, rel=1e-12)
     dp4, ex4 = fusion_costs(spec, 512, 384, k=3)
     assert dp4 == pytest.approx(ex4, rel=1e-12) and dp4 >= dp - 1e-9
+
+
+def test_analytic_fit_override_from_environment():
+    """WT_ANALYTIC_FIT replaces the built-in calibration (nine numbers); a
+    malformed value falls back to the built-in fit with a message."""
+    import os
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, '.'); import paper_1909_07190_amd as wt; "
+            "from synth import pipelines as P; "
+            "print(wt.from_spec(P.unsharp_mask()).plan(2048, 2048, mode='analytic', no_device=True, "
+            "no_compile=True).describe())")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+    def plan_text(fit):
+        env = dict(os.environ)
+        env.pop("WT_ANALYTIC_FIT", None)
+        if fit is not None:
+            env["WT_ANALYTIC_FIT"] = fit
+        r = subprocess.run([sys.executable, "-c", code], cwd=root, env=env, capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr
+        return r.stdout.strip(), r.stderr
+
+    base, _ = plan_text(None)
+    # a huge weight on (1 - occupancy) versus one on the overlap fraction
+    # lead to different configurations
+    occ, _ = plan_text("0,1,0,50,0,0,0,0,0")
+    ovl, _ = plan_text("0,1,0,0,0,0,0,50,0")
+    assert occ != ovl
+    bad, err = plan_text("1,2,3")
+    assert bad == base and "WT_ANALYTIC_FIT" in err
