@@ -236,6 +236,14 @@ wt_status wt_fusion_costs(const wt_pipeline* p, int width, int height, int fp16,
  * `ws`, and the scratchpad elements of one block for tile[3] and overlap[3]:
  * prod_i ceil(block_i / warp_i) * (tile_i * warp_i + overlap_i). */
 wt_status wt_alg2_eval(int machine, const double* in, const double* w, double* out);
+
+/* Achievable-bandwidth reference (not a pipeline operation): copies `bytes`
+ * bytes from `src` to `dst`, both device pointers owned by the caller,
+ * 16-byte aligned and not overlapping, asynchronously on `stream` (a
+ * hipStream_t; NULL = the null stream), one 16-byte element per thread with
+ * nontemporal loads and stores.  WT_E_INVALID for null or misaligned
+ * pointers or overlapping ranges; WT_E_HIP when the launch fails. */
+wt_status wt_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
 wt_status wt_otpw_geometry(const int* block, int ws, const int* tile, const int* overlap, int* warp,
                            int64_t* scratch_elems);
 

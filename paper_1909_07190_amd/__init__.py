@@ -80,6 +80,7 @@ _sig("wt_plan_run", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtImage), ctyp
      ctypes.POINTER(WtImage), ctypes.c_int, ctypes.c_void_p)
 _sig("wt_plan_run_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
+_sig("wt_stream_copy", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _sig("wt_plan_describe", ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t,
      ctypes.POINTER(ctypes.c_size_t))
 _sig("wt_plan_source", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t,
@@ -164,6 +165,21 @@ class Pipeline:
             model_path = GFX950_COST_MODEL
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
                     autotune_topk, any_width, no_compile)
+
+
+def stream_copy(src, dst, stream=None):
+    """Copies device tensor `src` into `dst` (same byte size, contiguous)
+    with the library's streaming copy kernel, the achievable-bandwidth
+    reference, on `stream` (default: torch's current stream)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_contiguous() and dst.is_contiguous()) or dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("stream_copy needs contiguous tensors of equal byte size")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib.wt_stream_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                              ctypes.c_void_p(s)))
 
 
 # The cost network trained on gfx950: 4444 timed candidate groups of 93

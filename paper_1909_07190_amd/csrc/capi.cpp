@@ -447,6 +447,18 @@ wt_status wt_otpw_geometry(const int* block, int ws, const int* tile, const int*
     });
 }
 
+wt_status wt_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    return guard([&] {
+        if (bytes == 0) return;
+        if (!src || !dst) wt::fail(WT_E_INVALID, "null pointer");
+        if (((uintptr_t)src | (uintptr_t)dst) % 16) wt::fail(WT_E_INVALID, "pointers must be 16-byte aligned");
+        const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+        if (a < b + bytes && b < a + bytes) wt::fail(WT_E_INVALID, "source and destination overlap");
+        hipError_t e = wt::stream_copy(src, dst, bytes, (hipStream_t)stream);
+        if (e != hipSuccess) wt::fail(WT_E_HIP, std::string("stream copy: ") + hipGetErrorString(e));
+    });
+}
+
 wt_status wt_mlp_create(const int* dims, int nlayers, uint64_t seed, wt_mlp** out) {
     return guard([&] {
         if (!dims || !out || nlayers < 2 || nlayers > 16) wt::fail(WT_E_INVALID, "bad mlp arguments");

@@ -10,6 +10,10 @@
 
 namespace wt {
 
+// Streaming device copy, the benchmark's achievable-bandwidth reference
+// (copyref.hip).
+hipError_t stream_copy(const void* src, void* dst, size_t bytes, hipStream_t stream);
+
 struct Mlp {
     std::vector<int> dims;              // layer widths, input first
     std::vector<size_t> woff, boff;     // offsets of W_l (dims[l] x dims[l+1], row-major) and b_l

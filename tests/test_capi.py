@@ -150,3 +150,15 @@ def test_preprofiling_microbenchmarks_compile_for_gfx950():
             if st["kind"] in ("stencil", "pointwise"):
                 ns, vg, measured = wt.stage_profile(pipe, nin + k, 128, 64, measure=False)
                 assert ns > 0 and vg >= 2 and not measured
+
+
+def test_stream_copy_argument_checks():
+    """The copy reference rejects null, misaligned and overlapping ranges
+    before touching the device (host-side checks only)."""
+    import ctypes
+    lib = wt.lib
+    assert lib.wt_stream_copy(None, None, 0, None) == 0  # nothing to copy
+    assert lib.wt_stream_copy(None, ctypes.c_void_p(4096), 64, None) == -1
+    assert lib.wt_stream_copy(ctypes.c_void_p(4100), ctypes.c_void_p(8192), 64, None) == -1  # misaligned
+    assert lib.wt_stream_copy(ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 32), 64, None) == -1  # overlap
+    assert "overlap" in lib.wt_last_error().decode()

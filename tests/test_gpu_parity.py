@@ -387,3 +387,19 @@ def test_consumed_liveout_rows_stored(fixed, w, h):
     ref = oracle.evaluate(BLUR_BOTH, {"img": img})
     for k in BLUR_BOTH["outputs"]:
         assert_exact(got[k], ref[k], f"{fixed}: {k}")
+
+
+# --------------------------------------------- achievable-bandwidth reference
+@pytest.mark.parametrize("nbytes", [16, 4096 + 12, 3 * 2048 * 2048 * 4])
+def test_stream_copy_reference(nbytes):
+    """The library's streaming copy reproduces its source byte for byte,
+    including a tail shorter than one 16-byte element."""
+    import torch
+    import paper_1909_07190_amd as wt
+    _say(f"stream copy {nbytes} bytes")
+    g = torch.Generator(device="cuda:0").manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, device="cuda:0", generator=g)
+    dst = torch.zeros_like(src)
+    wt.stream_copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
