@@ -7,6 +7,8 @@
 // for every group (rewritten before each run, so only the pointers of the
 // caller's images may change between runs), the per-group work prefix sums
 // and the instantiated graph.
+#include <cstdlib>
+#include <cstdio>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +40,12 @@ int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads) {
     int waves_wg = (threads + 63) / 64;
     int own = std::max(1, 4 * waves_simd / waves_wg);
     if (lds > 0) own = std::max(1, std::min(own, plan.machine.lds_per_cu / lds));
-    return std::max(api, own);
+    int res = std::max(api, own);
+    if (const char* e = std::getenv("WT_DEBUG_BATCH"))
+        if (*e && *e != '0')
+            std::fprintf(stderr, "wavetile batch: threads=%d regs=%d lds=%d api=%d own=%d -> %d per CU\n", threads,
+                         regs, lds, api, own, res);
+    return res;
 }
 
 namespace {

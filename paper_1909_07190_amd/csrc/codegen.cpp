@@ -310,6 +310,60 @@ struct Gen {
                     line("float " + v + "[" + I(V) + "];");
                     for (int e = 0; e < V; ++e) dst.push_back(v + "[" + I(e) + "]");
                 }
+                if (!border && V == 1) {
+                    // interior wave, one column per lane: lane t loads coarse
+                    // column bc + t (coalesced) of the three coarse rows,
+                    // blends them vertically, forms both horizontal phases
+                    // with its DPP neighbours (even: 1/8, 3/4, 1/8 of
+                    // columns c-1, c, c+1; odd: 1/2, 1/2 of c, c+1), and each
+                    // lane picks its phase of column x/2 from lane x/2 - bc
+                    // through the LDS crossbar: 3 loads and 2 lane gathers per
+                    // column instead of 9 gathered loads
+                    line("{ const int xs0 = x0 + " + I(n.skew) + " + " + I(k * SUB) + ";");
+                    line("  const int bc = (xs0 >> 1) - 1;");
+                    line("  const int cl = wt_clampi(bc + lane, 0, Wc - 1);");
+                    line("  const float q = fmaf(wy2, (float)r2[cl], fmaf(wy1, (float)r1[cl], wy0 * (float)r0[cl]));");
+                    line("  const float qm = wt_mov_shr1(q), qp = wt_mov_shl1(q);");
+                    line("  const float ev = fmaf(0.125f, qp, fmaf(0.75f, q, 0.125f * qm));");
+                    line("  const float od = fmaf(0.5f, qp, 0.5f * q);");
+                    line("  const int x = xs0 + lane;");
+                    line("  const int sa = (((x >> 1) - bc) & 63) << 2;");
+                    line("  const float e2 = wt_bperm(sa, ev), o2 = wt_bperm(sa, od);");
+                    line("  " + dst[0] + " = (x & 1) ? o2 : e2;");
+                    line("}");
+                    if (k < SX) emit_lds_store(n, slot, ch, k, v);
+                    continue;
+                }
+                if (!border && V % 2 == 0) {
+                    // interior wave, even V: a lane's first column is even
+                    // (tile origins, skews and sub-tile widths are multiples
+                    // of V), so its V columns share coarse columns
+                    // ib-1 .. ib+V/2 (V/2 + 2 loads per coarse row instead
+                    // of 3 per column) and each column's parity, hence its
+                    // horizontal weights, is known here
+                    const int nc = V / 2 + 2;
+                    line("{ const int ib = (x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) + ") >> 1;");
+                    for (int c = 0; c < nc; ++c)
+                        line("  const int xc" + I(c) + " = wt_clampi(ib + " + I(c - 1) + ", 0, Wc - 1);");
+                    const char* rows[3] = {"r0", "r1", "r2"};
+                    for (int r = 0; r < 3; ++r)
+                        for (int c = 0; c < nc; ++c)
+                            line("  const float c" + I(r) + "_" + I(c) + " = (float)" + rows[r] + "[xc" + I(c) + "];");
+                    for (int e = 0; e < V; ++e) {
+                        const int m = e / 2;
+                        std::string h[3];
+                        for (int r = 0; r < 3; ++r) {
+                            std::string a = "c" + I(r) + "_" + I(m), b = "c" + I(r) + "_" + I(m + 1),
+                                        cc = "c" + I(r) + "_" + I(m + 2);
+                            h[r] = (e % 2 == 0) ? "fmaf(0.125f, " + cc + ", fmaf(0.75f, " + b + ", 0.125f * " + a + "))"
+                                                : "fmaf(0.5f, " + cc + ", 0.5f * " + b + ")";
+                        }
+                        line("  " + dst[e] + " = fmaf(wy2, " + h[2] + ", fmaf(wy1, " + h[1] + ", wy0 * " + h[0] + "));");
+                    }
+                    line("}");
+                    if (k < SX) emit_lds_store(n, slot, ch, k, v);
+                    continue;
+                }
                 for (int e = 0; e < V; ++e) {
                     line("{ const int xf = wt_clampi(x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) +
                          " + " + I(e) + ", 0, W - 1);");

@@ -200,6 +200,14 @@ EXP_SPEC = {"inputs": [{"name": "img", "channels": 1}],
     ("nodes=1;nodes=3,4 V=1 TX=1 SX=0 TY=6 align=1 exp=2", 67, 13, False),
     ("nodes=1;nodes=3 V=1 TY=4 exp=2;nodes=4 V=1 exp=2", 67, 13, False),
     ("nodes=1;nodes=3,4 V=1 TX=2 SX=0 TY=7 exp=2 fp16=1", 65, 15, True),
+    # wide enough for interior waves (their even-V expansion path)
+    ("nodes=1;nodes=3,4 V=4 TX=1 SX=0 TY=8 exp=2", 700, 21, False),
+    ("nodes=1;nodes=3,4 V=2 TX=2 SX=1 TY=5 PF=1 exp=2", 601, 17, False),
+    ("nodes=1;nodes=3,4 V=2 TX=1 SX=0 TY=6 align=1 exp=2", 390, 13, False),
+    ("nodes=1;nodes=3,4 V=2 TX=1 SX=0 TY=8 exp=2 fp16=1", 402, 15, True),
+    ("nodes=1;nodes=3,4 V=1 TX=1 SX=0 TY=6 exp=2", 261, 13, False),
+    ("nodes=1;nodes=3,4 V=1 TX=2 SX=1 TY=5 PF=1 exp=2", 391, 17, False),
+    ("nodes=1;nodes=3,4 V=1 TX=2 SX=0 TY=8 align=1 exp=2 fp16=1", 333, 11, True),
 ])
 def test_expanded_up2_emulated(fixed, w, h, fp16):
     img = synth.uniform_image(3, 1, h, w)

@@ -289,6 +289,11 @@ RESAMPLE_SPEC = {"inputs": [{"name": "img", "channels": 2}],
     ("nodes=1,2 V=2 TX=2 SX=1 TY=5 PF=1 dec=3;nodes=5,6 V=2 TX=2 SX=1 TY=7 exp=4", 130, 17),
     ("nodes=1,2 V=1 TX=1 SX=0 TY=6 align=1 dec=3;nodes=5 V=1 exp=4;nodes=6 V=1 exp=4", 67, 13),
     (None, 2048, 1024),
+    # interior waves with even V (the shared-coarse-column expansion)
+    ("nodes=1,2 V=4 TX=1 SX=0 TY=8 dec=3;nodes=5,6 V=4 TX=1 SX=0 TY=16 exp=4", 1032, 37),
+    ("nodes=1,2 V=2 TX=1 SX=0 TY=8 dec=3;nodes=5,6 V=2 TX=2 SX=1 TY=7 PF=1 exp=4", 602, 23),
+    ("nodes=1,2 V=1 TX=2 SX=0 TY=8 dec=3;nodes=5,6 V=1 TX=2 SX=1 TY=7 PF=1 exp=4", 517, 29),
+    ("nodes=1,2 V=1 TX=1 SX=0 TY=8 dec=3;nodes=5,6 V=1 TX=1 SX=0 TY=16 PF=2 align=1 exp=4", 389, 40),
 ])
 def test_fused_resampling(fixed, w, h):
     _say(f"fused resampling {fixed} {w}x{h}")
