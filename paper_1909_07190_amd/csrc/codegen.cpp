@@ -82,6 +82,16 @@ struct Gen {
     }
 
     bool has_regs(const NodeGeom& n) const { return RX > 0 && (n.consumed || !n.member); }
+    // ghost registers of a loaded node (GH=1): lanes 64-nl..63 of `gl` hold
+    // the nl*V columns left of slot 0 (as lanes of a sub-tile -1 would), lanes
+    // 0..nr-1 of `gr` the nr*V columns right of the last slot; a single ghost
+    // lane is kept where its one-lane shift lands instead (lane 0 of `gl`,
+    // lane 63 of `gr`)
+    int ghost_lanes_l(const NodeGeom& n) const { return (n.ghl + V - 1) / V; }
+    int ghost_lanes_r(const NodeGeom& n) const { return (n.ghr + V - 1) / V; }
+    std::string ghost(int id, bool left, int slot, int ch, int e) {
+        return "g" + I(id) + (left ? "l" : "r") + "[" + I(slot) + "][" + I(ch) + "][" + I(e) + "]";
+    }
     bool has_lds(const NodeGeom& n) const { return SX > 0 && (n.consumed || !n.member); }
     std::string reg(int id, int slot, int ch, int kr, int e) {
         return "w" + I(id) + "[" + I(slot) + "][" + I(ch) + "][" + I(kr) + "][" + I(e) + "]";
@@ -149,6 +159,13 @@ struct Gen {
                     std::string b = memoize(lread(p, slot, chp, I((k - 1) * SUB + 63 * V + ep)));
                     return xchg(p, "wt_shr1(" + cur + ", " + b + ")");
                 }
+                if (pg.ghl > 0) {
+                    // one ghost lane: it sits in lane 0 already, so a single
+                    // DPP shift keeps it there as the shift's old value
+                    std::string gv = ghost(p, true, slot, chp, ep);
+                    if (ghost_lanes_l(pg) == 1) return xchg(p, "wt_shr1(" + cur + ", " + gv + ")");
+                    return xchg(p, "wt_shift1(" + cur + ", " + gv + ")");
+                }
                 // lane 0 belongs to the overlap: any value
                 return xchg(p, "wt_mov_shr1(" + cur + ")");
             }
@@ -161,6 +178,11 @@ struct Gen {
                 std::string pv = memoize(lread(p, slot, chp, I((k - 1) * SUB) + " + ((lane - " + I(d) +
                                                                ") & 63) * " + I(V) + " + " + I(ep)));
                 return xchg(p, "wt_shiftd_l(" + cur + ", " + pv + ", " + I(d) + ", lane)");
+            }
+            if (pg.ghl > 0) {  // lanes t < d read the ghost lanes 64-d+t
+                std::string gv = ghost(p, true, slot, chp, ep);
+                if (d == 2) return xchg(p, "wt_shift2(" + cur + ", " + gv + ")");
+                return xchg(p, "wt_shiftd(" + cur + ", " + gv + ", " + I(d) + ", lane)");
             }
             if (d == 2) return xchg(p, "wt_shift2(" + cur + ", " + cur + ")");
             return xchg(p, "wt_shiftd(" + cur + ", " + cur + ", " + I(d) + ", lane)");
@@ -180,6 +202,13 @@ struct Gen {
             return memoize("(lane >= " + I(64 - d) + " ? " + rv + " : " + lv + ")");
         }
         std::string cur = reg(p, slot, chp, k - SX, ep);
+        if (k + 1 >= g.TX && pg.ghr > 0) {  // lanes t >= 64-d read the ghost lanes t+d-64
+            std::string gv = ghost(p, false, slot, chp, ep);
+            if (d == 1 && ghost_lanes_r(pg) == 1) return xchg(p, "wt_shl1(" + cur + ", " + gv + ")");
+            if (d == 1) return xchg(p, "wt_shift1n(" + cur + ", " + gv + ")");
+            if (d == 2) return xchg(p, "wt_shift2n(" + cur + ", " + gv + ")");
+            return xchg(p, "wt_shiftdn(" + cur + ", " + gv + ", " + I(d) + ", lane)");
+        }
         if (k + 1 >= g.TX) {  // lanes past the strip belong to the overlap: any value
             if (d == 1) return xchg(p, "wt_mov_shl1(" + cur + ")");
             if (d == 2) return xchg(p, "wt_shift2n(" + cur + ", " + cur + ")");
@@ -428,10 +457,45 @@ struct Gen {
                 line("}");
                 if (k < SX) emit_lds_store(n, slot, ch, k, v);
             }
+            if (n.ghl > 0) emit_ghost_load(li, n, true, slot, ch, ty, ct);
+            if (n.ghr > 0) emit_ghost_load(li, n, false, slot, ch, ty, ct);
             ind.resize(ind.size() - 4);
             line("}");
         }
         if (SX > 0) line("wt_wave_sync();");
+    }
+
+    // Ghost columns of a loaded row.  Every lane loads (lanes outside the
+    // ghost lanes repeat the nearest ghost lane's address, so the load stays
+    // within one or two cache lines and needs no branch); interior waves read
+    // in-bounds columns, border waves clamp each column like the main load.
+    // (Range-checked buffer loads with only the ghost lanes in range measured
+    // slower on gfx950 than these replicated-address loads.)
+    void emit_ghost_load(int li, const NodeGeom& n, bool left, int slot, int ch, const std::string& ty,
+                         const std::string& ct) {
+        (void)li;
+        const int nl = left ? ghost_lanes_l(n) : ghost_lanes_r(n);
+        std::string xg;
+        if (nl == 1)  // one lane, placed where the one-lane shift reads it
+            xg = left ? "x0 + " + I(n.skew) + " - " + I(V) : "x0 + " + I(n.skew) + " + " + I(g.TX * SUB);
+        else
+            xg = left ? "x0 + " + I(n.skew) + " - (64 - max(lane, " + I(64 - nl) + ")) * " + I(V)
+                      : "x0 + " + I(n.skew) + " + " + I(g.TX * SUB) + " + min(lane, " + I(nl - 1) + ") * " + I(V);
+        line("{ const int xg = " + xg + ";  // ghost columns " + std::string(left ? "left" : "right"));
+        std::vector<std::string> dst;
+        for (int e = 0; e < V; ++e) dst.push_back(ghost(n.id, left, slot, ch, e));
+        if (!border) {
+            if (V == 1) line("  " + dst[0] + " = (" + ct + ")rp[xg];");
+            else {
+                std::string vt = vec(ty, V);
+                line("  const " + vt + " q = *(const " + vt + "*)(rp + xg);");
+                for (int e = 0; e < V; ++e) line("  " + dst[e] + " = (" + ct + ")q[" + I(e) + "];");
+            }
+        } else {
+            for (int e = 0; e < V; ++e)
+                line("  " + dst[e] + " = (" + ct + ")rp[wt_clampi(xg + " + I(e) + ", 0, W - 1)];");
+        }
+        line("}");
     }
 
     void emit_lds_store(const NodeGeom& n, int slot, int ch, int k, const std::string& arr) {
@@ -695,9 +759,14 @@ struct Gen {
     void body(bool b) {
         border = b;
         ind += "    ";
-        for (auto& n : geo.nodes)
+        for (auto& n : geo.nodes) {
             if (has_regs(n))
                 line(ctype(n.id) + " w" + I(n.id) + "[" + I(n.win) + "][" + I(n.nch) + "][" + I(RX) + "][" + I(V) + "] = {};");
+            if (n.ghl > 0)
+                line(ctype(n.id) + " g" + I(n.id) + "l[" + I(n.win) + "][" + I(n.nch) + "][" + I(V) + "] = {};");
+            if (n.ghr > 0)
+                line(ctype(n.id) + " g" + I(n.id) + "r[" + I(n.win) + "][" + I(n.nch) + "][" + I(V) + "] = {};");
+        }
         for (int s = 0; s < geo.D; ++s) emit_step(s % geo.U, "y0 - " + I(geo.D - s), s, -1);
         if (geo.NMAIN > 0) {
             line("for (int it = 0; it < " + I(geo.NMAIN) + "; ++it) {");
@@ -778,7 +847,12 @@ struct Gen {
         line("const int x0 = tx * " + I(geo.X) + " + (" + I(geo.base) + ");");
         line("const int y0 = ty * " + I(g.TY) + ";");
         line("const int kend = y0 + " + I(g.TY) + ";");
-        line("const bool bx = (x0 + " + I(amin_) + " < 0) || (x0 + " + I(amax_) + " + " + I(N) + " > W);");
+        int gml = 0, gmr = 0;  // ghost columns read past the slots
+        for (auto& n : geo.nodes) {
+            gml = std::max(gml, ghost_lanes_l(n) * V);
+            gmr = std::max(gmr, ghost_lanes_r(n) * V);
+        }
+        line("const bool bx = (x0 + " + I(amin_ - gml) + " < 0) || (x0 + " + I(amax_ + gmr) + " + " + I(N) + " > W);");
         // buffer resources for the live-outs, one per channel plane
         for (size_t oi = 0; oi < geo.liveouts.size(); ++oi) {
             const NodeGeom& n = G(geo.liveouts[oi]);

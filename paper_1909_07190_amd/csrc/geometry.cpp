@@ -46,6 +46,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
     if (g.TY < 1 || g.TY > 1024) fail(WT_E_INVALID, "TY must be in 1..1024");
     if (g.WPB < 1 || g.WPB > 16) fail(WT_E_INVALID, "WPB must be in 1..16");
     if (g.PF < 0 || g.PF > 8) fail(WT_E_INVALID, "PF must be in 0..8");
+    if (g.GH != 0 && g.GH != 1) fail(WT_E_INVALID, "GH must be 0 or 1");
 
     GroupGeom geo;
     std::set<int> mem(g.nodes.begin(), g.nodes.end());
@@ -169,6 +170,31 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
             ng.win += g.PF;
         }
 
+    // ghost columns (GH=1): a plain loaded node carries, beyond its slots,
+    // the columns its member consumers read there, so it is valid on
+    // [-ghl, N + ghr) and those consumers on every slot
+    if (g.GH) {
+        if (g.SX != 0 || g.align != 0 || g.BLK) fail(WT_E_UNSUPPORTED, "GH=1 needs SX=0, align=0 and BLK=0");
+        for (auto& ng : geo.nodes) {
+            if (ng.member || ng.expand_src >= 0) continue;
+            int l = 0, r = 0;
+            for (int c : cons[ng.id]) {
+                if (!mem.count(c)) continue;
+                const NodeGeom& cg = geo.nodes[geo.index[c]];
+                for (const Tap& t : p.taps(c, ng.id)) {
+                    int delta = t.dx - (ng.skew - cg.skew);
+                    l = std::max(l, -delta);
+                    r = std::max(r, delta);
+                }
+            }
+            if (l > 64 * g.V || r > 64 * g.V) fail(WT_E_UNSUPPORTED, "ghost columns exceed one sub-tile");
+            ng.ghl = l;
+            ng.ghr = r;
+            ng.vlo = -l;
+            ng.vhi = -r;
+        }
+    }
+
     // valid slot range [vlo, N - vhi), producers before consumers: a read at
     // slot offset delta = dx - (a_p - a_c) needs slot j + delta valid.
     for (auto& ng : geo.nodes) {
@@ -262,6 +288,7 @@ std::string describe_group(const GroupSched& g) {
        << " XCD=" << g.XCD << " NT=" << g.NT;
     if (g.ORD) os << " ORD=" << g.ORD;
     if (g.BLK) os << " BLK=" << g.BLK;
+    if (g.GH) os << " GH=" << g.GH;
     if (!g.dec.empty()) {
         os << " dec=";
         for (size_t i = 0; i < g.dec.size(); ++i) os << (i ? "," : "") << g.dec[i];
@@ -306,6 +333,7 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
                 else if (k == "XCD") g.XCD = std::stoi(v);
                 else if (k == "ORD") g.ORD = std::stoi(v);
                 else if (k == "BLK") g.BLK = std::stoi(v);
+                else if (k == "GH") g.GH = std::stoi(v);
                 else if (k == "dec" || k == "exp") {
                     std::istringstream vs(v);
                     std::string n;

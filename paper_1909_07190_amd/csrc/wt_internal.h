@@ -114,6 +114,12 @@ struct GroupSched {
     int BLK = 0;             // 1: one tile per workgroup, stages in LDS with
                              // workgroup barriers between them (the paper's
                              // OTPTB baseline); tile (64*V*TX) x TY
+    int GH = 0;              // 1: loaded rows carry ghost columns (the halo
+                             // their direct consumers read past the tile's
+                             // slots) in the edge lanes of two extra
+                             // registers, so those consumers are valid on every
+                             // slot and tiles start on 64*V*TX-column
+                             // boundaries (requires SX=0, align=0)
 };
 int block_tile_w(const GroupSched& g);  // output columns of a BLK tile
 bool is_resample_group(const Pipeline& p, const GroupSched& g);
@@ -144,6 +150,7 @@ struct NodeGeom {
     int lds_off;        // byte offset of its LDS ring within the wave's LDS
     bool half;          // in-group storage is FP16
     bool mem_half;      // its memory buffer holds FP16 (set by the runtime)
+    int ghl = 0, ghr = 0;  // ghost columns loaded left / right of the slots (GH=1)
 };
 struct GroupGeom {
     std::vector<NodeGeom> nodes;    // loaded nodes first, then members (topo)

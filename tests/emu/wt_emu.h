@@ -74,6 +74,18 @@ static inline void wt_emu_bstore(T v, wt_emu_rsrc r, int off) {
 #define __builtin_amdgcn_raw_buffer_store_b32(v, r, o, so, aux) wt_emu_bstore((v), (r), (o))
 #define __builtin_amdgcn_raw_buffer_store_b64(v, r, o, so, aux) wt_emu_bstore((v), (r), (o))
 #define __builtin_amdgcn_raw_buffer_store_b128(v, r, o, so, aux) wt_emu_bstore((v), (r), (o))
+// buffer loads: offsets past num_records read 0 (the hardware range check)
+template <class T>
+static inline T wt_emu_bload(wt_emu_rsrc r, int off) {
+    T v{};
+    if ((uint64_t)(uint32_t)off + sizeof(T) <= r.num) std::memcpy(&v, r.base + (uint32_t)off, sizeof(T));
+    return v;
+}
+#define __builtin_amdgcn_raw_buffer_load_b8(r, o, so, aux) wt_emu_bload<unsigned char>((r), (o))
+#define __builtin_amdgcn_raw_buffer_load_b16(r, o, so, aux) wt_emu_bload<unsigned short>((r), (o))
+#define __builtin_amdgcn_raw_buffer_load_b32(r, o, so, aux) wt_emu_bload<unsigned int>((r), (o))
+#define __builtin_amdgcn_raw_buffer_load_b64(r, o, so, aux) wt_emu_bload<wt_u2>((r), (o))
+#define __builtin_amdgcn_raw_buffer_load_b128(r, o, so, aux) wt_emu_bload<wt_u4>((r), (o))
 
 #define __global__
 #define __device__

@@ -103,6 +103,10 @@ def test_batched_persistent_kernels_emulated():
     outs = emulate_batch(spec, images, nblocks=2, mode="fixed", fixed="nodes=1,2,3,4 V=1 TX=1 TY=8 WPB=4 BLK=1")
     for inp, got in zip(images, outs):
         check_unsharp(got["mask"], inp["img"], 1e-5, spec)
+    # ghost columns on loaded rows
+    outs = emulate_batch(spec, images, nblocks=3, mode="fixed", fixed="nodes=1,2,3,4 V=1 TX=2 SX=0 TY=8 PF=1 GH=1")
+    for inp, got in zip(images, outs):
+        check_unsharp(got["mask"], inp["img"], 1e-5, spec)
     spec = P.pyramid_blend(3)
     sizes = [(45, 37), (30, 21)]
     images = [{"A": synth.uniform_image(50 + i, 1, h, w), "B": synth.uniform_image(60 + i, 1, h, w),
@@ -304,3 +308,51 @@ def test_random_pipeline_analytic_emulated(seed):
     ref = oracle.evaluate(spec, imgs)
     for k in spec["outputs"]:
         assert_normwise(got[k], ref[k], 1e-5, f"{k}: {plan.describe()}")
+
+
+# ------------------------------------- ghost columns of loaded rows (GH=1)
+# Loaded rows carry the columns their direct consumers read past the tile's
+# slots, so those consumers are valid on every slot and tiles are aligned.
+@pytest.mark.parametrize("spec,fixed,w,h", [
+    (UM, "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=8 PF=2 GH=1", 392, 21),
+    (UM, "nodes=1,2,3,4 V=1 TX=2 SX=0 TY=5 PF=1 GH=1", 300, 13),
+    (UM, "nodes=1,2,3,4 V=4 TX=1 SX=0 TY=6 PF=2 NT=1 GH=1", 772, 11),
+    (UM, "nodes=1,2,3,4 V=1 TX=1 SX=0 TY=4 PF=0 GH=1", 61, 7),
+    (UM, "nodes=1,2 V=2 TX=1 SX=0 TY=8 GH=1;nodes=3,4 V=2 TX=1 SX=0 TY=8 GH=1", 260, 17),
+    (BLUR, "nodes=1,2 V=1 TX=3 SX=0 TY=8 GH=1", 400, 12),
+    (HARRIS_EXACT, "nodes=1,2,3,4,5,6,7,8,9,10 V=2 TX=1 SX=0 TY=8 PF=1 GH=1", 260, 19),
+    (CHAIN3, "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=8 PF=1 GH=1", 390, 23),
+    (P.integer_unsharp(), "nodes=1,2,3,4 V=4 TX=1 SX=0 TY=6 PF=2 GH=1", 520, 13),
+])
+def test_ghost_columns_emulated(spec, fixed, w, h):
+    if spec["inputs"][0].get("dtype") == "u8":
+        img = synth.integer_image(7, 1, h, w, 0, 255)
+    elif spec is HARRIS_EXACT:
+        img = synth.white_squares(np.zeros((3, h, w), np.float32), 3, count=6, side_lo=3, side_hi=9)
+    else:
+        img = synth.dyadic_image(7, spec["inputs"][0]["channels"], h, w)
+    got, plan = emulate(spec, {"img": img}, mode="fixed", fixed=fixed)
+    assert "GH=1" in plan.describe()
+    ref = oracle.evaluate(spec, {"img": img})
+    for k in spec["outputs"]:
+        if ref[k].dtype == np.int64:
+            assert np.array_equal(got[k], ref[k]), fixed
+        else:
+            assert_exact(got[k], ref[k], f"{fixed}: {k}")
+
+
+def test_ghost_columns_align_tiles():
+    """With ghosts the unsharp mask's tiles are the full 64*V*TX columns
+    (no overlap), so every tile starts on a 512-byte boundary."""
+    import ctypes
+    from emu_runner import GroupInfo
+    import paper_1909_07190_amd as wt
+    for gh, cols in ((0, 124), (1, 128)):
+        plan = wt.from_spec(UM).plan(2048, 2048, mode="fixed", no_device=True, no_compile=True,
+                                     fixed=f"nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1 GH={gh}")
+        gi = GroupInfo()
+        wt._check(wt.lib.wt_plan_group_info(plan._h, 0, ctypes.byref(gi)))
+        assert gi.tiles_x == -(-2048 // cols), (gh, gi.tiles_x)
+    with pytest.raises(wt.WtError):
+        wt.from_spec(UM).plan(256, 64, mode="fixed", no_device=True, no_compile=True,
+                              fixed="nodes=1,2,3,4 V=2 TX=2 SX=1 TY=8 GH=1")

@@ -408,3 +408,27 @@ def test_stream_copy_reference(nbytes):
     wt.stream_copy(src, dst)
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+# ------------------------------------- ghost columns of loaded rows (GH=1)
+@pytest.mark.parametrize("name,fixed,w,h", [
+    ("unsharp", "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1 GH=1", 2048, 2048),
+    ("unsharp", "nodes=1,2,3,4 V=4 TX=1 SX=0 TY=16 PF=2 GH=1", 772, 45),
+    ("unsharp", "nodes=1,2,3,4 V=1 TX=2 SX=0 TY=7 PF=1 GH=1", 301, 33),
+    ("blur", "nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 GH=1", 258, 77),
+    ("harris", "nodes=1,2,3,4,5,6,7,8,9,10 V=2 TX=1 SX=0 TY=16 PF=2 GH=1", 516, 70),
+])
+def test_ghost_columns(name, fixed, w, h):
+    """Loaded rows with ghost columns: aligned tiles with no horizontal
+    overlap, against the oracle."""
+    _say(f"ghost columns {name} {fixed} {w}x{h}")
+    spec = {"blur": BLUR, "unsharp": UM, "harris": P.harris()}[name]
+    img = synth.uniform_image(13, spec["inputs"][0]["channels"], h, w)
+    got, plan = run_gpu(spec, {"img": img}, mode="fixed", fixed=fixed)
+    assert "GH=1" in plan.describe()
+    if name == "unsharp":
+        check_unsharp(got["mask"], img, 1e-5, UM)
+    else:
+        ref = oracle.evaluate(spec, {"img": img})
+        for k in spec["outputs"]:
+            assert_normwise(got[k], ref[k], 1e-5, fixed)
