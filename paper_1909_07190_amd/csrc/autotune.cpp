@@ -104,9 +104,8 @@ void write_db_line(std::ofstream& db, const std::string& tag, const Plan& plan, 
 // launches, minimum of the sample means.
 double time_group_us(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st,
                      int reps) {
-    hipEvent_t e0, e1;
-    hip_check(hipEventCreate(&e0), "hipEventCreate");
-    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    OwnedEvents ev;
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     for (int i = 0; i < 3; ++i) launch_group(plan, gr, mem, st);
     double best = INFINITY;
     for (int s = 0; s < 3; ++s) {
@@ -118,8 +117,6 @@ double time_group_us(const Plan& plan, const GroupRt& gr, const std::map<int, Im
         hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
         best = std::min(best, (double)ms * 1e3 / reps);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     return best;
 }
 
@@ -143,8 +140,8 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
     const Pipeline& p = plan.p;
     DeviceScratch sc;
     std::map<int, ImgRef> mem = scratch_memory(plan, sc);
-    hipStream_t st;
-    hip_check(hipStreamCreate(&st), "hipStreamCreate");
+    OwnedStream ost;
+    hipStream_t st = ost.s;
     const char* dbp = std::getenv("WT_MEASURE_DB");
     std::ofstream db;
     if (dbp && *dbp) db.open(dbp, std::ios::app);
@@ -245,7 +242,6 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
         for (auto& t : trials) unload_group(t);
         plan.sched.groups[gi] = best;
     }
-    hipStreamDestroy(st);
     build_groups(plan);
 }
 
@@ -296,23 +292,20 @@ void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vecto
         int64_t rs = (d.first + 63) / 64 * 64;
         mem[n.id] = {scr.alloc((size_t)rs * d.second * n.channels * 4), rs, rs * d.second};
     }
-    hipStream_t st;
-    hip_check(hipStreamCreate(&st), "hipStreamCreate");
+    OwnedStream ost;
     const char* dbp = std::getenv("WT_MEASURE_DB");
     std::ofstream db;
     if (dbp && *dbp) db.open(dbp, std::ios::app);
     try {
         for (size_t k = 0; k < ok.size(); ++k) {
-            double us = time_group_us(plan, *ok[k], mem, st, reps);
+            double us = time_group_us(plan, *ok[k], mem, ost.s, reps);
             out_us[idx[k]] = us;
             if (db.is_open() && !ok[k]->resample) write_db_line(db, tag, plan, *ok[k], us);
         }
     } catch (...) {
-        hipStreamDestroy(st);
         for (auto* t : ok) unload_group(*t);
         throw;
     }
-    hipStreamDestroy(st);
     for (auto* t : ok) unload_group(*t);
 }
 

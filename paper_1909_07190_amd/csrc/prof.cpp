@@ -128,9 +128,8 @@ std::string bench_source(const Pipeline& p, int id, const std::string& kname) {
 }
 
 double time_kernel_ns(hipFunction_t fn, float* out, hipStream_t st) {
-    hipEvent_t e0, e1;
-    hip_check(hipEventCreate(&e0), "hipEventCreate");
-    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    OwnedEvents ev;
+    hipEvent_t e0 = ev.e0, e1 = ev.e1;
     int iters = kIters;
     void* params[] = {&out, &iters};
     double best = INFINITY;
@@ -143,8 +142,6 @@ double time_kernel_ns(hipFunction_t fn, float* out, hipStream_t st) {
         hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
         if (s > 0) best = std::min(best, (double)ms * 1e6);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     return best;
 }
 

@@ -91,6 +91,34 @@ struct ImgRef {
 };
 
 void hip_check(hipError_t e, const char* what);
+
+// Owned HIP stream and event pair, released on every exit path.
+struct OwnedStream {
+    hipStream_t s = nullptr;
+    OwnedStream() { hip_check(hipStreamCreate(&s), "hipStreamCreate"); }
+    ~OwnedStream() {
+        if (s) hipStreamDestroy(s);
+    }
+    OwnedStream(const OwnedStream&) = delete;
+    OwnedStream& operator=(const OwnedStream&) = delete;
+};
+struct OwnedEvents {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    OwnedEvents() {
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        if (hipEventCreate(&e1) != hipSuccess) {
+            hipEventDestroy(e0);
+            e0 = nullptr;
+            hip_check(hipErrorOutOfMemory, "hipEventCreate");
+        }
+    }
+    ~OwnedEvents() {
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+    }
+    OwnedEvents(const OwnedEvents&) = delete;
+    OwnedEvents& operator=(const OwnedEvents&) = delete;
+};
 // Bytes per element of node `id`'s images in memory (`half`: FP16 storage of
 // a float intermediate).
 inline int node_esize(const Pipeline& p, int id, bool half) {
