@@ -143,9 +143,19 @@ enum {
     WT_PLAN_NO_DEVICE = 1, /* generate and compile code only; run() refused   */
     WT_PLAN_ANY_WIDTH = 2, /* caller images may have any width and stride:
                               groups touching them use one element per lane */
-    WT_PLAN_NO_COMPILE = 4 /* schedule and generate code only (implies
-                              WT_PLAN_NO_DEVICE); wt_plan_source still works */
+    WT_PLAN_NO_COMPILE = 4, /* schedule and generate code only (implies
+                               WT_PLAN_NO_DEVICE); wt_plan_source still works */
+    WT_PLAN_RETUNE = 8      /* WT_SCHED_AUTOTUNE: measure again even when the
+                               schedule cache holds a result (and replace it) */
 };
+
+/* WT_SCHED_AUTOTUNE results are cached, keyed by the device architecture,
+ * a hash of the pipeline's definition, the size bucket (width and height in
+ * units of 256, and width mod 4), the FP16 and any-width choices, the
+ * candidate count and the model path: in process memory and, when a cache
+ * directory is set, as lines of <cache_dir>/autotune.tsv ("key<TAB>schedule
+ * text"), read on first use.  A hit builds the cached schedule without
+ * measuring anything. */
 
 typedef struct {
     int32_t mode;               /* wt_sched_mode                               */

@@ -35,6 +35,7 @@ DTYPES = {"f32": F32, "u8": U8, "u16": U16, "i16": I16, "i32": I32}
 PLAN_NO_DEVICE = 1
 PLAN_ANY_WIDTH = 2
 PLAN_NO_COMPILE = 4
+PLAN_RETUNE = 8
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 
@@ -157,14 +158,16 @@ class Pipeline:
 
     def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
              no_device=False, model_path=None, cache_dir=None, autotune_topk=0,
-             any_width=False, no_compile=False) -> "Plan":
+             any_width=False, no_compile=False, retune=False) -> "Plan":
         """Schedules and compiles the pipeline for width x height.  mode
         "mlp" without a model_path uses the network trained on gfx950
-        measurements that ships with the package (GFX950_COST_MODEL)."""
+        measurements that ships with the package (GFX950_COST_MODEL).  Mode
+        "autotune" reuses a cached result for the same pipeline, device and
+        size bucket unless `retune`."""
         if mode == "mlp" and model_path is None:
             model_path = GFX950_COST_MODEL
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
-                    autotune_topk, any_width, no_compile)
+                    autotune_topk, any_width, no_compile, retune)
 
 
 def stream_copy(src, dst, stream=None):
@@ -233,10 +236,10 @@ class Plan:
     """A compiled schedule for one image size."""
 
     def __init__(self, pipe: Pipeline, width, height, mode, fp16, fixed, no_device,
-                 model_path, cache_dir, autotune_topk, any_width=False, no_compile=False):
+                 model_path, cache_dir, autotune_topk, any_width=False, no_compile=False, retune=False):
         self.pipe = pipe  # keeps the pipeline alive
         flags = ((PLAN_NO_DEVICE if no_device else 0) | (PLAN_ANY_WIDTH if any_width else 0)
-                 | (PLAN_NO_COMPILE if no_compile else 0))
+                 | (PLAN_NO_COMPILE if no_compile else 0) | (PLAN_RETUNE if retune else 0))
         opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), flags,
                            autotune_topk, fixed.encode() if fixed else None,
                            model_path.encode() if model_path else None,

@@ -10,6 +10,9 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <mutex>
+#include <set>
 #include <sstream>
 #include <thread>
 
@@ -72,6 +75,88 @@ Plan::~Plan() {
         if (b.second.ptr) hipFree(b.second.ptr);
 }
 
+namespace {
+
+// ---------------------------------------------------- autotune schedule cache
+std::mutex g_tune_mu;
+std::map<std::string, std::string> g_tune;  // key -> schedule text
+std::set<std::string> g_tune_dirs;          // cache directories already read
+
+uint64_t fnv1a64(const std::string& s) {
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+// Everything that defines what a pipeline computes, in node order.
+std::string pipeline_signature(const Pipeline& p) {
+    std::ostringstream os;
+    os.precision(17);
+    for (const Node& n : p.nodes) {
+        os << (int)n.kind << ':' << n.channels << ':' << n.level << ':' << n.dtype << ':';
+        for (int s : n.srcs) os << s << ',';
+        os << ':' << n.kw << 'x' << n.kh << '@' << n.ax << ',' << n.ay << ':' << n.scale << ':' << n.divisor << ':'
+           << n.expr_text << ':';
+        for (double w : n.weights) os << w << ',';
+        for (long long w : n.iweights) os << w << ',';
+        os << ';';
+    }
+    os << "out:";
+    for (int o : p.outputs) os << o << ',';
+    return os.str();
+}
+
+std::string tune_file(const std::string& dir) { return dir + "/autotune.tsv"; }
+
+}  // namespace
+
+std::string schedule_text(const Schedule& s) {
+    std::string t;
+    for (size_t i = 0; i < s.groups.size(); ++i) t += (i ? ";" : "") + describe_group(s.groups[i]);
+    return t;
+}
+
+std::string tune_key(const Plan& plan, const wt_sched_opts& opts) {
+    hipDeviceProp_t prop;
+    hip_check(hipGetDeviceProperties(&prop, plan.device), "hipGetDeviceProperties");
+    std::ostringstream os;
+    os << prop.gcnArchName << '|' << (plan.W + 255) / 256 << 'x' << (plan.H + 255) / 256 << 'm' << (plan.W & 3) << '|'
+       << (plan.fp16 ? 1 : 0) << (plan.any_width ? 1 : 0) << '|' << opts.autotune_topk << '|'
+       << (opts.model_path ? opts.model_path : "") << '|' << std::hex << fnv1a64(pipeline_signature(plan.p));
+    std::string k = os.str();
+    for (char& c : k)
+        if (c == '\t' || c == '\n' || c == '\r') c = ' ';
+    return k;
+}
+
+bool tune_cache_lookup(const std::string& dir, const std::string& key, std::string& text) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!dir.empty() && !g_tune_dirs.count(dir)) {
+        g_tune_dirs.insert(dir);
+        std::ifstream f(tune_file(dir));
+        std::string line;
+        while (std::getline(f, line)) {
+            size_t tab = line.find('\t');
+            if (tab != std::string::npos && tab + 1 < line.size()) g_tune[line.substr(0, tab)] = line.substr(tab + 1);
+        }
+    }
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    text = it->second;
+    return true;
+}
+
+void tune_cache_store(const std::string& dir, const std::string& key, const std::string& text) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = text;
+    if (dir.empty()) return;
+    std::ofstream f(tune_file(dir), std::ios::app);
+    if (f) f << key << '\t' << text << '\n';
+}
+
 std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H) {
     if (W <= 0 || H <= 0) fail(WT_E_SHAPE, "plan size must be positive");
     if (W > (1 << 24) || H > (1 << 24)) fail(WT_E_SHAPE, "plan size too large");
@@ -100,13 +185,28 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     req.any_width = plan->any_width;
     if (opts.fixed_schedule) req.fixed = opts.fixed_schedule;
     if (opts.model_path) req.model_path = opts.model_path;
+    const bool tune = opts.mode == WT_SCHED_AUTOTUNE && !plan->no_device;
+    std::string key;
+    if (tune) {
+        key = tune_key(*plan, opts);
+        std::string text;
+        if (!(opts.flags & WT_PLAN_RETUNE) && tune_cache_lookup(plan->cache_dir, key, text)) {
+            req.mode = WT_SCHED_FIXED;
+            req.fixed = text;
+            plan->sched = make_schedule(p, plan->machine, req);
+            build_groups(*plan);
+            return plan;
+        }
+    }
     if (!plan->no_device && preprofile_enabled() &&
         (opts.mode == WT_SCHED_ANALYTIC || opts.mode == WT_SCHED_MLP || opts.mode == WT_SCHED_AUTOTUNE))
         preprofile(*plan);
     plan->sched = make_schedule(p, plan->machine, req);
     build_groups(*plan);
-    if (opts.mode == WT_SCHED_AUTOTUNE && !plan->no_device)
+    if (tune) {
         autotune_plan(*plan, opts.autotune_topk > 0 ? opts.autotune_topk : 6, opts.model_path ? opts.model_path : "");
+        tune_cache_store(plan->cache_dir, key, schedule_text(plan->sched));
+    }
     return plan;
 }
 

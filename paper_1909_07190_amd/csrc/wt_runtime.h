@@ -136,6 +136,11 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
 // Measures candidate configurations of every fused group and keeps the
 // fastest; candidates ranked by the learned model when `model_path` is set.
 void autotune_plan(Plan& plan, int topk, const std::string& model_path = "");
+// Autotune schedule cache (see wt.h): key of a plan, lookup and store.
+std::string schedule_text(const Schedule& s);
+std::string tune_key(const Plan& plan, const wt_sched_opts& opts);
+bool tune_cache_lookup(const std::string& dir, const std::string& key, std::string& text);
+void tune_cache_store(const std::string& dir, const std::string& key, const std::string& text);
 // Times every stage body of plan.p not yet profiled (needs a device).
 void preprofile(const Plan& plan);
 bool preprofile_enabled();

@@ -432,3 +432,36 @@ def test_ghost_columns(name, fixed, w, h):
         ref = oracle.evaluate(spec, {"img": img})
         for k in spec["outputs"]:
             assert_normwise(got[k], ref[k], 1e-5, fixed)
+
+
+# ------------------------------------------------- autotune schedule cache
+def test_autotune_schedule_cache(tmp_path, monkeypatch):
+    """An autotuned schedule is measured once per (pipeline, device, size
+    bucket, options): a second plan in the same bucket measures nothing and
+    takes the same schedule, which is also on disk; retune measures again."""
+    import re
+    import paper_1909_07190_amd as wt
+    db = tmp_path / "measure.jsonl"
+    monkeypatch.setenv("WT_MEASURE_DB", str(db))
+    spec = P.unsharp_mask(channels=1)
+    _say("autotune cache: first plan")
+
+    def lines():
+        return len(db.read_text().splitlines()) if db.exists() else 0
+
+    def groups(plan):
+        return [re.sub(r" batch_\S+", "", g) for g in plan.describe().strip().splitlines()]
+
+    p1 = wt.from_spec(spec).plan(512, 256, mode="autotune", autotune_topk=2, cache_dir=str(tmp_path))
+    n1 = lines()
+    assert n1 > 0
+    p2 = wt.from_spec(spec).plan(500, 250, mode="autotune", autotune_topk=2, cache_dir=str(tmp_path))
+    assert lines() == n1 and groups(p2) == groups(p1)
+    tsv = (tmp_path / "autotune.tsv").read_text().splitlines()
+    assert len(tsv) == 1 and "\t" in tsv[0]
+    img = synth.uniform_image(21, 1, 250, 500)
+    got, _ = run_gpu(spec, {"img": img}, mode="autotune", autotune_topk=2, cache_dir=str(tmp_path))
+    check_unsharp(got["mask"], img, 1e-5, spec)
+    assert lines() == n1
+    wt.from_spec(spec).plan(512, 256, mode="autotune", autotune_topk=2, cache_dir=str(tmp_path), retune=True)
+    assert lines() > n1
