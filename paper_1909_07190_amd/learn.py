@@ -197,6 +197,15 @@ def load_db(paths):
     return rows
 
 
+def split_by_holdout(rows, path):
+    """(train tags, test tags) with the test tags read from `path` (one per
+    line), so a split survives the database growing."""
+    with open(path) as f:
+        te = {ln.strip() for ln in f if ln.strip()}
+    tags = {r["pipeline"] for r in rows}
+    return tags - te, tags & te
+
+
 def split_tags(rows, test_fraction=0.2, seed=0):
     tags = sorted({r["pipeline"] for r in rows})
     rng = random.Random(seed)
@@ -480,16 +489,19 @@ def main(argv=None):
                    help="time only the analytical model's current picks")
     t = sub.add_parser("train", help="train the network on the device")
     t.add_argument("--db", required=True, nargs="+")
+    t.add_argument("--holdout", help="file of held-out pipeline tags (default: a seeded fifth)")
     t.add_argument("--model", required=True)
     t.add_argument("--epochs", type=int, default=200)
     t.add_argument("--report", help="write the ranking report (JSON) here")
     f = sub.add_parser("fit-analytic", help="refit the analytical model's coefficients")
     f.add_argument("--db", required=True, nargs="+")
+    f.add_argument("--holdout", help="file of held-out pipeline tags (default: a seeded fifth)")
     f.add_argument("--out", help="write the fit and its report (JSON) here")
     f.add_argument("--picks-db", nargs="+", help="rows of the model's own picks, from collect --picks-only")
     f.add_argument("--picks-weight", type=float, default=5.0, help="weight of each picks row in the fit")
     e = sub.add_parser("evaluate", help="compare whole-plan schedules on held-out pipelines")
     e.add_argument("--db", required=True, nargs="+")
+    e.add_argument("--holdout", help="file of held-out pipeline tags (default: a seeded fifth)")
     e.add_argument("--model", required=True)
     e.add_argument("--max-pipelines", type=int, default=0)
     e.add_argument("--skip", type=int, default=0, help="skip the first held-out pipelines")
@@ -512,7 +524,7 @@ def main(argv=None):
                 compile_only=a.compile_only, picks_only=a.picks_only)
     elif a.cmd == "train":
         rows = load_db(a.db)
-        tr, te = split_tags(rows)
+        tr, te = split_by_holdout(rows, a.holdout) if a.holdout else split_tags(rows)
         train_rows = [r for r in rows if r["pipeline"] in tr]
         net = train(train_rows, a.model, epochs=a.epochs, log=log)
         fit = fit_analytic(train_rows)
@@ -526,7 +538,7 @@ def main(argv=None):
                 json.dump(rep, f, indent=1)
     elif a.cmd == "fit-analytic":
         rows = load_db(a.db)
-        tr, te = split_tags(rows)
+        tr, te = split_by_holdout(rows, a.holdout) if a.holdout else split_tags(rows)
         train_rows = [r for r in rows if r["pipeline"] in tr]
         test_rows = [r for r in rows if r["pipeline"] in te]
         # the model's own picks (collect --picks-only) on training pipelines
@@ -546,7 +558,7 @@ def main(argv=None):
         log(json.dumps(summarize(res)))
     elif a.cmd == "evaluate":
         rows = load_db(a.db)
-        _, te = split_tags(rows)
+        _, te = split_by_holdout(rows, a.holdout) if a.holdout else split_tags(rows)
         tags = sorted(te, key=lambda s: int(s[3:]) if s[3:].isdigit() else s)
         tags = tags[a.skip:]
         if a.max_pipelines:

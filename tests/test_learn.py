@@ -117,3 +117,17 @@ def test_split_by_pipeline_is_disjoint():
     rows = [{"pipeline": f"dag{i % 10}"} for i in range(100)]
     tr, te = learn.split_tags(rows, 0.2, seed=1)
     assert not (tr & te) and len(te) == 2 and len(tr) == 8
+
+
+def test_split_by_holdout_file(tmp_path):
+    """A held-out list keeps its pipelines out of training however the
+    database grows; tags it names that the database lacks are ignored."""
+    from paper_1909_07190_amd import learn
+    rows = [{"pipeline": f"dag{i}"} for i in range(10)]
+    f = tmp_path / "holdout.txt"
+    f.write_text("dag3\ndag7\n\ndag42\n")
+    tr, te = learn.split_by_holdout(rows, str(f))
+    assert te == {"dag3", "dag7"} and tr == {f"dag{i}" for i in range(10)} - te
+    rows += [{"pipeline": "dag10"}, {"pipeline": "dag11"}]
+    tr2, te2 = learn.split_by_holdout(rows, str(f))
+    assert te2 == te and tr2 == tr | {"dag10", "dag11"}
