@@ -193,8 +193,19 @@ wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in,
                             const wt_image* out, void* hip_stream);
 
 /* Schedule as text: one line per group,
- *   "g<i> nodes=<id,id,...> V=<v> TX=<t> SX=<s> TY=<rows> WPB=<w> fp16=<0|1>"
- * The same text (lines or ';'-separated) is accepted by WT_SCHED_FIXED.
+ *   "g<i> nodes=<id,id,...> V=<v> TX=<t> SX=<s> TY=<rows> WPB=<w> PF=<p>
+ *    fp16=<0|1> align=<0|1> XCD=<0|1> NT=<0|1> [ORD=1] [BLK=1] [GH=1]
+ *    [dec=<id,...>] [exp=<id,...>]"
+ * V: columns per lane (1, 2, 4); TX: sub-tiles of 64*V columns, the first
+ * SX in LDS; TY: output rows per wave tile; WPB: waves per workgroup; PF:
+ * rows loaded ahead; align=1: the paper's right-hyperplane skew; XCD=1:
+ * adjacent tiles on one XCD; NT: nontemporal memory access; ORD=1: tiles
+ * ordered along x; BLK=1: one tile per workgroup with barriers between
+ * stages (the paper's baseline); GH=1: loaded rows carry ghost columns;
+ * dec: down2 stages written decimated by this group; exp: up2 stages read
+ * by expansion.  Batched plans append batch_* launch figures.
+ * The same text (lines or ';'-separated) is accepted by WT_SCHED_FIXED;
+ * omitted keys take their defaults.
  * Writes at most `len` bytes including the terminator; *needed gets the full
  * size. */
 wt_status wt_plan_describe(const wt_plan* plan, char* buf, size_t len, size_t* needed);
