@@ -456,8 +456,10 @@ def summarize(results):
         if r:
             out[m] = {"geomean_over_best": gm(r), "within_10pct": float(np.mean([v <= 1.10 for v in r])),
                       "pipelines": len(r)}
-    out["mlp_gain_over_analytic"] = gm([x["analytic_us"] / x["mlp_us"] for x in results])
-    out["mlp_speedup_over_unfused"] = gm([x["unfused_us"] / x["mlp_us"] for x in results])
+    out["mlp_gain_over_analytic"] = gm([x["analytic_us"] / x["mlp_us"] for x in results
+                                         if "analytic_us" in x and "mlp_us" in x])
+    out["mlp_speedup_over_unfused"] = gm([x["unfused_us"] / x["mlp_us"] for x in results
+                                           if "unfused_us" in x and "mlp_us" in x])
     return out
 
 

@@ -131,3 +131,13 @@ def test_split_by_holdout_file(tmp_path):
     rows += [{"pipeline": "dag10"}, {"pipeline": "dag11"}]
     tr2, te2 = learn.split_by_holdout(rows, str(f))
     assert te2 == te and tr2 == tr | {"dag10", "dag11"}
+
+
+def test_summarize_subset_of_modes():
+    """Evaluation lines that time only some modes still summarise."""
+    from paper_1909_07190_amd import learn
+    rows = [{"pipeline": "dag1", "mlp_us": 10.0, "mlp_autotune_us": 9.0, "best_us": 9.0},
+            {"pipeline": "dag2", "mlp_us": 12.0, "mlp_autotune_us": 12.0, "best_us": 12.0}]
+    out = learn.summarize(rows)
+    assert out["mlp"]["pipelines"] == 2 and out["mlp_autotune"]["within_10pct"] == 1.0
+    assert out["mlp_gain_over_analytic"] is None and "analytic" not in out
