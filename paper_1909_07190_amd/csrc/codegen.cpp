@@ -314,9 +314,53 @@ struct Gen {
     // (x first, then y: even index 2i -> (P(i-1) + 6 P(i) + P(i+1)) / 8, odd
     // 2i+1 -> (P(i) + P(i+1)) / 2, coarse indices clamped), gathered from the
     // coarse image (a quarter of the fine one, mostly served by the caches).
+    // Expanded inputs in interior waves with one column per lane keep the
+    // three coarse rows they blend (lane t: coarse column bc + t) in
+    // registers across steps: the row index advances by at most one per
+    // step, so each step loads only the lowest row and shifts the others
+    // when the index has moved.
+    bool coarse_ring(const NodeGeom& n) const { return !border && V == 1 && n.expand_src >= 0; }
+    std::string cring(int id, int ch, int k, char which) {
+        return "xr" + I(id) + "_" + I(ch) + "_" + I(k) + which;
+    }
+    void prime_coarse_rings() {
+        int li = 0;
+        for (auto& n : geo.nodes) {
+            if (n.member) continue;
+            const int l = li++;
+            if (!coarse_ring(n)) continue;
+            const std::string ty = n.mem_half ? "_Float16" : "float";
+            for (int ch = 0; ch < n.nch; ++ch)
+                for (int k = 0; k < g.TX; ++k)
+                    line("float " + cring(n.id, ch, k, 'p') + ", " + cring(n.id, ch, k, 'c') + ", " +
+                         cring(n.id, ch, k, 'n') + ";");
+            line("int xj" + I(n.id) + ";  // coarse row held in the middle of node " + I(n.id) + "'s ring");
+            line("{ const int Wc = (W + 1) >> 1, Hc = (H + 1) >> 1;");
+            line("  const int jf = wt_clampi(y0 - " + I(geo.D - n.first_step) + " + " + I(n.lead) + ", 0, H - 1) >> 1;");
+            line("  xj" + I(n.id) + " = jf;");
+            for (int ch = 0; ch < n.nch; ++ch) {
+                line("  { const " + ty + "* cb = (const " + ty + "*)A.src[" + I(l) + "] + " + chan_off(n.id, false, l, ch) + ";");
+                line("    const " + ty + "* r0 = cb + (long long)wt_clampi(jf - 1, 0, Hc - 1) * A.src_rs[" + I(l) + "];");
+                line("    const " + ty + "* r1 = cb + (long long)jf * A.src_rs[" + I(l) + "];");
+                line("    const " + ty + "* r2 = cb + (long long)min(jf + 1, Hc - 1) * A.src_rs[" + I(l) + "];");
+                for (int k = 0; k < g.TX; ++k) {
+                    line("    { const int cl = wt_clampi(((x0 + " + I(n.skew) + " + " + I(k * SUB) + ") >> 1) - 1 + lane, 0, Wc - 1);");
+                    line("      " + cring(n.id, ch, k, 'p') + " = (float)r0[cl];");
+                    line("      " + cring(n.id, ch, k, 'c') + " = (float)r1[cl];");
+                    line("      " + cring(n.id, ch, k, 'n') + " = (float)r2[cl]; }");
+                }
+                line("  }");
+            }
+            line("}");
+        }
+    }
     void emit_expand_load(int li, const NodeGeom& n, int ph) {
         const std::string ty = n.mem_half ? "_Float16" : "float";
         int slot = pmod(ph, n.win);
+        if (coarse_ring(n)) {
+            line("const bool adv" + I(n.id) + " = (wt_clampi(kk + " + I(n.lead) + ", 0, H - 1) >> 1) != xj" + I(n.id) + ";");
+            line("xj" + I(n.id) + " = wt_clampi(kk + " + I(n.lead) + ", 0, H - 1) >> 1;");
+        }
         for (int ch = 0; ch < n.nch; ++ch) {
             line("{  // expand node " + I(n.expand_src) + " into node " + I(n.id) + " channel slot " + I(ch) +
                  ", row kk + " + I(n.lead));
@@ -339,19 +383,23 @@ struct Gen {
                     line("float " + v + "[" + I(V) + "];");
                     for (int e = 0; e < V; ++e) dst.push_back(v + "[" + I(e) + "]");
                 }
-                if (!border && V == 1) {
-                    // interior wave, one column per lane: lane t loads coarse
-                    // column bc + t (coalesced) of the three coarse rows,
-                    // blends them vertically, forms both horizontal phases
-                    // with its DPP neighbours (even: 1/8, 3/4, 1/8 of
-                    // columns c-1, c, c+1; odd: 1/2, 1/2 of c, c+1), and each
-                    // lane picks its phase of column x/2 from lane x/2 - bc
-                    // through the LDS crossbar: 3 loads and 2 lane gathers per
-                    // column instead of 9 gathered loads
+                if (coarse_ring(n)) {
+                    // interior wave, one column per lane: lane t holds coarse
+                    // column bc + t of the three coarse rows in its ring (one
+                    // new row loaded per step), blends them vertically, forms
+                    // both horizontal phases with its DPP neighbours (even:
+                    // 1/8, 3/4, 1/8 of columns c-1, c, c+1; odd: 1/2, 1/2 of
+                    // c, c+1), and each lane picks its phase of column x/2
+                    // from lane x/2 - bc through the LDS crossbar
+                    const std::string P = cring(n.id, ch, k, 'p'), C = cring(n.id, ch, k, 'c'), N = cring(n.id, ch, k, 'n');
                     line("{ const int xs0 = x0 + " + I(n.skew) + " + " + I(k * SUB) + ";");
                     line("  const int bc = (xs0 >> 1) - 1;");
                     line("  const int cl = wt_clampi(bc + lane, 0, Wc - 1);");
-                    line("  const float q = fmaf(wy2, (float)r2[cl], fmaf(wy1, (float)r1[cl], wy0 * (float)r0[cl]));");
+                    line("  const float nl = (float)r2[cl];");
+                    line("  " + P + " = adv" + I(n.id) + " ? " + C + " : " + P + ";");
+                    line("  " + C + " = adv" + I(n.id) + " ? " + N + " : " + C + ";");
+                    line("  " + N + " = nl;");
+                    line("  const float q = fmaf(wy2, " + N + ", fmaf(wy1, " + C + ", wy0 * " + P + "));");
                     line("  const float qm = wt_mov_shr1(q), qp = wt_mov_shl1(q);");
                     line("  const float ev = fmaf(0.125f, qp, fmaf(0.75f, q, 0.125f * qm));");
                     line("  const float od = fmaf(0.5f, qp, 0.5f * q);");
@@ -767,6 +815,7 @@ struct Gen {
             if (n.ghr > 0)
                 line(ctype(n.id) + " g" + I(n.id) + "r[" + I(n.win) + "][" + I(n.nch) + "][" + I(V) + "] = {};");
         }
+        prime_coarse_rings();
         for (int s = 0; s < geo.D; ++s) emit_step(s % geo.U, "y0 - " + I(geo.D - s), s, -1);
         if (geo.NMAIN > 0) {
             line("for (int it = 0; it < " + I(geo.NMAIN) + "; ++it) {");
