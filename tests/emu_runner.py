@@ -188,6 +188,20 @@ def _result(b):
     return b.astype(np.int64) if np.issubdtype(b.dtype, np.integer) else b.astype(np.float32)
 
 
+def _check_caller_alignment(plan, g, gi, caller, width):
+    """The device runtime refuses caller images whose rows are not aligned to
+    a group's vector width (its intermediates are padded); the emulator runs
+    the same code on the host, so it refuses such images too instead of
+    taking a misaligned vector access."""
+    if gi.resample:
+        return
+    toks = plan.describe().splitlines()[g].split()
+    v = int(next(t for t in toks if t.startswith("V=")).split("=")[1])
+    nodes = list(gi.loaded[:gi.nloaded]) + list(gi.liveouts[:gi.nliveouts])
+    if v > 1 and width % v and any(n in caller for n in nodes):
+        raise ValueError(f"group {g}: image rows of width {width} not aligned to V={v}")
+
+
 def emulate(spec, inputs, **plan_kw):
     """Runs `spec` through the generated kernels on the CPU; returns the outputs."""
     names, lv, ch = _meta(spec)
@@ -211,9 +225,11 @@ def emulate(spec, inputs, **plan_kw):
     for i, inp in enumerate(spec["inputs"]):
         t = SPEC_NP[inp.get("dtype", "f32")]
         bufs[i] = np.ascontiguousarray(inputs[inp["name"]]).astype(t).reshape(ch[inp["name"]], h, w)
+    caller = set(range(len(spec["inputs"]))) | {names.index(o) for o in spec["outputs"]}
     for g in range(plan.num_groups):
         gi = GroupInfo()
         wt._check(wt.lib.wt_plan_group_info(plan._h, g, ctypes.byref(gi)))
+        _check_caller_alignment(plan, g, gi, caller, w)
         lib = libs[g]
         a = Args()
         for i in range(gi.nloaded):

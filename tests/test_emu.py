@@ -58,7 +58,7 @@ HARRIS_SCHED = [
 
 @pytest.mark.parametrize("fixed", HARRIS_SCHED)
 def test_harris_emulated(fixed):
-    h, w = 21, 150
+    h, w = 21, 152
     sq = synth.white_squares(np.zeros((3, h, w), np.float32), 5, count=6, side_lo=3, side_hi=12)
     got, _ = emulate(HARRIS_EXACT, {"img": sq}, mode="fixed", fixed=fixed)
     assert_exact(got["R"], oracle.evaluate(HARRIS_EXACT, {"img": sq})["R"], fixed)
@@ -122,10 +122,10 @@ INT_CASES = [
     (P.binomial_u8(), "nodes=1,2 V=1 TX=2 SX=1 TY=5 PF=1 align=1", 131, 19, 0, 255),
     (P.integer_unsharp(), "nodes=1,2,3,4 V=2 TX=2 SX=0 TY=6 PF=1", 150, 37, 0, 255),
     (P.integer_unsharp(), "nodes=1,2,3,4 V=4 TX=2 SX=1 TY=4 PF=2 align=1", 300, 13, 0, 255),
-    (P.integer_unsharp(), "nodes=1 V=2 TY=4;nodes=2 V=1 TY=8;nodes=3,4 V=4 TY=16", 77, 21, 0, 255),
+    (P.integer_unsharp(), "nodes=1 V=2 TY=4;nodes=2 V=1 TY=8;nodes=3,4 V=4 TY=16", 76, 21, 0, 255),
     (P.integer_gradient(), "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=8;nodes=5;nodes=6 V=1", 90, 33, 0, 65535),
     (P.integer_gradient(), "nodes=1 V=4;nodes=2 V=1 TY=3;nodes=3 V=2;nodes=4 V=4 TX=2 SX=1;nodes=5;nodes=6 V=2",
-     130, 17, 0, 65535),
+     132, 17, 0, 65535),
 ]
 
 
@@ -206,7 +206,7 @@ EXP_SPEC = {"inputs": [{"name": "img", "channels": 1}],
     ("nodes=1;nodes=3,4 V=1 TX=2 SX=0 TY=7 exp=2 fp16=1", 65, 15, True),
     # wide enough for interior waves (their even-V expansion path)
     ("nodes=1;nodes=3,4 V=4 TX=1 SX=0 TY=8 exp=2", 700, 21, False),
-    ("nodes=1;nodes=3,4 V=2 TX=2 SX=1 TY=5 PF=1 exp=2", 601, 17, False),
+    ("nodes=1;nodes=3,4 V=2 TX=2 SX=1 TY=5 PF=1 exp=2", 602, 17, False),
     ("nodes=1;nodes=3,4 V=2 TX=1 SX=0 TY=6 align=1 exp=2", 390, 13, False),
     ("nodes=1;nodes=3,4 V=2 TX=1 SX=0 TY=8 exp=2 fp16=1", 402, 15, True),
     ("nodes=1;nodes=3,4 V=1 TX=1 SX=0 TY=6 exp=2", 261, 13, False),
