@@ -180,7 +180,7 @@ def bench_other(args, torch, wt, synth, P):
         # plans are scheduled (and autotuned) at the median image size
         mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
         for mode in ("autotune", "mlp", "analytic", "unfused"):
-            plan = wt.from_spec(spec).plan(mw, mh, mode=mode, any_width=True)
+            plan = wt.from_spec(spec).plan(mw, mh, mode=mode, any_width=True, batch_images=len(sizes))
             for _ in range(2):
                 plan.run_batch(ins, outs)
             torch.cuda.synchronize()

@@ -166,6 +166,10 @@ typedef struct {
     const char* model_path;     /* WT_SCHED_MLP weights file; with WT_SCHED_
                                    AUTOTUNE, the learned model ranks candidates */
     const char* cache_dir;      /* code-object cache; NULL = $WT_CACHE_DIR or none */
+    int32_t batch_images;       /* images per batched run (0 or 1: single): the
+                                   analytical cost counts waves and traffic of
+                                   that many images of this size, so tile
+                                   shapes suit the persistent batch launch */
 } wt_sched_opts;
 
 /* Plans `p` for width x height inputs: fusion, tile sizes, code generation and

@@ -50,7 +50,7 @@ class WtSchedOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("fp16_intermediates", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("autotune_topk", ctypes.c_int32),
                 ("fixed_schedule", ctypes.c_char_p), ("model_path", ctypes.c_char_p),
-                ("cache_dir", ctypes.c_char_p)]
+                ("cache_dir", ctypes.c_char_p), ("batch_images", ctypes.c_int32)]
 
 
 def _sig(name, restype, *args):
@@ -158,16 +158,18 @@ class Pipeline:
 
     def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
              no_device=False, model_path=None, cache_dir=None, autotune_topk=0,
-             any_width=False, no_compile=False, retune=False) -> "Plan":
+             any_width=False, no_compile=False, retune=False, batch_images=1) -> "Plan":
         """Schedules and compiles the pipeline for width x height.  mode
         "mlp" without a model_path uses the network trained on gfx950
         measurements that ships with the package (GFX950_COST_MODEL).  Mode
         "autotune" reuses a cached result for the same pipeline, device and
-        size bucket unless `retune`."""
+        size bucket unless `retune`.  `batch_images`: how many images of about
+        this size run_batch will process together (the analytical cost then
+        counts their waves and traffic)."""
         if mode == "mlp" and model_path is None:
             model_path = GFX950_COST_MODEL
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
-                    autotune_topk, any_width, no_compile, retune)
+                    autotune_topk, any_width, no_compile, retune, batch_images)
 
 
 def stream_copy(src, dst, stream=None):
@@ -236,14 +238,15 @@ class Plan:
     """A compiled schedule for one image size."""
 
     def __init__(self, pipe: Pipeline, width, height, mode, fp16, fixed, no_device,
-                 model_path, cache_dir, autotune_topk, any_width=False, no_compile=False, retune=False):
+                 model_path, cache_dir, autotune_topk, any_width=False, no_compile=False, retune=False,
+                 batch_images=1):
         self.pipe = pipe  # keeps the pipeline alive
         flags = ((PLAN_NO_DEVICE if no_device else 0) | (PLAN_ANY_WIDTH if any_width else 0)
                  | (PLAN_NO_COMPILE if no_compile else 0) | (PLAN_RETUNE if retune else 0))
         opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), flags,
                            autotune_topk, fixed.encode() if fixed else None,
                            model_path.encode() if model_path else None,
-                           cache_dir.encode() if cache_dir else None)
+                           cache_dir.encode() if cache_dir else None, int(batch_images))
         h = ctypes.c_void_p()
         _check(lib.wt_plan_create(pipe._h, ctypes.byref(opts), width, height, ctypes.byref(h)))
         self._h = h

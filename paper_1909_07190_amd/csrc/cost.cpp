@@ -163,8 +163,9 @@ StageProfile estimate_stage(const Pipeline& p, int id, const Machine& m) {
 }
 
 GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& geo, const Machine& m,
-                     int W, int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7]) {
+                     int W, int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7], int batch) {
     GroupCost c;
+    batch = std::max(1, batch);
     int lw = W, lh = H;
     for (int i = 0; i < p.nodes[g.nodes[0]].level; ++i) {
         lw = (lw + 1) / 2;
@@ -177,7 +178,7 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     }
     long long tiles_x = (lw - (amin - amax) + geo.X - 1) / geo.X;
     long long tiles_y = (lh + g.TY - 1) / g.TY;
-    long long nwaves = tiles_x * tiles_y * (geo.chan_parallel ? geo.C : 1);
+    long long nwaves = tiles_x * tiles_y * (geo.chan_parallel ? geo.C : 1) * batch;
     c.nwaves = nwaves;
     long long total_wg = (nwaves + g.WPB - 1) / g.WPB;
     int steps = geo.D + g.TY;
@@ -230,12 +231,13 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
         store_bytes += (double)g.TY * geo.X * esz * n.nch / 4.0;
         comp_bytes += (double)lw * lh * esz * p.nodes[ds.first].channels / 4.0;
     }
+    comp_bytes *= batch;
     lds = geo.lds_bytes_per_wg;
     tx_comp = 0;
     for (int l : geo.loaded) {
         const NodeGeom& n = geo.nodes[geo.index.at(l)];
         int esz = p.nodes[l].is_int() ? dtype_size(p.nodes[l].dtype) : (n.mem_half ? 2 : 4);
-        tx_comp += std::ceil((double)lw * lh * esz * p.nodes[l].channels / tx_size);
+        tx_comp += std::ceil((double)lw * lh * esz * p.nodes[l].channels / tx_size) * batch;
     }
 
     Alg2In in;

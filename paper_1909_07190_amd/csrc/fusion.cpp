@@ -282,7 +282,10 @@ std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, con
                             GroupGeom gg = geo;
                             gg.lds_bytes_per_wg = geo.lds_bytes * WPB;
                             for (int tx : {m.tx_sizes[0], m.tx_sizes[1]}) {
-                                GroupCost c = group_cost(p, s, gg, m, r.W, r.H, prof, tx, w);
+                                // the network was trained on single images: it
+                                // sees single-image features
+                                GroupCost c = group_cost(p, s, gg, m, r.W, r.H, prof, tx, w,
+                                                         r.mode == WT_SCHED_MLP ? 1 : r.batch);
                                 if (!c.alg2.feasible || c.nwaves <= 0) continue;
                                 out.push_back({s, c, tx, shared});
                             }

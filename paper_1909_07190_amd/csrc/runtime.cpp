@@ -124,7 +124,8 @@ std::string tune_key(const Plan& plan, const wt_sched_opts& opts) {
     hip_check(hipGetDeviceProperties(&prop, plan.device), "hipGetDeviceProperties");
     std::ostringstream os;
     os << prop.gcnArchName << '|' << (plan.W + 255) / 256 << 'x' << (plan.H + 255) / 256 << 'm' << (plan.W & 3) << '|'
-       << (plan.fp16 ? 1 : 0) << (plan.any_width ? 1 : 0) << '|' << opts.autotune_topk << '|'
+       << (plan.fp16 ? 1 : 0) << (plan.any_width ? 1 : 0) << 'b' << std::max(1, opts.batch_images) << '|'
+       << opts.autotune_topk << '|'
        << (opts.model_path ? opts.model_path : "") << '|' << std::hex << fnv1a64(pipeline_signature(plan.p));
     std::string k = os.str();
     for (char& c : k)
@@ -183,6 +184,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     req.W = W;
     req.H = H;
     req.any_width = plan->any_width;
+    req.batch = std::max(1, opts.batch_images);
     if (opts.fixed_schedule) req.fixed = opts.fixed_schedule;
     if (opts.model_path) req.model_path = opts.model_path;
     const bool tune = opts.mode == WT_SCHED_AUTOTUNE && !plan->no_device;

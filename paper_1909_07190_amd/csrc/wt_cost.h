@@ -57,8 +57,10 @@ struct GroupCost {
     double code_ops = 0;         // straight-line VALU operations per kernel body
     double cal_us = 0;           // calibrated time (active_fit())
 };
+// `batch`: images of this size run together (one persistent launch per
+// group), which multiplies the waves and the compulsory traffic.
 GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& geo, const Machine& m, int W,
-                     int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7]);
+                     int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7], int batch = 1);
 // One scored configuration of a group.
 struct ScoredConfig {
     GroupSched g;

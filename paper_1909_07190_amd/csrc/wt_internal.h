@@ -235,6 +235,7 @@ struct SchedRequest {
     std::string model_path;
     int max_group = 12;               // bound on stages per fused group
     bool any_width = false;           // caller images of any width / stride
+    int batch = 1;                    // images per batched run (analytical cost only)
     const double* weights = nullptr;  // Algorithm 2 weights (default: refitted table)
     Mlp* model = nullptr;             // learned cost model (WT_SCHED_MLP)
 };

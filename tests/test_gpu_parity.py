@@ -346,7 +346,7 @@ def test_pyramid_batch_full_workload():
         tin.append([a, b, m])
         tout.append([torch.full((1, h, w), float("nan"), device=dev)])
     mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
-    plan = wt.from_spec(spec).plan(mw, mh, mode="analytic", any_width=True)
+    plan = wt.from_spec(spec).plan(mw, mh, mode="analytic", any_width=True, batch_images=len(sizes))
     plan.run_batch(tin, tout)
     torch.cuda.synchronize()
     for i in range(len(sizes)):
