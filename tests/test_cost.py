@@ -134,3 +134,22 @@ def test_analytic_fit_override_from_environment():
     assert occ != ovl
     bad, err = plan_text("1,2,3")
     assert bad == base and "WT_ANALYTIC_FIT" in err
+
+
+def test_batch_hint_prefers_taller_tiles():
+    """With many images per batched run the analytical cost no longer needs
+    short tiles for parallelism: the pyramid's level-0 blur-and-decimate
+    groups get taller tiles than when planned for one image."""
+    import re
+    import synth
+    spec = P.pyramid_blend(4)
+    sizes = synth.batch_sizes(4, 64)
+    mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
+
+    def ty(batch):
+        d = wt.from_spec(spec).plan(mw, mh, mode="analytic", any_width=True, no_device=True, no_compile=True,
+                                    batch_images=batch).describe()
+        line = next(l for l in d.splitlines() if " nodes=3,4 " in l)
+        return int(re.search(r"TY=(\d+)", line).group(1))
+
+    assert ty(64) > ty(1)
