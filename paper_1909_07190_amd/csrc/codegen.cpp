@@ -1037,8 +1037,15 @@ struct BlockGen {
     }
     // value of producer p (channel slot chp) at global (gx + dx, gy + dy),
     // clamped to the image (per-stage clamp to edge)
+    bool fast = false;  // interior tile: every region lies inside the image
     std::string rd(int c, int p, int chp, int dx, int dy) {
         const Region& r = reg.at(p);
+        if (fast) {  // no clamps: the element's own offset plus a constant
+            const Region& rc = reg.at(c);
+            std::string v = arr(p) + "[" + I((long long)chp * RW(p) * RH(p)) + " + (iy + (" + I(rc.y0 + dy - r.y0) +
+                            ")) * " + I(RW(p)) + " + ix + (" + I(rc.x0 + dx - r.x0) + ")]";
+            return (!P.nodes[c].is_int() && P.nodes[p].is_int()) ? "(float)" + v : v;
+        }
         std::string x = "(wt_clampi(gx + (" + I(dx) + "), 0, W - 1) - ox - (" + I(r.x0) + "))";
         std::string y = "(wt_clampi(gy + (" + I(dy) + "), 0, H - 1) - oy - (" + I(r.y0) + "))";
         std::string v = arr(p) + "[" + I((long long)chp * RW(p) * RH(p)) + " + wt_clampi(" + y + ", 0, " + I(RH(p) - 1) +
@@ -1124,6 +1131,26 @@ struct BlockGen {
         o << "    (void)cp;\n";
         o << "    const int W = A.W, H = A.H;\n";
         o << "    const int ox = tx * " << BX << ", oy = ty * " << BY << ";\n";
+        int x0 = 0, x1 = BX, y0 = 0, y1 = BY;
+        for (auto& kv : reg) {
+            x0 = std::min(x0, kv.second.x0);
+            x1 = std::max(x1, kv.second.x1);
+            y0 = std::min(y0, kv.second.y0);
+            y1 = std::max(y1, kv.second.y1);
+        }
+        // tiles whose halo-grown regions lie inside the image read without
+        // clamps (the workgroup takes one branch, so its barriers match)
+        o << "    const bool fin = ox + (" << x0 << ") >= 0 && ox + " << x1 << " <= W && oy + (" << y0 << ") >= 0 && oy + "
+          << y1 << " <= H;\n";
+        o << "    if (fin) {\n";
+        stages(true);
+        o << "    } else {\n";
+        stages(false);
+        o << "    }\n";
+        stores();
+    }
+    void stages(bool f) {
+        fast = f;
         // stage the loaded nodes
         for (size_t li = 0; li < geo.loaded.size(); ++li) {
             const NodeGeom& n = G(geo.loaded[li]);
@@ -1133,8 +1160,13 @@ struct BlockGen {
                 o << "    { const " << ty << "* s = (const " << ty << "*)A.src[" << li << "] + " << chan_off(n.id, false, (int)li, ch)
                   << ";\n";
                 o << "      for (int i = threadIdx.x; i < " << RW(n.id) * RH(n.id) << "; i += " << T << ") {\n";
-                o << "        const int gx = wt_clampi(ox + (" << r.x0 << ") + i % " << RW(n.id) << ", 0, W - 1);\n";
-                o << "        const int gy = wt_clampi(oy + (" << r.y0 << ") + i / " << RW(n.id) << ", 0, H - 1);\n";
+                if (fast) {
+                    o << "        const int gx = ox + (" << r.x0 << ") + i % " << RW(n.id) << ";\n";
+                    o << "        const int gy = oy + (" << r.y0 << ") + i / " << RW(n.id) << ";\n";
+                } else {
+                    o << "        const int gx = wt_clampi(ox + (" << r.x0 << ") + i % " << RW(n.id) << ", 0, W - 1);\n";
+                    o << "        const int gy = wt_clampi(oy + (" << r.y0 << ") + i / " << RW(n.id) << ", 0, H - 1);\n";
+                }
                 o << "        " << arr(n.id) << "[" << (long long)ch * RW(n.id) * RH(n.id) << " + i] = (" << ct(n.id)
                   << ")s[(long long)gy * A.src_rs[" << li << "] + gx];\n";
                 o << "      } }\n";
@@ -1146,13 +1178,18 @@ struct BlockGen {
             const Region& r = reg.at(m);
             for (int ch = 0; ch < n.nch; ++ch) {
                 o << "    for (int i = threadIdx.x; i < " << RW(m) * RH(m) << "; i += " << T << ") {  // stage " << m << "\n";
-                o << "      const int gx = ox + (" << r.x0 << ") + i % " << RW(m) << ", gy = oy + (" << r.y0 << ") + i / "
-                  << RW(m) << ";\n";
+                if (fast)
+                    o << "      const int ix = i % " << RW(m) << ", iy = i / " << RW(m) << ";\n";
+                else
+                    o << "      const int gx = ox + (" << r.x0 << ") + i % " << RW(m) << ", gy = oy + (" << r.y0
+                      << ") + i / " << RW(m) << ";\n";
                 o << "      " << arr(m) << "[" << (long long)ch * RW(m) * RH(m) << " + i] = " << value(m, ch) << ";\n";
                 o << "    }\n";
             }
             o << "    __syncthreads();\n";
         }
+    }
+    void stores() {
         for (size_t oi = 0; oi < geo.liveouts.size(); ++oi) {
             int id = geo.liveouts[oi];
             const NodeGeom& n = G(id);
