@@ -169,7 +169,10 @@ typedef struct {
     int32_t batch_images;       /* images per batched run (0 or 1: single): the
                                    analytical cost counts waves and traffic of
                                    that many images of this size, so tile
-                                   shapes suit the persistent batch launch */
+                                   shapes suit the persistent batch launch;
+                                   WT_SCHED_AUTOTUNE times its candidates on
+                                   an image as tall as up to that many (its
+                                   buffers within 4 GiB of scratch) */
 } wt_sched_opts;
 
 /* Plans `p` for width x height inputs: fusion, tile sizes, code generation and

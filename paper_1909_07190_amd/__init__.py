@@ -165,7 +165,8 @@ class Pipeline:
         "autotune" reuses a cached result for the same pipeline, device and
         size bucket unless `retune`.  `batch_images`: how many images of about
         this size run_batch will process together (the analytical cost then
-        counts their waves and traffic)."""
+        counts their waves and traffic; "autotune" times its candidates on an
+        image as tall as up to that many)."""
         if mode == "mlp" and model_path is None:
             model_path = GFX950_COST_MODEL
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -136,7 +137,51 @@ std::map<int, ImgRef> scratch_memory(const Plan& plan, DeviceScratch& sc) {
     return mem;
 }
 
-void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
+namespace {
+
+// Buffers a group reads and writes, each at its level's size for a W x H
+// image: (node id, bytes of one plane, channels).
+std::vector<std::array<int64_t, 3>> group_planes(const Plan& plan, const GroupRt& gr, int W, int H) {
+    std::vector<std::array<int64_t, 3>> out;
+    std::set<int> seen;
+    auto add = [&](int id) {
+        if (!seen.insert(id).second) return;
+        auto d = level_dims(W, H, plan.p.nodes[id].level);
+        int64_t rs = (d.first + 63) / 64 * 64;
+        out.push_back({id, rs * d.second * 4, plan.p.nodes[id].channels});
+    };
+    for (int id : gr.loaded) add(id);
+    for (int id : gr.liveouts) add(id);
+    return out;
+}
+
+// How many images' worth of rows a batched plan's candidates are timed on:
+// up to the batch size, with the group's buffers within 4 GiB and every
+// plane under 1 GiB.
+int stack_count(const Plan& plan, const GroupRt& gr, int batch) {
+    if (batch <= 1) return 1;
+    int64_t total = 0, plane = 1;
+    for (auto& b : group_planes(plan, gr, plan.W, plan.H)) {
+        total += b[1] * b[2];
+        plane = std::max(plane, b[1]);
+    }
+    int64_t k = std::min<int64_t>(batch, std::max<int64_t>(1, (int64_t(4) << 30) / std::max<int64_t>(1, total)));
+    k = std::min<int64_t>(k, std::max<int64_t>(1, (int64_t(1) << 30) / plane));
+    k = std::min<int64_t>(k, std::max(1, (1 << 24) / std::max(1, plan.H)));
+    return (int)std::max<int64_t>(1, k);
+}
+
+// Sets a plan's height for the lifetime of the guard.
+struct PlanHeight {
+    Plan& plan;
+    int saved;
+    PlanHeight(Plan& p, int h) : plan(p), saved(p.H) { plan.H = h; }
+    ~PlanHeight() { plan.H = saved; }
+};
+
+}  // namespace
+
+void autotune_plan(Plan& plan, int topk, const std::string& model_path, int batch) {
     const Pipeline& p = plan.p;
     DeviceScratch sc;
     std::map<int, ImgRef> mem = scratch_memory(plan, sc);
@@ -152,6 +197,9 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
     req.H = plan.H;
     req.fp16 = plan.fp16;
     req.any_width = plan.any_width;
+    // the network was trained on single images; the analytical ranking takes
+    // the batch size
+    req.batch = model ? 1 : std::max(1, batch);
     uint64_t phash = 1469598103934665603ull;
     for (auto& g : plan.groups)
         for (unsigned char c : g.kname) phash = (phash ^ c) * 1099511628211ull;
@@ -200,10 +248,12 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
         for (int i = 0; i < topk && i < (int)by_pred.size(); ++i) add(by_pred[i]->g);
         for (int i = 0; i < topk && i < (int)by_score.size(); ++i) add(by_score[i]->g);
         int vmax = max_vector_width(p, cur, plan.W, plan.H, plan.any_width);
-        for (int V : {4, 2})
+        for (int V : {4, 2, 1})
             for (int TX : {1, 2})
-                for (int TY : {16, 32}) {
-                    if (V > vmax) continue;
+                for (int TY : {16, 32, 64}) {
+                    // one column per lane only where no wider vector fits;
+                    // 64-row tiles only for batches
+                    if (V > vmax || (V == 1 && vmax > 1) || (TY == 64 && batch <= 1)) continue;
                     GroupSched g = cur;
                     g.V = V;
                     g.TX = TX;
@@ -213,6 +263,14 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
                     g.WPB = 1;
                     add(g);
                 }
+        // A batched plan runs each group over the tiles of every image at
+        // once; one image of the planning size gives too few waves to rank
+        // tall tiles as they run there, so its candidates are timed on an
+        // image as tall as several of them.
+        const int k = stack_count(plan, plan.groups[gi], batch);
+        PlanHeight tall(plan, plan.H * k);
+        DeviceScratch tall_scratch;
+        std::map<int, ImgRef> tall_mem;
         std::vector<GroupRt> trials;
         for (auto& g : cands) {
             GroupRt gr;
@@ -229,10 +287,18 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path) {
         std::vector<GroupRt*> ptrs;
         for (auto& t : trials) ptrs.push_back(&t);
         compile_groups(plan, ptrs);
+        if (k > 1)
+            for (auto& t : trials)
+                for (auto& b : group_planes(plan, t, plan.W, plan.H)) {
+                    if (tall_mem.count((int)b[0])) continue;
+                    auto d = level_dims(plan.W, plan.H, p.nodes[b[0]].level);
+                    int64_t rs = (d.first + 63) / 64 * 64;
+                    tall_mem[(int)b[0]] = {tall_scratch.alloc((size_t)b[1] * b[2]), rs, rs * d.second};
+                }
         double best_t = INFINITY;
         GroupSched best = cur;
         for (auto& t : trials) {
-            double us = time_group_us(plan, t, mem, st, 20);
+            double us = time_group_us(plan, t, k > 1 ? tall_mem : mem, st, 20);
             if (us < best_t) {
                 best_t = us;
                 best = t.g;

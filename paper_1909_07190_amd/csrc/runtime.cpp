@@ -206,7 +206,8 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     plan->sched = make_schedule(p, plan->machine, req);
     build_groups(*plan);
     if (tune) {
-        autotune_plan(*plan, opts.autotune_topk > 0 ? opts.autotune_topk : 6, opts.model_path ? opts.model_path : "");
+        autotune_plan(*plan, opts.autotune_topk > 0 ? opts.autotune_topk : 6, opts.model_path ? opts.model_path : "",
+                      req.batch);
         tune_cache_store(plan->cache_dir, key, schedule_text(plan->sched));
     }
     return plan;

@@ -135,7 +135,9 @@ int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads);
 void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
 // Measures candidate configurations of every fused group and keeps the
 // fastest; candidates ranked by the learned model when `model_path` is set.
-void autotune_plan(Plan& plan, int topk, const std::string& model_path = "");
+// With `batch` > 1 the candidates are timed on an image as tall as up to
+// `batch` images of the plan's size, the wave count of a batched launch.
+void autotune_plan(Plan& plan, int topk, const std::string& model_path = "", int batch = 1);
 // Autotune schedule cache (see wt.h): key of a plan, lookup and store.
 std::string schedule_text(const Schedule& s);
 std::string tune_key(const Plan& plan, const wt_sched_opts& opts);

@@ -223,6 +223,43 @@ def test_batched_persistent_graph(spec_name):
             assert torch.equal(a, b), f"replay differs for image {k}"
 
 
+def test_autotune_batched_times_stacked_images(tmp_path, monkeypatch):
+    """Autotuning a plan for a batch times each fused group's candidates on
+    an image as tall as the batch (the database records that height), and
+    the tuned plan's batched run matches the oracle on every image."""
+    import json
+    import torch
+    import paper_1909_07190_amd as wt
+    from wt_helpers import _channels, _levels
+    db = tmp_path / "measure.jsonl"
+    monkeypatch.setenv("WT_MEASURE_DB", str(db))
+    spec = P.pyramid_blend(3)
+    sizes = [(130, 67), (201, 150), (64, 64), (97, 41)]
+    _say(f"autotune batched pyramid {sizes}")
+    w0, h0 = sizes[0]
+    plan = wt.from_spec(spec).plan(w0, h0, mode="autotune", autotune_topk=2, any_width=True,
+                                   batch_images=len(sizes))
+    rows = [json.loads(l) for l in db.read_text().splitlines()]
+    assert rows and {(r["W"], r["H"]) for r in rows} == {(w0, h0 * len(sizes))}
+    images = _batch_inputs(spec, sizes, 90)
+    dev = torch.device("cuda:0")
+    lv, ch = _levels(spec), _channels(spec)
+    tin = [[torch.from_numpy(img[i["name"]]).to(dev) for i in spec["inputs"]] for img in images]
+    tout = []
+    for (w, h) in sizes:
+        outs = []
+        for o in spec["outputs"]:
+            ow, oh = oracle.level_size(w, h, lv[o])
+            outs.append(torch.full((ch[o], oh, ow), float("nan"), device=dev))
+        tout.append(outs)
+    plan.run_batch(tin, tout)
+    torch.cuda.synchronize()
+    o = spec["outputs"][0]
+    for k in range(len(sizes)):
+        ref = oracle.evaluate(spec, images[k])
+        assert_normwise(tout[k][0].cpu().numpy(), ref[o], 1e-5, f"image {k}: {plan.describe()}")
+
+
 # ------------------------------------------------------------ integer stages
 # Bit-exact against the oracle's int64 arithmetic (sums, rounded divisions and
 # saturation), through fused, split and unfused schedules, LDS sub-tiles,
