@@ -179,8 +179,12 @@ def bench_other(args, torch, wt, synth, P):
             px += w * h
         # plans are scheduled (and autotuned) at the median image size
         mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
-        for mode in ("autotune", "mlp", "analytic", "unfused"):
-            plan = wt.from_spec(spec).plan(mw, mh, mode=mode, any_width=True, batch_images=len(sizes))
+        legs = (("autotune", None), ("autotune", wt.GFX950_COST_MODEL), ("mlp", None), ("analytic", None),
+                ("unfused", None))
+        for mode, model in legs:
+            plan = wt.from_spec(spec).plan(mw, mh, mode=mode, any_width=True, batch_images=len(sizes),
+                                           model_path=model)
+            key = f"mlp_{mode}" if model else mode
             for _ in range(2):
                 plan.run_batch(ins, outs)
             torch.cuda.synchronize()
@@ -197,10 +201,10 @@ def bench_other(args, torch, wt, synth, P):
                 torch.cuda.synchronize()
                 samples.append(e0.elapsed_time(e1) / reps)
             ms = sorted(samples)[len(samples) // 2]
-            res[mode] = {"Mpix/s": px / (ms * 1e-3) / 1e6, "ms": ms, "ms_samples": samples, "groups": plan.num_groups,
-                         "GB/s_algorithmic": 16 * px / (ms * 1e-3) / 1e9,
-                         "schedule": plan.describe().strip()}
-            log(f"pyramid batch {mode}: {ms:.2f} ms, {res[mode]['Mpix/s']:.0f} Mpix/s, {plan.num_groups} launches")
+            res[key] = {"Mpix/s": px / (ms * 1e-3) / 1e6, "ms": ms, "ms_samples": samples,
+                        "groups": plan.num_groups, "GB/s_algorithmic": 16 * px / (ms * 1e-3) / 1e9,
+                        "schedule": plan.describe().strip()}
+            log(f"pyramid batch {key}: {ms:.2f} ms, {res[key]['Mpix/s']:.0f} Mpix/s, {plan.num_groups} launches")
             # the same schedule, one plan per image size, images run one by one
             fixed = plan.describe()
             plans = [wt.from_spec(spec).plan(w, h, mode="fixed", fixed=fixed, any_width=True) for (w, h) in sizes]
@@ -214,8 +218,8 @@ def bench_other(args, torch, wt, synth, P):
             e1.record(s)
             torch.cuda.synchronize()
             ms1 = e0.elapsed_time(e1) / reps
-            res[mode]["per_image_ms"] = ms1
-            log(f"pyramid per-image {mode}: {ms1:.2f} ms, {px / (ms1 * 1e-3) / 1e6:.0f} Mpix/s")
+            res[key]["per_image_ms"] = ms1
+            log(f"pyramid per-image {key}: {ms1:.2f} ms, {px / (ms1 * 1e-3) / 1e6:.0f} Mpix/s")
             del plans
         res["pixels"] = px
     print(json.dumps(res), flush=True)
