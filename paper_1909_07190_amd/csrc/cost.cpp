@@ -266,8 +266,9 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     // Predicted time (the additive quantity the fusion search sums): HBM
     // time for the compulsory bytes plus a share of the redundant halo
     // traffic, derated when too few bytes are in flight; VALU time at the
-    // SIMD issue rate; launch overhead; and the tail of the last round of
-    // workgroups.
+    // SIMD issue rate; and the launch overhead.  The partly filled last
+    // round of waves is not modelled here (Algorithm 2's extra-blocks term
+    // describes it, and the gfx950 refit gives that term weight 0).
     double hbm_bytes = comp_bytes + 0.5 * std::max(0.0, c.requested_bytes - comp_bytes);
     double resident_waves = std::min<double>(nwaves, c.alg2.occupancy * m.max_waves_per_cu * m.ncu);
     double row_in_flight = 0;
