@@ -169,7 +169,7 @@ typedef struct {
     int32_t batch_images;       /* images per batched run (0 or 1: single): the
                                    analytical cost counts waves and traffic of
                                    that many images of this size, so tile
-                                   shapes suit the persistent batch launch;
+                                   shapes suit the batched launch;
                                    WT_SCHED_AUTOTUNE times its candidates on
                                    an image as tall as up to that many (its
                                    buffers within 4 GiB of scratch) */
@@ -189,8 +189,10 @@ wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
 
 /* Runs the plan over a batch of `nimg` image sets of possibly different
  * sizes: in[i*nin + k] is input k of image i, out[i*nout + k] output k.
- * Every group runs as one persistent launch over the tiles of all images
- * (the project's batched launch); the group sequence is captured in a
+ * Every group runs as one launch over the tiles of all images (one
+ * workgroup per work unit; with the environment variable
+ * WT_BATCH_GRID=resident, only the workgroups that fit on the device at
+ * once, each looping over its share); the group sequence is captured in a
  * hipGraph on the first run of a batch shape (the list of sizes) and
  * replayed while the shape is unchanged (only image pointers may change).
  * Intermediates live in a plan-owned arena sized for the shape.  Each

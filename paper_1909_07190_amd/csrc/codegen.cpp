@@ -942,9 +942,10 @@ struct Gen {
         return o.str();
     }
 
-    // Batched persistent kernel: the launch's waves loop over the tiles of
-    // all images; image i owns tiles start[i] .. start[i+1]-1 and its
-    // arguments are AB[i].
+    // Batched kernel: the launch's waves loop over the tiles of all images
+    // with the launch's stride (one pass per wave when the grid has a
+    // workgroup per work unit); image i owns tiles start[i] .. start[i+1]-1
+    // and its arguments are AB[i].
     std::string batch_kernel(const std::string& kname) {
         o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * g.WPB << ") " << kname
           << "_batch(const WtArgs* __restrict__ AB, const int* __restrict__ start, const int nimg, const int total) {\n";

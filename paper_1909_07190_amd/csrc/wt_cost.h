@@ -57,8 +57,8 @@ struct GroupCost {
     double code_ops = 0;         // straight-line VALU operations per kernel body
     double cal_us = 0;           // calibrated time (active_fit())
 };
-// `batch`: images of this size run together (one persistent launch per
-// group), which multiplies the waves and the compulsory traffic.
+// `batch`: images of this size run together (one launch per group over
+// all of them), which multiplies the waves and the compulsory traffic.
 GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& geo, const Machine& m, int W,
                      int H, const std::map<int, StageProfile>& prof, int tx_size, const double w[7], int batch = 1);
 // One scored configuration of a group.

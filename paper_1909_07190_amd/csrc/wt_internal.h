@@ -209,7 +209,9 @@ Machine machine_from_device(int device);  // falls back to the constant table
 
 // ------------------------------------------------------------- codegen ---
 // A group's kernels: the single-image kernel `kname` and the batched
-// persistent kernel `kname_batch`, each after the shared device prelude.
+// kernel `kname_batch` (its waves loop over the tiles of all images with the
+// launch's stride, so any grid size covers them), each after the shared
+// device prelude.
 // They are compiled as separate modules (the batched one on first use).
 struct GroupSources {
     std::string prelude, common, single, batch;  // common: helpers both kernels call

@@ -45,7 +45,7 @@ struct GroupRt {
     std::string src_single, src_batch; // the two compiled modules
     hipModule_t mod = nullptr, mod_batch = nullptr;
     hipFunction_t fn = nullptr;        // single image, one wave (or block) per tile
-    hipFunction_t fn_batch = nullptr;  // persistent, all images of a batch
+    hipFunction_t fn_batch = nullptr;  // all images of a batch
     int W = 0, H = 0, Ws = 0, Hs = 0;
     int tiles_x = 0, tiles_y = 0, nwaves = 0;
     std::vector<int> loaded, liveouts;

@@ -223,6 +223,42 @@ def test_batched_persistent_graph(spec_name):
             assert torch.equal(a, b), f"replay differs for image {k}"
 
 
+def test_batch_grid_resident_equals_per_tile(monkeypatch):
+    """A batched launch with one workgroup per work unit (the default) and
+    one sized to the resident workgroups, each looping over several units
+    (WT_BATCH_GRID=resident), give bit-identical outputs."""
+    import re
+    import torch
+    import paper_1909_07190_amd as wt
+    spec = P.unsharp_mask()
+    sizes = [(2050, 1030), (130, 67), (201, 150), (97, 41)]
+    fixed = "nodes=1,2,3,4 V=1 TX=1 SX=0 TY=8 PF=2"
+    _say(f"batch grids unsharp {sizes} {fixed}")
+    images = _batch_inputs(spec, sizes, 110)
+    dev = torch.device("cuda:0")
+    tin = [[torch.from_numpy(img["img"]).to(dev)] for img in images]
+
+    def run(grid):
+        if grid:
+            monkeypatch.setenv("WT_BATCH_GRID", grid)
+        else:
+            monkeypatch.delenv("WT_BATCH_GRID", raising=False)
+        plan = wt.from_spec(spec).plan(130, 67, mode="fixed", fixed=fixed, any_width=True)
+        outs = [[torch.full((3, h, w), float("nan"), device=dev)] for (w, h) in sizes]
+        plan.run_batch(tin, outs)
+        torch.cuda.synchronize()
+        return [int(x) for x in re.findall(r"batch_grid=(\d+)", plan.describe())], outs
+
+    g1, a = run(None)
+    g2, b = run("resident")
+    # 35 x 129 tiles x 3 channels of the large image alone exceed the
+    # resident workgroups, so the resident grid loops
+    assert len(g1) == len(g2) == 1 and g1[0] > g2[0]
+    for k in range(len(sizes)):
+        assert torch.isfinite(a[k][0]).all() and torch.equal(a[k][0], b[k][0]), f"image {k}"
+    check_unsharp(a[1][0].cpu().numpy(), images[1]["img"], 1e-5, spec)
+
+
 def test_autotune_batched_times_stacked_images(tmp_path, monkeypatch):
     """Autotuning a plan for a batch times each fused group's candidates on
     an image as tall as the batch (the database records that height), and
