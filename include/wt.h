@@ -145,8 +145,12 @@ enum {
                               groups touching them use one element per lane */
     WT_PLAN_NO_COMPILE = 4, /* schedule and generate code only (implies
                                WT_PLAN_NO_DEVICE); wt_plan_source still works */
-    WT_PLAN_RETUNE = 8      /* WT_SCHED_AUTOTUNE: measure again even when the
+    WT_PLAN_RETUNE = 8,     /* WT_SCHED_AUTOTUNE: measure again even when the
                                schedule cache holds a result (and replace it) */
+    WT_PLAN_BATCH_RESIDENT = 16 /* wt_plan_run_batch launches only the
+                               workgroups resident at once, each looping over
+                               its share of the work units (persistent); by
+                               default every work unit gets a workgroup */
 };
 
 /* WT_SCHED_AUTOTUNE results are cached, keyed by the device architecture,
@@ -190,9 +194,10 @@ wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
 /* Runs the plan over a batch of `nimg` image sets of possibly different
  * sizes: in[i*nin + k] is input k of image i, out[i*nout + k] output k.
  * Every group runs as one launch over the tiles of all images (one
- * workgroup per work unit; with the environment variable
- * WT_BATCH_GRID=resident, only the workgroups that fit on the device at
- * once, each looping over its share); the group sequence is captured in a
+ * workgroup per work unit; with WT_PLAN_BATCH_RESIDENT or the environment
+ * variable WT_BATCH_GRID=resident, only the workgroups that fit on the
+ * device at once, each looping over its share); the group sequence is
+ * captured in a
  * hipGraph on the first run of a batch shape (the list of sizes) and
  * replayed while the shape is unchanged (only image pointers may change).
  * Intermediates live in a plan-owned arena sized for the shape.  Each

@@ -50,13 +50,14 @@ int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads) {
 
 namespace {
 
-// WT_BATCH_GRID=resident sizes a batched launch to the workgroups that fit
-// on the device at once, each looping over its share of the work units
-// (persistent); by default every work unit gets a workgroup of its own and
-// the hardware dispatcher hands them out as earlier ones finish, which
-// balances the uneven tiles of a batch better (17-20% faster on the
-// 64-image pyramid blend).
-bool batch_grid_resident() {
+// WT_PLAN_BATCH_RESIDENT (or WT_BATCH_GRID=resident in the environment)
+// sizes a batched launch to the workgroups that fit on the device at once,
+// each looping over its share of the work units (persistent); by default
+// every work unit gets a workgroup of its own and the hardware dispatcher
+// hands them out as earlier ones finish, which balances the uneven tiles of
+// a batch better (17-20% faster on the 64-image pyramid blend).
+bool batch_grid_resident(const Plan& plan) {
+    if (plan.batch_resident) return true;
     const char* e = std::getenv("WT_BATCH_GRID");
     return e && std::string(e) == "resident";
 }
@@ -186,7 +187,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
             int per_cu = resident_blocks_per_cu(plan, gr.fn_batch, threads);
             st->per_cu[g] = per_cu;
             int units = (gr.resample || gr.g.BLK) ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
-            st->grid[g] = batch_grid_resident() ? std::max(1, std::min(units, per_cu * plan.machine.ncu))
+            st->grid[g] = batch_grid_resident(plan) ? std::max(1, std::min(units, per_cu * plan.machine.ncu))
                                                 : std::max(1, units);
         }
         // device argument table: [g][img] WtArgs, then [g][nimg + 1] starts

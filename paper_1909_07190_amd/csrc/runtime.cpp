@@ -173,6 +173,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     plan->no_compile = (opts.flags & WT_PLAN_NO_COMPILE) != 0;
     plan->fp16 = opts.fp16_intermediates != 0;
     plan->any_width = (opts.flags & WT_PLAN_ANY_WIDTH) != 0;
+    plan->batch_resident = (opts.flags & WT_PLAN_BATCH_RESIDENT) != 0;
     const char* env_cache = std::getenv("WT_CACHE_DIR");
     plan->cache_dir = opts.cache_dir ? opts.cache_dir : (env_cache ? env_cache : "");
     if (!plan->no_device) hip_check(hipGetDevice(&plan->device), "hipGetDevice");

@@ -80,6 +80,7 @@ struct Plan {
     bool no_compile = false;
     bool fp16 = false;
     bool any_width = false;
+    bool batch_resident = false;  // WT_PLAN_BATCH_RESIDENT
     std::string cache_dir;
     std::unique_ptr<BatchState> batch;
     ~Plan();

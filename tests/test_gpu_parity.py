@@ -226,7 +226,7 @@ def test_batched_persistent_graph(spec_name):
 def test_batch_grid_resident_equals_per_tile(monkeypatch):
     """A batched launch with one workgroup per work unit (the default) and
     one sized to the resident workgroups, each looping over several units
-    (WT_BATCH_GRID=resident), give bit-identical outputs."""
+    (the plan flag, or WT_BATCH_GRID=resident), give bit-identical outputs."""
     import re
     import torch
     import paper_1909_07190_amd as wt
@@ -238,12 +238,12 @@ def test_batch_grid_resident_equals_per_tile(monkeypatch):
     dev = torch.device("cuda:0")
     tin = [[torch.from_numpy(img["img"]).to(dev)] for img in images]
 
-    def run(grid):
+    def run(grid, flag=False):
         if grid:
             monkeypatch.setenv("WT_BATCH_GRID", grid)
         else:
             monkeypatch.delenv("WT_BATCH_GRID", raising=False)
-        plan = wt.from_spec(spec).plan(130, 67, mode="fixed", fixed=fixed, any_width=True)
+        plan = wt.from_spec(spec).plan(130, 67, mode="fixed", fixed=fixed, any_width=True, batch_resident=flag)
         outs = [[torch.full((3, h, w), float("nan"), device=dev)] for (w, h) in sizes]
         plan.run_batch(tin, outs)
         torch.cuda.synchronize()
@@ -251,11 +251,13 @@ def test_batch_grid_resident_equals_per_tile(monkeypatch):
 
     g1, a = run(None)
     g2, b = run("resident")
+    g3, c = run(None, flag=True)
     # 35 x 129 tiles x 3 channels of the large image alone exceed the
     # resident workgroups, so the resident grid loops
-    assert len(g1) == len(g2) == 1 and g1[0] > g2[0]
+    assert len(g1) == len(g2) == 1 and g1[0] > g2[0] and g3 == g2
     for k in range(len(sizes)):
         assert torch.isfinite(a[k][0]).all() and torch.equal(a[k][0], b[k][0]), f"image {k}"
+        assert torch.equal(a[k][0], c[k][0]), f"image {k} (plan flag)"
     check_unsharp(a[1][0].cpu().numpy(), images[1]["img"], 1e-5, spec)
 
 
