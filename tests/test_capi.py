@@ -27,6 +27,19 @@ def test_library_exports_every_declared_function():
     assert not missing, missing
 
 
+def test_binding_constants_match_header():
+    """The binding's WT_PLAN_* flag bits and the sizes of its option struct
+    follow include/wt.h."""
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "wt.h")).read(), flags=re.S)
+    flags = {k: int(v) for k, v in re.findall(r"\bWT_PLAN_([A-Z_]+)\s*=\s*(\d+)", text)}
+    assert flags == {"NO_DEVICE": 1, "ANY_WIDTH": 2, "NO_COMPILE": 4, "RETUNE": 8, "BATCH_RESIDENT": 16}
+    for k, v in flags.items():
+        assert getattr(wt, "PLAN_" + k) == v, k
+    body = re.search(r"typedef struct \{([^}]*)\} wt_sched_opts;", text).group(1)
+    fields = re.findall(r"\b([a-z_0-9]+);", body)
+    assert fields == [f for f, _ in wt.WtSchedOpts._fields_]
+
+
 def test_builder_rejects_bad_arguments():
     p = wt.Pipeline()
     img = p.input(3)
