@@ -258,8 +258,9 @@ def main():
                     help="unsharp (default, the reported metric) or a secondary workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(tiles and images are independent; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (tiles and images "
+              "are independent, so a batch or the tile rows of an image would be split across "
+              "GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
