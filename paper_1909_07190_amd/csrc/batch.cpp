@@ -187,8 +187,10 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
             int per_cu = resident_blocks_per_cu(plan, gr.fn_batch, threads);
             st->per_cu[g] = per_cu;
             int units = (gr.resample || gr.g.BLK) ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
+            // the per-unit grid is capped at 2^22 workgroups (far above the
+            // resident set; the waves' stride loop covers any remainder)
             st->grid[g] = batch_grid_resident(plan) ? std::max(1, std::min(units, per_cu * plan.machine.ncu))
-                                                : std::max(1, units);
+                                                : std::max(1, std::min(units, 1 << 22));
         }
         // device argument table: [g][img] WtArgs, then [g][nimg + 1] starts
         st->args_bytes = (size_t)G * nimg * sizeof(WtArgsHost);
