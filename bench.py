@@ -1,20 +1,30 @@
 #!/usr/bin/env python3
-"""Throughput of the fused wave-tiled unsharp-mask pipeline on one MI355X.
+"""Throughput of fused wave-tiled stencil pipelines on one MI355X.
 
-Workload: 4-stage unsharp mask (5-tap binomial blur in x, blur in y,
-sharpen = img + 1.5 (img - blur), select(|img - blur| < 0.01, img, sharpen))
-on a 3x2048x2048 FP32 image, pixels uniform in [0, 1) from a seeded
-splitmix64 stream.  One step = one run of the whole pipeline over the image.
+Headline workload: the batched four-level Laplacian-pyramid blend -- 64
+image pairs (A, B) with each side uniform in 512..4096 (seeded), FP32
+uniform in [0, 1), a ramp mask per pair; per level a 5-tap binomial blur
+in x and y with 2x decimation, 2x expansion and subtraction for the
+Laplacian bands, the bands blended under the mask's Gaussian pyramid and
+collapsed.  The plan is the learned scheduler's (the cost network shipped
+with the package ranks fusion groupings and tile configurations); every
+group runs as one launch over the tiles of all 64 pairs, the sequence
+replayed from a hipGraph.  One step = one run of the whole batch.
 
-value = output Mpixels/s of the fused path (one kernel per step), with the
-inputs resident in HBM.  Input/output buffer sets rotate over more than the
-256 MB Infinity Cache so each step reads from and writes to HBM.  The unfused
-path (one kernel per stage, intermediates through HBM), the FP16-intermediate
-variant and the FP64 oracle on the host cores are reported beside it.
+value = level-0 output Mpixels/s of the batch (inputs resident in HBM).
+Beside it: the same batch unfused, analytically scheduled and autotuned;
+the unsharp mask on 3x2048x2048 and the Harris corner response on
+3x4096x4096 (each fused, unfused, with FP16 intermediates, and the
+unsharp mask also as one tile per workgroup, the paper's baseline); the FP64
+oracle on the host cores; a streaming device copy as the achievable
+bandwidth.
 
-Roofline: algorithmic bytes = 12 B in + 12 B out per output pixel (3 FP32
-channels), divided by the fused kernel's average duration over the timed
-region (HIP events on the launch stream), against MI355X's 8 TB/s HBM peak.
+Roofline: the dominant kernel of the headline plan (the group with the
+longest launch) is timed on its own with HIP events on the stream it runs
+on (the library launches groups of a batched run directly for this); its
+achieved bandwidth is its algorithmic bytes (every buffer it reads or
+writes, once, at the buffer's pyramid level, summed over the batch)
+divided by that time, against MI355X's 8 TB/s.
 """
 import argparse
 import json
@@ -26,27 +36,95 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mpixels/s per pipeline, fused vs unfused on 1 GPU; % of HBM roofline"
-C, H, W = 3, 2048, 2048
-BYTES_PER_PX = 24  # 3 channels x (4 B in + 4 B out)
 HBM_PEAK_GBS = 8000.0
-OTPTB_FUSED = "nodes=1,2,3,4 V=1 TX=1 TY=16 WPB=4 BLK=1"
-DEFAULT_FUSED = "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1"
+# headline workload: 64 pyramid-blend pairs, sides uniform in 512..4096
+PYR_LEVELS, PYR_PAIRS, PYR_SEED = 4, 64, 4
+HEADLINE_MODE = "mlp"
+# secondary workloads: (channels, height, width, input seed)
+UNSHARP = (3, 2048, 2048, 2)
+HARRIS = (3, 4096, 4096, 3)
+# the best unsharp-mask schedule found by sweeps, and the paper's baseline
+SWEPT_UNSHARP = "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1"
+OTPTB_UNSHARP = "nodes=1,2,3,4 V=1 TX=1 TY=16 WPB=4 BLK=1"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_sets(torch, img, nsets):
-    dev = torch.device("cuda:0")
-    base = torch.from_numpy(img).to(dev)
-    ins, outs = [], []
-    for i in range(nsets):
-        x = base.clone() if i else base
-        ins.append(x)
-        outs.append(torch.empty_like(x))
-    return ins, outs
+# ------------------------------------------------------------------ inputs --
 
+def pyramid_batch(synth):
+    """(sizes, [[A, B, M] per pair] as numpy arrays) of the headline batch."""
+    sizes = synth.batch_sizes(PYR_SEED, PYR_PAIRS)
+    return sizes, [pyramid_pair(synth, i, w, h) for i, (w, h) in enumerate(sizes)]
+
+
+def pyramid_pair(synth, i, w, h):
+    return [synth.uniform_image(4000 + 2 * i, 1, h, w), synth.uniform_image(4001 + 2 * i, 1, h, w),
+            synth.ramp_mask(h, w)]
+
+
+def median_size(sizes):
+    return sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
+
+
+def plan_pyramid(wt, P, sizes, mode, model=None):
+    mw, mh = median_size(sizes)
+    return wt.from_spec(P.pyramid_blend(PYR_LEVELS)).plan(mw, mh, mode=mode, any_width=True,
+                                                          batch_images=len(sizes), model_path=model)
+
+
+# --------------------------------------------------------- algorithmic bytes --
+
+def node_levels(spec):
+    lv = {i["name"]: 0 for i in spec["inputs"]}
+    for st in spec["stages"]:
+        k = st["kind"]
+        src = st["src"] if k in ("stencil", "down2", "up2") else st["srcs"][0]
+        lv[st["name"]] = lv[src] + (1 if k == "down2" else -1 if k == "up2" else 0)
+    return lv
+
+
+def node_channels(spec):
+    ch = {i["name"]: i["channels"] for i in spec["inputs"]}
+    for st in spec["stages"]:
+        ch[st["name"]] = st["channels"] if st["kind"] == "pointwise" else ch[st["src"]]
+    return ch
+
+
+def level_dims(w, h, level):
+    for _ in range(level):
+        w, h = (w + 1) // 2, (h + 1) // 2
+    return w, h
+
+
+ESIZE = {0: 4, 1: 2, 2: 1, 3: 2, 4: 2, 5: 4}  # wt_dtype -> bytes
+
+
+def group_bytes(wt, plan, pipe, spec, group, sizes):
+    """Algorithmic bytes of one launch of `group` over images of `sizes`:
+    every buffer it reads (loaded nodes; an expanded up2 reads its coarse
+    source) or writes (live-outs and decimated outputs) counted once, at its
+    own level's size."""
+    import ctypes
+    gi = wt.GroupInfo()
+    wt._check(wt.lib.wt_plan_group_info(plan._h, group, ctypes.byref(gi)))
+    names = {v: k for k, v in pipe.names.items()}
+    lv, ch = node_levels(spec), node_channels(spec)
+    bufs = [(gi.loaded[i], gi.loaded_dtype[i], gi.loaded_half[i]) for i in range(gi.nloaded)]
+    bufs += [(gi.liveouts[i], gi.liveout_dtype[i], gi.liveout_half[i]) for i in range(gi.nliveouts)]
+    total = 0
+    for nid, dt, half in bufs:
+        n = names[nid]
+        esz = 2 if half else ESIZE[dt]
+        for (w, h) in sizes:
+            lw, lh = level_dims(w, h, lv[n])
+            total += ch[n] * lw * lh * esz
+    return total
+
+
+# ------------------------------------------------------------------ timing --
 
 def calibrate_sleep(torch):
     """GPU spin cycles per millisecond of torch.cuda._sleep."""
@@ -56,181 +134,37 @@ def calibrate_sleep(torch):
     torch.cuda._sleep(10_000_000)
     e1.record(s)
     torch.cuda.synchronize()
-    ms = max(e0.elapsed_time(e1), 1e-3)
-    return 10_000_000 / ms
+    return 10_000_000 / max(e0.elapsed_time(e1), 1e-3)
 
 
-def time_plan(torch, plan, ins, outs, steps, warmup, cycles_per_ms):
-    """Average ms per step over `steps` back-to-back runs on the current
-    stream.  The stream is held by a GPU spin while the launches are queued,
-    so host launch overhead does not appear as gaps between kernels."""
-    n = len(ins)
+def timed(torch, fn, steps, warmup, cycles_per_ms, host_ms_hint=0.05):
+    """Average ms per call of fn(i) over `steps` back-to-back calls on the
+    current stream, bracketed by synchronisations; the stream is held by a
+    GPU spin while the calls are queued, so host launch overhead does not
+    show as gaps between kernels."""
     t0 = time.perf_counter()
     for i in range(warmup):
-        plan.run([ins[i % n]], [outs[i % n]])
+        fn(i)
     torch.cuda.synchronize()
-    host_ms = (time.perf_counter() - t0) * 1e3 / max(warmup, 1)
+    host_ms = max(host_ms_hint, (time.perf_counter() - t0) * 1e3 / max(warmup, 1))
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    torch.cuda._sleep(int(cycles_per_ms * (host_ms * steps * 1.5 + 5.0)))
+    torch.cuda._sleep(int(cycles_per_ms * (host_ms * steps * 1.5 + 2.0)))
     e0.record(s)
     for i in range(steps):
-        plan.run([ins[i % n]], [outs[i % n]])
+        fn(i)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
 
 
-def copy_reference(torch, ins, outs, steps, cycles_per_ms):
-    """HBM bandwidth of a plain device copy of the same buffers (read + write
-    of one 3x2048x2048 FP32 image per step), timed like the pipeline."""
-    n = len(ins)
-    for i in range(5):
-        outs[i % n].copy_(ins[i % n])
-    torch.cuda.synchronize()
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda._sleep(int(cycles_per_ms * 5.0))
-    e0.record(s)
-    for i in range(steps):
-        outs[i % n].copy_(ins[i % n])
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    nbytes = 2 * ins[0].numel() * ins[0].element_size()
-    # the library's streaming copy (16 B per thread, nontemporal), same buffers
-    import paper_1909_07190_amd as wt
-    for i in range(5):
-        wt.stream_copy(ins[i % n], outs[i % n])
-    torch.cuda.synchronize()
-    torch.cuda._sleep(int(cycles_per_ms * (0.05 * steps + 5.0)))  # covers the host's enqueue time
-    e0.record(s)
-    for i in range(steps):
-        wt.stream_copy(ins[i % n], outs[i % n], s)
-    e1.record(s)
-    torch.cuda.synchronize()
-    ms_s = e0.elapsed_time(e1) / steps
-    return {"GB/s": nbytes / (ms * 1e-3) / 1e9, "us_per_copy": ms * 1e3, "bytes": nbytes,
-            "streaming_GB/s": nbytes / (ms_s * 1e-3) / 1e9, "streaming_us_per_copy": ms_s * 1e3}
-
-
-def cpu_baseline(img, seconds=10.0):
-    """The FP64 oracle, as it stands, on a band of rows of the same image."""
-    import numpy as np
-    import oracle
-    from synth import pipelines as P
-    spec = P.unsharp_mask()
-    rows = 128
-    band = np.ascontiguousarray(img[:, :rows, :])
-    t0 = time.perf_counter()
-    n = 0
-    while True:
-        oracle.evaluate(spec, {"img": band})
-        n += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    per = el / n
-    return {"value": rows * W / per / 1e6, "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of the 3x{H}x{W} input ({n} runs, {el:.1f} s; "
-                      "numpy float64, single-threaded)"}
-
-
-def bench_other(args, torch, wt, synth, P):
-    """Secondary workloads (same timing method), one JSON line each."""
-    import numpy as np
-    cyc = calibrate_sleep(torch)
-    dev = torch.device("cuda:0")
-    res = {"workload": args.workload}
-    if args.workload in ("harris", "blur"):
-        if args.workload == "harris":
-            C_, H_, W_, spec, seed = 3, 4096, 4096, P.harris(), 3
-            img = synth.white_squares(synth.uniform_image(seed, C_, H_, W_), seed, count=200)
-            bpp = 16  # 12 B RGB in + 4 B out
-        else:
-            C_, H_, W_, spec, seed = 1, 256, 256, P.gaussian_blur(), 1
-            img = synth.uniform_image(seed, C_, H_, W_)
-            bpp = 8
-        base = torch.from_numpy(img).to(dev)
-        nsets = max(2, min(8, int(1.2e9 // (base.numel() * 4 * 1.33)) or 2))
-        ins = [base.clone() for _ in range(nsets)]
-        outs = [torch.empty((1, H_, W_), device=dev) for _ in range(nsets)]
-        legs = (("autotune", True, None), ("autotune", False, None), ("mlp", False, None),
-                ("autotune", False, wt.GFX950_COST_MODEL), ("unfused", False, None))
-        for mode, fp16, model in legs:
-            plan = wt.from_spec(spec).plan(W_, H_, mode=mode, fp16=fp16, model_path=model)
-            ms = time_plan(torch, plan, ins, outs, args.steps, args.warmup, cyc)
-            key = f"{'mlp_' if model else ''}{mode}{'_fp16' if fp16 else ''}"
-            res[key] = {"Mpix/s": H_ * W_ / (ms * 1e-3) / 1e6, "us": ms * 1e3,
-                        "GB/s_algorithmic": bpp * H_ * W_ / (ms * 1e-3) / 1e9,
-                        "kernels": plan.num_groups, "schedule": plan.describe().strip()}
-            log(f"{args.workload} {key}: {ms * 1e3:.1f} us, {res[key]['GB/s_algorithmic']:.0f} GB/s")
-    elif args.workload == "pyramid":
-        spec = P.pyramid_blend(4)
-        sizes = synth.batch_sizes(4, 64)
-        ins, outs, px = [], [], 0
-        for i, (w, h) in enumerate(sizes):
-            a = torch.from_numpy(synth.uniform_image(4000 + 2 * i, 1, h, w)).to(dev)
-            b = torch.from_numpy(synth.uniform_image(4001 + 2 * i, 1, h, w)).to(dev)
-            m = torch.from_numpy(synth.ramp_mask(h, w)).to(dev)
-            ins.append([a, b, m])
-            outs.append([torch.empty((1, h, w), device=dev)])
-            px += w * h
-        # plans are scheduled (and autotuned) at the median image size
-        mw, mh = sorted(sizes, key=lambda s: s[0] * s[1])[len(sizes) // 2]
-        legs = (("autotune", None), ("autotune", wt.GFX950_COST_MODEL), ("mlp", None), ("analytic", None),
-                ("unfused", None))
-        for mode, model in legs:
-            plan = wt.from_spec(spec).plan(mw, mh, mode=mode, any_width=True, batch_images=len(sizes),
-                                           model_path=model)
-            key = f"mlp_{mode}" if model else mode
-            for _ in range(2):
-                plan.run_batch(ins, outs)
-            torch.cuda.synchronize()
-            s = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            # median of 5 samples of 3 batches each: a rare multi-millisecond
-            # stall of a single launch does not decide the figure
-            reps, samples = 3, []
-            for _ in range(5):
-                e0.record(s)
-                for _ in range(reps):
-                    plan.run_batch(ins, outs)
-                e1.record(s)
-                torch.cuda.synchronize()
-                samples.append(e0.elapsed_time(e1) / reps)
-            ms = sorted(samples)[len(samples) // 2]
-            res[key] = {"Mpix/s": px / (ms * 1e-3) / 1e6, "ms": ms, "ms_samples": samples,
-                        "groups": plan.num_groups, "GB/s_algorithmic": 16 * px / (ms * 1e-3) / 1e9,
-                        "schedule": plan.describe().strip()}
-            log(f"pyramid batch {key}: {ms:.2f} ms, {res[key]['Mpix/s']:.0f} Mpix/s, {plan.num_groups} launches")
-            # the same schedule, one plan per image size, images run one by one
-            fixed = plan.describe()
-            plans = [wt.from_spec(spec).plan(w, h, mode="fixed", fixed=fixed, any_width=True) for (w, h) in sizes]
-            for pl, i, o in zip(plans, ins, outs):
-                pl.run(i, o)
-            torch.cuda.synchronize()
-            e0.record(s)
-            for _ in range(reps):
-                for pl, i, o in zip(plans, ins, outs):
-                    pl.run(i, o)
-            e1.record(s)
-            torch.cuda.synchronize()
-            ms1 = e0.elapsed_time(e1) / reps
-            res[key]["per_image_ms"] = ms1
-            log(f"pyramid per-image {key}: {ms1:.2f} ms, {px / (ms1 * 1e-3) / 1e6:.0f} Mpix/s")
-            del plans
-        res["pixels"] = px
-    print(json.dumps(res), flush=True)
-
-
 def profile_traffic(kname):
     """HBM bytes per launch of kernel `kname` from the committed rocprofv3
     counter summaries (FETCH_SIZE and WRITE_SIZE in KiB per dispatch, each
-    scaled by what the counter reads for a copy kernel of known size), or
-    None when no summary covers this exact kernel (its name carries a hash of
-    its source, so a changed kernel has no figure until it is profiled)."""
+    scaled by what the counter reads for a copy of known size), or None when
+    no summary covers this exact kernel (its name carries a hash of its
+    source, so a changed kernel has no figure until it is profiled)."""
     import glob
     import re
     pat = re.compile(r"^traffic (\S+) fetch_kib=([\d.]+) write_kib=([\d.]+) "
@@ -244,18 +178,239 @@ def profile_traffic(kname):
     return None
 
 
+def kernel_name(plan, group, batched):
+    import re
+    m = re.search(r"wt_g\d+_\w+?_[0-9a-f]{12}", plan.source(group))
+    return (m.group(0) + ("_batch" if batched else "")) if m else None
+
+
+# ------------------------------------------------------------- CPU oracle --
+
+def _oracle_worker(i, w, h, barrier, samples, out):
+    import numpy as np  # noqa: F401
+    import oracle
+    import synth
+    from synth import pipelines as P
+    a, b, m = pyramid_pair(synth, i, w, h)
+    spec = P.pyramid_blend(PYR_LEVELS)
+    res = []
+    for _ in range(samples):
+        barrier.wait()
+        t0 = time.monotonic()
+        oracle.evaluate(spec, {"A": a, "B": b, "M": m})
+        res.append((t0, time.monotonic()))
+    out.put((i, res))
+
+
+def cpu_cores():
+    """Host cores this process may use, at most 16 (one GPU's share of the
+    host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sizes, samples=3):
+    """The FP64 oracle, as it stands, on a sample of the headline batch: the
+    first `cores` pairs, one process per pair on all usable host cores
+    (started together at a barrier; a sample lasts until the last pair is
+    done), and the first pair alone on one core; `samples` samples each, the
+    best kept (the minimum of the per-sample times)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    cores = cpu_cores()
+
+    def run(pairs):
+        bar = ctx.Barrier(len(pairs))
+        q = ctx.Queue()
+        procs = [ctx.Process(target=_oracle_worker, args=(i, w, h, bar, samples, q)) for i, (w, h) in pairs]
+        for p in procs:
+            p.start()
+        res = dict(q.get() for _ in procs)
+        for p in procs:
+            p.join()
+        walls = [max(res[i][s][1] for i, _ in pairs) - min(res[i][s][0] for i, _ in pairs) for s in range(samples)]
+        px = sum(w * h for _, (w, h) in pairs)
+        return px, min(walls), walls
+
+    env_threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for k in env_threads:
+        os.environ[k] = "1"
+    try:
+        pairs = list(enumerate(sizes))[:cores]
+        px, best, walls = run(pairs)
+        px1, best1, walls1 = run(pairs[:1])
+    finally:
+        for k, v in env_threads.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return {"value": px / best / 1e6, "unit": "Mpixels/s", "cores": cores, "kind": "oracle",
+            "sample": f"pairs 0..{len(pairs) - 1} of the 64-pair batch ({px / 1e6:.1f} Mpx of level-0 output), one "
+                      f"process per pair on {cores} cores, numpy float64; best of {samples} samples "
+                      f"({', '.join(f'{t:.1f}' for t in walls)} s)",
+            "one_core": {"value": px1 / best1 / 1e6, "unit": "Mpixels/s",
+                         "sample": f"pair 0 ({sizes[0][0]}x{sizes[0][1]}) on one core, best of {samples} "
+                                   f"({', '.join(f'{t:.1f}' for t in walls1)} s)"},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+# ------------------------------------------------------------ workloads --
+
+def bench_pyramid(args, torch, wt, synth, P, cyc):
+    dev = torch.device("cuda:0")
+    spec = P.pyramid_blend(PYR_LEVELS)
+    sizes, host = pyramid_batch(synth)
+    ins = [[torch.from_numpy(x).to(dev) for x in pair] for pair in host]
+    del host
+    outs = [[torch.empty((1, h, w), device=dev)] for (w, h) in sizes]
+    px = sum(w * h for w, h in sizes)
+
+    def run_mode(mode, model=None):
+        plan = plan_pyramid(wt, P, sizes, mode, model)
+        ms = timed(torch, lambda i: plan.run_batch(ins, outs), args.steps, args.warmup, cyc, host_ms_hint=0.5)
+        return plan, ms
+
+    log(f"pyramid batch: {len(sizes)} pairs, {px / 1e6:.1f} Mpx; planning ({HEADLINE_MODE})")
+    plan, ms = run_mode(HEADLINE_MODE)
+    log(f"pyramid {HEADLINE_MODE}: {ms:.3f} ms per batch, {px / (ms * 1e-3) / 1e6:.0f} Mpix/s, "
+        f"{plan.num_groups} launches")
+    # per-group launch times (each group launched directly, same grid)
+    pipe = plan.pipe
+    groups = []
+    for g in range(plan.num_groups):
+        gms = timed(torch, lambda i, g=g: plan.run_batch_groups(g, 1, ins, outs), args.steps, 2, cyc,
+                    host_ms_hint=0.5)
+        nbytes = group_bytes(wt, plan, pipe, spec, g, sizes)
+        groups.append({"group": g, "ms": gms, "bytes": nbytes, "GB/s": nbytes / (gms * 1e-3) / 1e9,
+                       "kernel": kernel_name(plan, g, True)})
+    dom = max(groups, key=lambda r: r["ms"])
+    log(f"dominant kernel g{dom['group']} {dom['kernel']}: {dom['ms']:.3f} ms, {dom['GB/s']:.0f} GB/s algorithmic")
+    # the headline plan's output, kept to check the other modes against
+    ref = [o[0].clone() for o in outs]
+
+    extra = {"groups": groups}
+    if not args.no_extra:
+        legs = (("unfused", None), ("analytic", None), ("autotune", wt.GFX950_COST_MODEL))
+        for mode, model in legs:
+            pl, mms = run_mode(mode, model)
+            key = "autotune_mlp_ranked" if model else mode
+            diff = max(float((o[0] - r).abs().max() / r.abs().max()) for o, r in zip(outs, ref))
+            extra[key] = {"value": px / (mms * 1e-3) / 1e6, "ms_per_step": mms, "launches": pl.num_groups,
+                          "vs_headline": mms / ms, "max_rel_diff_vs_headline": diff,
+                          "schedule": pl.describe().strip()}
+            log(f"pyramid {key}: {mms:.3f} ms ({pl.num_groups} launches), max rel diff {diff:.1e}")
+            del pl
+    result = {
+        "value": px / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+        "config": {"workload": f"pyramid blend, {len(sizes)} pairs of uneven sizes (sides uniform in 512..4096, "
+                               f"seed {PYR_SEED}), FP32 uniform [0,1) and a ramp mask, 4 levels, one launch per "
+                               f"group over all pairs replayed from a hipGraph",
+                   "pairs": len(sizes), "level0_pixels": px, "mode": HEADLINE_MODE, "launches": plan.num_groups,
+                   "schedule": plan.describe().strip()},
+        "roofline": {"bound": "hbm", "achieved": dom["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["GB/s"] / HBM_PEAK_GBS, "traffic": profile_traffic(dom["kernel"]),
+                     "kernel": dom["kernel"], "group": dom["group"], "algorithmic_bytes": dom["bytes"],
+                     "kernel_ms": dom["ms"]},
+        "batch_GB/s_algorithmic_16B_per_px": 16 * px / (ms * 1e-3) / 1e9,
+    }
+    result.update(extra)
+    return result, sizes
+
+
+def bench_image(args, torch, wt, synth, P, cyc, name):
+    """A single-image workload (unsharp mask or Harris): the learned
+    scheduler's plan with its roofline, plus unfused, FP16-intermediate and
+    (unsharp mask) the swept schedule and the one-tile-per-workgroup
+    baseline."""
+    dev = torch.device("cuda:0")
+    if name == "unsharp":
+        C, H, W, seed = UNSHARP
+        spec = P.unsharp_mask()
+        img = synth.uniform_image(seed, C, H, W)
+        oc = C
+    else:
+        C, H, W, seed = HARRIS
+        spec = P.harris()
+        img = synth.white_squares(synth.uniform_image(seed, C, H, W), seed, count=200)
+        oc = 1
+    base = torch.from_numpy(img).to(dev)
+    # rotate buffer sets over more than the 256 MB Infinity Cache
+    per_set = base.numel() * 4 + oc * H * W * 4
+    nsets = max(2, min(8, int(1.1e9 // per_set) + 1))
+    ins = [base.clone() for _ in range(nsets)]
+    outs = [torch.empty((oc, H, W), device=dev) for _ in range(nsets)]
+
+    def leg(mode, fixed=None, fp16=False, model=None):
+        plan = wt.from_spec(spec).plan(W, H, mode=mode, fixed=fixed, fp16=fp16, model_path=model)
+        ms = timed(torch, lambda i: plan.run([ins[i % nsets]], [outs[i % nsets]]), args.steps, args.warmup, cyc)
+        return plan, ms
+
+    plan, ms = leg(HEADLINE_MODE)
+    pipe = plan.pipe
+    nbytes = sum(group_bytes(wt, plan, pipe, spec, g, [(W, H)]) for g in range(plan.num_groups))
+    kname = kernel_name(plan, 0, False) if plan.num_groups == 1 else None
+    res = {"value": H * W / (ms * 1e-3) / 1e6, "ms_per_step": ms, "mode": HEADLINE_MODE,
+           "launches": plan.num_groups, "schedule": plan.describe().strip(), "buffer_sets": nsets,
+           "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": profile_traffic(kname) if kname else None, "kernel": kname,
+                        "algorithmic_bytes": nbytes}}
+    log(f"{name} {HEADLINE_MODE}: {ms * 1e3:.2f} us, {res['roofline']['achieved']:.0f} GB/s ({plan.describe().strip()})")
+    ref = outs[(args.steps - 1) % nsets].clone()
+    if args.no_extra:
+        return res
+    legs = [("unfused", dict(mode="unfused")),
+            ("autotune_mlp_ranked", dict(mode="autotune", model=wt.GFX950_COST_MODEL)),
+            ("fp16_intermediates", dict(mode=HEADLINE_MODE, fp16=True))]
+    if name == "unsharp":
+        legs += [("swept_schedule", dict(mode="fixed", fixed=SWEPT_UNSHARP)),
+                 ("one_tile_per_workgroup", dict(mode="fixed", fixed=OTPTB_UNSHARP))]
+    for key, kw in legs:
+        pl, lms = leg(**kw)
+        got = outs[(args.steps - 1) % nsets]
+        diff = float((got - ref).abs().max() / ref.abs().max())
+        res[key] = {"value": H * W / (lms * 1e-3) / 1e6, "ms_per_step": lms, "launches": pl.num_groups,
+                    "vs_scheduled": lms / ms, "max_rel_diff": diff, "schedule": pl.describe().strip()}
+        log(f"{name} {key}: {lms * 1e3:.2f} us ({pl.num_groups} launches), max rel diff {diff:.1e}")
+        del pl
+    if name == "unsharp":
+        res["copy_reference"] = copy_reference(torch, wt, ins, outs, args.steps, cyc)
+    return res
+
+
+def copy_reference(torch, wt, ins, outs, steps, cyc):
+    """The same bytes as the unsharp mask's compulsory traffic (one image in,
+    one out) moved by the runtime's copy and by the library's streaming copy
+    kernel."""
+    n = len(ins)
+    ms = timed(torch, lambda i: outs[i % n].copy_(ins[i % n]), steps, 5, cyc)
+    ms_s = timed(torch, lambda i: wt.stream_copy(ins[i % n], outs[i % n]), steps, 5, cyc)
+    nbytes = 2 * ins[0].numel() * ins[0].element_size()
+    return {"bytes": nbytes, "GB/s": nbytes / (ms * 1e-3) / 1e9, "streaming_GB/s": nbytes / (ms_s * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--mode", default="fixed", help="schedule mode of the fused path")
-    ap.add_argument("--schedule", default=DEFAULT_FUSED, help="fixed schedule of the fused path")
-    ap.add_argument("--sets", type=int, default=6, help="rotating buffer sets (>256 MB total)")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the unfused and FP16 legs")
-    ap.add_argument("--workload", default="unsharp", choices=["unsharp", "harris", "blur", "pyramid"],
-                    help="unsharp (default, the reported metric) or a secondary workload")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline plan of each workload")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the unsharp-mask and Harris workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (tiles and images "
@@ -263,83 +418,36 @@ def main():
               "GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import paper_1909_07190_amd as wt
     import synth
     from synth import pipelines as P
 
-    if args.workload != "unsharp":
-        return bench_other(args, torch, wt, synth, P)
-    img = synth.uniform_image(2, C, H, W)
-    ins, outs = make_sets(torch, img, args.sets)
-    cyc = calibrate_sleep(torch)
-    spec = P.unsharp_mask()
-    fixed = args.schedule if args.mode == "fixed" else None
-
-    log(f"fused plan ({args.mode}: {fixed})")
-    fused = wt.from_spec(spec).plan(W, H, mode=args.mode, fixed=fixed)
-    ms = time_plan(torch, fused, ins, outs, args.steps, args.warmup, cyc)
-    mpix = H * W / (ms * 1e-3) / 1e6
-    achieved = BYTES_PER_PX * H * W / (ms * 1e-3) / 1e9
-    log(f"fused: {ms * 1e3:.2f} us/step, {mpix:.0f} Mpix/s, {achieved:.0f} GB/s")
-    ref_out = outs[(args.steps - 1) % len(outs)].clone()
-
-    extra = {}
-    if not args.no_extra:
-        unf = wt.from_spec(spec).plan(W, H, mode="unfused")
-        ms_u = time_plan(torch, unf, ins, outs, args.steps, args.warmup, cyc)
-        chk = outs[(args.steps - 1) % len(outs)]
-        diff = float((chk - ref_out).abs().max() / ref_out.abs().max())
-        extra["unfused"] = {"value": H * W / (ms_u * 1e-3) / 1e6, "ms_per_step": ms_u,
-                            "kernels_per_step": unf.num_groups, "fused_speedup": ms_u / ms,
-                            "max_rel_diff_vs_fused": diff}
-        log(f"unfused: {ms_u * 1e3:.2f} us/step ({unf.num_groups} kernels), fused speedup {ms_u / ms:.2f}x")
-        f16 = wt.from_spec(spec).plan(W, H, mode="fixed", fixed=(fixed or DEFAULT_FUSED) + " fp16=1",
-                                      fp16=True)
-        ms_h = time_plan(torch, f16, ins, outs, args.steps, args.warmup, cyc)
-        extra["fp16_intermediates"] = {"value": H * W / (ms_h * 1e-3) / 1e6, "ms_per_step": ms_h}
-        log(f"fp16 intermediates: {ms_h * 1e3:.2f} us/step")
-        # the paper's baseline execution model: one overlapped tile per
-        # workgroup, stages in LDS with workgroup barriers (same fusion)
-        blk = wt.from_spec(spec).plan(W, H, mode="fixed", fixed=OTPTB_FUSED)
-        ms_b = time_plan(torch, blk, ins, outs, args.steps, args.warmup, cyc)
-        extra["one_tile_per_workgroup"] = {"value": H * W / (ms_b * 1e-3) / 1e6, "ms_per_step": ms_b,
-                                           "schedule": OTPTB_FUSED, "wave_tile_speedup": ms_b / ms}
-        log(f"one tile per workgroup: {ms_b * 1e3:.2f} us/step, wave tiles {ms_b / ms:.2f}x faster")
-        # what the schedulers choose for this pipeline on their own
-        sched = {}
-        for mode in ("mlp", "analytic"):
-            pl = wt.from_spec(spec).plan(W, H, mode=mode)
-            ms_s = time_plan(torch, pl, ins, outs, args.steps, args.warmup, cyc)
-            sched[mode] = {"value": H * W / (ms_s * 1e-3) / 1e6, "ms_per_step": ms_s,
-                           "schedule": pl.describe().strip()}
-            log(f"{mode} schedule: {ms_s * 1e3:.2f} us/step ({pl.describe().strip()})")
-        extra["schedulers"] = sched
-    copy = copy_reference(torch, ins, outs, args.steps, cyc)
-    log(f"device copy reference: {copy['GB/s']:.0f} GB/s (runtime copy), "
-        f"{copy['streaming_GB/s']:.0f} GB/s (streaming copy kernel)")
-    cpu = None if args.no_cpu else cpu_baseline(img)
+    # the host baseline runs first, in child processes forked before this
+    # process initialises the GPU
+    cpu = None if args.no_cpu else cpu_baseline(synth.batch_sizes(PYR_SEED, PYR_PAIRS))
     if cpu:
-        log(f"oracle: {cpu['value']:.2f} Mpix/s on {cpu['cores']} core(s)")
-
-    import re
-    kname = re.search(r"wt_g0_fused_[0-9a-f]+", fused.source(0)).group(0)
-    traffic = profile_traffic(kname)
+        log(f"oracle: {cpu['value']:.2f} Mpix/s on {cpu['cores']} cores, {cpu['one_core']['value']:.2f} on one")
+    cyc = calibrate_sleep(torch)
+    head, sizes = bench_pyramid(args, torch, wt, synth, P, cyc)
+    torch.cuda.empty_cache()
+    secondary = {}
+    if not args.no_secondary:
+        for name in ("unsharp", "harris"):
+            secondary[name] = bench_image(args, torch, wt, synth, P, cyc, name)
+            torch.cuda.empty_cache()
     out = {
-        "metric": METRIC, "value": mpix, "unit": "Mpixels/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "metric": METRIC, "value": head.pop("value"), "unit": "Mpixels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "unsharp mask 3x2048x2048 FP32, uniform [0,1) seed 2; "
-                               "blur x, blur y, sharpen, select fused in one wave-tiled kernel",
-                   "schedule": fused.describe().strip(), "kernel": kname, "buffer_sets": args.sets},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "data": "synthetic", "config": head.pop("config"), "roofline": head.pop("roofline"),
         "cpu_baseline": cpu,
     }
-    out["copy_reference"] = copy
-    out.update(extra)
+    out.update(head)
+    if "unsharp" in secondary:
+        out["unsharp_3x2048x2048"] = secondary["unsharp"]
+    if "harris" in secondary:
+        out["harris_3x4096x4096"] = secondary["harris"]
     print(json.dumps(out), flush=True)
 
 

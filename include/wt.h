@@ -76,6 +76,16 @@ void wt_pipeline_destroy(wt_pipeline* p);
 /* An input image with `channels` planes (WT_F32 elements). */
 wt_status wt_input(wt_pipeline* p, int channels, int* id);
 
+/* Declares |value| <= max_abs for every element of float input `id` (the
+ * default is 1).  The builders propagate these magnitude bounds through
+ * every stage (sum of |weights| times the source's bound for stencils,
+ * interval arithmetic on expressions), and FP16 intermediates are used only
+ * for stages whose bound fits FP16's finite range (|v| <= 65504): other
+ * stages keep FP32 storage.  Must be called before any stage reads `id`
+ * (WT_E_INVALID otherwise, and for integer inputs or a bound that is not
+ * positive and finite). */
+wt_status wt_input_bound(wt_pipeline* p, int id, double max_abs);
+
 /* An input image of element type `dtype` (WT_F32, WT_U8, WT_U16, WT_I16 or
  * WT_I32).  Integer inputs make integer stages possible downstream; float
  * stages reading them see the values converted to FP32. */
@@ -163,7 +173,9 @@ enum {
 
 typedef struct {
     int32_t mode;               /* wt_sched_mode                               */
-    int32_t fp16_intermediates; /* store fused/materialised intermediates FP16 */
+    int32_t fp16_intermediates; /* store fused/materialised intermediates FP16
+                                   (stages whose magnitude bound exceeds
+                                   65504 keep FP32; see wt_input_bound)     */
     int32_t flags;              /* WT_PLAN_* bits                              */
     int32_t autotune_topk;      /* candidates measured in WT_SCHED_AUTOTUNE    */
     const char* fixed_schedule; /* WT_SCHED_FIXED (see wt_plan_describe)       */
@@ -179,20 +191,43 @@ typedef struct {
                                    buffers within 4 GiB of scratch) */
 } wt_sched_opts;
 
-/* Plans `p` for width x height inputs: fusion, tile sizes, code generation and
- * compilation.  `opts` may be NULL (analytic mode, FP32).  Allocates device
- * buffers for intermediates materialised between groups. */
+/* Plans `p` for width x height inputs (the paper, Section 6 and Fig. 6): the
+ * fusion of stages into groups (DP-Fusion driven by the GPU cost function),
+ * per group the argmin of Algorithm 2 over tile sizes, workgroup size,
+ * register fraction and transaction size (or the learned model's, or the
+ * autotuner's measured choice), then code generation (Section 4's one
+ * overlapped tile per wavefront, Section 5's hybrid VGPR/LDS tiling,
+ * Algorithm 1) and compilation for the current device.  `opts` may be NULL
+ * (analytic mode, FP32).  Measurements made while planning (Section 6's
+ * pre-profiling, WT_SCHED_AUTOTUNE's timings) run on `hip_stream` (a
+ * hipStream_t) when it is not NULL, else on a stream the library creates and
+ * destroys; the call returns when they are done.  Allocates device buffers
+ * for intermediates materialised between groups; *out is owned by the
+ * caller (wt_plan_destroy).  WT_E_SHAPE for sizes outside 1..2^24,
+ * WT_E_INVALID for a malformed schedule text, WT_E_UNSUPPORTED when no
+ * feasible schedule exists, WT_E_COMPILE / WT_E_HIP on device failures. */
 wt_status wt_plan_create(const wt_pipeline* p, const wt_sched_opts* opts,
-                         int width, int height, wt_plan** out);
+                         int width, int height, void* hip_stream, wt_plan** out);
 
 /* Runs the plan asynchronously on `hip_stream` (a hipStream_t; NULL = the
- * default stream).  in[i] is input i (creation order), out[i] output i; sizes
- * must equal the planned ones.  Inputs and outputs must not alias. */
+ * default stream): one launch per group, in the order the fusion search
+ * chose.  The outputs equal the plain stage-by-stage evaluation of the
+ * pipeline up to floating-point rounding (Section 2.2: overlapped tiles
+ * recompute their halos and change no values).  in[i] is input i (creation
+ * order), out[i] output i, device buffers owned by the caller; sizes must
+ * equal the planned ones (WT_E_SHAPE otherwise, and for a channel count,
+ * element type or stride the node does not allow).  Outputs must not alias
+ * any other image (WT_E_INVALID).  Kernel faults surface at the caller's
+ * next synchronisation. */
 wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
                       const wt_image* out, int nout, void* hip_stream);
 
 /* Runs the plan over a batch of `nimg` image sets of possibly different
- * sizes: in[i*nin + k] is input k of image i, out[i*nout + k] output k.
+ * sizes (the paper runs one image per launch sequence, Section 7; batching
+ * is this library's addition, each image's result being the one
+ * wt_plan_run computes): in[i*nin + k] is input k of image i,
+ * out[i*nout + k] output k; the image checks of wt_plan_run apply to every
+ * image, and no output may alias any image of the batch.
  * Every group runs as one launch over the tiles of all images (one
  * workgroup per work unit; with WT_PLAN_BATCH_RESIDENT or the environment
  * variable WT_BATCH_GRID=resident, only the workgroups that fit on the
@@ -206,7 +241,22 @@ wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
 wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in,
                             const wt_image* out, void* hip_stream);
 
-/* Schedule as text: one line per group,
+/* Runs only groups first .. first+count-1 of the batched plan over the same
+ * arguments as wt_plan_run_batch, with the same kernels and launch grids,
+ * launched directly on `hip_stream` (not from the graph), in group order.
+ * The groups read the intermediates their producer groups wrote in the
+ * batch's arena by the last run of the same batch shape, so a complete
+ * wt_plan_run_batch must precede it for results to be meaningful.  Meant for
+ * per-kernel measurement (timing one group's launch with events) and for
+ * callers interleaving other work between groups.  WT_E_INVALID for a
+ * range outside 0 .. wt_plan_num_groups(plan); the image checks of
+ * wt_plan_run_batch apply. */
+wt_status wt_plan_run_batch_groups(wt_plan* plan, int first, int count, int nimg, const wt_image* in,
+                                   const wt_image* out, void* hip_stream);
+
+/* The plan's schedule (the paper's fusion groups, Section 6, and each
+ * group's tile configuration, Algorithm 2's arguments) as text: one line per
+ * group,
  *   "g<i> nodes=<id,id,...> V=<v> TX=<t> SX=<s> TY=<rows> WPB=<w> PF=<p>
  *    fp16=<0|1> align=<0|1> XCD=<0|1> NT=<0|1> [ORD=1] [BLK=1] [GH=1]
  *    [dec=<id,...>] [exp=<id,...>]"
@@ -306,6 +356,25 @@ wt_status wt_mlp_adam_step(wt_mlp* m, const float* grads, float lr);
  * set, stored in the model); returns the last epoch's mean loss. */
 wt_status wt_mlp_train(wt_mlp* m, const float* x, const float* t, int n, int epochs, int batch,
                        float lr, uint64_t seed, float* final_loss);
+/* Trains the learned cost model from a measurement database and saves it
+ * (the network this library adds to the paper's analytical model of
+ * Section 6, used by WT_SCHED_MLP and to rank WT_SCHED_AUTOTUNE's
+ * candidates).  `measure_db` is a JSON-lines file as wt_measure_groups and
+ * the autotuner append (WT_MEASURE_DB): per line a configuration, its
+ * measured_us, the analytical model's pred_us and terms, and its 40
+ * features.  Usable lines (positive finite time, all quantities finite) are
+ * the training set: the target is log(measured_us), features and target
+ * are standardised on it, and a 40-128-128-128-1 ReLU network is trained
+ * for 200 epochs of Adam (batch 256, lr 1e-3, seed 1) on the device with the
+ * library's kernels, on `hip_stream` (a hipStream_t; NULL: a stream of the
+ * model's own).  Held-out evaluation is the caller's: pass a file holding
+ * the training pipelines' lines only.  Synchronous.  The model is written
+ * to `out_model` (wt_mlp_save's format).  WT_E_INVALID for an unreadable
+ * file, a line without measured_us or fewer than two usable lines. */
+wt_status wt_model_train(const char* measure_db, const char* out_model, void* hip_stream);
+/* Number of usable lines (as wt_model_train counts them) in a measurement
+ * database; reads the file only. */
+wt_status wt_model_rows(const char* measure_db, int* rows);
 /* Prediction in target units for n feature rows (stored normalisation). */
 wt_status wt_mlp_predict(wt_mlp* m, const float* x, int n, float* y);
 wt_status wt_mlp_save(const wt_mlp* m, const char* path);

@@ -347,16 +347,3 @@ def evaluate(spec: dict, inputs: dict, keep_all: bool = False) -> dict:
         return vals
     return {name: vals[name] for name in spec["outputs"]}
 
-
-def magnitude(x: np.ndarray) -> float:
-    """max |x| (0 for empty arrays)."""
-    return float(np.max(np.abs(x))) if x.size else 0.0
-
-
-def normwise_error(got: np.ndarray, ref: np.ndarray) -> float:
-    """max_p |got - ref| / max_p |ref| per the whole array (inf-norm relative)."""
-    d = float(np.max(np.abs(got.astype(np.float64) - ref))) if ref.size else 0.0
-    m = magnitude(ref)
-    if m == 0.0:
-        return d
-    return d / m

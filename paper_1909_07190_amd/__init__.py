@@ -54,6 +54,16 @@ class WtSchedOpts(ctypes.Structure):
                 ("cache_dir", ctypes.c_char_p), ("batch_images", ctypes.c_int32)]
 
 
+class GroupInfo(ctypes.Structure):
+    """wt_group_info: a group's launch shape and buffers."""
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("resample", "waves_per_group", "nwaves", "tiles_x", "tiles_y", "width", "height",
+                 "src_width", "src_height", "channels", "nloaded", "nliveouts")] + \
+               [("loaded", ctypes.c_int32 * 16), ("liveouts", ctypes.c_int32 * 16),
+                ("loaded_half", ctypes.c_int32 * 16), ("liveout_half", ctypes.c_int32 * 16),
+                ("loaded_dtype", ctypes.c_int32 * 16), ("liveout_dtype", ctypes.c_int32 * 16)]
+
+
 def _sig(name, restype, *args):
     f = getattr(lib, name)
     f.restype = restype
@@ -65,6 +75,7 @@ _sig("wt_last_error", ctypes.c_char_p)
 _sig("wt_pipeline_create", ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
 _sig("wt_pipeline_destroy", None, ctypes.c_void_p)
 _sig("wt_input", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, _c_int_p)
+_sig("wt_input_bound", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_double)
 _sig("wt_input_typed", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p)
 _sig("wt_stencil_int", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
      ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int, _c_int_p)
@@ -77,17 +88,20 @@ _sig("wt_pointwise", ctypes.c_int, ctypes.c_void_p, _c_int_p, ctypes.c_int, ctyp
 _sig("wt_resample", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p)
 _sig("wt_output", ctypes.c_int, ctypes.c_void_p, ctypes.c_int)
 _sig("wt_plan_create", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtSchedOpts), ctypes.c_int,
-     ctypes.c_int, ctypes.POINTER(ctypes.c_void_p))
+     ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p))
 _sig("wt_plan_run", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtImage), ctypes.c_int,
      ctypes.POINTER(WtImage), ctypes.c_int, ctypes.c_void_p)
 _sig("wt_plan_run_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
+_sig("wt_plan_run_batch_groups", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+     ctypes.POINTER(WtImage), ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_stream_copy", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 _sig("wt_plan_describe", ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t,
      ctypes.POINTER(ctypes.c_size_t))
 _sig("wt_plan_source", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t,
      ctypes.POINTER(ctypes.c_size_t))
 _sig("wt_plan_num_groups", ctypes.c_int, ctypes.c_void_p)
+_sig("wt_plan_group_info", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(GroupInfo))
 _sig("wt_plan_destroy", None, ctypes.c_void_p)
 
 
@@ -124,6 +138,11 @@ class Pipeline:
         _check(lib.wt_input_typed(self._h, channels, DTYPES[dtype], ctypes.byref(i)))
         self.channels[i.value] = channels
         return i.value
+
+    def input_bound(self, node: int, max_abs: float):
+        """Declares |value| <= max_abs for a float input (default 1); stages
+        whose propagated bound exceeds FP16's range keep FP32 storage."""
+        _check(lib.wt_input_bound(self._h, node, float(max_abs)))
 
     def stencil_int(self, src, kw, kh, ax, ay, weights, divisor, dtype) -> int:
         w = (ctypes.c_int32 * (kw * kh))(*[int(v) for v in weights])
@@ -203,6 +222,8 @@ def from_spec(spec: dict) -> Pipeline:
     p = Pipeline()
     for inp in spec["inputs"]:
         p.names[inp["name"]] = p.input(inp["channels"], inp.get("dtype", "f32"))
+        if "bound" in inp:
+            p.input_bound(p.names[inp["name"]], inp["bound"])
     for st in spec["stages"]:
         k = st["kind"]
         dt = st.get("dtype", "f32")
@@ -254,7 +275,11 @@ class Plan:
                            model_path.encode() if model_path else None,
                            cache_dir.encode() if cache_dir else None, int(batch_images))
         h = ctypes.c_void_p()
-        _check(lib.wt_plan_create(pipe._h, ctypes.byref(opts), width, height, ctypes.byref(h)))
+        s = None
+        if not (no_device or no_compile):
+            import torch
+            s = torch.cuda.current_stream().cuda_stream
+        _check(lib.wt_plan_create(pipe._h, ctypes.byref(opts), width, height, ctypes.c_void_p(s), ctypes.byref(h)))
         self._h = h
         self.width, self.height = width, height
 
@@ -286,6 +311,19 @@ class Plan:
             stream = torch.cuda.current_stream()
         s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         _check(lib.wt_plan_run_batch(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
+
+    def run_batch_groups(self, first, count, inputs, outputs, stream=None):
+        """Launches groups first .. first+count-1 of a batched run directly
+        (after a complete run_batch of the same shape)."""
+        import torch
+        ins = [_image(t) for img in inputs for t in img]
+        outs = [_image(t) for img in outputs for t in img]
+        a_in = (WtImage * len(ins))(*ins)
+        a_out = (WtImage * len(outs))(*outs)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(lib.wt_plan_run_batch_groups(self._h, first, count, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
 
     def describe(self) -> str:
         n = ctypes.c_size_t()
@@ -320,6 +358,8 @@ _sig("wt_mlp_forward_backward", ctypes.c_int, ctypes.c_void_p, _f_p, _f_p, ctype
 _sig("wt_mlp_adam_step", ctypes.c_int, ctypes.c_void_p, _f_p, ctypes.c_float)
 _sig("wt_mlp_train", ctypes.c_int, ctypes.c_void_p, _f_p, _f_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
      ctypes.c_float, ctypes.c_uint64, _f_p)
+_sig("wt_model_train", ctypes.c_int, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_void_p)
+_sig("wt_model_rows", ctypes.c_int, ctypes.c_char_p, _c_int_p)
 _sig("wt_mlp_predict", ctypes.c_int, ctypes.c_void_p, _f_p, ctypes.c_int, _f_p)
 _sig("wt_mlp_save", ctypes.c_int, ctypes.c_void_p, ctypes.c_char_p)
 _sig("wt_mlp_load", ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p))
@@ -413,6 +453,23 @@ class Mlp:
         _check(lib.wt_mlp_load(path.encode(), ctypes.byref(h)))
         m = cls(_handle=h)
         return m
+
+
+def model_train(measure_db, out_model, stream=None):
+    """Trains the cost network on a measurement database (JSON lines) on the
+    device and saves it to `out_model` (C-ABI wt_model_train)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(lib.wt_model_train(measure_db.encode(), out_model.encode(), ctypes.c_void_p(s)))
+
+
+def model_rows(measure_db):
+    """Usable lines of a measurement database, as model_train counts them."""
+    n = ctypes.c_int()
+    _check(lib.wt_model_rows(measure_db.encode(), ctypes.byref(n)))
+    return n.value
 
 
 def group_features(pipe, nodes, width, height, fp16=False, max_rows=4096):

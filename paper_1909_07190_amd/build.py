@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["ir.cpp", "geometry.cpp", "codegen.cpp", "sched.cpp", "fusion.cpp",
-                "cost.cpp", "prof.cpp", "autotune.cpp", "batch.cpp", "mlp.cpp", "jit.cpp", "runtime.cpp",
+                "cost.cpp", "prof.cpp", "autotune.cpp", "batch.cpp", "mlp.cpp", "train_db.cpp", "jit.cpp", "runtime.cpp",
                 "capi.cpp"]
 DEVICE_SOURCES: list[str] = ["mlp.hip", "copyref.hip"]
 # Packed-FP32 VALU forms are disabled in every HIP compilation.

@@ -185,7 +185,7 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path, int batc
     const Pipeline& p = plan.p;
     DeviceScratch sc;
     std::map<int, ImgRef> mem = scratch_memory(plan, sc);
-    OwnedStream ost;
+    OwnedStream ost(plan.setup_stream);
     hipStream_t st = ost.s;
     const char* dbp = std::getenv("WT_MEASURE_DB");
     std::ofstream db;

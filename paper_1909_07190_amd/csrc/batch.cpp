@@ -62,6 +62,17 @@ bool batch_grid_resident(const Plan& plan) {
     return e && std::string(e) == "resident";
 }
 
+// One group's batched launch (the kernel over every image's work units).
+hipError_t launch_batch_group(const Plan& plan, const BatchState& st, int g, int nimg, hipStream_t s) {
+    const GroupRt& gr = plan.groups[g];
+    const void* a = static_cast<char*>(st.dargs) + (size_t)g * nimg * sizeof(WtArgsHost);
+    const void* starts = static_cast<char*>(st.dargs) + st.args_bytes + (size_t)g * (nimg + 1) * sizeof(int);
+    int ni = nimg, tot = st.total[g];
+    void* params[] = {&a, &starts, &ni, &tot};
+    int threads = gr.resample ? 256 : 64 * gr.g.WPB;
+    return hipModuleLaunchKernel(gr.fn_batch, st.grid[g], 1, 1, threads, 1, 1, 0, s, params, nullptr);
+}
+
 void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, int& ty, int& work) {
     const Pipeline& p = plan.p;
     if (gr.resample) {
@@ -90,22 +101,23 @@ void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, i
     work = tx * ty * (gr.geo.chan_parallel ? gr.geo.C : 1);
 }
 
-void check_batch_image(const wt_image& im, const Node& n, int W, int H, const std::string& tag) {
-    if (!im.data) fail(WT_E_INVALID, tag + ": null data");
-    if (im.width != W || im.height != H) fail(WT_E_SHAPE, tag + ": size mismatch within the image's set");
-    if (im.channels != n.channels) fail(WT_E_SHAPE, tag + ": wrong channel count");
-    if (im.dtype != n.dtype) fail(WT_E_SHAPE, tag + ": element type differs from the node's");
-}
 
 }  // namespace
 
-void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
+void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream, int first,
+                    int count) {
     if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
     const Pipeline& p = plan.p;
     const int nin = (int)p.inputs.size(), nout = (int)p.outputs.size();
     if (nimg < 1) fail(WT_E_INVALID, "batch needs at least one image");
     if (!in || !out) fail(WT_E_INVALID, "null image array");
     const int G = (int)plan.groups.size();
+    const bool all = count < 0;
+    if (all) {
+        first = 0;
+        count = G;
+    }
+    if (first < 0 || count < 1 || first > G - count) fail(WT_E_INVALID, "group range outside the plan");
 
     // sizes and per-image memory of the caller's images
     std::vector<std::pair<int, int>> sizes(nimg);
@@ -118,19 +130,25 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
         for (int k = 0; k < nin; ++k) {
             const wt_image& im = in[(size_t)i * nin + k];
             int id = p.inputs[k];
-            check_batch_image(im, p.nodes[id], W, H, "batch image " + std::to_string(i) + " input " + std::to_string(k));
-            int64_t rs = im.row_stride ? im.row_stride : im.width;
-            mem[i][id] = {im.data, rs, im.chan_stride ? im.chan_stride : rs * im.height};
+            mem[i][id] = check_image(im, p.nodes[id], W, H, "batch image " + std::to_string(i) + " input " + std::to_string(k));
         }
         for (int k = 0; k < nout; ++k) {
             const wt_image& im = out[(size_t)i * nout + k];
             int id = p.outputs[k];
             auto d = level_dims(W, H, p.nodes[id].level);
-            check_batch_image(im, p.nodes[id], d.first, d.second,
-                              "batch image " + std::to_string(i) + " output " + std::to_string(k));
-            int64_t rs = im.row_stride ? im.row_stride : im.width;
-            mem[i][id] = {im.data, rs, im.chan_stride ? im.chan_stride : rs * im.height};
+            mem[i][id] = check_image(im, p.nodes[id], d.first, d.second,
+                                     "batch image " + std::to_string(i) + " output " + std::to_string(k));
         }
+    }
+    // no output may alias any other image of the batch
+    {
+        std::map<const void*, int> seen;  // data pointer -> times named
+        for (int i = 0; i < nimg * nin; ++i) ++seen[in[i].data];
+        for (int i = 0; i < nimg * nout; ++i) ++seen[out[i].data];
+        for (int i = 0; i < nimg * nout; ++i)
+            if (seen[out[i].data] > 1)
+                fail(WT_E_INVALID, "batch image " + std::to_string(i / std::max(nout, 1)) + " output " +
+                                       std::to_string(i % std::max(nout, 1)) + " aliases another image");
     }
 
     if (!plan.batch || plan.batch->sizes != sizes) {
@@ -202,13 +220,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
         hip_check(hipStreamCreate(&cs), "hipStreamCreate");
         hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
         for (int g = 0; g < G; ++g) {
-            const GroupRt& gr = plan.groups[g];
-            const void* a = static_cast<char*>(st->dargs) + (size_t)g * nimg * sizeof(WtArgsHost);
-            const void* s = static_cast<char*>(st->dargs) + st->args_bytes + (size_t)g * (nimg + 1) * sizeof(int);
-            int ni = nimg, tot = st->total[g];
-            void* params[] = {&a, &s, &ni, &tot};
-            int threads = gr.resample ? 256 : 64 * gr.g.WPB;
-            hipError_t e = hipModuleLaunchKernel(gr.fn_batch, st->grid[g], 1, 1, threads, 1, 1, 0, cs, params, nullptr);
+            hipError_t e = launch_batch_group(plan, *st, g, nimg, cs);
             if (e != hipSuccess) {
                 hipGraph_t tmp;
                 hipStreamEndCapture(cs, &tmp);
@@ -236,6 +248,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
             WtArgsHost& a = reinterpret_cast<WtArgsHost*>(st.host.data())[(size_t)g * nimg + i];
             auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[gr.g.nodes[0]].level);
             fill_args(plan, gr, mem[i], a, "batch image " + std::to_string(i));
+            check_store_planes(plan, gr, a, d.second);
             a.W = d.first;
             a.H = d.second;
             if (gr.resample) {
@@ -253,8 +266,17 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
         starts[nimg] = acc;
     }
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    hip_check(hipMemcpyAsync(st.dargs, st.host.data(), st.host.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-    hip_check(hipGraphLaunch(st.exec, s), "hipGraphLaunch");
+    // the table changes only when the caller's image pointers or strides do
+    if (st.uploaded != st.host) {
+        hip_check(hipMemcpyAsync(st.dargs, st.host.data(), st.host.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+        st.uploaded = st.host;
+    }
+    if (all) {
+        hip_check(hipGraphLaunch(st.exec, s), "hipGraphLaunch");
+        return;
+    }
+    for (int g = first; g < first + count; ++g)
+        hip_check(launch_batch_group(plan, st, g, nimg, s), "hipModuleLaunchKernel");
 }
 
 }  // namespace wt

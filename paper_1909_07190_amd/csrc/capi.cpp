@@ -88,6 +88,21 @@ wt_status wt_input_typed(wt_pipeline* p, int channels, int dtype, int* id) {
 
 wt_status wt_input(wt_pipeline* p, int channels, int* id) { return wt_input_typed(p, channels, WT_F32, id); }
 
+wt_status wt_input_bound(wt_pipeline* p, int id, double max_abs) {
+    return guard([&] {
+        if (!p) wt::fail(WT_E_INVALID, "null pipeline");
+        if (id < 0 || id >= (int)p->p.nodes.size() || p->p.nodes[id].kind != wt::Kind::Input)
+            wt::fail(WT_E_INVALID, "node " + std::to_string(id) + " is not an input");
+        wt::Node& n = p->p.nodes[id];
+        if (n.is_int()) wt::fail(WT_E_INVALID, "integer inputs carry their type's range");
+        if (!(max_abs > 0.0) || !std::isfinite(max_abs)) wt::fail(WT_E_INVALID, "bound must be positive and finite");
+        for (const wt::Node& m : p->p.nodes)
+            for (int s : m.srcs)
+                if (s == id) wt::fail(WT_E_INVALID, "declare an input's bound before a stage reads it");
+        n.bound = max_abs;
+    });
+}
+
 namespace {
 // Integer values are exact in 32-bit registers below this magnitude.
 constexpr double kInt32Max = 2147483647.0;
@@ -283,11 +298,12 @@ wt_status wt_output(wt_pipeline* p, int id) {
     });
 }
 
-wt_status wt_plan_create(const wt_pipeline* p, const wt_sched_opts* opts, int width, int height, wt_plan** out) {
+wt_status wt_plan_create(const wt_pipeline* p, const wt_sched_opts* opts, int width, int height, void* stream,
+                         wt_plan** out) {
     return guard([&] {
         if (!p || !out) wt::fail(WT_E_INVALID, "null argument");
         *out = nullptr;
-        auto impl = wt::create_plan(p->p, opts, width, height);
+        auto impl = wt::create_plan(p->p, opts, width, height, stream);
         *out = new wt_plan{std::move(impl)};
     });
 }
@@ -303,6 +319,15 @@ wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in, const w
     return guard([&] {
         if (!plan) wt::fail(WT_E_INVALID, "null plan");
         wt::run_plan_batch(*plan->impl, nimg, in, out, stream);
+    });
+}
+
+wt_status wt_plan_run_batch_groups(wt_plan* plan, int first, int count, int nimg, const wt_image* in,
+                                   const wt_image* out, void* stream) {
+    return guard([&] {
+        if (!plan) wt::fail(WT_E_INVALID, "null plan");
+        if (count < 1) wt::fail(WT_E_INVALID, "count must be at least 1");
+        wt::run_plan_batch(*plan->impl, nimg, in, out, stream, first, count);
     });
 }
 
@@ -506,6 +531,21 @@ wt_status wt_mlp_train(wt_mlp* m, const float* x, const float* t, int n, int epo
         if (final_loss) *final_loss = l;
     });
 }
+wt_status wt_model_train(const char* measure_db, const char* out_model, void* stream) {
+    return guard([&] {
+        if (!measure_db || !out_model) wt::fail(WT_E_INVALID, "null path");
+        wt::train_model_from_db(measure_db, out_model, reinterpret_cast<hipStream_t>(stream));
+    });
+}
+
+wt_status wt_model_rows(const char* measure_db, int* rows) {
+    return guard([&] {
+        if (!measure_db || !rows) wt::fail(WT_E_INVALID, "null argument");
+        std::vector<float> x, t;
+        *rows = wt::read_measure_db(measure_db, x, t);
+    });
+}
+
 wt_status wt_mlp_predict(wt_mlp* m, const float* x, int n, float* y) {
     return guard([&] {
         if (!m || !x || !y || n < 1) wt::fail(WT_E_INVALID, "bad predict arguments");

@@ -641,7 +641,7 @@ struct Gen {
     }
     bool dec_half(size_t k) const {
         int d = geo.dec[k].first;
-        return g.fp16 && !P.nodes[d].is_int() && !P.is_output(d);
+        return g.fp16 && P.half_storable(d) && !P.is_output(d);
     }
     // Decimated store of a member row (down2 fused into its producer): on
     // even rows, the elements at even x go to (x/2, r/2) of the down2 node;

@@ -84,7 +84,10 @@ struct Search {
         base.nodes = nodes;
         base.fp16 = r.fp16;
         if (nodes.size() == 1 && !fusable[pos[nodes[0]]]) {
-            double t = resample_pred_us(p, nodes[0], m, r.W, r.H, r.fp16, r.fp16 && !p.is_output(nodes[0]));
+            int src = p.nodes[nodes[0]].srcs[0];
+            double t = resample_pred_us(p, nodes[0], m, r.W, r.H,
+                                        r.fp16 && p.half_storable(src) && !p.is_output(src),
+                                        r.fp16 && p.half_storable(nodes[0]) && !p.is_output(nodes[0]));
             auto res = std::make_pair(t, base);
             gcache[g] = res;
             return res;
@@ -272,7 +275,7 @@ std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, con
                         continue;
                     }
                     for (auto& ng : geo.nodes)
-                        ng.mem_half = r.fp16 && p.nodes[ng.id].kind != Kind::Input && !p.is_output(ng.id) &&
+                        ng.mem_half = r.fp16 && p.half_storable(ng.id) && !p.is_output(ng.id) &&
                                       (!ng.member || ng.liveout);
                     auto shared = std::make_shared<const GroupGeom>(geo);
                     for (int TY : {8, 16, 32, 64})

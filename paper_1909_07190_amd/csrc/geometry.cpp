@@ -121,7 +121,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         ng.vlo = ng.vhi = 0;
         ng.consumed = false;
         ng.lds_off = 0;
-        ng.half = g.fp16 && ng.member && !p.nodes[ng.id].is_int();
+        ng.half = g.fp16 && ng.member && p.half_storable(ng.id);
         ng.mem_half = false;
     }
 

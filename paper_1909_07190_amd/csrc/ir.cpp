@@ -20,6 +20,14 @@ std::vector<std::vector<int>> Pipeline::consumers() const {
     return c;
 }
 
+// Largest finite FP16 value.
+constexpr double kHalfMax = 65504.0;
+
+bool Pipeline::half_storable(int n) const {
+    const Node& nd = nodes[n];
+    return nd.kind != Kind::Input && !nd.is_int() && nd.bound <= kHalfMax;
+}
+
 bool Pipeline::is_output(int n) const {
     for (int o : outputs)
         if (o == n) return true;

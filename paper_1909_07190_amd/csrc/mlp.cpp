@@ -69,7 +69,16 @@ Mlp::Mlp(const std::vector<int>& d, uint64_t seed) : dims(d) {
     in_std.assign(dims[0], 1.f);
 }
 
-Mlp::~Mlp() { release(); }
+Mlp::~Mlp() {
+    release();
+    if (stream && own_stream) hipStreamDestroy(stream);
+}
+
+void Mlp::use_stream(hipStream_t s) {
+    if (dparams) fail(WT_E_INVALID, "the model's stream is set before its first device operation");
+    stream = s;
+    own_stream = false;
+}
 
 void Mlp::release() {
     for (float* p : {dparams, dgrads, dm, dv, dx, dt, dy, dloss})
@@ -86,7 +95,10 @@ void Mlp::release() {
 
 void Mlp::ensure_device(int batch) {
     if (!dparams) {
-        hip_check(hipStreamCreate(&stream), "hipStreamCreate");
+        if (!stream) {
+            hip_check(hipStreamCreate(&stream), "hipStreamCreate");
+            own_stream = true;
+        }
         dparams = dalloc(nparams);
         dgrads = dalloc(nparams);
         dm = dalloc(nparams);

@@ -204,8 +204,8 @@ void preprofile(const Plan& plan) {
 
     float* out = nullptr;
     if (hipMalloc(&out, 256) != hipSuccess) fail(WT_E_NOMEM, "profile scratch");
-    hipStream_t st;
-    hip_check(hipStreamCreate(&st), "hipStreamCreate");
+    OwnedStream ost(plan.setup_stream);
+    hipStream_t st = ost.s;
     std::vector<StageProfile> res(todo.size());
     try {
         double base = time_kernel_ns(benches.back().fn, out, st) / kIters;
@@ -226,13 +226,11 @@ void preprofile(const Plan& plan) {
             res[i] = sp;
         }
     } catch (...) {
-        hipStreamDestroy(st);
         hipFree(out);
         for (auto& b : benches) unload_group(b);
         for (auto& u : units) unload_group(u);
         throw;
     }
-    hipStreamDestroy(st);
     hipFree(out);
     for (auto& b : benches) unload_group(b);
     for (auto& u : units) unload_group(u);

@@ -158,7 +158,7 @@ void tune_cache_store(const std::string& dir, const std::string& key, const std:
     if (f) f << key << '\t' << text << '\n';
 }
 
-std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H) {
+std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H, void* stream) {
     if (W <= 0 || H <= 0) fail(WT_E_SHAPE, "plan size must be positive");
     if (W > (1 << 24) || H > (1 << 24)) fail(WT_E_SHAPE, "plan size too large");
     if (p.outputs.empty()) fail(WT_E_INVALID, "pipeline has no outputs");
@@ -174,6 +174,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     plan->fp16 = opts.fp16_intermediates != 0;
     plan->any_width = (opts.flags & WT_PLAN_ANY_WIDTH) != 0;
     plan->batch_resident = (opts.flags & WT_PLAN_BATCH_RESIDENT) != 0;
+    plan->setup_stream = reinterpret_cast<hipStream_t>(stream);
     const char* env_cache = std::getenv("WT_CACHE_DIR");
     plan->cache_dir = opts.cache_dir ? opts.cache_dir : (env_cache ? env_cache : "");
     if (!plan->no_device) hip_check(hipGetDevice(&plan->device), "hipGetDevice");
@@ -223,7 +224,7 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     gr.W = d.first;
     gr.H = d.second;
     auto half_mem = [&](int id) {
-        return plan.fp16 && p.nodes[id].kind != Kind::Input && !p.is_output(id) && !p.nodes[id].is_int();
+        return plan.fp16 && p.half_storable(id) && !p.is_output(id);
     };
     gr.mem_half_in.clear();
     gr.mem_half_out.clear();
@@ -374,10 +375,7 @@ void build_groups(Plan& plan) {
     }
 }
 
-namespace {
-
-ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const char* what, int idx) {
-    std::string tag = std::string(what) + " " + std::to_string(idx);
+ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const std::string& tag) {
     if (!im.data) fail(WT_E_INVALID, tag + ": null data");
     if (im.width != W || im.height != H)
         fail(WT_E_SHAPE, tag + ": size " + std::to_string(im.width) + "x" + std::to_string(im.height) +
@@ -398,6 +396,15 @@ ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const char* 
     return r;
 }
 
+void check_store_planes(const Plan& plan, const GroupRt& gr, const WtArgsHost& a, int H) {
+    // stores address a plane with 32-bit byte offsets (buffer stores)
+    for (size_t i = 0; i < gr.liveouts.size(); ++i)
+        if ((double)a.dst_rs[i] * H * node_esize(plan.p, gr.liveouts[i], gr.mem_half_out[i]) >= 2147483647.0)
+            fail(WT_E_UNSUPPORTED, "an output plane of 2 GiB or more");
+}
+
+namespace {
+
 void check_align(const ImgRef& r, int V, int esize, const std::string& tag) {
     if (V == 1) return;
     if ((reinterpret_cast<uintptr_t>(r.ptr) % (esize * V)) || (r.rs % V) || (r.cs % V))
@@ -414,11 +421,12 @@ void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int 
         fail(WT_E_INVALID, "expected " + std::to_string(p.outputs.size()) + " outputs");
     if ((!in && nin) || (!out && nout)) fail(WT_E_INVALID, "null image array");
     std::map<int, ImgRef> mem;
-    for (int i = 0; i < nin; ++i) mem[p.inputs[i]] = check_image(in[i], p.nodes[p.inputs[i]], plan.W, plan.H, "input", i);
+    for (int i = 0; i < nin; ++i)
+        mem[p.inputs[i]] = check_image(in[i], p.nodes[p.inputs[i]], plan.W, plan.H, "input " + std::to_string(i));
     for (int i = 0; i < nout; ++i) {
         int id = p.outputs[i];
         auto d = level_dims(plan.W, plan.H, p.nodes[id].level);
-        ImgRef r = check_image(out[i], p.nodes[id], d.first, d.second, "output", i);
+        ImgRef r = check_image(out[i], p.nodes[id], d.first, d.second, "output " + std::to_string(i));
         for (auto& kv : mem)
             if (kv.second.ptr == r.ptr) fail(WT_E_INVALID, "output " + std::to_string(i) + " aliases another image");
         mem[id] = r;
@@ -456,9 +464,7 @@ void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRe
     const Pipeline& p = plan.p;
     WtArgsHost a;
     fill_args(plan, gr, mem, a, "");
-    for (size_t i = 0; i < gr.liveouts.size(); ++i)
-        if ((double)a.dst_rs[i] * gr.H * node_esize(plan.p, gr.liveouts[i], gr.mem_half_out[i]) >= 2147483647.0)
-            fail(WT_E_UNSUPPORTED, "an output plane of 2 GiB or more");
+    check_store_planes(plan, gr, a, gr.H);
     a.W = gr.W;
     a.H = gr.H;
     a.Ws = gr.Ws;

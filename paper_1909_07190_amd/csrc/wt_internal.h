@@ -67,7 +67,7 @@ struct Node {
     // pointwise
     std::string expr_text;
     Expr expr;
-    double bound = 1.0;          // magnitude bound (inputs assumed in [-1, 1])
+    double bound = 1.0;          // magnitude bound (float inputs: 1, or as declared)
     // element type; integer stencils use integer weights and a divisor
     int dtype = WT_F32;
     std::vector<long long> iweights;
@@ -86,6 +86,10 @@ struct Pipeline {
     // read p, or reads it through a resampling dependence).
     std::vector<Tap> taps(int c, int p) const;
     bool is_output(int n) const;
+    // FP16 storage (the plan's FP16-intermediate option) is allowed for
+    // float stages whose magnitude bound fits FP16's finite range; every
+    // other stage keeps its own element type.
+    bool half_storable(int n) const;
 };
 
 // ---------------------------------------------------------- schedule -----

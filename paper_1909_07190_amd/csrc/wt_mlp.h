@@ -32,6 +32,9 @@ struct Mlp {
     float train(const float* x, const float* t, int n, int epochs, int batch, float lr, uint64_t seed);
     void predict(const float* x, int n, float* y);                  // normalised in, target units out
     double max_abs_z(const float* x) const;
+    // Device work runs on `s` (the caller's, kept) instead of a stream of
+    // the model's own; call before the first device operation.
+    void use_stream(hipStream_t s);
     void upload_params();
     void download_params();
     void save(const std::string& path) const;
@@ -39,6 +42,7 @@ struct Mlp {
 
    private:
     hipStream_t stream = nullptr;
+    bool own_stream = false;
     float *dparams = nullptr, *dgrads = nullptr, *dm = nullptr, *dv = nullptr;
     float *dx = nullptr, *dt = nullptr, *dy = nullptr, *dloss = nullptr;
     std::vector<float*> dact, ddz;
@@ -49,5 +53,13 @@ struct Mlp {
     void adam_step(float lr);
     void release();
 };
+
+// Rows of a measurement database (JSON lines): the 40 features (row-major
+// into x) and log(measured microseconds) (into t) of every usable line;
+// returns the row count.
+int read_measure_db(const std::string& path, std::vector<float>& x, std::vector<float>& t);
+// Trains the cost network (40-128-128-128-1, 200 epochs of Adam, batch 256,
+// lr 1e-3, seed 1) on every usable row of `db` and saves it to `out_model`.
+void train_model_from_db(const std::string& db, const std::string& out_model, hipStream_t stream);
 
 }  // namespace wt

@@ -63,6 +63,7 @@ struct BatchState {
     void* dargs = nullptr;                 // device argument table
     size_t args_bytes = 0, dargs_bytes = 0;
     std::vector<char> host;                // host copy of the table
+    std::vector<char> uploaded;            // the table as last copied to the device
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~BatchState();
@@ -81,6 +82,7 @@ struct Plan {
     bool fp16 = false;
     bool any_width = false;
     bool batch_resident = false;  // WT_PLAN_BATCH_RESIDENT
+    hipStream_t setup_stream = nullptr;  // caller's stream for planning-time measurements
     std::string cache_dir;
     std::unique_ptr<BatchState> batch;
     ~Plan();
@@ -94,11 +96,19 @@ struct ImgRef {
 void hip_check(hipError_t e, const char* what);
 
 // Owned HIP stream and event pair, released on every exit path.
+// A stream for the library's own measurements: the caller's when given
+// (not destroyed), else one created and destroyed here.
 struct OwnedStream {
     hipStream_t s = nullptr;
-    OwnedStream() { hip_check(hipStreamCreate(&s), "hipStreamCreate"); }
+    bool owned = false;
+    explicit OwnedStream(hipStream_t ext = nullptr) : s(ext) {
+        if (!s) {
+            hip_check(hipStreamCreate(&s), "hipStreamCreate");
+            owned = true;
+        }
+    }
     ~OwnedStream() {
-        if (s) hipStreamDestroy(s);
+        if (s && owned) hipStreamDestroy(s);
     }
     OwnedStream(const OwnedStream&) = delete;
     OwnedStream& operator=(const OwnedStream&) = delete;
@@ -129,11 +139,20 @@ std::pair<int, int> level_dims(int W, int H, int level);
 void prepare_group(const Plan& plan, GroupRt& gr, int gi);
 void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch = false);
 void unload_group(GroupRt& gr);
+// Validates a caller image against node `n` at W x H (null data, size,
+// channels, element type, strides); returns its dense-resolved strides.
+ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const std::string& tag);
+// Refuses live-out planes whose byte offsets would not fit the 32-bit
+// offsets of buffer stores.
+void check_store_planes(const Plan& plan, const GroupRt& gr, const WtArgsHost& a, int H);
 void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st);
 void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, WtArgsHost& a,
                const std::string& tag);
 int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads);
-void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
+// count < 0: every group, replayed from the batch shape's graph; otherwise
+// groups [first, first + count), launched directly on the stream.
+void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream, int first = 0,
+                    int count = -1);
 // Measures candidate configurations of every fused group and keeps the
 // fastest; candidates ranked by the learned model when `model_path` is set.
 // With `batch` > 1 the candidates are timed on an image as tall as up to
@@ -152,7 +171,7 @@ bool preprofile_enabled();
 StageProfile stage_profile(const Pipeline& p, int id, int W, int H, bool measure);
 void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vector<std::string>& descs, int reps,
                     const std::string& tag, double* out_us);
-std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H);
+std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H, void* stream);
 void build_groups(Plan& plan);
 void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int nout, void* stream);
 std::string describe_plan(const Plan& plan);

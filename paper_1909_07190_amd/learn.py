@@ -214,16 +214,21 @@ def split_tags(rows, test_fraction=0.2, seed=0):
     return set(tags[ntest:]), set(tags[:ntest])
 
 
-def train(rows, model_path, epochs=200, batch=256, lr=1e-3, seed=1, log=print):
-    x = np.array([r["features"] for r in rows], np.float32)
-    y = np.log(np.array([r["measured_us"] for r in rows], np.float64)).astype(np.float32)
-    assert x.shape[1] == NUM_FEATURES
-    net = Mlp(seed=seed)
+def train(rows, model_path, log=print):
+    """Trains the cost network on `rows` through the library's
+    wt_model_train (the rows are written to a JSON-lines file beside the
+    model, which the library parses, standardises and trains on)."""
+    from . import model_rows, model_train
+    db = model_path + ".train.jsonl"
+    with open(db, "w") as f:
+        for r in rows:
+            f.write(json.dumps(r) + "\n")
+    assert model_rows(db) == len(rows)
     t0 = time.time()
-    loss = net.train(x, y, epochs=epochs, batch=batch, lr=lr, seed=seed)
-    log(f"train: {len(rows)} rows, {epochs} epochs, {time.time() - t0:.1f} s, final loss {loss}")
-    net.save(model_path)
-    return net
+    model_train(db, model_path)
+    os.remove(db)
+    log(f"train: {len(rows)} rows, {time.time() - t0:.1f} s")
+    return Mlp.load(model_path)
 
 
 def kendall_tau(a, b):
@@ -493,7 +498,6 @@ def main(argv=None):
     t.add_argument("--db", required=True, nargs="+")
     t.add_argument("--holdout", help="file of held-out pipeline tags (default: a seeded fifth)")
     t.add_argument("--model", required=True)
-    t.add_argument("--epochs", type=int, default=200)
     t.add_argument("--report", help="write the ranking report (JSON) here")
     f = sub.add_parser("fit-analytic", help="refit the analytical model's coefficients")
     f.add_argument("--db", required=True, nargs="+")
@@ -528,7 +532,7 @@ def main(argv=None):
         rows = load_db(a.db)
         tr, te = split_by_holdout(rows, a.holdout) if a.holdout else split_tags(rows)
         train_rows = [r for r in rows if r["pipeline"] in tr]
-        net = train(train_rows, a.model, epochs=a.epochs, log=log)
+        net = train(train_rows, a.model, log=log)
         fit = fit_analytic(train_rows)
         rep = {"train_pipelines": len(tr), "test_pipelines": len(te), "train_rows": len(train_rows),
                "test_rows": len(rows) - len(train_rows), "analytic_fit": fit,

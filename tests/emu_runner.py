@@ -16,13 +16,7 @@ CACHE = os.path.join(os.path.dirname(HERE), "_build", "emu")
 CLANG = "/opt/rocm/llvm/bin/clang++"
 
 
-class GroupInfo(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in
-                ("resample", "waves_per_group", "nwaves", "tiles_x", "tiles_y", "width", "height",
-                 "src_width", "src_height", "channels", "nloaded", "nliveouts")] + \
-               [("loaded", ctypes.c_int32 * 16), ("liveouts", ctypes.c_int32 * 16),
-                ("loaded_half", ctypes.c_int32 * 16), ("liveout_half", ctypes.c_int32 * 16),
-                ("loaded_dtype", ctypes.c_int32 * 16), ("liveout_dtype", ctypes.c_int32 * 16)]
+GroupInfo = wt.GroupInfo
 
 
 class Args(ctypes.Structure):
@@ -32,8 +26,6 @@ class Args(ctypes.Structure):
                [(n, ctypes.c_int32) for n in ("W", "H", "Ws", "Hs", "tiles_x", "tiles_y", "nwaves", "pad")]
 
 
-wt.lib.wt_plan_group_info.restype = ctypes.c_int
-wt.lib.wt_plan_group_info.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(GroupInfo)]
 
 RUNNER = r"""
 extern "C" int wt_emu_run(const WtArgs* a, int nwaves, int wpb) {

@@ -356,3 +356,41 @@ def test_ghost_columns_align_tiles():
     with pytest.raises(wt.WtError):
         wt.from_spec(UM).plan(256, 64, mode="fixed", no_device=True, no_compile=True,
                               fixed="nodes=1,2,3,4 V=2 TX=2 SX=1 TY=8 GH=1")
+
+
+def _harris_255():
+    spec = P.harris()
+    spec["inputs"][0]["bound"] = 255.0
+    return spec
+
+
+def test_fp16_storage_follows_magnitude_bounds():
+    """With inputs declared within [-255, 255], the Harris products and box
+    sums can exceed FP16's range (|Ix|^2 <= 1020^2): only gray and the Sobel
+    gradients are stored FP16, the rest stays FP32 (unfused plan, every
+    intermediate in memory)."""
+    import ctypes
+    import paper_1909_07190_amd as wt
+    from emu_runner import GroupInfo
+    for spec, want in ((P.harris(), {"gray", "Ix", "Iy", "Ixx", "Iyy", "Ixy", "Sxx", "Syy", "Sxy"}),
+                       (_harris_255(), {"gray", "Ix", "Iy"})):
+        pipe = wt.from_spec(spec)
+        plan = pipe.plan(256, 64, mode="unfused", fp16=True, no_device=True)
+        names = {v: k for k, v in pipe.names.items()}
+        half = set()
+        for g in range(plan.num_groups):
+            gi = GroupInfo()
+            wt._check(wt.lib.wt_plan_group_info(plan._h, g, ctypes.byref(gi)))
+            half |= {names[gi.liveouts[i]] for i in range(gi.nliveouts) if gi.liveout_half[i]}
+        assert half == want
+
+
+def test_fp16_harris_on_0_255_inputs_stays_finite():
+    """Harris on 0..255-scaled RGB with FP16 intermediates, fused: the
+    stages past FP16's range keep FP32, so the response is finite and within
+    the FP16 tolerance of the oracle."""
+    spec = _harris_255()
+    img = (synth.uniform_image(11, 3, 21, 260) * 255.0).astype(np.float32)
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fp16=True,
+                     fixed="nodes=1,2,3,4,5,6,7,8,9,10 V=4 TX=1 SX=0 TY=8 PF=1 fp16=1")
+    assert_normwise(got["R"], oracle.evaluate(spec, {"img": img})["R"], 2e-3, "harris 0..255 fp16")

@@ -60,3 +60,32 @@ def test_fits_a_teacher_network():
     pred = net.predict(x.astype(np.float32))
     mse = float(np.mean((pred - t) ** 2)) / float(np.var(t))
     assert mse < 2e-2, f"relative training MSE {mse:.3e}"
+
+
+def test_model_train_from_measurement_db(tmp_path):
+    """wt_model_train on a measurement database equals training the same
+    network on the same rows through wt_mlp_train (same seed, same device
+    kernels), and fits the database's timings."""
+    import json
+    print("model train from a measurement database", flush=True)
+    rng = np.random.default_rng(9)
+    tdims = [40, 8, 1]
+    tp = rng.normal(size=sum(a * b + b for a, b in zip(tdims[:-1], tdims[1:]))) * 0.3
+    x = rng.normal(size=(1200, 40)).astype(np.float32)
+    logt = M.forward(tp, tdims, x.astype(np.float64))[-1][:, 0]
+    db = tmp_path / "db.jsonl"
+    with open(db, "w") as f:
+        for i in range(len(x)):
+            f.write(json.dumps({"pipeline": f"p{i % 7}", "W": 64, "H": 64, "group": "nodes=1",
+                                "measured_us": float(np.exp(logt[i])), "pred_us": 1.0, "score": 0.0,
+                                "terms": [0.0] * 7, "features": [float(v) for v in x[i]]}) + "\n")
+    model = str(tmp_path / "m.txt")
+    wt.model_train(str(db), model)
+    got = wt.Mlp.load(model)
+    t32 = np.log(np.array([float(np.exp(v)) for v in logt], np.float64)).astype(np.float32)
+    ref = wt.Mlp(DIMS, seed=1)
+    ref.train(x, t32, epochs=200, batch=256, lr=1e-3, seed=1)
+    np.testing.assert_array_equal(got.params(), ref.params())
+    np.testing.assert_array_equal(got.predict(x), ref.predict(x))
+    mse = float(np.mean((got.predict(x) - logt) ** 2)) / float(np.var(logt))
+    assert mse < 5e-2, f"relative training MSE {mse:.3e}"

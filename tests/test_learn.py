@@ -141,3 +141,34 @@ def test_summarize_subset_of_modes():
     out = learn.summarize(rows)
     assert out["mlp"]["pipelines"] == 2 and out["mlp_autotune"]["within_10pct"] == 1.0
     assert out["mlp_gain_over_analytic"] is None and "analytic" not in out
+
+
+def test_measure_db_rows_counted_by_the_library(tmp_path):
+    """The C-ABI parser of the measurement database keeps exactly the lines
+    with a positive finite time, 40 finite features and defined analytical
+    quantities (the rule learn.load_db applies)."""
+    import json
+    import paper_1909_07190_amd as wt
+    from paper_1909_07190_amd import learn
+    good = {"pipeline": "dag1", "W": 64, "H": 64, "group": "nodes=1 V=4", "measured_us": 12.5,
+            "pred_us": 10.0, "score": 3.0, "terms": [0.5] * 7, "features": [0.25] * 40}
+    lines = [json.dumps(good),
+             json.dumps(dict(good, measured_us=None)),
+             json.dumps(dict(good, measured_us=-1.0)),
+             json.dumps(dict(good, pred_us=None)),
+             json.dumps(dict(good, features=[0.25] * 39)),
+             json.dumps(dict(good, features=[0.25] * 39 + [None])),
+             json.dumps(dict(good, terms=[0.5] * 6 + [None])),
+             json.dumps(good).replace('"score": 3.0', '"score": 3.0e0'),
+             json.dumps(dict(good, measured_us=3e2, features=[-1.5e-3] * 40)),
+             json.dumps(dict(good, terms=[0.5] * 6 + [None])).replace("null", "inf"),
+             ""]
+    db = tmp_path / "db.jsonl"
+    db.write_text("\n".join(lines) + "\n")
+    assert wt.model_rows(str(db)) == 3 == len(learn.load_db([str(db)]))
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"pipeline": "x"}\n')
+    with pytest.raises(wt.WtError):
+        wt.model_rows(str(bad))
+    with pytest.raises(wt.WtError):
+        wt.model_rows(str(tmp_path / "missing.jsonl"))
