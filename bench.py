@@ -371,6 +371,8 @@ def bench_image(args, torch, wt, synth, P, cyc, name):
                         "algorithmic_bytes": nbytes}}
     log(f"{name} {HEADLINE_MODE}: {ms * 1e3:.2f} us, {res['roofline']['achieved']:.0f} GB/s ({plan.describe().strip()})")
     ref = outs[(args.steps - 1) % nsets].clone()
+    if name == "unsharp":
+        res["copy_reference"] = copy_reference(torch, wt, ins, outs, args.steps, cyc)
     if args.no_extra:
         return res
     legs = [("unfused", dict(mode="unfused")),
@@ -387,8 +389,6 @@ def bench_image(args, torch, wt, synth, P, cyc, name):
                     "vs_scheduled": lms / ms, "max_rel_diff": diff, "schedule": pl.describe().strip()}
         log(f"{name} {key}: {lms * 1e3:.2f} us ({pl.num_groups} launches), max rel diff {diff:.1e}")
         del pl
-    if name == "unsharp":
-        res["copy_reference"] = copy_reference(torch, wt, ins, outs, args.steps, cyc)
     return res
 
 

@@ -151,16 +151,23 @@ typedef enum {
 
 enum {
     WT_PLAN_NO_DEVICE = 1, /* generate and compile code only; run() refused   */
-    WT_PLAN_ANY_WIDTH = 2, /* caller images may have any width and stride:
-                              groups touching them use one element per lane */
+    WT_PLAN_ANY_WIDTH = 2, /* caller images of 8- or 16-bit integer
+                              elements may have any width and stride: groups
+                              touching them use one element per lane (32-bit
+                              elements allow any width and stride in every
+                              plan) */
     WT_PLAN_NO_COMPILE = 4, /* schedule and generate code only (implies
                                WT_PLAN_NO_DEVICE); wt_plan_source still works */
     WT_PLAN_RETUNE = 8,     /* WT_SCHED_AUTOTUNE: measure again even when the
                                schedule cache holds a result (and replace it) */
-    WT_PLAN_BATCH_RESIDENT = 16 /* wt_plan_run_batch launches only the
+    WT_PLAN_BATCH_RESIDENT = 16, /* wt_plan_run_batch launches only the
                                workgroups resident at once, each looping over
                                its share of the work units (persistent); by
                                default every work unit gets a workgroup */
+    WT_PLAN_NO_FOLD = 32    /* the fusion search keeps every up2 out of the
+                               groups (read by expansion in its consumers'
+                               groups) instead of folding an up2 of a
+                               decimated stage into that stage's group */
 };
 
 /* WT_SCHED_AUTOTUNE results are cached, keyed by the device architecture,
@@ -235,9 +242,10 @@ wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
  * captured in a
  * hipGraph on the first run of a batch shape (the list of sizes) and
  * replayed while the shape is unchanged (only image pointers may change).
- * Intermediates live in a plan-owned arena sized for the shape.  Each
- * image must satisfy the plan's vector-width alignment (plan with
- * WT_PLAN_ANY_WIDTH for arbitrary widths).  Asynchronous on `hip_stream`. */
+ * Intermediates live in a plan-owned arena sized for the shape.  Images of
+ * 8- or 16-bit integer elements must satisfy the plan's vector-width
+ * alignment (plan with WT_PLAN_ANY_WIDTH for arbitrary widths).
+ * Asynchronous on `hip_stream`. */
 wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in,
                             const wt_image* out, void* hip_stream);
 

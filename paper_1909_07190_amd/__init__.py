@@ -37,6 +37,7 @@ PLAN_ANY_WIDTH = 2
 PLAN_NO_COMPILE = 4
 PLAN_RETUNE = 8
 PLAN_BATCH_RESIDENT = 16
+PLAN_NO_FOLD = 32
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 
@@ -179,7 +180,7 @@ class Pipeline:
     def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
              no_device=False, model_path=None, cache_dir=None, autotune_topk=0,
              any_width=False, no_compile=False, retune=False, batch_images=1,
-             batch_resident=False) -> "Plan":
+             batch_resident=False, no_fold=False) -> "Plan":
         """Schedules and compiles the pipeline for width x height.  mode
         "mlp" without a model_path uses the network trained on gfx950
         measurements that ships with the package (GFX950_COST_MODEL).  Mode
@@ -189,11 +190,13 @@ class Pipeline:
         counts their waves and traffic; "autotune" times its candidates on an
         image as tall as up to that many).  `batch_resident`: run_batch
         launches only the workgroups resident at once, each looping over its
-        share of the tiles, instead of one workgroup per work unit."""
+        share of the tiles, instead of one workgroup per work unit.
+        `no_fold`: the fusion search never folds an up2 into the group of
+        the stage whose decimation it expands."""
         if mode == "mlp" and model_path is None:
             model_path = GFX950_COST_MODEL
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
-                    autotune_topk, any_width, no_compile, retune, batch_images, batch_resident)
+                    autotune_topk, any_width, no_compile, retune, batch_images, batch_resident, no_fold)
 
 
 def stream_copy(src, dst, stream=None):
@@ -265,11 +268,11 @@ class Plan:
 
     def __init__(self, pipe: Pipeline, width, height, mode, fp16, fixed, no_device,
                  model_path, cache_dir, autotune_topk, any_width=False, no_compile=False, retune=False,
-                 batch_images=1, batch_resident=False):
+                 batch_images=1, batch_resident=False, no_fold=False):
         self.pipe = pipe  # keeps the pipeline alive
         flags = ((PLAN_NO_DEVICE if no_device else 0) | (PLAN_ANY_WIDTH if any_width else 0)
                  | (PLAN_NO_COMPILE if no_compile else 0) | (PLAN_RETUNE if retune else 0)
-                 | (PLAN_BATCH_RESIDENT if batch_resident else 0))
+                 | (PLAN_BATCH_RESIDENT if batch_resident else 0) | (PLAN_NO_FOLD if no_fold else 0))
         opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), flags,
                            autotune_topk, fixed.encode() if fixed else None,
                            model_path.encode() if model_path else None,

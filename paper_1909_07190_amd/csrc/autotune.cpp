@@ -181,7 +181,7 @@ struct PlanHeight {
 
 }  // namespace
 
-void autotune_plan(Plan& plan, int topk, const std::string& model_path, int batch) {
+double autotune_plan(Plan& plan, int topk, const std::string& model_path, int batch) {
     const Pipeline& p = plan.p;
     DeviceScratch sc;
     std::map<int, ImgRef> mem = scratch_memory(plan, sc);
@@ -207,10 +207,14 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path, int batc
     std::snprintf(hbuf, sizeof hbuf, "%016llx", (unsigned long long)phash);
     const std::string tag = hbuf;
 
+    double total_us = 0;  // the chosen configurations' times per image
     for (size_t gi = 0; gi < plan.sched.groups.size(); ++gi) {
-        if (plan.groups[gi].resample) continue;
+        if (plan.groups[gi].resample) {
+            total_us += time_group_us(plan, plan.groups[gi], mem, st, 20);
+            continue;
+        }
         const GroupSched cur = plan.sched.groups[gi];
-        std::vector<ScoredConfig> all = score_configs(p, plan.machine, req, cur.nodes);
+        std::vector<ScoredConfig> all = score_configs(p, plan.machine, req, cur.nodes, cur.dec);
         std::vector<const ScoredConfig*> by_pred, by_score;
         for (auto& c : all) {
             by_pred.push_back(&c);
@@ -307,8 +311,13 @@ void autotune_plan(Plan& plan, int topk, const std::string& model_path, int batc
         }
         for (auto& t : trials) unload_group(t);
         plan.sched.groups[gi] = best;
+        total_us += best_t / k;
+        if (verbose())
+            std::fprintf(stderr, "wavetile autotune: group %zu of %zu, %zu candidates, best %.1f us on %d image(s): %s\n",
+                         gi + 1, plan.sched.groups.size(), trials.size(), best_t, k, describe_group(best).c_str());
     }
     build_groups(plan);
+    return total_us;
 }
 
 // Times arbitrary candidate groups of a pipeline on scratch images (every

@@ -67,6 +67,13 @@ struct Gen {
                         t == "unsigned char" ? "wt_b" : t == "unsigned short" ? "wt_us" : "wt_s";
         return b + std::to_string(V);
     }
+    // vector type for a global load of V elements of C type `t`: 32-bit
+    // elements need only their own alignment (rows may start anywhere)
+    static std::string gvec(const std::string& t, int V) {
+        if (t == "float") return "wt_f" + std::to_string(V) + "d";
+        if (t == "int") return "wt_i" + std::to_string(V) + "d";
+        return vec(t, V);
+    }
     // unsigned type of `bytes` bytes and the buffer store of that width
     static std::string store_ty(int bytes) {
         switch (bytes) {
@@ -93,7 +100,21 @@ struct Gen {
         return "g" + I(id) + (left ? "l" : "r") + "[" + I(slot) + "][" + I(ch) + "][" + I(e) + "]";
     }
     bool has_lds(const NodeGeom& n) const { return SX > 0 && (n.consumed || !n.member); }
+    // FP16 members with an even number of elements per lane keep their
+    // register rows as packed pairs, two values per VGPR (wt_h2); they are
+    // converted to FP32 when read (the arithmetic stays FP32).
+    bool packed(int id) const {
+        const NodeGeom& n = G(id);
+        return n.half && V % 2 == 0 && has_regs(n);
+    }
+    // The packed pair holding element e, as an lvalue.
+    std::string preg(int id, int slot, int ch, int kr, int e) {
+        return "w" + I(id) + "[" + I(slot) + "][" + I(ch) + "][" + I(kr) + "][" + I(e / 2) + "]";
+    }
+    // Element e of a register row: an lvalue, or for packed rows the
+    // element converted to FP32 (an rvalue; writes go through preg).
     std::string reg(int id, int slot, int ch, int kr, int e) {
+        if (packed(id)) return "((float)" + preg(id, slot, ch, kr, e) + "[" + I(e % 2) + "])";
         return "w" + I(id) + "[" + I(slot) + "][" + I(ch) + "][" + I(kr) + "][" + I(e) + "]";
     }
     // LDS element index of (slot, ch, j) of node id
@@ -491,7 +512,7 @@ struct Gen {
                     std::string ld0 = g.NT ? "__builtin_nontemporal_load(rp + xb)" : "rp[xb]";
                     if (V == 1) line("  " + dst[0] + " = (" + ct + ")" + ld0 + ";");
                     else {
-                        std::string vt = vec(ty, V);
+                        std::string vt = gvec(ty, V);
                         if (g.NT)
                             line("  const " + vt + " q = __builtin_nontemporal_load((const " + vt + "*)(rp + xb));");
                         else
@@ -535,7 +556,7 @@ struct Gen {
         if (!border) {
             if (V == 1) line("  " + dst[0] + " = (" + ct + ")rp[xg];");
             else {
-                std::string vt = vec(ty, V);
+                std::string vt = gvec(ty, V);
                 line("  const " + vt + " q = *(const " + vt + "*)(rp + xg);");
                 for (int e = 0; e < V; ++e) line("  " + dst[e] + " = (" + ct + ")q[" + I(e) + "];");
             }
@@ -695,7 +716,11 @@ struct Gen {
             for (int k = 0; k < g.TX; ++k)
                 for (int e = 0; e < V; ++e) {
                     std::string pos = "(x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) + " + " + I(e) + ")";
-                    if (k >= SX) {
+                    if (k >= SX && packed(n.id)) {
+                        std::string r = reg(n.id, slot, ch, k - SX, e);
+                        line(preg(n.id, slot, ch, k - SX, e) + "[" + I(e % 2) + "] = (_Float16)(" + pos + " < 0 ? " +
+                             e0 + " : (" + pos + " >= W ? " + ew + " : " + r + "));");
+                    } else if (k >= SX) {
                         std::string r = reg(n.id, slot, ch, k - SX, e);
                         line(r + " = " + pos + " < 0 ? " + e0 + " : (" + pos + " >= W ? " + ew + " : " + r + ");");
                     } else {
@@ -713,7 +738,13 @@ struct Gen {
     void copy_row(const NodeGeom& n, int from, int to) {
         for (int ch = 0; ch < n.nch; ++ch) {
             for (int kr = 0; kr < RX; ++kr)
-                for (int e = 0; e < V; ++e) line(reg(n.id, to, ch, kr, e) + " = " + reg(n.id, from, ch, kr, e) + ";");
+                for (int e = 0; e < V; ++e) {
+                    if (packed(n.id)) {
+                        if (e % 2 == 0) line(preg(n.id, to, ch, kr, e) + " = " + preg(n.id, from, ch, kr, e) + ";");
+                    } else {
+                        line(reg(n.id, to, ch, kr, e) + " = " + reg(n.id, from, ch, kr, e) + ";");
+                    }
+                }
             for (int k = 0; k < SX; ++k)
                 for (int e = 0; e < V; ++e) {
                     std::string j = I(k * SUB) + " + lane * " + I(V) + " + " + I(e);
@@ -722,22 +753,102 @@ struct Gen {
         }
     }
 
+    // ----------------------------------------------------- folded up2 --
+    // u = up2(down2(P)) computed from P's rows (P is a member whose down2
+    // this group writes decimated).  Row r of u blends the even rows of P
+    // around it: r even -> (P(r-2) + 6 P(r) + P(r+2)) / 8, r odd ->
+    // (P(r-1) + P(r+1)) / 2; the same in x on the blended row.  A tap past
+    // the last even row (column) of P -- 2*ceil(H/2)-2 -- takes the even row
+    // (column) the coarse clamp selects: the centre tap for even points, the
+    // lower tap for odd ones.  Taps before row (column) 0 read P's clamped
+    // rows, which equal row (column) 0, as the coarse clamp at 0 does.
+    void fold_weights(const NodeGeom& n, const std::string& R) {
+        if (kpar >= 0)  // this step's row parity is known here
+            line("const bool fo" + I(n.id) + " = " + ((kpar + n.lead) & 1 ? "true" : "false") + ";");
+        else
+            line("const bool fo" + I(n.id) + " = (" + R + " & 1) != 0;");
+        line("const bool fc" + I(n.id) + " = " + R + " + 2 - (" + R + " & 1) > ((H + 1) >> 1) * 2 - 2;");
+    }
+    std::vector<std::vector<std::string>> fold_vertical(const NodeGeom& n, int ch, int ph) {
+        const int src = P.fold_source(n.id);
+        const int chp = src_chan(G(src), ch, -1);
+        const std::string fo = "fo" + I(n.id), fc = "fc" + I(n.id);
+        // blended at the producer's own slots (its skew relative to u)
+        const int sk = G(src).skew - n.skew;
+        std::vector<std::vector<std::string>> q(g.TX, std::vector<std::string>(V));
+        for (int k = 0; k < g.TX; ++k)
+            for (int e = 0; e < V; ++e) {
+                std::string m2 = read(n.id, src, chp, k, e, sk, -2, ph), m1 = read(n.id, src, chp, k, e, sk, -1, ph),
+                            c0 = read(n.id, src, chp, k, e, sk, 0, ph), p1 = read(n.id, src, chp, k, e, sk, 1, ph),
+                            p2 = read(n.id, src, chp, k, e, sk, 2, ph);
+                q[k][e] = memoize("(" + fo + " ? fmaf(0.5f, " + fc + " ? " + m1 + " : " + p1 + ", 0.5f * " + m1 +
+                                  ") : fmaf(0.125f, " + fc + " ? " + c0 + " : " + p2 + ", fmaf(0.75f, " + c0 +
+                                  ", 0.125f * " + m2 + ")))");
+            }
+        return q;
+    }
+    // Value of the blended row at element e + dx of sub-tile k: own lane,
+    // or a neighbouring lane through a DPP shift (lanes past the tile's edge
+    // belong to the overlap and take any value).
+    std::string fold_read(const std::vector<std::vector<std::string>>& q, int k, int e, int dx) {
+        int qq = e + dx;
+        if (qq >= 0 && qq < V) return q[k][qq];
+        if (qq < 0) {
+            int d = (-qq + V - 1) / V, ep = qq + d * V;
+            const std::string& cur = q[k][ep];
+            const std::string& prv = k > 0 ? q[k - 1][ep] : cur;
+            if (d == 1) return memoize(k > 0 ? "wt_shift1(" + cur + ", " + prv + ")" : "wt_mov_shr1(" + cur + ")");
+            if (d == 2) return memoize("wt_shift2(" + cur + ", " + prv + ")");
+            return memoize("wt_shiftd(" + cur + ", " + prv + ", " + I(d) + ", lane)");
+        }
+        int d = qq / V, ep = qq - d * V;
+        const std::string& cur = q[k][ep];
+        const std::string& nxt = k + 1 < g.TX ? q[k + 1][ep] : cur;
+        if (d == 1) return memoize(k + 1 < g.TX ? "wt_shift1n(" + cur + ", " + nxt + ")" : "wt_mov_shl1(" + cur + ")");
+        if (d == 2) return memoize("wt_shift2n(" + cur + ", " + nxt + ")");
+        return memoize("wt_shiftdn(" + cur + ", " + nxt + ", " + I(d) + ", lane)");
+    }
+    std::string fold_horizontal(const NodeGeom& n, const std::vector<std::vector<std::string>>& q, int k, int e) {
+        std::string x = memoize("(x0 + " + I(n.skew) + " + " + I(k * SUB) + " + lane * " + I(V) + " + " + I(e) + ")");
+        const int sk = G(P.fold_source(n.id)).skew - n.skew;
+        std::string m2 = fold_read(q, k, e, -2 - sk), m1 = fold_read(q, k, e, -1 - sk), c0 = fold_read(q, k, e, -sk),
+                    p1 = fold_read(q, k, e, 1 - sk), p2 = fold_read(q, k, e, 2 - sk);
+        // interior waves: every tap of a valid slot lies inside the image,
+        // so the right-edge clamp never applies there
+        std::string hi = border ? memoize("(" + x + " + 2 - (" + x + " & 1) > ((W + 1) >> 1) * 2 - 2)") : "false";
+        return "((" + x + " & 1) ? fmaf(0.5f, " + hi + " ? " + m1 + " : " + p1 + ", 0.5f * " + m1 +
+               ") : fmaf(0.125f, " + hi + " ? " + c0 + " : " + p2 + ", fmaf(0.75f, " + c0 + ", 0.125f * " + m2 + ")))";
+    }
+
     // ----------------------------------------------------------- member --
     void emit_member(const NodeGeom& n, int ph, bool stores) {
         int slot = pmod(ph, n.win);
+        if (n.even_rows && kpar >= 0 && ((kpar + n.lead) & 1)) {
+            line("// stage " + I(n.id) + ": row kk + " + I(n.lead) + " is odd and never used");
+            return;
+        }
         line("// stage " + I(n.id) + ": row r = kk + " + I(n.lead));
         std::string R = "r" + I(n.id);
         line("const int " + R + " = kk + " + I(n.lead) + ";");
         int oi = -1;
         for (size_t i = 0; i < geo.liveouts.size(); ++i)
             if (geo.liveouts[i] == n.id) oi = (int)i;
+        const bool folded = P.nodes[n.id].kind == Kind::Up2;
+        if (folded) fold_weights(n, R);
         for (int ch = 0; ch < n.nch; ++ch) {
+            std::vector<std::vector<std::string>> qv;
+            if (folded) qv = fold_vertical(n, ch, ph);
             for (int k = 0; k < g.TX; ++k) {
                 std::string arr = fresh("v");
                 line(ctype(n.id) + " " + arr + "[" + I(V) + "];");
-                for (int e = 0; e < V; ++e) line(arr + "[" + I(e) + "] = " + value(n.id, ch, k, e, ph) + ";");
+                for (int e = 0; e < V; ++e)
+                    line(arr + "[" + I(e) + "] = " + (folded ? fold_horizontal(n, qv, k, e) : value(n.id, ch, k, e, ph)) + ";");
                 if (n.consumed) {
-                    if (k >= SX) {
+                    if (k >= SX && packed(n.id)) {
+                        for (int e = 0; e < V; e += 2)
+                            line(preg(n.id, slot, ch, k - SX, e) + " = wt_h2{(_Float16)" + arr + "[" + I(e) +
+                                 "], (_Float16)" + arr + "[" + I(e + 1) + "]};");
+                    } else if (k >= SX) {
                         for (int e = 0; e < V; ++e)
                             line(reg(n.id, slot, ch, k - SX, e) + " = " + (n.half ? "wt_h(" + arr + "[" + I(e) + "])"
                                                                                   : arr + "[" + I(e) + "]") + ";");
@@ -780,8 +891,13 @@ struct Gen {
     // `pro` >= 0 marks prologue step `pro` (only nodes whose rows are already
     // needed are computed; stores only of rows inside the tile); `q` >= 0 is the output-row index of an
     // epilogue step (loads past the tile's last needed row are skipped).
-    void emit_step(int ph, const std::string& kk, int pro, int q) {
+    // Parity of the current step's kk when the generator knows it (tiles
+    // start on even rows and the unrolled period is even), else -1.
+    int kpar = -1;
+
+    void emit_step(int ph, const std::string& kk, int pro, int q, int par = -1) {
         memo.clear();
+        kpar = g.TY % 2 == 0 ? par : -1;
         line("{ const int kk = " + kk + ";");
         ind += "    ";
         int li = 0;
@@ -808,7 +924,9 @@ struct Gen {
         border = b;
         ind += "    ";
         for (auto& n : geo.nodes) {
-            if (has_regs(n))
+            if (packed(n.id))
+                line("wt_h2 w" + I(n.id) + "[" + I(n.win) + "][" + I(n.nch) + "][" + I(RX) + "][" + I(V / 2) + "] = {};");
+            else if (has_regs(n))
                 line(ctype(n.id) + " w" + I(n.id) + "[" + I(n.win) + "][" + I(n.nch) + "][" + I(RX) + "][" + I(V) + "] = {};");
             if (n.ghl > 0)
                 line(ctype(n.id) + " g" + I(n.id) + "l[" + I(n.win) + "][" + I(n.nch) + "][" + I(V) + "] = {};");
@@ -816,18 +934,19 @@ struct Gen {
                 line(ctype(n.id) + " g" + I(n.id) + "r[" + I(n.win) + "][" + I(n.nch) + "][" + I(V) + "] = {};");
         }
         prime_coarse_rings();
-        for (int s = 0; s < geo.D; ++s) emit_step(s % geo.U, "y0 - " + I(geo.D - s), s, -1);
+        for (int s = 0; s < geo.D; ++s) emit_step(s % geo.U, "y0 - " + I(geo.D - s), s, -1, (geo.D - s) & 1);
         if (geo.NMAIN > 0) {
             line("for (int it = 0; it < " + I(geo.NMAIN) + "; ++it) {");
             ind += "    ";
             line("const int kb = y0 + it * " + I(geo.U) + ";");
-            for (int j = 0; j < geo.U; ++j) emit_step((geo.D + j) % geo.U, "kb + " + I(j), -1, -1);
+            for (int j = 0; j < geo.U; ++j)
+                emit_step((geo.D + j) % geo.U, "kb + " + I(j), -1, -1, geo.U % 2 == 0 ? j & 1 : -1);
             ind.resize(ind.size() - 4);
             line("}");
         }
         for (int j = 0; j < geo.E; ++j) {
             int qrow = geo.NMAIN * geo.U + j;
-            emit_step((geo.D + j) % geo.U, "y0 + " + I(qrow), -1, qrow);
+            emit_step((geo.D + j) % geo.U, "y0 + " + I(qrow), -1, qrow, qrow & 1);
         }
         ind.resize(ind.size() - 4);
     }
@@ -994,6 +1113,9 @@ struct BlockGen {
     BlockGen(const Pipeline& p, const GroupSched& gs, const GroupGeom& ge)
         : P(p), g(gs), geo(ge), BX(block_tile_w(gs)), BY(gs.TY), T(64 * gs.WPB) {
         std::set<int> mem(g.nodes.begin(), g.nodes.end());
+        for (int m : g.nodes)
+            if (P.nodes[m].kind == Kind::Up2)
+                fail(WT_E_UNSUPPORTED, "one-tile-per-workgroup groups do not fold up2 stages");
         auto cons = P.consumers();
         for (int lo : geo.outs) reg[lo] = {0, BX, 0, BY, 0};
         std::vector<int> order;

@@ -192,7 +192,10 @@ GroupCost group_cost(const Pipeline& p, const GroupSched& g, const GroupGeom& ge
     for (const NodeGeom& n : geo.nodes) {
         int RX = g.TX - g.SX;
         bool stored = !n.member || n.consumed;
-        if (stored) regs += (double)n.win * n.nch * RX * g.V;
+        // FP16 register rows with an even number of elements per lane pack
+        // two values per VGPR
+        double per = n.half && n.member && g.V % 2 == 0 ? 0.5 : 1.0;
+        if (stored) regs += (double)n.win * n.nch * RX * g.V * per;
         if (!n.member) {
             const Node& nd = p.nodes[n.id];
             int esz = p.nodes[n.id].is_int() ? dtype_size(p.nodes[n.id].dtype) : (n.mem_half ? 2 : 4);
@@ -335,7 +338,14 @@ std::vector<double> group_features(const Pipeline& p, const GroupSched& g, const
         } else if (n.kind == Kind::Down2) {
             ++ndn;
         } else if (n.kind == Kind::Up2) {
-            ++nup;
+            // a folded up2 runs as a separable 5-tap stencil pair on the
+            // stage it folds (half its taps weigh zero at each point)
+            ++nst;
+            taps += 10;
+            hx_max = std::max(hx_max, 2);
+            hy_max = std::max(hy_max, 2);
+            hx_sum += 2;
+            hy_sum += 2;
         }
     }
     f.push_back(g.nodes.size());

@@ -22,6 +22,14 @@ typedef unsigned short wt_us2 __attribute__((ext_vector_type(2)));
 typedef unsigned short wt_us4 __attribute__((ext_vector_type(4)));
 typedef short wt_s2 __attribute__((ext_vector_type(2)));
 typedef short wt_s4 __attribute__((ext_vector_type(4)));
+// The same vectors of 32-bit elements with 4-byte alignment: global loads
+// of rows that start at any element (the caller's images of any width and
+// row stride).  gfx950 executes them as single dwordx2 / dwordx4 loads (the
+// memory system runs in unaligned-access mode under ROCm).
+typedef float wt_f2d __attribute__((ext_vector_type(2), aligned(4)));
+typedef float wt_f4d __attribute__((ext_vector_type(4), aligned(4)));
+typedef int wt_i2d __attribute__((ext_vector_type(2), aligned(4)));
+typedef int wt_i4d __attribute__((ext_vector_type(4), aligned(4)));
 
 // Buffer resource word 3 for raw (untyped, stride 0) buffers on GFX9/CDNA,
 // and an offset past any buffer this library describes (<= 2 GiB): stores

@@ -41,7 +41,9 @@ struct Search {
     std::vector<int> stages;           // stage node ids (non-inputs), ascending
     std::map<int, int> pos;            // node id -> bit
     std::vector<uint64_t> prod, adj;   // per bit: producer bits / undirected neighbours
-    std::vector<bool> fusable;
+    std::vector<bool> fusable;         // may be a member of a multi-stage group
+    std::vector<int> flevel;           // pyramid level of the group it may join
+    uint64_t resample_bits = 0;        // down2 / up2 stages
     std::map<int, StageProfile> prof;
     std::unordered_map<uint64_t, std::pair<double, GroupSched>> gcache;
     std::unordered_map<uint64_t, std::pair<double, uint64_t>> memo;
@@ -58,18 +60,70 @@ struct Search {
         prod.assign(stages.size(), 0);
         adj.assign(stages.size(), 0);
         fusable.assign(stages.size(), false);
+        flevel.assign(stages.size(), 0);
         for (size_t i = 0; i < stages.size(); ++i) {
             const Node& n = p.nodes[stages[i]];
-            fusable[i] = n.kind == Kind::Stencil || n.kind == Kind::Pointwise;
+            flevel[i] = n.level;
+            if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise) {
+                fusable[i] = true;
+            } else if (n.kind == Kind::Down2) {
+                // written decimated by the group of its source
+                resample_bits |= 1ull << i;
+                const Node& src = p.nodes[n.srcs[0]];
+                fusable[i] = src.kind == Kind::Stencil || src.kind == Kind::Pointwise;
+                flevel[i] = src.level;
+            } else {
+                // folded into the group of the stage whose decimation it expands
+                resample_bits |= 1ull << i;
+                fusable[i] = r.fold && p.fold_source(n.id) >= 0;
+            }
             for (int s : n.srcs)
                 if (pos.count(s)) {
                     prod[i] |= 1ull << pos[s];
                     adj[i] |= 1ull << pos[s];
                     adj[pos[s]] |= 1ull << i;
                 }
+        }
+        // stages reading the same pipeline input are neighbours too: fused,
+        // they share one load of it
+        for (int in : p.inputs) {
+            uint64_t readers = 0;
+            for (size_t i = 0; i < stages.size(); ++i)
+                for (int s : p.nodes[stages[i]].srcs)
+                    if (s == in) readers |= 1ull << i;
+            for (size_t i = 0; i < stages.size(); ++i)
+                if (readers >> i & 1) adj[i] |= readers & ~(1ull << i);
+        }
+        for (size_t i = 0; i < stages.size(); ++i) {
             prof[stages[i]] = estimate_stage(p, stages[i], m);
         }
         K = r.max_group > 0 ? r.max_group : 12;
+    }
+
+    // Stages of a group that count towards its size bound (a decimated
+    // store is not a stage of the kernel's body).
+    int group_size(uint64_t g) const {
+        uint64_t down = 0;
+        for (size_t i = 0; i < stages.size(); ++i)
+            if ((g >> i & 1) && p.nodes[stages[i]].kind == Kind::Down2) down |= 1ull << i;
+        return __builtin_popcountll(g & ~down);
+    }
+    // A multi-stage group may hold a down2 only with its source, and an up2
+    // only with the down2 it expands (hence with the stage it folds).
+    bool admissible(uint64_t g) const {
+        if (__builtin_popcountll(g) == 1) return true;
+        bool body = false;
+        for (size_t i = 0; i < stages.size(); ++i) {
+            if (!(g >> i & 1)) continue;
+            if (!fusable[i]) return false;
+            const Node& n = p.nodes[stages[i]];
+            if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise) body = true;
+            if (n.kind == Kind::Down2 || n.kind == Kind::Up2) {
+                auto it = pos.find(n.srcs[0]);
+                if (it == pos.end() || !(g >> it->second & 1)) return false;
+            }
+        }
+        return body;
     }
 
     // Best configuration of one group and its time.
@@ -77,13 +131,20 @@ struct Search {
         auto it = gcache.find(g);
         if (it != gcache.end()) return it->second;
         ++groups_costed;
-        std::vector<int> nodes;
+        std::vector<int> nodes, dec;
         for (size_t i = 0; i < stages.size(); ++i)
-            if (g >> i & 1) nodes.push_back(stages[i]);
+            if (g >> i & 1) (p.nodes[stages[i]].kind == Kind::Down2 && __builtin_popcountll(g) > 1 ? dec : nodes)
+                                .push_back(stages[i]);
         GroupSched base;
         base.nodes = nodes;
+        base.dec = dec;
         base.fp16 = r.fp16;
-        if (nodes.size() == 1 && !fusable[pos[nodes[0]]]) {
+        if (!admissible(g)) {
+            auto res = std::make_pair((double)INFINITY, base);
+            gcache[g] = res;
+            return res;
+        }
+        if (nodes.size() == 1 && (resample_bits >> pos[nodes[0]] & 1)) {
             int src = p.nodes[nodes[0]].srcs[0];
             double t = resample_pred_us(p, nodes[0], m, r.W, r.H,
                                         r.fp16 && p.half_storable(src) && !p.is_output(src),
@@ -94,7 +155,7 @@ struct Search {
         }
         double best_score = INFINITY, best_pred = INFINITY;
         GroupSched best = base;
-        std::vector<ScoredConfig> cfgs = score_configs(p, m, r, nodes);
+        std::vector<ScoredConfig> cfgs = score_configs(p, m, r, nodes, dec);
         if (r.model && !cfgs.empty()) {
             // learned model: predicted time of every configuration; the
             // analytical prediction stands in outside the training range
@@ -132,22 +193,22 @@ struct Search {
     void enumerate(uint64_t S, int seed, std::vector<uint64_t>& out) {
         uint64_t all = stages.size() == 64 ? ~0ull : ((1ull << stages.size()) - 1);
         uint64_t avail = all & ~S;
-        int lvl = p.nodes[stages[seed]].level;
+        int lvl = flevel[seed];
         std::function<void(uint64_t, uint64_t)> grow = [&](uint64_t G, uint64_t ext) {
             // G is connected; record it if ready
             bool ready = true;
             for (size_t i = 0; i < stages.size() && ready; ++i)
                 if ((G >> i & 1) && (prod[i] & ~(S | G))) ready = false;
             if (ready) out.push_back(G);
-            if (__builtin_popcountll(G) >= K) return;
             while (ext) {
                 int v = __builtin_ctzll(ext);
                 ext &= ext - 1;
                 uint64_t ng = G | (1ull << v);
+                if (group_size(ng) > K) continue;  // (a decimated store always fits)
                 uint64_t next = ext;
                 uint64_t nb = adj[v] & avail & ~ng & ~((1ull << seed) - 1) & ~(1ull << seed);
                 for (size_t i = 0; i < stages.size(); ++i)
-                    if ((nb >> i & 1) && (!fusable[i] || p.nodes[stages[i]].level != lvl)) nb &= ~(1ull << i);
+                    if ((nb >> i & 1) && (!fusable[i] || flevel[i] != lvl)) nb &= ~(1ull << i);
                 // neighbours of v not adjacent to G before (ESU extension)
                 uint64_t gadj = 0;
                 for (size_t i = 0; i < stages.size(); ++i)
@@ -156,13 +217,15 @@ struct Search {
                 grow(ng, next);
             }
         };
-        if (!fusable[seed]) {
+        if (!fusable[seed] || (resample_bits >> seed & 1)) {
+            // a resampling stage on its own (a larger group holding it has
+            // a lower stage: the one it decimates or folds)
             if (!(prod[seed] & ~S)) out.push_back(1ull << seed);
             return;
         }
         uint64_t ext = adj[seed] & avail & ~((1ull << seed) - 1) & ~(1ull << seed);
         for (size_t i = 0; i < stages.size(); ++i)
-            if ((ext >> i & 1) && (!fusable[i] || p.nodes[stages[i]].level != lvl)) ext &= ~(1ull << i);
+            if ((ext >> i & 1) && (!fusable[i] || flevel[i] != lvl)) ext &= ~(1ull << i);
         grow(1ull << seed, ext);
     }
 
@@ -249,12 +312,13 @@ const AnalyticFit& active_fit() {
 }
 
 std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,
-                                        const std::vector<int>& nodes) {
+                                        const std::vector<int>& nodes, const std::vector<int>& dec) {
     std::vector<ScoredConfig> out;
     std::map<int, StageProfile> prof;
     for (int n : nodes) prof[n] = estimate_stage(p, n, m);
     GroupSched base;
     base.nodes = nodes;
+    base.dec = dec;
     base.fp16 = r.fp16;
     int vmax = max_vector_width(p, base, r.W, r.H, r.any_width);
     const double* w = r.weights ? r.weights : kGfx950Weights;
@@ -345,12 +409,13 @@ void fusion_costs(const Pipeline& p, const Machine& m, const SchedRequest& r, do
                 // group admissibility as in the DP
                 uint64_t G = gs[pick];
                 int cnt = __builtin_popcountll(G);
-                if (cnt > srch.K) return;
+                if (srch.group_size(G) > srch.K) return;
+                if (!srch.admissible(G)) return;
                 int lvl = -1;
                 for (size_t j = 0; j < n; ++j)
                     if (G >> j & 1) {
                         if (cnt > 1 && !srch.fusable[j]) return;
-                        int l = p.nodes[srch.stages[j]].level;
+                        int l = cnt > 1 ? srch.flevel[j] : p.nodes[srch.stages[j]].level;
                         if (lvl >= 0 && l != lvl) return;
                         lvl = l;
                     }

@@ -50,23 +50,38 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
 
     GroupGeom geo;
     std::set<int> mem(g.nodes.begin(), g.nodes.end());
+    std::set<int> dec(g.dec.begin(), g.dec.end());
     int level = p.nodes[g.nodes[0]].level;
     for (size_t i = 0; i < g.nodes.size(); ++i) {
         const Node& n = p.nodes[g.nodes[i]];
-        if (n.kind != Kind::Stencil && n.kind != Kind::Pointwise)
+        if (n.kind == Kind::Up2) {
+            // a folded up2: the group holds the stage it folds and writes
+            // the down2 between them decimated
+            int f = p.fold_source(n.id);
+            if (f < 0 || !mem.count(f) || !dec.count(n.srcs[0]))
+                fail(WT_E_INVALID, "up2 node " + std::to_string(n.id) +
+                                       " can only be fused with the stage whose decimation it expands");
+        } else if (n.kind != Kind::Stencil && n.kind != Kind::Pointwise) {
             fail(WT_E_INVALID, "node " + std::to_string(n.id) + " cannot be fused");
+        }
         if (n.level != level) fail(WT_E_INVALID, "group spans pyramid levels");
         if (i && g.nodes[i] <= g.nodes[i - 1]) fail(WT_E_INVALID, "group nodes must be sorted");
     }
+    // the group's dependence graph: a folded up2 reads the stage it folds
+    auto gsrcs = [&](int m) -> std::vector<int> {
+        if (p.nodes[m].kind == Kind::Up2) return {p.fold_source(m)};
+        return p.nodes[m].srcs;
+    };
     auto cons = p.consumers();
+    for (int m : g.nodes)
+        if (p.nodes[m].kind == Kind::Up2) cons[p.fold_source(m)].push_back(m);
 
     // loaded nodes and live-outs
     std::set<int> loaded;
     for (int m : g.nodes)
-        for (int s : p.nodes[m].srcs)
+        for (int s : gsrcs(m))
             if (!mem.count(s)) loaded.insert(s);
     geo.loaded.assign(loaded.begin(), loaded.end());
-    std::set<int> dec(g.dec.begin(), g.dec.end());
     for (int d : g.dec) {
         if (d < 0 || d >= (int)p.nodes.size() || p.nodes[d].kind != Kind::Down2)
             fail(WT_E_INVALID, "dec names a node that is not a down2 stage");
@@ -163,6 +178,22 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         if (ng.fix_bot) ng.win = std::max(ng.win, 2);  // keeps row r-1 for the copy
     }
 
+    // members whose rows are used only on even rows: decimated (and not
+    // otherwise stored) or read only by folded up2s
+    for (auto& ng : geo.nodes) {
+        if (!ng.member || ng.liveout) continue;
+        bool uses = false, only_even = true;
+        for (int c : cons[ng.id]) {
+            if (dec.count(c)) {
+                uses = true;
+            } else if (mem.count(c)) {
+                uses = true;
+                if (p.nodes[c].kind != Kind::Up2) only_even = false;
+            }
+        }
+        ng.even_rows = uses && only_even;
+    }
+
     // loads run PF rows ahead of their first use (software prefetch)
     for (auto& ng : geo.nodes)
         if (!ng.member) {
@@ -200,7 +231,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
     for (auto& ng : geo.nodes) {
         if (!ng.member) continue;
         int lo = 0, hi = 0;
-        for (int s : p.nodes[ng.id].srcs) {
+        for (int s : gsrcs(ng.id)) {
             const NodeGeom& pg = geo.nodes[geo.index[s]];
             for (const Tap& t : p.taps(ng.id, s)) {
                 int delta = t.dx - (pg.skew - ng.skew);
@@ -257,6 +288,12 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
             ng.win = w;
         }
     }
+    // a folded up2 weighs its source's rows by their parity: an even period
+    // fixes every step's row parity at compile time (with even TY)
+    bool folds = false;
+    for (int m : g.nodes)
+        if (p.nodes[m].kind == Kind::Up2) folds = true;
+    if (folds && U % 2 && 2 * U <= 24) U *= 2;
     geo.U = U;
     // main loop of whole periods; the epilogue holds the rest and at least
     // the last PF steps, whose loads would fetch rows past the tile

@@ -36,9 +36,25 @@ bool Pipeline::is_output(int n) const {
 
 // Dependence vectors of consumer c on producer p as (dx, dy) offsets: the
 // consumer at (x, y) reads the producer at (x + dx, y + dy).
+int Pipeline::fold_source(int u) const {
+    if (u < 0 || u >= (int)nodes.size() || nodes[u].kind != Kind::Up2) return -1;
+    const Node& d = nodes[nodes[u].srcs[0]];
+    if (d.kind != Kind::Down2) return -1;
+    const Node& s = nodes[d.srcs[0]];
+    if ((s.kind != Kind::Stencil && s.kind != Kind::Pointwise) || s.is_int() || nodes[u].is_int()) return -1;
+    if (s.channels != nodes[u].channels || s.level != nodes[u].level) return -1;
+    return s.id;
+}
+
 std::vector<Tap> Pipeline::taps(int c, int p) const {
     const Node& n = nodes[c];
     std::vector<Tap> t;
+    if (n.kind == Kind::Up2) {
+        if (fold_source(c) != p) return t;
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) t.push_back({dx, dy, 0.0});
+        return t;
+    }
     if (n.kind == Kind::Stencil) {
         if (n.srcs[0] != p) return t;
         for (int j = 0; j < n.kh; ++j)

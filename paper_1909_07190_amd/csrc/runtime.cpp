@@ -158,6 +158,55 @@ void tune_cache_store(const std::string& dir, const std::string& key, const std:
     if (f) f << key << '\t' << text << '\n';
 }
 
+// WT_VERBOSE set (and not "0"): planning reports its measured steps on stderr.
+bool verbose() {
+    static const bool v = [] {
+        const char* e = std::getenv("WT_VERBOSE");
+        return e && *e && std::string(e) != "0";
+    }();
+    return v;
+}
+
+namespace {
+
+// Whether two schedules fuse the same stages the same way (configurations
+// aside).
+bool same_grouping(const Schedule& a, const Schedule& b) {
+    auto key = [](const Schedule& s) {
+        std::vector<std::string> k;
+        for (const GroupSched& g : s.groups) {
+            std::ostringstream os;
+            for (int n : g.nodes) os << n << ',';
+            os << '|';
+            for (int n : g.dec) os << n << ',';
+            os << '|';
+            for (int n : g.exp) os << n << ',';
+            k.push_back(os.str());
+        }
+        std::sort(k.begin(), k.end());
+        return k;
+    };
+    return key(a) == key(b);
+}
+
+// The planning settings of `from` (pipeline, size, device, options).
+void copy_settings(const Plan& from, Plan& to) {
+    to.p = from.p;
+    to.W = from.W;
+    to.H = from.H;
+    to.device = from.device;
+    to.no_device = from.no_device;
+    to.no_compile = from.no_compile;
+    to.fp16 = from.fp16;
+    to.any_width = from.any_width;
+    to.batch_resident = from.batch_resident;
+    to.setup_stream = from.setup_stream;
+    to.cache_dir = from.cache_dir;
+    to.machine = from.machine;
+}
+
+}  // namespace
+
 std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H, void* stream) {
     if (W <= 0 || H <= 0) fail(WT_E_SHAPE, "plan size must be positive");
     if (W > (1 << 24) || H > (1 << 24)) fail(WT_E_SHAPE, "plan size too large");
@@ -187,6 +236,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     req.H = H;
     req.any_width = plan->any_width;
     req.batch = std::max(1, opts.batch_images);
+    req.fold = (opts.flags & WT_PLAN_NO_FOLD) == 0;
     if (opts.fixed_schedule) req.fixed = opts.fixed_schedule;
     if (opts.model_path) req.model_path = opts.model_path;
     const bool tune = opts.mode == WT_SCHED_AUTOTUNE && !plan->no_device;
@@ -208,8 +258,26 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     plan->sched = make_schedule(p, plan->machine, req);
     build_groups(*plan);
     if (tune) {
-        autotune_plan(*plan, opts.autotune_topk > 0 ? opts.autotune_topk : 6, opts.model_path ? opts.model_path : "",
-                      req.batch);
+        const int topk = opts.autotune_topk > 0 ? opts.autotune_topk : 6;
+        const std::string model = opts.model_path ? opts.model_path : "";
+        double t = autotune_plan(*plan, topk, model, req.batch);
+        // The search's grouping with up2 stages only expanded (never folded
+        // into the group of the stage they resample), when it differs, is
+        // measured too: the faster of the two tuned plans is kept.
+        SchedRequest alt_req = req;
+        alt_req.fold = false;
+        Schedule alt_sched = req.fold ? make_schedule(p, plan->machine, alt_req) : plan->sched;
+        if (!same_grouping(plan->sched, alt_sched)) {
+            auto alt = std::make_unique<Plan>();
+            copy_settings(*plan, *alt);
+            alt->sched = alt_sched;
+            build_groups(*alt);
+            double t_alt = autotune_plan(*alt, topk, model, req.batch);
+            if (verbose())
+                std::fprintf(stderr, "wavetile autotune: %.1f us per image with folded up2s, %.1f us without\n", t,
+                             t_alt);
+            if (t_alt < t) plan = std::move(alt);
+        }
         tune_cache_store(plan->cache_dir, key, schedule_text(plan->sched));
     }
     return plan;
@@ -405,8 +473,13 @@ void check_store_planes(const Plan& plan, const GroupRt& gr, const WtArgsHost& a
 
 namespace {
 
+// Caller images: 32-bit elements need only their own alignment (vector
+// accesses of them are 4-byte aligned); narrower integer elements are
+// accessed in aligned vectors of V elements.
 void check_align(const ImgRef& r, int V, int esize, const std::string& tag) {
-    if (V == 1) return;
+    if (reinterpret_cast<uintptr_t>(r.ptr) % esize)
+        fail(WT_E_SHAPE, tag + ": buffer not aligned to its element size");
+    if (V == 1 || esize >= 4) return;
     if ((reinterpret_cast<uintptr_t>(r.ptr) % (esize * V)) || (r.rs % V) || (r.cs % V))
         fail(WT_E_SHAPE, tag + ": buffer or strides not aligned to " + std::to_string(V) +
                              " elements as the plan's vector width requires");

@@ -27,15 +27,19 @@ Schedule schedule_unfused(const Pipeline& p, bool fp16) {
 
 Schedule schedule_analytic(const Pipeline& p, const Machine& m, const SchedRequest& r);
 
-// Largest vector width a group may use: groups that read pipeline inputs or
-// write pipeline outputs address the caller's dense rows, so V must divide
-// that level's width (intermediate buffers are padded by the library).
+// Largest vector width a group may use.  Loads and stores of 32-bit
+// elements need only 4-byte alignment, so rows of any width and stride take
+// any V; groups that read or write the caller's images of narrower integer
+// elements address its dense rows in vectors of V elements aligned to V, so
+// V must divide that level's width (intermediate buffers are padded by the
+// library).
 int max_vector_width(const Pipeline& p, const GroupSched& g, int W, int H, bool any_width) {
     bool user = false;
+    auto narrow = [&](int id) { return p.nodes[id].is_int() && dtype_size(p.nodes[id].dtype) < 4; };
     for (int n : g.nodes) {
-        if (p.is_output(n)) user = true;
+        if (p.is_output(n) && narrow(n)) user = true;
         for (int s : p.nodes[n].srcs)
-            if (p.nodes[s].kind == Kind::Input) user = true;
+            if (p.nodes[s].kind == Kind::Input && narrow(s)) user = true;
     }
     if (!user) return 4;
     if (any_width) return 1;

@@ -68,9 +68,10 @@ struct ScoredConfig {
     int tx_size = 128;
     std::shared_ptr<const GroupGeom> geo;  // geometry of (V, TX, SX, PF)
 };
-// Every feasible configuration of the group `nodes` over the search grid.
+// Every feasible configuration of the group `nodes` (writing the down2
+// stages `dec` decimated) over the search grid.
 std::vector<ScoredConfig> score_configs(const Pipeline& p, const Machine& m, const SchedRequest& r,
-                                        const std::vector<int>& nodes);
+                                        const std::vector<int>& nodes, const std::vector<int>& dec = {});
 // Algorithm 2's weights as the paper's Table 3 gives them for the V100 (the
 // score keeps the paper's form; it is also one of the learned model's
 // features).

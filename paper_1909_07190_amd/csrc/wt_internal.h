@@ -83,8 +83,17 @@ struct Pipeline {
     // consumers[n] = node ids reading n
     std::vector<std::vector<int>> consumers() const;
     // Constant-offset taps of consumer c on producer p (empty if c does not
-    // read p, or reads it through a resampling dependence).
+    // read p, or reads it through a resampling dependence).  A foldable up2
+    // (below) has the 5x5 footprint {-2..2}^2 on the stage it folds (weight
+    // 0 in the list: its weights depend on the parity of the point).
     std::vector<Tap> taps(int c, int p) const;
+    // The stage P an up2 node u folds, or -1.  u = up2(down2(P)) with P a
+    // float stencil or pointwise stage is, at P's level, a constant-offset
+    // dependence on P (the paper's alignment and scaling, Section 5): the
+    // 2x expansion of P's even samples reads P at offsets -2..2 in x and y,
+    // with weights set by the parity of the point.  A fused group that holds
+    // P and writes the down2 decimated may then compute u from P's rows.
+    int fold_source(int u) const;
     bool is_output(int n) const;
     // FP16 storage (the plan's FP16-intermediate option) is allowed for
     // float stages whose magnitude bound fits FP16's finite range; every
@@ -151,6 +160,8 @@ struct NodeGeom {
     int vhi;            // invalid slots at the right end of a row
     int first_step;     // first step (0 = tile start) at which its row is needed
     bool consumed;      // read by another member of the group
+    bool even_rows = false;  // only its even rows are used (by decimated
+                             // stores and folded up2s): odd rows may be skipped
     int lds_off;        // byte offset of its LDS ring within the wave's LDS
     bool half;          // in-group storage is FP16
     bool mem_half;      // its memory buffer holds FP16 (set by the runtime)
@@ -242,6 +253,7 @@ struct SchedRequest {
     int max_group = 12;               // bound on stages per fused group
     bool any_width = false;           // caller images of any width / stride
     int batch = 1;                    // images per batched run (analytical cost only)
+    bool fold = true;                 // the search may fold up2 stages into groups
     const double* weights = nullptr;  // Algorithm 2 weights (default: refitted table)
     Mlp* model = nullptr;             // learned cost model (WT_SCHED_MLP)
 };

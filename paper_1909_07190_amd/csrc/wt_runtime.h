@@ -157,7 +157,9 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
 // fastest; candidates ranked by the learned model when `model_path` is set.
 // With `batch` > 1 the candidates are timed on an image as tall as up to
 // `batch` images of the plan's size, the wave count of a batched launch.
-void autotune_plan(Plan& plan, int topk, const std::string& model_path = "", int batch = 1);
+// Returns the measured time of the chosen plan per image (the sum over its
+// groups, in microseconds).
+double autotune_plan(Plan& plan, int topk, const std::string& model_path = "", int batch = 1);
 // Autotune schedule cache (see wt.h): key of a plan, lookup and store.
 std::string schedule_text(const Schedule& s);
 std::string tune_key(const Plan& plan, const wt_sched_opts& opts);
@@ -172,6 +174,8 @@ StageProfile stage_profile(const Pipeline& p, int id, int W, int H, bool measure
 void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vector<std::string>& descs, int reps,
                     const std::string& tag, double* out_us);
 std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int W, int H, void* stream);
+// WT_VERBOSE is set: planning steps that measure report progress on stderr.
+bool verbose();
 void build_groups(Plan& plan);
 void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int nout, void* stream);
 std::string describe_plan(const Plan& plan);

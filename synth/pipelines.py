@@ -133,6 +133,19 @@ def pyramid_blend(levels: int = 4) -> dict:
             "stages": st, "outputs": ["R0"]}
 
 
+def laplacian_band(channels: int = 1) -> dict:
+    """One level of a Laplacian pyramid: the Gaussian level below
+    (G1 = down2(blur_y(blur_x(img)))) and the band img - up2(G1), plus a
+    blur of G1 so the coarse level has a consumer of its own."""
+    return {"inputs": [{"name": "img", "channels": channels}],
+            "stages": [blur_x("bx", "img"), blur_y("by", "bx"),
+                       {"name": "G1", "kind": "down2", "src": "by"},
+                       {"name": "U", "kind": "up2", "src": "G1"},
+                       _pw("L", ["img", "U"], "s0 - s1", channels),
+                       blur_x("c1", "G1")],
+            "outputs": ["L", "c1"]}
+
+
 def _istencil(name, src, kw, kh, ax, ay, weights, divisor, dtype):
     return {"name": name, "kind": "stencil", "src": src, "kw": kw, "kh": kh,
             "ax": ax, "ay": ay, "weights": [int(w) for w in weights],

@@ -190,7 +190,10 @@ def _check_caller_alignment(plan, g, gi, caller, width):
     toks = plan.describe().splitlines()[g].split()
     v = int(next(t for t in toks if t.startswith("V=")).split("=")[1])
     nodes = list(gi.loaded[:gi.nloaded]) + list(gi.liveouts[:gi.nliveouts])
-    if v > 1 and width % v and any(n in caller for n in nodes):
+    narrow = {2, 3, 4}  # u8, u16, i16 element codes
+    dts = {gi.loaded[i]: gi.loaded_dtype[i] for i in range(gi.nloaded)}
+    dts.update({gi.liveouts[i]: gi.liveout_dtype[i] for i in range(gi.nliveouts)})
+    if v > 1 and width % v and any(n in caller and dts.get(n) in narrow for n in nodes):
         raise ValueError(f"group {g}: image rows of width {width} not aligned to V={v}")
 
 

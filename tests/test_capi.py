@@ -32,7 +32,8 @@ def test_binding_constants_match_header():
     follow include/wt.h."""
     text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "wt.h")).read(), flags=re.S)
     flags = {k: int(v) for k, v in re.findall(r"\bWT_PLAN_([A-Z_]+)\s*=\s*(\d+)", text)}
-    assert flags == {"NO_DEVICE": 1, "ANY_WIDTH": 2, "NO_COMPILE": 4, "RETUNE": 8, "BATCH_RESIDENT": 16}
+    assert flags == {"NO_DEVICE": 1, "ANY_WIDTH": 2, "NO_COMPILE": 4, "RETUNE": 8, "BATCH_RESIDENT": 16,
+                     "NO_FOLD": 32}
     for k, v in flags.items():
         assert getattr(wt, "PLAN_" + k) == v, k
     body = re.search(r"typedef struct \{([^}]*)\} wt_sched_opts;", text).group(1)

@@ -96,9 +96,10 @@ def fusion_costs(spec, w, h, k=12):
     return dp.value, ex.value
 
 
-@pytest.mark.parametrize("name", ["blur", "unsharp", "harris", "dag3", "dag11", "dag21"])
+@pytest.mark.parametrize("name", ["blur", "unsharp", "harris", "lapband", "dag3", "dag11", "dag21"])
 def test_fusion_dp_equals_exhaustive(name):
-    spec = {"blur": P.gaussian_blur, "unsharp": P.unsharp_mask, "harris": P.harris}.get(name)
+    spec = {"blur": P.gaussian_blur, "unsharp": P.unsharp_mask, "harris": P.harris,
+            "lapband": P.laplacian_band}.get(name)
     spec = spec() if spec else dags.random_dag(int(name[3:]), lo=6, hi=10)
     dp, ex = fusion_costs(spec, 512, 384)
     assert len(spec["stages"]) <= 10
@@ -152,7 +153,7 @@ def test_batch_hint_prefers_taller_tiles():
     def ty(batch):
         d = wt.from_spec(spec).plan(mw, mh, mode="analytic", any_width=True, no_device=True, no_compile=True,
                                     batch_images=batch).describe()
-        line = next(l for l in d.splitlines() if " nodes=3,4 " in l)
+        line = next(l for l in d.splitlines() if " nodes=3,4 " in l or " nodes=3,4," in l)
         return int(re.search(r"TY=(\d+)", line).group(1))
 
     assert ty(64) > ty(1)

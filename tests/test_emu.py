@@ -394,3 +394,121 @@ def test_fp16_harris_on_0_255_inputs_stays_finite():
     got, _ = emulate(spec, {"img": img}, mode="fixed", fp16=True,
                      fixed="nodes=1,2,3,4,5,6,7,8,9,10 V=4 TX=1 SX=0 TY=8 PF=1 fp16=1")
     assert_normwise(got["R"], oracle.evaluate(spec, {"img": img})["R"], 2e-3, "harris 0..255 fp16")
+
+
+# ------------------------------------- folded up2: groups across two levels
+# Laplacian band: node 1 bx, 2 by, 3 G1 = down2(by), 4 U = up2(G1),
+# 5 L = img - U, 6 c1 = blur_x(G1).  With G1 written decimated by the group
+# of by, U is computed from by's rows in the same kernel (the 2x expansion of
+# by's even samples), so the band needs no pass over the coarse level.
+LAPBAND = P.laplacian_band()
+FOLD_CASES = [
+    ("nodes=1,2,4,5 V=1 TX=2 SX=0 TY=8 PF=1 dec=3;nodes=6 V=1", 130, 40),
+    ("nodes=1,2,4,5 V=1 TX=1 SX=0 TY=5 PF=2 dec=3;nodes=6 V=1", 67, 9),
+    ("nodes=1,2,4,5 V=1 TX=1 SX=0 TY=16 PF=2 dec=3;nodes=6 V=1", 400, 30),
+    ("nodes=1,2,4,5 V=2 TX=2 SX=1 TY=8 PF=1 dec=3;nodes=6 V=2", 262, 34),
+    ("nodes=1,2,4,5 V=4 TX=1 SX=0 TY=16 PF=2 dec=3;nodes=6 V=4", 516, 40),
+    ("nodes=1,2,4,5 V=1 TX=2 SX=0 TY=8 PF=1 align=1 dec=3;nodes=6 V=1", 131, 21),
+    ("nodes=1,2,4,5 V=2 TX=3 SX=3 TY=4 PF=0 dec=3;nodes=6 V=2", 90, 11),
+    # the folded up2 as a live-out of its group, read by a later group
+    ("nodes=1,2,4 V=1 TX=1 SX=0 TY=8 dec=3;nodes=5 V=1;nodes=6 V=1", 33, 21),
+]
+
+
+@pytest.mark.parametrize("fixed,w,h", FOLD_CASES)
+def test_folded_up2_emulated_exact(fixed, w, h):
+    """Dyadic inputs keep every intermediate exact (2^-18 grid), so any
+    indexing, parity or edge-clamp error shows as a bit mismatch; odd and
+    even sizes cover both right/bottom coarse clamps."""
+    img = synth.dyadic_image(9, 1, h, w)
+    got, _ = emulate(LAPBAND, {"img": img}, mode="fixed", fixed=fixed)
+    ref = oracle.evaluate(LAPBAND, {"img": img})
+    for k in ref:
+        assert_exact(got[k], ref[k], f"{k}: {fixed}")
+
+
+def test_folded_up2_fp16_emulated():
+    fixed = "nodes=1,2,4,5 V=2 TX=2 SX=0 TY=8 PF=2 fp16=1 dec=3;nodes=6 V=2 fp16=1"
+    img = synth.uniform_image(10, 1, 37, 262)
+    got, _ = emulate(LAPBAND, {"img": img}, mode="fixed", fixed=fixed, fp16=True)
+    ref = oracle.evaluate(LAPBAND, {"img": img})
+    for k in ref:
+        assert_normwise(got[k], ref[k], 2e-3, f"{k}: {fixed}")
+
+
+def test_fusion_search_folds_the_band():
+    """The analytical search puts the expansion of by's decimation, and the
+    band that reads it, into the group of by."""
+    img = synth.dyadic_image(11, 1, 29, 97)
+    got, plan = emulate(LAPBAND, {"img": img}, mode="analytic", any_width=True)
+    first = plan.describe().splitlines()[0]
+    assert "nodes=1,2,4,5 " in first and "dec=3" in first, plan.describe()
+    ref = oracle.evaluate(LAPBAND, {"img": img})
+    for k in ref:
+        assert_exact(got[k], ref[k], plan.describe())
+
+
+def _pyramid_fold_schedule(spec, levels, cfg, m_apart):
+    """Every level's analysis in one group: blurs of A, B (and M), the
+    decimated next level, the folded expansions, the bands and their blend;
+    then the coarsest blend and the collapse, expanding each coarser result."""
+    import paper_1909_07190_amd as wt
+    ids = wt.from_spec(spec).names
+
+    def grp(nodes, dec=(), exp=(), c=cfg):
+        s = "nodes=" + ",".join(str(ids[n]) for n in sorted(nodes, key=lambda n: ids[n])) + " " + c
+        if dec:
+            s += " dec=" + ",".join(str(ids[n]) for n in dec)
+        if exp:
+            s += " exp=" + ",".join(str(ids[n]) for n in exp)
+        return s
+
+    top = levels - 1
+    groups = []
+    for l in range(top):
+        body = [f"Abx{l}", f"Aby{l}", f"AU{l}", f"AL{l}", f"Bbx{l}", f"Bby{l}", f"BU{l}", f"BL{l}", f"Lb{l}"]
+        dec = [f"AG{l + 1}", f"BG{l + 1}"]
+        if m_apart:
+            groups.append(grp([f"Mbx{l}", f"Mby{l}"], dec=[f"MG{l + 1}"]))
+        else:
+            body += [f"Mbx{l}", f"Mby{l}"]
+            dec.append(f"MG{l + 1}")
+        groups.append(grp(body, dec=dec))
+    groups.append(grp([f"Lb{top}"]))
+    for l in range(top - 1, -1, -1):
+        groups.append(grp([f"R{l}"], exp=[f"RU{l}"]))
+    return "\n".join(groups)
+
+
+@pytest.mark.parametrize("cfg,m_apart", [("V=1 TX=1 SX=0 TY=8 PF=2", False), ("V=1 TX=2 SX=1 TY=5 PF=1", True)])
+def test_pyramid_folded_levels_emulated(cfg, m_apart):
+    """The blend with each level's bands computed in the pass that
+    decimates it: exact on a two-level pyramid with dyadic inputs and a 0/1
+    mask, and within 1e-5 on the four-level pyramid."""
+    spec2 = P.pyramid_blend(2)
+    h, w = 21, 33
+    a, b = synth.dyadic_image(31, 1, h, w), synth.dyadic_image(32, 1, h, w)
+    for m in (np.ones((1, h, w), np.float32), np.zeros((1, h, w), np.float32)):
+        ins = {"A": a, "B": b, "M": m}
+        got, _ = emulate(spec2, ins, mode="fixed", fixed=_pyramid_fold_schedule(spec2, 2, cfg, m_apart),
+                         any_width=True)
+        assert_exact(got["R0"], oracle.evaluate(spec2, ins)["R0"], cfg)
+    spec4 = P.pyramid_blend(4)
+    h, w = 37, 70
+    ins = {"A": synth.uniform_image(21, 1, h, w), "B": synth.uniform_image(22, 1, h, w), "M": synth.ramp_mask(h, w)}
+    got, _ = emulate(spec4, ins, mode="fixed", fixed=_pyramid_fold_schedule(spec4, 4, cfg, m_apart), any_width=True)
+    assert_normwise(got["R0"], oracle.evaluate(spec4, ins)["R0"], 1e-5, cfg)
+
+
+def test_pyramid_folded_batch_emulated():
+    """Batched kernels of the folded schedule over images of different
+    sizes, with a grid smaller than the work."""
+    from emu_runner import emulate_batch
+    spec = P.pyramid_blend(3)
+    sizes = [(45, 37), (30, 21), (66, 40)]
+    images = [{"A": synth.uniform_image(70 + i, 1, h, w), "B": synth.uniform_image(80 + i, 1, h, w),
+               "M": synth.ramp_mask(h, w)} for i, (w, h) in enumerate(sizes)]
+    fixed = _pyramid_fold_schedule(spec, 3, "V=1 TX=1 SX=0 TY=8 PF=2", False)
+    outs = emulate_batch(spec, images, nblocks=2, mode="fixed", fixed=fixed, any_width=True)
+    for inp, got in zip(images, outs):
+        assert_normwise(got["R0"], oracle.evaluate(spec, inp)["R0"], 1e-5, "batched folded pyramid")
