@@ -249,6 +249,31 @@ wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
 wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in,
                             const wt_image* out, void* hip_stream);
 
+/* Bytes of device memory in the library's fixed workspace: one copy on each
+ * GPU that wt_plan_run_batch_static runs on, held until the process ends. */
+#define WT_STATIC_SCRATCH_BYTES (256u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * batch of wt_plan_run_batch, same arguments, same kernels and launch
+ * grids and bit-identical outputs, with every intermediate and the
+ * per-image argument table in the library's fixed workspace
+ * (WT_STATIC_SCRATCH_BYTES) instead of plan-owned device memory.  Calls no
+ * device allocator and captures no graph: every group is launched directly
+ * on `hip_stream`, after an asynchronous copy of the argument table from
+ * host memory the plan owns (reused by the plan's next call).  Every call
+ * on one GPU, from any plan, shares that GPU's workspace: calls that
+ * overlap on one GPU (different streams, or threads) race, while calls in
+ * order on one stream are safe (nothing in the workspace needs to start
+ * at zero: each group writes the intermediates it produces before any
+ * later group reads them).  Needs the plan's batched kernels loaded
+ * (planned with batch_images > 1, or after a wt_plan_run_batch) and the
+ * plan's device current (WT_E_INVALID otherwise); WT_E_NOMEM, before any
+ * launch, when the batch's intermediates and table exceed the workspace;
+ * the image checks of wt_plan_run_batch apply. */
+wt_status wt_plan_run_batch_static(wt_plan* plan, int nimg, const wt_image* in,
+                                   const wt_image* out, void* hip_stream);
+
 /* Runs only groups first .. first+count-1 of the batched plan over the same
  * arguments as wt_plan_run_batch, with the same kernels and launch grids,
  * launched directly on `hip_stream` (not from the graph), in group order.

@@ -94,6 +94,8 @@ _sig("wt_plan_run", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtImage), ctyp
      ctypes.POINTER(WtImage), ctypes.c_int, ctypes.c_void_p)
 _sig("wt_plan_run_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
+_sig("wt_plan_run_batch_static", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
+     ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_run_batch_groups", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
      ctypes.POINTER(WtImage), ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_stream_copy", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -314,6 +316,20 @@ class Plan:
             stream = torch.cuda.current_stream()
         s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         _check(lib.wt_plan_run_batch(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
+
+    def run_batch_static(self, inputs, outputs, stream=None):
+        """run_batch with the intermediates in the library's fixed device
+        workspace: allocates no device memory (the plan's batched kernels
+        must be loaded: plan with batch_images > 1)."""
+        import torch
+        ins = [_image(t) for img in inputs for t in img]
+        outs = [_image(t) for img in outputs for t in img]
+        a_in = (WtImage * len(ins))(*ins)
+        a_out = (WtImage * len(outs))(*outs)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(lib.wt_plan_run_batch_static(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
 
     def run_batch_groups(self, first, count, inputs, outputs, stream=None):
         """Launches groups first .. first+count-1 of a batched run directly

@@ -21,8 +21,8 @@ namespace wt {
 BatchState::~BatchState() {
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
-    if (arena) hipFree(arena);
-    if (dargs) hipFree(dargs);
+    if (owned && arena) hipFree(arena);
+    if (owned && dargs) hipFree(dargs);
 }
 
 // Workgroups of `fn` resident on one CU: the runtime's occupancy answer, or
@@ -104,24 +104,18 @@ void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, i
 
 }  // namespace
 
-void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream, int first,
-                    int count) {
-    if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
+namespace {
+
+// The caller's images of a batch, validated as single runs validate theirs:
+// per image its size and the memory of its inputs and outputs.
+void check_batch(const Plan& plan, int nimg, const wt_image* in, const wt_image* out,
+                 std::vector<std::pair<int, int>>& sizes, std::vector<std::map<int, ImgRef>>& mem) {
     const Pipeline& p = plan.p;
     const int nin = (int)p.inputs.size(), nout = (int)p.outputs.size();
     if (nimg < 1) fail(WT_E_INVALID, "batch needs at least one image");
     if (!in || !out) fail(WT_E_INVALID, "null image array");
-    const int G = (int)plan.groups.size();
-    const bool all = count < 0;
-    if (all) {
-        first = 0;
-        count = G;
-    }
-    if (first < 0 || count < 1 || first > G - count) fail(WT_E_INVALID, "group range outside the plan");
-
-    // sizes and per-image memory of the caller's images
-    std::vector<std::pair<int, int>> sizes(nimg);
-    std::vector<std::map<int, ImgRef>> mem(nimg);
+    sizes.assign(nimg, {0, 0});
+    mem.assign(nimg, {});
     for (int i = 0; i < nimg; ++i) {
         const wt_image& first = in[(size_t)i * nin];
         int W = first.width, H = first.height;
@@ -141,80 +135,150 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
         }
     }
     // no output may alias any other image of the batch
-    {
-        std::map<const void*, int> seen;  // data pointer -> times named
-        for (int i = 0; i < nimg * nin; ++i) ++seen[in[i].data];
-        for (int i = 0; i < nimg * nout; ++i) ++seen[out[i].data];
-        for (int i = 0; i < nimg * nout; ++i)
-            if (seen[out[i].data] > 1)
-                fail(WT_E_INVALID, "batch image " + std::to_string(i / std::max(nout, 1)) + " output " +
-                                       std::to_string(i % std::max(nout, 1)) + " aliases another image");
+    std::map<const void*, int> seen;  // data pointer -> times named
+    for (int i = 0; i < nimg * nin; ++i) ++seen[in[i].data];
+    for (int i = 0; i < nimg * nout; ++i) ++seen[out[i].data];
+    for (int i = 0; i < nimg * nout; ++i)
+        if (seen[out[i].data] > 1)
+            fail(WT_E_INVALID, "batch image " + std::to_string(i / std::max(nout, 1)) + " output " +
+                                   std::to_string(i % std::max(nout, 1)) + " aliases another image");
+}
+
+// Everything of a batch shape that needs no device memory: every image's
+// intermediates at 256-byte aligned offsets from the arena's start, the
+// per-group work and launch grids, and the argument table's size.  The
+// batched kernels must be loaded.
+std::unique_ptr<BatchState> layout_batch(const Plan& plan, const std::vector<std::pair<int, int>>& sizes) {
+    const Pipeline& p = plan.p;
+    const int nimg = (int)sizes.size(), G = (int)plan.groups.size();
+    auto st = std::make_unique<BatchState>();
+    st->sizes = sizes;
+    st->offs.assign(nimg, {});
+    size_t off = 0;
+    for (int i = 0; i < nimg; ++i)
+        for (auto& gr : plan.groups)
+            for (size_t k = 0; k < gr.liveouts.size(); ++k) {
+                int id = gr.liveouts[k];
+                if (p.is_output(id) || st->offs[i].count(id)) continue;
+                auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[id].level);
+                Buf b;
+                b.half = gr.mem_half_out[k];
+                b.rs = (d.first + 63) / 64 * 64;
+                b.cs = b.rs * d.second;
+                b.ptr = reinterpret_cast<void*>(off);  // an offset until the arena is placed
+                off += ((size_t)b.cs * p.nodes[id].channels * node_esize(p, id, b.half) + 255) / 256 * 256;
+                st->offs[i][id] = b;
+            }
+    st->arena_bytes = off;
+    st->total.resize(G);
+    st->grid.resize(G);
+    st->per_cu.resize(G);
+    st->tiles.assign((size_t)G * nimg, {0, 0, 0});
+    for (int g = 0; g < G; ++g) {
+        int tot = 0;
+        for (int i = 0; i < nimg; ++i) {
+            auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[plan.groups[g].g.nodes[0]].level);
+            int tx, ty, w;
+            tile_counts(plan, plan.groups[g], d.first, d.second, tx, ty, w);
+            st->tiles[(size_t)g * nimg + i] = {tx, ty, w};
+            tot += w;
+        }
+        st->total[g] = tot;
+        const GroupRt& gr = plan.groups[g];
+        int threads = gr.resample ? 256 : 64 * gr.g.WPB;
+        int per_cu = resident_blocks_per_cu(plan, gr.fn_batch, threads);
+        st->per_cu[g] = per_cu;
+        int units = (gr.resample || gr.g.BLK) ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
+        // the per-unit grid is capped at 2^22 workgroups (far above the
+        // resident set; the waves' stride loop covers any remainder)
+        st->grid[g] = batch_grid_resident(plan) ? std::max(1, std::min(units, per_cu * plan.machine.ncu))
+                                                : std::max(1, std::min(units, 1 << 22));
     }
+    // argument table: [g][img] WtArgs, then [g][nimg + 1] work prefix sums
+    st->args_bytes = (size_t)G * nimg * sizeof(WtArgsHost);
+    st->dargs_bytes = st->args_bytes + (size_t)G * (nimg + 1) * sizeof(int);
+    st->host.resize(st->dargs_bytes);
+    return st;
+}
+
+// Places the intermediates in `arena` and the argument table at `dargs`.
+void place_batch(BatchState& st, void* arena, void* dargs) {
+    st.arena = arena;
+    st.dargs = dargs;
+    st.bufs = st.offs;
+    for (auto& m : st.bufs)
+        for (auto& kv : m) kv.second.ptr = static_cast<char*>(arena) + reinterpret_cast<size_t>(kv.second.ptr);
+}
+
+// The argument table of this run on the host (st.host).
+void fill_table(const Plan& plan, BatchState& st, std::vector<std::map<int, ImgRef>>& mem) {
+    const Pipeline& p = plan.p;
+    const int nimg = (int)st.sizes.size(), G = (int)plan.groups.size();
+    for (int i = 0; i < nimg; ++i)
+        for (auto& kv : st.bufs[i]) mem[i][kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
+    std::memset(st.host.data(), 0, st.host.size());
+    for (int g = 0; g < G; ++g) {
+        const GroupRt& gr = plan.groups[g];
+        int* starts = reinterpret_cast<int*>(st.host.data() + st.args_bytes) + (size_t)g * (nimg + 1);
+        int acc = 0;
+        for (int i = 0; i < nimg; ++i) {
+            WtArgsHost& a = reinterpret_cast<WtArgsHost*>(st.host.data())[(size_t)g * nimg + i];
+            auto d = level_dims(st.sizes[i].first, st.sizes[i].second, p.nodes[gr.g.nodes[0]].level);
+            fill_args(plan, gr, mem[i], a, "batch image " + std::to_string(i));
+            check_store_planes(plan, gr, a, d.second);
+            a.W = d.first;
+            a.H = d.second;
+            if (gr.resample) {
+                auto sd = level_dims(st.sizes[i].first, st.sizes[i].second,
+                                     p.nodes[p.nodes[gr.g.nodes[0]].srcs[0]].level);
+                a.Ws = sd.first;
+                a.Hs = sd.second;
+            }
+            const auto& t = st.tiles[(size_t)g * nimg + i];
+            a.tiles_x = t[0];
+            a.tiles_y = t[1];
+            a.nwaves = t[2];
+            starts[i] = acc;
+            acc += t[2];
+        }
+        starts[nimg] = acc;
+    }
+}
+
+}  // namespace
+
+void load_batch_kernels(const Plan& plan_c, std::vector<GroupRt>& groups) {
+    std::vector<GroupRt*> need;
+    for (auto& gr : groups)
+        if (!gr.fn_batch) need.push_back(&gr);
+    if (!need.empty()) compile_groups(plan_c, need, true);
+}
+
+void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream, int first,
+                    int count) {
+    if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
+    const int G = (int)plan.groups.size();
+    const bool all = count < 0;
+    if (all) {
+        first = 0;
+        count = G;
+    }
+    if (first < 0 || count < 1 || first > G - count) fail(WT_E_INVALID, "group range outside the plan");
+    std::vector<std::pair<int, int>> sizes;
+    std::vector<std::map<int, ImgRef>> mem;
+    check_batch(plan, nimg, in, out, sizes, mem);
 
     if (!plan.batch || plan.batch->sizes != sizes) {
         plan.batch.reset();
-        {  // the batched kernels, compiled on first use
-            std::vector<GroupRt*> need;
-            for (auto& gr : plan.groups)
-                if (!gr.fn_batch) need.push_back(&gr);
-            if (!need.empty()) compile_groups(plan, need, true);
-        }
-        auto st = std::make_unique<BatchState>();
-        st->sizes = sizes;
-        // arena for every image's intermediates
-        std::vector<std::map<int, Buf>> bufs(nimg);
-        size_t off = 0;
-        for (int i = 0; i < nimg; ++i)
-            for (auto& gr : plan.groups)
-                for (size_t k = 0; k < gr.liveouts.size(); ++k) {
-                    int id = gr.liveouts[k];
-                    if (p.is_output(id) || bufs[i].count(id)) continue;
-                    auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[id].level);
-                    Buf b;
-                    b.half = gr.mem_half_out[k];
-                    b.rs = (d.first + 63) / 64 * 64;
-                    b.cs = b.rs * d.second;
-                    b.ptr = reinterpret_cast<void*>(off);  // offset until the arena exists
-                    off += ((size_t)b.cs * p.nodes[id].channels * node_esize(p, id, b.half) + 255) / 256 * 256;
-                    bufs[i][id] = b;
-                }
-        if (off) {
-            if (hipMalloc(&st->arena, off) != hipSuccess) fail(WT_E_NOMEM, "batch intermediates");
-            st->arena_bytes = off;
-        }
-        st->bufs = bufs;
-        for (auto& m : st->bufs)
-            for (auto& kv : m) kv.second.ptr = static_cast<char*>(st->arena) + reinterpret_cast<size_t>(kv.second.ptr);
-        // per-group work and launch grids
-        st->total.resize(G);
-        st->grid.resize(G);
-        st->per_cu.resize(G);
-        st->tiles.assign((size_t)G * nimg, {0, 0, 0});
-        for (int g = 0; g < G; ++g) {
-            int tot = 0;
-            for (int i = 0; i < nimg; ++i) {
-                auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[plan.groups[g].g.nodes[0]].level);
-                int tx, ty, w;
-                tile_counts(plan, plan.groups[g], d.first, d.second, tx, ty, w);
-                st->tiles[(size_t)g * nimg + i] = {tx, ty, w};
-                tot += w;
-            }
-            st->total[g] = tot;
-            const GroupRt& gr = plan.groups[g];
-            int threads = gr.resample ? 256 : 64 * gr.g.WPB;
-            int per_cu = resident_blocks_per_cu(plan, gr.fn_batch, threads);
-            st->per_cu[g] = per_cu;
-            int units = (gr.resample || gr.g.BLK) ? tot : (tot + gr.g.WPB - 1) / gr.g.WPB;
-            // the per-unit grid is capped at 2^22 workgroups (far above the
-            // resident set; the waves' stride loop covers any remainder)
-            st->grid[g] = batch_grid_resident(plan) ? std::max(1, std::min(units, per_cu * plan.machine.ncu))
-                                                : std::max(1, std::min(units, 1 << 22));
-        }
-        // device argument table: [g][img] WtArgs, then [g][nimg + 1] starts
-        st->args_bytes = (size_t)G * nimg * sizeof(WtArgsHost);
-        st->dargs_bytes = st->args_bytes + (size_t)G * (nimg + 1) * sizeof(int);
-        if (hipMalloc(&st->dargs, st->dargs_bytes) != hipSuccess) fail(WT_E_NOMEM, "batch argument table");
-        st->host.resize(st->dargs_bytes);
+        load_batch_kernels(plan, plan.groups);  // compiled on first use
+        auto st = layout_batch(plan, sizes);
+        void* arena = nullptr;
+        void* dargs = nullptr;
+        if (st->arena_bytes && hipMalloc(&arena, st->arena_bytes) != hipSuccess)
+            fail(WT_E_NOMEM, "batch intermediates");
+        st->arena = arena;  // owned from here on
+        if (hipMalloc(&dargs, st->dargs_bytes) != hipSuccess) fail(WT_E_NOMEM, "batch argument table");
+        place_batch(*st, arena, dargs);
         // capture the launch sequence once for this shape
         hipStream_t cs;
         hip_check(hipStreamCreate(&cs), "hipStreamCreate");
@@ -236,35 +300,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
     }
 
     BatchState& st = *plan.batch;
-    for (int i = 0; i < nimg; ++i)
-        for (auto& kv : st.bufs[i]) mem[i][kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
-    // fill the argument table
-    std::memset(st.host.data(), 0, st.host.size());
-    for (int g = 0; g < G; ++g) {
-        const GroupRt& gr = plan.groups[g];
-        int* starts = reinterpret_cast<int*>(st.host.data() + st.args_bytes) + (size_t)g * (nimg + 1);
-        int acc = 0;
-        for (int i = 0; i < nimg; ++i) {
-            WtArgsHost& a = reinterpret_cast<WtArgsHost*>(st.host.data())[(size_t)g * nimg + i];
-            auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[gr.g.nodes[0]].level);
-            fill_args(plan, gr, mem[i], a, "batch image " + std::to_string(i));
-            check_store_planes(plan, gr, a, d.second);
-            a.W = d.first;
-            a.H = d.second;
-            if (gr.resample) {
-                auto sd = level_dims(sizes[i].first, sizes[i].second, p.nodes[p.nodes[gr.g.nodes[0]].srcs[0]].level);
-                a.Ws = sd.first;
-                a.Hs = sd.second;
-            }
-            const auto& t = st.tiles[(size_t)g * nimg + i];
-            a.tiles_x = t[0];
-            a.tiles_y = t[1];
-            a.nwaves = t[2];
-            starts[i] = acc;
-            acc += t[2];
-        }
-        starts[nimg] = acc;
-    }
+    fill_table(plan, st, mem);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // the table changes only when the caller's image pointers or strides do
     if (st.uploaded != st.host) {
@@ -276,6 +312,40 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
         return;
     }
     for (int g = first; g < first + count; ++g)
+        hip_check(launch_batch_group(plan, st, g, nimg, s), "hipModuleLaunchKernel");
+}
+
+void run_plan_batch_static(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
+    if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
+    for (const auto& gr : plan.groups)
+        if (!gr.fn_batch)
+            fail(WT_E_INVALID, "the plan's batched kernels are not loaded (create the plan with batch_images > 1, "
+                               "or run wt_plan_run_batch once)");
+    int dev = -1;
+    hip_check(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != plan.device) fail(WT_E_INVALID, "the current device is not the plan's");
+    std::vector<std::pair<int, int>> sizes;
+    std::vector<std::map<int, ImgRef>> mem;
+    check_batch(plan, nimg, in, out, sizes, mem);
+    if (!plan.batch_static || plan.batch_static->sizes != sizes) {
+        plan.batch_static = layout_batch(plan, sizes);
+        plan.batch_static->owned = false;  // the workspace is the library's
+    }
+    BatchState& st = *plan.batch_static;
+    const size_t arena = (st.arena_bytes + 255) / 256 * 256;
+    const size_t need = arena + st.dargs_bytes;
+    if (need > (size_t)WT_STATIC_SCRATCH_BYTES)
+        fail(WT_E_NOMEM, "batch needs " + std::to_string(need) + " bytes of workspace (intermediates and argument "
+                         "table); the fixed workspace holds " + std::to_string((size_t)WT_STATIC_SCRATCH_BYTES));
+    hipError_t e = hipSuccess;
+    char* base = static_cast<char*>(static_scratch(dev, &e));
+    hip_check(e, "hipGetSymbolAddress (fixed workspace)");
+    place_batch(st, base, base + arena);
+    fill_table(plan, st, mem);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // every call rewrites the table: the workspace is shared by all plans
+    hip_check(hipMemcpyAsync(st.dargs, st.host.data(), st.host.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    for (int g = 0; g < (int)plan.groups.size(); ++g)
         hip_check(launch_batch_group(plan, st, g, nimg, s), "hipModuleLaunchKernel");
 }
 

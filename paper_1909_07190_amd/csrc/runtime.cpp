@@ -249,6 +249,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
             req.fixed = text;
             plan->sched = make_schedule(p, plan->machine, req);
             build_groups(*plan);
+            if (opts.batch_images > 1) load_batch_kernels(*plan, plan->groups);
             return plan;
         }
     }
@@ -280,6 +281,9 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
         }
         tune_cache_store(plan->cache_dir, key, schedule_text(plan->sched));
     }
+    // a plan made for batches loads its batched kernels now, so batched runs
+    // (wt_plan_run_batch_static in particular) need no compilation
+    if (!plan->no_device && opts.batch_images > 1) load_batch_kernels(*plan, plan->groups);
     return plan;
 }
 

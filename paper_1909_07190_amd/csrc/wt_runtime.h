@@ -57,6 +57,7 @@ struct BatchState {
     std::vector<std::pair<int, int>> sizes;
     void* arena = nullptr;
     size_t arena_bytes = 0;
+    std::vector<std::map<int, Buf>> offs;  // per image: intermediates' offsets in the arena
     std::vector<std::map<int, Buf>> bufs;  // per image: intermediates in the arena
     std::vector<std::array<int, 3>> tiles; // [group][img]: tiles_x, tiles_y, work items
     std::vector<int> total, grid, per_cu;  // per group
@@ -66,6 +67,7 @@ struct BatchState {
     std::vector<char> uploaded;            // the table as last copied to the device
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool owned = true;                     // arena and table allocated for this state
     ~BatchState();
 };
 
@@ -85,6 +87,7 @@ struct Plan {
     hipStream_t setup_stream = nullptr;  // caller's stream for planning-time measurements
     std::string cache_dir;
     std::unique_ptr<BatchState> batch;
+    std::unique_ptr<BatchState> batch_static;  // layout of the last run in the fixed workspace
     ~Plan();
 };
 
@@ -153,6 +156,13 @@ int resident_blocks_per_cu(const Plan& plan, hipFunction_t fn, int threads);
 // groups [first, first + count), launched directly on the stream.
 void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream, int first = 0,
                     int count = -1);
+// The same batch with its intermediates and argument table in the library's
+// fixed workspace, every group launched directly: no device allocation.
+void run_plan_batch_static(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
+// Compiles and loads the batched kernels of the groups that lack them.
+void load_batch_kernels(const Plan& plan, std::vector<GroupRt>& groups);
+// The fixed workspace (scratch.hip): `device`'s copy, device current.
+void* static_scratch(int device, hipError_t* err);
 // Measures candidate configurations of every fused group and keeps the
 // fastest; candidates ranked by the learned model when `model_path` is set.
 // With `batch` > 1 the candidates are timed on an image as tall as up to
