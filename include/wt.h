@@ -184,7 +184,8 @@ typedef struct {
                                    (stages whose magnitude bound exceeds
                                    65504 keep FP32; see wt_input_bound)     */
     int32_t flags;              /* WT_PLAN_* bits                              */
-    int32_t autotune_topk;      /* candidates measured in WT_SCHED_AUTOTUNE    */
+    int32_t autotune_topk;      /* candidates measured in WT_SCHED_AUTOTUNE per
+                                   ranking (0: 4)                             */
     const char* fixed_schedule; /* WT_SCHED_FIXED (see wt_plan_describe)       */
     const char* model_path;     /* WT_SCHED_MLP weights file; with WT_SCHED_
                                    AUTOTUNE, the learned model ranks candidates */
@@ -415,7 +416,9 @@ wt_status wt_mlp_load(const char* path, wt_mlp** out);
 /* Features of every configuration the search grid holds for `nodes` of a
  * pipeline planned at width x height (row-major, 40 per configuration), with
  * each configuration's schedule text (';'-separated) -- the learned model's
- * inputs as the scheduler sees them. */
+ * inputs as the scheduler sees them.  down2 stages among `nodes` are written
+ * decimated by the group (the source must be a member), and an up2 of such
+ * a down2 is folded into it. */
 wt_status wt_group_features(const wt_pipeline* p, const int* nodes, int nnodes, int width, int height,
                             int fp16, float* features, int max_rows, int* rows, char* text,
                             size_t text_len);

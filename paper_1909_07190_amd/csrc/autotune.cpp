@@ -181,7 +181,7 @@ struct PlanHeight {
 
 }  // namespace
 
-double autotune_plan(Plan& plan, int topk, const std::string& model_path, int batch) {
+double autotune_plan(Plan& plan, int topk, const std::string& model_path, int batch, TuneMemo* memo) {
     const Pipeline& p = plan.p;
     DeviceScratch sc;
     std::map<int, ImgRef> mem = scratch_memory(plan, sc);
@@ -214,6 +214,21 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
             continue;
         }
         const GroupSched cur = plan.sched.groups[gi];
+        // a group tuned before (for another grouping of the same plan)
+        std::ostringstream key;
+        for (int v : cur.nodes) key << v << ',';
+        key << '|';
+        for (int v : cur.dec) key << v << ',';
+        key << '|';
+        for (int v : cur.exp) key << v << ',';
+        if (memo) {
+            auto hit = memo->find(key.str());
+            if (hit != memo->end()) {
+                plan.sched.groups[gi] = hit->second.first;
+                total_us += hit->second.second;
+                continue;
+            }
+        }
         std::vector<ScoredConfig> all = score_configs(p, plan.machine, req, cur.nodes, cur.dec);
         std::vector<const ScoredConfig*> by_pred, by_score;
         for (auto& c : all) {
@@ -255,9 +270,8 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         for (int V : {4, 2, 1})
             for (int TX : {1, 2})
                 for (int TY : {16, 32, 64}) {
-                    // one column per lane only where no wider vector fits;
-                    // 64-row tiles only for batches
-                    if (V > vmax || (V == 1 && vmax > 1) || (TY == 64 && batch <= 1)) continue;
+                    // the widest vector only; 64-row tiles only for batches
+                    if (V != vmax || (TY == 64 && batch <= 1)) continue;
                     GroupSched g = cur;
                     g.V = V;
                     g.TX = TX;
@@ -301,8 +315,9 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
                 }
         double best_t = INFINITY;
         GroupSched best = cur;
+        const int reps = std::max(5, 20 / k);  // tall images: fewer, longer launches
         for (auto& t : trials) {
-            double us = time_group_us(plan, t, k > 1 ? tall_mem : mem, st, 20);
+            double us = time_group_us(plan, t, k > 1 ? tall_mem : mem, st, reps);
             if (us < best_t) {
                 best_t = us;
                 best = t.g;
@@ -312,6 +327,7 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         for (auto& t : trials) unload_group(t);
         plan.sched.groups[gi] = best;
         total_us += best_t / k;
+        if (memo) (*memo)[key.str()] = {best, best_t / k};
         if (verbose())
             std::fprintf(stderr, "wavetile autotune: group %zu of %zu, %zu candidates, best %.1f us on %d image(s): %s\n",
                          gi + 1, plan.sched.groups.size(), trials.size(), best_t, k, describe_group(best).c_str());

@@ -580,9 +580,15 @@ wt_status wt_group_features(const wt_pipeline* p, const int* nodes, int nnodes, 
         r.W = width;
         r.H = height;
         r.fp16 = fp16 != 0;
-        std::vector<int> ns(nodes, nodes + nnodes);
+        std::vector<int> ns, dec;
+        for (int i = 0; i < nnodes; ++i) {
+            if (nodes[i] < 0 || nodes[i] >= (int)p->p.nodes.size()) wt::fail(WT_E_INVALID, "node out of range");
+            (p->p.nodes[nodes[i]].kind == wt::Kind::Down2 ? dec : ns).push_back(nodes[i]);
+        }
         std::sort(ns.begin(), ns.end());
-        auto cfgs = wt::score_configs(p->p, wt::Machine{}, r, ns);
+        std::sort(dec.begin(), dec.end());
+        if (ns.empty()) wt::fail(WT_E_INVALID, "group without a fusable stage");
+        auto cfgs = wt::score_configs(p->p, wt::Machine{}, r, ns, dec);
         std::string all;
         int n = 0;
         for (const auto& c : cfgs) {

@@ -340,7 +340,39 @@ struct Gen {
     // registers across steps: the row index advances by at most one per
     // step, so each step loads only the lowest row and shifts the others
     // when the index has moved.
-    bool coarse_ring(const NodeGeom& n) const { return !border && V == 1 && n.expand_src >= 0; }
+    bool coarse_ring(const NodeGeom& n) const { return !border && n.expand_src >= 0 && (V == 1 || V == 2 || V == 4); }
+    // Even V: lane t of sub-tile k holds coarse columns bc_k + t*V/2 .. +V/2-1
+    // (its fine columns' own coarse columns, one aligned-to-dword vector load
+    // per coarse row); the columns just left and right of a sub-tile (for its
+    // edge lanes) are ghosts every lane loads at one address.
+    std::string cvec(int id, int ch, int k, char which) { return "xv" + I(id) + "_" + I(ch) + "_" + I(k) + which; }
+    std::string cghost(int id, int ch, int k, char side, char which) {
+        return "xg" + I(id) + "_" + I(ch) + "_" + I(k) + side + which;
+    }
+    // Emits the loads of coarse row `row` (an expression, already clamped)
+    // for sub-tile k of an even-V ring into rows `which`.
+    void load_coarse_even(const NodeGeom& n, int li, int ch, int k, const std::string& rowp, char which) {
+        const int h = V / 2;
+        const std::string bc = "((x0 + " + I(n.skew) + " + " + I(k * SUB) + ") >> 1)";
+        if (h == 1) {
+            line("  " + cvec(n.id, ch, k, which) + "[0] = (float)" + rowp + "[wt_clampi(" + bc + " + lane, 0, Wc - 1)];");
+        } else if (n.mem_half) {
+            line("  { const int c0 = " + bc + " + lane * 2;");
+            line("    " + cvec(n.id, ch, k, which) + "[0] = (float)" + rowp + "[min(c0, Wc - 1)]; " +
+                 cvec(n.id, ch, k, which) + "[1] = (float)" + rowp + "[min(c0 + 1, Wc - 1)]; }");
+        } else {
+            // interior waves: both coarse columns of every lane lie inside
+            // the coarse row
+            line("  { const wt_f2d q = *(const wt_f2d*)(" + rowp + " + " + bc + " + lane * 2); " +
+                 cvec(n.id, ch, k, which) + "[0] = q[0]; " + cvec(n.id, ch, k, which) + "[1] = q[1]; }");
+        }
+        if (k == 0)
+            line("  " + cghost(n.id, ch, k, 'l', which) + " = (float)" + rowp + "[wt_clampi(" + bc + " - 1, 0, Wc - 1)];");
+        if (k == g.TX - 1)
+            line("  " + cghost(n.id, ch, k, 'r', which) + " = (float)" + rowp + "[min(" + bc + " + " + I(64 * h) +
+                 ", Wc - 1)];");
+        (void)li;
+    }
     std::string cring(int id, int ch, int k, char which) {
         return "xr" + I(id) + "_" + I(ch) + "_" + I(k) + which;
     }
@@ -352,9 +384,18 @@ struct Gen {
             if (!coarse_ring(n)) continue;
             const std::string ty = n.mem_half ? "_Float16" : "float";
             for (int ch = 0; ch < n.nch; ++ch)
-                for (int k = 0; k < g.TX; ++k)
-                    line("float " + cring(n.id, ch, k, 'p') + ", " + cring(n.id, ch, k, 'c') + ", " +
-                         cring(n.id, ch, k, 'n') + ";");
+                for (int k = 0; k < g.TX; ++k) {
+                    if (V == 1) {
+                        line("float " + cring(n.id, ch, k, 'p') + ", " + cring(n.id, ch, k, 'c') + ", " +
+                             cring(n.id, ch, k, 'n') + ";");
+                        continue;
+                    }
+                    for (char w : {'p', 'c', 'n'}) {
+                        line("float " + cvec(n.id, ch, k, w) + "[" + I(V / 2) + "];");
+                        if (k == 0) line("float " + cghost(n.id, ch, k, 'l', w) + ";");
+                        if (k == g.TX - 1) line("float " + cghost(n.id, ch, k, 'r', w) + ";");
+                    }
+                }
             line("int xj" + I(n.id) + ";  // coarse row held in the middle of node " + I(n.id) + "'s ring");
             line("{ const int Wc = (W + 1) >> 1, Hc = (H + 1) >> 1;");
             line("  const int jf = wt_clampi(y0 - " + I(geo.D - n.first_step) + " + " + I(n.lead) + ", 0, H - 1) >> 1;");
@@ -364,6 +405,15 @@ struct Gen {
                 line("    const " + ty + "* r0 = cb + (long long)wt_clampi(jf - 1, 0, Hc - 1) * A.src_rs[" + I(l) + "];");
                 line("    const " + ty + "* r1 = cb + (long long)jf * A.src_rs[" + I(l) + "];");
                 line("    const " + ty + "* r2 = cb + (long long)min(jf + 1, Hc - 1) * A.src_rs[" + I(l) + "];");
+                if (V > 1) {
+                    for (int k = 0; k < g.TX; ++k) {
+                        load_coarse_even(n, l, ch, k, "r0", 'p');
+                        load_coarse_even(n, l, ch, k, "r1", 'c');
+                        load_coarse_even(n, l, ch, k, "r2", 'n');
+                    }
+                    line("  }");
+                    continue;
+                }
                 for (int k = 0; k < g.TX; ++k) {
                     line("    { const int cl = wt_clampi(((x0 + " + I(n.skew) + " + " + I(k * SUB) + ") >> 1) - 1 + lane, 0, Wc - 1);");
                     line("      " + cring(n.id, ch, k, 'p') + " = (float)r0[cl];");
@@ -394,6 +444,66 @@ struct Gen {
             line("const " + ty + "* r0 = cb + (long long)wt_clampi(jr - 1, 0, Hc - 1) * A.src_rs[" + I(li) + "];");
             line("const " + ty + "* r1 = cb + (long long)min(jr, Hc - 1) * A.src_rs[" + I(li) + "];");
             line("const " + ty + "* r2 = cb + (long long)min(jr + 1, Hc - 1) * A.src_rs[" + I(li) + "];");
+            // even V, interior wave: advance the ring, load the lowest coarse
+            // row, blend the three rows per coarse column; fine column 2c
+            // takes 1/8, 3/4, 1/8 of coarse columns c-1, c, c+1 and 2c+1
+            // half of c and c+1, the neighbours of a lane's edge columns
+            // coming from the next lanes by DPP (the sub-tile's edge lanes
+            // from the neighbouring sub-tile or the ghosts)
+            std::vector<std::vector<std::string>> ev;  // [k][e] fine values
+            if (coarse_ring(n) && V > 1) {
+                const int h = V / 2;
+                std::vector<std::vector<std::string>> q(g.TX, std::vector<std::string>(h));
+                std::string ql, qr;
+                auto blend = [&](const std::string& P, const std::string& C, const std::string& N) {
+                    std::string t = fresh("q");
+                    line("const float " + t + " = fmaf(wy2, " + N + ", fmaf(wy1, " + C + ", wy0 * " + P + "));");
+                    return t;
+                };
+                const std::string a = "adv" + I(n.id);
+                for (int k = 0; k < g.TX; ++k) {
+                    for (int m = 0; m < h; ++m) {
+                        const std::string P = cvec(n.id, ch, k, 'p') + "[" + I(m) + "]",
+                                          C = cvec(n.id, ch, k, 'c') + "[" + I(m) + "]",
+                                          N = cvec(n.id, ch, k, 'n') + "[" + I(m) + "]";
+                        line(P + " = " + a + " ? " + C + " : " + P + ";");
+                        line(C + " = " + a + " ? " + N + " : " + C + ";");
+                    }
+                    for (char side : {'l', 'r'}) {
+                        if ((side == 'l' && k != 0) || (side == 'r' && k != g.TX - 1)) continue;
+                        const std::string P = cghost(n.id, ch, k, side, 'p'), C = cghost(n.id, ch, k, side, 'c'),
+                                          N = cghost(n.id, ch, k, side, 'n');
+                        line(P + " = " + a + " ? " + C + " : " + P + ";");
+                        line(C + " = " + a + " ? " + N + " : " + C + ";");
+                    }
+                    load_coarse_even(n, li, ch, k, "r2", 'n');
+                    for (int m = 0; m < h; ++m)
+                        q[k][m] = blend(cvec(n.id, ch, k, 'p') + "[" + I(m) + "]", cvec(n.id, ch, k, 'c') + "[" + I(m) + "]",
+                                        cvec(n.id, ch, k, 'n') + "[" + I(m) + "]");
+                    if (k == 0)
+                        ql = blend(cghost(n.id, ch, k, 'l', 'p'), cghost(n.id, ch, k, 'l', 'c'), cghost(n.id, ch, k, 'l', 'n'));
+                    if (k == g.TX - 1)
+                        qr = blend(cghost(n.id, ch, k, 'r', 'p'), cghost(n.id, ch, k, 'r', 'c'), cghost(n.id, ch, k, 'r', 'n'));
+                }
+                ev.assign(g.TX, std::vector<std::string>(V));
+                for (int k = 0; k < g.TX; ++k) {
+                    std::string L = fresh("ql"), R = fresh("qr");
+                    if (k > 0)
+                        line("const float " + L + " = wt_shift1(" + q[k][h - 1] + ", " + q[k - 1][h - 1] + ");");
+                    else
+                        line("const float " + L + " = wt_shr1(" + q[k][h - 1] + ", " + ql + ");");
+                    if (k + 1 < g.TX)
+                        line("const float " + R + " = wt_shift1n(" + q[k][0] + ", " + q[k + 1][0] + ");");
+                    else
+                        line("const float " + R + " = wt_shl1(" + q[k][0] + ", " + qr + ");");
+                    for (int e = 0; e < V; ++e) {
+                        const int m = e / 2;
+                        const std::string qa = m > 0 ? q[k][m - 1] : L, qb = m + 1 < h ? q[k][m + 1] : R;
+                        ev[k][e] = e % 2 == 0 ? "fmaf(0.125f, " + qb + ", fmaf(0.75f, " + q[k][m] + ", 0.125f * " + qa + "))"
+                                              : "fmaf(0.5f, " + qb + ", 0.5f * " + q[k][m] + ")";
+                    }
+                }
+            }
             for (int k = 0; k < g.TX; ++k) {
                 std::vector<std::string> dst;
                 std::string v;
@@ -403,6 +513,11 @@ struct Gen {
                     v = fresh("ld");
                     line("float " + v + "[" + I(V) + "];");
                     for (int e = 0; e < V; ++e) dst.push_back(v + "[" + I(e) + "]");
+                }
+                if (coarse_ring(n) && V > 1) {
+                    for (int e = 0; e < V; ++e) line(dst[e] + " = " + ev[k][e] + ";");
+                    if (k < SX) emit_lds_store(n, slot, ch, k, v);
+                    continue;
                 }
                 if (coarse_ring(n)) {
                     // interior wave, one column per lane: lane t holds coarse

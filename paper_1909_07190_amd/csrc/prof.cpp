@@ -192,8 +192,13 @@ void preprofile(const Plan& plan) {
     for (size_t i = 0; i < todo.size(); ++i) {
         units[i].g.nodes = {todo[i]};
         units[i].g.fp16 = false;
-        int vmax = max_vector_width(p, units[i].g, plan.W, plan.H, true);
-        units[i].g.V = std::min(4, vmax);
+        // the stage's unfused kernel at the widths the cost models were
+        // fitted with: one column per lane for a stage that reads a
+        // pipeline input or writes an output, four otherwise
+        bool user = p.is_output(todo[i]);
+        for (int s : p.nodes[todo[i]].srcs)
+            if (p.nodes[s].kind == Kind::Input) user = true;
+        units[i].g.V = user ? 1 : 4;
         prepare_group(plan, units[i], 0);
     }
     std::vector<GroupRt*> all;

@@ -259,25 +259,45 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     plan->sched = make_schedule(p, plan->machine, req);
     build_groups(*plan);
     if (tune) {
-        const int topk = opts.autotune_topk > 0 ? opts.autotune_topk : 6;
+        const int topk = opts.autotune_topk > 0 ? opts.autotune_topk : 4;
         const std::string model = opts.model_path ? opts.model_path : "";
-        double t = autotune_plan(*plan, topk, model, req.batch);
-        // The search's grouping with up2 stages only expanded (never folded
-        // into the group of the stage they resample), when it differs, is
-        // measured too: the faster of the two tuned plans is kept.
-        SchedRequest alt_req = req;
-        alt_req.fold = false;
-        Schedule alt_sched = req.fold ? make_schedule(p, plan->machine, alt_req) : plan->sched;
-        if (!same_grouping(plan->sched, alt_sched)) {
+        TuneMemo memo;
+        double t = autotune_plan(*plan, topk, model, req.batch, &memo);
+        // Other groupings the search proposes are measured too, and the
+        // fastest tuned plan is kept: the same search with up2 stages only
+        // expanded (never folded into the group of the stage they
+        // resample), and the analytical model's search for one image of
+        // this size (the cost models rank folded groups differently; a
+        // group tuned for one grouping is reused by the others).
+        std::vector<SchedRequest> alts;
+        SchedRequest nofold = req;
+        nofold.fold = false;
+        if (req.fold) alts.push_back(nofold);
+        SchedRequest one = req;
+        one.mode = WT_SCHED_ANALYTIC;
+        one.model_path.clear();
+        one.batch = 1;
+        alts.push_back(one);
+        std::vector<Schedule> seen = {plan->sched};
+        for (const SchedRequest& ar : alts) {
+            Schedule alt_sched = make_schedule(p, plan->machine, ar);
+            bool dup = false;
+            for (const Schedule& sc : seen) dup = dup || same_grouping(sc, alt_sched);
+            if (dup) continue;
+            seen.push_back(alt_sched);
             auto alt = std::make_unique<Plan>();
             copy_settings(*plan, *alt);
             alt->sched = alt_sched;
             build_groups(*alt);
-            double t_alt = autotune_plan(*alt, topk, model, req.batch);
+            double t_alt = autotune_plan(*alt, topk, model, req.batch, &memo);
             if (verbose())
-                std::fprintf(stderr, "wavetile autotune: %.1f us per image with folded up2s, %.1f us without\n", t,
-                             t_alt);
-            if (t_alt < t) plan = std::move(alt);
+                std::fprintf(stderr, "wavetile autotune: another grouping (%s%s): %.1f us per image, against %.1f\n",
+                             ar.mode == WT_SCHED_ANALYTIC && ar.batch == 1 ? "analytical, one image" : "search",
+                             ar.fold ? "" : ", no folded up2s", t_alt, t);
+            if (t_alt < t) {
+                plan = std::move(alt);
+                t = t_alt;
+            }
         }
         tune_cache_store(plan->cache_dir, key, schedule_text(plan->sched));
     }

@@ -168,8 +168,11 @@ void* static_scratch(int device, hipError_t* err);
 // With `batch` > 1 the candidates are timed on an image as tall as up to
 // `batch` images of the plan's size, the wave count of a batched launch.
 // Returns the measured time of the chosen plan per image (the sum over its
-// groups, in microseconds).
-double autotune_plan(Plan& plan, int topk, const std::string& model_path = "", int batch = 1);
+// groups, in microseconds).  `memo` (optional) keeps each tuned group's
+// choice and time by its stages, for tuning other groupings of the plan.
+using TuneMemo = std::map<std::string, std::pair<GroupSched, double>>;
+double autotune_plan(Plan& plan, int topk, const std::string& model_path = "", int batch = 1,
+                     TuneMemo* memo = nullptr);
 // Autotune schedule cache (see wt.h): key of a plan, lookup and store.
 std::string schedule_text(const Schedule& s);
 std::string tune_key(const Plan& plan, const wt_sched_opts& opts);

@@ -101,17 +101,103 @@ class Dag:
         return sorted(g) if len(g) >= 2 else None
 
 
+def all_groups(dag, max_size=10):
+    """Every group of 2..max_size fusable stages of one level that is
+    connected (a producer-consumer edge or a shared pipeline input between
+    members) and convex: the fusion search's candidate set without
+    resampling stages, enumerated exhaustively (each connected set once, by
+    extending from its smallest stage with exclusive neighbourhoods)."""
+    fus = [i for i in dag.stages if dag.fusable(i)]
+    adj = {i: set() for i in fus}
+    for i in fus:
+        for u in dag.prod[i] + dag.cons[i]:
+            if u in adj and dag.level[u] == dag.level[i]:
+                adj[i].add(u)
+                adj[u].add(i)
+    for inp, kind in dag.kind.items():
+        if kind != "input":
+            continue
+        readers = [i for i in dag.cons[inp] if i in adj]
+        for a in readers:
+            for b in readers:
+                if a != b and dag.level[a] == dag.level[b]:
+                    adj[a].add(b)
+    out = []
+
+    def extend(sub, ext, v):
+        if len(sub) >= 2 and dag.convex(sorted(sub)):
+            out.append(tuple(sorted(sub)))
+        if len(sub) == max_size:
+            return
+        ext = set(ext)
+        while ext:
+            w = min(ext)
+            ext.discard(w)
+            near = set().union(*(adj[x] for x in sub)) | sub
+            excl = {u for u in adj[w] if u > v and u not in near}
+            extend(sub | {w}, ext | excl, v)
+
+    for v in fus:
+        extend({v}, {u for u in adj[v] if u > v}, v)
+    return out
+
+
+# tile configurations of the exhaustive search (every group under each)
+EXHAUSTIVE_GRID = ("V=4 TX=1 SX=0 TY=16 PF=2", "V=4 TX=1 SX=0 TY=32 PF=2", "V=2 TX=1 SX=0 TY=16 PF=2",
+                   "V=2 TX=2 SX=0 TY=16 PF=2", "V=4 TX=2 SX=0 TY=8 PF=2", "V=2 TX=1 SX=0 TY=32 PF=1",
+                   "V=1 TX=4 SX=2 TY=16 PF=1", "V=4 TX=1 SX=1 TY=16 PF=2")
+
+
+def exhaustive_schedule(dag, pipe, width, height, grid=EXHAUSTIVE_GRID, max_size=10, reps=20):
+    """Measures every admissible group (and every stage alone) under every
+    configuration of `grid`, then assembles the fastest schedule from the
+    measurements (a dynamic program over down-closed stage sets); returns
+    (total microseconds, schedule text, timings taken)."""
+    groups = [(i,) for i in dag.stages if dag.fusable(i)] + all_groups(dag, max_size)
+    texts = [_group_text(list(g), cfg) for g in groups for cfg in grid]
+    times = measure_groups(pipe, texts, width, height, reps=reps, tag="exhaustive")
+    rows = [{"group": t, "measured_us": us} for t, us in zip(texts, times) if math.isfinite(us)]
+    res_us = {}
+    for i in dag.stages:
+        if not dag.fusable(i):
+            t = measure_groups(pipe, [_group_text([i])], width, height, reps=reps)[0]
+            res_us[i] = (t, _group_text([i]))
+    total, text = best_measured_schedule(dag, rows, res_us)
+    return total, text, len(texts)
+
+
 def _group_text(nodes, cfg=""):
     return "nodes=" + ",".join(str(n) for n in nodes) + (" " + cfg if cfg else "")
 
 
 def _parse_groups(describe_text):
+    """(members plus decimated down2 stages, group text) per group of a plan
+    description; the text keeps the group's decimated and expanded stages."""
     out = []
     for line in describe_text.strip().splitlines():
-        toks = [t for t in line.split() if "=" in t and not t.startswith(("batch_", "dec=", "exp="))]
+        toks = [t for t in line.split() if "=" in t and not t.startswith("batch_")]
         nodes = [int(x) for x in toks[0].split("=")[1].split(",")]
-        out.append((nodes, " ".join(toks)))
+        for t in toks:
+            if t.startswith("dec="):
+                nodes += [int(x) for x in t[4:].split(",")]
+        out.append((sorted(nodes), " ".join(toks)))
     return out
+
+
+def _with_resampling(dag, group, rng):
+    """The group with, for some members, their down2 written decimated and
+    an up2 of that down2 folded in (the fusion search's cross-level groups),
+    or the group unchanged."""
+    out = list(group)
+    for p in group:
+        for d in dag.cons[p]:
+            if dag.kind[d] != "down2" or rng.random() < 0.5:
+                continue
+            out.append(d)
+            for u in dag.cons[d]:
+                if dag.kind[u] == "up2" and rng.random() < 0.7:
+                    out.append(u)
+    return sorted(out)
 
 
 # ------------------------------------------------------------------ collect --
@@ -148,10 +234,10 @@ def collect(specs, db, width=2048, height=2048, configs_per_group=4, random_grou
         for _ in range(0 if picks_only else random_groups):
             g = dag.random_group(rng, rng.randint(2, 12))
             if g:
-                groups.append((g, configs_per_group))
+                groups.append((_with_resampling(dag, g, rng) if rng.random() < 0.5 else g, configs_per_group))
         plan = pipe.plan(width, height, mode="analytic", no_compile=True)
         for nodes, text in _parse_groups(plan.describe()):
-            if len(nodes) == 1 and not dag.fusable(nodes[0]):
+            if not any(dag.fusable(n) for n in nodes):
                 continue  # resampling kernels have no model features
             groups.append((nodes, 0 if picks_only else configs_per_group))
             texts.append(text)  # the analytical pick itself
@@ -395,11 +481,13 @@ def best_measured_schedule(dag, rows, resample_us):
     return t, ";".join(texts)
 
 
-ALL_MODES = ("unfused", "analytic", "mlp", "autotune", "mlp_autotune", "best_measured")
+ALL_MODES = ("unfused", "analytic", "mlp", "autotune", "mlp_autotune", "best_measured", "exhaustive")
+# modes that use the learned model (excluded from the reference it is judged by)
+LEARNED_MODES = ("mlp", "mlp_autotune")
 
 
 def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, log=print, out_path=None,
-             modes=ALL_MODES):
+             modes=ALL_MODES, exhaustive_max_stages=10):
     import torch
 
     dev = torch.device("cuda:0")
@@ -438,10 +526,20 @@ def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, 
             if math.isfinite(t_sum):
                 plans["best_measured"] = pipe.plan(width, height, mode="fixed", fixed=text)
                 res["best_measured_sum_us"] = t_sum
+        if "exhaustive" in modes and len(spec["stages"]) <= exhaustive_max_stages:
+            t_sum, text, n = exhaustive_schedule(dag, pipe, width, height)
+            if math.isfinite(t_sum):
+                plans["exhaustive"] = pipe.plan(width, height, mode="fixed", fixed=text)
+                res["exhaustive_sum_us"] = t_sum
+                res["exhaustive_timings"] = n
         for name, plan in plans.items():
             res[name + "_us"] = _time_plan(torch, plan, ins, outs)
             res[name + "_groups"] = plan.num_groups
-        res["best_us"] = min(v for k, v in res.items() if k.endswith("_us") and not k.endswith("sum_us"))
+        timed = {k[:-3]: v for k, v in res.items() if k.endswith("_us") and not k.endswith("sum_us")}
+        res["best_us"] = min(timed.values())
+        # the reference the learned model is judged by: the fastest plan no
+        # learned mode produced (the exhaustive search where it ran)
+        res["ref_us"] = min(v for k, v in timed.items() if k not in LEARNED_MODES)
         results.append(res)
         log(json.dumps(res))
         if out_path:  # one line per pipeline as it completes
@@ -456,11 +554,22 @@ def summarize(results):
         return float(np.exp(np.mean(np.log(xs)))) if xs else None
 
     out = {"pipelines": len(results)}
-    for m in ("analytic", "mlp", "autotune", "mlp_autotune", "best_measured", "unfused"):
+    for m in ("analytic", "mlp", "autotune", "mlp_autotune", "best_measured", "exhaustive", "unfused"):
         r = [x[m + "_us"] / x["best_us"] for x in results if m + "_us" in x]
         if r:
             out[m] = {"geomean_over_best": gm(r), "within_10pct": float(np.mean([v <= 1.10 for v in r])),
                       "pipelines": len(r)}
+            ref = [x[m + "_us"] / x["ref_us"] for x in results if m + "_us" in x and "ref_us" in x]
+            if ref:
+                out[m]["geomean_over_reference"] = gm(ref)
+                out[m]["within_10pct_of_reference"] = float(np.mean([v <= 1.10 for v in ref]))
+    ex = [x for x in results if "exhaustive_us" in x]
+    if ex:
+        out["exhaustive_pipelines"] = len(ex)
+        for m in ("mlp", "mlp_autotune", "analytic"):
+            r = [x[m + "_us"] / x["exhaustive_us"] for x in ex if m + "_us" in x]
+            if r:
+                out[m + "_over_exhaustive"] = {"geomean": gm(r), "within_10pct": float(np.mean([v <= 1.10 for v in r]))}
     out["mlp_gain_over_analytic"] = gm([x["analytic_us"] / x["mlp_us"] for x in results
                                          if "analytic_us" in x and "mlp_us" in x])
     out["mlp_speedup_over_unfused"] = gm([x["unfused_us"] / x["mlp_us"] for x in results

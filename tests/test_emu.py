@@ -212,6 +212,10 @@ EXP_SPEC = {"inputs": [{"name": "img", "channels": 1}],
     ("nodes=1;nodes=3,4 V=1 TX=1 SX=0 TY=6 exp=2", 261, 13, False),
     ("nodes=1;nodes=3,4 V=1 TX=2 SX=1 TY=5 PF=1 exp=2", 391, 17, False),
     ("nodes=1;nodes=3,4 V=1 TX=2 SX=0 TY=8 align=1 exp=2 fp16=1", 333, 11, True),
+    # even V: coarse rows kept per lane, neighbours by DPP and edge ghosts
+    ("nodes=1;nodes=3,4 V=4 TX=2 SX=0 TY=8 exp=2", 1100, 21, False),
+    ("nodes=1;nodes=3,4 V=4 TX=2 SX=1 TY=6 exp=2 fp16=1", 1030, 13, True),
+    ("nodes=1;nodes=3,4 V=2 TX=3 SX=0 TY=7 exp=2", 1001, 15, False),
 ])
 def test_expanded_up2_emulated(fixed, w, h, fp16):
     img = synth.uniform_image(3, 1, h, w)
@@ -480,7 +484,8 @@ def _pyramid_fold_schedule(spec, levels, cfg, m_apart):
     return "\n".join(groups)
 
 
-@pytest.mark.parametrize("cfg,m_apart", [("V=1 TX=1 SX=0 TY=8 PF=2", False), ("V=1 TX=2 SX=1 TY=5 PF=1", True)])
+@pytest.mark.parametrize("cfg,m_apart", [("V=1 TX=1 SX=0 TY=8 PF=2", False), ("V=1 TX=2 SX=1 TY=5 PF=1", True),
+                                         ("V=4 TX=1 SX=0 TY=8 PF=2", False)])
 def test_pyramid_folded_levels_emulated(cfg, m_apart):
     """The blend with each level's bands computed in the pass that
     decimates it: exact on a two-level pyramid with dyadic inputs and a 0/1
@@ -494,7 +499,7 @@ def test_pyramid_folded_levels_emulated(cfg, m_apart):
                          any_width=True)
         assert_exact(got["R0"], oracle.evaluate(spec2, ins)["R0"], cfg)
     spec4 = P.pyramid_blend(4)
-    h, w = 37, 70
+    h, w = (37, 70) if "V=1" in cfg else (37, 1203)
     ins = {"A": synth.uniform_image(21, 1, h, w), "B": synth.uniform_image(22, 1, h, w), "M": synth.ramp_mask(h, w)}
     got, _ = emulate(spec4, ins, mode="fixed", fixed=_pyramid_fold_schedule(spec4, 4, cfg, m_apart), any_width=True)
     assert_normwise(got["R0"], oracle.evaluate(spec4, ins)["R0"], 1e-5, cfg)

@@ -26,6 +26,11 @@ def _say(msg):
     sys.stdout.flush()
 
 
+def _model():
+    import paper_1909_07190_amd as wt
+    return wt.GFX950_COST_MODEL
+
+
 def _unsharp_image():
     C, H, W, seed = bench.UNSHARP
     return synth.uniform_image(seed, C, H, W)
@@ -37,13 +42,15 @@ def _harris_image():
 
 
 def test_unsharp_benchmark_schedules_full_size():
-    """The swept schedule and the learned scheduler's plan (FP32 and FP16
-    intermediates) on the 3x2048x2048 unsharp-mask workload."""
+    """The swept schedule, the benchmark's autotuned plan (FP32 and FP16
+    intermediates), the learned scheduler's plan and the one-tile-per-
+    workgroup baseline on the 3x2048x2048 unsharp-mask workload."""
     spec = P.unsharp_mask()
     img = _unsharp_image()
     for kw, rtol in ((dict(mode="fixed", fixed=bench.SWEPT_UNSHARP), 1e-5),
-                     (dict(mode=bench.HEADLINE_MODE), 1e-5),
-                     (dict(mode=bench.HEADLINE_MODE, fp16=True), 2e-3),
+                     (dict(mode=bench.HEADLINE_MODE, model_path=_model()), 1e-5),
+                     (dict(mode=bench.HEADLINE_MODE, fp16=True, model_path=_model()), 2e-3),
+                     (dict(mode="mlp"), 1e-5),
                      (dict(mode="fixed", fixed=bench.OTPTB_UNSHARP), 1e-5)):
         _say(f"unsharp 3x2048x2048 {kw}")
         got, plan = run_gpu(spec, {"img": img}, **kw)
@@ -95,11 +102,13 @@ def _pyramid_tensors(torch, sizes, idx):
 
 
 def test_pyramid_headline_batch_full_workload():
-    """The benchmark's headline: the 64-pair batch under the learned
+    """The benchmark's headline workload: the 64-pair batch under the learned
     scheduler's plan, one launch per group over all pairs from a hipGraph.
     Every image is finite; the three smallest and the three largest are
     checked entirely against the oracle.  Relaunching the last group alone
-    (the benchmark's per-kernel timing path) rewrites the same outputs."""
+    (the benchmark's per-kernel timing path) rewrites the same outputs.
+    (The benchmark's own plan is the autotuner's, tested on a sub-batch
+    below: tuning the whole batch takes minutes.)"""
     import torch
     import paper_1909_07190_amd as wt
     spec = P.pyramid_blend(bench.PYR_LEVELS)
@@ -108,7 +117,7 @@ def test_pyramid_headline_batch_full_workload():
     check = order[:3] + order[-3:]
     _say(f"pyramid headline batch: {len(sizes)} pairs, checking {[sizes[k] for k in check]}")
     tin, tout, host = _pyramid_tensors(torch, sizes, set(check))
-    plan = bench.plan_pyramid(wt, P, sizes, bench.HEADLINE_MODE)
+    plan = bench.plan_pyramid(wt, P, sizes, "mlp", wt.GFX950_COST_MODEL)
     _say(f"  plan: {plan.describe().strip()}")
     plan.run_batch(tin, tout)
     torch.cuda.synchronize()
@@ -129,6 +138,31 @@ def test_pyramid_headline_batch_full_workload():
         a, b, m = host[i]
         ref = oracle.evaluate(spec, {"A": a, "B": b, "M": m})
         assert_normwise(first[i].cpu().numpy(), ref[spec["outputs"][0]], 1e-5, f"image {i} {w}x{h}")
+
+
+def test_pyramid_autotuned_sub_batch(tmp_path, monkeypatch):
+    """The benchmark's planning path (autotune ranked by the learned model,
+    with and without folded expansions, candidates timed on stacked images)
+    on 6 pairs of the headline batch, two candidates per ranking; the
+    smallest and the largest pair against the oracle."""
+    import torch
+    import paper_1909_07190_amd as wt
+    monkeypatch.setenv("WT_CACHE_DIR", str(tmp_path))
+    spec = P.pyramid_blend(bench.PYR_LEVELS)
+    sizes = synth.batch_sizes(bench.PYR_SEED, bench.PYR_PAIRS)[:6]
+    order = sorted(range(len(sizes)), key=lambda k: sizes[k][0] * sizes[k][1])
+    check = [order[0], order[-1]]
+    tin, tout, host = _pyramid_tensors(torch, sizes, set(check))
+    plan = bench.plan_pyramid(wt, P, sizes, bench.HEADLINE_MODE, topk=2)
+    _say(f"  plan: {plan.describe().strip()}")
+    plan.run_batch(tin, tout)
+    torch.cuda.synchronize()
+    for i in check:
+        w, h = sizes[i]
+        _say(f"  oracle {w}x{h}")
+        a, b, m = host[i]
+        ref = oracle.evaluate(spec, {"A": a, "B": b, "M": m})
+        assert_normwise(tout[i][0].cpu().numpy(), ref[spec["outputs"][0]], 1e-5, f"image {i} {w}x{h}")
 
 
 def test_batch_refuses_bad_strides_and_aliases():

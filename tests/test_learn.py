@@ -172,3 +172,41 @@ def test_measure_db_rows_counted_by_the_library(tmp_path):
         wt.model_rows(str(bad))
     with pytest.raises(wt.WtError):
         wt.model_rows(str(tmp_path / "missing.jsonl"))
+
+
+@pytest.mark.parametrize("seed", [3, 7, 11])
+def test_all_groups_is_the_exhaustive_candidate_set(seed):
+    """The exhaustive search's groups are exactly the connected (edges or a
+    shared input), convex, single-level sets of 2..max fusable stages, found
+    by brute force over all subsets, each once."""
+    spec = dags.random_dag(seed, lo=6, hi=10)
+    pipe = wt.from_spec(spec)
+    dag = learn.Dag(spec, pipe)
+    got = learn.all_groups(dag, max_size=10)
+    assert len(got) == len(set(got))
+    fus = [i for i in dag.stages if dag.fusable(i)]
+    readers = {}
+    for inp, kind in dag.kind.items():
+        if kind == "input":
+            readers[inp] = set(dag.cons[inp])
+
+    def linked(a, b):
+        if dag.level[a] != dag.level[b]:
+            return False
+        if b in dag.prod[a] or a in dag.prod[b]:
+            return True
+        return any(a in r and b in r for r in readers.values())
+
+    want = set()
+    for n in range(2, min(10, len(fus)) + 1):
+        for sub in itertools.combinations(fus, n):
+            seen, stack = {sub[0]}, [sub[0]]
+            while stack:
+                v = stack.pop()
+                for u in sub:
+                    if u not in seen and linked(v, u):
+                        seen.add(u)
+                        stack.append(u)
+            if len(seen) == n and dag.convex(list(sub)):
+                want.add(tuple(sorted(sub)))
+    assert set(got) == want
