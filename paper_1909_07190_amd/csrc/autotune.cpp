@@ -102,16 +102,21 @@ void write_db_line(std::ofstream& db, const std::string& tag, const Plan& plan, 
 }  // namespace
 
 // Measured time (microseconds) of one launch of `gr`: 3 samples of `reps`
-// launches, minimum of the sample means.
-double time_group_us(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st,
-                     int reps) {
+// launches, minimum of the sample means.  Consecutive launches use the
+// memory sets in turn, so with sets spanning more than the last-level cache
+// every launch reads its inputs from HBM, as a pipeline run on fresh images
+// does.
+double time_group_us(const Plan& plan, const GroupRt& gr, const std::vector<std::map<int, ImgRef>>& sets,
+                     hipStream_t st, int reps) {
     OwnedEvents ev;
     hipEvent_t e0 = ev.e0, e1 = ev.e1;
-    for (int i = 0; i < 3; ++i) launch_group(plan, gr, mem, st);
+    const size_t n = sets.size();
+    size_t next = 0;
+    for (int i = 0; i < 3; ++i) launch_group(plan, gr, sets[next++ % n], st);
     double best = INFINITY;
     for (int s = 0; s < 3; ++s) {
         hip_check(hipEventRecord(e0, st), "hipEventRecord");
-        for (int i = 0; i < reps; ++i) launch_group(plan, gr, mem, st);
+        for (int i = 0; i < reps; ++i) launch_group(plan, gr, sets[next++ % n], st);
         hip_check(hipEventRecord(e1, st), "hipEventRecord");
         hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0;
@@ -119,6 +124,11 @@ double time_group_us(const Plan& plan, const GroupRt& gr, const std::map<int, Im
         best = std::min(best, (double)ms * 1e3 / reps);
     }
     return best;
+}
+
+double time_group_us(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>& mem, hipStream_t st,
+                     int reps) {
+    return time_group_us(plan, gr, std::vector<std::map<int, ImgRef>>{mem}, st, reps);
 }
 
 std::map<int, ImgRef> scratch_memory(const Plan& plan, DeviceScratch& sc) {
@@ -135,6 +145,28 @@ std::map<int, ImgRef> scratch_memory(const Plan& plan, DeviceScratch& sc) {
     }
     for (auto& kv : plan.bufs) mem[kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
     return mem;
+}
+
+// Copies of every buffer of a plan (its inputs, outputs and materialised
+// intermediates, the first copy being scratch_memory's) until the copies
+// hold at least 1 GiB (at most 8), more than the MI355X's 256 MB Infinity
+// Cache.
+std::vector<std::map<int, ImgRef>> scratch_sets(const Plan& plan, DeviceScratch& sc) {
+    const Pipeline& p = plan.p;
+    std::vector<std::map<int, ImgRef>> sets{scratch_memory(plan, sc)};
+    size_t bytes = 0;
+    for (auto& kv : sets[0]) bytes += (size_t)kv.second.cs * p.nodes[kv.first].channels * 4;
+    const size_t want = (size_t)1 << 30;
+    const int n = (int)std::min<size_t>(8, std::max<size_t>(1, (want + std::max<size_t>(bytes, 1) - 1) / std::max<size_t>(bytes, 1)));
+    for (int c = 1; c < n; ++c) {
+        std::map<int, ImgRef> m;
+        for (auto& kv : sets[0]) {
+            const ImgRef& r = kv.second;
+            m[kv.first] = {sc.alloc((size_t)r.cs * p.nodes[kv.first].channels * 4), r.rs, r.cs};
+        }
+        sets.push_back(std::move(m));
+    }
+    return sets;
 }
 
 namespace {
@@ -184,7 +216,7 @@ struct PlanHeight {
 double autotune_plan(Plan& plan, int topk, const std::string& model_path, int batch, TuneMemo* memo) {
     const Pipeline& p = plan.p;
     DeviceScratch sc;
-    std::map<int, ImgRef> mem = scratch_memory(plan, sc);
+    std::vector<std::map<int, ImgRef>> sets = scratch_sets(plan, sc);
     OwnedStream ost(plan.setup_stream);
     hipStream_t st = ost.s;
     const char* dbp = std::getenv("WT_MEASURE_DB");
@@ -210,7 +242,7 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
     double total_us = 0;  // the chosen configurations' times per image
     for (size_t gi = 0; gi < plan.sched.groups.size(); ++gi) {
         if (plan.groups[gi].resample) {
-            total_us += time_group_us(plan, plan.groups[gi], mem, st, 20);
+            total_us += time_group_us(plan, plan.groups[gi], sets, st, 20);
             continue;
         }
         const GroupSched cur = plan.sched.groups[gi];
@@ -317,7 +349,7 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         GroupSched best = cur;
         const int reps = std::max(5, 20 / k);  // tall images: fewer, longer launches
         for (auto& t : trials) {
-            double us = time_group_us(plan, t, k > 1 ? tall_mem : mem, st, reps);
+            double us = k > 1 ? time_group_us(plan, t, tall_mem, st, reps) : time_group_us(plan, t, sets, st, reps);
             if (us < best_t) {
                 best_t = us;
                 best = t.g;
@@ -325,6 +357,69 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
             if (db.is_open()) write_db_line(db, tag, plan, t, us);
         }
         for (auto& t : trials) unload_group(t);
+        // Local search around the winner: one configuration parameter at a
+        // time (vector width, sub-tiles, tile height, waves per workgroup,
+        // prefetch depth), while a step still helps.  The grid above samples
+        // each axis coarsely; the optimum often sits one step from its best.
+        for (int round = 0; round < 2 && std::isfinite(best_t); ++round) {
+            std::vector<GroupSched> nb;
+            auto try_add = [&](GroupSched g) {
+                if (seen.insert(describe_group(g)).second) nb.push_back(g);
+            };
+            auto step = [&](int GroupSched::*f, int v, int lo, int hi) {
+                if (v < lo || v > hi) return;
+                GroupSched g = best;
+                g.*f = v;
+                if (g.SX > g.TX) g.SX = g.TX;
+                try_add(g);
+            };
+            step(&GroupSched::V, best.V * 2, 1, vmax);
+            step(&GroupSched::V, best.V / 2, 1, vmax);
+            step(&GroupSched::TX, best.TX * 2, 1, 4);
+            step(&GroupSched::TX, best.TX / 2, 1, 4);
+            step(&GroupSched::TY, best.TY * 2, 8, 64);
+            step(&GroupSched::TY, best.TY / 2, 8, 64);
+            step(&GroupSched::WPB, best.WPB * 2, 1, 4);
+            step(&GroupSched::WPB, best.WPB / 2, 1, 4);
+            step(&GroupSched::PF, 3 - best.PF, 1, 2);
+            std::vector<GroupRt> more;
+            for (auto& g : nb) {
+                GroupRt gr;
+                gr.g = g;
+                gr.g.dec = cur.dec;
+                gr.g.exp = cur.exp;
+                try {
+                    prepare_group(plan, gr, (int)gi);
+                } catch (const Error&) {
+                    continue;
+                }
+                more.push_back(std::move(gr));
+            }
+            if (more.empty()) break;
+            std::vector<GroupRt*> mp;
+            for (auto& t : more) mp.push_back(&t);
+            compile_groups(plan, mp);
+            if (k > 1)
+                for (auto& t : more)
+                    for (auto& b : group_planes(plan, t, plan.W, plan.H)) {
+                        if (tall_mem.count((int)b[0])) continue;
+                        auto d = level_dims(plan.W, plan.H, p.nodes[b[0]].level);
+                        int64_t rs = (d.first + 63) / 64 * 64;
+                        tall_mem[(int)b[0]] = {tall_scratch.alloc((size_t)b[1] * b[2]), rs, rs * d.second};
+                    }
+            bool improved = false;
+            for (auto& t : more) {
+                double us = k > 1 ? time_group_us(plan, t, tall_mem, st, reps) : time_group_us(plan, t, sets, st, reps);
+                if (db.is_open()) write_db_line(db, tag, plan, t, us);
+                if (us < best_t) {
+                    best_t = us;
+                    best = t.g;
+                    improved = true;
+                }
+            }
+            for (auto& t : more) unload_group(t);
+            if (!improved) break;
+        }
         plan.sched.groups[gi] = best;
         total_us += best_t / k;
         if (memo) (*memo)[key.str()] = {best, best_t / k};
@@ -377,11 +472,21 @@ void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vecto
         return;
     }
     DeviceScratch scr;
-    std::map<int, ImgRef> mem;
+    std::vector<std::map<int, ImgRef>> mem(1);
+    size_t bytes = 0;
     for (const Node& n : p.nodes) {
         auto d = level_dims(W, H, n.level);
         int64_t rs = (d.first + 63) / 64 * 64;
-        mem[n.id] = {scr.alloc((size_t)rs * d.second * n.channels * 4), rs, rs * d.second};
+        mem[0][n.id] = {scr.alloc((size_t)rs * d.second * n.channels * 4), rs, rs * d.second};
+        bytes += (size_t)rs * d.second * n.channels * 4;
+    }
+    // copies spanning more than the last-level cache (see scratch_sets)
+    const int nsets = (int)std::min<size_t>(8, std::max<size_t>(1, (((size_t)1 << 30) + bytes - 1) / std::max<size_t>(bytes, 1)));
+    for (int c = 1; c < nsets; ++c) {
+        std::map<int, ImgRef> m;
+        for (auto& kv : mem[0])
+            m[kv.first] = {scr.alloc((size_t)kv.second.cs * p.nodes[kv.first].channels * 4), kv.second.rs, kv.second.cs};
+        mem.push_back(std::move(m));
     }
     OwnedStream ost;
     const char* dbp = std::getenv("WT_MEASURE_DB");

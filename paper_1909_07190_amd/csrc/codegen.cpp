@@ -166,10 +166,10 @@ struct Gen {
             if (k >= SX) return reg(p, slot, chp, k - SX, q);                 // type 1
             return memoize(lread(p, slot, chp, own + " + " + I(q)));            // type 2
         }
+        if ((q < 0 && (-q + V - 1) / V > 63) || q / V > 63) return read_far(p, slot, chp, k, q);
         if (q < 0) {
             int d = (-q + V - 1) / V;
             int ep = q + d * V;
-            if (d > 63) fail(WT_E_UNSUPPORTED, "dependence distance exceeds one wavefront; raise V");
             if (k < SX)  // whole read inside the LDS sub-tiles: type 2 for every lane
                 return memoize(lread(p, slot, chp, "max(" + own + " + " + I(q) + ", 0)"));
             std::string cur = reg(p, slot, chp, k - SX, ep);
@@ -211,7 +211,6 @@ struct Gen {
         // q >= V: source to the right (lane t + d, or the next sub-tile)
         int d = q / V;
         int ep = q - d * V;
-        if (d > 63) fail(WT_E_UNSUPPORTED, "dependence distance exceeds one wavefront; raise V");
         if (k < SX) {
             std::string lv = memoize(lread(p, slot, chp, "min(" + own + " + " + I(q) + ", " + I(SX * SUB - 1) + ")"));
             if (k + 1 < SX || SX == g.TX) return lv;  // type 2 (or overlap past the strip)
@@ -239,6 +238,49 @@ struct Gen {
         if (d == 1) return xchg(p, "wt_shift1n(" + cur + ", " + next + ")");
         if (d == 2) return xchg(p, "wt_shift2n(" + cur + ", " + next + ")");
         return xchg(p, "wt_shiftdn(" + cur + ", " + next + ", " + I(d) + ", lane)");
+    }
+
+    // A source 64 or more lanes to the left (Appendix A's lookback across
+    // several sub-tiles: under the right-hyperplane skew the offsets of a
+    // deep group add up along its chains).  With the lane distance
+    // d = 64 j + r, lane t reads lane t - r of sub-tile k - j, and lanes
+    // t < r read lane t - r + 64 of sub-tile k - j - 1; register sub-tiles
+    // exchange across lanes, LDS sub-tiles are indexed directly.  Sub-tiles
+    // left of the strip hold overlap columns, whose values no valid output
+    // depends on; ghost columns (a few lanes wide) cannot stand in for them.
+    std::string read_far(int p, int slot, int chp, int k, int q) {
+        const NodeGeom& pg = G(p);
+        const std::string own = I(k * SUB) + " + lane * " + I(V);
+        const std::string any = "((" + ctype(p) + ")0)";
+        if (q < 0) {
+            const int d = (-q + V - 1) / V, ep = q + d * V, j = d / 64, r = d % 64;
+            const int A = k - j, B = A - 1;
+            if (pg.ghl > 0 && (A < 0 || (r > 0 && B < 0)))
+                fail(WT_E_UNSUPPORTED, "ghost columns do not reach a dependence spanning sub-tiles");
+            if (A < 0) return any;
+            if (A < SX) {  // every source position lies in the LDS sub-tiles
+                if (r == 0) return memoize(lread(p, slot, chp, I(A * SUB) + " + lane * " + I(V) + " + " + I(ep)));
+                return memoize(lread(p, slot, chp, "max(" + own + " + " + I(q) + ", 0)"));
+            }
+            const std::string cur = reg(p, slot, chp, A - SX, ep);
+            if (r == 0) return cur;
+            if (B >= SX) {
+                const std::string prv = reg(p, slot, chp, B - SX, ep);
+                if (r == 1) return xchg(p, "wt_shift1(" + cur + ", " + prv + ")");
+                if (r == 2) return xchg(p, "wt_shift2(" + cur + ", " + prv + ")");
+                return xchg(p, "wt_shiftd(" + cur + ", " + prv + ", " + I(r) + ", lane)");
+            }
+            if (B >= 0) {
+                const std::string pv = memoize(lread(p, slot, chp, I(B * SUB) + " + ((lane - " + I(r) + ") & 63) * " +
+                                                                    I(V) + " + " + I(ep)));
+                return xchg(p, "wt_shiftd_l(" + cur + ", " + pv + ", " + I(r) + ", lane)");
+            }
+            return xchg(p, "wt_shiftd(" + cur + ", " + cur + ", " + I(r) + ", lane)");  // lanes t < r: overlap
+        }
+        // to the right a source is at most 14 columns away (stencil sides are
+        // at most 15 and right-hyperplane tiles read only from the left)
+        fail(WT_E_INTERNAL, "dependence distance to the right exceeds one wavefront");
+        return {};
     }
 
     int src_chan(const NodeGeom& p, int ch_c, int explicit_ch) {
@@ -1015,6 +1057,13 @@ struct Gen {
         kpar = g.TY % 2 == 0 ? par : -1;
         line("{ const int kk = " + kk + ";");
         ind += "    ";
+        // The group's last stage is followed by no sync, and it may read a
+        // loaded node's LDS sub-tile across lanes; the loads below overwrite
+        // such a sub-tile's oldest ring slot, so the previous step's reads
+        // must be ordered before them.
+        bool lds_loads = false;
+        for (auto& n : geo.nodes) lds_loads |= !n.member && has_lds(n);
+        if (lds_loads) line("wt_wave_sync();");
         int li = 0;
         for (auto& n : geo.nodes) {
             if (n.member) continue;

@@ -189,3 +189,18 @@ def integer_gradient() -> dict:
                         "weights": [1.0, 2.0, 1.0], "scale": 0.25}],
             "outputs": ["mag", "box", "f"]}
 
+
+
+def wide_chain(depth: int = 10, taps: int = 15) -> dict:
+    """`depth` horizontal `taps`-wide box-like stencils in a chain, then the
+    chain's end minus half the input.  Under right-hyperplane tiles each
+    stencil shifts its stage by taps // 2 columns, so the last stage reads the
+    input depth * (taps // 2) columns back (70 for the defaults: more than
+    one 64-lane wavefront at one element per lane)."""
+    w = [float(1 + j % 3) for j in range(taps)]
+    stages, src = [], "img"
+    for i in range(depth):
+        stages.append(_stencil(f"s{i}", src, taps, 1, taps // 2, 0, w, 1.0 / sum(w)))
+        src = f"s{i}"
+    stages.append(_pw("out", [src, "img"], "s0 - 0.5 * s1", 1))
+    return {"inputs": [{"name": "img", "channels": 1}], "stages": stages, "outputs": ["out"]}

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_1909_07190_amd as wt
 import synth
 from synth import pipelines as P
 from emu_runner import emulate
@@ -517,3 +518,32 @@ def test_pyramid_folded_batch_emulated():
     outs = emulate_batch(spec, images, nblocks=2, mode="fixed", fixed=fixed, any_width=True)
     for inp, got in zip(images, outs):
         assert_normwise(got["R0"], oracle.evaluate(spec, inp)["R0"], 1e-5, "batched folded pyramid")
+
+
+WIDE = P.wide_chain()
+WIDE_NODES = ",".join(str(i) for i in range(1, 12))
+
+
+@pytest.mark.parametrize("cfg", [
+    "V=1 TX=3 SX=0 TY=5 PF=1 align=1",   # registers only: lanes exchange across two sub-tiles back
+    "V=1 TX=3 SX=1 TY=5 PF=2 align=1",   # the wrapping lanes read an LDS sub-tile
+    "V=1 TX=4 SX=2 TY=4 PF=1 align=1",   # both sub-tiles of some reads in LDS
+    "V=1 TX=3 SX=3 TY=8 PF=1 align=1",   # every sub-tile in LDS
+])
+def test_lookback_across_sub_tiles_emulated(cfg):
+    """The input edge of a ten-stencil chain spans 70 columns under the
+    right-hyperplane skew: more than one wavefront at one element per lane,
+    so lanes read sub-tiles two back (Appendix A's multi-sub-tile lookback)."""
+    img = synth.uniform_image(31, 1, 13, 300)
+    fixed = f"nodes={WIDE_NODES} {cfg}"
+    got, plan = emulate(WIDE, {"img": img}, mode="fixed", fixed=fixed)
+    assert "align=1" in plan.describe()
+    assert_normwise(got["out"], oracle.evaluate(WIDE, {"img": img})["out"], 1e-5, fixed)
+
+
+def test_lookback_source_reads_two_sub_tiles_back():
+    """The generated source for the chain exchanges lanes between sub-tiles
+    k-1 and k-2 (lane distance 70 = 64 + 6)."""
+    src = wt.from_spec(WIDE).plan(300, 13, mode="fixed", fixed=f"nodes={WIDE_NODES} V=1 TX=3 SX=0 TY=5 PF=1 align=1",
+                                  no_device=True, no_compile=True).source(0)
+    assert ", 6, lane)" in src

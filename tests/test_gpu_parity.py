@@ -53,6 +53,26 @@ def test_blur_schedules(fixed, w, h):
     assert_exact(got["by"], oracle.evaluate(BLUR, {"img": dy})["by"], fixed)
 
 
+WIDE = P.wide_chain()
+WIDE_NODES = ",".join(str(i) for i in range(1, 12))
+
+
+@pytest.mark.parametrize("cfg,w,h", [
+    ("V=1 TX=3 SX=0 TY=16 PF=2 align=1", 1500, 130),
+    ("V=1 TX=3 SX=1 TY=8 PF=1 align=1", 777, 41),
+    ("V=1 TX=4 SX=2 TY=5 PF=1 align=1", 640, 23),
+    ("V=1 TX=3 SX=3 TY=8 PF=1 align=1", 301, 17),
+])
+def test_lookback_across_sub_tiles(cfg, w, h):
+    """Right-hyperplane tiles of a ten-stencil chain: the input edge spans
+    70 columns, more than one wavefront at one element per lane."""
+    fixed = f"nodes={WIDE_NODES} {cfg}"
+    _say(f"wide chain {w}x{h} [{fixed}]")
+    img = synth.uniform_image(32, 1, h, w)
+    got, _ = run_gpu(WIDE, {"img": img}, mode="fixed", fixed=fixed)
+    assert_normwise(got["out"], oracle.evaluate(WIDE, {"img": img})["out"], 1e-5, fixed)
+
+
 @pytest.mark.parametrize("w,h", [(1, 1), (3, 2), (5, 7), (64, 1), (1, 64)])
 def test_blur_tiny(w, h):
     _say(f"blur tiny {w}x{h}")
