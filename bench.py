@@ -46,6 +46,7 @@ HEADLINE_MODE = "autotune"  # ranked by the shipped cost network
 # secondary workloads: (channels, height, width, input seed)
 UNSHARP = (3, 2048, 2048, 2)
 HARRIS = (3, 4096, 4096, 3)
+HIST_WORKLOAD = (3, 2048, 2048, 6)  # blur + 256-bin histogram
 # the best unsharp-mask schedule found by sweeps, and the paper's baseline
 SWEPT_UNSHARP = "nodes=1,2,3,4 V=2 TX=1 SX=0 TY=32 PF=2 NT=1"
 OTPTB_UNSHARP = "nodes=1,2,3,4 V=1 TX=1 TY=16 WPB=4 BLK=1"
@@ -428,6 +429,46 @@ def bench_image(args, torch, wt, synth, P, cyc, name):
     return res
 
 
+def bench_histogram(args, torch, wt, synth, P, cyc):
+    """A reduction stage fused with its producer: the 256-bin histogram of
+    the blurred 3x2048x2048 image, counted by the blur's group (the blurred
+    image is never stored) against the unfused pipeline (the blur stored,
+    then read back by the lone histogram kernel)."""
+    dev = torch.device("cuda:0")
+    C, H, W, seed = HIST_WORKLOAD
+    spec = P.blur_histogram(channels=C, bins=256)
+    base = torch.from_numpy(synth.uniform_image(seed, C, H, W)).to(dev)
+    nsets = max(2, min(16, int(1.1e9 // (base.numel() * 4)) + 1))
+    ins = [base.clone() for _ in range(nsets)]
+    outs = [torch.zeros((C, 1, 256), dtype=torch.int32, device=dev) for _ in range(nsets)]
+
+    def leg(mode, model=None):
+        plan = wt.from_spec(spec).plan(W, H, mode=mode, model_path=model)
+        ms = timed(torch, lambda i: plan.run([ins[i % nsets]], [outs[i % nsets]]), args.steps, args.warmup, cyc)
+        return plan, ms, outs[(args.steps - 1) % nsets].clone()
+
+    plan, ms, ref = leg(HEADLINE_MODE, wt.GFX950_COST_MODEL)
+    nbytes = C * H * W * 4 + C * 256 * 4  # the image in, the counts out
+    kname = kernel_name(plan, 0, False) if plan.num_groups == 1 else None
+    res = {"value": H * W / (ms * 1e-3) / 1e6, "ms_per_step": ms, "mode": HEADLINE_MODE,
+           "launches": plan.num_groups, "schedule": plan.describe().strip(), "buffer_sets": nsets,
+           "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "traffic": profile_traffic(kname) if kname else None, "kernel": kname,
+                        "algorithmic_bytes": nbytes},
+           "counted": int(ref.sum().item())}
+    log(f"histogram {HEADLINE_MODE}: {ms * 1e3:.2f} us, {res['roofline']['achieved']:.0f} GB/s "
+        f"({plan.describe().strip()})")
+    if not args.no_extra:
+        pl, lms, got = leg("unfused")
+        res["unfused"] = {"value": H * W / (lms * 1e-3) / 1e6, "ms_per_step": lms, "launches": pl.num_groups,
+                          "vs_scheduled": lms / ms, "counts_equal": bool(torch.equal(got, ref)),
+                          "schedule": pl.describe().strip()}
+        log(f"histogram unfused: {lms * 1e3:.2f} us ({pl.num_groups} launches), counts equal "
+            f"{res['unfused']['counts_equal']}")
+    return res
+
+
 def copy_reference(torch, wt, ins, outs, steps, cyc):
     """The same bytes as the unsharp mask's compulsory traffic (one image in,
     one out) moved by the runtime's copy and by the library's streaming copy
@@ -474,6 +515,8 @@ def main():
         for name in ("unsharp", "harris"):
             secondary[name] = bench_image(args, torch, wt, synth, P, cyc, name)
             torch.cuda.empty_cache()
+        secondary["histogram"] = bench_histogram(args, torch, wt, synth, P, cyc)
+        torch.cuda.empty_cache()
     out = {
         "metric": METRIC, "value": head.pop("value"), "unit": "Mpixels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
@@ -486,6 +529,8 @@ def main():
         out["unsharp_3x2048x2048"] = secondary["unsharp"]
     if "harris" in secondary:
         out["harris_3x4096x4096"] = secondary["harris"]
+    if "histogram" in secondary:
+        out["blur_histogram_3x2048x2048"] = secondary["histogram"]
     print(json.dumps(out), flush=True)
 
 

@@ -134,6 +134,18 @@ wt_status wt_pointwise_typed(wt_pipeline* p, const int* srcs, int nsrc, const ch
  *             odd 2i+1 -> (P(i)+P(i+1))/2, to the next finer level's domain. */
 wt_status wt_resample(wt_pipeline* p, int src, int kind, int* id);
 
+/* Histogram of a stage (a reduction; the paper's Section 7 names such
+ * scatter/reduction stages, as in the bilateral grid, as what its fusion
+ * does not cover).  Per channel, `bins` int32 counts: a value v of `src`
+ * (converted to FP32) falls in bin floor((v - lo) * (bins / (hi - lo))),
+ * computed in FP32 and clamped to 0..bins-1 (values outside [lo, hi) count
+ * in the end bins; NaN counts in bin 0).  Its image is bins x 1 (WT_I32,
+ * the source's channels) and must be a pipeline output; no stage may read
+ * it.  A group that computes `src` accumulates the histogram as it goes, so
+ * `src` itself need not be stored.  bins in 1..4096, lo < hi, both finite;
+ * WT_E_INVALID otherwise. */
+wt_status wt_histogram(wt_pipeline* p, int src, int bins, double lo, double hi, int* id);
+
 /* Marks a node as a pipeline output (outputs are numbered in call order). */
 wt_status wt_output(wt_pipeline* p, int id);
 

@@ -33,6 +33,14 @@ Readings where the paper is silent (it uses interior-only domains):
     sees its value converted exactly.  Integer stages do not take up2
     (a rounding rule for the expansion is not defined) and never read float
     stages.
+  * a histogram stage (a reduction, the kind of stage the paper's Section 7
+    names as outside its fusion, as in the bilateral grid's scatter) counts,
+    per channel, its source's values in `bins` equal bins over [lo, hi):
+    value v goes to bin floor((v - lo) * s), s = bins / (hi - lo), with v,
+    lo and s rounded to FP32 and the subtraction and product done in FP32
+    (the decision's precision is part of the stage's definition), clamped to
+    0..bins-1 (NaN in bin 0).  Its result is [C, 1, bins] int64 counts; no
+    stage reads it.
 
 Every function below is pinned by tests under ``tests/`` (brute force on tiny
 images, closed forms on ramps, steps, impulses and corners, and invariants).
@@ -267,6 +275,23 @@ def pointwise(expr: str, srcs, channels: int, dtype: str = "f32") -> np.ndarray:
     return out
 
 
+def histogram(p: np.ndarray, bins: int, lo: float, hi: float) -> np.ndarray:
+    """Per channel, the counts of p's values in `bins` equal bins over
+    [lo, hi): bin floor((v - lo) * s) with s = bins / (hi - lo), computed in
+    FP32 (v, lo and s rounded to FP32 first), clamped to 0..bins-1; NaN
+    counts in bin 0.  Returns [C, 1, bins] int64."""
+    v = np.asarray(p).astype(np.float32)
+    lo32 = np.float32(lo)
+    s32 = np.float32(bins / (hi - lo))
+    t = (v - lo32) * s32  # float32 operands: each operation rounded to FP32
+    with np.errstate(invalid="ignore"):
+        idx = np.where(t >= 0, np.where(t >= bins, bins - 1, np.floor(np.where(t >= 0, t, 0))), 0).astype(np.int64)
+    out = np.zeros((v.shape[0], 1, bins), dtype=np.int64)
+    for c in range(v.shape[0]):
+        out[c, 0] = np.bincount(idx[c].ravel(), minlength=bins)
+    return out
+
+
 # --------------------------------------------------------------------------
 # Whole pipelines
 # --------------------------------------------------------------------------
@@ -283,6 +308,8 @@ def _levels(spec):
             if lv[st["src"]] < 1:
                 raise ValueError("up2 of a level-0 stage")
             lv[st["name"]] = lv[st["src"]] - 1
+        elif k == "hist":
+            lv[st["name"]] = lv[st["src"]]
         elif k == "pointwise":
             ls = {lv[s] for s in st["srcs"]}
             if len(ls) != 1:
@@ -304,6 +331,8 @@ def evaluate_stage(st, vals, lv, width, height):
                        st["weights"], st["scale"])
     if k == "down2":
         return down2(vals[st["src"]])
+    if k == "hist":
+        return histogram(vals[st["src"]], st["bins"], st["lo"], st["hi"])
     if k == "up2":
         if vals[st["src"]].dtype == np.int64:
             raise ValueError("up2 of an integer stage")

@@ -87,6 +87,8 @@ _sig("wt_stencil", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ct
 _sig("wt_pointwise", ctypes.c_int, ctypes.c_void_p, _c_int_p, ctypes.c_int, ctypes.c_char_p,
      ctypes.c_int, _c_int_p)
 _sig("wt_resample", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p)
+_sig("wt_histogram", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+     _c_int_p)
 _sig("wt_output", ctypes.c_int, ctypes.c_void_p, ctypes.c_int)
 _sig("wt_plan_create", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtSchedOpts), ctypes.c_int,
      ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p))
@@ -176,6 +178,12 @@ class Pipeline:
         self.channels[i.value] = self.channels[src]
         return i.value
 
+    def histogram(self, src, bins, lo, hi) -> int:
+        i = ctypes.c_int()
+        _check(lib.wt_histogram(self._h, src, bins, float(lo), float(hi), ctypes.byref(i)))
+        self.channels[i.value] = self.channels[src]
+        return i.value
+
     def output(self, node: int):
         _check(lib.wt_output(self._h, node))
 
@@ -242,6 +250,8 @@ def from_spec(spec: dict) -> Pipeline:
             i = p.pointwise([p.names[s] for s in st["srcs"]], st["expr"], st["channels"], dt)
         elif k in ("down2", "up2"):
             i = p.resample(p.names[st["src"]], DOWN2 if k == "down2" else UP2)
+        elif k == "hist":
+            i = p.histogram(p.names[st["src"]], st["bins"], st["lo"], st["hi"])
         else:
             raise ValueError(f"unknown stage kind {k!r}")
         p.names[st["name"]] = i

@@ -19,7 +19,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HOST_SOURCES = ["ir.cpp", "geometry.cpp", "codegen.cpp", "sched.cpp", "fusion.cpp",
                 "cost.cpp", "prof.cpp", "autotune.cpp", "batch.cpp", "mlp.cpp", "train_db.cpp", "jit.cpp", "runtime.cpp",
                 "capi.cpp"]
-DEVICE_SOURCES: list[str] = ["mlp.hip", "copyref.hip", "scratch.hip"]
+DEVICE_SOURCES: list[str] = ["mlp.hip", "copyref.hip", "scratch.hip", "histzero.hip"]
 # Packed-FP32 VALU forms are disabled in every HIP compilation.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -139,7 +139,7 @@ std::map<int, ImgRef> scratch_memory(const Plan& plan, DeviceScratch& sc) {
         mem[id] = {sc.alloc(n * 4), plan.W, (int64_t)plan.W * plan.H};
     }
     for (int id : p.outputs) {
-        auto d = level_dims(plan.W, plan.H, p.nodes[id].level);
+        auto d = node_dims(p, id, plan.W, plan.H);
         int64_t rs = (d.first + 63) / 64 * 64;
         mem[id] = {sc.alloc((size_t)rs * d.second * p.nodes[id].channels * 4), rs, rs * d.second};
     }
@@ -178,7 +178,7 @@ std::vector<std::array<int64_t, 3>> group_planes(const Plan& plan, const GroupRt
     std::set<int> seen;
     auto add = [&](int id) {
         if (!seen.insert(id).second) return;
-        auto d = level_dims(W, H, plan.p.nodes[id].level);
+        auto d = node_dims(plan.p, id, W, H);
         int64_t rs = (d.first + 63) / 64 * 64;
         out.push_back({id, rs * d.second * 4, plan.p.nodes[id].channels});
     };
@@ -253,6 +253,8 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         for (int v : cur.dec) key << v << ',';
         key << '|';
         for (int v : cur.exp) key << v << ',';
+        key << '|';
+        for (int v : cur.hst) key << v << ',';
         if (memo) {
             auto hit = memo->find(key.str());
             if (hit != memo->end()) {
@@ -327,6 +329,7 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
             gr.g = g;
             gr.g.dec = cur.dec;  // decimated outputs and expanded inputs stay with the group
             gr.g.exp = cur.exp;
+            gr.g.hst = cur.hst;
             try {
                 prepare_group(plan, gr, (int)gi);
             } catch (const Error&) {
@@ -341,7 +344,7 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
             for (auto& t : trials)
                 for (auto& b : group_planes(plan, t, plan.W, plan.H)) {
                     if (tall_mem.count((int)b[0])) continue;
-                    auto d = level_dims(plan.W, plan.H, p.nodes[b[0]].level);
+                    auto d = node_dims(p, (int)b[0], plan.W, plan.H);
                     int64_t rs = (d.first + 63) / 64 * 64;
                     tall_mem[(int)b[0]] = {tall_scratch.alloc((size_t)b[1] * b[2]), rs, rs * d.second};
                 }
@@ -388,6 +391,7 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
                 gr.g = g;
                 gr.g.dec = cur.dec;
                 gr.g.exp = cur.exp;
+                gr.g.hst = cur.hst;
                 try {
                     prepare_group(plan, gr, (int)gi);
                 } catch (const Error&) {
@@ -403,7 +407,7 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
                 for (auto& t : more)
                     for (auto& b : group_planes(plan, t, plan.W, plan.H)) {
                         if (tall_mem.count((int)b[0])) continue;
-                        auto d = level_dims(plan.W, plan.H, p.nodes[b[0]].level);
+                        auto d = node_dims(p, (int)b[0], plan.W, plan.H);
                         int64_t rs = (d.first + 63) / 64 * 64;
                         tall_mem[(int)b[0]] = {tall_scratch.alloc((size_t)b[1] * b[2]), rs, rs * d.second};
                     }
@@ -475,7 +479,7 @@ void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vecto
     std::vector<std::map<int, ImgRef>> mem(1);
     size_t bytes = 0;
     for (const Node& n : p.nodes) {
-        auto d = level_dims(W, H, n.level);
+        auto d = node_dims(p, n.id, W, H);
         int64_t rs = (d.first + 63) / 64 * 64;
         mem[0][n.id] = {scr.alloc((size_t)rs * d.second * n.channels * 4), rs, rs * d.second};
         bytes += (size_t)rs * d.second * n.channels * 4;

@@ -68,6 +68,13 @@ hipError_t launch_batch_group(const Plan& plan, const BatchState& st, int g, int
     const void* a = static_cast<char*>(st.dargs) + (size_t)g * nimg * sizeof(WtArgsHost);
     const void* starts = static_cast<char*>(st.dargs) + st.args_bytes + (size_t)g * (nimg + 1) * sizeof(int);
     int ni = nimg, tot = st.total[g];
+    for (size_t i = 0; i < gr.liveouts.size(); ++i) {  // histograms accumulate from zero
+        const Node& hn = plan.p.nodes[gr.liveouts[i]];
+        if (hn.kind == Kind::Hist) {
+            hipError_t ez = zero_hist_batch(a, nimg, (int)i, hn.bins, hn.channels, s);
+            if (ez != hipSuccess) return ez;
+        }
+    }
     void* params[] = {&a, &starts, &ni, &tot};
     int threads = gr.resample ? 256 : 64 * gr.g.WPB;
     return hipModuleLaunchKernel(gr.fn_batch, st.grid[g], 1, 1, threads, 1, 1, 0, s, params, nullptr);
@@ -129,7 +136,7 @@ void check_batch(const Plan& plan, int nimg, const wt_image* in, const wt_image*
         for (int k = 0; k < nout; ++k) {
             const wt_image& im = out[(size_t)i * nout + k];
             int id = p.outputs[k];
-            auto d = level_dims(W, H, p.nodes[id].level);
+            auto d = node_dims(p, id, W, H);
             mem[i][id] = check_image(im, p.nodes[id], d.first, d.second,
                                      "batch image " + std::to_string(i) + " output " + std::to_string(k));
         }

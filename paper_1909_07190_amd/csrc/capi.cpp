@@ -50,6 +50,7 @@ wt::Node& new_node(wt_pipeline* p, wt::Kind k) {
 
 void check_src(const wt_pipeline* p, int src) {
     if (src < 0 || src >= (int)p->p.nodes.size()) wt::fail(WT_E_INVALID, "unknown source node " + std::to_string(src));
+    if (p->p.nodes[src].kind == wt::Kind::Hist) wt::fail(WT_E_UNSUPPORTED, "a histogram cannot be read by a stage");
 }
 }  // namespace
 
@@ -288,10 +289,32 @@ wt_status wt_resample(wt_pipeline* p, int src, int kind, int* id) {
     });
 }
 
+wt_status wt_histogram(wt_pipeline* p, int src, int bins, double lo, double hi, int* id) {
+    return guard([&] {
+        if (!p || !id) wt::fail(WT_E_INVALID, "null argument");
+        check_src(p, src);
+        if (bins < 1 || bins > 4096) wt::fail(WT_E_INVALID, "histogram bins must be in 1..4096");
+        if (!std::isfinite(lo) || !std::isfinite(hi) || !(lo < hi)) wt::fail(WT_E_INVALID, "histogram needs lo < hi");
+        const wt::Node s = p->p.nodes[src];
+        wt::Node& n = new_node(p, wt::Kind::Hist);
+        n.srcs = {src};
+        n.channels = s.channels;
+        n.level = s.level;
+        n.dtype = WT_I32;
+        n.bins = bins;
+        n.hlo = lo;
+        n.hhi = hi;
+        n.bound = 2147483647.0;
+        n.rlo = 0;
+        n.rhi = 2147483647.0;
+        *id = n.id;
+    });
+}
+
 wt_status wt_output(wt_pipeline* p, int id) {
     return guard([&] {
         if (!p) wt::fail(WT_E_INVALID, "null pipeline");
-        check_src(p, id);
+        if (id < 0 || id >= (int)p->p.nodes.size()) wt::fail(WT_E_INVALID, "unknown node " + std::to_string(id));
         if (p->p.nodes[id].kind == wt::Kind::Input) wt::fail(WT_E_INVALID, "an input cannot be an output");
         if (p->p.is_output(id)) wt::fail(WT_E_INVALID, "node already marked as output");
         p->p.outputs.push_back(id);

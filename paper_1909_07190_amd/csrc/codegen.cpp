@@ -847,6 +847,55 @@ struct Gen {
         line("}");
     }
 
+    // ------------------------------------------------------- histograms --
+    // Each wave counts into bins of its own in LDS (hb: every histogram of
+    // the group, per channel slot, one after another); the tile's counts are
+    // added to the device-wide output once, at its end.
+    int hist_off(size_t k) const {
+        int o = 0;
+        for (size_t i = 0; i < k; ++i) o += P.nodes[geo.hist[i].first].bins * G(geo.hist[i].second).nch;
+        return o;
+    }
+    int hist_oi(size_t k) const { return (int)(geo.liveouts.size() + geo.dec.size() + k); }
+    // Counts the values of member n at row R that belong to this tile's
+    // output range and to the image.
+    void emit_hist(size_t k, const NodeGeom& n, int ch, int kk, const std::string& arr, const std::string& R) {
+        const Node& h = P.nodes[geo.hist[k].first];
+        const std::string lo = flit((double)(float)h.hlo), sc = flit((double)(float)(h.bins / (h.hhi - h.hlo)));
+        const std::string base = "hb + " + I(hist_off(k) + ch * h.bins);
+        line("{ const int jb = " + I(kk * SUB) + " + lane * " + I(V) + ";");
+        line("  const int xp = x0 + " + I(n.skew) + " + jb;");
+        line("  const bool okh = " + R + " >= y0 && " + R + " < kend && " + R + " < H && jb >= " + I(geo.S0) +
+             " && jb < " + I(geo.S0 + geo.X) + ";");
+        for (int e = 0; e < V; ++e) {
+            // the value as the group holds it (FP16 rows are rounded)
+            std::string v = arr + "[" + I(e) + "]";
+            if (isint(n.id)) v = "(float)" + v;
+            else if (n.half) v = "(float)(_Float16)" + v;
+            line("  if (okh && xp + " + I(e) + " >= 0 && xp + " + I(e) + " < W) wt_count_lds(" + base +
+                 " + wt_hist_bin(" + v + ", " + lo + ", " + sc + ", " + I(h.bins) + "), 1u);");
+        }
+        line("}");
+    }
+    void emit_hist_clear() {
+        if (geo.hist.empty()) return;
+        line("wt_wave_sync();");
+        line("for (int i = lane; i < " + I(hist_off(geo.hist.size())) + "; i += 64) hb[i] = 0u;");
+        line("wt_wave_sync();");
+    }
+    void emit_hist_flush() {
+        if (geo.hist.empty()) return;
+        line("wt_wave_sync();");
+        for (size_t k = 0; k < geo.hist.size(); ++k) {
+            const Node& h = P.nodes[geo.hist[k].first];
+            const int oi = hist_oi(k);
+            for (int ch = 0; ch < G(geo.hist[k].second).nch; ++ch)
+                line("for (int i = lane; i < " + I(h.bins) + "; i += 64) { const unsigned int c = hb[" +
+                     I(hist_off(k) + ch * h.bins) + " + i]; if (c) wt_count_global((unsigned int*)A.dst[" + I(oi) +
+                     "] + " + chan_off(geo.hist[k].second, true, oi, ch) + " + i, c); }");
+        }
+    }
+
     // ----------------------------------------------------- clamp fix-ups --
     // Positions of a stage row outside [0, W) take the value at x = 0 / W-1
     // (per-stage clamp to edge); only border waves execute this.
@@ -1016,6 +1065,8 @@ struct Gen {
                 if (oi >= 0 && stores) emit_store(oi, n, ch, k, arr, R);
                 for (size_t d = 0; d < geo.dec.size(); ++d)
                     if (stores && geo.dec[d].second == n.id) emit_dec_store(d, n, ch, k, arr, R);
+                for (size_t h = 0; h < geo.hist.size(); ++h)
+                    if (stores && geo.hist[h].second == n.id) emit_hist(h, n, ch, k, arr, R);
             }
         }
         if (n.consumed && SX > 0) line("wt_wave_sync();");
@@ -1152,6 +1203,11 @@ struct Gen {
     }
 
     void lds_decl() {
+        if (!geo.hist.empty()) {
+            const int nb = hist_off(geo.hist.size());
+            line("__shared__ unsigned int wt_hb[" + I(nb * g.WPB) + "];");
+            line("unsigned int* hb = wt_hb + (threadIdx.x >> 6) * " + I(nb) + ";");
+        }
         if (geo.lds_bytes <= 0) return;
         line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
         line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
@@ -1204,11 +1260,13 @@ struct Gen {
                      I(dec_size(k)) + " * (" + chan_off(src.id, true, oi, ch) + "), 0, (int)((long long)((H + 1) >> 1) * A.dst_rs[" +
                      I(oi) + "] * " + I(dec_size(k)) + "), WT_RSRC_W3);");
         }
+        emit_hist_clear();
         line("if (!bx) {");
         body(false);
         line("} else {");
         body(true);
         line("}");
+        emit_hist_flush();
     }
 
     // Single-image kernel: one wave per tile.
@@ -1532,10 +1590,11 @@ int block_tile_w(const GroupSched& g) { return 64 * g.V * g.TX; }
 
 GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const GroupGeom& geo,
                                    const std::string& kname) {
-    if ((int)geo.loaded.size() > 16 || (int)(geo.liveouts.size() + geo.dec.size()) > 16)
+    if ((int)geo.loaded.size() > 16 || (int)(geo.liveouts.size() + geo.dec.size() + geo.hist.size()) > 16)
         fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
     if (g.BLK) {
         if (!geo.dec.empty() || !g.exp.empty()) fail(WT_E_UNSUPPORTED, "fused resampling in a one-tile-per-workgroup group");
+        if (!geo.hist.empty()) fail(WT_E_UNSUPPORTED, "histogram in a one-tile-per-workgroup group");
         BlockGen b(p, g, geo);
         std::string single = b.single(kname);
         std::string batch = b.batch(kname);
@@ -1560,9 +1619,57 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const
 // (tiles_x, tiles_y, channels) grid; the batched kernel loops its workgroups
 // over the blocks of all images.
 void resample_block(const Pipeline& p, const GroupSched& g, int& bw, int& bh) {
-    bool up = p.nodes[g.nodes[0]].kind == Kind::Up2;
-    bw = up ? 128 : 64;
-    bh = up ? 8 : 4;
+    const Kind k = p.nodes[g.nodes[0]].kind;
+    bw = k == Kind::Up2 ? 128 : 64;
+    bh = k == Kind::Up2 ? 8 : k == Kind::Hist ? 64 : 4;
+}
+
+// A histogram of a stage held in memory (its source not computed by a fused
+// group): a workgroup counts a 64 x 64 block of one channel into LDS bins
+// (each thread 16 rows of one column), then adds its non-zero bins to the
+// output.  Same launch shape as the resampling kernels.
+GroupSources generate_hist_source(const Pipeline& p, const GroupSched& g, const std::string& kname, bool src_half) {
+    const Node& n = p.nodes[g.nodes[0]];
+    const Node& sn = p.nodes[n.srcs[0]];
+    const std::string st = sn.is_int() ? dtype_ctype(sn.dtype) : src_half ? "_Float16" : "float";
+    const std::string lo = flit((double)(float)n.hlo), sc = flit((double)(float)(n.bins / (n.hhi - n.hlo)));
+    std::ostringstream o;
+    o << "static __device__ __forceinline__ void " << kname << "_body(const WtArgs& A, int bxi, int byi, int c) {\n";
+    o << "    __shared__ unsigned int hb[" << n.bins << "];\n";
+    o << "    __syncthreads();\n";
+    o << "    for (int i = threadIdx.x; i < " << n.bins << "; i += 256) hb[i] = 0u;\n";
+    o << "    __syncthreads();\n";
+    o << "    const " << st << "* s = (const " << st << "*)A.src[0] + (long long)c * A.src_cs[0];\n";
+    o << "    const int x = bxi * 64 + (threadIdx.x & 63);\n";
+    o << "    if (x < A.W)\n";
+    o << "        for (int r = 0; r < 16; ++r) {\n";
+    o << "            const int y = byi * 64 + (threadIdx.x >> 6) + 4 * r;\n";
+    o << "            if (y < A.H) wt_count_lds(hb + wt_hist_bin((float)s[(long long)y * A.src_rs[0] + x], " << lo << ", "
+      << sc << ", " << n.bins << "), 1u);\n";
+    o << "        }\n";
+    o << "    __syncthreads();\n";
+    o << "    unsigned int* d = (unsigned int*)A.dst[0] + (long long)c * A.dst_cs[0];\n";
+    o << "    for (int i = threadIdx.x; i < " << n.bins << "; i += 256) if (hb[i]) wt_count_global(d + i, hb[i]);\n";
+    o << "}\n";
+    const std::string body = o.str();
+    o.str("");
+    o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname << "(const WtArgs A) {\n";
+    o << "    " << kname << "_body(A, blockIdx.x, blockIdx.y, blockIdx.z);\n";
+    o << "}\n";
+    const std::string single = o.str();
+    o.str("");
+    o << "extern \"C\" __global__ void __launch_bounds__(256) " << kname
+      << "_batch(const WtArgs* __restrict__ AB, const int* __restrict__ start, const int nimg, const int total) {\n";
+    o << "    for (int t = blockIdx.x; t < total; t += gridDim.x) {\n";
+    o << "        int lo = 0, hi = nimg;\n";
+    o << "        while (hi - lo > 1) { const int mid = (lo + hi) >> 1; if (start[mid] <= t) lo = mid; else hi = mid; }\n";
+    o << "        const WtArgs A = AB[lo];\n";
+    o << "        const int l = t - start[lo];\n";
+    o << "        const int r = l / A.tiles_x;\n";
+    o << "        " << kname << "_body(A, l % A.tiles_x, r % A.tiles_y, r / A.tiles_y);\n";
+    o << "    }\n";
+    o << "}\n";
+    return GroupSources{device_prelude(), body, single, o.str()};
 }
 
 GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g, const std::string& kname,

@@ -309,7 +309,7 @@ double resample_pred_us(const Pipeline& p, int id, const Machine& m, int W, int 
         sh = (sh + 1) / 2;
     }
     double in_b = (double)n.channels * (n.kind == Kind::Down2 ? (double)lw * lh : (double)sw * sh) * (half_in ? 2 : 4);
-    double out_b = (double)n.channels * lw * lh * (half_out ? 2 : 4);
+    double out_b = (double)n.channels * (n.kind == Kind::Hist ? (double)n.bins : (double)lw * lh) * (half_out ? 2 : 4);
     return (in_b + out_b) / (m.hbm_bw * m.hbm_efficiency) * 1e6 + m.launch_us;
 }
 

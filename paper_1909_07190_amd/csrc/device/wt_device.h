@@ -166,6 +166,21 @@ WT_DEV float wt_h(float v) { return (float)(_Float16)v; }
 
 WT_DEV int wt_clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Histogram bin of value v: floor((v - lo) * scale) in FP32, clamped to
+// 0..nb-1 (NaN and values below lo count in bin 0, values at or past the
+// top in bin nb-1).
+WT_DEV int wt_hist_bin(float v, float lo, float scale, int nb) {
+    const float t = (v - lo) * scale;
+    return !(t >= 0.0f) ? 0 : (t >= (float)nb ? nb - 1 : (int)t);
+}
+// Counter increments: a wave's own LDS bins, and the device-wide output
+WT_DEV void wt_count_lds(unsigned int* p, unsigned int v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+WT_DEV void wt_count_global(unsigned int* p, unsigned int v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Integer stage arithmetic (exact in 32 bits: the library bounds every sum).
 // Quotient rounded half up: floor((a + d/2) / d) for d >= 1.
 WT_DEV int wt_rdiv(int a, int d) {

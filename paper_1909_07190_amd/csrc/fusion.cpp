@@ -66,8 +66,8 @@ struct Search {
             flevel[i] = n.level;
             if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise) {
                 fusable[i] = true;
-            } else if (n.kind == Kind::Down2) {
-                // written decimated by the group of its source
+            } else if (n.kind == Kind::Down2 || n.kind == Kind::Hist) {
+                // written decimated, or counted, by the group of its source
                 resample_bits |= 1ull << i;
                 const Node& src = p.nodes[n.srcs[0]];
                 fusable[i] = src.kind == Kind::Stencil || src.kind == Kind::Pointwise;
@@ -105,7 +105,8 @@ struct Search {
     int group_size(uint64_t g) const {
         uint64_t down = 0;
         for (size_t i = 0; i < stages.size(); ++i)
-            if ((g >> i & 1) && p.nodes[stages[i]].kind == Kind::Down2) down |= 1ull << i;
+            if ((g >> i & 1) && (p.nodes[stages[i]].kind == Kind::Down2 || p.nodes[stages[i]].kind == Kind::Hist))
+                down |= 1ull << i;
         return __builtin_popcountll(g & ~down);
     }
     // A multi-stage group may hold a down2 only with its source, and an up2
@@ -118,7 +119,7 @@ struct Search {
             if (!fusable[i]) return false;
             const Node& n = p.nodes[stages[i]];
             if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise) body = true;
-            if (n.kind == Kind::Down2 || n.kind == Kind::Up2) {
+            if (n.kind == Kind::Down2 || n.kind == Kind::Up2 || n.kind == Kind::Hist) {
                 auto it = pos.find(n.srcs[0]);
                 if (it == pos.end() || !(g >> it->second & 1)) return false;
             }
@@ -131,13 +132,17 @@ struct Search {
         auto it = gcache.find(g);
         if (it != gcache.end()) return it->second;
         ++groups_costed;
-        std::vector<int> nodes, dec;
-        for (size_t i = 0; i < stages.size(); ++i)
-            if (g >> i & 1) (p.nodes[stages[i]].kind == Kind::Down2 && __builtin_popcountll(g) > 1 ? dec : nodes)
-                                .push_back(stages[i]);
+        std::vector<int> nodes, dec, hst;
+        for (size_t i = 0; i < stages.size(); ++i) {
+            if (!(g >> i & 1)) continue;
+            const Kind k = p.nodes[stages[i]].kind;
+            const bool multi = __builtin_popcountll(g) > 1;
+            (multi && k == Kind::Down2 ? dec : multi && k == Kind::Hist ? hst : nodes).push_back(stages[i]);
+        }
         GroupSched base;
         base.nodes = nodes;
         base.dec = dec;
+        base.hst = hst;
         base.fp16 = r.fp16;
         if (!admissible(g)) {
             auto res = std::make_pair((double)INFINITY, base);
@@ -184,6 +189,7 @@ struct Search {
                     best = sc.g;
                 }
         }
+        best.hst = hst;
         auto res = std::make_pair(best_pred, best);
         gcache[g] = res;
         return res;

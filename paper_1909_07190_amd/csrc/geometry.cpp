@@ -36,6 +36,10 @@ bool is_resample_group(const Pipeline& p, const GroupSched& g) {
     return k == Kind::Down2 || k == Kind::Up2;
 }
 
+bool is_hist_group(const Pipeline& p, const GroupSched& g) {
+    return g.nodes.size() == 1 && p.nodes[g.nodes[0]].kind == Kind::Hist;
+}
+
 static int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
@@ -51,6 +55,7 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
     GroupGeom geo;
     std::set<int> mem(g.nodes.begin(), g.nodes.end());
     std::set<int> dec(g.dec.begin(), g.dec.end());
+    std::set<int> hst(g.hst.begin(), g.hst.end());
     int level = p.nodes[g.nodes[0]].level;
     for (size_t i = 0; i < g.nodes.size(); ++i) {
         const Node& n = p.nodes[g.nodes[i]];
@@ -89,15 +94,24 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         if (!mem.count(s)) fail(WT_E_INVALID, "dec node " + std::to_string(d) + " decimates a non-member");
         geo.dec.push_back({d, s});
     }
+    for (int h : g.hst) {
+        if (h < 0 || h >= (int)p.nodes.size() || p.nodes[h].kind != Kind::Hist)
+            fail(WT_E_INVALID, "hst names a node that is not a histogram stage");
+        int s = p.nodes[h].srcs[0];
+        if (!mem.count(s)) fail(WT_E_INVALID, "hst node " + std::to_string(h) + " counts a non-member");
+        geo.hist.push_back({h, s});
+    }
     for (int m : g.nodes) {
         bool lo = p.is_output(m);
         for (int c : cons[m])
-            if (!mem.count(c) && !dec.count(c)) lo = true;
+            if (!mem.count(c) && !dec.count(c) && !hst.count(c)) lo = true;
         if (lo) geo.liveouts.push_back(m);
     }
     geo.outs = geo.liveouts;
     for (auto& ds : geo.dec)
         if (std::find(geo.outs.begin(), geo.outs.end(), ds.second) == geo.outs.end()) geo.outs.push_back(ds.second);
+    for (auto& hs : geo.hist)
+        if (std::find(geo.outs.begin(), geo.outs.end(), hs.second) == geo.outs.end()) geo.outs.push_back(hs.second);
     std::sort(geo.outs.begin(), geo.outs.end());
     if (geo.outs.empty()) fail(WT_E_INVALID, "group has no live-out");
 
@@ -184,7 +198,10 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         if (!ng.member || ng.liveout) continue;
         bool uses = false, only_even = true;
         for (int c : cons[ng.id]) {
-            if (dec.count(c)) {
+            if (hst.count(c)) {
+                uses = true;
+                only_even = false;
+            } else if (dec.count(c)) {
                 uses = true;
             } else if (mem.count(c)) {
                 uses = true;
@@ -334,6 +351,10 @@ std::string describe_group(const GroupSched& g) {
         os << " exp=";
         for (size_t i = 0; i < g.exp.size(); ++i) os << (i ? "," : "") << g.exp[i];
     }
+    if (!g.hst.empty()) {
+        os << " hst=";
+        for (size_t i = 0; i < g.hst.size(); ++i) os << (i ? "," : "") << g.hst[i];
+    }
     return os.str();
 }
 
@@ -371,10 +392,11 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
                 else if (k == "ORD") g.ORD = std::stoi(v);
                 else if (k == "BLK") g.BLK = std::stoi(v);
                 else if (k == "GH") g.GH = std::stoi(v);
-                else if (k == "dec" || k == "exp") {
+                else if (k == "dec" || k == "exp" || k == "hst") {
                     std::istringstream vs(v);
                     std::string n;
-                    while (std::getline(vs, n, ',')) (k == "dec" ? g.dec : g.exp).push_back(std::stoi(n));
+                    while (std::getline(vs, n, ','))
+                        (k == "dec" ? g.dec : k == "exp" ? g.exp : g.hst).push_back(std::stoi(n));
                 }
                 else if (k == "NT") g.NT = std::stoi(v);
                 else fail(WT_E_INVALID, "unknown schedule key '" + k + "'");
@@ -394,6 +416,10 @@ Schedule parse_schedule(const std::string& text, const Pipeline& p, bool partial
         for (int d : g.dec) {  // a decimated down2 is produced by this group
             if (d < 0 || d >= (int)p.nodes.size()) fail(WT_E_INVALID, "dec names an unknown node");
             if (!seen.insert(d).second) fail(WT_E_INVALID, "node " + std::to_string(d) + " in two groups");
+        }
+        for (int h : g.hst) {  // an accumulated histogram is produced by this group
+            if (h < 0 || h >= (int)p.nodes.size()) fail(WT_E_INVALID, "hst names an unknown node");
+            if (!seen.insert(h).second) fail(WT_E_INVALID, "node " + std::to_string(h) + " in two groups");
         }
         for (int u : g.exp) expanded.insert(u);  // may be expanded by several groups
         s.groups.push_back(g);

@@ -33,6 +33,12 @@ std::pair<int, int> level_dims(int W, int H, int level) {
     return {W, H};
 }
 
+std::pair<int, int> node_dims(const Pipeline& p, int id, int W, int H) {
+    const Node& n = p.nodes[id];
+    if (n.kind == Kind::Hist) return {n.bins, 1};
+    return level_dims(W, H, n.level);
+}
+
 namespace {
 
 int64_t round_up64(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
@@ -181,6 +187,8 @@ bool same_grouping(const Schedule& a, const Schedule& b) {
             for (int n : g.dec) os << n << ',';
             os << '|';
             for (int n : g.exp) os << n << ',';
+            os << '|';
+            for (int n : g.hst) os << n << ',';
             k.push_back(os.str());
         }
         std::sort(k.begin(), k.end());
@@ -310,7 +318,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
 // Geometry, memory dtypes and generated source of group `gi` of a plan.
 void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     const Pipeline& p = plan.p;
-    gr.resample = is_resample_group(p, gr.g);
+    gr.resample = is_resample_group(p, gr.g) || is_hist_group(p, gr.g);
     int lvl = p.nodes[gr.g.nodes[0]].level;
     auto d = level_dims(plan.W, plan.H, lvl);
     gr.W = d.first;
@@ -327,8 +335,13 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
         gr.Hs = sd.second;
         gr.loaded = {n.srcs[0]};
         gr.liveouts = {n.id};
-        name_sources(gr, generate_resample_source(p, gr.g, kNamePlaceholder, half_mem(n.srcs[0]), half_mem(n.id)),
-                     gi);
+        if (n.kind == Kind::Hist) {
+            if (!p.is_output(n.id)) fail(WT_E_INVALID, "histogram node " + std::to_string(n.id) + " is not an output");
+            name_sources(gr, generate_hist_source(p, gr.g, kNamePlaceholder, half_mem(n.srcs[0])), gi);
+        } else {
+            name_sources(gr, generate_resample_source(p, gr.g, kNamePlaceholder, half_mem(n.srcs[0]), half_mem(n.id)),
+                         gi);
+        }
         gr.mem_half_in = {half_mem(n.srcs[0])};
         gr.mem_half_out = {half_mem(n.id)};
         int bw, bh;
@@ -354,6 +367,11 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     for (auto& ds : gr.geo.dec) {  // decimated outputs follow the live-outs
         gr.liveouts.push_back(ds.first);
         gr.mem_half_out.push_back(half_mem(ds.first));
+    }
+    for (auto& hs : gr.geo.hist) {  // then accumulated histograms
+        if (!p.is_output(hs.first)) fail(WT_E_INVALID, "histogram node " + std::to_string(hs.first) + " is not an output");
+        gr.liveouts.push_back(hs.first);
+        gr.mem_half_out.push_back(false);
     }
     name_sources(gr, generate_group_source(p, gr.g, gr.geo, kNamePlaceholder), gi);
     int amin = 1 << 30, amax = 0;
@@ -491,7 +509,8 @@ ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const std::s
 void check_store_planes(const Plan& plan, const GroupRt& gr, const WtArgsHost& a, int H) {
     // stores address a plane with 32-bit byte offsets (buffer stores)
     for (size_t i = 0; i < gr.liveouts.size(); ++i)
-        if ((double)a.dst_rs[i] * H * node_esize(plan.p, gr.liveouts[i], gr.mem_half_out[i]) >= 2147483647.0)
+        if (plan.p.nodes[gr.liveouts[i]].kind != Kind::Hist &&
+            (double)a.dst_rs[i] * H * node_esize(plan.p, gr.liveouts[i], gr.mem_half_out[i]) >= 2147483647.0)
             fail(WT_E_UNSUPPORTED, "an output plane of 2 GiB or more");
 }
 
@@ -522,7 +541,7 @@ void run_plan(Plan& plan, const wt_image* in, int nin, const wt_image* out, int 
         mem[p.inputs[i]] = check_image(in[i], p.nodes[p.inputs[i]], plan.W, plan.H, "input " + std::to_string(i));
     for (int i = 0; i < nout; ++i) {
         int id = p.outputs[i];
-        auto d = level_dims(plan.W, plan.H, p.nodes[id].level);
+        auto d = node_dims(p, id, plan.W, plan.H);
         ImgRef r = check_image(out[i], p.nodes[id], d.first, d.second, "output " + std::to_string(i));
         for (auto& kv : mem)
             if (kv.second.ptr == r.ptr) fail(WT_E_INVALID, "output " + std::to_string(i) + " aliases another image");
@@ -549,7 +568,7 @@ void fill_args(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRef>&
     for (size_t i = 0; i < gr.liveouts.size(); ++i) {
         const ImgRef& r = mem.at(gr.liveouts[i]);
         bool decimated = std::find(gr.g.dec.begin(), gr.g.dec.end(), gr.liveouts[i]) != gr.g.dec.end();
-        if (!gr.resample && !decimated && p.is_output(gr.liveouts[i]))
+        if (!gr.resample && !decimated && p.is_output(gr.liveouts[i]) && p.nodes[gr.liveouts[i]].kind != Kind::Hist)
             check_align(r, gr.g.V, node_esize(p, gr.liveouts[i], false), tag + " output node " + std::to_string(gr.liveouts[i]));
         a.dst[i] = const_cast<void*>(r.ptr);
         a.dst_rs[i] = r.rs;
@@ -569,6 +588,10 @@ void launch_group(const Plan& plan, const GroupRt& gr, const std::map<int, ImgRe
     a.tiles_x = gr.tiles_x;
     a.tiles_y = gr.tiles_y;
     a.nwaves = gr.nwaves;
+    for (size_t i = 0; i < gr.liveouts.size(); ++i) {  // histograms accumulate from zero
+        const Node& hn = p.nodes[gr.liveouts[i]];
+        if (hn.kind == Kind::Hist) hip_check(zero_hist(a.dst[i], a.dst_cs[i], hn.bins, hn.channels, st), "zero_hist");
+    }
     void* params[] = {&a};
     hipError_t e;
     if (gr.resample) {

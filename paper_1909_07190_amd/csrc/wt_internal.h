@@ -39,7 +39,7 @@ double expr_bound(const Expr& e, const std::vector<double>& src_bounds);
 bool expr_has_explicit_channel(const Expr& e);
 int expr_max_channel(const Expr& e, int src);
 
-enum class Kind { Input, Stencil, Pointwise, Down2, Up2 };
+enum class Kind { Input, Stencil, Pointwise, Down2, Up2, Hist };
 
 // Element types (wt_dtype): integer stages compute exactly in 32-bit
 // integers and saturate to their type's range.
@@ -73,6 +73,10 @@ struct Node {
     std::vector<long long> iweights;
     long long divisor = 1;
     double rlo = 0, rhi = 0;     // integer stages: value interval (after saturation)
+    // histogram (a reduction): per channel, `bins` int32 counts of the
+    // source's values over [hlo, hhi); its image is bins x 1
+    int bins = 0;
+    double hlo = 0, hhi = 1;
     bool is_int() const { return is_int_dtype(dtype); }
 };
 
@@ -124,6 +128,8 @@ struct GroupSched {
                              // rows and columns of a member, stored decimated
     std::vector<int> exp;    // up2 stages this group reads by expanding their
                              // coarse source on the fly (never materialised)
+    std::vector<int> hst;    // histogram stages this group accumulates from a
+                             // member's values as it computes them
     int BLK = 0;             // 1: one tile per workgroup, stages in LDS with
                              // workgroup barriers between them (the paper's
                              // OTPTB baseline); tile (64*V*TX) x TY
@@ -136,6 +142,8 @@ struct GroupSched {
 };
 int block_tile_w(const GroupSched& g);  // output columns of a BLK tile
 bool is_resample_group(const Pipeline& p, const GroupSched& g);
+// a lone histogram stage (its source read from memory)
+bool is_hist_group(const Pipeline& p, const GroupSched& g);
 
 struct Schedule { std::vector<GroupSched> groups; };
 
@@ -185,7 +193,9 @@ struct GroupGeom {
     std::vector<int> loaded, liveouts;
     std::vector<std::pair<int, int>> dec;  // (down2 node, member it decimates)
     std::vector<int> outs;          // nodes needed over the tile's output range:
-                                    // live-outs and decimated members
+                                    // live-outs, decimated members and the
+                                    // sources of accumulated histograms
+    std::vector<std::pair<int, int>> hist;  // (histogram node, member it counts)
 };
 GroupGeom group_geometry(const Pipeline& p, const GroupSched& g);
 
@@ -238,8 +248,11 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g,
                                    const GroupGeom& geo, const std::string& kname);
 GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g,
                                       const std::string& kname, bool src_half, bool dst_half);
+// A lone histogram stage: counts its source read from memory.
+GroupSources generate_hist_source(const Pipeline& p, const GroupSched& g, const std::string& kname, bool src_half);
 // Output pixels one 256-thread workgroup of a resampling kernel covers:
-// down2 64 x 4 (a pixel per thread), up2 128 x 8 (a 2x2 quad per thread).
+// down2 64 x 4 (a pixel per thread), up2 128 x 8 (a 2x2 quad per thread);
+// source pixels of a lone histogram's workgroup: 64 x 64.
 void resample_block(const Pipeline& p, const GroupSched& g, int& bw, int& bh);
 std::string device_prelude();
 

@@ -139,6 +139,14 @@ inline int node_esize(const Pipeline& p, int id, bool half) {
     return p.nodes[id].is_int() ? dtype_size(p.nodes[id].dtype) : (half ? 2 : 4);
 }
 std::pair<int, int> level_dims(int W, int H, int level);
+// a node's image size for a W x H pipeline: its level's, or bins x 1 for a
+// histogram
+std::pair<int, int> node_dims(const Pipeline& p, int id, int W, int H);
+// Clears histogram outputs (int32 counts) before the group that accumulates
+// them: `planes` planes of n counts, cs elements apart; the batched form
+// takes output `d` of each of the nimg entries of a device argument table.
+hipError_t zero_hist(void* base, long long cs, int n, int planes, hipStream_t s);
+hipError_t zero_hist_batch(const void* table, int nimg, int d, int n, int planes, hipStream_t s);
 void prepare_group(const Plan& plan, GroupRt& gr, int gi);
 void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch = false);
 void unload_group(GroupRt& gr);

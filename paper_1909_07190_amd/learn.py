@@ -148,14 +148,18 @@ EXHAUSTIVE_GRID = ("V=4 TX=1 SX=0 TY=16 PF=2", "V=4 TX=1 SX=0 TY=32 PF=2", "V=2 
                    "V=1 TX=4 SX=2 TY=16 PF=1", "V=4 TX=1 SX=1 TY=16 PF=2")
 
 
-def exhaustive_schedule(dag, pipe, width, height, grid=EXHAUSTIVE_GRID, max_size=10, reps=20):
+def exhaustive_schedule(dag, pipe, width, height, grid=EXHAUSTIVE_GRID, max_size=10, reps=20, log=None):
     """Measures every admissible group (and every stage alone) under every
     configuration of `grid`, then assembles the fastest schedule from the
     measurements (a dynamic program over down-closed stage sets); returns
     (total microseconds, schedule text, timings taken)."""
     groups = [(i,) for i in dag.stages if dag.fusable(i)] + all_groups(dag, max_size)
     texts = [_group_text(list(g), cfg) for g in groups for cfg in grid]
-    times = measure_groups(pipe, texts, width, height, reps=reps, tag="exhaustive")
+    times = []
+    for c in range(0, len(texts), 96):  # in chunks, reporting progress
+        times += measure_groups(pipe, texts[c:c + 96], width, height, reps=reps, tag="exhaustive")
+        if log:
+            log(f"exhaustive: {len(times)} of {len(texts)} candidates timed")
     rows = [{"group": t, "measured_us": us} for t, us in zip(texts, times) if math.isfinite(us)]
     res_us = {}
     for i in dag.stages:
@@ -514,7 +518,11 @@ def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, 
             "mlp_autotune": lambda: pipe.plan(width, height, mode="autotune", autotune_topk=autotune_topk,
                                               model_path=model_path),
         }
-        plans = {m: make[m]() for m in modes if m in make}
+        plans = {}
+        for m in modes:
+            if m in make:
+                log(f"{tag}: planning {m}")
+                plans[m] = make[m]()
         drows = [r for r in rows if r["pipeline"] == tag]
         if drows and "best_measured" in modes:
             res_us = {}
@@ -527,7 +535,7 @@ def evaluate(specs, rows, model_path, width=2048, height=2048, autotune_topk=4, 
                 plans["best_measured"] = pipe.plan(width, height, mode="fixed", fixed=text)
                 res["best_measured_sum_us"] = t_sum
         if "exhaustive" in modes and len(spec["stages"]) <= exhaustive_max_stages:
-            t_sum, text, n = exhaustive_schedule(dag, pipe, width, height)
+            t_sum, text, n = exhaustive_schedule(dag, pipe, width, height, log=log)
             if math.isfinite(t_sum):
                 plans["exhaustive"] = pipe.plan(width, height, mode="fixed", fixed=text)
                 res["exhaustive_sum_us"] = t_sum
@@ -615,7 +623,9 @@ def main(argv=None):
     f.add_argument("--picks-db", nargs="+", help="rows of the model's own picks, from collect --picks-only")
     f.add_argument("--picks-weight", type=float, default=5.0, help="weight of each picks row in the fit")
     e = sub.add_parser("evaluate", help="compare whole-plan schedules on held-out pipelines")
-    e.add_argument("--db", required=True, nargs="+")
+    e.add_argument("--db", nargs="+", help="measurement database (its held-out pipelines are evaluated)")
+    e.add_argument("--seeds", help="evaluate these random pipelines instead (no database needed)")
+    e.add_argument("--stages", default="8-24", help="stage-count range of the --seeds pipelines, e.g. 6-9")
     e.add_argument("--holdout", help="file of held-out pipeline tags (default: a seeded fifth)")
     e.add_argument("--model", required=True)
     e.add_argument("--max-pipelines", type=int, default=0)
@@ -672,13 +682,21 @@ def main(argv=None):
                 res.extend(json.loads(line) for line in f if line.strip())
         log(json.dumps(summarize(res)))
     elif a.cmd == "evaluate":
-        rows = load_db(a.db)
-        _, te = split_by_holdout(rows, a.holdout) if a.holdout else split_tags(rows)
-        tags = sorted(te, key=lambda s: int(s[3:]) if s[3:].isdigit() else s)
-        tags = tags[a.skip:]
-        if a.max_pipelines:
-            tags = tags[:a.max_pipelines]
-        specs = {tg: dags.random_dag(int(tg[3:])) for tg in tags}
+        if a.seeds:
+            # pipelines no campaign measured, so none the network trained on
+            rows = []
+            lo, hi = (int(x) for x in a.stages.split("-"))
+            specs = {f"dag{s}": dags.random_dag(s, lo=lo, hi=hi) for s in _seeds(a.seeds)}
+        else:
+            if not a.db:
+                ap.error("evaluate needs --db or --seeds")
+            rows = load_db(a.db)
+            _, te = split_by_holdout(rows, a.holdout) if a.holdout else split_tags(rows)
+            tags = sorted(te, key=lambda s: int(s[3:]) if s[3:].isdigit() else s)
+            tags = tags[a.skip:]
+            if a.max_pipelines:
+                tags = tags[:a.max_pipelines]
+            specs = {tg: dags.random_dag(int(tg[3:])) for tg in tags}
         modes = tuple(a.modes.split(",")) if a.modes else ALL_MODES
         res = evaluate(specs, rows, a.model, a.size, a.size, log=log, out_path=a.out, modes=modes)
         log(json.dumps(summarize(res)))

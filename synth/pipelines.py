@@ -204,3 +204,24 @@ def wide_chain(depth: int = 10, taps: int = 15) -> dict:
         src = f"s{i}"
     stages.append(_pw("out", [src, "img"], "s0 - 0.5 * s1", 1))
     return {"inputs": [{"name": "img", "channels": 1}], "stages": stages, "outputs": ["out"]}
+
+
+def blur_histogram(channels: int = 1, bins: int = 64, lo: float = 0.0, hi: float = 1.0,
+                   keep_blur: bool = False, of: str = "by") -> dict:
+    """Separable 5-tap blur, then a histogram (`bins` equal bins over
+    [lo, hi) per channel) of stage `of` (the blurred image "by", or the
+    x-blur "bx" that "by" reads); the blurred image is an output too when
+    `keep_blur`."""
+    return {"inputs": [{"name": "img", "channels": channels}],
+            "stages": [blur_x("bx", "img"), blur_y("by", "bx"),
+                       {"name": "h", "kind": "hist", "src": of, "bins": bins, "lo": lo, "hi": hi}],
+            "outputs": ["h", "by"] if keep_blur else ["h"]}
+
+
+def u8_histogram() -> dict:
+    """8-bit binomial blur and the 256-bin histogram of its result."""
+    return {"inputs": [{"name": "img", "channels": 1, "dtype": "u8"}],
+            "stages": [_istencil("bx", "img", 5, 1, 2, 0, [1, 4, 6, 4, 1], 16, "u8"),
+                       _istencil("by", "bx", 1, 5, 0, 2, [1, 4, 6, 4, 1], 16, "u8"),
+                       {"name": "h", "kind": "hist", "src": "by", "bins": 256, "lo": 0.0, "hi": 256.0}],
+            "outputs": ["h"]}

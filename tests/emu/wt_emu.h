@@ -58,6 +58,13 @@ static inline int wt_emu_dpp(int old, int src, int ctrl, bool bound_ctrl) {
 // whole workgroup for one-tile-per-workgroup kernels
 #define __syncthreads() wt_emu_bar->arrive_and_wait()
 #define __builtin_amdgcn_fence(a, b) ((void)0)
+// atomics: the lanes are threads
+#define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_RELAXED)
+#ifndef __HIP_MEMORY_SCOPE_WAVEFRONT
+#define __HIP_MEMORY_SCOPE_WAVEFRONT 0
+#define __HIP_MEMORY_SCOPE_WORKGROUP 0
+#define __HIP_MEMORY_SCOPE_AGENT 0
+#endif
 
 struct wt_emu_rsrc { char* base; uint32_t num; };
 #define __amdgpu_buffer_rsrc_t wt_emu_rsrc

@@ -110,6 +110,26 @@ extern "C" int wt_emu_run_grid_batch(const WtArgs* ab, const int* start, int nim
         }
     return 0;
 }
+// lone-histogram kernels: a 3-D grid of workgroups whose threads meet at
+// __syncthreads (nthr threads started together, one workgroup at a time)
+extern "C" int wt_emu_run_grid_wg(const WtArgs* a, int gx, int gy, int gz, int nthr) {
+    std::barrier<> bar(nthr);
+    wt_emu_bar = &bar;
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthr; ++t)
+        th.emplace_back([&, t] {
+            wt_emu_lane = t & 63;
+            for (int z = 0; z < gz; ++z) for (int y = 0; y < gy; ++y) for (int x = 0; x < gx; ++x) {
+                blockIdx.x = x; blockIdx.y = y; blockIdx.z = z; threadIdx.x = t;
+                gridDim.x = gx; gridDim.y = gy; gridDim.z = gz;
+                bar.arrive_and_wait();
+                WT_EMU_KERNEL(*a);
+                bar.arrive_and_wait();
+            }
+        });
+    for (auto& t : th) t.join();
+    return 0;
+}
 extern "C" int wt_emu_run_grid(const WtArgs* a, int gx, int gy, int gz, int nthr) {
     for (int z = 0; z < gz; ++z) for (int y = 0; y < gy; ++y) for (int x = 0; x < gx; ++x)
         for (int t = 0; t < nthr; ++t) {
@@ -136,6 +156,7 @@ def _compile(src, kname):
     lib = ctypes.CDLL(so)
     lib.wt_emu_run.argtypes = [ctypes.POINTER(Args), ctypes.c_int, ctypes.c_int]
     lib.wt_emu_run_grid.argtypes = [ctypes.POINTER(Args)] + [ctypes.c_int] * 4
+    lib.wt_emu_run_grid_wg.argtypes = [ctypes.POINTER(Args)] + [ctypes.c_int] * 4
     lib.wt_emu_run_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 4
     lib.wt_emu_run_grid_batch.argtypes = [ctypes.c_void_p, ctypes.c_void_p] + [ctypes.c_int] * 3
     lib.wt_emu_run_wg.argtypes = [ctypes.POINTER(Args), ctypes.c_int, ctypes.c_int]
@@ -205,11 +226,16 @@ def emulate(spec, inputs, **plan_kw):
     plan = wt.from_spec(spec).plan(w, h, no_device=True, **plan_kw)
     bufs = {}  # node id -> array
 
+    hists = {st["name"]: st for st in spec["stages"] if st["kind"] == "hist"}
+
     def buf(node_id, code):
         if node_id not in bufs:
             nm = names[node_id]
-            bw, bh = oracle.level_size(w, h, lv[nm])
-            bufs[node_id] = _blank((ch[nm], bh, bw), code)
+            if nm in hists:  # counts start at zero (the runtime clears them before the group)
+                bufs[node_id] = np.zeros((ch[nm], 1, hists[nm]["bins"]), dtype=NP_DTYPE[code])
+            else:
+                bw, bh = oracle.level_size(w, h, lv[nm])
+                bufs[node_id] = _blank((ch[nm], bh, bw), code)
         return bufs[node_id]
 
     import concurrent.futures as cf
@@ -237,7 +263,9 @@ def emulate(spec, inputs, **plan_kw):
             a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
         a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
         a.tiles_x, a.tiles_y, a.nwaves = gi.tiles_x, gi.tiles_y, gi.nwaves
-        if gi.resample:
+        if gi.resample and names[gi.liveouts[0]] in hists:
+            lib.wt_emu_run_grid_wg(ctypes.byref(a), gi.tiles_x, gi.tiles_y, gi.channels, 256)
+        elif gi.resample:
             lib.wt_emu_run_grid(ctypes.byref(a), gi.tiles_x, gi.tiles_y, gi.channels, 256)
         elif _is_blk(plan, g):
             lib.wt_emu_run_wg(ctypes.byref(a), gi.nwaves // gi.waves_per_group, gi.waves_per_group)
@@ -253,6 +281,7 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
     so the grid-stride loop runs; per-image arguments come from one plan per
     image size (no device).  Returns one output dict per image."""
     names, lv, ch = _meta(spec)
+    hists = {st["name"]: st for st in spec["stages"] if st["kind"] == "hist"}
     plans, bufs_all = [], []
     for inputs in images:
         first = inputs[spec["inputs"][0]["name"]]
@@ -287,8 +316,11 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
             def buf(node_id, code):
                 if node_id not in bufs:
                     nm = names[node_id]
-                    bw, bh = oracle.level_size(w, h, lv[nm])
-                    bufs[node_id] = _blank((ch[nm], bh, bw), code)
+                    if nm in hists:  # counts start at zero
+                        bufs[node_id] = np.zeros((ch[nm], 1, hists[nm]["bins"]), dtype=NP_DTYPE[code])
+                    else:
+                        bw, bh = oracle.level_size(w, h, lv[nm])
+                        bufs[node_id] = _blank((ch[nm], bh, bw), code)
                 return bufs[node_id]
 
             a = arr[k]
@@ -312,7 +344,9 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
             start[k] = total
             total += work
         start[len(images)] = total
-        if resample:
+        if resample and names[gi.liveouts[0]] in hists:  # 256 threads meeting at __syncthreads
+            lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, 4)
+        elif resample:
             lib.wt_emu_run_grid_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks)
         elif _is_blk(plans[0], g):
             lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)

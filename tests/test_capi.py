@@ -176,3 +176,28 @@ def test_stream_copy_argument_checks():
     assert lib.wt_stream_copy(ctypes.c_void_p(4100), ctypes.c_void_p(8192), 64, None) == -1  # misaligned
     assert lib.wt_stream_copy(ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 32), 64, None) == -1  # overlap
     assert "overlap" in lib.wt_last_error().decode()
+
+
+def test_histogram_builder_and_plan_rules():
+    """wt_histogram checks its arguments; no stage may read a histogram; a
+    histogram must be an output; the lone and the fused histogram kernels
+    compile for gfx950."""
+    p = wt.Pipeline()
+    img = p.input(1)
+    for bins, lo, hi in ((0, 0.0, 1.0), (4097, 0.0, 1.0), (8, 1.0, 1.0), (8, 0.0, float("nan"))):
+        with pytest.raises(wt.WtError):
+            p.histogram(img, bins, lo, hi)
+    h = p.histogram(img, 16, 0.0, 1.0)
+    with pytest.raises(wt.WtError):
+        p.resample(h, wt.DOWN2)
+    with pytest.raises(wt.WtError):
+        p.stencil(h, 3, 1, 1, 0, [1.0, 2.0, 1.0], 0.25)
+    b = p.stencil(img, 3, 1, 1, 0, [1.0, 2.0, 1.0], 0.25)
+    p.histogram(b, 8, 0.0, 1.0)   # never marked as an output
+    p.output(b)
+    with pytest.raises(wt.WtError, match="not an output"):
+        p.plan(64, 64, mode="unfused", no_device=True, no_compile=True)
+    spec = P.blur_histogram(channels=3, bins=256)
+    wt.from_spec(spec).plan(512, 256, mode="unfused", no_device=True)
+    for fixed in ("nodes=1,2 V=4 TX=1 SX=0 TY=16 PF=2 hst=3", "nodes=1,2 V=1 TX=2 SX=1 TY=8 PF=1 WPB=2 hst=3"):
+        assert "wt_count_global" in _compile(spec, fixed).source(0)

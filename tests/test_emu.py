@@ -547,3 +547,61 @@ def test_lookback_source_reads_two_sub_tiles_back():
     src = wt.from_spec(WIDE).plan(300, 13, mode="fixed", fixed=f"nodes={WIDE_NODES} V=1 TX=3 SX=0 TY=5 PF=1 align=1",
                                   no_device=True, no_compile=True).source(0)
     assert ", 6, lane)" in src
+
+
+# ---------------------------------------------------------------- histogram --
+
+HIST = P.blur_histogram(channels=2, bins=64)
+
+
+@pytest.mark.parametrize("mode,fixed", [
+    ("fixed", "nodes=1,2 V=4 TX=1 SX=0 TY=8 PF=1 hst=3"),
+    ("fixed", "nodes=1,2 V=1 TX=2 SX=1 TY=5 PF=1 hst=3"),     # LDS sub-tiles
+    ("fixed", "nodes=1,2 V=2 TX=2 SX=0 TY=6 PF=2 align=1 hst=3"),  # right-hyperplane skew
+    ("fixed", "nodes=1,2 V=4 TX=1 SX=0 TY=8 PF=1 WPB=2 hst=3"),
+    ("unfused", None),                                        # the lone histogram kernel
+    ("analytic", None),
+])
+def test_histogram_emulated_exact(mode, fixed):
+    """Counts of the blurred dyadic image, fused into the blur's group (each
+    wave counts its tile's output range into LDS bins, then adds them to the
+    output) or counted by the lone kernel: bit-exact against the oracle."""
+    img = synth.dyadic_image(2, 2, 41, 300)
+    got, plan = emulate(HIST, {"img": img}, mode=mode, fixed=fixed)
+    if mode == "analytic":
+        assert "hst=3" in plan.describe()
+    ref = oracle.evaluate(HIST, {"img": img})["h"]
+    assert got["h"].shape == ref.shape and np.array_equal(got["h"], ref), (mode, fixed)
+
+
+def test_histogram_of_a_leading_member_and_a_stored_source_emulated():
+    """The histogram of the x-blur, which the y-blur reads (so its rows run
+    ahead of the tile's): each row still counted once; and with the blurred
+    image also an output, the group both stores and counts it."""
+    img = synth.dyadic_image(3, 1, 37, 200)
+    spec = P.blur_histogram(channels=1, bins=32, of="bx")
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fixed="nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3")
+    assert np.array_equal(got["h"], oracle.evaluate(spec, {"img": img})["h"])
+    spec = P.blur_histogram(channels=1, bins=32, keep_blur=True)
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fixed="nodes=1,2 V=4 TX=1 SX=0 TY=8 PF=1 hst=3")
+    ref = oracle.evaluate(spec, {"img": img})
+    assert np.array_equal(got["h"], ref["h"])
+    assert_exact(got["by"], ref["by"], "stored source")
+
+
+@pytest.mark.parametrize("mode,fixed", [("fixed", "nodes=1,2 V=4 TX=1 SX=0 TY=8 PF=1 hst=3"), ("unfused", None)])
+def test_histogram_u8_emulated_exact(mode, fixed):
+    spec = P.u8_histogram()
+    img = synth.integer_image(7, 1, 29, 260, 0, 255)
+    got, _ = emulate(spec, {"img": img}, mode=mode, fixed=fixed)
+    assert np.array_equal(got["h"], oracle.evaluate(spec, {"img": img})["h"])
+
+
+def test_histogram_batch_emulated_exact():
+    """Batched kernels over images of three sizes: every image's histogram
+    accumulates in its own output."""
+    from emu_runner import emulate_batch
+    images = [{"img": synth.dyadic_image(10 + i, 2, h, w)} for i, (w, h) in enumerate([(300, 41), (70, 9), (131, 66)])]
+    outs = emulate_batch(HIST, images, mode="fixed", fixed="nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3")
+    for im, o in zip(images, outs):
+        assert np.array_equal(o["h"], oracle.evaluate(HIST, im)["h"])

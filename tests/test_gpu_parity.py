@@ -564,3 +564,81 @@ def test_autotune_schedule_cache(tmp_path, monkeypatch):
     assert lines() == n1
     wt.from_spec(spec).plan(512, 256, mode="autotune", autotune_topk=2, cache_dir=str(tmp_path), retune=True)
     assert lines() > n1
+
+
+# ---------------------------------------------------------------- histogram --
+
+def _near_bin_edges(vals, bins, lo, hi, eps=1e-3):
+    """Per channel, how many values of a stage (FP64, from the oracle) lie
+    within eps of a bin edge, in bin units: the only values whose bin the
+    device's FP32 evaluation of the stage may legitimately move."""
+    t = (vals - lo) * (bins / (hi - lo))
+    return [int(np.sum(np.abs(t[c] - np.round(t[c])) < eps)) for c in range(vals.shape[0])]
+
+
+@pytest.mark.parametrize("mode,fixed", [
+    ("analytic", None),
+    ("fixed", "nodes=1,2 V=4 TX=1 SX=0 TY=16 PF=2 hst=3"),
+    ("fixed", "nodes=1,2 V=1 TX=2 SX=1 TY=8 PF=1 WPB=2 hst=3"),
+    ("unfused", None),
+])
+def test_histogram_full_size(mode, fixed):
+    """A 256-bin histogram of the blurred 3x2048x2048 image, counted by the
+    blur's fused group or by the lone kernel: every pixel counted once, and
+    the counts equal the oracle's except where FP32 rounding of the blur
+    moves a value across a bin edge (at most two counts per such value);
+    on a dyadic image (every value exact in FP32) bit-exact."""
+    spec = P.blur_histogram(channels=3, bins=256)
+    _say(f"histogram 3x2048x2048 {mode} [{fixed}]")
+    img = synth.uniform_image(41, 3, 2048, 2048)
+    got, plan = run_gpu(spec, {"img": img}, mode=mode, fixed=fixed)
+    if mode == "analytic":
+        assert "hst=3" in plan.describe()
+    ref = oracle.evaluate(spec, {"img": img}, keep_all=True)
+    near = _near_bin_edges(ref["by"], 256, 0.0, 1.0)
+    for c in range(3):
+        assert got["h"][c].sum() == 2048 * 2048
+        assert np.abs(got["h"][c] - ref["h"][c]).sum() <= 2 * near[c], (c, near[c])
+    dy = synth.dyadic_image(42, 3, 2048, 2048)
+    got, _ = run_gpu(spec, {"img": dy}, mode=mode, fixed=fixed)
+    assert np.array_equal(got["h"], oracle.evaluate(spec, {"img": dy})["h"])
+
+
+def test_histogram_u8_4096():
+    spec = P.u8_histogram()
+    _say("u8 histogram 4096x4096")
+    img = synth.integer_image(43, 1, 4096, 4096, 0, 255)
+    for mode in ("analytic", "unfused"):
+        got, _ = run_gpu(spec, {"img": img}, mode=mode)
+        assert np.array_equal(got["h"], oracle.evaluate(spec, {"img": img})["h"]), mode
+
+
+def test_histogram_batch_and_replays():
+    """Batched histograms of images of uneven sizes, from a hipGraph: each
+    image's counts equal the oracle's, and replaying the graph (which clears
+    the counts with a kernel node before accumulating) gives the same counts,
+    not twice them."""
+    import torch
+    import paper_1909_07190_amd as wt
+    spec = P.blur_histogram(channels=2, bins=128)
+    sizes = [(1000, 517), (64, 33), (2047, 1500), (300, 2001)]
+    _say(f"batched histogram {sizes}")
+    imgs = [synth.dyadic_image(50 + k, 2, h, w) for k, (w, h) in enumerate(sizes)]
+    plan = wt.from_spec(spec).plan(1000, 1000, mode="analytic", any_width=True, batch_images=len(sizes))
+    assert "hst=3" in plan.describe()
+    dev = torch.device("cuda:0")
+    tin = [[torch.from_numpy(im).to(dev)] for im in imgs]
+    for rep in range(3):
+        tout = [[torch.full((2, 1, 128), 0x5A, dtype=torch.int32, device=dev)] for _ in sizes]
+        plan.run_batch(tin, tout)
+        torch.cuda.synchronize()
+        for k, im in enumerate(imgs):
+            ref = oracle.evaluate(spec, {"img": im})["h"]
+            assert np.array_equal(tout[k][0].cpu().numpy().astype(np.int64), ref), (rep, k)
+    # single-image runs of the same plan also start from zero every time
+    single = wt.from_spec(spec).plan(300, 2001, mode="analytic")
+    out = torch.full((2, 1, 128), 7, dtype=torch.int32, device=dev)
+    for _ in range(2):
+        single.run(tin[3], [out])
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().astype(np.int64), oracle.evaluate(spec, {"img": imgs[3]})["h"])

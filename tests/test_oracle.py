@@ -274,3 +274,53 @@ def test_generators_are_exact_and_seeded():
     assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
     sq = synth.white_squares(np.zeros((3, 64, 64), np.float32), 1, count=5)
     assert sq.max() == 1.0 and np.all(sq[0] == sq[2])
+
+
+# ---------------------------------------------------------------- histogram --
+
+def test_histogram_of_exact_bin_values():
+    """Values k/16 (k = 0..15, each k+1 times) in 16 bins over [0, 1): bin k
+    holds exactly k+1 counts."""
+    vals = np.concatenate([np.full(k + 1, k / 16.0) for k in range(16)])
+    h = oracle.histogram(vals.reshape(1, 1, -1), 16, 0.0, 1.0)
+    assert h.shape == (1, 1, 16) and h.dtype == np.int64
+    assert h[0, 0].tolist() == list(range(1, 17))
+
+
+def test_histogram_out_of_range_values():
+    """Below lo and NaN go to bin 0; hi and above to the last bin; the value
+    one FP32 step below an edge stays in the lower bin, while 0.5 - 1e-9
+    (0.5 once rounded to FP32, the decision's precision) goes up."""
+    below = float(np.nextafter(np.float32(0.5), np.float32(0.0)))
+    v = np.array([[[-5.0, np.nan, 1.0, 7.0, below, 0.5, 0.5 - 1e-9]]])
+    h = oracle.histogram(v, 4, 0.0, 1.0)[0, 0]
+    assert h.tolist() == [2, 1, 2, 2]
+
+
+def test_histogram_matches_numpy_away_from_edges():
+    """Random values more than 1e-5 from every bin edge: the same counts as
+    numpy.histogram over the same edges, channel by channel (the channels
+    hold different distributions), and every value counted once."""
+    rng = np.random.default_rng(5)
+    v = np.stack([rng.uniform(-0.2, 1.2, 20000), rng.beta(2, 5, 20000) * 1.5]).reshape(2, 100, 200)
+    lo, hi, nb = -0.1, 1.3, 35
+    edges = np.linspace(lo, hi, nb + 1)
+    far = np.min(np.abs(v[..., None] - edges), axis=-1) > 1e-5
+    h = oracle.histogram(np.where(far, v, lo + 0.5 * (hi - lo) / nb), nb, lo, hi)
+    for c in range(2):
+        x = np.where(far[c], v[c], lo + 0.5 * (hi - lo) / nb).ravel()
+        ref, _ = np.histogram(np.clip(x, lo, np.nextafter(hi, lo)), bins=edges)
+        assert h[c, 0].tolist() == ref.tolist()
+        assert h[c, 0].sum() == v[c].size
+
+
+def test_histogram_stage_in_a_pipeline():
+    """A histogram stage counts its source stage over the whole image, one
+    histogram per channel, of shape [C, 1, bins]."""
+    spec = P.blur_histogram(channels=2, bins=8)
+    img = np.zeros((2, 5, 7))
+    img[1] = 0.999
+    out = oracle.evaluate(spec, {"img": img})["h"]
+    assert out.shape == (2, 1, 8)
+    assert out[0, 0].tolist() == [35, 0, 0, 0, 0, 0, 0, 0]
+    assert out[1, 0].tolist() == [0, 0, 0, 0, 0, 0, 0, 35]

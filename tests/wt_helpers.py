@@ -14,7 +14,8 @@ _MOVE = {"f32": np.float32, "u8": np.uint8, "u16": np.int16, "i16": np.int16, "i
 def _dtypes(spec):
     dt = {i["name"]: i.get("dtype", "f32") for i in spec["inputs"]}
     for st in spec["stages"]:
-        dt[st["name"]] = dt[st["src"]] if st["kind"] in ("down2", "up2") else st.get("dtype", "f32")
+        dt[st["name"]] = (dt[st["src"]] if st["kind"] in ("down2", "up2") else
+                          "i32" if st["kind"] == "hist" else st.get("dtype", "f32"))
     return dt
 
 
@@ -37,8 +38,9 @@ def run_gpu(spec, inputs, width=None, height=None, **plan_kw):
     ins = [to_dev(inputs[i["name"]], dts[i["name"]]) for i in spec["inputs"]]
     lv = _levels(spec)
     outs = []
+    hists = {st["name"]: st["bins"] for st in spec["stages"] if st["kind"] == "hist"}
     for o in spec["outputs"]:
-        ow, oh = oracle.level_size(w, h, lv[o])
+        ow, oh = (hists[o], 1) if o in hists else oracle.level_size(w, h, lv[o])
         ch = _channels(spec)[o]
         if dts[o] == "f32":
             outs.append(torch.full((ch, oh, ow), float("nan"), device=dev, dtype=torch.float32))
@@ -64,7 +66,7 @@ def _levels(spec):
             lv[st["name"]] = lv[st["src"]] + 1
         elif st["kind"] == "up2":
             lv[st["name"]] = lv[st["src"]] - 1
-        elif st["kind"] == "stencil":
+        elif st["kind"] in ("stencil", "hist"):
             lv[st["name"]] = lv[st["src"]]
         else:
             lv[st["name"]] = lv[st["srcs"][0]]
