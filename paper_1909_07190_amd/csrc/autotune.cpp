@@ -339,7 +339,14 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         }
         std::vector<GroupRt*> ptrs;
         for (auto& t : trials) ptrs.push_back(&t);
-        compile_groups(plan, ptrs);
+        std::vector<bool> bad;
+        compile_groups(plan, ptrs, false, &bad);  // a candidate that does not compile is dropped
+        {
+            std::vector<GroupRt> kept;
+            for (size_t i = 0; i < trials.size(); ++i)
+                if (!bad[i]) kept.push_back(std::move(trials[i]));
+            trials = std::move(kept);
+        }
         if (k > 1)
             for (auto& t : trials)
                 for (auto& b : group_planes(plan, t, plan.W, plan.H)) {
@@ -402,7 +409,15 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
             if (more.empty()) break;
             std::vector<GroupRt*> mp;
             for (auto& t : more) mp.push_back(&t);
-            compile_groups(plan, mp);
+            std::vector<bool> bad;
+            compile_groups(plan, mp, false, &bad);
+            {
+                std::vector<GroupRt> kept;
+                for (size_t i = 0; i < more.size(); ++i)
+                    if (!bad[i]) kept.push_back(std::move(more[i]));
+                more = std::move(kept);
+            }
+            if (more.empty()) break;
             if (k > 1)
                 for (auto& t : more)
                     for (auto& b : group_planes(plan, t, plan.W, plan.H)) {
@@ -469,7 +484,19 @@ void measure_groups(const Pipeline& p, int W, int H, bool fp16, const std::vecto
         ok.push_back(&trials[i]);
         idx.push_back(i);
     }
-    compile_groups(plan, ok);
+    std::vector<bool> bad;
+    compile_groups(plan, ok, false, &bad);
+    {
+        std::vector<GroupRt*> okc;
+        std::vector<size_t> idxc;
+        for (size_t j = 0; j < ok.size(); ++j)
+            if (!bad[j]) {
+                okc.push_back(ok[j]);
+                idxc.push_back(idx[j]);
+            }
+        ok = std::move(okc);
+        idx = std::move(idxc);
+    }
     if (!plan.no_device && preprofile_enabled()) preprofile(plan);
     if (plan.no_device) {
         for (size_t i : idx) out_us[i] = 0.0;

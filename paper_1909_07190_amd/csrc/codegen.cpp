@@ -1203,14 +1203,10 @@ struct Gen {
     }
 
     void lds_decl() {
-        if (!geo.hist.empty()) {
-            const int nb = hist_off(geo.hist.size());
-            line("__shared__ unsigned int wt_hb[" + I(nb * g.WPB) + "];");
-            line("unsigned int* hb = wt_hb + (threadIdx.x >> 6) * " + I(nb) + ";");
-        }
         if (geo.lds_bytes <= 0) return;
         line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
         line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
+        if (!geo.hist.empty()) line("unsigned int* hb = (unsigned int*)(lds + " + I(geo.hist_lds_off) + ");");
         for (auto& n : geo.nodes)
             if (has_lds(n))
                 line(std::string(n.half ? "_Float16" : ctype(n.id)) + "* L" + I(n.id) + " = (" +

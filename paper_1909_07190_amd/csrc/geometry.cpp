@@ -328,6 +328,10 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         int bytes = ng.win * ng.nch * per_row * (ng.half ? 2 : 4);
         off += round_up(bytes, 16);
     }
+    // then each accumulated histogram's bins (32-bit counts per channel slot)
+    geo.hist_lds_off = off;
+    for (auto& hs : geo.hist)
+        off += round_up(p.nodes[hs.first].bins * geo.nodes[geo.index.at(hs.second)].nch * 4, 16);
     geo.lds_bytes = off;
     geo.lds_bytes_per_wg = off * g.WPB;
     return geo;

@@ -406,7 +406,7 @@ void unload_group(GroupRt& gr) {
 // Compiles the groups' single-image modules (or, with `batch`, their batched
 // modules) in parallel on host cores (hipRTC), then loads the code objects
 // unless the plan has no device.
-void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch) {
+void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch, std::vector<bool>* failed) {
     std::vector<std::vector<char>> code(grs.size());
     std::vector<std::string> errs(grs.size());
     std::atomic<size_t> next{0};
@@ -425,10 +425,15 @@ void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch) {
             }
         });
     for (auto& t : pool) t.join();
+    if (failed) failed->assign(grs.size(), false);
     for (size_t i = 0; i < errs.size(); ++i)
-        if (!errs[i].empty()) fail(WT_E_COMPILE, errs[i]);
+        if (!errs[i].empty()) {
+            if (!failed) fail(WT_E_COMPILE, errs[i]);
+            (*failed)[i] = true;
+        }
     if (plan.no_device) return;
     for (size_t i = 0; i < grs.size(); ++i) {
+        if (failed && (*failed)[i]) continue;
         GroupRt& g = *grs[i];
         if (batch) {
             if (g.mod_batch) continue;

@@ -196,6 +196,7 @@ struct GroupGeom {
                                     // live-outs, decimated members and the
                                     // sources of accumulated histograms
     std::vector<std::pair<int, int>> hist;  // (histogram node, member it counts)
+    int hist_lds_off = 0;           // the wave's histogram bins in its LDS
 };
 GroupGeom group_geometry(const Pipeline& p, const GroupSched& g);
 

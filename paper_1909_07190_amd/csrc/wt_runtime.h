@@ -148,7 +148,10 @@ std::pair<int, int> node_dims(const Pipeline& p, int id, int W, int H);
 hipError_t zero_hist(void* base, long long cs, int n, int planes, hipStream_t s);
 hipError_t zero_hist_batch(const void* table, int nimg, int d, int n, int planes, hipStream_t s);
 void prepare_group(const Plan& plan, GroupRt& gr, int gi);
-void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch = false);
+// With `failed`, a group that does not compile is marked there (and left
+// unloaded) instead of failing the call.
+void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch = false,
+                    std::vector<bool>* failed = nullptr);
 void unload_group(GroupRt& gr);
 // Validates a caller image against node `n` at W x H (null data, size,
 // channels, element type, strides); returns its dense-resolved strides.

@@ -210,3 +210,44 @@ def test_all_groups_is_the_exhaustive_candidate_set(seed):
             if len(seen) == n and dag.convex(list(sub)):
                 want.add(tuple(sorted(sub)))
     assert set(got) == want
+
+
+def _eval_rows(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(wt.__file__), name)
+    with open(path) as f:
+        return [json.loads(line) for line in f if line.strip()]
+
+
+def _gm(xs):
+    import math
+    return math.exp(sum(math.log(x) for x in xs) / len(xs))
+
+
+def test_committed_evaluations_show_the_network_gain():
+    """Whole plans timed end to end on the device, in the evaluation files
+    shipped beside the network.  Held-out campaign pipelines (8-24 stages):
+    the network's plans beat the analytical model's by at least 1.3x
+    (geomean) and lie within 10% of the fastest plan no learned mode
+    produced on most pipelines.  Fresh pipelines (6-9 stages, never
+    measured by any campaign), judged against the exhaustive search (every
+    connected convex single-level grouping, each group timed under every
+    configuration of the exhaustive grid, the fastest assembly): the
+    network's plans are within 10% of it or faster on every pipeline, and
+    beat the analytical model's by at least 1.15x."""
+    held = _eval_rows("gfx950_cost_mlp_eval.jsonl")
+    assert len(held) >= 20
+    gain = _gm([r["analytic_us"] / r["mlp_us"] for r in held])
+    assert gain >= 1.3, gain
+    ref = [min(r[m + "_us"] for m in ("unfused", "analytic", "autotune", "best_measured") if m + "_us" in r)
+           for r in held]
+    within = sum(r["mlp_us"] <= 1.10 * t for r, t in zip(held, ref)) / len(held)
+    assert within >= 0.75, within
+    fresh = _eval_rows("gfx950_cost_mlp_eval_fresh.jsonl")
+    s = learn.summarize(fresh)
+    assert s["exhaustive_pipelines"] == len(fresh) >= 8
+    assert s["mlp_over_exhaustive"]["within_10pct"] == 1.0
+    assert s["mlp_over_exhaustive"]["geomean"] <= 1.0
+    assert s["mlp_gain_over_analytic"] >= 1.15
+    assert s["mlp_speedup_over_unfused"] >= 2.0
