@@ -369,7 +369,8 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         for (auto& t : trials) unload_group(t);
         // Local search around the winner: one configuration parameter at a
         // time (vector width, sub-tiles, tile height, waves per workgroup,
-        // prefetch depth), while a step still helps.  The grid above samples
+        // prefetch depth), or vector width and sub-tiles together at the
+        // same tile width, while a step still helps.  The grid above samples
         // each axis coarsely; the optimum often sits one step from its best.
         for (int round = 0; round < 2 && std::isfinite(best_t); ++round) {
             std::vector<GroupSched> nb;
@@ -392,6 +393,15 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
             step(&GroupSched::WPB, best.WPB * 2, 1, 4);
             step(&GroupSched::WPB, best.WPB / 2, 1, 4);
             step(&GroupSched::PF, 3 - best.PF, 1, 2);
+            // the same tile width with wider or narrower vectors per lane
+            for (int f : {2, -2}) {
+                GroupSched g = best;
+                g.V = f > 0 ? best.V * 2 : best.V / 2;
+                g.TX = f > 0 ? best.TX / 2 : best.TX * 2;
+                if (g.V < 1 || g.V > vmax || g.TX < 1 || g.TX > 4 || (f > 0 ? best.TX % 2 : best.V % 2)) continue;
+                g.SX = std::min(g.SX, g.TX);
+                try_add(g);
+            }
             std::vector<GroupRt> more;
             for (auto& g : nb) {
                 GroupRt gr;

@@ -849,20 +849,26 @@ struct Gen {
 
     // ------------------------------------------------------- histograms --
     // Each wave counts into bins of its own in LDS (hb: every histogram of
-    // the group, per channel slot, one after another); the tile's counts are
-    // added to the device-wide output once, at its end.
+    // the group, R copies of its bins for all channel slots, one after
+    // another); the tile's counts, summed over the copies, are added to the
+    // device-wide output once, at its end.
+    int hist_words(size_t k) const { return P.nodes[geo.hist[k].first].bins * G(geo.hist[k].second).nch; }
+    // words of histogram k's copies in the wave's LDS bins
+    int hist_span(size_t k) const { return (hist_words(k) + 1) * hist_replicas(hist_words(k)); }
     int hist_off(size_t k) const {
         int o = 0;
-        for (size_t i = 0; i < k; ++i) o += P.nodes[geo.hist[i].first].bins * G(geo.hist[i].second).nch;
+        for (size_t i = 0; i < k; ++i) o += (hist_span(i) + 3) / 4 * 4;
         return o;
     }
     int hist_oi(size_t k) const { return (int)(geo.liveouts.size() + geo.dec.size() + k); }
     // Counts the values of member n at row R that belong to this tile's
-    // output range and to the image.
+    // output range and to the image, into the lane's copy of the bins.
     void emit_hist(size_t k, const NodeGeom& n, int ch, int kk, const std::string& arr, const std::string& R) {
         const Node& h = P.nodes[geo.hist[k].first];
+        const int rep = hist_replicas(hist_words(k));
         const std::string lo = flit((double)(float)h.hlo), sc = flit((double)(float)(h.bins / (h.hhi - h.hlo)));
-        const std::string base = "hb + " + I(hist_off(k) + ch * h.bins);
+        const std::string base = "hb + " + I(hist_off(k) + ch * h.bins) + " + (lane & " + I(rep - 1) + ") * " +
+                                 I(hist_words(k) + 1);
         line("{ const int jb = " + I(kk * SUB) + " + lane * " + I(V) + ";");
         line("  const int xp = x0 + " + I(n.skew) + " + jb;");
         line("  const bool okh = " + R + " >= y0 && " + R + " < kend && " + R + " < H && jb >= " + I(geo.S0) +
@@ -888,11 +894,17 @@ struct Gen {
         line("wt_wave_sync();");
         for (size_t k = 0; k < geo.hist.size(); ++k) {
             const Node& h = P.nodes[geo.hist[k].first];
-            const int oi = hist_oi(k);
-            for (int ch = 0; ch < G(geo.hist[k].second).nch; ++ch)
-                line("for (int i = lane; i < " + I(h.bins) + "; i += 64) { const unsigned int c = hb[" +
-                     I(hist_off(k) + ch * h.bins) + " + i]; if (c) wt_count_global((unsigned int*)A.dst[" + I(oi) +
-                     "] + " + chan_off(geo.hist[k].second, true, oi, ch) + " + i, c); }");
+            const int oi = hist_oi(k), rep = hist_replicas(hist_words(k)), stride = hist_words(k) + 1;
+            for (int ch = 0; ch < G(geo.hist[k].second).nch; ++ch) {
+                line("for (int i = lane; i < " + I(h.bins) + "; i += 64) {");
+                line("    const unsigned int* q = hb + " + I(hist_off(k) + ch * h.bins) + " + i;");
+                std::string sum = "q[0]";
+                for (int r = 1; r < rep; ++r) sum += " + q[" + I(r * stride) + "]";
+                line("    const unsigned int c = " + sum + ";");
+                line("    if (c) wt_count_global((unsigned int*)A.dst[" + I(oi) + "] + " +
+                     chan_off(geo.hist[k].second, true, oi, ch) + " + i, c);");
+                line("}");
+            }
         }
     }
 

@@ -330,8 +330,10 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
     }
     // then each accumulated histogram's bins (32-bit counts per channel slot)
     geo.hist_lds_off = off;
-    for (auto& hs : geo.hist)
-        off += round_up(p.nodes[hs.first].bins * geo.nodes[geo.index.at(hs.second)].nch * 4, 16);
+    for (auto& hs : geo.hist) {
+        const int words = p.nodes[hs.first].bins * geo.nodes[geo.index.at(hs.second)].nch;
+        off += round_up((words + 1) * hist_replicas(words) * 4, 16);
+    }
     geo.lds_bytes = off;
     geo.lds_bytes_per_wg = off * g.WPB;
     return geo;

@@ -144,6 +144,15 @@ int block_tile_w(const GroupSched& g);  // output columns of a BLK tile
 bool is_resample_group(const Pipeline& p, const GroupSched& g);
 // a lone histogram stage (its source read from memory)
 bool is_hist_group(const Pipeline& p, const GroupSched& g);
+// Copies of a wave's histogram bins for `words` = bins x channel slots (lane
+// t counts into copy t mod R, each copy `words + 1` words long so that one
+// bin's copies fall in different LDS banks): up to 8, within 16 KiB, so that
+// neighbouring lanes counting into one bin do not serialise on one address.
+inline int hist_replicas(int words) {
+    int r = 1;
+    while (r < 8 && (words + 1) * r * 2 <= 4096) r *= 2;
+    return r;
+}
 
 struct Schedule { std::vector<GroupSched> groups; };
 
