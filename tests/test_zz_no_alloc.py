@@ -72,3 +72,29 @@ def test_static_batch_refuses_workspace_overflow():
     assert e.value.status == -4  # WT_E_NOMEM
     assert "workspace" in str(e.value)
     torch.cuda.synchronize()
+
+
+def test_static_batch_histograms_twice():
+    """A histogram fused into the blur's group through the allocation-free
+    entry point: its counts are cleared by the library's kernel before each
+    accumulation, so two calls in a row (the second with fewer images) each
+    equal wt_plan_run_batch's counts and the oracle's."""
+    import torch
+    import paper_1909_07190_amd as wt
+    spec = P.blur_histogram(channels=2, bins=64)
+    plan = wt.from_spec(spec).plan(400, 300, mode="analytic", any_width=True, batch_images=4)
+    assert "hst=3" in plan.describe()
+    dev = torch.device("cuda:0")
+    for call, sizes in enumerate(([(400, 300), (97, 41), (1000, 513), (64, 64)], [(97, 41), (250, 130)])):
+        _say(f"histogram call {call}: {sizes}")
+        imgs = [synth.dyadic_image(960 + 10 * call + i, 2, h, w) for i, (w, h) in enumerate(sizes)]
+        ins = [[torch.from_numpy(im).to(dev)] for im in imgs]
+        ref = [[torch.full((2, 1, 64), 0x5A, dtype=torch.int32, device=dev)] for _ in sizes]
+        got = [[torch.full((2, 1, 64), 0x5A, dtype=torch.int32, device=dev)] for _ in sizes]
+        plan.run_batch(ins, ref)
+        plan.run_batch_static(ins, got)
+        torch.cuda.synchronize()
+        for i, im in enumerate(imgs):
+            assert torch.equal(ref[i][0], got[i][0]), f"call {call} image {i}"
+            want = oracle.evaluate(spec, {"img": im})["h"]
+            assert np.array_equal(got[i][0].cpu().numpy().astype(np.int64), want), f"call {call} image {i}"
