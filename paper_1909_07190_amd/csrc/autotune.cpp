@@ -369,8 +369,8 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         for (auto& t : trials) unload_group(t);
         // Local search around the winner: one configuration parameter at a
         // time (vector width, sub-tiles, tile height, waves per workgroup,
-        // prefetch depth), or vector width and sub-tiles together at the
-        // same tile width, while a step still helps.  The grid above samples
+        // prefetch depth up to 4 rows), or vector width and sub-tiles
+        // together at the same tile width, while a step still helps.  The grid above samples
         // each axis coarsely; the optimum often sits one step from its best.
         for (int round = 0; round < 2 && std::isfinite(best_t); ++round) {
             std::vector<GroupSched> nb;
@@ -392,7 +392,8 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
             step(&GroupSched::TY, best.TY / 2, 8, 64);
             step(&GroupSched::WPB, best.WPB * 2, 1, 4);
             step(&GroupSched::WPB, best.WPB / 2, 1, 4);
-            step(&GroupSched::PF, 3 - best.PF, 1, 2);
+            step(&GroupSched::PF, best.PF * 2, 1, 4);
+            step(&GroupSched::PF, best.PF / 2, 1, 4);
             // the same tile width with wider or narrower vectors per lane
             for (int f : {2, -2}) {
                 GroupSched g = best;
