@@ -142,8 +142,10 @@ wt_status wt_resample(wt_pipeline* p, int src, int kind, int* id);
  * in the end bins; NaN counts in bin 0).  Its image is bins x 1 (WT_I32,
  * the source's channels) and must be a pipeline output; no stage may read
  * it.  A group that computes `src` accumulates the histogram as it goes, so
- * `src` itself need not be stored.  bins in 1..4096, lo < hi, both finite;
- * WT_E_INVALID otherwise. */
+ * `src` itself need not be stored; with FP16 intermediates the value
+ * counted is the FP16-rounded one the plan keeps.  The plan clears the
+ * counts before accumulating (every run starts from zero).  bins in
+ * 1..4096, lo < hi, both finite; WT_E_INVALID otherwise. */
 wt_status wt_histogram(wt_pipeline* p, int src, int bins, double lo, double hi, int* id);
 
 /* Marks a node as a pipeline output (outputs are numbered in call order). */
