@@ -466,6 +466,16 @@ def bench_histogram(args, torch, wt, synth, P, cyc):
                           "schedule": pl.describe().strip()}
         log(f"histogram unfused: {lms * 1e3:.2f} us ({pl.num_groups} launches), counts equal "
             f"{res['unfused']['counts_equal']}")
+        # the counts' consumer: equalisation of the blur and a blend with
+        # the input, in the kernel after the counting one
+        espec = P.blur_equalize(channels=C, bins=256)
+        eouts = [torch.empty((C, H, W), device=dev) for _ in range(nsets)]
+        for emode in (HEADLINE_MODE, "unfused"):
+            epl = wt.from_spec(espec).plan(W, H, mode=emode, model_path=wt.GFX950_COST_MODEL)
+            ems = timed(torch, lambda i: epl.run([ins[i % nsets]], [eouts[i % nsets]]), args.steps, args.warmup, cyc)
+            res["equalize_" + emode] = {"value": H * W / (ems * 1e-3) / 1e6, "ms_per_step": ems,
+                                        "launches": epl.num_groups, "schedule": epl.describe().strip()}
+            log(f"equalize {emode}: {ems * 1e3:.2f} us ({epl.num_groups} launches)")
     return res
 
 

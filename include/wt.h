@@ -140,13 +140,24 @@ wt_status wt_resample(wt_pipeline* p, int src, int kind, int* id);
  * (converted to FP32) falls in bin floor((v - lo) * (bins / (hi - lo))),
  * computed in FP32 and clamped to 0..bins-1 (values outside [lo, hi) count
  * in the end bins; NaN counts in bin 0).  Its image is bins x 1 (WT_I32,
- * the source's channels) and must be a pipeline output; no stage may read
- * it.  A group that computes `src` accumulates the histogram as it goes, so
+ * the source's channels) and must be a pipeline output or read by
+ * wt_equalize stages; no other stage may read it.  A group that computes `src` accumulates the histogram as it goes, so
  * `src` itself need not be stored; with FP16 intermediates the value
  * counted is the FP16-rounded one the plan keeps.  The plan clears the
  * counts before accumulating (every run starts from zero).  bins in
  * 1..4096, lo < hi, both finite; WT_E_INVALID otherwise. */
 wt_status wt_histogram(wt_pipeline* p, int src, int bins, double lo, double hi, int* id);
+
+/* Histogram equalisation, a stage that reads a reduction: per channel, the
+ * value v of `src` maps to C(b) / N, where b is v's bin in histogram `hist`
+ * (the bin rule of wt_histogram, with hist's bins, lo and hi), C(b) the
+ * count of bins 0..b and N the total count; C(b) converted to FP32 times
+ * 1/N rounded to FP32 (0 when N = 0).  `hist` must count a stage with
+ * src's channels; it is computed by an earlier kernel than the one that
+ * reads it (the counts must be complete), and its counts need not be an
+ * output.  The result is FP32 in [0, 1] at src's level.  WT_E_INVALID for a
+ * `hist` that is not a histogram or a channel mismatch. */
+wt_status wt_equalize(wt_pipeline* p, int src, int hist, int* id);
 
 /* Marks a node as a pipeline output (outputs are numbered in call order). */
 wt_status wt_output(wt_pipeline* p, int id);

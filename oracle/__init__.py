@@ -292,6 +292,27 @@ def histogram(p: np.ndarray, bins: int, lo: float, hi: float) -> np.ndarray:
     return out
 
 
+def equalize(p: np.ndarray, counts: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    """Histogram equalisation: per channel, value v maps to C(b) / N, b its
+    bin under the histogram's rule (bins = counts.shape[-1], [lo, hi)), C the
+    inclusive cumulative counts, N their total; C(b) in FP32 times 1/N
+    rounded to FP32 (0 when N = 0).  Returns float64 values of those FP32
+    results."""
+    bins = counts.shape[-1]
+    v = np.asarray(p).astype(np.float32)
+    lo32, s32 = np.float32(lo), np.float32(bins / (hi - lo))
+    t = (v - lo32) * s32
+    with np.errstate(invalid="ignore"):
+        idx = np.where(t >= 0, np.where(t >= bins, bins - 1, np.floor(np.where(t >= 0, t, 0))), 0).astype(np.int64)
+    out = np.zeros(v.shape, dtype=np.float64)
+    for c in range(v.shape[0]):
+        cum = np.cumsum(counts[c].reshape(-1))
+        total = cum[-1]
+        rn = np.float32(1.0) / np.float32(total) if total else np.float32(0.0)
+        out[c] = (cum[idx[c]].astype(np.float32) * rn).astype(np.float64)
+    return out
+
+
 # --------------------------------------------------------------------------
 # Whole pipelines
 # --------------------------------------------------------------------------
@@ -308,7 +329,7 @@ def _levels(spec):
             if lv[st["src"]] < 1:
                 raise ValueError("up2 of a level-0 stage")
             lv[st["name"]] = lv[st["src"]] - 1
-        elif k == "hist":
+        elif k in ("hist", "equalize"):
             lv[st["name"]] = lv[st["src"]]
         elif k == "pointwise":
             ls = {lv[s] for s in st["srcs"]}
@@ -320,7 +341,7 @@ def _levels(spec):
     return lv
 
 
-def evaluate_stage(st, vals, lv, width, height):
+def evaluate_stage(st, vals, lv, width, height, stages=None):
     k = st["kind"]
     dtype = st.get("dtype", "f32")
     if k == "stencil":
@@ -333,6 +354,9 @@ def evaluate_stage(st, vals, lv, width, height):
         return down2(vals[st["src"]])
     if k == "hist":
         return histogram(vals[st["src"]], st["bins"], st["lo"], st["hi"])
+    if k == "equalize":
+        h = stages[st["hist"]]  # the histogram's bin rule
+        return equalize(vals[st["src"]], vals[st["hist"]], h["lo"], h["hi"])
     if k == "up2":
         if vals[st["src"]].dtype == np.int64:
             raise ValueError("up2 of an integer stage")
@@ -371,7 +395,7 @@ def evaluate(spec: dict, inputs: dict, keep_all: bool = False) -> dict:
         vals[inp["name"]] = a
     height, width = shape
     for st in spec["stages"]:
-        vals[st["name"]] = evaluate_stage(st, vals, lv, width, height)
+        vals[st["name"]] = evaluate_stage(st, vals, lv, width, height, {s["name"]: s for s in spec["stages"]})
     if keep_all:
         return vals
     return {name: vals[name] for name in spec["outputs"]}

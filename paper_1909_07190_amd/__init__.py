@@ -89,6 +89,7 @@ _sig("wt_pointwise", ctypes.c_int, ctypes.c_void_p, _c_int_p, ctypes.c_int, ctyp
 _sig("wt_resample", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p)
 _sig("wt_histogram", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
      _c_int_p)
+_sig("wt_equalize", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _c_int_p)
 _sig("wt_output", ctypes.c_int, ctypes.c_void_p, ctypes.c_int)
 _sig("wt_plan_create", ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(WtSchedOpts), ctypes.c_int,
      ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p))
@@ -184,6 +185,12 @@ class Pipeline:
         self.channels[i.value] = self.channels[src]
         return i.value
 
+    def equalize(self, src, hist) -> int:
+        i = ctypes.c_int()
+        _check(lib.wt_equalize(self._h, src, hist, ctypes.byref(i)))
+        self.channels[i.value] = self.channels[src]
+        return i.value
+
     def output(self, node: int):
         _check(lib.wt_output(self._h, node))
 
@@ -252,6 +259,8 @@ def from_spec(spec: dict) -> Pipeline:
             i = p.resample(p.names[st["src"]], DOWN2 if k == "down2" else UP2)
         elif k == "hist":
             i = p.histogram(p.names[st["src"]], st["bins"], st["lo"], st["hi"])
+        elif k == "equalize":
+            i = p.equalize(p.names[st["src"]], p.names[st["hist"]])
         else:
             raise ValueError(f"unknown stage kind {k!r}")
         p.names[st["name"]] = i

@@ -167,7 +167,7 @@ std::unique_ptr<BatchState> layout_batch(const Plan& plan, const std::vector<std
             for (size_t k = 0; k < gr.liveouts.size(); ++k) {
                 int id = gr.liveouts[k];
                 if (p.is_output(id) || st->offs[i].count(id)) continue;
-                auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[id].level);
+                auto d = node_dims(p, id, sizes[i].first, sizes[i].second);
                 Buf b;
                 b.half = gr.mem_half_out[k];
                 b.rs = (d.first + 63) / 64 * 64;

@@ -311,6 +311,24 @@ wt_status wt_histogram(wt_pipeline* p, int src, int bins, double lo, double hi, 
     });
 }
 
+wt_status wt_equalize(wt_pipeline* p, int src, int hist, int* id) {
+    return guard([&] {
+        if (!p || !id) wt::fail(WT_E_INVALID, "null argument");
+        check_src(p, src);
+        if (hist < 0 || hist >= (int)p->p.nodes.size() || p->p.nodes[hist].kind != wt::Kind::Hist)
+            wt::fail(WT_E_INVALID, "equalize needs a histogram node");
+        const wt::Node s = p->p.nodes[src];
+        if (s.channels != p->p.nodes[hist].channels) wt::fail(WT_E_INVALID, "equalize: channel counts differ");
+        wt::Node& n = new_node(p, wt::Kind::Equalize);
+        n.srcs = {src, hist};
+        n.channels = s.channels;
+        n.level = s.level;
+        n.dtype = WT_F32;
+        n.bound = 1.0;
+        *id = n.id;
+    });
+}
+
 wt_status wt_output(wt_pipeline* p, int id) {
     return guard([&] {
         if (!p) wt::fail(WT_E_INVALID, "null pipeline");

@@ -333,6 +333,15 @@ struct Gen {
         }
         int p = n.srcs[0];
         int chp = src_chan(G(p), ch, -1);
+        if (n.kind == Kind::Equalize) {  // the cumulative count of the value's bin, scaled
+            const Node& h = P.nodes[n.srcs[1]];
+            std::string v = read(c, p, chp, k, e, 0, 0, ph);
+            if (isint(p)) v = "(float)" + v;
+            const int tk = table_index(h.id), ts = geo.chan_parallel ? 0 : chp;
+            const std::string lo = flit((double)(float)h.hlo), sc = flit((double)(float)(h.bins / (h.hhi - h.hlo)));
+            return "((float)ht" + I(tk) + "[" + I(ts * h.bins) + " + wt_hist_bin(" + v + ", " + lo + ", " + sc + ", " +
+                   I(h.bins) + ")] * rn" + I(tk) + "_" + I(ts) + ")";
+        }
         if (n.is_int()) {
             // exact integer sum, quotient rounded half up, saturation
             std::string acc;
@@ -883,6 +892,56 @@ struct Gen {
         }
         line("}");
     }
+    // ----------------------------------------------------- equalize tables --
+    // A histogram an equalize member reads is loaded whole at the start of
+    // each tile and turned into cumulative counts in the wave's LDS: each
+    // lane sums a run of consecutive bins, the lanes' totals are added up
+    // for the lanes above them, and rn<k>_<slot> = 1 / total (0 for an empty
+    // histogram).
+    int table_index(int h) const {
+        for (size_t i = 0; i < geo.tables.size(); ++i)
+            if (geo.tables[i] == h) return (int)i;
+        fail(WT_E_INTERNAL, "equalize table not in the group");
+        return -1;
+    }
+    int table_off(size_t k) const {
+        int o = 0;
+        for (size_t i = 0; i < k; ++i) {
+            const Node& h = P.nodes[geo.tables[i]];
+            o += (h.bins * (geo.chan_parallel ? 1 : h.channels) + 3) / 4 * 4;
+        }
+        return o;
+    }
+    void emit_tables() {
+        if (geo.tables.empty()) return;
+        const std::string scr = "(tb + " + I(table_off(geo.tables.size())) + ")";
+        for (size_t k = 0; k < geo.tables.size(); ++k) {
+            const Node& h = P.nodes[geo.tables[k]];
+            const int si = (int)geo.loaded.size() + (int)k, nch = geo.chan_parallel ? 1 : h.channels;
+            const int cnk = (h.bins + 63) / 64;
+            line("unsigned int* ht" + I((int)k) + " = tb + " + I(table_off(k)) + ";");
+            for (int ch = 0; ch < nch; ++ch) {
+                std::string coff = geo.chan_parallel ? (h.channels == 1 ? "0" : "(long long)cp * A.src_cs[" + I(si) + "]")
+                                                     : "(long long)" + I(ch) + " * A.src_cs[" + I(si) + "]";
+                const std::string T = "ht" + I((int)k) + " + " + I(ch * h.bins);
+                line("float rn" + I((int)k) + "_" + I(ch) + ";");
+                line("{ const unsigned int* cnt = (const unsigned int*)A.src[" + I(si) + "] + " + coff + ";");
+                line("  unsigned int* T = " + T + ";");
+                line("  unsigned int run = 0u;");
+                line("  for (int i = 0; i < " + I(cnk) + "; ++i) { const int b = lane * " + I(cnk) +
+                     " + i; if (b < " + I(h.bins) + ") { run += cnt[b]; T[b] = run; } }");
+                line("  " + scr + "[lane] = run;");
+                line("  wt_wave_sync();");
+                line("  unsigned int below = 0u;");
+                line("  for (int j = 0; j < lane; ++j) below += " + scr + "[j];");
+                line("  for (int i = 0; i < " + I(cnk) + "; ++i) { const int b = lane * " + I(cnk) +
+                     " + i; if (b < " + I(h.bins) + ") T[b] += below; }");
+                line("  wt_wave_sync();");
+                line("  const unsigned int tot = T[" + I(h.bins - 1) + "];");
+                line("  rn" + I((int)k) + "_" + I(ch) + " = tot ? 1.0f / (float)tot : 0.0f; }");
+            }
+        }
+    }
     void emit_hist_clear() {
         if (geo.hist.empty()) return;
         line("wt_wave_sync();");
@@ -1219,6 +1278,7 @@ struct Gen {
         line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
         line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
         if (!geo.hist.empty()) line("unsigned int* hb = (unsigned int*)(lds + " + I(geo.hist_lds_off) + ");");
+        if (!geo.tables.empty()) line("unsigned int* tb = (unsigned int*)(lds + " + I(geo.table_lds_off) + ");");
         for (auto& n : geo.nodes)
             if (has_lds(n))
                 line(std::string(n.half ? "_Float16" : ctype(n.id)) + "* L" + I(n.id) + " = (" +
@@ -1269,6 +1329,7 @@ struct Gen {
                      I(oi) + "] * " + I(dec_size(k)) + "), WT_RSRC_W3);");
         }
         emit_hist_clear();
+        emit_tables();
         line("if (!bx) {");
         body(false);
         line("} else {");
@@ -1598,11 +1659,13 @@ int block_tile_w(const GroupSched& g) { return 64 * g.V * g.TX; }
 
 GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const GroupGeom& geo,
                                    const std::string& kname) {
-    if ((int)geo.loaded.size() > 16 || (int)(geo.liveouts.size() + geo.dec.size() + geo.hist.size()) > 16)
+    if ((int)(geo.loaded.size() + geo.tables.size()) > 16 ||
+        (int)(geo.liveouts.size() + geo.dec.size() + geo.hist.size()) > 16)
         fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
     if (g.BLK) {
         if (!geo.dec.empty() || !g.exp.empty()) fail(WT_E_UNSUPPORTED, "fused resampling in a one-tile-per-workgroup group");
-        if (!geo.hist.empty()) fail(WT_E_UNSUPPORTED, "histogram in a one-tile-per-workgroup group");
+        if (!geo.hist.empty() || !geo.tables.empty())
+            fail(WT_E_UNSUPPORTED, "histogram or equalize stage in a one-tile-per-workgroup group");
         BlockGen b(p, g, geo);
         std::string single = b.single(kname);
         std::string batch = b.batch(kname);

@@ -151,6 +151,8 @@ StageProfile estimate_stage(const Pipeline& p, int id, const Machine& m) {
         ops = taps + (dx ? 2 : 0);
     } else if (n.kind == Kind::Pointwise) {
         ops = std::max(1, expr_ops(n.expr));
+    } else if (n.kind == Kind::Equalize) {
+        ops = 8;  // the bin, an LDS read of its cumulative count, a scale
     } else {
         ops = 12;
     }
@@ -333,7 +335,7 @@ std::vector<double> group_features(const Pipeline& p, const GroupSched& g, const
             hy_max = std::max(hy_max, hy);
             hx_sum += hx;
             hy_sum += hy;
-        } else if (n.kind == Kind::Pointwise) {
+        } else if (n.kind == Kind::Pointwise || n.kind == Kind::Equalize) {
             ++npw;
         } else if (n.kind == Kind::Down2) {
             ++ndn;

@@ -64,7 +64,7 @@ struct Search {
         for (size_t i = 0; i < stages.size(); ++i) {
             const Node& n = p.nodes[stages[i]];
             flevel[i] = n.level;
-            if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise) {
+            if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise || n.kind == Kind::Equalize) {
                 fusable[i] = true;
             } else if (n.kind == Kind::Down2 || n.kind == Kind::Hist) {
                 // written decimated, or counted, by the group of its source
@@ -118,7 +118,13 @@ struct Search {
             if (!(g >> i & 1)) continue;
             if (!fusable[i]) return false;
             const Node& n = p.nodes[stages[i]];
-            if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise) body = true;
+            if (n.kind == Kind::Stencil || n.kind == Kind::Pointwise || n.kind == Kind::Equalize) body = true;
+            // a histogram's counts are complete only after the kernel that
+            // accumulates them: no stage of that kernel may read them
+            if (n.kind == Kind::Equalize) {
+                auto h = pos.find(n.srcs[1]);
+                if (h != pos.end() && (g >> h->second & 1)) return false;
+            }
             if (n.kind == Kind::Down2 || n.kind == Kind::Up2 || n.kind == Kind::Hist) {
                 auto it = pos.find(n.srcs[0]);
                 if (it == pos.end() || !(g >> it->second & 1)) return false;

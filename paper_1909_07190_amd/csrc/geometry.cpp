@@ -66,6 +66,10 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
             if (f < 0 || !mem.count(f) || !dec.count(n.srcs[0]))
                 fail(WT_E_INVALID, "up2 node " + std::to_string(n.id) +
                                        " can only be fused with the stage whose decimation it expands");
+        } else if (n.kind == Kind::Equalize) {
+            if (hst.count(n.srcs[1]))
+                fail(WT_E_INVALID, "equalize node " + std::to_string(n.id) +
+                                       " reads a histogram its own group accumulates");
         } else if (n.kind != Kind::Stencil && n.kind != Kind::Pointwise) {
             fail(WT_E_INVALID, "node " + std::to_string(n.id) + " cannot be fused");
         }
@@ -75,8 +79,13 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
     // the group's dependence graph: a folded up2 reads the stage it folds
     auto gsrcs = [&](int m) -> std::vector<int> {
         if (p.nodes[m].kind == Kind::Up2) return {p.fold_source(m)};
+        if (p.nodes[m].kind == Kind::Equalize) return {p.nodes[m].srcs[0]};  // its histogram is a table
         return p.nodes[m].srcs;
     };
+    for (int m : g.nodes)
+        if (p.nodes[m].kind == Kind::Equalize &&
+            std::find(geo.tables.begin(), geo.tables.end(), p.nodes[m].srcs[1]) == geo.tables.end())
+            geo.tables.push_back(p.nodes[m].srcs[1]);
     auto cons = p.consumers();
     for (int m : g.nodes)
         if (p.nodes[m].kind == Kind::Up2) cons[p.fold_source(m)].push_back(m);
@@ -334,6 +343,11 @@ GroupGeom group_geometry(const Pipeline& p, const GroupSched& g) {
         const int words = p.nodes[hs.first].bins * geo.nodes[geo.index.at(hs.second)].nch;
         off += round_up((words + 1) * hist_replicas(words) * 4, 16);
     }
+    // then the cumulative counts of the tables equalize members read, and 64
+    // words for the lanes' partial sums while they are formed
+    geo.table_lds_off = off;
+    for (int t : geo.tables) off += round_up(p.nodes[t].bins * (par ? 1 : p.nodes[t].channels) * 4, 16);
+    if (!geo.tables.empty()) off += 256;
     geo.lds_bytes = off;
     geo.lds_bytes_per_wg = off * g.WPB;
     return geo;

@@ -66,6 +66,8 @@ std::vector<Tap> Pipeline::taps(int c, int p) const {
     } else if (n.kind == Kind::Pointwise) {
         for (int s : n.srcs)
             if (s == p) { t.push_back({0, 0, 1.0}); break; }
+    } else if (n.kind == Kind::Equalize) {
+        if (n.srcs[0] == p) t.push_back({0, 0, 1.0});  // the histogram is read whole, not by offsets
     }
     return t;
 }

@@ -33,6 +33,14 @@ std::pair<int, int> level_dims(int W, int H, int level) {
     return {W, H};
 }
 
+// A histogram is of use as an output or as the table of equalize stages.
+static bool hist_is_read(const Pipeline& p, int h) {
+    if (p.is_output(h)) return true;
+    for (const Node& n : p.nodes)
+        if (n.kind == Kind::Equalize && n.srcs[1] == h) return true;
+    return false;
+}
+
 std::pair<int, int> node_dims(const Pipeline& p, int id, int W, int H) {
     const Node& n = p.nodes[id];
     if (n.kind == Kind::Hist) return {n.bins, 1};
@@ -336,7 +344,8 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
         gr.loaded = {n.srcs[0]};
         gr.liveouts = {n.id};
         if (n.kind == Kind::Hist) {
-            if (!p.is_output(n.id)) fail(WT_E_INVALID, "histogram node " + std::to_string(n.id) + " is not an output");
+            if (!hist_is_read(p, n.id))
+                fail(WT_E_INVALID, "histogram node " + std::to_string(n.id) + " is not an output and no stage reads it");
             name_sources(gr, generate_hist_source(p, gr.g, kNamePlaceholder, half_mem(n.srcs[0])), gi);
         } else {
             name_sources(gr, generate_resample_source(p, gr.g, kNamePlaceholder, half_mem(n.srcs[0]), half_mem(n.id)),
@@ -363,13 +372,18 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
     for (int l : gr.geo.liveouts) gr.mem_half_out.push_back(half_mem(l));
     gr.loaded.clear();
     for (int l : gr.geo.loaded) gr.loaded.push_back(buffer_of(l));
+    for (int t : gr.geo.tables) {  // histograms read whole follow the loaded rows
+        gr.loaded.push_back(t);
+        gr.mem_half_in.push_back(false);
+    }
     gr.liveouts = gr.geo.liveouts;
     for (auto& ds : gr.geo.dec) {  // decimated outputs follow the live-outs
         gr.liveouts.push_back(ds.first);
         gr.mem_half_out.push_back(half_mem(ds.first));
     }
     for (auto& hs : gr.geo.hist) {  // then accumulated histograms
-        if (!p.is_output(hs.first)) fail(WT_E_INVALID, "histogram node " + std::to_string(hs.first) + " is not an output");
+        if (!hist_is_read(p, hs.first))
+            fail(WT_E_INVALID, "histogram node " + std::to_string(hs.first) + " is not an output and no stage reads it");
         gr.liveouts.push_back(hs.first);
         gr.mem_half_out.push_back(false);
     }
@@ -477,7 +491,7 @@ void build_groups(Plan& plan) {
         for (size_t i = 0; i < gr.liveouts.size(); ++i) {
             int id = gr.liveouts[i];
             if (p.is_output(id) || plan.bufs.count(id)) continue;
-            auto d = level_dims(plan.W, plan.H, p.nodes[id].level);
+            auto d = node_dims(p, id, plan.W, plan.H);
             Buf b;
             b.half = gr.mem_half_out[i];
             b.rs = round_up64(d.first, 64);

@@ -39,7 +39,7 @@ double expr_bound(const Expr& e, const std::vector<double>& src_bounds);
 bool expr_has_explicit_channel(const Expr& e);
 int expr_max_channel(const Expr& e, int src);
 
-enum class Kind { Input, Stencil, Pointwise, Down2, Up2, Hist };
+enum class Kind { Input, Stencil, Pointwise, Down2, Up2, Hist, Equalize };
 
 // Element types (wt_dtype): integer stages compute exactly in 32-bit
 // integers and saturate to their type's range.
@@ -206,6 +206,9 @@ struct GroupGeom {
                                     // sources of accumulated histograms
     std::vector<std::pair<int, int>> hist;  // (histogram node, member it counts)
     int hist_lds_off = 0;           // the wave's histogram bins in its LDS
+    std::vector<int> tables;        // histograms read whole by equalize members
+                                    // (after `loaded` in the source slots)
+    int table_lds_off = 0;          // their cumulative counts in the wave's LDS
 };
 GroupGeom group_geometry(const Pipeline& p, const GroupSched& g);
 

@@ -225,3 +225,16 @@ def u8_histogram() -> dict:
                        _istencil("by", "bx", 1, 5, 0, 2, [1, 4, 6, 4, 1], 16, "u8"),
                        {"name": "h", "kind": "hist", "src": "by", "bins": 256, "lo": 0.0, "hi": 256.0}],
             "outputs": ["h"]}
+
+
+def blur_equalize(channels: int = 1, bins: int = 256) -> dict:
+    """Histogram equalisation of a blurred image, then a blend of the result
+    with the input: the histogram of the blur (over [0, 1)) is a reduction
+    its equalisation reads whole, so they run in separate kernels; the blend
+    reads the equalised values at the same point."""
+    return {"inputs": [{"name": "img", "channels": channels}],
+            "stages": [blur_x("bx", "img"), blur_y("by", "bx"),
+                       {"name": "h", "kind": "hist", "src": "by", "bins": bins, "lo": 0.0, "hi": 1.0},
+                       {"name": "eq", "kind": "equalize", "src": "by", "hist": "h"},
+                       _pw("out", ["eq", "img"], "0.75 * s0 + 0.25 * s1", channels)],
+            "outputs": ["out"]}

@@ -201,3 +201,24 @@ def test_histogram_builder_and_plan_rules():
     wt.from_spec(spec).plan(512, 256, mode="unfused", no_device=True)
     for fixed in ("nodes=1,2 V=4 TX=1 SX=0 TY=16 PF=2 hst=3", "nodes=1,2 V=1 TX=2 SX=1 TY=8 PF=1 WPB=2 hst=3"):
         assert "wt_count_global" in _compile(spec, fixed).source(0)
+
+
+def test_equalize_builder_rules():
+    """wt_equalize needs a histogram with the source's channel count; a
+    histogram read by an equalize stage need not be an output (the plan
+    keeps its counts in an intermediate buffer)."""
+    p = wt.Pipeline()
+    img = p.input(2)
+    one = p.input(1)
+    b = p.stencil(img, 3, 1, 1, 0, [1.0, 2.0, 1.0], 0.25)
+    with pytest.raises(wt.WtError):
+        p.equalize(b, b)                  # not a histogram
+    h1 = p.histogram(one, 16, 0.0, 1.0)
+    with pytest.raises(wt.WtError):
+        p.equalize(b, h1)                 # 2 channels against 1
+    h = p.histogram(b, 16, 0.0, 1.0)
+    e = p.equalize(b, h)
+    p.output(e)
+    p.output(h1)
+    plan = p.plan(128, 64, mode="analytic", no_device=True)
+    assert "hst=" in plan.describe()

@@ -605,3 +605,53 @@ def test_histogram_batch_emulated_exact():
     outs = emulate_batch(HIST, images, mode="fixed", fixed="nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3")
     for im, o in zip(images, outs):
         assert np.array_equal(o["h"], oracle.evaluate(HIST, im)["h"])
+
+
+def test_histogram_in_a_channel_mixing_group_emulated():
+    """A group whose gray stage mixes channels keeps all three channels of
+    the x-blur in one wave: the histogram of that blur counts each channel
+    slot into its own bins."""
+    spec = {"inputs": [{"name": "img", "channels": 3}],
+            "stages": [P.blur_x("bx", "img"),
+                       {"name": "gray", "kind": "pointwise", "srcs": ["bx"],
+                        "expr": "0.25 * s0[0] + 0.5 * s0[1] + 0.25 * s0[2]", "channels": 1},
+                       {"name": "h", "kind": "hist", "src": "bx", "bins": 32, "lo": 0.0, "hi": 1.0}],
+            "outputs": ["gray", "h"]}
+    img = synth.dyadic_image(12, 3, 23, 150)
+    got, plan = emulate(spec, {"img": img}, mode="fixed", fixed="nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3")
+    assert "chan_parallel=0" in plan.source(0)
+    ref = oracle.evaluate(spec, {"img": img})
+    assert np.array_equal(got["h"], ref["h"])
+    assert_exact(got["gray"], ref["gray"], "gray")
+
+
+EQ = P.blur_equalize(channels=2, bins=64)
+EQ_ONLY = dict(EQ, stages=EQ["stages"][:4], outputs=["eq"])
+
+
+@pytest.mark.parametrize("mode,fixed", [
+    ("analytic", None),
+    ("unfused", None),
+    ("fixed", "nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3;nodes=4,5 V=1 TX=2 SX=1 TY=5 PF=1"),
+    ("fixed", "nodes=1,2 V=4 TX=1 SX=0 TY=8 PF=1 hst=3;nodes=4,5 V=4 TX=1 SX=0 TY=6 PF=2 WPB=2"),
+])
+def test_equalize_emulated(mode, fixed):
+    """Histogram equalisation reading the counts a previous kernel
+    accumulated: each tile loads the histogram whole and forms its
+    cumulative counts in LDS; the equalised values (exact on dyadic inputs)
+    and their blend with the input against the oracle."""
+    img = synth.dyadic_image(3, 2, 41, 300)
+    got, plan = emulate(EQ_ONLY, {"img": img}, mode=mode, fixed=fixed.replace("4,5", "4") if fixed else None)
+    assert_exact(got["eq"], oracle.evaluate(EQ_ONLY, {"img": img})["eq"], f"{mode} {fixed}")
+    got, plan = emulate(EQ, {"img": img}, mode=mode, fixed=fixed)
+    if mode == "analytic":
+        d = plan.describe()
+        assert "hst=3" in d and " nodes=4,5 " in d
+    assert_normwise(got["out"], oracle.evaluate(EQ, {"img": img})["out"], 1e-6, f"{mode} {fixed}")
+
+
+def test_equalize_refuses_its_own_histogram_group():
+    """A group may not read the counts it accumulates."""
+    with pytest.raises(wt.WtError):
+        wt.from_spec(EQ).plan(64, 64, mode="fixed", fixed="nodes=1,2,4,5 V=1 TX=1 SX=0 TY=8 hst=3",
+                              no_device=True, no_compile=True)

@@ -324,3 +324,30 @@ def test_histogram_stage_in_a_pipeline():
     assert out.shape == (2, 1, 8)
     assert out[0, 0].tolist() == [35, 0, 0, 0, 0, 0, 0, 0]
     assert out[1, 0].tolist() == [0, 0, 0, 0, 0, 0, 0, 35]
+
+
+def test_equalize_maps_bins_to_cumulative_fractions():
+    """Values k/16 (k = 0..15, each k+1 times) in 16 bins: value k/16 maps to
+    the fraction of values at or below it, (k+1)(k+2)/2 of 136, to FP32
+    rounding; the largest value maps to 1 within one FP32 step; the map is
+    non-decreasing in the value."""
+    vals = np.concatenate([np.full(k + 1, k / 16.0) for k in range(16)]).reshape(1, 1, -1)
+    h = oracle.histogram(vals, 16, 0.0, 1.0)
+    e = oracle.equalize(np.arange(16).reshape(1, 1, 16) / 16.0, h, 0.0, 1.0)[0, 0]
+    want = np.array([(k + 1) * (k + 2) / 2 / 136 for k in range(16)])
+    assert np.max(np.abs(e - want)) <= 2 ** -23
+    assert abs(e[-1] - 1.0) <= 2 ** -23 and np.all(np.diff(e) > 0)
+
+
+def test_equalize_flattens_the_distribution_and_handles_empty_counts():
+    """Equalising an image by its own histogram spreads its values evenly:
+    the share of pixels mapped at or below q is q, up to the mass of one
+    bin; an all-zero histogram maps everything to 0."""
+    rng = np.random.default_rng(3)
+    img = (rng.beta(5, 2, (1, 300, 400)) * 0.999)
+    h = oracle.histogram(img, 256, 0.0, 1.0)
+    e = oracle.equalize(img, h, 0.0, 1.0)
+    top = h.max() / img.size
+    for q in (0.1, 0.25, 0.5, 0.75, 0.9):
+        assert abs(np.mean(e <= q) - q) <= top + 1e-9
+    assert np.all(oracle.equalize(img, np.zeros_like(h), 0.0, 1.0) == 0.0)

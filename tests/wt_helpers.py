@@ -66,7 +66,7 @@ def _levels(spec):
             lv[st["name"]] = lv[st["src"]] + 1
         elif st["kind"] == "up2":
             lv[st["name"]] = lv[st["src"]] - 1
-        elif st["kind"] in ("stencil", "hist"):
+        elif st["kind"] in ("stencil", "hist", "equalize"):
             lv[st["name"]] = lv[st["src"]]
         else:
             lv[st["name"]] = lv[st["srcs"][0]]
