@@ -915,6 +915,7 @@ struct Gen {
     void emit_tables() {
         if (geo.tables.empty()) return;
         const std::string scr = "(tb + " + I(table_off(geo.tables.size())) + ")";
+        line("wt_wave_sync();  // a previous tile of this wave may still be reading the tables");
         for (size_t k = 0; k < geo.tables.size(); ++k) {
             const Node& h = P.nodes[geo.tables[k]];
             const int si = (int)geo.loaded.size() + (int)k, nch = geo.chan_parallel ? 1 : h.channels;

@@ -655,3 +655,14 @@ def test_equalize_refuses_its_own_histogram_group():
     with pytest.raises(wt.WtError):
         wt.from_spec(EQ).plan(64, 64, mode="fixed", fixed="nodes=1,2,4,5 V=1 TX=1 SX=0 TY=8 hst=3",
                               no_device=True, no_compile=True)
+
+
+def test_equalize_batch_emulated_exact():
+    """Batched kernels whose waves loop over several tiles of images of three
+    sizes: every tile reloads its own image's cumulative counts."""
+    from emu_runner import emulate_batch
+    images = [{"img": synth.dyadic_image(20 + i, 2, h, w)} for i, (w, h) in enumerate([(300, 41), (70, 9), (131, 66)])]
+    outs = emulate_batch(EQ_ONLY, images, nblocks=3,
+                         mode="fixed", fixed="nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3;nodes=4 V=1 TX=2 SX=0 TY=8 PF=1")
+    for im, o in zip(images, outs):
+        assert_exact(o["eq"], oracle.evaluate(EQ_ONLY, im)["eq"], "batched equalize")
