@@ -666,3 +666,20 @@ def test_equalize_batch_emulated_exact():
                          mode="fixed", fixed="nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3;nodes=4 V=1 TX=2 SX=0 TY=8 PF=1")
     for im, o in zip(images, outs):
         assert_exact(o["eq"], oracle.evaluate(EQ_ONLY, im)["eq"], "batched equalize")
+
+
+def test_histogram_of_an_input_and_of_a_decimated_stage_emulated():
+    """A histogram of a pipeline input, and one of a down2 stage (level 1),
+    are counted by the lone kernel over that node's own domain."""
+    spec = {"inputs": [{"name": "img", "channels": 1}],
+            "stages": [{"name": "h0", "kind": "hist", "src": "img", "bins": 16, "lo": 0.0, "hi": 1.0},
+                       P.blur_x("bx", "img"),
+                       {"name": "d", "kind": "down2", "src": "bx"},
+                       {"name": "h1", "kind": "hist", "src": "d", "bins": 8, "lo": 0.0, "hi": 1.0}],
+            "outputs": ["h0", "h1"]}
+    img = synth.dyadic_image(13, 1, 37, 141)
+    for mode in ("analytic", "unfused"):
+        got, _ = emulate(spec, {"img": img}, mode=mode)
+        ref = oracle.evaluate(spec, {"img": img})
+        assert np.array_equal(got["h0"], ref["h0"]) and np.array_equal(got["h1"], ref["h1"]), mode
+        assert got["h1"].sum() == 19 * 71
