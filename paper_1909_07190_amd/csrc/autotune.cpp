@@ -213,6 +213,59 @@ struct PlanHeight {
 
 }  // namespace
 
+namespace {
+
+// What a group computes, independent of which nodes it computes it for: each
+// member's stage (kind, channels, level, type and parameters) with its
+// sources as members (by position) or as outside nodes (their kind, level
+// and channels), and its decimated, expanded and counted stages likewise.
+// Two groups with one signature run the same kernel on different images.
+std::string group_signature(const Pipeline& p, const GroupSched& g) {
+    std::map<int, int> pos;
+    for (size_t i = 0; i < g.nodes.size(); ++i) pos[g.nodes[i]] = (int)i;
+    std::ostringstream os;
+    os.precision(17);
+    auto stage = [&](int id) {
+        const Node& n = p.nodes[id];
+        os << (int)n.kind << ':' << n.channels << ':' << n.level << ':' << n.dtype << ':' << n.kw << 'x' << n.kh << ':'
+           << n.ax << ',' << n.ay << ':' << n.scale << ':' << n.divisor << ':' << n.bins << ':' << n.hlo << ':' << n.hhi
+           << ':' << n.expr_text << '[';
+        for (double w : n.weights) os << w << ',';
+        for (long long w : n.iweights) os << w << ',';
+        os << "](";
+        for (int s : n.srcs) {
+            auto it = pos.find(s);
+            if (it != pos.end()) os << 'm' << it->second << ',';
+            else os << 'x' << (int)p.nodes[s].kind << '.' << p.nodes[s].level << '.' << p.nodes[s].channels << ',';
+        }
+        os << ')';
+    };
+    for (int m : g.nodes) stage(m);
+    for (const auto* list : {&g.dec, &g.exp, &g.hst}) {
+        os << '|';
+        for (int d : *list) stage(d);
+    }
+    return os.str();
+}
+
+void copy_config(const GroupSched& from, GroupSched& to) {
+    to.V = from.V;
+    to.TX = from.TX;
+    to.SX = from.SX;
+    to.TY = from.TY;
+    to.WPB = from.WPB;
+    to.PF = from.PF;
+    to.XCD = from.XCD;
+    to.ORD = from.ORD;
+    to.NT = from.NT;
+    to.align = from.align;
+    to.fp16 = from.fp16;
+    to.BLK = from.BLK;
+    to.GH = from.GH;
+}
+
+}  // namespace
+
 double autotune_plan(Plan& plan, int topk, const std::string& model_path, int batch, TuneMemo* memo) {
     const Pipeline& p = plan.p;
     DeviceScratch sc;
@@ -240,7 +293,10 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
     const std::string tag = hbuf;
 
     double total_us = 0;  // the chosen configurations' times per image
-    for (size_t gi = 0; gi < plan.sched.groups.size(); ++gi) {
+    const size_t G = plan.sched.groups.size();
+    std::vector<double> gtime(G, -1.0);  // each tuned group's time per image
+    std::vector<std::string> gkey(G);
+    for (size_t gi = 0; gi < G; ++gi) {
         if (plan.groups[gi].resample) {
             total_us += time_group_us(plan, plan.groups[gi], sets, st, 20);
             continue;
@@ -255,11 +311,13 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         for (int v : cur.exp) key << v << ',';
         key << '|';
         for (int v : cur.hst) key << v << ',';
+        gkey[gi] = key.str();
         if (memo) {
             auto hit = memo->find(key.str());
             if (hit != memo->end()) {
                 plan.sched.groups[gi] = hit->second.first;
                 total_us += hit->second.second;
+                gtime[gi] = hit->second.second;
                 continue;
             }
         }
@@ -452,10 +510,34 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         }
         plan.sched.groups[gi] = best;
         total_us += best_t / k;
+        gtime[gi] = best_t / k;
         if (memo) (*memo)[key.str()] = {best, best_t / k};
         if (verbose())
             std::fprintf(stderr, "wavetile autotune: group %zu of %zu, %zu candidates, best %.1f us on %d image(s): %s\n",
                          gi + 1, plan.sched.groups.size(), trials.size(), best_t, k, describe_group(best).c_str());
+    }
+    // Groups that compute the same stages on different images (a pyramid's
+    // blurs of each input) are tuned one by one, each from its own
+    // candidates; every one of them takes the fastest configuration any of
+    // them found.
+    std::map<std::string, size_t> fastest;
+    std::vector<std::string> sig(G);
+    for (size_t gi = 0; gi < G; ++gi) {
+        if (gtime[gi] < 0) continue;
+        sig[gi] = group_signature(p, plan.sched.groups[gi]);
+        auto it = fastest.find(sig[gi]);
+        if (it == fastest.end() || gtime[gi] < gtime[it->second]) fastest[sig[gi]] = gi;
+    }
+    for (size_t gi = 0; gi < G; ++gi) {
+        if (gtime[gi] < 0) continue;
+        const size_t j = fastest[sig[gi]];
+        if (j == gi) continue;
+        copy_config(plan.sched.groups[j], plan.sched.groups[gi]);
+        total_us += gtime[j] - gtime[gi];
+        if (memo) (*memo)[gkey[gi]] = {plan.sched.groups[gi], gtime[j]};
+        if (verbose())
+            std::fprintf(stderr, "wavetile autotune: group %zu of %zu takes group %zu's configuration (%.1f against %.1f us per image)\n",
+                         gi + 1, G, j + 1, gtime[j], gtime[gi]);
     }
     build_groups(plan);
     return total_us;
