@@ -307,6 +307,12 @@ def bench_pyramid(args, torch, wt, synth, P, cyc):
 
     def run_mode(mode, model=None):
         plan = plan_pyramid(wt, P, sizes, mode, model)
+        if mode == "autotune":
+            # the autotuner's last step: its candidates timed on this batch
+            t0 = time.time()
+            plan.tune_batch(ins, outs)
+            torch.cuda.synchronize()
+            log(f"pyramid {mode}: tuned on the batch in {time.time() - t0:.1f} s")
         ms = timed(torch, lambda i: plan.run_batch(ins, outs), args.steps, args.warmup, cyc, host_ms_hint=0.5)
         return plan, ms
 

@@ -99,6 +99,8 @@ _sig("wt_plan_run_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.PO
      ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_run_batch_static", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
+_sig("wt_plan_tune_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
+     ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_run_batch_groups", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
      ctypes.POINTER(WtImage), ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_stream_copy", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -349,6 +351,20 @@ class Plan:
             stream = torch.cuda.current_stream()
         s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         _check(lib.wt_plan_run_batch_static(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
+
+    def tune_batch(self, inputs, outputs, stream=None):
+        """Tunes every group's configuration on this batch itself (batched
+        kernels over these images) and rebuilds the plan; outputs then hold
+        the batch's result."""
+        import torch
+        ins = [_image(t) for img in inputs for t in img]
+        outs = [_image(t) for img in outputs for t in img]
+        a_in = (WtImage * len(ins))(*ins)
+        a_out = (WtImage * len(outs))(*outs)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(lib.wt_plan_tune_batch(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
 
     def run_batch_groups(self, first, count, inputs, outputs, stream=None):
         """Launches groups first .. first+count-1 of a batched run directly

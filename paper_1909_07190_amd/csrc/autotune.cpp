@@ -213,6 +213,39 @@ struct PlanHeight {
 
 }  // namespace
 
+// One step from `best` along one configuration axis: V, TX, TY, WPB and PF
+// halved or doubled within their ranges, or V and TX traded at one tile
+// width.
+std::vector<GroupSched> config_neighbours(const GroupSched& best, int vmax) {
+    std::vector<GroupSched> nb;
+    auto step = [&](int GroupSched::*f, int v, int lo, int hi) {
+        if (v < lo || v > hi) return;
+        GroupSched g = best;
+        g.*f = v;
+        if (g.SX > g.TX) g.SX = g.TX;
+        nb.push_back(g);
+    };
+    step(&GroupSched::V, best.V * 2, 1, vmax);
+    step(&GroupSched::V, best.V / 2, 1, vmax);
+    step(&GroupSched::TX, best.TX * 2, 1, 4);
+    step(&GroupSched::TX, best.TX / 2, 1, 4);
+    step(&GroupSched::TY, best.TY * 2, 8, 64);
+    step(&GroupSched::TY, best.TY / 2, 8, 64);
+    step(&GroupSched::WPB, best.WPB * 2, 1, 4);
+    step(&GroupSched::WPB, best.WPB / 2, 1, 4);
+    step(&GroupSched::PF, best.PF * 2, 1, 4);
+    step(&GroupSched::PF, best.PF / 2, 1, 4);
+    for (int f : {2, -2}) {
+        GroupSched g = best;
+        g.V = f > 0 ? best.V * 2 : best.V / 2;
+        g.TX = f > 0 ? best.TX / 2 : best.TX * 2;
+        if (g.V < 1 || g.V > vmax || g.TX < 1 || g.TX > 4 || (f > 0 ? best.TX % 2 : best.V % 2)) continue;
+        g.SX = std::min(g.SX, g.TX);
+        nb.push_back(g);
+    }
+    return nb;
+}
+
 namespace {
 
 // What a group computes, independent of which nodes it computes it for: each
@@ -432,35 +465,8 @@ double autotune_plan(Plan& plan, int topk, const std::string& model_path, int ba
         // each axis coarsely; the optimum often sits one step from its best.
         for (int round = 0; round < 2 && std::isfinite(best_t); ++round) {
             std::vector<GroupSched> nb;
-            auto try_add = [&](GroupSched g) {
+            for (const GroupSched& g : config_neighbours(best, vmax))
                 if (seen.insert(describe_group(g)).second) nb.push_back(g);
-            };
-            auto step = [&](int GroupSched::*f, int v, int lo, int hi) {
-                if (v < lo || v > hi) return;
-                GroupSched g = best;
-                g.*f = v;
-                if (g.SX > g.TX) g.SX = g.TX;
-                try_add(g);
-            };
-            step(&GroupSched::V, best.V * 2, 1, vmax);
-            step(&GroupSched::V, best.V / 2, 1, vmax);
-            step(&GroupSched::TX, best.TX * 2, 1, 4);
-            step(&GroupSched::TX, best.TX / 2, 1, 4);
-            step(&GroupSched::TY, best.TY * 2, 8, 64);
-            step(&GroupSched::TY, best.TY / 2, 8, 64);
-            step(&GroupSched::WPB, best.WPB * 2, 1, 4);
-            step(&GroupSched::WPB, best.WPB / 2, 1, 4);
-            step(&GroupSched::PF, best.PF * 2, 1, 4);
-            step(&GroupSched::PF, best.PF / 2, 1, 4);
-            // the same tile width with wider or narrower vectors per lane
-            for (int f : {2, -2}) {
-                GroupSched g = best;
-                g.V = f > 0 ? best.V * 2 : best.V / 2;
-                g.TX = f > 0 ? best.TX / 2 : best.TX * 2;
-                if (g.V < 1 || g.V > vmax || g.TX < 1 || g.TX > 4 || (f > 0 ? best.TX % 2 : best.V % 2)) continue;
-                g.SX = std::min(g.SX, g.TX);
-                try_add(g);
-            }
             std::vector<GroupRt> more;
             for (auto& g : nb) {
                 GroupRt gr;

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <set>
 
 #include "wt_runtime.h"
 
@@ -354,6 +355,147 @@ void run_plan_batch_static(Plan& plan, int nimg, const wt_image* in, const wt_im
     hip_check(hipMemcpyAsync(st.dargs, st.host.data(), st.host.size(), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     for (int g = 0; g < (int)plan.groups.size(); ++g)
         hip_check(launch_batch_group(plan, st, g, nimg, s), "hipModuleLaunchKernel");
+}
+
+}  // namespace wt
+
+namespace wt {
+
+// Tuning on the batch itself.  A plan made for batches is tuned on a proxy
+// (one tall image of the planning size), which ranks some configurations
+// differently from the uneven images of the real batch.  Here every group's
+// configuration and its neighbours (config_neighbours) are timed as batched
+// kernels over the caller's images, reading the intermediates the previous
+// groups left in the batch's arena, for up to two rounds per group; the
+// fastest is kept.  Changing one group's configuration leaves its inputs
+// and outputs, hence the arena's layout, unchanged.
+void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
+    if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    run_plan_batch(plan, nimg, in, out, stream);  // validates; every intermediate filled
+    hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+    std::vector<std::pair<int, int>> sizes;
+    std::vector<std::map<int, ImgRef>> mem;
+    check_batch(plan, nimg, in, out, sizes, mem);
+    const BatchState& bs = *plan.batch;
+    for (int i = 0; i < nimg; ++i)
+        for (auto& kv : bs.bufs[i]) mem[i][kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
+    const Pipeline& p = plan.p;
+    const size_t tbytes = (size_t)nimg * sizeof(WtArgsHost) + (size_t)(nimg + 1) * sizeof(int);
+    void* dtab = nullptr;
+    if (hipMalloc(&dtab, tbytes) != hipSuccess) fail(WT_E_NOMEM, "batch tuning table");
+    struct Free {
+        void* p;
+        ~Free() { hipFree(p); }
+    } free_tab{dtab};
+    std::vector<char> host(tbytes);
+    OwnedEvents ev;
+
+    // time of one batched launch of candidate `gr` (group gi), microseconds
+    auto time_candidate = [&](GroupRt& gr) -> double {
+        std::memset(host.data(), 0, host.size());
+        int* starts = reinterpret_cast<int*>(host.data() + (size_t)nimg * sizeof(WtArgsHost));
+        int acc = 0;
+        for (int i = 0; i < nimg; ++i) {
+            WtArgsHost& a = reinterpret_cast<WtArgsHost*>(host.data())[i];
+            auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[gr.g.nodes[0]].level);
+            fill_args(plan, gr, mem[i], a, "batch image " + std::to_string(i));
+            check_store_planes(plan, gr, a, d.second);
+            a.W = d.first;
+            a.H = d.second;
+            int tx, ty, w;
+            tile_counts(plan, gr, d.first, d.second, tx, ty, w);
+            a.tiles_x = tx;
+            a.tiles_y = ty;
+            a.nwaves = w;
+            starts[i] = acc;
+            acc += w;
+        }
+        starts[nimg] = acc;
+        hip_check(hipMemcpyAsync(dtab, host.data(), tbytes, hipMemcpyHostToDevice, st), "hipMemcpyAsync");
+        const void* a = dtab;
+        const void* sp = static_cast<char*>(dtab) + (size_t)nimg * sizeof(WtArgsHost);
+        int ni = nimg, tot = acc;
+        void* params[] = {&a, &sp, &ni, &tot};
+        const int units = (tot + gr.g.WPB - 1) / gr.g.WPB;
+        const int grid = std::max(1, std::min(units, 1 << 22));
+        auto launch = [&] {
+            for (size_t i = 0; i < gr.liveouts.size(); ++i) {  // as launch_batch_group does
+                const Node& hn = p.nodes[gr.liveouts[i]];
+                if (hn.kind == Kind::Hist)
+                    hip_check(zero_hist_batch(a, nimg, (int)i, hn.bins, hn.channels, st), "zero_hist_batch");
+            }
+            hip_check(hipModuleLaunchKernel(gr.fn_batch, grid, 1, 1, 64 * gr.g.WPB, 1, 1, 0, st, params, nullptr),
+                      "hipModuleLaunchKernel");
+        };
+        launch();
+        double best = INFINITY;
+        for (int s = 0; s < 3; ++s) {
+            hip_check(hipEventRecord(ev.e0, st), "hipEventRecord");
+            for (int r = 0; r < 3; ++r) launch();
+            hip_check(hipEventRecord(ev.e1, st), "hipEventRecord");
+            hip_check(hipEventSynchronize(ev.e1), "hipEventSynchronize");
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, ev.e0, ev.e1), "hipEventElapsedTime");
+            best = std::min(best, (double)ms * 1e3 / 3);
+        }
+        return best;
+    };
+
+    bool changed = false;
+    for (size_t gi = 0; gi < plan.groups.size(); ++gi) {
+        if (plan.groups[gi].resample || plan.groups[gi].g.BLK) continue;
+        GroupSched best = plan.sched.groups[gi];
+        double best_t = time_candidate(plan.groups[gi]);
+        const double start_t = best_t;
+        std::set<std::string> seen{describe_group(best)};
+        const int vmax = max_vector_width(p, best, plan.W, plan.H, plan.any_width);
+        for (int round = 0; round < 2; ++round) {
+            std::vector<GroupRt> cands;
+            for (const GroupSched& g : config_neighbours(best, vmax)) {
+                if (!seen.insert(describe_group(g)).second) continue;
+                GroupRt gr;
+                gr.g = g;
+                try {
+                    prepare_group(plan, gr, (int)gi);
+                } catch (const Error&) {
+                    continue;
+                }
+                cands.push_back(std::move(gr));
+            }
+            std::vector<GroupRt*> ptrs;
+            for (auto& c : cands) ptrs.push_back(&c);
+            std::vector<bool> bad;
+            compile_groups(plan, ptrs, true, &bad);
+            bool improved = false;
+            for (size_t c = 0; c < cands.size(); ++c) {
+                if (bad[c]) continue;
+                double t = INFINITY;
+                try {
+                    t = time_candidate(cands[c]);
+                } catch (const Error&) {
+                }
+                if (t < best_t) {
+                    best_t = t;
+                    best = cands[c].g;
+                    improved = true;
+                }
+            }
+            for (auto& c : cands) unload_group(c);
+            if (!improved) break;
+        }
+        if (verbose())
+            std::fprintf(stderr, "wavetile batch tuning: group %zu of %zu, %.1f us (was %.1f): %s\n", gi + 1,
+                         plan.groups.size(), best_t, start_t, describe_group(best).c_str());
+        if (describe_group(best) != describe_group(plan.sched.groups[gi])) {
+            plan.sched.groups[gi] = best;
+            changed = true;
+        }
+    }
+    if (!changed) return;
+    build_groups(plan);  // resets the batch state and its graph
+    load_batch_kernels(plan, plan.groups);
+    run_plan_batch(plan, nimg, in, out, stream);
 }
 
 }  // namespace wt

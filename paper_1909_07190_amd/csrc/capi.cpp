@@ -370,6 +370,13 @@ wt_status wt_plan_run_batch_static(wt_plan* plan, int nimg, const wt_image* in, 
     });
 }
 
+wt_status wt_plan_tune_batch(wt_plan* plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
+    return guard([&] {
+        if (!plan) wt::fail(WT_E_INVALID, "null plan");
+        wt::tune_plan_batch(*plan->impl, nimg, in, out, stream);
+    });
+}
+
 wt_status wt_plan_run_batch_groups(wt_plan* plan, int first, int count, int nimg, const wt_image* in,
                                    const wt_image* out, void* stream) {
     return guard([&] {

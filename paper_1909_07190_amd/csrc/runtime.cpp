@@ -467,6 +467,7 @@ void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch, st
 void build_groups(Plan& plan) {
     const Pipeline& p = plan.p;
     plan.batch.reset();
+    plan.batch_static.reset();  // its tile counts and grids follow the groups
     for (auto& g : plan.groups) unload_group(g);
     plan.groups.clear();
     std::vector<bool> in_memory(p.nodes.size(), false);

@@ -170,6 +170,11 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
 // The same batch with its intermediates and argument table in the library's
 // fixed workspace, every group launched directly: no device allocation.
 void run_plan_batch_static(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
+// Times each group's configuration and its neighbours on this batch itself
+// (the batched kernels over the caller's images), keeps the fastest per
+// group, rebuilds the plan and runs the batch once more.
+void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
+std::vector<GroupSched> config_neighbours(const GroupSched& best, int vmax);
 // Compiles and loads the batched kernels of the groups that lack them.
 void load_batch_kernels(const Plan& plan, std::vector<GroupRt>& groups);
 // The fixed workspace (scratch.hip): `device`'s copy, device current.

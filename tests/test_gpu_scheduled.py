@@ -200,3 +200,33 @@ def test_batch_refuses_bad_strides_and_aliases():
     assert run(ok_in, ok_out, first=plan.num_groups) == -1
     assert run(ok_in, ok_out, first=0) == 0
     torch.cuda.synchronize()
+
+
+def test_pyramid_tuned_on_the_batch():
+    """Tuning a plan on the batch itself (every group's configuration and
+    its neighbours timed as batched kernels over these images) leaves a plan
+    whose outputs, written by the tuning call and by a later replay, match
+    the oracle."""
+    import torch
+    import paper_1909_07190_amd as wt
+    spec = P.pyramid_blend(bench.PYR_LEVELS)
+    sizes = synth.batch_sizes(bench.PYR_SEED, bench.PYR_PAIRS)[:5]
+    order = sorted(range(len(sizes)), key=lambda k: sizes[k][0] * sizes[k][1])
+    check = [order[0], order[-1]]
+    tin, tout, host = _pyramid_tensors(torch, sizes, set(check))
+    plan = bench.plan_pyramid(wt, P, sizes, "analytic")
+    before = plan.describe()
+    plan.tune_batch(tin, tout)
+    torch.cuda.synchronize()
+    _say(f"  tuned: {plan.describe().strip()}")
+    for rep in range(2):
+        if rep:
+            tout = [[torch.full((1, h, w), float("nan"), device=tin[0][0].device)] for (w, h) in sizes]
+            plan.run_batch(tin, tout)
+            torch.cuda.synchronize()
+        for i in check:
+            w, h = sizes[i]
+            a, b, m = host[i]
+            ref = oracle.evaluate(spec, {"A": a, "B": b, "M": m})
+            assert_normwise(tout[i][0].cpu().numpy(), ref[spec["outputs"][0]], 1e-5, f"rep {rep} image {i} {w}x{h}")
+    assert len(plan.describe().splitlines()) == len(before.splitlines())
