@@ -337,8 +337,10 @@ wt_status wt_plan_describe(const wt_plan* plan, char* buf, size_t len, size_t* n
  * protocol, on the caller's images instead of a proxy image): runs the
  * batch once, then for every group times its configuration and each
  * neighbouring one (V, TX, TY, WPB, PF one step away) as batched kernels
- * over these images, for up to two rounds, keeps the fastest, rebuilds the
- * plan and runs the batch again, so `out` holds the pipeline's result.
+ * over these images, for up to four rounds, keeps the fastest, rebuilds the
+ * plan and runs the batch again, so `out` holds the pipeline's result.  The
+ * result is cached (in memory and in the plan's cache directory) per
+ * device, starting schedule and image sizes, and reused without timing.
  * Arguments and errors as wt_plan_run_batch; it allocates a small table
  * and compiles candidates (seconds). */
 wt_status wt_plan_tune_batch(wt_plan* plan, int nimg, const wt_image* in, const wt_image* out, void* stream);

@@ -366,8 +366,9 @@ namespace wt {
 // differently from the uneven images of the real batch.  Here every group's
 // configuration and its neighbours (config_neighbours) are timed as batched
 // kernels over the caller's images, reading the intermediates the previous
-// groups left in the batch's arena, for up to two rounds per group; the
-// fastest is kept.  Changing one group's configuration leaves its inputs
+// groups left in the batch's arena, for up to four rounds per group while a
+// round still helps; the fastest is kept, and the result is cached per
+// starting schedule and image sizes.  Changing one group's configuration leaves its inputs
 // and outputs, hence the arena's layout, unchanged.
 void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
     if (plan.no_device) fail(WT_E_INVALID, "plan was created with WT_PLAN_NO_DEVICE");
@@ -381,6 +382,31 @@ void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* o
     for (int i = 0; i < nimg; ++i)
         for (auto& kv : bs.bufs[i]) mem[i][kv.first] = {kv.second.ptr, kv.second.rs, kv.second.cs};
     const Pipeline& p = plan.p;
+    // a batch tuned before (same device, starting schedule and image sizes)
+    // takes the schedule found then
+    std::string key;
+    {
+        hipDeviceProp_t prop;
+        hip_check(hipGetDeviceProperties(&prop, plan.device), "hipGetDeviceProperties");
+        uint64_t h = 1469598103934665603ull;
+        auto mix = [&](const std::string& t) {
+            for (unsigned char c : t) h = (h ^ c) * 1099511628211ull;
+        };
+        mix(schedule_text(plan.sched));
+        for (auto& sz : sizes) mix(std::to_string(sz.first) + "x" + std::to_string(sz.second) + ",");
+        char hb[32];
+        std::snprintf(hb, sizeof hb, "%016llx", (unsigned long long)h);
+        key = std::string("batch|") + prop.gcnArchName + "|" + hb;
+    }
+    std::string cached;
+    if (tune_cache_lookup(plan.cache_dir, key, cached)) {
+        if (cached == schedule_text(plan.sched)) return;
+        plan.sched = parse_schedule(cached, p);
+        build_groups(plan);
+        load_batch_kernels(plan, plan.groups);
+        run_plan_batch(plan, nimg, in, out, stream);
+        return;
+    }
     const size_t tbytes = (size_t)nimg * sizeof(WtArgsHost) + (size_t)(nimg + 1) * sizeof(int);
     void* dtab = nullptr;
     if (hipMalloc(&dtab, tbytes) != hipSuccess) fail(WT_E_NOMEM, "batch tuning table");
@@ -450,7 +476,7 @@ void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* o
         const double start_t = best_t;
         std::set<std::string> seen{describe_group(best)};
         const int vmax = max_vector_width(p, best, plan.W, plan.H, plan.any_width);
-        for (int round = 0; round < 2; ++round) {
+        for (int round = 0; round < 4; ++round) {
             std::vector<GroupRt> cands;
             for (const GroupSched& g : config_neighbours(best, vmax)) {
                 if (!seen.insert(describe_group(g)).second) continue;
@@ -492,6 +518,7 @@ void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* o
             changed = true;
         }
     }
+    tune_cache_store(plan.cache_dir, key, schedule_text(plan.sched));
     if (!changed) return;
     build_groups(plan);  // resets the batch state and its graph
     load_batch_kernels(plan, plan.groups);
