@@ -519,9 +519,11 @@ void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* o
         }
     }
     tune_cache_store(plan.cache_dir, key, schedule_text(plan.sched));
-    if (!changed) return;
-    build_groups(plan);  // resets the batch state and its graph
-    load_batch_kernels(plan, plan.groups);
+    if (changed) {
+        build_groups(plan);  // resets the batch state and its graph
+        load_batch_kernels(plan, plan.groups);
+    }
+    // the candidates wrote the groups' outputs: the plan's own run rewrites them
     run_plan_batch(plan, nimg, in, out, stream);
 }
 
