@@ -683,3 +683,31 @@ def test_histogram_of_an_input_and_of_a_decimated_stage_emulated():
         ref = oracle.evaluate(spec, {"img": img})
         assert np.array_equal(got["h0"], ref["h0"]) and np.array_equal(got["h1"], ref["h1"]), mode
         assert got["h1"].sum() == 19 * 71
+
+
+def test_equalize_u8_emulated_exact():
+    """Equalisation of an 8-bit blurred image by its 256-bin histogram
+    (integer values, exact bins), fused with the blur's kernel's successor."""
+    spec = P.u8_histogram()
+    spec = dict(spec, stages=spec["stages"] + [{"name": "eq", "kind": "equalize", "src": "by", "hist": "h"}],
+                outputs=["eq", "h"])
+    img = synth.integer_image(17, 1, 33, 200, 0, 255)
+    for mode in ("analytic", "unfused"):
+        got, _ = emulate(spec, {"img": img}, mode=mode)
+        ref = oracle.evaluate(spec, {"img": img})
+        assert np.array_equal(got["h"], ref["h"]), mode
+        assert_exact(got["eq"], ref["eq"], mode)
+
+
+def test_histogram_with_fp16_intermediates_emulated():
+    """With FP16 intermediates the fused group counts the FP16-rounded blur:
+    every pixel is counted once, and the counts differ from the FP64
+    oracle's only by values that rounding to FP16 moves across a bin edge."""
+    spec = P.blur_histogram(channels=1, bins=64)
+    img = synth.uniform_image(18, 1, 40, 260)
+    got, _ = emulate(spec, {"img": img}, mode="fixed", fixed="nodes=1,2 V=2 TX=1 SX=0 TY=8 PF=1 hst=3", fp16=True)
+    ref = oracle.evaluate(spec, {"img": img}, keep_all=True)
+    assert got["h"].sum() == 40 * 260
+    t = ref["by"] * 64
+    near = int(np.sum(np.abs(t - np.round(t)) < 64 * 2.0 ** -11))  # within an FP16 step of an edge
+    assert np.abs(got["h"] - ref["h"]).sum() <= 2 * near
