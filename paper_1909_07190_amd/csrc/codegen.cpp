@@ -1437,8 +1437,9 @@ struct BlockGen {
             r.off = lds_elems;
             lds_elems += (r.x1 - r.x0) * (r.y1 - r.y0) * ng.nch;
         }
-        if ((long long)lds_elems * 4 > 64 * 1024)
-            fail(WT_E_UNSUPPORTED, "one-tile-per-workgroup group needs more than 64 KiB of LDS");
+        // a workgroup may hold up to 160 KiB of LDS on gfx950
+        if ((long long)lds_elems * 4 > 160 * 1024)
+            fail(WT_E_UNSUPPORTED, "one-tile-per-workgroup group needs more than 160 KiB of LDS");
     }
     const NodeGeom& G(int id) const { return geo.nodes.at(geo.index.at(id)); }
     static std::string I(long long v) { return std::to_string(v); }

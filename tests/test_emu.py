@@ -246,6 +246,7 @@ def test_pyramid_schedule_expands_and_decimates():
     (UM, "nodes=1,2,3,4 V=1 TX=1 TY=16 WPB=4 BLK=1", 140, 37),
     (HARRIS_EXACT, "nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=1 TY=8 WPB=8 BLK=1", 90, 21),
     (BLUR, "nodes=1,2 V=2 TX=1 TY=8 WPB=16 BLK=1", 260, 20),
+    (UM, "nodes=1,2,3,4 V=2 TX=1 TY=32 WPB=4 BLK=1", 300, 70),   # 85 KiB of LDS
 ])
 def test_one_tile_per_workgroup_emulated(spec, fixed, w, h):
     if spec["inputs"][0].get("dtype") == "u8":

@@ -411,6 +411,8 @@ def test_fused_resampling(fixed, w, h):
     ("blur", "nodes=1,2 V=2 TX=1 TY=16 WPB=4 BLK=1", 300, 77),
     ("unsharp", "nodes=1,2,3,4 V=2 TX=1 TY=8 WPB=4 BLK=1", 260, 96),
     ("harris", "nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=1 TY=8 WPB=4 BLK=1", 200, 50),
+    ("unsharp", "nodes=1,2,3,4 V=2 TX=1 TY=32 WPB=4 BLK=1", 600, 150),                # 85 KiB of LDS
+    ("harris", "nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=1 TY=32 WPB=4 BLK=1", 300, 130),  # 114 KiB of LDS
 ])
 def test_one_tile_per_workgroup(name, fixed, w, h):
     _say(f"otptb {name} {fixed} {w}x{h}")
