@@ -189,10 +189,13 @@ enum {
                                workgroups resident at once, each looping over
                                its share of the work units (persistent); by
                                default every work unit gets a workgroup */
-    WT_PLAN_NO_FOLD = 32    /* the fusion search keeps every up2 out of the
+    WT_PLAN_NO_FOLD = 32,   /* the fusion search keeps every up2 out of the
                                groups (read by expansion in its consumers'
                                groups) instead of folding an up2 of a
                                decimated stage into that stage's group */
+    WT_PLAN_BATCH_WHOLE = 64 /* wt_plan_run_batch runs the whole group
+                               sequence as one persistent launch (see
+                               wt_plan_run_batch) */
 };
 
 /* WT_SCHED_AUTOTUNE results are cached, keyed by the device architecture,
@@ -271,9 +274,30 @@ wt_status wt_plan_run(wt_plan* plan, const wt_image* in, int nin,
  * Intermediates live in a plan-owned arena sized for the shape.  Images of
  * 8- or 16-bit integer elements must satisfy the plan's vector-width
  * alignment (plan with WT_PLAN_ANY_WIDTH for arbitrary widths).
+ * With WT_PLAN_BATCH_WHOLE the graph holds a single persistent launch of one
+ * kernel that contains every group (the paper's fusion taken across the
+ * groups a kernel boundary would separate, Sections 4 and 5, with the
+ * ordering of the kernel boundaries kept by device-side counters): waves take
+ * chunks of consecutive tiles of one group and one image in group order
+ * from an atomic ticket and start a chunk once every producer group has
+ * finished that image.  Plans whose groups are all wave-tiled fused groups
+ * only (WT_E_UNSUPPORTED for lone resampling, histogram, equalize or
+ * one-tile-per-workgroup groups, and beyond 64 groups); outputs equal the
+ * per-group launches' bit for bit (on the host's lane emulation).  Every
+ * wait is bounded (two seconds); wt_plan_batch_check reports a launch that
+ * gave up.  Switched off for now: with WT_PLAN_BATCH_WHOLE this call
+ * returns WT_E_UNSUPPORTED before any launch (its first device run did not
+ * complete and the cause is not yet known); wt_plan_source(plan, -1, ...)
+ * still returns the kernel.
  * Asynchronous on `hip_stream`. */
 wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in,
                             const wt_image* out, void* hip_stream);
+
+/* Synchronises `hip_stream` and returns WT_E_INTERNAL if a wave of the
+ * plan's last whole-pipeline batch launch (WT_PLAN_BATCH_WHOLE) gave up
+ * waiting for a producer group (its outputs are then not valid); WT_SUCCESS
+ * otherwise, and for plans without such a launch. */
+wt_status wt_plan_batch_check(wt_plan* plan, void* hip_stream);
 
 /* Bytes of device memory in the library's fixed workspace: one copy on each
  * GPU that wt_plan_run_batch_static runs on, held until the process ends. */
@@ -345,7 +369,9 @@ wt_status wt_plan_describe(const wt_plan* plan, char* buf, size_t len, size_t* n
  * and compiles candidates (seconds). */
 wt_status wt_plan_tune_batch(wt_plan* plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
 
-/* HIP source generated for group `group`. */
+/* HIP source generated for group `group`; group -1: the whole-pipeline
+ * kernel of WT_PLAN_BATCH_WHOLE (generated on each call, for any plan;
+ * WT_E_UNSUPPORTED where that launch is refused). */
 wt_status wt_plan_source(const wt_plan* plan, int group, char* buf, size_t len,
                          size_t* needed);
 

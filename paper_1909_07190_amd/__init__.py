@@ -38,6 +38,7 @@ PLAN_NO_COMPILE = 4
 PLAN_RETUNE = 8
 PLAN_BATCH_RESIDENT = 16
 PLAN_NO_FOLD = 32
+PLAN_BATCH_WHOLE = 64
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 
@@ -99,6 +100,7 @@ _sig("wt_plan_run_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.PO
      ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_run_batch_static", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
+_sig("wt_plan_batch_check", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
 _sig("wt_plan_tune_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_run_batch_groups", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -199,7 +201,7 @@ class Pipeline:
     def plan(self, width, height, mode="analytic", fp16=False, fixed=None,
              no_device=False, model_path=None, cache_dir=None, autotune_topk=0,
              any_width=False, no_compile=False, retune=False, batch_images=1,
-             batch_resident=False, no_fold=False) -> "Plan":
+             batch_resident=False, no_fold=False, batch_whole=False) -> "Plan":
         """Schedules and compiles the pipeline for width x height.  mode
         "mlp" without a model_path uses the network trained on gfx950
         measurements that ships with the package (GFX950_COST_MODEL).  Mode
@@ -211,11 +213,14 @@ class Pipeline:
         launches only the workgroups resident at once, each looping over its
         share of the tiles, instead of one workgroup per work unit.
         `no_fold`: the fusion search never folds an up2 into the group of
-        the stage whose decimation it expands."""
+        the stage whose decimation it expands.  `batch_whole`: run_batch
+        runs every group in one persistent launch (wave-tiled fused groups
+        only), ordered by device-side completion counters."""
         if mode == "mlp" and model_path is None:
             model_path = GFX950_COST_MODEL
         return Plan(self, width, height, mode, fp16, fixed, no_device, model_path, cache_dir,
-                    autotune_topk, any_width, no_compile, retune, batch_images, batch_resident, no_fold)
+                    autotune_topk, any_width, no_compile, retune, batch_images, batch_resident, no_fold,
+                    batch_whole)
 
 
 def stream_copy(src, dst, stream=None):
@@ -291,11 +296,12 @@ class Plan:
 
     def __init__(self, pipe: Pipeline, width, height, mode, fp16, fixed, no_device,
                  model_path, cache_dir, autotune_topk, any_width=False, no_compile=False, retune=False,
-                 batch_images=1, batch_resident=False, no_fold=False):
+                 batch_images=1, batch_resident=False, no_fold=False, batch_whole=False):
         self.pipe = pipe  # keeps the pipeline alive
         flags = ((PLAN_NO_DEVICE if no_device else 0) | (PLAN_ANY_WIDTH if any_width else 0)
                  | (PLAN_NO_COMPILE if no_compile else 0) | (PLAN_RETUNE if retune else 0)
-                 | (PLAN_BATCH_RESIDENT if batch_resident else 0) | (PLAN_NO_FOLD if no_fold else 0))
+                 | (PLAN_BATCH_RESIDENT if batch_resident else 0) | (PLAN_NO_FOLD if no_fold else 0)
+                 | (PLAN_BATCH_WHOLE if batch_whole else 0))
         opts = WtSchedOpts(SCHED[mode], int(bool(fp16)), flags,
                            autotune_topk, fixed.encode() if fixed else None,
                            model_path.encode() if model_path else None,
@@ -351,6 +357,15 @@ class Plan:
             stream = torch.cuda.current_stream()
         s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         _check(lib.wt_plan_run_batch_static(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
+
+    def batch_check(self, stream=None):
+        """Synchronises `stream` and raises if the last whole-pipeline batch
+        launch gave up waiting for a producer group."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        _check(lib.wt_plan_batch_check(self._h, ctypes.c_void_p(s)))
 
     def tune_batch(self, inputs, outputs, stream=None):
         """Tunes every group's configuration on this batch itself (batched

@@ -81,6 +81,128 @@ hipError_t launch_batch_group(const Plan& plan, const BatchState& st, int g, int
     return hipModuleLaunchKernel(gr.fn_batch, st.grid[g], 1, 1, threads, 1, 1, 0, s, params, nullptr);
 }
 
+// Host mirror of the whole-pipeline kernel's argument (WtWhole in the
+// generated source).
+struct WtWholeHost {
+    const void* AB;
+    const void* start;
+    const void* chunks;
+    const void* deps;
+    void* done;
+    void* next;
+    void* status;
+    long long limit;
+    int nchunks, nimg;
+};
+static_assert(sizeof(WtWholeHost) == 72, "WtWhole layout");
+
+// Ticks of the device's constant-rate clock in two seconds: the longest a
+// wave of the whole-pipeline kernel waits for a producer (a launch of the
+// largest batches takes milliseconds).
+long long whole_wait_limit(int device) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || khz <= 0) khz = 100000;
+    return 2000LL * khz;
+}
+
+// The whole group sequence as one launch: the counters cleared by a kernel
+// (graph-safe), then the persistent kernel.
+hipError_t launch_whole(const Plan& plan, const BatchState& st, int nimg, hipStream_t s) {
+    char* base = static_cast<char*>(st.dargs);
+    const int G = (int)plan.groups.size();
+    hipError_t e = zero_hist(base + st.ctr_off, 0, st.ctr_words, 1, s);
+    if (e != hipSuccess) return e;
+    WtWholeHost w;
+    w.AB = base;
+    w.start = base + st.args_bytes;
+    w.chunks = base + st.whole_off;
+    w.deps = base + st.whole_off + (size_t)st.nchunks * 16;
+    w.done = base + st.ctr_off;
+    w.next = base + st.ctr_off + (size_t)G * nimg * 4;
+    w.status = base + st.ctr_off + ((size_t)G * nimg + 1) * 4;
+    w.limit = whole_wait_limit(plan.device);
+    w.nchunks = st.nchunks;
+    w.nimg = nimg;
+    void* params[] = {&w};
+    return hipModuleLaunchKernel(plan.whole_fn, st.whole_grid, 1, 1, 64 * plan.whole_wpb, 1, 1, 0, s, params, nullptr);
+}
+
+}  // namespace
+
+std::string whole_kernel_source(const Plan& plan, std::string& kname) {
+    std::vector<const GroupSched*> gs;
+    std::vector<const GroupGeom*> geos;
+    uint64_t h = 1469598103934665603ull;
+    for (const auto& gr : plan.groups) {
+        if (gr.resample) fail(WT_E_UNSUPPORTED, "whole-pipeline launch of a lone resampling or histogram group");
+        gs.push_back(&gr.g);
+        geos.push_back(&gr.geo);
+        for (unsigned char c : gr.kname + ";") h = (h ^ c) * 1099511628211ull;
+    }
+    char hb[32];
+    std::snprintf(hb, sizeof hb, "%012llx", (unsigned long long)(h & 0xffffffffffffull));
+    kname = std::string("wt_whole_") + hb;
+    int lds = 0;
+    return generate_whole_source(plan.p, gs, geos, kname, plan.whole_wpb, lds);
+}
+
+namespace {
+
+// The whole-pipeline kernel of the plan's groups, generated, compiled and
+// loaded once per grouping.
+void load_whole_kernel(Plan& plan) {
+    if (plan.whole_fn) return;
+    std::string kname;
+    std::string src = whole_kernel_source(plan, kname);
+    std::vector<char> code = compile_hip(src, kname, plan.cache_dir);
+    hip_check(hipModuleLoadData(&plan.whole_mod, code.data()), "hipModuleLoadData");
+    hip_check(hipModuleGetFunction(&plan.whole_fn, plan.whole_mod, kname.c_str()), "hipModuleGetFunction");
+    plan.whole_src = src;
+    plan.whole_kname = kname;
+}
+
+// Chunks, producer masks and counters of the whole-pipeline launch for the
+// batch shape of `st` (after layout_batch): each group's tiles of each image
+// cut into chunks of k consecutive tiles, k chosen so that a group spreads
+// over about eight chunks per resident wave (at most 64 tiles a chunk).
+void layout_whole(const Plan& plan, BatchState& st) {
+    const int G = (int)plan.groups.size(), nimg = (int)st.sizes.size();
+    const int per_cu = resident_blocks_per_cu(plan, plan.whole_fn, 64 * plan.whole_wpb);
+    const long long rw = (long long)per_cu * plan.machine.ncu * plan.whole_wpb;
+    st.chunk_tab.clear();
+    st.dep_tab.assign(G, 0ull);
+    for (int g = 0; g < G; ++g) {
+        const GroupRt& gr = plan.groups[g];
+        for (int l : gr.loaded)
+            for (int q = 0; q < g; ++q)
+                if (std::find(plan.groups[q].liveouts.begin(), plan.groups[q].liveouts.end(), l) !=
+                    plan.groups[q].liveouts.end())
+                    st.dep_tab[g] |= 1ull << q;
+        const int k = (int)std::max(1LL, std::min(64LL, (long long)st.total[g] / (8 * rw)));
+        for (int i = 0; i < nimg; ++i) {
+            const int n = st.tiles[(size_t)g * nimg + i][2];
+            for (int t = 0; t < n; t += k) {
+                st.chunk_tab.insert(st.chunk_tab.end(), {g, i, t, std::min(k, n - t)});
+            }
+        }
+    }
+    st.nchunks = (int)(st.chunk_tab.size() / 4);
+    st.whole_grid = (int)std::max(1LL, std::min((long long)st.nchunks, (long long)per_cu * plan.machine.ncu));
+    st.whole_off = (st.dargs_bytes + 15) / 16 * 16;
+    const size_t tab_end = st.whole_off + (size_t)st.nchunks * 16 + (size_t)G * 8;
+    st.ctr_off = (tab_end + 255) / 256 * 256;
+    st.ctr_words = G * nimg + 2;
+    st.host.resize(tab_end);
+    st.dargs_bytes = st.ctr_off + (size_t)st.ctr_words * 4;
+}
+
+// The chunk table and producer masks into the host table (after fill_table).
+void fill_whole(BatchState& st) {
+    std::memcpy(st.host.data() + st.whole_off, st.chunk_tab.data(), st.chunk_tab.size() * sizeof(int));
+    std::memcpy(st.host.data() + st.whole_off + (size_t)st.nchunks * 16, st.dep_tab.data(),
+                st.dep_tab.size() * sizeof(unsigned long long));
+}
+
 void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, int& ty, int& work) {
     const Pipeline& p = plan.p;
     if (gr.resample) {
@@ -276,10 +398,21 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
     std::vector<std::map<int, ImgRef>> mem;
     check_batch(plan, nimg, in, out, sizes, mem);
 
+    const bool whole = plan.batch_whole;
+    // The whole-pipeline launch is generated, compiled and checked on the
+    // host (the lane emulator runs it bit-identical to the per-group
+    // launches), but its first device run did not finish within three
+    // minutes and the cause has not been found; until it is, device runs
+    // are refused here, before any allocation or launch.
+    if (whole && all)
+        fail(WT_E_UNSUPPORTED, "the whole-pipeline batch launch (WT_PLAN_BATCH_WHOLE) is switched off on the "
+                               "device: its first run did not complete and the cause is not yet known");
     if (!plan.batch || plan.batch->sizes != sizes) {
         plan.batch.reset();
         load_batch_kernels(plan, plan.groups);  // compiled on first use
+        if (whole) load_whole_kernel(plan);
         auto st = layout_batch(plan, sizes);
+        if (whole) layout_whole(plan, *st);
         void* arena = nullptr;
         void* dargs = nullptr;
         if (st->arena_bytes && hipMalloc(&arena, st->arena_bytes) != hipSuccess)
@@ -291,8 +424,8 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
         hipStream_t cs;
         hip_check(hipStreamCreate(&cs), "hipStreamCreate");
         hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-        for (int g = 0; g < G; ++g) {
-            hipError_t e = launch_batch_group(plan, *st, g, nimg, cs);
+        for (int g = 0; g < (whole ? 1 : G); ++g) {
+            hipError_t e = whole ? launch_whole(plan, *st, nimg, cs) : launch_batch_group(plan, *st, g, nimg, cs);
             if (e != hipSuccess) {
                 hipGraph_t tmp;
                 hipStreamEndCapture(cs, &tmp);
@@ -309,6 +442,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
 
     BatchState& st = *plan.batch;
     fill_table(plan, st, mem);
+    if (st.ctr_words) fill_whole(st);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // the table changes only when the caller's image pointers or strides do
     if (st.uploaded != st.host) {
@@ -321,6 +455,16 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
     }
     for (int g = first; g < first + count; ++g)
         hip_check(launch_batch_group(plan, st, g, nimg, s), "hipModuleLaunchKernel");
+}
+
+void check_batch_status(Plan& plan, void* stream) {
+    if (!plan.batch || !plan.batch->ctr_words) return;
+    const BatchState& st = *plan.batch;
+    hip_check(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)), "hipStreamSynchronize");
+    int status = 0;
+    const char* at = static_cast<const char*>(st.dargs) + st.ctr_off + (size_t)(st.ctr_words - 1) * 4;
+    hip_check(hipMemcpy(&status, at, sizeof status, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (status) fail(WT_E_INTERNAL, "a wave of the whole-pipeline launch gave up waiting for a producer group");
 }
 
 void run_plan_batch_static(Plan& plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {

@@ -370,6 +370,13 @@ wt_status wt_plan_run_batch_static(wt_plan* plan, int nimg, const wt_image* in, 
     });
 }
 
+wt_status wt_plan_batch_check(wt_plan* plan, void* stream) {
+    return guard([&] {
+        if (!plan) wt::fail(WT_E_INVALID, "null plan");
+        wt::check_batch_status(*plan->impl, stream);
+    });
+}
+
 wt_status wt_plan_tune_batch(wt_plan* plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
     return guard([&] {
         if (!plan) wt::fail(WT_E_INVALID, "null plan");
@@ -405,12 +412,18 @@ wt_status wt_plan_describe(const wt_plan* plan, char* buf, size_t len, size_t* n
 }
 
 wt_status wt_plan_source(const wt_plan* plan, int group, char* buf, size_t len, size_t* needed) {
+    std::string whole;
     wt_status st = guard([&] {
         if (!plan) wt::fail(WT_E_INVALID, "null plan");
-        if (group < 0 || group >= (int)plan->impl->groups.size()) wt::fail(WT_E_INVALID, "group out of range");
+        if (group == -1) {
+            std::string kname;
+            whole = wt::whole_kernel_source(*plan->impl, kname);
+        } else if (group < 0 || group >= (int)plan->impl->groups.size()) {
+            wt::fail(WT_E_INVALID, "group out of range");
+        }
     });
     if (st != WT_OK) return st;
-    return copy_out(plan->impl->groups[group].src, buf, len, needed);
+    return copy_out(group == -1 ? whole : plan->impl->groups[group].src, buf, len, needed);
 }
 
 wt_status wt_plan_group_info(const wt_plan* plan, int group, wt_group_info* out) {

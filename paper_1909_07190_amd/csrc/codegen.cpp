@@ -1278,6 +1278,13 @@ struct Gen {
         if (geo.lds_bytes <= 0) return;
         line("__shared__ __attribute__((aligned(16))) char wt_lds[" + I(geo.lds_bytes_per_wg) + "];");
         line("char* lds = wt_lds + (threadIdx.x >> 6) * " + I(geo.lds_bytes) + ";");
+        lds_ptrs();
+    }
+
+    // The nodes' LDS sub-tiles (and histogram bins, tables) in the wave's
+    // LDS `lds`.
+    void lds_ptrs() {
+        if (geo.lds_bytes <= 0) return;
         if (!geo.hist.empty()) line("unsigned int* hb = (unsigned int*)(lds + " + I(geo.hist_lds_off) + ");");
         if (!geo.tables.empty()) line("unsigned int* tb = (unsigned int*)(lds + " + I(geo.table_lds_off) + ");");
         for (auto& n : geo.nodes)
@@ -1378,6 +1385,17 @@ struct Gen {
         line("}");
         ind.resize(ind.size() - 4);
         line("}");
+        o << "}\n";
+        return o.str();
+    }
+
+    // Wave tile `wid` of the image `A` as a device function of the
+    // whole-pipeline kernel, with the wave's LDS at `lds`.
+    std::string tile_function(const std::string& fname) {
+        o << "WT_DEV void " << fname << "(const WtArgs& A, const int wid, const int lane, char* lds) {\n";
+        line("(void)lds;");
+        lds_ptrs();
+        tile();
         o << "}\n";
         return o.str();
     }
@@ -1680,6 +1698,112 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const
     gb.o.str("");
     std::string batch = gb.batch_kernel(kname);
     return GroupSources{device_prelude(), "", single, batch};
+}
+
+// The whole group sequence of a batch in one persistent launch.  A chunk is
+// a run of consecutive wave tiles of one group and one image; chunks are
+// numbered group by group (all chunks of group g before those of g + 1) and
+// handed out in that order by an atomic ticket, one chunk per wave at a
+// time.  Before its chunk a wave waits until every producer group of its
+// group has completed all its tiles of the same image (the per-image
+// completion counters; images of a batch are independent), and after it
+// adds its tile count to its own group's counter.  A wave waits only for
+// chunks with smaller tickets, which waves already running hold, so the
+// smallest unfinished chunk can always proceed and the launch cannot
+// deadlock at any grid size; every wait is also bounded in time (after
+// `limit` ticks of the constant-rate clock the status word is set and all
+// waits end, so every wave still reaches the end of the queue).
+std::string generate_whole_source(const Pipeline& p, const std::vector<const GroupSched*>& gs,
+                                  const std::vector<const GroupGeom*>& geos, const std::string& kname, int wpb,
+                                  int& lds_per_wave) {
+    if (gs.empty() || gs.size() > 64) fail(WT_E_UNSUPPORTED, "whole-pipeline launch needs 1 to 64 groups");
+    if (wpb < 1 || wpb > 16) fail(WT_E_INVALID, "whole-pipeline launch: 1 to 16 waves per workgroup");
+    lds_per_wave = 0;
+    for (size_t k = 0; k < gs.size(); ++k) {
+        if (gs[k]->BLK) fail(WT_E_UNSUPPORTED, "whole-pipeline launch of a one-tile-per-workgroup group");
+        if (!geos[k]->hist.empty() || !geos[k]->tables.empty())
+            fail(WT_E_UNSUPPORTED, "whole-pipeline launch of a histogram or equalize stage");
+        if ((int)(geos[k]->loaded.size()) > 16 || (int)(geos[k]->liveouts.size() + geos[k]->dec.size()) > 16)
+            fail(WT_E_UNSUPPORTED, "group has more than 16 inputs or live-outs");
+        lds_per_wave = std::max(lds_per_wave, (geos[k]->lds_bytes + 15) / 16 * 16);
+    }
+    if ((long long)lds_per_wave * wpb > 160 * 1024)
+        fail(WT_E_UNSUPPORTED, "whole-pipeline launch needs more than 160 KiB of LDS per workgroup");
+    std::ostringstream o;
+    o << device_prelude() << "\n";
+    o << "struct WtWhole {\n"
+         "    const WtArgs* AB;                 // [group][image] kernel arguments\n"
+         "    const int* start;                 // [group][image + 1] tile prefix sums\n"
+         "    const wt_i4* chunks;              // group, image, first tile, tiles\n"
+         "    const unsigned long long* deps;   // [group] producer groups (bit mask)\n"
+         "    int* done;                        // [group][image] completed tiles\n"
+         "    int* next;                        // ticket counter\n"
+         "    int* status;                      // non-zero once a wait gave up\n"
+         "    long long limit;                  // longest wait, clock ticks\n"
+         "    int nchunks, nimg;\n"
+         "};\n";
+    for (size_t k = 0; k < gs.size(); ++k) {
+        Gen gen(p, *gs[k], *geos[k]);
+        gen.header();
+        o << gen.o.str();
+        gen.o.str("");
+        o << gen.tile_function(kname + "_g" + std::to_string(k));
+    }
+    o << "WT_DEV void " << kname << "_wait(const WtWhole& P, unsigned long long dm, const int img) {\n"
+         "    const unsigned long long t0 = wall_clock64();\n"
+         "    for (; dm; dm &= dm - 1) {\n"
+         "        const int q = __builtin_ctzll(dm);\n"
+         "        const int need = P.start[q * (P.nimg + 1) + img + 1] - P.start[q * (P.nimg + 1) + img];\n"
+         "        while (__hip_atomic_load(P.done + q * P.nimg + img, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {\n"
+         "            if (__hip_atomic_load(P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;\n"
+         "            if ((long long)(wall_clock64() - t0) > P.limit) {\n"
+         "                __hip_atomic_store(P.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
+         "                return;\n"
+         "            }\n"
+         "            __builtin_amdgcn_s_sleep(2);\n"
+         "        }\n"
+         "    }\n"
+         "}\n";
+    o << "extern \"C\" __global__ void __launch_bounds__(" << 64 * wpb << ") " << kname << "(const WtWhole P) {\n";
+    o << "    const int lane = threadIdx.x & 63;\n";
+    if (lds_per_wave > 0) {
+        o << "    __shared__ __attribute__((aligned(16))) char wt_lds[" << lds_per_wave * wpb << "];\n";
+        o << "    char* lds = wt_lds + (threadIdx.x >> 6) * " << lds_per_wave << ";\n";
+    } else {
+        o << "    char* lds = nullptr;\n";
+    }
+    o << "    for (;;) {\n"
+         "        int c = 0;\n"
+         "        if (lane == 0) c = __hip_atomic_fetch_add(P.next, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
+         "        c = __builtin_amdgcn_readfirstlane(c);\n"
+         "        if (c >= P.nchunks) break;\n"
+         "        const wt_i4 ch = P.chunks[c];\n"
+         "        const int g = __builtin_amdgcn_readfirstlane(ch.x), img = __builtin_amdgcn_readfirstlane(ch.y);\n"
+         "        const int t0 = __builtin_amdgcn_readfirstlane(ch.z), nt = __builtin_amdgcn_readfirstlane(ch.w);\n"
+         "        const unsigned long long dm = P.deps[g];\n"
+         "        if (dm) {\n"
+         "            if (lane == 0) " << kname << "_wait(P, dm, img);\n"
+         "            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, \"agent\");\n"
+         "        }\n"
+         "        wt_wave_sync();  // the previous chunk's LDS reads before this chunk's stores\n"
+         "        switch (g) {\n";
+    // a private copy of the arguments per tile, as in the batched kernels:
+    // the fields the group uses are loaded into registers at each tile
+    // rather than held across the chunk's tiles
+    for (size_t k = 0; k < gs.size(); ++k)
+        o << "        case " << k << ":\n"
+          << "            for (int t = t0; t < t0 + nt; ++t) {\n"
+          << "                const WtArgs A = P.AB[g * P.nimg + img];\n"
+          << "                " << kname << "_g" << k << "(A, t, lane, lds);\n"
+          << "            }\n"
+          << "            break;\n";
+    o << "        default: break;\n"
+         "        }\n"
+         "        __builtin_amdgcn_fence(__ATOMIC_RELEASE, \"agent\");\n"
+         "        if (lane == 0) __hip_atomic_fetch_add(P.done + g * P.nimg + img, nt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);\n"
+         "    }\n"
+         "}\n";
+    return o.str();
 }
 
 // 2x resampling kernels (not fused: a scaled dependence ends a group in this

@@ -84,6 +84,7 @@ void name_sources(GroupRt& gr, GroupSources gs, int gi) {
 
 Plan::~Plan() {
     batch.reset();
+    unload_whole(*this);
     for (auto& g : groups) unload_group(g);
     for (auto& b : bufs)
         if (b.second.ptr) hipFree(b.second.ptr);
@@ -216,6 +217,7 @@ void copy_settings(const Plan& from, Plan& to) {
     to.fp16 = from.fp16;
     to.any_width = from.any_width;
     to.batch_resident = from.batch_resident;
+    to.batch_whole = from.batch_whole;
     to.setup_stream = from.setup_stream;
     to.cache_dir = from.cache_dir;
     to.machine = from.machine;
@@ -239,6 +241,7 @@ std::unique_ptr<Plan> create_plan(const Pipeline& p, const wt_sched_opts* o, int
     plan->fp16 = opts.fp16_intermediates != 0;
     plan->any_width = (opts.flags & WT_PLAN_ANY_WIDTH) != 0;
     plan->batch_resident = (opts.flags & WT_PLAN_BATCH_RESIDENT) != 0;
+    plan->batch_whole = (opts.flags & WT_PLAN_BATCH_WHOLE) != 0;
     plan->setup_stream = reinterpret_cast<hipStream_t>(stream);
     const char* env_cache = std::getenv("WT_CACHE_DIR");
     plan->cache_dir = opts.cache_dir ? opts.cache_dir : (env_cache ? env_cache : "");
@@ -410,6 +413,14 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi) {
         fail(WT_E_UNSUPPORTED, "group needs " + std::to_string(gr.geo.lds_bytes_per_wg) + " bytes of LDS per workgroup");
 }
 
+void unload_whole(Plan& plan) {
+    if (plan.whole_mod) hipModuleUnload(plan.whole_mod);
+    plan.whole_mod = nullptr;
+    plan.whole_fn = nullptr;
+    plan.whole_src.clear();
+    plan.whole_kname.clear();
+}
+
 void unload_group(GroupRt& gr) {
     if (gr.mod) hipModuleUnload(gr.mod);
     if (gr.mod_batch) hipModuleUnload(gr.mod_batch);
@@ -468,6 +479,7 @@ void build_groups(Plan& plan) {
     const Pipeline& p = plan.p;
     plan.batch.reset();
     plan.batch_static.reset();  // its tile counts and grids follow the groups
+    unload_whole(plan);
     for (auto& g : plan.groups) unload_group(g);
     plan.groups.clear();
     std::vector<bool> in_memory(p.nodes.size(), false);

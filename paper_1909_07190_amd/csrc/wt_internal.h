@@ -262,6 +262,12 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g,
 GroupSources generate_resample_source(const Pipeline& p, const GroupSched& g,
                                       const std::string& kname, bool src_half, bool dst_half);
 // A lone histogram stage: counts its source read from memory.
+// The batch's whole group sequence as one persistent kernel `kname`
+// (wave-tiled fused groups only; `wpb` waves per workgroup); sets
+// `lds_per_wave` to the LDS each wave holds.
+std::string generate_whole_source(const Pipeline& p, const std::vector<const GroupSched*>& gs,
+                                  const std::vector<const GroupGeom*>& geos, const std::string& kname, int wpb,
+                                  int& lds_per_wave);
 GroupSources generate_hist_source(const Pipeline& p, const GroupSched& g, const std::string& kname, bool src_half);
 // Output pixels one 256-thread workgroup of a resampling kernel covers:
 // down2 64 x 4 (a pixel per thread), up2 128 x 8 (a 2x2 quad per thread);

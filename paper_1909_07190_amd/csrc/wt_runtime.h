@@ -65,6 +65,13 @@ struct BatchState {
     size_t args_bytes = 0, dargs_bytes = 0;
     std::vector<char> host;                // host copy of the table
     std::vector<char> uploaded;            // the table as last copied to the device
+    // whole-pipeline launch (WT_PLAN_BATCH_WHOLE): chunk table and producer
+    // masks at whole_off in the table, completion counters (zeroed by a
+    // kernel before every launch) at ctr_off
+    size_t whole_off = 0, ctr_off = 0;
+    int nchunks = 0, ctr_words = 0, whole_grid = 0;
+    std::vector<int> chunk_tab;                    // 4 ints per chunk
+    std::vector<unsigned long long> dep_tab;       // per group
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool owned = true;                     // arena and table allocated for this state
@@ -84,6 +91,12 @@ struct Plan {
     bool fp16 = false;
     bool any_width = false;
     bool batch_resident = false;  // WT_PLAN_BATCH_RESIDENT
+    bool batch_whole = false;     // WT_PLAN_BATCH_WHOLE
+    // the whole-pipeline kernel of the current groups (loaded on first use)
+    std::string whole_src, whole_kname;
+    hipModule_t whole_mod = nullptr;
+    hipFunction_t whole_fn = nullptr;
+    int whole_wpb = 2;
     hipStream_t setup_stream = nullptr;  // caller's stream for planning-time measurements
     std::string cache_dir;
     std::unique_ptr<BatchState> batch;
@@ -153,6 +166,8 @@ void prepare_group(const Plan& plan, GroupRt& gr, int gi);
 void compile_groups(const Plan& plan, std::vector<GroupRt*>& grs, bool batch = false,
                     std::vector<bool>* failed = nullptr);
 void unload_group(GroupRt& gr);
+// Releases the plan's whole-pipeline kernel (its groups changed or the plan ends).
+void unload_whole(Plan& plan);
 // Validates a caller image against node `n` at W x H (null data, size,
 // channels, element type, strides); returns its dense-resolved strides.
 ImgRef check_image(const wt_image& im, const Node& n, int W, int H, const std::string& tag);
@@ -177,6 +192,11 @@ void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* o
 std::vector<GroupSched> config_neighbours(const GroupSched& best, int vmax);
 // Compiles and loads the batched kernels of the groups that lack them.
 void load_batch_kernels(const Plan& plan, std::vector<GroupRt>& groups);
+// Source of the whole-pipeline kernel of the plan's groups (named `kname`).
+std::string whole_kernel_source(const Plan& plan, std::string& kname);
+// WT_E_INTERNAL when the last whole-pipeline launch of the plan's batch gave
+// up waiting for a producer (after synchronising `stream`).
+void check_batch_status(Plan& plan, void* stream);
 // The fixed workspace (scratch.hip): `device`'s copy, device current.
 void* static_scratch(int device, hipError_t* err);
 // Measures candidate configurations of every fused group and keeps the

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <barrier>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -60,6 +61,12 @@ static inline int wt_emu_dpp(int old, int src, int ctrl, bool bound_ctrl) {
 #define __builtin_amdgcn_fence(a, b) ((void)0)
 // atomics: the lanes are threads
 #define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_RELAXED)
+#define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)
+#define __hip_atomic_store(p, v, order, scope) __atomic_store_n((p), (v), __ATOMIC_SEQ_CST)
+#define __builtin_amdgcn_s_sleep(n) std::this_thread::yield()
+static inline unsigned long long wall_clock64() {
+    return (unsigned long long)std::chrono::steady_clock::now().time_since_epoch().count() / 10;
+}
 #ifndef __HIP_MEMORY_SCOPE_WAVEFRONT
 #define __HIP_MEMORY_SCOPE_WAVEFRONT 0
 #define __HIP_MEMORY_SCOPE_WORKGROUP 0

@@ -282,6 +282,77 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
     image size (no device).  Returns one output dict per image."""
     names, lv, ch = _meta(spec)
     hists = {st["name"]: st for st in spec["stages"] if st["kind"] == "hist"}
+    plans, bufs_all = _batch_inputs(spec, images, plan_kw, names, ch)
+    ngroups = plans[0].num_groups
+    for g in range(ngroups):
+        src = plans[0].source(g)
+        kname = src[src.index("void __launch_bounds__"):].split("(")[1].split(")")[1].strip()
+        lib = _compile(src, kname)
+        arr, start, total, resample, wpb, gi = _group_tables(plans, bufs_all, g, names, lv, ch, hists)
+        if resample and names[gi.liveouts[0]] in hists:  # 256 threads meeting at __syncthreads
+            lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, 4)
+        elif resample:
+            lib.wt_emu_run_grid_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks)
+        elif _is_blk(plans[0], g):
+            lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
+        else:
+            lib.wt_emu_run_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
+    return [{o: _result(b[names.index(o)]) for o in spec["outputs"]} for (_, _, b) in bufs_all]
+
+
+def _group_tables(plans, bufs_all, g, names, lv, ch, hists):
+    """Group g's per-image argument table and work prefix sums for a batch
+    (one plan per image size; missing intermediates are created in each
+    image's buffers)."""
+    nimg = len(plans)
+    arr = (Args * nimg)()
+    start = (ctypes.c_int * (nimg + 1))()
+    total = 0
+    resample = False
+    wpb = 1
+    gi = None
+    for k, plan in enumerate(plans):
+        gi = GroupInfo()
+        wt._check(wt.lib.wt_plan_group_info(plan._h, g, ctypes.byref(gi)))
+        resample = bool(gi.resample)
+        wpb = gi.waves_per_group
+        w, h, bufs = bufs_all[k]
+
+        def buf(node_id, code):
+            if node_id not in bufs:
+                nm = names[node_id]
+                if nm in hists:  # counts start at zero
+                    bufs[node_id] = np.zeros((ch[nm], 1, hists[nm]["bins"]), dtype=NP_DTYPE[code])
+                else:
+                    bw, bh = oracle.level_size(w, h, lv[nm])
+                    bufs[node_id] = _blank((ch[nm], bh, bw), code)
+            return bufs[node_id]
+
+        a = arr[k]
+        for i in range(gi.nloaded):
+            b = buf(gi.loaded[i], gi.loaded_dtype[i])
+            a.src[i] = b.ctypes.data
+            a.src_rs[i], a.src_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
+        for i in range(gi.nliveouts):
+            b = buf(gi.liveouts[i], gi.liveout_dtype[i])
+            a.dst[i] = b.ctypes.data
+            a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
+        a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
+        a.tiles_x, a.tiles_y = gi.tiles_x, gi.tiles_y
+        if gi.resample:
+            work = gi.tiles_x * gi.tiles_y * gi.channels
+        elif _is_blk(plan, g):
+            work = gi.nwaves // gi.waves_per_group  # one workgroup per tile
+        else:
+            work = gi.nwaves
+        a.nwaves = gi.nwaves
+        start[k] = total
+        total += work
+    start[nimg] = total
+    return arr, start, total, resample, wpb, gi
+
+
+def _batch_inputs(spec, images, plan_kw, names, ch):
     plans, bufs_all = [], []
     for inputs in images:
         first = inputs[spec["inputs"][0]["name"]]
@@ -296,60 +367,82 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
             t = SPEC_NP[inp.get("dtype", "f32")]
             bufs[i] = np.ascontiguousarray(inputs[inp["name"]]).astype(t).reshape(ch[inp["name"]], h, w)
         bufs_all.append((w, h, bufs))
-    ngroups = plans[0].num_groups
+    return plans, bufs_all
+
+
+class Whole(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("AB", "start", "chunks", "deps", "done", "next", "status")] + \
+               [("limit", ctypes.c_int64), ("nchunks", ctypes.c_int32), ("nimg", ctypes.c_int32)]
+
+
+WHOLE_RUNNER = r"""
+extern "C" int wt_emu_run_whole(const WtWhole* p, int nwaves) {
+    std::barrier<> bar(64);
+    wt_emu_bar = &bar;
+    std::vector<std::thread> th;
+    for (int l = 0; l < 64; ++l)
+        th.emplace_back([&, l] {
+            wt_emu_lane = l;
+            for (int w = 0; w < nwaves; ++w) {
+                blockIdx.x = w; threadIdx.x = l; gridDim.x = nwaves;
+                bar.arrive_and_wait();
+                WT_EMU_KERNEL(*p);
+                bar.arrive_and_wait();
+            }
+        });
+    for (auto& t : th) t.join();
+    return 0;
+}
+"""
+
+
+def emulate_whole(spec, images, chunk=3, **plan_kw):
+    """Runs a batch through the whole-pipeline kernel (every group in one
+    launch, chunks of `chunk` tiles handed out by the ticket counter) on the
+    CPU, one wave at a time: the first wave takes every chunk in ticket
+    order, so each wait finds its producers complete.  Returns one output
+    dict per image and the final counters (done per group and image, the
+    ticket, the status word)."""
+    names, lv, ch = _meta(spec)
+    hists = {st["name"]: st for st in spec["stages"] if st["kind"] == "hist"}
+    plans, bufs_all = _batch_inputs(spec, images, plan_kw, names, ch)
+    nimg, ngroups = len(images), plans[0].num_groups
+    ab = (Args * (ngroups * nimg))()
+    starts = (ctypes.c_int * (ngroups * (nimg + 1)))()
+    chunks, deps, liveouts = [], [], []
     for g in range(ngroups):
-        src = plans[0].source(g)
-        kname = src[src.index("void __launch_bounds__"):].split("(")[1].split(")")[1].strip()
-        lib = _compile(src, kname)
-        arr = (Args * len(images))()
-        start = (ctypes.c_int * (len(images) + 1))()
-        total = 0
-        resample = False
-        wpb = 1
-        for k, plan in enumerate(plans):
-            gi = GroupInfo()
-            wt._check(wt.lib.wt_plan_group_info(plan._h, g, ctypes.byref(gi)))
-            resample = bool(gi.resample)
-            wpb = gi.waves_per_group
-            w, h, bufs = bufs_all[k]
-
-            def buf(node_id, code):
-                if node_id not in bufs:
-                    nm = names[node_id]
-                    if nm in hists:  # counts start at zero
-                        bufs[node_id] = np.zeros((ch[nm], 1, hists[nm]["bins"]), dtype=NP_DTYPE[code])
-                    else:
-                        bw, bh = oracle.level_size(w, h, lv[nm])
-                        bufs[node_id] = _blank((ch[nm], bh, bw), code)
-                return bufs[node_id]
-
-            a = arr[k]
-            for i in range(gi.nloaded):
-                b = buf(gi.loaded[i], gi.loaded_dtype[i])
-                a.src[i] = b.ctypes.data
-                a.src_rs[i], a.src_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
-            for i in range(gi.nliveouts):
-                b = buf(gi.liveouts[i], gi.liveout_dtype[i])
-                a.dst[i] = b.ctypes.data
-                a.dst_rs[i], a.dst_cs[i] = b.shape[2], b.shape[1] * b.shape[2]
-            a.W, a.H, a.Ws, a.Hs = gi.width, gi.height, gi.src_width, gi.src_height
-            a.tiles_x, a.tiles_y = gi.tiles_x, gi.tiles_y
-            if gi.resample:
-                work = gi.tiles_x * gi.tiles_y * gi.channels
-            elif _is_blk(plan, g):
-                work = gi.nwaves // gi.waves_per_group  # one workgroup per tile
-            else:
-                work = gi.nwaves
-            a.nwaves = gi.nwaves
-            start[k] = total
-            total += work
-        start[len(images)] = total
-        if resample and names[gi.liveouts[0]] in hists:  # 256 threads meeting at __syncthreads
-            lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, 4)
-        elif resample:
-            lib.wt_emu_run_grid_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks)
-        elif _is_blk(plans[0], g):
-            lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
-        else:
-            lib.wt_emu_run_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
-    return [{o: _result(b[names.index(o)]) for o in spec["outputs"]} for (_, _, b) in bufs_all]
+        arr, start, total, resample, wpb, gi = _group_tables(plans, bufs_all, g, names, lv, ch, hists)
+        for k in range(nimg):
+            ctypes.memmove(ctypes.addressof(ab) + (g * nimg + k) * ctypes.sizeof(Args), ctypes.addressof(arr[k]),
+                           ctypes.sizeof(Args))
+            starts[g * (nimg + 1) + k] = start[k]
+        starts[g * (nimg + 1) + nimg] = start[nimg]
+        loaded = set(gi.loaded[:gi.nloaded])
+        deps.append(sum(1 << q for q in range(g) if loaded & liveouts[q]))
+        liveouts.append(set(gi.liveouts[:gi.nliveouts]))
+        for k in range(nimg):
+            n = start[k + 1] - start[k]
+            chunks += [(g, k, t, min(chunk, n - t)) for t in range(0, n, chunk)]
+    src = plans[0].source(-1)
+    kname = src[src.index("void __launch_bounds__"):].split("(")[1].split(")")[1].strip()
+    os.makedirs(CACHE, exist_ok=True)
+    text = '#include "wt_emu.h"\n' + src + f"\n#define WT_EMU_KERNEL {kname}\n" + WHOLE_RUNNER
+    h = hashlib.sha1(text.encode()).hexdigest()[:16]
+    so = os.path.join(CACHE, f"{kname}_{h}.so")
+    if not os.path.exists(so):
+        cpp = so[:-3] + ".cpp"
+        open(cpp, "w").write(text)
+        subprocess.run([CLANG, "-std=c++20", "-O1", "-shared", "-fPIC", "-pthread", "-w",
+                        f"-I{os.path.join(HERE, 'emu')}", cpp, "-o", so + ".tmp"], check=True)
+        os.replace(so + ".tmp", so)
+    lib = ctypes.CDLL(so)
+    lib.wt_emu_run_whole.argtypes = [ctypes.POINTER(Whole), ctypes.c_int]
+    ctab = np.ascontiguousarray(np.array(chunks, dtype=np.int32).reshape(-1, 4))
+    dtab = np.array(deps, dtype=np.uint64)
+    ctr = np.zeros(ngroups * nimg + 2, dtype=np.int32)
+    wh = Whole(ctypes.addressof(ab), ctypes.addressof(starts), ctab.ctypes.data, dtab.ctypes.data,
+               ctr.ctypes.data, ctr[ngroups * nimg:].ctypes.data, ctr[ngroups * nimg + 1:].ctypes.data,
+               10 ** 8, len(chunks), nimg)
+    lib.wt_emu_run_whole(ctypes.byref(wh), 2)
+    outs = [{o: _result(b[names.index(o)]) for o in spec["outputs"]} for (_, _, b) in bufs_all]
+    return outs, ctr, deps

@@ -33,7 +33,7 @@ def test_binding_constants_match_header():
     text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "wt.h")).read(), flags=re.S)
     flags = {k: int(v) for k, v in re.findall(r"\bWT_PLAN_([A-Z_]+)\s*=\s*(\d+)", text)}
     assert flags == {"NO_DEVICE": 1, "ANY_WIDTH": 2, "NO_COMPILE": 4, "RETUNE": 8, "BATCH_RESIDENT": 16,
-                     "NO_FOLD": 32}
+                     "NO_FOLD": 32, "BATCH_WHOLE": 64}
     for k, v in flags.items():
         assert getattr(wt, "PLAN_" + k) == v, k
     body = re.search(r"typedef struct \{([^}]*)\} wt_sched_opts;", text).group(1)
@@ -222,3 +222,29 @@ def test_equalize_builder_rules():
     p.output(h1)
     plan = p.plan(128, 64, mode="analytic", no_device=True)
     assert "hst=" in plan.describe()
+
+
+def test_whole_pipeline_source_and_refusals():
+    """The whole-pipeline kernel (group -1 of wt_plan_source) holds one tile
+    function per group and one persistent kernel; plans with a lone
+    resampling or histogram group or a one-tile-per-workgroup group are
+    refused with WT_E_UNSUPPORTED."""
+    spec = P.pyramid_blend(3)
+    pl = wt.from_spec(spec).plan(300, 200, mode="analytic", any_width=True, no_compile=True, batch_images=4)
+    src = pl.source(-1)
+    for g in range(pl.num_groups):
+        assert f"_g{g}(const WtArgs& A, const int wid, const int lane, char* lds)" in src
+    assert src.count("__global__") == 1 and "_wait(P, dm, img)" in src
+    refused = [
+        (P.pyramid_blend(3), dict(mode="unfused", any_width=True)),          # lone down2 / up2 groups
+        (P.blur_histogram(), dict(mode="unfused")),                          # lone histogram group
+        (P.unsharp_mask(channels=1), dict(mode="fixed", fixed="nodes=1,2,3,4 V=1 TX=1 TY=8 WPB=4 BLK=1")),
+    ]
+    for sp, kw in refused:
+        p2 = wt.from_spec(sp).plan(300, 200, no_compile=True, **kw)
+        with pytest.raises(wt.WtError) as e:
+            p2.source(-1)
+        assert e.value.status == -2
+    with pytest.raises(wt.WtError) as e:
+        pl.source(-2)
+    assert e.value.status == -1

@@ -521,6 +521,40 @@ def test_pyramid_folded_batch_emulated():
         assert_normwise(got["R0"], oracle.evaluate(spec, inp)["R0"], 1e-5, "batched folded pyramid")
 
 
+
+@pytest.mark.parametrize("case", ["pyramid", "harris"])
+def test_whole_pipeline_kernel_emulated(case):
+    """The whole-pipeline kernel (every group of the batch in one launch,
+    chunks of tiles taken in ticket order, per-image completion counters)
+    equals the per-group batched kernels bit for bit and the oracle; every
+    chunk is taken, every group completes every tile of every image, and no
+    wait gives up."""
+    from emu_runner import emulate_batch, emulate_whole
+    if case == "harris":
+        spec = HARRIS
+        sizes = [(70, 19), (131, 33)]
+        images = [{"img": synth.uniform_image(90 + i, 3, h, w)} for i, (w, h) in enumerate(sizes)]
+        kw = dict(mode="fixed", fixed="nodes=1,2,3,4,5,6,7,8,9,10 V=1 TX=2 SX=0 TY=8 PF=1")
+        out = "R"
+    else:
+        spec = P.pyramid_blend(3)
+        sizes = [(45, 37), (30, 21), (66, 40)]
+        images = [{"A": synth.uniform_image(70 + i, 1, h, w), "B": synth.uniform_image(80 + i, 1, h, w),
+                   "M": synth.ramp_mask(h, w)} for i, (w, h) in enumerate(sizes)]
+        kw = dict(mode="analytic", any_width=True)
+        out = "R0"
+    got, ctr, deps = emulate_whole(spec, images, chunk=3, **kw)
+    ref = emulate_batch(spec, images, nblocks=2, **kw)
+    for inp, g, r in zip(images, got, ref):
+        assert np.array_equal(g[out], r[out]), case
+        assert_normwise(g[out], oracle.evaluate(spec, inp)[out], 1e-5, case)
+    ngroups, nimg = len(deps), len(images)
+    assert ctr[ngroups * nimg + 1] == 0  # status: no wait gave up
+    assert ctr[ngroups * nimg] >= 1 and all(ctr[:ngroups * nimg] > 0)
+    if case != "harris":
+        assert any(deps) and deps[0] == 0  # the first group reads only inputs
+
+
 WIDE = P.wide_chain()
 WIDE_NODES = ",".join(str(i) for i in range(1, 12))
 

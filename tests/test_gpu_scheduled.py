@@ -230,3 +230,88 @@ def test_pyramid_tuned_on_the_batch():
             ref = oracle.evaluate(spec, {"A": a, "B": b, "M": m})
             assert_normwise(tout[i][0].cpu().numpy(), ref[spec["outputs"][0]], 1e-5, f"rep {rep} image {i} {w}x{h}")
     assert len(plan.describe().splitlines()) == len(before.splitlines())
+
+
+@pytest.mark.skip(reason="the whole-pipeline launch is switched off on the device: its first run went silent for "
+                         "three minutes and was killed, cause not found (host emulation is bit-identical); "
+                         "wt_plan_run_batch refuses WT_PLAN_BATCH_WHOLE until the cause is fixed")
+def test_whole_pipeline_launch():
+    """The whole group sequence as one persistent launch (every group's
+    tiles taken in ticket order, each chunk started once its producer groups
+    have finished that image) writes exactly what the per-group launches
+    write, on a batch of uneven pyramid pairs and on a Harris batch; replays
+    of its graph with other work between them give the same outputs; no wait
+    gives up; the smallest and largest pairs match the oracle.  A plan with a
+    lone histogram group is refused on the host before any launch."""
+    import torch
+    import paper_1909_07190_amd as wt
+    spec = P.pyramid_blend(bench.PYR_LEVELS)
+    sizes = synth.batch_sizes(bench.PYR_SEED, bench.PYR_PAIRS)[:6]
+    order = sorted(range(len(sizes)), key=lambda k: sizes[k][0] * sizes[k][1])
+    check = [order[0], order[-1]]
+    tin, tout, host = _pyramid_tensors(torch, sizes, set(check))
+    plan = bench.plan_pyramid(wt, P, sizes, "analytic")
+    mw, mh = bench.median_size(sizes)
+    whole = wt.from_spec(spec).plan(mw, mh, mode="fixed", fixed=plan.describe(), any_width=True,
+                                    batch_images=len(sizes), batch_whole=True)
+    _say(f"  {len(sizes)} pairs, {plan.num_groups} groups")
+    plan.run_batch(tin, tout)
+    wout = [[torch.full_like(t[0], float("nan"))] for t in tout]
+    whole.run_batch(tin, wout)
+    whole.batch_check()
+    for i in range(len(sizes)):
+        assert torch.equal(wout[i][0], tout[i][0]), f"pair {i} {sizes[i]}"
+    for rep in range(3):
+        torch.cuda.synchronize()
+        junk = torch.ones((1 << 20,), device=tin[0][0].device).cumsum(0)  # eager work between replays
+        rout = [[torch.full_like(t[0], float("nan"))] for t in tout]
+        whole.run_batch(tin, rout)
+        whole.batch_check()
+        del junk
+        for i in range(len(sizes)):
+            assert torch.equal(rout[i][0], tout[i][0]), f"replay {rep} pair {i}"
+    for i in check:
+        a, b, m = host[i]
+        ref = oracle.evaluate(spec, {"A": a, "B": b, "M": m})
+        assert_normwise(wout[i][0].cpu().numpy(), ref[spec["outputs"][0]], 1e-5, f"pair {i} {sizes[i]}")
+    _say("  pyramid batch ok")
+
+    dev = torch.device("cuda:0")
+    hs = [(300, 200), (517, 129)]
+    imgs = [torch.from_numpy(synth.uniform_image(30 + k, 3, h, w)).to(dev) for k, (w, h) in enumerate(hs)]
+    fixed = "nodes=1,2,3,4,5,6,7,8,9,10 V=2 TX=1 SX=0 TY=16 WPB=2 PF=2"
+    ref_plan = wt.from_spec(P.harris()).plan(300, 200, mode="fixed", fixed=fixed, batch_images=2)
+    hw = wt.from_spec(P.harris()).plan(300, 200, mode="fixed", fixed=fixed, batch_images=2, batch_whole=True)
+    o1 = [[torch.empty((1, h, w), device=dev)] for (w, h) in hs]
+    o2 = [[torch.full((1, h, w), float("nan"), device=dev)] for (w, h) in hs]
+    ref_plan.run_batch([[x] for x in imgs], o1)
+    hw.run_batch([[x] for x in imgs], o2)
+    hw.batch_check()
+    for k in range(len(hs)):
+        assert torch.equal(o1[k][0], o2[k][0]), f"harris image {k}"
+    _say("  harris batch ok")
+
+    hp = wt.from_spec(P.blur_histogram()).plan(256, 128, mode="unfused", batch_images=2, batch_whole=True)
+    x = [torch.rand((1, 128, 256), device=dev) for _ in range(2)]
+    hout = [[torch.empty((1, 1, 64), dtype=torch.int32, device=dev)] for _ in range(2)]
+    with pytest.raises(wt.WtError) as e:
+        hp.run_batch([[t] for t in x], hout)
+    assert e.value.status == -2
+
+
+def test_whole_pipeline_launch_refused():
+    """While the whole-pipeline launch is switched off, a batch run of a plan
+    made with it is refused with WT_E_UNSUPPORTED on the host, before any
+    allocation or launch; the same plan still runs groups one by one."""
+    import torch
+    import paper_1909_07190_amd as wt
+    dev = torch.device("cuda:0")
+    fixed = "nodes=1,2,3,4 V=1 TX=2 SX=0 TY=8 PF=1"
+    pl = wt.from_spec(P.unsharp_mask(channels=1)).plan(128, 64, mode="fixed", fixed=fixed, batch_images=2,
+                                                      batch_whole=True)
+    x = [torch.rand((1, 64, 128), device=dev) for _ in range(2)]
+    y = [torch.empty((1, 64, 128), device=dev) for _ in range(2)]
+    with pytest.raises(wt.WtError) as e:
+        pl.run_batch([[t] for t in x], [[t] for t in y])
+    assert e.value.status == -2
+    pl.batch_check()  # no whole-pipeline launch ran: nothing to report
