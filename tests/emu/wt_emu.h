@@ -26,12 +26,19 @@ static thread_local wt_emu_dim3 threadIdx, blockIdx, gridDim;
 static thread_local int wt_emu_lane = 0;
 static std::barrier<>* wt_emu_bar = nullptr;
 static uint32_t wt_emu_x[64];
+// Several waves running at once: each lane thread names its own wave's
+// barrier and exchange buffer (otherwise the shared ones above serve).
+static thread_local std::barrier<>* wt_emu_wave_bar = nullptr;
+static thread_local uint32_t* wt_emu_wave_x = nullptr;
+
+static inline void wt_emu_sync() { (wt_emu_wave_bar ? wt_emu_wave_bar : wt_emu_bar)->arrive_and_wait(); }
 
 static inline uint32_t wt_emu_xchg(uint32_t v, int src) {
-    wt_emu_x[wt_emu_lane] = v;
-    wt_emu_bar->arrive_and_wait();
-    uint32_t r = wt_emu_x[src & 63];
-    wt_emu_bar->arrive_and_wait();
+    uint32_t* x = wt_emu_wave_x ? wt_emu_wave_x : wt_emu_x;
+    x[wt_emu_lane] = v;
+    wt_emu_sync();
+    uint32_t r = x[src & 63];
+    wt_emu_sync();
     return r;
 }
 
@@ -54,11 +61,21 @@ static inline int wt_emu_dpp(int old, int src, int ctrl, bool bound_ctrl) {
 #define __builtin_amdgcn_ds_bpermute(addr, v) ((int)wt_emu_xchg((uint32_t)(v), ((addr) >> 2) & 63))
 #define __builtin_amdgcn_readlane(v, l) ((int)wt_emu_xchg((uint32_t)(v), (l)))
 #define __builtin_amdgcn_readfirstlane(v) ((int)wt_emu_xchg((uint32_t)(v), 0))
-#define __builtin_amdgcn_wave_barrier() wt_emu_bar->arrive_and_wait()
+#define __builtin_amdgcn_wave_barrier() wt_emu_sync()
 // a barrier over the threads the runner started together: one wave, or a
 // whole workgroup for one-tile-per-workgroup kernels
-#define __syncthreads() wt_emu_bar->arrive_and_wait()
-#define __builtin_amdgcn_fence(a, b) ((void)0)
+#define __syncthreads() wt_emu_sync()
+// A wavefront executes in lockstep, so every lane's earlier stores precede
+// an agent-scope fence the whole wave executes; the lane threads meet at it.
+// (Wave-scope fences only order the compiler's view: nothing to do here.)
+static inline void wt_emu_fence(const char* scope) {
+    if (scope[0] == 'a') {
+        std::atomic_thread_fence(std::memory_order_seq_cst);
+        wt_emu_sync();
+        std::atomic_thread_fence(std::memory_order_seq_cst);
+    }
+}
+#define __builtin_amdgcn_fence(a, b) wt_emu_fence(b)
 // atomics: the lanes are threads
 #define __hip_atomic_fetch_add(p, v, order, scope) __atomic_fetch_add((p), (v), __ATOMIC_RELAXED)
 #define __hip_atomic_load(p, order, scope) __atomic_load_n((p), __ATOMIC_SEQ_CST)

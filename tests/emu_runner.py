@@ -142,10 +142,17 @@ extern "C" int wt_emu_run_grid(const WtArgs* a, int gx, int gy, int gz, int nthr
 """
 
 
+def _text_hash(text):
+    """Cache key of an emulator build: its source and the emulation header it
+    includes (a changed header rebuilds every kernel)."""
+    with open(os.path.join(HERE, "emu", "wt_emu.h"), "rb") as f:
+        return hashlib.sha1(text.encode() + f.read()).hexdigest()[:16]
+
+
 def _compile(src, kname):
     os.makedirs(CACHE, exist_ok=True)
     text = '#include "wt_emu.h"\n' + src + f"\n#define WT_EMU_KERNEL {kname}\n#define WT_EMU_KERNEL_BATCH {kname}_batch\n" + RUNNER
-    h = hashlib.sha1(text.encode()).hexdigest()[:16]
+    h = _text_hash(text)
     so = os.path.join(CACHE, f"{kname}_{h}.so")
     if not os.path.exists(so):
         cpp = so[:-3] + ".cpp"
@@ -297,6 +304,7 @@ def emulate_batch(spec, images, nblocks=3, **plan_kw):
             lib.wt_emu_run_wg_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
         else:
             lib.wt_emu_run_batch(ctypes.addressof(arr), ctypes.addressof(start), len(images), total, nblocks, wpb)
+    emulate_batch.buffers = bufs_all  # every image's node buffers, for diagnosis
     return [{o: _result(b[names.index(o)]) for o in spec["outputs"]} for (_, _, b) in bufs_all]
 
 
@@ -393,16 +401,39 @@ extern "C" int wt_emu_run_whole(const WtWhole* p, int nwaves) {
     for (auto& t : th) t.join();
     return 0;
 }
+// `nwaves` waves at once, 64 lane threads each with the wave's own barrier
+// and exchange buffer; wave w uses LDS slot w (the kernel's LDS array is
+// widened to 16 slots for this runner).
+extern "C" int wt_emu_run_whole_concurrent(const WtWhole* p, int nwaves) {
+    std::vector<std::barrier<>*> bars;
+    std::vector<std::vector<uint32_t>> xs(nwaves, std::vector<uint32_t>(64));
+    for (int w = 0; w < nwaves; ++w) bars.push_back(new std::barrier<>(64));
+    std::vector<std::thread> th;
+    for (int w = 0; w < nwaves; ++w)
+        for (int l = 0; l < 64; ++l)
+            th.emplace_back([&, w, l] {
+                wt_emu_lane = l;
+                wt_emu_wave_bar = bars[w];
+                wt_emu_wave_x = xs[w].data();
+                blockIdx.x = 0; threadIdx.x = w * 64 + l; gridDim.x = 1;
+                WT_EMU_KERNEL(*p);
+            });
+    for (auto& t : th) t.join();
+    for (auto* b : bars) delete b;
+    return 0;
+}
 """
 
 
-def emulate_whole(spec, images, chunk=3, **plan_kw):
+def emulate_whole(spec, images, chunk=3, concurrent=0, limit_s=60, **plan_kw):
     """Runs a batch through the whole-pipeline kernel (every group in one
     launch, chunks of `chunk` tiles handed out by the ticket counter) on the
-    CPU, one wave at a time: the first wave takes every chunk in ticket
-    order, so each wait finds its producers complete.  Returns one output
-    dict per image and the final counters (done per group and image, the
-    ticket, the status word)."""
+    CPU.  By default one wave at a time: the first wave takes every chunk in
+    ticket order, so each wait finds its producers complete.  With
+    `concurrent` = n, n waves run at once and take chunks as they free up,
+    so waits on producers still in progress really block.  Returns one
+    output dict per image, the final counters (done per group and image,
+    the ticket, the status word) and the producer masks."""
     names, lv, ch = _meta(spec)
     hists = {st["name"]: st for st in spec["stages"] if st["kind"] == "hist"}
     plans, bufs_all = _batch_inputs(spec, images, plan_kw, names, ch)
@@ -425,9 +456,13 @@ def emulate_whole(spec, images, chunk=3, **plan_kw):
             chunks += [(g, k, t, min(chunk, n - t)) for t in range(0, n, chunk)]
     src = plans[0].source(-1)
     kname = src[src.index("void __launch_bounds__"):].split("(")[1].split(")")[1].strip()
+    if concurrent:  # one LDS slot per emulated wave
+        import re
+        src = re.sub(r"char wt_lds\[(\d+)\];", lambda m: f"char wt_lds[{int(m.group(1)) * 16}];", src)
+        assert concurrent <= 16
     os.makedirs(CACHE, exist_ok=True)
     text = '#include "wt_emu.h"\n' + src + f"\n#define WT_EMU_KERNEL {kname}\n" + WHOLE_RUNNER
-    h = hashlib.sha1(text.encode()).hexdigest()[:16]
+    h = _text_hash(text)
     so = os.path.join(CACHE, f"{kname}_{h}.so")
     if not os.path.exists(so):
         cpp = so[:-3] + ".cpp"
@@ -437,12 +472,17 @@ def emulate_whole(spec, images, chunk=3, **plan_kw):
         os.replace(so + ".tmp", so)
     lib = ctypes.CDLL(so)
     lib.wt_emu_run_whole.argtypes = [ctypes.POINTER(Whole), ctypes.c_int]
+    lib.wt_emu_run_whole_concurrent.argtypes = [ctypes.POINTER(Whole), ctypes.c_int]
     ctab = np.ascontiguousarray(np.array(chunks, dtype=np.int32).reshape(-1, 4))
     dtab = np.array(deps, dtype=np.uint64)
     ctr = np.zeros(ngroups * nimg + 2, dtype=np.int32)
     wh = Whole(ctypes.addressof(ab), ctypes.addressof(starts), ctab.ctypes.data, dtab.ctypes.data,
                ctr.ctypes.data, ctr[ngroups * nimg:].ctypes.data, ctr[ngroups * nimg + 1:].ctypes.data,
-               10 ** 8, len(chunks), nimg)
-    lib.wt_emu_run_whole(ctypes.byref(wh), 2)
+               int(limit_s * 10 ** 8), len(chunks), nimg)
+    if concurrent:
+        lib.wt_emu_run_whole_concurrent(ctypes.byref(wh), concurrent)
+    else:
+        lib.wt_emu_run_whole(ctypes.byref(wh), 2)
     outs = [{o: _result(b[names.index(o)]) for o in spec["outputs"]} for (_, _, b) in bufs_all]
+    emulate_whole.buffers = bufs_all  # every image's node buffers, for diagnosis
     return outs, ctr, deps

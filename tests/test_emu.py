@@ -543,14 +543,18 @@ def test_whole_pipeline_kernel_emulated(case):
                    "M": synth.ramp_mask(h, w)} for i, (w, h) in enumerate(sizes)]
         kw = dict(mode="analytic", any_width=True)
         out = "R0"
-    got, ctr, deps = emulate_whole(spec, images, chunk=3, **kw)
     ref = emulate_batch(spec, images, nblocks=2, **kw)
-    for inp, g, r in zip(images, got, ref):
-        assert np.array_equal(g[out], r[out]), case
-        assert_normwise(g[out], oracle.evaluate(spec, inp)[out], 1e-5, case)
-    ngroups, nimg = len(deps), len(images)
-    assert ctr[ngroups * nimg + 1] == 0  # status: no wait gave up
-    assert ctr[ngroups * nimg] >= 1 and all(ctr[:ngroups * nimg] > 0)
+    # one wave taking every chunk in order, then eight waves at once taking
+    # one-tile chunks as they free up (waits on producers still running
+    # really block; the lanes of a wave meet at its agent-scope fences)
+    for chunk, conc in ((3, 0), (1, 8)):
+        got, ctr, deps = emulate_whole(spec, images, chunk=chunk, concurrent=conc, **kw)
+        for inp, g, r in zip(images, got, ref):
+            assert np.array_equal(g[out], r[out]), (case, conc)
+            assert_normwise(g[out], oracle.evaluate(spec, inp)[out], 1e-5, case)
+        ngroups, nimg = len(deps), len(images)
+        assert ctr[ngroups * nimg + 1] == 0  # status: no wait gave up
+        assert ctr[ngroups * nimg] >= 1 and all(ctr[:ngroups * nimg] > 0)
     if case != "harris":
         assert any(deps) and deps[0] == 0  # the first group reads only inputs
 
