@@ -295,8 +295,11 @@ wt_status wt_plan_run_batch(wt_plan* plan, int nimg, const wt_image* in,
 
 /* Synchronises `hip_stream` and returns WT_E_INTERNAL if a wave of the
  * plan's last whole-pipeline batch launch (WT_PLAN_BATCH_WHOLE) gave up
- * waiting for a producer group (its outputs are then not valid); WT_SUCCESS
- * otherwise, and for plans without such a launch. */
+ * waiting for a producer group (its outputs are then not valid); WT_OK
+ * otherwise, and for plans without such a launch.  A library addition: the
+ * paper launches one kernel per fused group (Section 7), where the kernel
+ * boundary itself orders producers before consumers; this call reports
+ * whether the device-side ordering that replaces those boundaries held. */
 wt_status wt_plan_batch_check(wt_plan* plan, void* hip_stream);
 
 /* Bytes of device memory in the library's fixed workspace: one copy on each
