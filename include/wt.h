@@ -372,6 +372,19 @@ wt_status wt_plan_describe(const wt_plan* plan, char* buf, size_t len, size_t* n
  * and compiles candidates (seconds). */
 wt_status wt_plan_tune_batch(wt_plan* plan, int nimg, const wt_image* in, const wt_image* out, void* stream);
 
+/* Test hook of WT_PLAN_BATCH_WHOLE's host logic (any plan, no device
+ * needed): for a batch of `nimg` images of sizes wh[2i] x wh[2i+1] and
+ * `resident_waves` waves resident at once, the chunk table the launch would
+ * hand out, 4 ints per chunk (group, image, first tile, tiles; group by
+ * group, images in order; a group's chunk holds about 1/(8 resident_waves)
+ * of its tiles, 1 to 64) into `chunks` (NULL: count only; WT_E_INVALID if
+ * more than `max_chunks`), their number into `nchunks`, and into `deps` (NULL,
+ * or one entry per group) each group's producer groups as a bit mask.
+ * WT_E_UNSUPPORTED as the launch itself refuses; WT_E_SHAPE for sizes
+ * outside 1..2^24. */
+wt_status wt_plan_whole_tables(const wt_plan* plan, int nimg, const int* wh, int resident_waves, int* chunks,
+                               int max_chunks, int* nchunks, unsigned long long* deps);
+
 /* HIP source generated for group `group`; group -1: the whole-pipeline
  * kernel of WT_PLAN_BATCH_WHOLE (generated on each call, for any plan;
  * WT_E_UNSUPPORTED where that launch is refused). */

@@ -101,6 +101,8 @@ _sig("wt_plan_run_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.PO
 _sig("wt_plan_run_batch_static", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_batch_check", ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p)
+_sig("wt_plan_whole_tables", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+     ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint64))
 _sig("wt_plan_tune_batch", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(WtImage),
      ctypes.POINTER(WtImage), ctypes.c_void_p)
 _sig("wt_plan_run_batch_groups", ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -357,6 +359,21 @@ class Plan:
             stream = torch.cuda.current_stream()
         s = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         _check(lib.wt_plan_run_batch_static(self._h, len(inputs), a_in, a_out, ctypes.c_void_p(s)))
+
+    def whole_tables(self, sizes, resident_waves):
+        """The whole-pipeline launch's chunk table (rows: group, image, first
+        tile, tiles) and per-group producer masks for a batch of (width,
+        height) `sizes` with `resident_waves` waves resident."""
+        import numpy as np
+        wh = (ctypes.c_int * (2 * len(sizes)))(*[v for s in sizes for v in s])
+        n = ctypes.c_int()
+        deps = (ctypes.c_uint64 * max(1, self.num_groups))()
+        _check(lib.wt_plan_whole_tables(self._h, len(sizes), wh, resident_waves, None, 0, ctypes.byref(n), deps))
+        tab = np.zeros((n.value, 4), dtype=np.int32)
+        _check(lib.wt_plan_whole_tables(self._h, len(sizes), wh, resident_waves,
+                                        tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), n.value, ctypes.byref(n),
+                                        deps))
+        return tab, [int(d) for d in deps[:self.num_groups]]
 
     def batch_check(self, stream=None):
         """Synchronises `stream` and raises if the last whole-pipeline batch

@@ -161,31 +161,13 @@ void load_whole_kernel(Plan& plan) {
     plan.whole_kname = kname;
 }
 
-// Chunks, producer masks and counters of the whole-pipeline launch for the
-// batch shape of `st` (after layout_batch): each group's tiles of each image
-// cut into chunks of k consecutive tiles, k chosen so that a group spreads
-// over about eight chunks per resident wave (at most 64 tiles a chunk).
+// Counters and table offsets of the whole-pipeline launch for the batch
+// shape of `st` (after layout_batch); the chunks and producer masks come from
+// whole_tables with the launch's resident waves.
 void layout_whole(const Plan& plan, BatchState& st) {
     const int G = (int)plan.groups.size(), nimg = (int)st.sizes.size();
     const int per_cu = resident_blocks_per_cu(plan, plan.whole_fn, 64 * plan.whole_wpb);
-    const long long rw = (long long)per_cu * plan.machine.ncu * plan.whole_wpb;
-    st.chunk_tab.clear();
-    st.dep_tab.assign(G, 0ull);
-    for (int g = 0; g < G; ++g) {
-        const GroupRt& gr = plan.groups[g];
-        for (int l : gr.loaded)
-            for (int q = 0; q < g; ++q)
-                if (std::find(plan.groups[q].liveouts.begin(), plan.groups[q].liveouts.end(), l) !=
-                    plan.groups[q].liveouts.end())
-                    st.dep_tab[g] |= 1ull << q;
-        const int k = (int)std::max(1LL, std::min(64LL, (long long)st.total[g] / (8 * rw)));
-        for (int i = 0; i < nimg; ++i) {
-            const int n = st.tiles[(size_t)g * nimg + i][2];
-            for (int t = 0; t < n; t += k) {
-                st.chunk_tab.insert(st.chunk_tab.end(), {g, i, t, std::min(k, n - t)});
-            }
-        }
-    }
+    whole_tables(plan, st.sizes, (long long)per_cu * plan.machine.ncu * plan.whole_wpb, st.chunk_tab, st.dep_tab);
     st.nchunks = (int)(st.chunk_tab.size() / 4);
     st.whole_grid = (int)std::max(1LL, std::min((long long)st.nchunks, (long long)per_cu * plan.machine.ncu));
     st.whole_off = (st.dargs_bytes + 15) / 16 * 16;
@@ -233,6 +215,37 @@ void tile_counts(const Plan& plan, const GroupRt& gr, int lw, int lh, int& tx, i
 
 
 }  // namespace
+
+void whole_tables(const Plan& plan, const std::vector<std::pair<int, int>>& sizes, long long rw,
+                  std::vector<int>& chunk_tab, std::vector<unsigned long long>& dep_tab) {
+    const Pipeline& p = plan.p;
+    const int G = (int)plan.groups.size(), nimg = (int)sizes.size();
+    if (G > 64) fail(WT_E_UNSUPPORTED, "whole-pipeline launch needs 1 to 64 groups");
+    chunk_tab.clear();
+    dep_tab.assign(G, 0ull);
+    rw = std::max(1LL, rw);
+    for (int g = 0; g < G; ++g) {
+        const GroupRt& gr = plan.groups[g];
+        if (gr.resample) fail(WT_E_UNSUPPORTED, "whole-pipeline launch of a lone resampling or histogram group");
+        for (int l : gr.loaded)
+            for (int q = 0; q < g; ++q)
+                if (std::find(plan.groups[q].liveouts.begin(), plan.groups[q].liveouts.end(), l) !=
+                    plan.groups[q].liveouts.end())
+                    dep_tab[g] |= 1ull << q;
+        std::vector<int> work(nimg);
+        long long total = 0;
+        for (int i = 0; i < nimg; ++i) {
+            auto d = level_dims(sizes[i].first, sizes[i].second, p.nodes[gr.g.nodes[0]].level);
+            int tx, ty;
+            tile_counts(plan, gr, d.first, d.second, tx, ty, work[i]);
+            total += work[i];
+        }
+        // about eight chunks per resident wave and group, at most 64 tiles each
+        const int k = (int)std::max(1LL, std::min(64LL, total / (8 * rw)));
+        for (int i = 0; i < nimg; ++i)
+            for (int t = 0; t < work[i]; t += k) chunk_tab.insert(chunk_tab.end(), {g, i, t, std::min(k, work[i] - t)});
+    }
+}
 
 namespace {
 

@@ -377,6 +377,29 @@ wt_status wt_plan_batch_check(wt_plan* plan, void* stream) {
     });
 }
 
+wt_status wt_plan_whole_tables(const wt_plan* plan, int nimg, const int* wh, int resident_waves, int* chunks,
+                               int max_chunks, int* nchunks, unsigned long long* deps) {
+    return guard([&] {
+        if (!plan || !wh || !nchunks) wt::fail(WT_E_INVALID, "null argument");
+        if (nimg < 1 || resident_waves < 1 || max_chunks < 0) wt::fail(WT_E_INVALID, "bad count");
+        std::vector<std::pair<int, int>> sizes(nimg);
+        for (int i = 0; i < nimg; ++i) {
+            if (wh[2 * i] < 1 || wh[2 * i + 1] < 1 || wh[2 * i] > (1 << 24) || wh[2 * i + 1] > (1 << 24))
+                wt::fail(WT_E_SHAPE, "bad image size");
+            sizes[i] = {wh[2 * i], wh[2 * i + 1]};
+        }
+        std::vector<int> tab;
+        std::vector<unsigned long long> dep;
+        wt::whole_tables(*plan->impl, sizes, resident_waves, tab, dep);
+        *nchunks = (int)(tab.size() / 4);
+        if (chunks) {
+            if (*nchunks > max_chunks) wt::fail(WT_E_INVALID, "chunk buffer too small");
+            std::memcpy(chunks, tab.data(), tab.size() * sizeof(int));
+        }
+        if (deps) std::memcpy(deps, dep.data(), dep.size() * sizeof(unsigned long long));
+    });
+}
+
 wt_status wt_plan_tune_batch(wt_plan* plan, int nimg, const wt_image* in, const wt_image* out, void* stream) {
     return guard([&] {
         if (!plan) wt::fail(WT_E_INVALID, "null plan");

@@ -192,6 +192,11 @@ void tune_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* o
 std::vector<GroupSched> config_neighbours(const GroupSched& best, int vmax);
 // Compiles and loads the batched kernels of the groups that lack them.
 void load_batch_kernels(const Plan& plan, std::vector<GroupRt>& groups);
+// Chunk table (group, image, first tile, tiles per chunk) and per-group
+// producer masks of the whole-pipeline launch for images of `sizes` with `rw`
+// waves resident (no device needed).
+void whole_tables(const Plan& plan, const std::vector<std::pair<int, int>>& sizes, long long rw,
+                  std::vector<int>& chunk_tab, std::vector<unsigned long long>& dep_tab);
 // Source of the whole-pipeline kernel of the plan's groups (named `kname`).
 std::string whole_kernel_source(const Plan& plan, std::string& kname);
 // WT_E_INTERNAL when the last whole-pipeline launch of the plan's batch gave

@@ -425,7 +425,7 @@ extern "C" int wt_emu_run_whole_concurrent(const WtWhole* p, int nwaves) {
 """
 
 
-def emulate_whole(spec, images, chunk=3, concurrent=0, limit_s=60, **plan_kw):
+def emulate_whole(spec, images, chunk=3, concurrent=0, limit_s=60, resident_waves=None, **plan_kw):
     """Runs a batch through the whole-pipeline kernel (every group in one
     launch, chunks of `chunk` tiles handed out by the ticket counter) on the
     CPU.  By default one wave at a time: the first wave takes every chunk in
@@ -433,7 +433,10 @@ def emulate_whole(spec, images, chunk=3, concurrent=0, limit_s=60, **plan_kw):
     `concurrent` = n, n waves run at once and take chunks as they free up,
     so waits on producers still in progress really block.  Returns one
     output dict per image, the final counters (done per group and image,
-    the ticket, the status word) and the producer masks."""
+    the ticket, the status word) and the producer masks.  With
+    `resident_waves`, the chunk table and producer masks are the library's
+    own (wt_plan_whole_tables for that many resident waves), checked here
+    against the masks and per-image tile counts derived from the plans."""
     names, lv, ch = _meta(spec)
     hists = {st["name"]: st for st in spec["stages"] if st["kind"] == "hist"}
     plans, bufs_all = _batch_inputs(spec, images, plan_kw, names, ch)
@@ -454,6 +457,18 @@ def emulate_whole(spec, images, chunk=3, concurrent=0, limit_s=60, **plan_kw):
         for k in range(nimg):
             n = start[k + 1] - start[k]
             chunks += [(g, k, t, min(chunk, n - t)) for t in range(0, n, chunk)]
+    if resident_waves:
+        sizes = [(w, h) for (w, h, _) in bufs_all]
+        tab, lib_deps = plans[0].whole_tables(sizes, resident_waves)
+        assert lib_deps == deps, (lib_deps, deps)
+        for g in range(ngroups):
+            for k in range(nimg):
+                rows = tab[(tab[:, 0] == g) & (tab[:, 1] == k)]
+                n = starts[g * (nimg + 1) + k + 1] - starts[g * (nimg + 1) + k]
+                assert rows[:, 3].sum() == n and (len(rows) == 0 or rows[0, 2] == 0), (g, k)
+                assert np.array_equal(rows[1:, 2], (rows[:, 2] + rows[:, 3])[:-1]), (g, k)  # contiguous
+        assert np.all(np.diff(tab[:, 0]) >= 0)  # group by group
+        chunks = [tuple(r) for r in tab.tolist()]
     src = plans[0].source(-1)
     kname = src[src.index("void __launch_bounds__"):].split("(")[1].split(")")[1].strip()
     if concurrent:  # one LDS slot per emulated wave

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1909_07190_amd as wt
@@ -248,3 +249,16 @@ def test_whole_pipeline_source_and_refusals():
     with pytest.raises(wt.WtError) as e:
         pl.source(-2)
     assert e.value.status == -1
+    # the launch's host tables: every tile of every group and image in exactly
+    # one chunk, group by group; chunk sizes follow the resident waves
+    sizes = [(300, 200), (64, 40), (517, 129), (1, 1)]
+    small, deps = pl.whole_tables(sizes, 10 ** 6)
+    assert set(small[:, 3].tolist()) == {1} and np.all(np.diff(small[:, 0]) >= 0)
+    assert deps[0] == 0 and all(d < (1 << g) for g, d in enumerate(deps)) and any(deps)
+    big, deps2 = pl.whole_tables(sizes, 1)
+    assert deps2 == deps and len(big) < len(small)
+    for g in range(pl.num_groups):
+        assert small[small[:, 0] == g].shape[0] == big[big[:, 0] == g][:, 3].sum()
+    with pytest.raises(wt.WtError) as e:
+        pl.whole_tables([(0, 5)], 64)
+    assert e.value.status == -3

@@ -547,8 +547,10 @@ def test_whole_pipeline_kernel_emulated(case):
     # one wave taking every chunk in order, then eight waves at once taking
     # one-tile chunks as they free up (waits on producers still running
     # really block; the lanes of a wave meet at its agent-scope fences)
-    for chunk, conc in ((3, 0), (1, 8)):
-        got, ctr, deps = emulate_whole(spec, images, chunk=chunk, concurrent=conc, **kw)
+    # (the second run takes the library's own chunk table and producer
+    # masks: one-tile chunks for a million resident waves)
+    for chunk, conc, rw in ((3, 0, None), (1, 8, 10 ** 6)):
+        got, ctr, deps = emulate_whole(spec, images, chunk=chunk, concurrent=conc, resident_waves=rw, **kw)
         for inp, g, r in zip(images, got, ref):
             assert np.array_equal(g[out], r[out]), (case, conc)
             assert_normwise(g[out], oracle.evaluate(spec, inp)[out], 1e-5, case)
