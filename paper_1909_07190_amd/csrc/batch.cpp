@@ -227,6 +227,9 @@ void whole_tables(const Plan& plan, const std::vector<std::pair<int, int>>& size
     for (int g = 0; g < G; ++g) {
         const GroupRt& gr = plan.groups[g];
         if (gr.resample) fail(WT_E_UNSUPPORTED, "whole-pipeline launch of a lone resampling or histogram group");
+        if (gr.g.BLK) fail(WT_E_UNSUPPORTED, "whole-pipeline launch of a one-tile-per-workgroup group");
+        if (!gr.geo.hist.empty() || !gr.geo.tables.empty())
+            fail(WT_E_UNSUPPORTED, "whole-pipeline launch of a histogram or equalize stage");
         for (int l : gr.loaded)
             for (int q = 0; q < g; ++q)
                 if (std::find(plan.groups[q].liveouts.begin(), plan.groups[q].liveouts.end(), l) !=
@@ -464,6 +467,7 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
     }
     if (all) {
         hip_check(hipGraphLaunch(st.exec, s), "hipGraphLaunch");
+        st.whole_ran = st.ctr_words > 0;
         return;
     }
     for (int g = first; g < first + count; ++g)
@@ -471,7 +475,9 @@ void run_plan_batch(Plan& plan, int nimg, const wt_image* in, const wt_image* ou
 }
 
 void check_batch_status(Plan& plan, void* stream) {
-    if (!plan.batch || !plan.batch->ctr_words) return;
+    // the status word is written only by a whole-pipeline launch (a batch
+    // state made by a run of some groups holds it uncleared)
+    if (!plan.batch || !plan.batch->whole_ran) return;
     const BatchState& st = *plan.batch;
     hip_check(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)), "hipStreamSynchronize");
     int status = 0;

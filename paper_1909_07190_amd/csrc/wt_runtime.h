@@ -70,6 +70,7 @@ struct BatchState {
     // kernel before every launch) at ctr_off
     size_t whole_off = 0, ctr_off = 0;
     int nchunks = 0, ctr_words = 0, whole_grid = 0;
+    bool whole_ran = false;                        // a whole-pipeline launch was issued
     std::vector<int> chunk_tab;                    // 4 ints per chunk
     std::vector<unsigned long long> dep_tab;       // per group
     hipGraph_t graph = nullptr;

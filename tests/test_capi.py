@@ -246,6 +246,9 @@ def test_whole_pipeline_source_and_refusals():
         with pytest.raises(wt.WtError) as e:
             p2.source(-1)
         assert e.value.status == -2
+        with pytest.raises(wt.WtError) as e:
+            p2.whole_tables([(300, 200)], 64)
+        assert e.value.status == -2
     with pytest.raises(wt.WtError) as e:
         pl.source(-2)
     assert e.value.status == -1

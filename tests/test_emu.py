@@ -538,7 +538,7 @@ def test_whole_pipeline_kernel_emulated(case):
         out = "R"
     else:
         spec = P.pyramid_blend(3)
-        sizes = [(45, 37), (30, 21), (66, 40)]
+        sizes = [(45, 37), (66, 21)]
         images = [{"A": synth.uniform_image(70 + i, 1, h, w), "B": synth.uniform_image(80 + i, 1, h, w),
                    "M": synth.ramp_mask(h, w)} for i, (w, h) in enumerate(sizes)]
         kw = dict(mode="analytic", any_width=True)
