@@ -4,6 +4,8 @@ readlane as exchanges), against the FP64 oracle.  Covers every producer-load
 type (own VGPR, LDS sub-tile, other lane of the same / neighbouring register
 sub-tile), both alignments, clamp fix-ups at all four image edges, channel-
 mixing groups, FP16 intermediates and multi-level pyramids."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -575,10 +577,13 @@ def test_lookback_across_sub_tiles_emulated(cfg):
     """The input edge of a ten-stencil chain spans 70 columns under the
     right-hyperplane skew: more than one wavefront at one element per lane,
     so lanes read sub-tiles two back (Appendix A's multi-sub-tile lookback)."""
-    img = synth.uniform_image(31, 1, 13, 300)
+    img = synth.uniform_image(31, 1, 9, 200)
     fixed = f"nodes={WIDE_NODES} {cfg}"
     got, plan = emulate(WIDE, {"img": img}, mode="fixed", fixed=fixed)
     assert "align=1" in plan.describe()
+    gi = wt.GroupInfo()
+    wt._check(wt.lib.wt_plan_group_info(plan._h, 0, ctypes.byref(gi)))
+    assert gi.tiles_x >= 2 and gi.tiles_y >= 2  # interior and edge tiles, a ragged last row
     assert_normwise(got["out"], oracle.evaluate(WIDE, {"img": img})["out"], 1e-5, fixed)
 
 
