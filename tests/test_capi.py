@@ -265,3 +265,26 @@ def test_whole_pipeline_source_and_refusals():
     with pytest.raises(wt.WtError) as e:
         pl.whole_tables([(0, 5)], 64)
     assert e.value.status == -3
+
+
+def test_whole_pipeline_kernel_compiles_for_gfx950():
+    """The whole-pipeline kernel of a three-level pyramid blend compiles for
+    gfx950 with the library's own run-time compile options (no device)."""
+    rtc = ctypes.CDLL("/opt/rocm/lib/libhiprtc.so")
+    pl = wt.from_spec(P.pyramid_blend(3)).plan(300, 200, mode="analytic", any_width=True, no_compile=True,
+                                               batch_images=4)
+    src = pl.source(-1).encode()
+    prog = ctypes.c_void_p()
+    assert rtc.hiprtcCreateProgram(ctypes.byref(prog), src, b"whole.hip", 0, None, None) == 0
+    opts = [b"--offload-arch=gfx950", b"-O3", b"-std=c++17", b"-Xclang", b"-target-feature", b"-Xclang",
+            b"-packed-fp32-ops"]
+    rc = rtc.hiprtcCompileProgram(prog, len(opts), (ctypes.c_char_p * len(opts))(*opts))
+    n = ctypes.c_size_t()
+    rtc.hiprtcGetProgramLogSize(prog, ctypes.byref(n))
+    log = ctypes.create_string_buffer(max(1, n.value))
+    rtc.hiprtcGetProgramLog(prog, log)
+    code = ctypes.c_size_t()
+    rtc.hiprtcGetCodeSize(prog, ctypes.byref(code))
+    rtc.hiprtcDestroyProgram(ctypes.byref(prog))
+    assert rc == 0, log.value.decode(errors="replace")[:2000]
+    assert code.value > 0
