@@ -1709,8 +1709,9 @@ GroupSources generate_group_source(const Pipeline& p, const GroupSched& g, const
 // completion counters; images of a batch are independent), and after it
 // adds its tile count to its own group's counter.  A wave waits only for
 // chunks with smaller tickets, which waves already running hold, so the
-// smallest unfinished chunk can always proceed and the launch cannot
-// deadlock at any grid size; every wait is also bounded in time (after
+// smallest unfinished chunk can always proceed and the ordering cannot
+// deadlock at any grid size (the argument; the lane emulator checks it with
+// several waves at once); every wait is also bounded in time (after
 // `limit` ticks of the constant-rate clock the status word is set and all
 // waits end, so every wave still reaches the end of the queue).
 std::string generate_whole_source(const Pipeline& p, const std::vector<const GroupSched*>& gs,
